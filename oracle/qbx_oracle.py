@@ -1,0 +1,458 @@
+"""CPU FP64 oracle for Quadrature by Expansion (QBX), 2D Helmholtz S and D.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product imports this module; only
+``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may call it.  It shares no code with the HIP path.
+
+It follows the paper (Kloeckner, Barnett, Greengard, O'Neil, "Quadrature by
+Expansion: A New Method for the Evaluation of Layer Potentials") step by step,
+in plain PyTorch CPU ops (float64 / complex128) so that autograd gives exact
+gradients of the discrete map:
+
+* Section 4.1: each panel carries a 16-term Legendre expansion of x(tau),
+  y(tau), obtained from the 16 Gauss-Legendre node values by GL quadrature
+  (a discrete Legendre transform).
+* Section 3.4.2: the density is interpolated from the target (Nystrom) grid to
+  the finer source grid; the source grid is the q_s = 16*oversample point GL
+  rule on the same panel (Section 4.1, "q = 6*16").  Weights are
+  w = omega*|dX/dtau|, normals n = (y', -x')/|X'| (outward for counter-
+  clockwise curves, Section 3.2), and the panel length h_m = sum of w.
+* Section 3.3, step 4(a): center c = x + s*r*h_m*n, s=+1 exterior, -1
+  interior, radius R = r*h_m (r = 1/2 in the paper).
+* Section 2, eq. (graf-coefficient) and Section 3.2 eq. (graf-coefficient-dlp):
+  a_l = sum_j w_j sigma_j H_l(k rho_j) e^{-i l theta_j}, l=-p..p, and the
+  double-layer variant with the source normal derivative of
+  H_l(k|x'-c|) e^{-i l theta'}, taken by the polar chain rule with
+  H_l' = H_{l-1} - (l/z) H_l (DLMF 10.6.2).
+  (The paper writes e^{+i l theta'} here and e^{-i l theta} at evaluation; the
+  index change l -> -l gives the convention used here, which is identical.)
+* Section 3.3, step 4(c): u = (i/4) sum_l a_l J_l(k|x-c|) e^{i l theta}, the
+  i/4 of the Helmholtz kernel (i/4) H_0 (Section 1) applied at evaluation.
+* Section 3.2: both one-sided limits are returned; the principal value of D is
+  their average (eq. dlp-twosided).
+
+Two modes:
+* ``mode="dense"``: every order l evaluated by its own library call
+  (scipy.special.hankel1 / h1vp / jv); numpy; tiny inputs only.
+* ``mode="fast"``: H_0, H_1 from the library, higher orders by the upward
+  recurrence H_{l+1} = (2l/z) H_l - H_{l-1} (DLMF 10.6.1); J_l from the
+  library.  Differentiable (torch autograd) for the adjoint.
+
+Layout conventions shared with the boundary: density [n_kinds][P*16] (S
+first, then D), output [n_sides][n_kinds][P*16] with the exterior limit first
+when both sides are requested.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.special as sps
+import torch
+
+Q = 16
+S_KIND = 1
+D_KIND = 2
+EXTERIOR = 1
+INTERIOR = -1
+BOTH = 0
+
+_F64 = torch.float64
+_C128 = torch.complex128
+
+
+# ---------------------------------------------------------------------------
+# special functions: library calls, wrapped so autograd can differentiate them
+# ---------------------------------------------------------------------------
+class _Hankel1(torch.autograd.Function):
+    """H^(1)_n(x) for real x > 0 (scipy); derivative (H_{n-1} - H_{n+1})/2 (DLMF 10.6.1)."""
+
+    @staticmethod
+    def forward(ctx, x, n):
+        ctx.save_for_backward(x)
+        ctx.n = n
+        return torch.from_numpy(np.asarray(sps.hankel1(n, x.detach().numpy()), dtype=np.complex128))
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        n = ctx.n
+        d = hankel1(n - 1, x) - hankel1(n + 1, x)
+        return torch.real(torch.conj(g) * 0.5 * d), None
+
+
+class _BesselJ(torch.autograd.Function):
+    """J_n(x) (scipy); derivative (J_{n-1} - J_{n+1})/2 (DLMF 10.6.1)."""
+
+    @staticmethod
+    def forward(ctx, x, n):
+        ctx.save_for_backward(x)
+        ctx.n = n
+        return torch.from_numpy(np.asarray(sps.jv(n, x.detach().numpy()), dtype=np.float64))
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        n = ctx.n
+        return g * 0.5 * (besselj(n - 1, x) - besselj(n + 1, x)), None
+
+
+def hankel1(n: int, x: torch.Tensor) -> torch.Tensor:
+    return _Hankel1.apply(x, int(n))
+
+
+def besselj(n: int, x: torch.Tensor) -> torch.Tensor:
+    return _BesselJ.apply(x, int(n))
+
+
+# ---------------------------------------------------------------------------
+# Section 4.1: Legendre panel representation; Section 3.4.2: source grid
+# ---------------------------------------------------------------------------
+def gauss_legendre(n: int) -> Tuple[np.ndarray, np.ndarray]:
+    """n-point Gauss-Legendre nodes (ascending) and weights on [-1, 1]."""
+    return np.polynomial.legendre.leggauss(n)
+
+
+def _legendre_transform(n: int = Q) -> np.ndarray:
+    """T[m, a]: Legendre coefficient m of the series through the n GL node values.
+
+    c_m = (2m+1)/2 * sum_a omega_a X_a P_m(tau_a) (GL quadrature of the
+    Legendre projection, as in Section 4.1)."""
+    tau, om = gauss_legendre(n)
+    P = np.polynomial.legendre.legvander(tau, n - 1)          # [a, m] = P_m(tau_a)
+    return ((2.0 * np.arange(n) + 1.0) / 2.0)[:, None] * (P * om[:, None]).T
+
+
+def _legendre_eval(tau: np.ndarray, n: int = Q) -> Tuple[np.ndarray, np.ndarray]:
+    """E[b, m] = P_m(tau_b) and E'[b, m] = P_m'(tau_b), m < n."""
+    E = np.polynomial.legendre.legvander(tau, n - 1)
+    Ed = np.zeros_like(E)
+    for m in range(n):
+        e = np.zeros(n)
+        e[m] = 1.0
+        Ed[:, m] = np.polynomial.legendre.legval(tau, np.polynomial.legendre.legder(e))
+    return E, Ed
+
+
+def interpolation_matrices(oversample: int) -> Dict[str, torch.Tensor]:
+    """Linear maps from the 16 node values of a panel to the source grid.
+
+    Returns value map V [q_s,16], tau-derivative map Vd [q_s,16], the
+    tau-derivative at the 16 nodes themselves Dn [16,16], and the source GL
+    weights omega [q_s]."""
+    qs = Q * oversample
+    T = _legendre_transform(Q)
+    tau_s, om_s = gauss_legendre(qs)
+    E, Ed = _legendre_eval(tau_s, Q)
+    tau_t, _ = gauss_legendre(Q)
+    _, Edt = _legendre_eval(tau_t, Q)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(_F64)
+    return {"V": t(E @ T), "Vd": t(Ed @ T), "Dn": t(Edt @ T), "omega": t(om_s)}
+
+
+def source_grid(nodes: torch.Tensor, oversample: int) -> Dict[str, torch.Tensor]:
+    """Oversampled source grid of every panel (Section 3.4.2, Section 4.1).
+
+    nodes: [P, 16, 2] float64.  Returns flat source arrays of length P*q_s
+    (x, y, w, nx, ny), the panel lengths h [P] and the target normals [P*16, 2]."""
+    M = interpolation_matrices(oversample)
+    P = nodes.shape[0]
+    Xs = torch.einsum("bq,pqd->pbd", M["V"], nodes)            # [P, qs, 2]
+    dXs = torch.einsum("bq,pqd->pbd", M["Vd"], nodes)
+    speed = torch.sqrt(dXs[..., 0] ** 2 + dXs[..., 1] ** 2)
+    w = M["omega"][None, :] * speed                              # arc-length weights
+    h = w.sum(dim=1)                                             # panel length
+    n_src = torch.stack([dXs[..., 1], -dXs[..., 0]], dim=-1) / speed[..., None]
+    dXt = torch.einsum("aq,pqd->pad", M["Dn"], nodes)           # tangent at targets
+    n_tgt = torch.stack([dXt[..., 1], -dXt[..., 0]], dim=-1)
+    n_tgt = n_tgt / torch.sqrt(n_tgt[..., 0] ** 2 + n_tgt[..., 1] ** 2)[..., None]
+    return {
+        "x": Xs[..., 0].reshape(-1), "y": Xs[..., 1].reshape(-1), "w": w.reshape(-1),
+        "nx": n_src[..., 0].reshape(-1), "ny": n_src[..., 1].reshape(-1),
+        "h": h, "n_tgt": n_tgt.reshape(P * Q, 2), "V": M["V"],
+    }
+
+
+def interpolate_density(density: torch.Tensor, oversample: int) -> torch.Tensor:
+    """Density on the source grid from its 16 node values per panel (Section 3.4.2).
+
+    density: [..., P*16] complex -> [..., P*q_s] complex."""
+    V = interpolation_matrices(oversample)["V"].to(_C128)
+    lead = density.shape[:-1]
+    d = density.reshape(*lead, -1, Q)
+    return torch.einsum("bq,...pq->...pb", V, d).reshape(*lead, -1)
+
+
+# ---------------------------------------------------------------------------
+# Section 3.3 step 4(a): expansion centers
+# ---------------------------------------------------------------------------
+def expansion_centers(nodes: torch.Tensor, h: torch.Tensor, n_tgt: torch.Tensor, r: float,
+                      side: int) -> Dict[str, torch.Tensor]:
+    """c = x + side*r*h_m*n (side=+1 exterior, -1 interior); R = r*h_m; theta = arg(x - c)."""
+    x = nodes.reshape(-1, 2)
+    R = (r * h)[:, None].expand(-1, Q).reshape(-1)
+    c = x + float(side) * R[:, None] * n_tgt
+    d = x - c
+    return {"cx": c[:, 0], "cy": c[:, 1], "R": R, "theta": torch.atan2(d[:, 1], d[:, 0])}
+
+
+# ---------------------------------------------------------------------------
+# Section 2 / 3.2: expansion coefficients a_l, l = -p..p
+# ---------------------------------------------------------------------------
+def _hankel_orders_fast(z: torch.Tensor, lmax: int):
+    """H_0..H_lmax at z by the upward recurrence from library H_0, H_1."""
+    H = [hankel1(0, z), hankel1(1, z)]
+    for l in range(1, lmax):
+        H.append((2.0 * l / z) * H[l] - H[l - 1])
+    return H[: lmax + 1]
+
+
+def _coefficients_chunk(src, dens, cx, cy, k, p, kind, mode):
+    """a[kind] [C, 2p+1] for one chunk of centers, summing over every source."""
+    vx = src["x"][None, :] - cx[:, None]
+    vy = src["y"][None, :] - cy[:, None]
+    rho = torch.sqrt(vx * vx + vy * vy)
+    theta = torch.atan2(vy, vx)
+    z = k * rho
+    out = {}
+    need_d = bool(kind & D_KIND)
+    if mode == "fast":
+        H = _hankel_orders_fast(z, p + 1)
+        Hd = [-H[1]] + [H[l - 1] - (l / z) * H[l] for l in range(1, p + 1)]
+
+        def Hl(L):
+            s = 1.0 if L >= 0 or (-L) % 2 == 0 else -1.0
+            return s * H[abs(L)]
+
+        def Hdl(L):
+            s = 1.0 if L >= 0 or (-L) % 2 == 0 else -1.0
+            return s * Hd[abs(L)]
+    else:
+        zn = z.detach().numpy()
+        cache_h, cache_d = {}, {}
+
+        def Hl(L):
+            if L not in cache_h:
+                cache_h[L] = torch.from_numpy(np.asarray(sps.hankel1(L, zn)))
+            return cache_h[L]
+
+        def Hdl(L):
+            if L not in cache_d:
+                cache_d[L] = torch.from_numpy(np.asarray(sps.h1vp(L, zn)))
+            return cache_d[L]
+
+    if need_d:
+        # n . v_hat and n . theta_hat for every pair (source normal n_j)
+        n_v = (src["nx"][None, :] * vx + src["ny"][None, :] * vy) / rho
+        n_t = (-src["nx"][None, :] * vy + src["ny"][None, :] * vx) / rho
+    coefs_s, coefs_d = [], []
+    for L in range(-p, p + 1):
+        phase = torch.exp(-1j * L * theta)
+        if kind & S_KIND:
+            f = Hl(L) * phase
+            coefs_s.append((f * dens["S"][None, :]).sum(dim=1))
+        if need_d:
+            g = (k * Hdl(L) * n_v - (1j * L / rho) * Hl(L) * n_t) * phase
+            coefs_d.append((g * dens["D"][None, :]).sum(dim=1))
+    if kind & S_KIND:
+        out["S"] = torch.stack(coefs_s, dim=1)
+    if need_d:
+        out["D"] = torch.stack(coefs_d, dim=1)
+    return out
+
+
+def coefficients(src, dens, ctr, k, p, kind, mode="fast", chunk_pairs=1 << 21):
+    """Coefficients a_l for every center (dict kind -> [C, 2p+1] complex)."""
+    C = ctr["cx"].shape[0]
+    N = src["x"].shape[0]
+    step = max(1, chunk_pairs // max(N, 1))
+    parts = []
+    for c0 in range(0, C, step):
+        sl = slice(c0, min(C, c0 + step))
+        parts.append(_coefficients_chunk(src, dens, ctr["cx"][sl], ctr["cy"][sl], k, p, kind, mode))
+    return {key: torch.cat([q[key] for q in parts], dim=0) for key in parts[0]}
+
+
+# ---------------------------------------------------------------------------
+# Section 3.3 step 4(c): evaluate the local expansion at the target
+# ---------------------------------------------------------------------------
+def evaluate(a: torch.Tensor, R: torch.Tensor, theta: torch.Tensor, k: float, p: int,
+             mode: str = "fast") -> torch.Tensor:
+    """u = (i/4) sum_{l=-p}^{p} a_l J_l(kR) e^{i l theta}."""
+    x = k * R
+    u = torch.zeros(a.shape[0], dtype=_C128)
+    for L in range(-p, p + 1):
+        if mode == "fast":
+            J = besselj(abs(L), x) * (1.0 if L >= 0 or (-L) % 2 == 0 else -1.0)
+        else:
+            J = torch.from_numpy(np.asarray(sps.jv(L, x.detach().numpy())))
+        u = u + a[:, L + p] * J * torch.exp(1j * L * theta)
+    return 0.25j * u
+
+
+# ---------------------------------------------------------------------------
+# top level
+# ---------------------------------------------------------------------------
+def _as_t(a, dtype):
+    if isinstance(a, torch.Tensor):
+        return a.to(dtype)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype)
+
+
+def sides_of(side: int) -> Sequence[int]:
+    return (EXTERIOR, INTERIOR) if side == BOTH else (side,)
+
+
+def kinds_of(kind: int) -> Sequence[str]:
+    return tuple(k for k, bit in (("S", S_KIND), ("D", D_KIND)) if kind & bit)
+
+
+def layer_potential(nodes, density, k: float, p: int, r: float = 0.5, oversample: int = 4,
+                    side: int = EXTERIOR, kind: int = S_KIND, targets=None, mode: str = "fast",
+                    return_aux: bool = False):
+    """One-sided QBX limits at the targets.
+
+    nodes [P,16,2] float64, density [n_kinds, P*16] complex128 (S first, then D).
+    ``targets``: optional index array into the P*16 targets (sampled evaluation).
+    Returns u [n_sides, n_kinds, T] complex128 (exterior first for BOTH)."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    kinds = kinds_of(kind)
+    src = source_grid(nodes, oversample)
+    fine = interpolate_density(density, oversample)
+    dens = {}
+    for i, kk in enumerate(kinds):
+        dens[kk] = src["w"].to(_C128) * fine[i]
+    outs, aux = [], {}
+    for s in sides_of(side):
+        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
+        if targets is not None:
+            idx = torch.as_tensor(np.asarray(targets), dtype=torch.long)
+            ctr = {key: val[idx] for key, val in ctr.items()}
+        a = coefficients(src, dens, ctr, k, p, kind, mode)
+        us = [evaluate(a[kk], ctr["R"], ctr["theta"], k, p, mode) for kk in kinds]
+        outs.append(torch.stack(us))
+        aux[s] = {"ctr": ctr, "a": a}
+    u = torch.stack(outs)
+    if return_aux:
+        return u, {"src": src, "sides": aux}
+    return u
+
+
+def graf_min_ratio(nodes, k, p, r=0.5, oversample=4, side=EXTERIOR) -> float:
+    """min over centers and sources of rho_ij / R_i (Graf's condition needs > 1)."""
+    with torch.no_grad():
+        nodes = _as_t(nodes, _F64)
+        src = source_grid(nodes, oversample)
+        best = math.inf
+        for s in sides_of(side):
+            ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
+            vx = src["x"][None, :] - ctr["cx"][:, None]
+            vy = src["y"][None, :] - ctr["cy"][:, None]
+            rho = torch.sqrt(vx * vx + vy * vy)
+            best = min(best, float((rho / ctr["R"][:, None]).min()))
+        return best
+
+
+def qbx_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+               kind_name: str = "S") -> np.ndarray:
+    """Dense QBX operator A [T, P*16] (targets x coarse density) for one side and kind.
+
+    A = K diag(w) U: K_ij = (i/4) sum_{|l|<=p} J_l(kR_i) e^{il theta_i} G_l(x'_j - c_i), the
+    regularized kernel of Section 2 (eq. qbx-kernel), with G_l = H_l(k rho) e^{-il theta'}
+    for S and its source-normal derivative (library derivative h1vp) for D, every order a
+    separate library call; w the source weights; U the block-diagonal 16 -> q_s
+    interpolation of Section 3.4.2.  Tiny inputs only."""
+    with torch.no_grad():
+        nodes = _as_t(nodes, _F64)
+        src = source_grid(nodes, oversample)
+        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, side)
+        vx = (src["x"][None, :] - ctr["cx"][:, None]).numpy()
+        vy = (src["y"][None, :] - ctr["cy"][:, None]).numpy()
+        rho = np.hypot(vx, vy)
+        th = np.arctan2(vy, vx)
+        z = k * rho
+        kR = (k * ctr["R"]).numpy()[:, None]
+        tht = ctr["theta"].numpy()[:, None]
+        nx, ny = src["nx"].numpy()[None, :], src["ny"].numpy()[None, :]
+        K = np.zeros(rho.shape, dtype=np.complex128)
+        for L in range(-p, p + 1):
+            beta = sps.jv(L, kR) * np.exp(1j * L * tht)
+            if kind_name == "S":
+                G = sps.hankel1(L, z) * np.exp(-1j * L * th)
+            else:
+                n_v = (nx * vx + ny * vy) / rho
+                n_t = (-nx * vy + ny * vx) / rho
+                G = (k * sps.h1vp(L, z) * n_v - (1j * L / rho) * sps.hankel1(L, z) * n_t) * np.exp(-1j * L * th)
+            K += beta * G
+        K *= 0.25j * src["w"].numpy()[None, :]
+        V = src["V"].numpy()
+        P = nodes.shape[0]
+        U = np.kron(np.eye(P), V)
+        return K @ U
+
+
+# ---------------------------------------------------------------------------
+# adjoint: gradients of L = Re <g, u> by autograd through the steps above
+# ---------------------------------------------------------------------------
+def vjp(nodes, density, k: float, p: int, r: float, oversample: int, side: int, kind: int,
+        cotangent, panels=None, chunk_pairs: int = 1 << 20):
+    """Gradients of L = Re sum conj(g) u with respect to density [n_kinds, P*16] (complex,
+    PyTorch convention dL/dRe + i dL/dIm) and nodes [P, 16, 2].
+
+    With ``panels`` (indices), only those panels' gradients are exact: the loss is
+    restricted to the pairs that touch them (their centers against every source, plus
+    every other center against their sources), which has the same gradient on them.
+    Work is split into center chunks, each rebuilt and back-propagated on its own."""
+    nodes_np = np.ascontiguousarray(np.asarray(nodes, dtype=np.float64))
+    dens_np = np.ascontiguousarray(np.asarray(density, dtype=np.complex128))
+    g_np = np.asarray(cotangent, dtype=np.complex128)
+    P = nodes_np.shape[0]
+    T = P * Q
+    qs = Q * oversample
+    kinds = kinds_of(kind)
+    g_nodes = torch.zeros(P, Q, 2, dtype=_F64)
+    g_dens = torch.zeros(len(kinds), T, dtype=_C128)
+    all_src = np.arange(P * qs)
+    if panels is None:
+        groups = [(np.arange(T), all_src)]
+    else:
+        pm = np.zeros(P, dtype=bool)
+        pm[np.asarray(panels)] = True
+        tgt_in = np.repeat(pm, Q)
+        src_in = np.repeat(pm, qs)
+        groups = [(np.nonzero(tgt_in)[0], all_src), (np.nonzero(~tgt_in)[0], np.nonzero(src_in)[0])]
+    for si, s in enumerate(sides_of(side)):
+        for tgt_idx, src_idx in groups:
+            if len(tgt_idx) == 0 or len(src_idx) == 0:
+                continue
+            step = max(1, chunk_pairs // len(src_idx))
+            for c0 in range(0, len(tgt_idx), step):
+                sel = torch.as_tensor(tgt_idx[c0:c0 + step], dtype=torch.long)
+                sidx = torch.as_tensor(src_idx, dtype=torch.long)
+                X = torch.from_numpy(nodes_np).clone().requires_grad_(True)
+                Dn = torch.from_numpy(dens_np).clone().requires_grad_(True)
+                src = source_grid(X, oversample)
+                fine = interpolate_density(Dn, oversample)
+                srcs = {key: src[key][sidx] for key in ("x", "y", "nx", "ny", "w")}
+                dens = {kk: srcs["w"].to(_C128) * fine[i][sidx] for i, kk in enumerate(kinds)}
+                ctr = expansion_centers(X, src["h"], src["n_tgt"], r, s)
+                ctr = {key: val[sel] for key, val in ctr.items()}
+                a = coefficients(srcs, dens, ctr, k, p, kind, "fast", chunk_pairs)
+                L = torch.zeros((), dtype=_F64)
+                for ki, kk in enumerate(kinds):
+                    u = evaluate(a[kk], ctr["R"], ctr["theta"], k, p, "fast")
+                    g = torch.from_numpy(g_np[si, ki][sel.numpy()])
+                    L = L + torch.real(torch.conj(g) * u).sum()
+                L.backward()
+                g_nodes += X.grad
+                g_dens += Dn.grad
+    return g_dens.numpy(), g_nodes.numpy()
+
+
+def loss(nodes, density, k, p, r, oversample, side, kind, cotangent) -> float:
+    """L = Re sum conj(g) u (the scalar whose gradients ``vjp`` returns)."""
+    with torch.no_grad():
+        u = layer_potential(nodes, density, k, p, r, oversample, side, kind).numpy()
+    return float(np.real(np.sum(np.conj(np.asarray(cotangent)) * u)))
