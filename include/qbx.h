@@ -1,0 +1,159 @@
+/*
+ * qbx.h -- C ABI of libqbx, the MI355X (gfx950) hot path of Quadrature by
+ * Expansion (QBX) for the 2D Helmholtz single-layer (S) and double-layer (D)
+ * potentials (Kloeckner, Barnett, Greengard, O'Neil, "Quadrature by
+ * Expansion: A New Method for the Evaluation of Layer Potentials").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers unless marked "host".  Complex
+ *    values are interleaved (re, im) doubles, the layout of torch.complex128.
+ *  - The caller owns every buffer.  The library never allocates, never frees
+ *    and keeps no pointer after a call returns; scratch memory comes from the
+ *    caller's workspace `ws` of `ws_bytes` bytes (sizes from the *_bytes
+ *    queries below, alignment 256 bytes).
+ *  - Work is enqueued on `stream` and is stream-ordered; no call synchronizes
+ *    the device except the ones documented as synchronous.  Calls that use
+ *    different workspaces may run concurrently.
+ *  - Return value: 0 on success, a negative qbx_status otherwise.  Argument
+ *    validation happens on the host before anything is enqueued, so invalid
+ *    arguments never reach the GPU.  qbx_strerror() names a code;
+ *    qbx_last_error() gives the message of the last failure on this thread.
+ *
+ * Geometry (Section 4.1 of the paper): a closed counter-clockwise curve split
+ * into n_panels panels, each carrying q = 16 nodes placed at the 16-point
+ * Gauss-Legendre abscissae of the panel parameter (ascending); the panel is
+ * the degree-15 polynomial through its nodes.  nodes[n_panels][16][2].
+ * Targets are the nodes themselves (the Nystrom grid, Section 3.4.2), in node
+ * order; T = 16*n_panels.
+ *
+ * Source grid (Section 3.4.2, Section 4.1): on every panel, the
+ * q_s = 16*oversample point Gauss-Legendre rule of the same panel; the
+ * density is interpolated there from its node values.
+ *
+ * Centers (Section 3.3, step 4(a)): c = x + s*r*h_m*n at every target x of
+ * panel m, s = +1 exterior, -1 interior; n the outward unit normal; h_m the
+ * panel arc length by the source rule; radius R = r*h_m (the paper takes
+ * r = 1/2).
+ *
+ * Output: the one-sided limits (Section 3.3, step 4(c))
+ *   u(x) = (i/4) sum_{l=-p..p} a_l J_l(k R) e^{i l theta},  theta = arg(x - c),
+ *   a_l  = sum_j w_j sigma_j H^(1)_l(k|x'_j - c|) e^{-i l theta'_j}      (S),
+ * and for D the same with d/dn' of the source factor applied to mu
+ * (Section 2 eq. graf-coefficient, Section 3.2 eq. graf-coefficient-dlp; the
+ * paper's e^{+il theta'} / e^{-il theta} convention is the same sum under
+ * l -> -l).  The principal value of D is the average of both limits
+ * (Section 3.2, eq. dlp-twosided).
+ * Layout out[n_sides][n_kinds][T] complex: for side = QBX_BOTH the exterior
+ * limit comes first; kinds in the order S, D.
+ */
+#ifndef QBX_H
+#define QBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QBX_Q 16             /* nodes per panel (Section 4.1)                  */
+#define QBX_PMAX 24          /* largest supported expansion order p            */
+#define QBX_OVERSAMPLE_MAX 8 /* source nodes per panel = 16*oversample <= 128  */
+
+enum qbx_kind { QBX_S = 1, QBX_D = 2 };                       /* bit mask; S|D fused */
+enum qbx_side { QBX_INTERIOR = -1, QBX_BOTH = 0, QBX_EXTERIOR = 1 };
+
+enum qbx_status {
+  QBX_OK = 0,
+  QBX_EINVAL = -1,     /* null pointer, n_panels < 3, q != 16, p < 0 or p > QBX_PMAX,
+                          k <= 0 or not finite, r <= 0 or not finite, oversample < 1
+                          or > QBX_OVERSAMPLE_MAX, bad side or kind, bad item        */
+  QBX_EWORKSPACE = -2, /* ws_bytes smaller than the matching *_bytes query           */
+  QBX_EORIENT = -3,    /* clockwise contour (negative signed area)                   */
+  QBX_EGRAF = -4,      /* a source lies inside a center's disk: Graf's condition
+                          |x - c| < |x' - c| (Section 2, eq. x-c-closest) fails     */
+  QBX_EDEVICE = -5     /* a HIP call failed; see qbx_last_error()                  */
+};
+
+typedef struct {
+  int32_t n_panels;     /* >= 3                                                  */
+  int32_t q;            /* must be QBX_Q                                          */
+  const double* nodes;  /* device, [n_panels][16][2], counter-clockwise           */
+} qbx_geometry;
+
+/* ---- sizes ------------------------------------------------------------- */
+
+/* Workspace bytes for qbx_layer_potential / _adjoint with these parameters
+ * (0 if the parameters are invalid). */
+size_t qbx_workspace_bytes(int n_panels, int q, int p, int oversample, int side, int kind);
+
+/* Bytes of the forward's tape (the per-center data the adjoint reuses). */
+size_t qbx_tape_bytes(int n_panels, int q, int p, int side, int kind);
+
+/* ---- forward ----------------------------------------------------------- */
+
+/* One-sided QBX limits of S sigma and/or D mu at every target.
+ *   density [n_kinds][T] complex: the S density first, then the D density,
+ *            sampled at the nodes (interpolated to the source grid inside).
+ *   k > 0 wavenumber, p expansion order, r center distance as a fraction of the
+ *   panel length, oversample source refinement, side, kind as above.
+ *   out [n_sides][n_kinds][T] complex.
+ *   tape: nullable device buffer of qbx_tape_bytes(); when given it receives
+ *         what the adjoint needs so that it need not recompute it.       */
+int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, int p,
+                        double r, int oversample, int side, int kind, double* out,
+                        double* tape, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- adjoint ----------------------------------------------------------- */
+
+/* Vector-Jacobian product of qbx_layer_potential for the real scalar
+ * L = Re sum conj(cotangent) * out (PyTorch convention):
+ *   grad_density [n_kinds][T] complex = (d out / d density)^H cotangent,
+ *   grad_nodes   [n_panels][16][2] real = dL/d nodes,
+ * through every step: source interpolation, weights, normals, panel lengths,
+ * centers, radii and the expansion sums.  cotangent has the layout of out.
+ * tape: the forward's tape, or NULL to recompute it.  Either gradient pointer
+ * may be NULL when not wanted.  The gradients are written, not accumulated. */
+int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, double k, int p,
+                                double r, int oversample, int side, int kind,
+                                const double* cotangent, const double* tape,
+                                double* grad_density, double* grad_nodes, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* ---- checks ------------------------------------------------------------ */
+
+/* SYNCHRONOUS geometry check (it waits for `stream`): signed area of the
+ * contour and min over all centers and sources of |x'_j - c_i| / R_i.
+ * Returns QBX_EORIENT if the area is negative, QBX_EGRAF if the minimum
+ * ratio is below 1 - 1e-12, QBX_OK otherwise.  area / min_ratio (host, may be
+ * NULL) receive the values. */
+int qbx_check_geometry(const qbx_geometry* g, int p, double r, int oversample, int side,
+                       double* area, double* min_ratio, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* Host-only signed area of a contour given in HOST memory, by the 16-point
+ * panel rule; used to reject clockwise input without a GPU.  Returns
+ * QBX_EINVAL for bad arguments, QBX_EORIENT if negative, else QBX_OK. */
+int qbx_signed_area_host(const double* nodes_host, int n_panels, double* area);
+
+/* ---- errors ------------------------------------------------------------ */
+
+const char* qbx_strerror(int code);
+const char* qbx_last_error(void);
+
+/* ---- special functions (test hooks) ------------------------------------ */
+
+/* H^(1)_0 and H^(1)_1 at n real points z > 0 exactly as the pair kernels
+ * compute them: z, h0, h1 device arrays ([n], [n] complex, [n] complex). */
+int qbx_debug_hankel01(const double* z, int n, double* h0, double* h1, hipStream_t stream);
+
+/* J_0..J_L at n points x >= 0 by the Miller recurrence used for every center:
+ * x [n], out [n][L+1]. L <= QBX_PMAX + 3. */
+int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QBX_H */

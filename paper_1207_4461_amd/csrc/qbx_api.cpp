@@ -1,0 +1,285 @@
+// Host side of libqbx: argument validation, workspace layout, launch order and
+// error reporting behind the C ABI of include/qbx.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/qbx.h"
+#include "qbx_internal.h"
+#include "qbx_special.h"
+
+namespace qbx {
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static int device_fail(hipError_t e, const char* where) {
+  return fail(QBX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
+               Dims* d) {
+  if (n_panels < 3 || q != kQ || p < 0 || p > kPMax || oversample < 1 ||
+      oversample > QBX_OVERSAMPLE_MAX)
+    return false;
+  if (side != QBX_INTERIOR && side != QBX_EXTERIOR && side != QBX_BOTH) return false;
+  if (kind != QBX_S && kind != QBX_D && kind != (QBX_S | QBX_D)) return false;
+  const long T = (long)n_panels * kQ;
+  const long N = T * oversample;
+  const long Mc = T * (side == QBX_BOTH ? 2 : 1);
+  if (N > (1L << 30) || Mc > (1L << 28)) return false;
+  d->P = n_panels;
+  d->qs = kQ * oversample;
+  d->T = (int)T;
+  d->N = (int)N;
+  d->n_sides = side == QBX_BOTH ? 2 : 1;
+  d->nk = (kind == 3) ? 2 : 1;
+  d->p = p;
+  d->Mc = (int)Mc;
+  d->NJ = p + 3;
+  d->side = side;
+  d->kind = kind;
+  d->k = k;
+  d->r = r;
+  d->chunks = (int)((N + kWave - 1) / kWave);
+  // enough wavefronts to fill 256 CUs several times over, but at least four
+  // 64-source chunks per wavefront
+  const long want_waves = 16384;
+  long split = (want_waves + Mc - 1) / Mc;
+  long max_split = d->chunks / 4;
+  if (max_split < 1) max_split = 1;
+  if (split > max_split) split = max_split;
+  if (split < 1) split = 1;
+  d->chunks_per_split = (int)((d->chunks + split - 1) / split);
+  d->n_split = (d->chunks + d->chunks_per_split - 1) / d->chunks_per_split;
+  return true;
+}
+
+Layout make_layout(const Dims& d) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.tables = take(sizeof(double) * table_layout(d.qs).total);
+  L.geo = take(sizeof(double4) * (size_t)d.N);
+  L.dens = take(sizeof(double2) * (size_t)d.nk * d.N);
+  L.wgt = take(sizeof(double) * (size_t)d.N);
+  L.h = take(sizeof(double) * (size_t)d.P);
+  L.ctr = take(sizeof(CenterRec) * (size_t)d.Mc);
+  L.jtab = take(sizeof(double) * (size_t)d.Mc * d.NJ);
+  L.partial = take(sizeof(double2) * (size_t)d.n_split * d.nk * d.Mc);
+  L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+static int validate(const qbx_geometry* g, int p, double k, double r, int oversample, int side,
+                    int kind, Dims* d) {
+  if (!g) return fail(QBX_EINVAL, "geometry is NULL");
+  if (!g->nodes) return fail(QBX_EINVAL, "geometry nodes pointer is NULL");
+  if (g->q != kQ) return fail(QBX_EINVAL, "q = %d, only %d nodes per panel are supported", g->q, kQ);
+  if (g->n_panels < 3) return fail(QBX_EINVAL, "n_panels = %d < 3", g->n_panels);
+  if (p < 0 || p > kPMax) return fail(QBX_EINVAL, "order p = %d outside [0, %d]", p, kPMax);
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(QBX_EINVAL, "wavenumber k = %g must be > 0", k);
+  if (!(r > 0.0) || !std::isfinite(r)) return fail(QBX_EINVAL, "center distance r = %g must be > 0", r);
+  if (oversample < 1 || oversample > QBX_OVERSAMPLE_MAX)
+    return fail(QBX_EINVAL, "oversample = %d outside [1, %d]", oversample, QBX_OVERSAMPLE_MAX);
+  if (side != QBX_INTERIOR && side != QBX_EXTERIOR && side != QBX_BOTH)
+    return fail(QBX_EINVAL, "side = %d is not -1, 0 or 1", side);
+  if (kind != QBX_S && kind != QBX_D && kind != (QBX_S | QBX_D))
+    return fail(QBX_EINVAL, "kind = %d is not 1 (S), 2 (D) or 3 (S|D)", kind);
+  if (!make_dims(g->n_panels, g->q, p, oversample, side, kind, k, r, d))
+    return fail(QBX_EINVAL, "problem too large");
+  return QBX_OK;
+}
+
+// tables + source grid + centers into the workspace
+static int prepare(const Dims& d, const Layout& L, const double* nodes, const double* density,
+                   void* ws, hipStream_t stream) {
+  hipError_t e = launch_tables(d, at<double>(ws, L.tables), stream);
+  if (e != hipSuccess) return device_fail(e, "tables kernel");
+  e = launch_upsample(d, nodes, density, at<double>(ws, L.tables), at<double4>(ws, L.geo),
+                      at<double2>(ws, L.dens), at<double>(ws, L.wgt), at<double>(ws, L.h),
+                      at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab), stream);
+  if (e != hipSuccess) return device_fail(e, "upsample kernel");
+  return QBX_OK;
+}
+
+}  // namespace qbx
+
+using namespace qbx;
+
+extern "C" {
+
+size_t qbx_workspace_bytes(int n_panels, int q, int p, int oversample, int side, int kind) {
+  Dims d;
+  if (!make_dims(n_panels, q, p, oversample, side, kind, 1.0, 0.5, &d)) return 0;
+  return make_layout(d).total;
+}
+
+size_t qbx_tape_bytes(int n_panels, int q, int p, int side, int kind) {
+  Dims d;
+  if (!make_dims(n_panels, q, p, 1, side, kind, 1.0, 0.5, &d)) return 0;
+  // per center and kind: the boundary coefficients a_{+-p}, a_{+-(p+1)}, a_{+-(p+2)}
+  return sizeof(double2) * (size_t)d.Mc * d.nk * 8;
+}
+
+int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, int p, double r,
+                        int oversample, int side, int kind, double* out, double* tape, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  (void)tape;
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!out) return fail(QBX_EINVAL, "out is NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  hipError_t e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                at<double2>(ws, L.partial), stream);
+  if (e != hipSuccess) return device_fail(e, "forward kernel");
+  e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
+  if (e != hipSuccess) return device_fail(e, "finalize kernel");
+  return QBX_OK;
+}
+
+int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, double k, int p,
+                                double r, int oversample, int side, int kind,
+                                const double* cotangent, const double* tape, double* grad_density,
+                                double* grad_nodes, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  (void)g; (void)density; (void)k; (void)p; (void)r; (void)oversample; (void)side; (void)kind;
+  (void)cotangent; (void)tape; (void)grad_density; (void)grad_nodes; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return fail(QBX_EINVAL, "adjoint not built yet");
+}
+
+int qbx_check_geometry(const qbx_geometry* g, int p, double r, int oversample, int side,
+                       double* area, double* min_ratio, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, 1.0, r, oversample, side, QBX_S, &d);
+  if (rc) return rc;
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  // any density works for the geometry; use the nodes array itself as a
+  // harmless real input (only its values are read)
+  Dims dg = d;
+  rc = prepare(dg, L, g->nodes, g->nodes, ws, stream);
+  if (rc) return rc;
+  hipError_t e = launch_check(d, at<double4>(ws, L.geo), at<double>(ws, L.wgt),
+                              at<CenterRec>(ws, L.ctr), at<double>(ws, L.scratch), stream);
+  if (e != hipSuccess) return device_fail(e, "check kernels");
+  double res[2];
+  e = hipMemcpyAsync(res, at<double>(ws, L.scratch), sizeof(res), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return device_fail(e, "copy of check results");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return device_fail(e, "stream synchronize");
+  if (area) *area = res[0];
+  if (min_ratio) *min_ratio = res[1];
+  if (res[0] < 0.0) return fail(QBX_EORIENT, "signed area %g < 0: contour is clockwise", res[0]);
+  if (res[1] < 1.0 - 1e-12)
+    return fail(QBX_EGRAF, "a source lies inside a center's disk (min |x'-c|/R = %.15g)", res[1]);
+  return QBX_OK;
+}
+
+int qbx_signed_area_host(const double* nodes, int n_panels, double* area) {
+  if (!nodes) return fail(QBX_EINVAL, "nodes is NULL");
+  if (n_panels < 3) return fail(QBX_EINVAL, "n_panels = %d < 3", n_panels);
+  // 16-point rule on each panel: area = 1/2 sum_a omega_a (x y' - y x')(tau_a)
+  double t16[kQ], w16[kQ], bw[kQ], D[kQ][kQ];
+  for (int a = 0; a < kQ; ++a) gauss_legendre_node(kQ, a, &t16[a], &w16[a]);
+  for (int a = 0; a < kQ; ++a) {
+    double pr = 1.0;
+    for (int c = 0; c < kQ; ++c)
+      if (c != a) pr *= (t16[a] - t16[c]);
+    bw[a] = 1.0 / pr;
+  }
+  for (int b = 0; b < kQ; ++b)
+    for (int a = 0; a < kQ; ++a) {
+      if (a != b) {
+        D[b][a] = (bw[a] / bw[b]) / (t16[b] - t16[a]);
+      } else {
+        double v = 0.0;
+        for (int c = 0; c < kQ; ++c)
+          if (c != b) v += 1.0 / (t16[b] - t16[c]);
+        D[b][a] = v;
+      }
+    }
+  double A = 0.0;
+  for (int m = 0; m < n_panels; ++m) {
+    const double* X = nodes + (size_t)m * 2 * kQ;
+    for (int b = 0; b < kQ; ++b) {
+      double dx = 0.0, dy = 0.0;
+      for (int a = 0; a < kQ; ++a) {
+        dx += D[b][a] * X[2 * a];
+        dy += D[b][a] * X[2 * a + 1];
+      }
+      A += 0.5 * w16[b] * (X[2 * b] * dy - X[2 * b + 1] * dx);
+    }
+  }
+  if (area) *area = A;
+  if (!std::isfinite(A)) return fail(QBX_EINVAL, "non-finite node coordinates");
+  if (A < 0.0) return fail(QBX_EORIENT, "signed area %g < 0: contour is clockwise", A);
+  return QBX_OK;
+}
+
+const char* qbx_strerror(int code) {
+  switch (code) {
+    case QBX_OK: return "success";
+    case QBX_EINVAL: return "invalid argument";
+    case QBX_EWORKSPACE: return "workspace too small";
+    case QBX_EORIENT: return "contour is clockwise";
+    case QBX_EGRAF: return "Graf condition violated (source inside an expansion disk)";
+    case QBX_EDEVICE: return "HIP device error";
+    default: return "unknown error";
+  }
+}
+
+const char* qbx_last_error(void) { return g_last_error.c_str(); }
+
+int qbx_debug_hankel01(const double* z, int n, double* h0, double* h1, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!z || !h0 || !h1))) return fail(QBX_EINVAL, "bad debug_hankel01 args");
+  hipError_t e = launch_debug_hankel01(z, n, h0, h1, stream);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "debug_hankel01");
+}
+
+int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t stream) {
+  if (n < 0 || L < 0 || L > QBX_PMAX + 3 || (n > 0 && (!x || !out)))
+    return fail(QBX_EINVAL, "bad debug_besselj args");
+  hipError_t e = launch_debug_besselj(x, n, L, out, stream);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "debug_besselj");
+}
+
+}  // extern "C"

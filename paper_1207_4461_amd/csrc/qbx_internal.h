@@ -1,0 +1,99 @@
+// Internal declarations shared by the host C-ABI and the HIP kernels of libqbx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qbx {
+
+constexpr int kQ = 16;      // nodes per panel
+constexpr int kWave = 64;   // CDNA wavefront
+constexpr int kPMax = 24;
+
+// One expansion center: position, radius and the direction of its target,
+// e^{i theta} = (ct, st) with theta = arg(x - c).  64 bytes so that a wave reads
+// a record with one scalar load.
+struct CenterRec {
+  double cx, cy, R, ct, st, x, y, pad;
+};
+
+// Problem dimensions derived from the call arguments.
+struct Dims {
+  int P;        // panels
+  int qs;       // source nodes per panel (16 * oversample)
+  int T;        // targets (16 * P)
+  int N;        // sources (qs * P)
+  int n_sides;  // 1 or 2
+  int nk;       // kinds (1 or 2)
+  int p;        // expansion order
+  int Mc;       // centers (T * n_sides)
+  int NJ;       // J table length per center (J_0 .. J_{NJ-1})
+  int side;     // QBX_INTERIOR / QBX_BOTH / QBX_EXTERIOR
+  int kind;     // bit mask S=1, D=2
+  double k, r;
+  // forward launch shape
+  int chunks;            // ceil(N / 64)
+  int n_split;           // source splits per center
+  int chunks_per_split;  // 64-source chunks per split
+};
+
+// Byte offsets of the workspace arrays (all 256-byte aligned).
+struct Layout {
+  size_t tables;   // double[table_doubles(qs)]
+  size_t geo;      // double4[N]  {x, y, nx, ny}
+  size_t dens;     // double2[nk][N]  w * density on the source grid
+  size_t wgt;      // double[N] source quadrature weights w
+  size_t h;        // double[P] panel lengths
+  size_t ctr;      // CenterRec[Mc]
+  size_t jtab;     // double[Mc][NJ]
+  size_t partial;  // double2[n_split][nk][Mc]
+  size_t scratch;  // double[4096] small reductions
+  size_t total;
+};
+
+// Offsets (in doubles) of the Gauss-Legendre / interpolation tables.
+struct TableLayout {
+  int tau16, w16, taus, ws, V, Vd, Dn, total;
+};
+
+__host__ __device__ inline TableLayout table_layout(int qs) {
+  TableLayout t;
+  t.tau16 = 0;
+  t.w16 = 16;
+  t.taus = 32;
+  t.ws = t.taus + qs;
+  t.V = t.ws + qs;            // [qs][16] value map 16 nodes -> source node
+  t.Vd = t.V + qs * kQ;       // [qs][16] d/dtau map
+  t.Dn = t.Vd + qs * kQ;      // [16][16] d/dtau at the nodes
+  t.total = t.Dn + kQ * kQ;
+  return t;
+}
+
+// side index -> sign (+1 exterior, -1 interior)
+__host__ __device__ inline double side_sign(int side, int si) {
+  if (side == 0) return si == 0 ? 1.0 : -1.0;
+  return side > 0 ? 1.0 : -1.0;
+}
+
+bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
+               Dims* d);
+Layout make_layout(const Dims& d);
+
+// ---- launchers (qbx_geometry.hip / qbx_forward.hip) ----
+hipError_t launch_tables(const Dims& d, double* tables, hipStream_t s);
+hipError_t launch_upsample(const Dims& d, const double* nodes, const double* density,
+                           const double* tables, double4* geo, double2* dens, double* wgt,
+                           double* h, CenterRec* ctr, double* jtab, hipStream_t s);
+hipError_t launch_forward(const Dims& d, const double4* geo, const double2* dens,
+                          const CenterRec* ctr, const double* jtab, double2* partial,
+                          hipStream_t s);
+hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s);
+// scratch[0] = signed area, scratch[1] = min_ij |x'_j - c_i| / R_i
+hipError_t launch_check(const Dims& d, const double4* geo, const double* wgt,
+                        const CenterRec* ctr, double* scratch, hipStream_t s);
+hipError_t launch_debug_hankel01(const double* z, int n, double* h0, double* h1, hipStream_t s);
+hipError_t launch_debug_besselj(const double* x, int n, int L, double* out, hipStream_t s);
+
+}  // namespace qbx

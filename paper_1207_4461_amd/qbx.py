@@ -1,0 +1,136 @@
+"""PyTorch-facing API of libqbx: tensors in, tensors out, on torch's current stream.
+
+Every step of the computation runs in the HIP library; this module only checks
+tensor shapes/dtypes/devices, allocates outputs and workspaces with torch, and
+passes raw device pointers through the C ABI (include/qbx.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib
+
+S = _lib.QBX_S
+D = _lib.QBX_D
+SD = _lib.QBX_S | _lib.QBX_D
+INTERIOR = _lib.QBX_INTERIOR
+EXTERIOR = _lib.QBX_EXTERIOR
+BOTH = _lib.QBX_BOTH
+Q = _lib.QBX_Q
+
+
+def n_kinds(kind: int) -> int:
+    return 2 if kind == SD else 1
+
+
+def n_sides(side: int) -> int:
+    return 2 if side == BOTH else 1
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(n_panels: int, p: int, oversample: int = 4, side: int = EXTERIOR,
+                    kind: int = S) -> int:
+    n = _lib.load().qbx_workspace_bytes(n_panels, Q, p, oversample, side, kind)
+    if n == 0:
+        raise _lib.QBXError(_lib.QBX_EINVAL, "invalid problem parameters")
+    return int(n)
+
+
+def tape_bytes(n_panels: int, p: int, side: int = EXTERIOR, kind: int = S) -> int:
+    return int(_lib.load().qbx_tape_bytes(n_panels, Q, p, side, kind))
+
+
+def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    if workspace is not None:
+        if workspace.device != device or workspace.dtype != torch.uint8:
+            raise ValueError("workspace must be a uint8 tensor on the nodes' device")
+        if workspace.numel() < nbytes:
+            raise ValueError(f"workspace holds {workspace.numel()} bytes, {nbytes} needed")
+        return workspace
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
+                    oversample: int = 4, side: int = EXTERIOR, kind: int = S,
+                    tape: Optional[torch.Tensor] = None,
+                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One-sided QBX limits, out[n_sides, n_kinds, 16*P] complex128 (exterior first)."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    out = torch.empty((n_sides(side), nk, P * Q), dtype=torch.complex128, device=dev)
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    tp = None
+    if tape is not None:
+        need = tape_bytes(P, p, side, kind)
+        if tape.device != dev or tape.numel() * tape.element_size() < need:
+            raise ValueError("tape too small or on the wrong device")
+        tp = tape.data_ptr()
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    rc = lib.qbx_layer_potential(C.byref(geo), density.data_ptr(), float(k), int(p), float(r),
+                                 int(oversample), int(side), int(kind), out.data_ptr(), tp,
+                                 ws.data_ptr(), ws.numel(), _stream(dev))
+    _lib.check(rc)
+    return out
+
+
+def check_geometry(nodes: torch.Tensor, p: int, r: float = 0.5, oversample: int = 4,
+                   side: int = EXTERIOR) -> Tuple[int, float, float]:
+    """Synchronous check: (status, signed area, min |x'-c|/R).  status is 0, QBX_EORIENT
+    or QBX_EGRAF."""
+    lib = _lib.load()
+    P = int(nodes.shape[0])
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    ws = torch.empty(workspace_bytes(P, p, oversample, side, S), dtype=torch.uint8,
+                     device=nodes.device)
+    area, ratio = C.c_double(), C.c_double()
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    rc = lib.qbx_check_geometry(C.byref(geo), int(p), float(r), int(oversample), int(side),
+                                C.byref(area), C.byref(ratio), ws.data_ptr(), ws.numel(),
+                                _stream(nodes.device))
+    if rc not in (_lib.QBX_OK, _lib.QBX_EORIENT, _lib.QBX_EGRAF):
+        _lib.check(rc)
+    return rc, area.value, ratio.value
+
+
+def hankel01(z: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+    """H_0^(1)(z), H_1^(1)(z) as the pair kernels compute them (test hook)."""
+    lib = _lib.load()
+    _need(z, "z", torch.float64, (z.numel(),))
+    h0 = torch.empty(z.numel(), dtype=torch.complex128, device=z.device)
+    h1 = torch.empty_like(h0)
+    _lib.check(lib.qbx_debug_hankel01(z.data_ptr(), z.numel(), h0.data_ptr(), h1.data_ptr(),
+                                      _stream(z.device)))
+    return h0, h1
+
+
+def besselj_table(x: torch.Tensor, L: int) -> torch.Tensor:
+    """J_0..J_L(x) by the library's Miller recurrence (test hook): [n, L+1]."""
+    lib = _lib.load()
+    _need(x, "x", torch.float64, (x.numel(),))
+    out = torch.empty((x.numel(), L + 1), dtype=torch.float64, device=x.device)
+    _lib.check(lib.qbx_debug_besselj(x.data_ptr(), x.numel(), int(L), out.data_ptr(),
+                                     _stream(x.device)))
+    return out

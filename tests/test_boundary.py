@@ -1,0 +1,118 @@
+"""Host-side tests of the C ABI (no GPU): the library loads, exports every symbol
+of include/qbx.h, sizes workspaces, and rejects bad arguments before anything
+reaches the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1207_4461_amd import _lib, inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qbx.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(qbx_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert "qbx_layer_potential" in names and "qbx_layer_potential_adjoint" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (qbx_[a-z0-9_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_workspace_sizes(lib):
+    n1 = lib.qbx_workspace_bytes(32, 16, 8, 4, I.EXTERIOR, 1)
+    n2 = lib.qbx_workspace_bytes(64, 16, 8, 4, I.EXTERIOR, 1)
+    n3 = lib.qbx_workspace_bytes(32, 16, 8, 4, I.BOTH, 3)
+    assert 0 < n1 < n2 and n1 < n3 and n1 % 256 == 0
+    # invalid parameters give 0
+    assert lib.qbx_workspace_bytes(2, 16, 8, 4, 1, 1) == 0
+    assert lib.qbx_workspace_bytes(32, 8, 8, 4, 1, 1) == 0
+    assert lib.qbx_workspace_bytes(32, 16, 25, 4, 1, 1) == 0
+    assert lib.qbx_workspace_bytes(32, 16, 8, 0, 1, 1) == 0
+    assert lib.qbx_workspace_bytes(32, 16, 8, 4, 2, 1) == 0
+    assert lib.qbx_workspace_bytes(32, 16, 8, 4, 1, 4) == 0
+    assert lib.qbx_tape_bytes(32, 16, 8, I.BOTH, 3) > 0
+
+
+BAD = C.c_void_p(16)  # never dereferenced: validation fails first
+
+
+def _call(lib, P=8, q=16, nodes=BAD, dens=BAD, k=3.0, p=6, r=0.5, os_=4, side=1, kind=1,
+          out=BAD, ws=BAD, nbytes=1 << 40):
+    g = _lib.Geometry(P, q, nodes)
+    return lib.qbx_layer_potential(C.byref(g), dens, k, p, r, os_, side, kind, out, None, ws,
+                                   nbytes, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(P=2), dict(q=8), dict(p=-1), dict(p=25), dict(k=0.0), dict(k=-1.0), dict(k=float("nan")),
+    dict(k=float("inf")), dict(r=0.0), dict(r=float("nan")), dict(os_=0), dict(os_=9),
+    dict(side=2), dict(kind=0), dict(kind=4), dict(nodes=None), dict(dens=None), dict(out=None),
+    dict(ws=None),
+])
+def test_invalid_arguments_are_rejected_on_the_host(lib, kw):
+    assert _call(lib, **kw) == _lib.QBX_EINVAL
+    assert len(lib.qbx_last_error()) > 0
+
+
+def test_small_workspace_is_rejected(lib):
+    need = lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1)
+    assert _call(lib, nbytes=need - 1) == _lib.QBX_EWORKSPACE
+    assert b"needed" in lib.qbx_last_error()
+
+
+def test_null_geometry_and_adjoint_args(lib):
+    assert lib.qbx_layer_potential(None, BAD, 1.0, 4, 0.5, 4, 1, 1, BAD, None, BAD, 1 << 40,
+                                   None) == _lib.QBX_EINVAL
+    g = _lib.Geometry(8, 16, BAD)
+    assert lib.qbx_layer_potential_adjoint(C.byref(g), BAD, 1.0, 30, 0.5, 4, 1, 1, BAD, None,
+                                           BAD, BAD, BAD, 1 << 40, None) == _lib.QBX_EINVAL
+    assert lib.qbx_layer_potential_adjoint(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, None, None,
+                                           BAD, BAD, BAD, 1 << 40, None) == _lib.QBX_EINVAL
+    assert lib.qbx_check_geometry(None, 4, 0.5, 4, 1, None, None, BAD, 1 << 40,
+                                  None) == _lib.QBX_EINVAL
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(lib.qbx_strerror(code)) > 3
+    assert lib.qbx_strerror(-99) == b"unknown error"
+
+
+def test_signed_area_host_and_orientation(lib):
+    pb = I.small(n_panels=12)
+    nodes = np.ascontiguousarray(pb.nodes)
+    area = C.c_double()
+    assert lib.qbx_signed_area_host(nodes.ctypes.data, 12, C.byref(area)) == _lib.QBX_OK
+    # area enclosed by r(t) = 1 + 0.15 cos(3t + 0.3): pi (1 + 0.15^2 / 2)
+    assert abs(area.value - np.pi * (1 + 0.15**2 / 2)) < 1e-12
+    rev = np.ascontiguousarray(nodes[::-1, ::-1, :])     # same curve, clockwise
+    assert lib.qbx_signed_area_host(rev.ctypes.data, 12, C.byref(area)) == _lib.QBX_EORIENT
+    assert area.value < 0
+    assert lib.qbx_signed_area_host(None, 12, None) == _lib.QBX_EINVAL
+    assert lib.qbx_signed_area_host(nodes.ctypes.data, 2, None) == _lib.QBX_EINVAL
+
+
+def test_debug_hooks_validate(lib):
+    assert lib.qbx_debug_hankel01(None, 4, None, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_debug_besselj(BAD, 4, 99, BAD, None) == _lib.QBX_EINVAL
