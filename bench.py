@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the QBX hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg4] [--mode fwdbwd]
+
+A step is one pass of the whole hot path over one batch of synthetic input that
+already sits in HBM: source grid and centers (upsampling), the pair kernels,
+evaluation, and (mode fwdbwd) the adjoint for the density and node gradients.
+Prints ONE JSON line: interactions/s (centers x sources x operators per second,
+forward and forward+backward), the dominant kernel's achieved FP64 rate against
+MI355X's vector FP64 peak (its launch durations timed with HIP events on the
+launch stream), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("QBX source-center interactions/s, fwd & fwd+bwd, FP64 @≤1e-11 rel; "
+          "% FP64 peak")
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg4", choices=["cfg0", "cfg1", "cfg2", "cfg4"])
+    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=10, help="targets in the oracle sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the hot path runs on a single "
+              "MI355X; how it would shard is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_1207_4461_amd import _lib, flops, inputs as I, qbx
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lib = _lib.load()
+    have_bwd = hasattr(qbx, "layer_potential_vjp")
+    mode = args.mode or ("fwdbwd" if have_bwd else "fwd")
+    if mode == "fwdbwd" and not have_bwd:
+        raise SystemExit("adjoint not available in this build")
+    pb = getattr(I, args.workload)()
+    dev = torch.device("cuda:0")
+    nodes = torch.from_numpy(pb.nodes).to(dev)
+    dens = torch.from_numpy(np.ascontiguousarray(pb.density)).to(dev)
+    cot = torch.from_numpy(np.ascontiguousarray(pb.cotangent)).to(dev)
+    ws = torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side, pb.kind),
+                     dtype=torch.uint8, device=dev)
+    log(f"workload {args.workload} ({pb.name}): P={pb.n_panels} p={pb.p} k={pb.k} "
+        f"centers={pb.n_centers} sources={pb.n_sources} kind={pb.kind} mode={mode}")
+
+    def fwd():
+        return qbx.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                   workspace=ws)
+
+    def step():
+        u = fwd()
+        if mode == "fwdbwd":
+            qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                    pb.kind, workspace=ws)
+        return u
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # forward alone (for the fwd interactions/s figure)
+    nfwd = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(nfwd):
+        fwd()
+    torch.cuda.synchronize()
+    fwd_s = (time.perf_counter() - t0) / nfwd
+
+    # timed steps
+    lib.qbx_kernel_timer(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = (C.c_double * 3)()
+    nl = (C.c_int * 3)()
+    _lib.check(lib.qbx_kernel_timer_read(ms, nl))
+    lib.qbx_kernel_timer(0)
+    step_ms = dt / args.steps * 1e3
+    inter = flops.interactions(pb.n_centers, pb.n_sources, pb.kind)
+    value = inter / (dt / args.steps)
+
+    # dominant kernel: the class with the largest total time
+    names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel"]
+    cls = max(range(3), key=lambda c: ms[c])
+    avg_ms = ms[cls] / max(nl[cls], 1)
+    pairs = pb.n_centers * pb.n_sources
+    if cls == 0:
+        fl = flops.flops_forward_pair(pb.p, pb.kind) * pairs
+    else:
+        fl = flops.flops_adjoint_pair(pb.p, pb.kind) * pairs
+    achieved = fl / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": names[cls], "kernel_avg_ms": round(avg_ms, 4),
+            "launches": int(nl[cls]), "flop_per_launch": fl}
+    log(f"step {step_ms:.2f} ms, {names[cls]} avg {avg_ms:.3f} ms, {achieved:.2f} TFLOP/s")
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if args.cpu_baseline:
+        from oracle import qbx_oracle as O
+
+        rng = np.random.default_rng(0)
+        idx = np.sort(rng.choice(pb.n_targets, size=min(args.cpu_sample, pb.n_targets),
+                                 replace=False))
+        t0 = time.perf_counter()
+        ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                pb.kind, targets=idx).numpy()
+        tc = time.perf_counter() - t0
+        ncent = len(idx) * pb.n_sides
+        cpu_inter = flops.interactions(ncent, pb.n_sources, pb.kind)
+        u = fwd().cpu().numpy()[:, :, idx]
+        err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
+                        for s in range(u.shape[0]) for k in range(u.shape[1])))
+        cpu = {"value": cpu_inter / tc, "unit": "interactions/s", "cores": torch.get_num_threads(),
+               "kind": "oracle",
+               "sample": f"forward at {len(idx)} random targets x {pb.n_sides} sides "
+                         f"({ncent} centers) against all {pb.n_sources} sources, "
+                         f"{tc:.1f} s; GPU/oracle max rel err on the sample {err:.2e}"}
+        log(f"cpu oracle: {cpu_inter / tc:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {pb.name}, {pb.n_panels} panels x 16 nodes, "
+                               f"oversample {pb.oversample}, k={pb.k}, p={pb.p}, "
+                               f"side={'both' if pb.side == 0 else pb.side}, "
+                               f"kind={'S+D' if pb.kind == 3 else ('S' if pb.kind == 1 else 'D')}",
+                   "mode": mode, "centers": pb.n_centers, "sources": pb.n_sources,
+                   "interactions_per_step": inter},
+        "fwd_value": inter / fwd_s,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,20 @@ int qbx_debug_hankel01(const double* z, int n, double* h0, double* h1, hipStream
  * x [n], out [n][L+1]. L <= QBX_PMAX + 3. */
 int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t stream);
 
+/* ---- kernel timing (profiling hook) ----------------------------------- */
+
+/* enable != 0: from now on every launch of a pair kernel (the forward and
+ * adjoint hot loops) is bracketed by two hipEvents recorded on the caller's
+ * stream; enable == 0 stops it and drops the records.  Host-side bookkeeping
+ * only; not thread-safe. */
+int qbx_kernel_timer(int enable);
+
+/* SYNCHRONOUS: waits for the recorded events and returns, per kernel class
+ * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
+ * kernel), the summed duration in milliseconds and the number of launches
+ * since the timer was enabled.  ms and launches are host arrays of 3. */
+int qbx_kernel_timer_read(double* ms, int* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,8 @@ def load() -> C.CDLL:
         "qbx_last_error": (C.c_char_p, []),
         "qbx_debug_hankel01": (i32, [vp, i32, vp, vp, vp]),
         "qbx_debug_besselj": (i32, [vp, i32, i32, vp, vp]),
+        "qbx_kernel_timer": (i32, [i32]),
+        "qbx_kernel_timer_read": (i32, [C.POINTER(dbl), C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

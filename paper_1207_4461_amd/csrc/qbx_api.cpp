@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/qbx.h"
 #include "qbx_internal.h"
@@ -117,6 +118,44 @@ static int validate(const qbx_geometry* g, int p, double k, double r, int oversa
   return QBX_OK;
 }
 
+// ---- kernel timer ----
+struct TimerRec {
+  int cls;
+  hipEvent_t a, b;
+};
+static bool g_timer_on = false;
+static std::vector<TimerRec> g_timer;
+static hipEvent_t g_pending[3];
+
+void timer_begin(int cls, hipStream_t s) {
+  if (!g_timer_on) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEventRecord(e, s);
+  g_pending[cls] = e;
+}
+
+void timer_end(int cls, hipStream_t s) {
+  if (!g_timer_on || !g_pending[cls]) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEventRecord(e, s);
+  g_timer.push_back({cls, g_pending[cls], e});
+  g_pending[cls] = nullptr;
+}
+
+static void timer_clear() {
+  for (auto& r : g_timer) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_timer.clear();
+  for (auto& e : g_pending) {
+    if (e) hipEventDestroy(e);
+    e = nullptr;
+  }
+}
+
 // tables + source grid + centers into the workspace
 static int prepare(const Dims& d, const Layout& L, const double* nodes, const double* density,
                    void* ws, hipStream_t stream) {
@@ -163,9 +202,11 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
+  timer_begin(0, stream);
   hipError_t e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                                 at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                                 at<double2>(ws, L.partial), stream);
+  timer_end(0, stream);
   if (e != hipSuccess) return device_fail(e, "forward kernel");
   e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
   if (e != hipSuccess) return device_fail(e, "finalize kernel");
@@ -252,6 +293,30 @@ int qbx_signed_area_host(const double* nodes, int n_panels, double* area) {
   if (area) *area = A;
   if (!std::isfinite(A)) return fail(QBX_EINVAL, "non-finite node coordinates");
   if (A < 0.0) return fail(QBX_EORIENT, "signed area %g < 0: contour is clockwise", A);
+  return QBX_OK;
+}
+
+int qbx_kernel_timer(int enable) {
+  timer_clear();
+  g_timer_on = enable != 0;
+  return QBX_OK;
+}
+
+int qbx_kernel_timer_read(double* ms, int* launches) {
+  if (!ms || !launches) return fail(QBX_EINVAL, "NULL output array");
+  for (int c = 0; c < 3; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (auto& r : g_timer) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return device_fail(e, "event synchronize");
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return device_fail(e, "event elapsed time");
+    ms[r.cls] += t;
+    launches[r.cls] += 1;
+  }
   return QBX_OK;
 }
 

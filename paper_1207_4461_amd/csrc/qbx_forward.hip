@@ -35,16 +35,17 @@
 namespace qbx {
 
 template <int P, int KIND>
-__device__ __forceinline__ void pair_kernel(double z, double cd, double sd, double cps, double sps,
-                                            const double* __restrict__ J, double& s_r, double& s_i,
-                                            double& d_r, double& d_i) {
+__device__ __forceinline__ void pair_kernel(double z, double iz, double cd, double sd, double cps,
+                                            double sps, const double* __restrict__ J,
+                                            const double* __restrict__ cf, double& s_r,
+                                            double& s_i, double& d_r, double& d_i) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int LMAX = kD ? P + 1 : P;
-  const H01 h = hankel01(z);
+  const H01 h = hankel01(z, iz, cf);
   double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
   double hc_r = h.h1r, hc_i = h.h1i;  // H_l
-  const double tz = 2.0 / z;
+  const double tz = 2.0 * iz;
   double tl = tz;                     // 2l/z
   const double two_cd = 2.0 * cd;
   // l = 0 terms
@@ -120,16 +121,18 @@ __global__ __launch_bounds__(256) void k_forward(const double4* __restrict__ geo
   const int sp = gw - ci * n_split;
   if (ci >= Mc) return;
   const double cx = ctr[ci].cx, cy = ctr[ci].cy, ct = ctr[ci].ct, st = ctr[ci].st;
-  double J[P + 3];
-  const double* Jc = jtab + (size_t)ci * NJ;
-#pragma unroll
-  for (int l = 0; l < P + 3; ++l) J[l] = Jc[l];
+  const double inv_k = 1.0 / k;
+  const double* Jtab = jtab + (size_t)ci * NJ;
   double accS_r = 0.0, accS_i = 0.0, accD_r = 0.0, accD_i = 0.0;
   const int c0 = sp * chunks_per_split;
   const int c1 = min(c0 + chunks_per_split, chunks);
   for (int c = c0; c < c1; ++c) {
     const int j = c * kWave + lane;
     if (j < N) {
+      // uniform tables re-read (scalar cache) every iteration, see opaque_zero()
+      const int z0 = opaque_zero();
+      const double* __restrict__ J = Jtab + z0;
+      const double* __restrict__ cf = g_seed_table + z0;
       const double4 g = geo[j];
       const double vx = g.x - cx, vy = g.y - cy;
       const double rho = sqrt(fma(vx, vx, vy * vy));
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256) void k_forward(const double4* __restrict__ geo
         sps = st * g.z - ct * g.w;                   // sin(theta_i - arg nu)
       }
       double s_r, s_i, d_r, d_i;
-      pair_kernel<P, KIND>(k * rho, cd, sd, cps, sps, J, s_r, s_i, d_r, d_i);
+      pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, s_r, s_i, d_r, d_i);
       if (kS) {
         const double2 w = dens[j];
         accS_r = fma(w.x, s_r, fma(-w.y, s_i, accS_r));

@@ -241,7 +241,7 @@ __global__ void k_debug_hankel01(const double* __restrict__ z, int n, double* __
                                  double* __restrict__ h1) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const H01 h = hankel01(z[i]);
+  const H01 h = hankel01(z[i], 1.0 / z[i], g_seed_table);
   h0[2 * i] = h.h0r;
   h0[2 * i + 1] = h.h0i;
   h1[2 * i] = h.h1r;

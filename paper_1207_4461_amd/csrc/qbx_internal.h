@@ -97,3 +97,10 @@ hipError_t launch_debug_hankel01(const double* z, int n, double* h0, double* h1,
 hipError_t launch_debug_besselj(const double* x, int n, int L, double* out, hipStream_t s);
 
 }  // namespace qbx
+
+namespace qbx {
+// kernel timer (qbx_kernel_timer): records an event pair around a launch of
+// kernel class `cls` when enabled; no-op otherwise
+void timer_begin(int cls, hipStream_t s);
+void timer_end(int cls, hipStream_t s);
+}  // namespace qbx

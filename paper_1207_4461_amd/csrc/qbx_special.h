@@ -10,22 +10,139 @@
 
 #include <hip/hip_runtime.h>
 
+#include "qbx_seed_coeffs.h"
+
 namespace qbx {
 
 // ---------------------------------------------------------------------------
-// Hankel seeds.  The ROCm device math library supplies j0, j1, y0, y1.
+// Hankel seeds H_0(z), H_1(z), z > 0 (coefficients: qbx_seed_coeffs.h, made by
+// gen_seed_coeffs.py from 40-digit reference values and exact rationals).
+//  * z >= Z0 = 6: H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} (P_nu + i Q_nu)
+//    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
+//    e^{i(z - pi/4)} by a three-part Cody-Waite reduction z = m pi/4 + r, m odd,
+//    |r| <= pi/4, and Taylor polynomials of sin r / r and cos r (DLMF 4.19.1);
+//    the phase of H_1 is that of H_0 turned by -pi/2.
+//  * z < Z0: Y_nu = (2/pi)(ln(z/2) + gamma) J_nu - nu 2/(pi z) + R_nu with J_nu, R_nu
+//    entire (DLMF 10.8.1, 10.8.2): for z < Z1 = 4 their ascending series in
+//    w = z^2/4 (DLMF 10.2.2), for Z1 <= z < Z0 polynomial fits in (z - 5).
+// Error <~ 2e-15 |H| for every z in (0, 2^20) (range of the reduction).
 // ---------------------------------------------------------------------------
 struct H01 {
   double h0r, h0i, h1r, h1i;
 };
 
-__device__ __forceinline__ H01 hankel01(double z) {
+struct D4 {
+  double a, b, c, d;
+};
+
+// Four interleaved polynomials c[4i + 0..3], i < LEN, at x, accumulated in the
+// power basis (x^i shared by the four): each step is one multiply for x^i and one
+// fused multiply-add per polynomial with the wave-uniform coefficient as a
+// multiplicand.  The polynomials are well conditioned on their ranges (|x| <= 1,
+// decaying coefficients), so the summation order costs no accuracy.
+template <int LEN>
+__host__ __device__ __forceinline__ D4 horner4(const double* __restrict__ c, double x) {
+  D4 r = {c[0], c[1], c[2], c[3]};
+  double pw = x;
+#pragma unroll
+  for (int i = 1; i < LEN; ++i) {
+    r.a = fma(c[4 * i], pw, r.a);
+    r.b = fma(c[4 * i + 1], pw, r.b);
+    r.c = fma(c[4 * i + 2], pw, r.c);
+    r.d = fma(c[4 * i + 3], pw, r.d);
+    if (i + 1 < LEN) pw *= x;
+  }
+  return r;
+}
+
+// two interleaved polynomials c[2i + 0..1], same scheme
+template <int LEN>
+__host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, double x, double& a,
+                                                 double& b) {
+  a = c[0];
+  b = c[1];
+  double pw = x;
+#pragma unroll
+  for (int i = 1; i < LEN; ++i) {
+    a = fma(c[2 * i], pw, a);
+    b = fma(c[2 * i + 1], pw, b);
+    if (i + 1 < LEN) pw *= x;
+  }
+}
+
+// iz = 1/z (callers already hold it); cf = the coefficient table seed::kTable
+// (QBX_SEED_TABLE_VALUES), read with wave-uniform loads
+__host__ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __restrict__ cf) {
+  constexpr double kTwoOverPi = 0.63661977236758134308;
+  constexpr double kSqrtTwoOverPi = 0.79788456080286535588;
+  constexpr double kEuler = 0.57721566490153286061;
+  constexpr double kInvTwoPi = 0.15915494309189533577;
   H01 h;
-  h.h0r = j0(z);
-  h.h0i = y0(z);
-  h.h1r = j1(z);
-  h.h1i = y1(z);
+  if (z >= seed::kZ0) {
+    const double t = seed::kZ0 * iz;
+    const double s = t * t;
+    const D4 pq = horner4<seed::kLARGELen>(cf + seed::kLARGEOff, s);
+    const double P0 = pq.a, Q0 = t * pq.b, P1 = pq.c, Q1 = t * pq.d;
+    // z - pi/4 = r + q pi/2 with r = z - (2q+1) pi/4
+    const double q = rint(fma(z, kTwoOverPi, -0.5));
+    const double m = fma(2.0, q, 1.0);
+    double r = fma(-m, seed::kPio4Hi, z);
+    r = fma(-m, seed::kPio4Mid, r);
+    r = fma(-m, seed::kPio4Lo, r);
+    const double u = r * r;
+    double sn, cs;
+    horner2<seed::kTRIGLen>(cf + seed::kTRIGOff, u, sn, cs);
+    sn *= r;
+    const int qi = ((int)q) & 3;
+    // e^{i q pi/2} (cs + i sn)
+    double er = (qi & 1) ? -sn : cs;
+    double ei = (qi & 1) ? cs : sn;
+    if (qi & 2) {
+      er = -er;
+      ei = -ei;
+    }
+    const double A = kSqrtTwoOverPi * sqrt(iz);
+    er *= A;
+    ei *= A;
+    h.h0r = fma(er, P0, -ei * Q0);     // E (P0 + i Q0)
+    h.h0i = fma(er, Q0, ei * P0);
+    h.h1r = fma(er, Q1, ei * P1);      // E (Q1 - i P1)
+    h.h1i = fma(ei, Q1, -er * P1);
+  } else {
+    const double L = log(0.5 * z) + kEuler;
+    double J0, J1, R0, R1;   // Y0 = (2/pi) L J0 + R0,  Y1 = (2/pi)(L J1 - 1/z) + R1
+    if (z >= seed::kZ1) {
+      const D4 f = horner4<seed::kMIDLen>(cf + seed::kMIDOff, (z - seed::kZC) * seed::kInvZH);
+      J0 = f.a;
+      R0 = f.b;
+      J1 = f.c;
+      R1 = f.d;
+    } else {
+      const double w = 0.25 * z * z;
+      const D4 f = horner4<seed::kSERLen>(cf + seed::kSEROff, w);
+      J0 = f.a;
+      J1 = 0.5 * z * f.b;
+      R0 = kTwoOverPi * f.c;
+      R1 = -kInvTwoPi * z * f.d;
+    }
+    h.h0r = J0;
+    h.h0i = fma(kTwoOverPi * L, J0, R0);
+    h.h1r = J1;
+    h.h1i = fma(kTwoOverPi * L, J1, fma(-kTwoOverPi, iz, R1));
+  }
   return h;
+}
+
+// Device copy of the seed coefficient table (one per translation unit).
+static __constant__ double g_seed_table[seed::kTableLen] = {QBX_SEED_TABLE_VALUES};
+
+// An SGPR zero the compiler cannot see through: offsetting a table pointer by it
+// inside a loop keeps the (uniform, scalar-cached) table loads in the loop instead
+// of hoisting hundreds of constants into registers.
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,54 @@
+"""Algorithmic FP64 operation counts of the pair kernels, per (center, source) pair.
+
+Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, divide and
+rint = 1 each.  The counts follow the kernels' formulas for the common branch
+(z = k*rho >= 6, the asymptotic seed), line by line:
+
+forward pair (one center, one source, order p):
+  geometry      v = x'-c (2), rho = sqrt(vx^2+vy^2) (4), 1/rho (1), cos/sin of
+                theta_i - theta' (8), z and 1/z (2)                        = 17
+  D geometry    cos/sin(theta_i - arg nu) (6)
+  seed H0, H1   4 interleaved degree-12 polynomials in (6/z)^2 (107),
+                Cody-Waite reduction (11), sin/cos polynomials (45), scale
+                and rotations (20), (6/z)^2 (2)                             = 184 (+1 for Q scaling)
+  recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
+  S per order   J_l cos(l D) (1) + accumulate (4) + Chebyshev cos (2)        =  7
+  D per order   J_{l+1} cos(lD+psi) - J_{l-1} cos(lD-psi) (3) + accumulate (4)
+                + two Chebyshev sequences (4)                                = 11
+  accumulation  w sigma K (8 per kind)
+
+Totals (derived in flops_forward_pair below; exact for the kernel code):
+  S:   210 + 12 p        D:   229 + 16 p        S+D: 243 + 23 p
+"""
+from __future__ import annotations
+
+
+def flops_forward_pair(p: int, kind: int) -> int:
+    """FP64 flops per (center, source) pair of the forward pair kernel."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    outer = 2 + 4 + 1 + 4 + 4 + 2          # v, rho, 1/rho, cos D, sin D, z, 1/z
+    if D:
+        outer += 6                          # cos psi, sin psi
+    outer += 8 * (int(S) + int(D))          # w*density*K accumulation
+    seed = 184
+    setup = 2                               # 2/z, 2 cos D
+    if S:
+        setup += 2 + 4                      # H0 J0 term, final 2*sum + term
+    if D:
+        setup += 3 + 6                      # H0 J1 cos psi term, cos(D +- psi)
+    lmax = p + 1 if D else p
+    orders = 0
+    for l in range(1, lmax + 1):
+        if S and l <= p:
+            orders += 5
+        if D:
+            orders += 7 if l <= p - 1 else 5
+        if l < lmax:
+            orders += 5 + (2 if S else 0) + (4 if D else 0)
+    return outer + seed + setup + orders
+
+
+def interactions(n_centers: int, n_sources: int, kind: int) -> int:
+    """Source-center interactions: centers x sources x operators."""
+    return n_centers * n_sources * (2 if kind == 3 else 1)
