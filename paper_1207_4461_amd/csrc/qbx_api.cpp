@@ -53,7 +53,7 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   d->nk = (kind == 3) ? 2 : 1;
   d->p = p;
   d->Mc = (int)Mc;
-  d->NJ = p + 3;
+  d->NJ = 2 * (p + 4);   // J_0..J_{p+3}, then J'_0..J'_{p+3}
   d->side = side;
   d->kind = kind;
   d->k = k;
@@ -69,6 +69,14 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   if (split < 1) split = 1;
   d->chunks_per_split = (int)((d->chunks + split - 1) / split);
   d->n_split = (d->chunks + d->chunks_per_split - 1) / d->chunks_per_split;
+  // adjoint: one wave per 64 sources and center split, >= 16 centers per split
+  long cs = (want_waves + d->chunks - 1) / d->chunks;
+  long max_cs = Mc / 16;
+  if (max_cs < 1) max_cs = 1;
+  if (cs > max_cs) cs = max_cs;
+  if (cs < 1) cs = 1;
+  d->centers_per_split = (int)((Mc + cs - 1) / cs);
+  d->n_csplit = (int)((Mc + d->centers_per_split - 1) / d->centers_per_split);
   return true;
 }
 
@@ -87,7 +95,13 @@ Layout make_layout(const Dims& d) {
   L.h = take(sizeof(double) * (size_t)d.P);
   L.ctr = take(sizeof(CenterRec) * (size_t)d.Mc);
   L.jtab = take(sizeof(double) * (size_t)d.Mc * d.NJ);
-  L.partial = take(sizeof(double2) * (size_t)d.n_split * d.nk * d.Mc);
+  L.partial = take(sizeof(double2) * (size_t)d.n_split * d.nk * d.Mc * 5);
+  L.tape = take(sizeof(double2) * (size_t)d.Mc * d.nk * 4);
+  L.G = take(sizeof(double2) * (size_t)d.nk * d.Mc);
+  L.cg = take(sizeof(double) * (size_t)d.Mc * 8);
+  const int NA = (d.kind & 1 ? 3 : 0) + (d.kind & 2 ? 4 : 0);
+  L.spart = take(sizeof(double2) * (size_t)d.n_csplit * NA * d.N);
+  L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
   L.total = o;
   return L;
@@ -183,14 +197,13 @@ size_t qbx_workspace_bytes(int n_panels, int q, int p, int oversample, int side,
 size_t qbx_tape_bytes(int n_panels, int q, int p, int side, int kind) {
   Dims d;
   if (!make_dims(n_panels, q, p, 1, side, kind, 1.0, 0.5, &d)) return 0;
-  // per center and kind: the boundary coefficients a_{+-p}, a_{+-(p+1)}, a_{+-(p+2)}
-  return sizeof(double2) * (size_t)d.Mc * d.nk * 8;
+  // per center and kind: sum_j w sigma dK/dR, dK/dtheta and grad_v K (x, y)
+  return sizeof(double2) * (size_t)d.Mc * d.nk * 4;
 }
 
 int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, int p, double r,
                         int oversample, int side, int kind, double* out, double* tape, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
-  (void)tape;
   Dims d;
   int rc = validate(g, p, k, r, oversample, side, kind, &d);
   if (rc) return rc;
@@ -202,10 +215,22 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
+  hipError_t e;
+  if (tape) {
+    timer_begin(0, stream);
+    e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                            at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                            at<double2>(ws, L.partial), stream);
+    timer_end(0, stream);
+    if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
+    e = launch_finalize_tape(d, at<double2>(ws, L.partial), out, reinterpret_cast<double2*>(tape),
+                             stream);
+    if (e != hipSuccess) return device_fail(e, "finalize (tape) kernel");
+    return QBX_OK;
+  }
   timer_begin(0, stream);
-  hipError_t e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
-                                at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
-                                at<double2>(ws, L.partial), stream);
+  e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens), at<CenterRec>(ws, L.ctr),
+                     at<double>(ws, L.jtab), at<double2>(ws, L.partial), stream);
   timer_end(0, stream);
   if (e != hipSuccess) return device_fail(e, "forward kernel");
   e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
@@ -218,10 +243,39 @@ int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, do
                                 const double* cotangent, const double* tape, double* grad_density,
                                 double* grad_nodes, void* ws, size_t ws_bytes,
                                 hipStream_t stream) {
-  (void)g; (void)density; (void)k; (void)p; (void)r; (void)oversample; (void)side; (void)kind;
-  (void)cotangent; (void)tape; (void)grad_density; (void)grad_nodes; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return fail(QBX_EINVAL, "adjoint not built yet");
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!cotangent) return fail(QBX_EINVAL, "cotangent is NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  if (!grad_density && !grad_nodes) return QBX_OK;
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  hipError_t e;
+  const double2* tp = reinterpret_cast<const double2*>(tape);
+  if (!tp) {
+    timer_begin(0, stream);
+    e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                            at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                            at<double2>(ws, L.partial), stream);
+    timer_end(0, stream);
+    if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
+    e = launch_finalize_tape(d, at<double2>(ws, L.partial), nullptr, at<double2>(ws, L.tape),
+                             stream);
+    if (e != hipSuccess) return device_fail(e, "finalize (tape) kernel");
+    tp = at<double2>(ws, L.tape);
+  }
+  e = launch_adjoint_rest(d, g->nodes, density, at<double>(ws, L.tables), at<double4>(ws, L.geo),
+                          at<double2>(ws, L.dens), at<CenterRec>(ws, L.ctr),
+                          at<double>(ws, L.jtab), cotangent, tp, at<double2>(ws, L.G),
+                          at<double>(ws, L.cg), at<double2>(ws, L.spart), at<double>(ws, L.sg),
+                          grad_density, grad_nodes, stream);
+  if (e != hipSuccess) return device_fail(e, "adjoint kernels");
+  return QBX_OK;
 }
 
 int qbx_check_geometry(const qbx_geometry* g, int p, double r, int oversample, int side,

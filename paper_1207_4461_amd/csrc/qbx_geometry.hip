@@ -163,7 +163,14 @@ __global__ __launch_bounds__(128) void k_upsample(Dims d, const double* __restri
     c.pad = 0.0;
     const size_t ci = (size_t)si * d.T + (size_t)m * kQ + a;
     ctr[ci] = c;
-    bessel_j_miller(d.k * R, d.NJ - 1, jtab + ci * d.NJ);
+    double* Jt = jtab + ci * d.NJ;
+    const int nj = d.NJ / 2;
+    bessel_j_miller(d.k * R, nj - 1, Jt);
+    // J'_l = (J_{l-1} - J_{l+1}) / 2 (DLMF 10.6.1), J'_0 = -J_1; the last one
+    // from J_{l-1} - (l/x) J_l (DLMF 10.6.2)
+    Jt[nj] = -Jt[1];
+    for (int l = 1; l + 1 < nj; ++l) Jt[nj + l] = 0.5 * (Jt[l - 1] - Jt[l + 1]);
+    Jt[2 * nj - 1] = (d.k * R > 0.0) ? Jt[nj - 2] - (nj - 1) / (d.k * R) * Jt[nj - 1] : 0.0;
   }
 }
 

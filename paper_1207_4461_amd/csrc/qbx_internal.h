@@ -29,7 +29,7 @@ struct Dims {
   int nk;       // kinds (1 or 2)
   int p;        // expansion order
   int Mc;       // centers (T * n_sides)
-  int NJ;       // J table length per center (J_0 .. J_{NJ-1})
+  int NJ;       // J table length per center: J_0..J_{p+3}, J'_0..J'_{p+3}
   int side;     // QBX_INTERIOR / QBX_BOTH / QBX_EXTERIOR
   int kind;     // bit mask S=1, D=2
   double k, r;
@@ -37,6 +37,9 @@ struct Dims {
   int chunks;            // ceil(N / 64)
   int n_split;           // source splits per center
   int chunks_per_split;  // 64-source chunks per split
+  // adjoint source-major launch shape
+  int n_csplit;           // center splits per 64-source chunk
+  int centers_per_split;  // centers per split
 };
 
 // Byte offsets of the workspace arrays (all 256-byte aligned).
@@ -48,8 +51,13 @@ struct Layout {
   size_t h;        // double[P] panel lengths
   size_t ctr;      // CenterRec[Mc]
   size_t jtab;     // double[Mc][NJ]
-  size_t partial;  // double2[n_split][nk][Mc]
-  size_t scratch;  // double[4096] small reductions
+  size_t partial;  // double2[n_split][nk][Mc][5] (the plain forward uses the first part)
+  size_t tape;     // double2[Mc][nk][4] tape recomputed by the adjoint when none is given
+  size_t G;        // double2[nk][Mc] conj(cotangent) i/4
+  size_t cg;       // double[Mc][8] per-center gradients
+  size_t spart;    // double2[n_csplit][NA][N] source-pass partial sums
+  size_t sg;       // double[N][8] per-source gradients
+  size_t scratch;  // double[16 + Mc] small reductions
   size_t total;
 };
 
@@ -90,6 +98,18 @@ hipError_t launch_forward(const Dims& d, const double4* geo, const double2* dens
                           const CenterRec* ctr, const double* jtab, double2* partial,
                           hipStream_t s);
 hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s);
+// ---- adjoint (qbx_adjoint.hip) ----
+hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
+                               const CenterRec* ctr, const double* jtab, double2* partial,
+                               hipStream_t s);
+hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
+                                hipStream_t s);
+hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
+                               const double* tables, const double4* geo, const double2* dens,
+                               const CenterRec* ctr, const double* jtab, const double* cot,
+                               const double2* tape, double2* G, double* cg, double2* spartial,
+                               double* sg, double* grad_density, double* grad_nodes,
+                               hipStream_t s);
 // scratch[0] = signed area, scratch[1] = min_ij |x'_j - c_i| / R_i
 hipError_t launch_check(const Dims& d, const double4* geo, const double* wgt,
                         const CenterRec* ctr, double* scratch, hipStream_t s);

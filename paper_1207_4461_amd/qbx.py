@@ -134,3 +134,72 @@ def besselj_table(x: torch.Tensor, L: int) -> torch.Tensor:
     _lib.check(lib.qbx_debug_besselj(x.data_ptr(), x.numel(), int(L), out.data_ptr(),
                                      _stream(x.device)))
     return out
+
+
+def layer_potential_vjp(nodes: torch.Tensor, density: torch.Tensor, cotangent: torch.Tensor,
+                        k: float, p: int, r: float = 0.5, oversample: int = 4,
+                        side: int = EXTERIOR, kind: int = S, tape: Optional[torch.Tensor] = None,
+                        want_density: bool = True, want_nodes: bool = True,
+                        workspace: Optional[torch.Tensor] = None):
+    """Vector-Jacobian product of layer_potential for L = Re sum conj(cotangent) * out.
+
+    Returns (grad_density [n_kinds, 16P] complex128, grad_nodes [P, 16, 2] float64); an
+    entry is None when not wanted.  ``tape``: the forward's tape (else recomputed)."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    _need(cotangent, "cotangent", torch.complex128, (n_sides(side), nk, P * Q))
+    dev = nodes.device
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    gd = torch.empty((nk, P * Q), dtype=torch.complex128, device=dev) if want_density else None
+    gn = torch.empty((P, Q, 2), dtype=torch.float64, device=dev) if want_nodes else None
+    tp = None
+    if tape is not None:
+        if tape.device != dev or tape.numel() * tape.element_size() < tape_bytes(P, p, side, kind):
+            raise ValueError("tape too small or on the wrong device")
+        tp = tape.data_ptr()
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    rc = lib.qbx_layer_potential_adjoint(
+        C.byref(geo), density.data_ptr(), float(k), int(p), float(r), int(oversample), int(side),
+        int(kind), cotangent.data_ptr(), tp, gd.data_ptr() if gd is not None else None,
+        gn.data_ptr() if gn is not None else None, ws.data_ptr(), ws.numel(), _stream(dev))
+    _lib.check(rc)
+    return gd, gn
+
+
+class _LayerPotential(torch.autograd.Function):
+    """out = layer_potential(nodes, density, ...) with the library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, nodes, density, k, p, r, oversample, side, kind):
+        tape = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            P = int(nodes.shape[0])
+            tape = torch.empty(tape_bytes(P, p, side, kind), dtype=torch.uint8,
+                               device=nodes.device)
+        out = layer_potential(nodes.detach(), density.detach(), k, p, r, oversample, side, kind,
+                              tape=tape)
+        ctx.save_for_backward(nodes, density)
+        ctx.tape = tape
+        ctx.args = (k, p, r, oversample, side, kind)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        nodes, density = ctx.saved_tensors
+        k, p, r, oversample, side, kind = ctx.args
+        gd, gn = layer_potential_vjp(nodes.detach(), density.detach(),
+                                     grad_out.contiguous().to(torch.complex128), k, p, r,
+                                     oversample, side, kind, tape=ctx.tape,
+                                     want_density=ctx.needs_input_grad[1],
+                                     want_nodes=ctx.needs_input_grad[0])
+        return gn, gd, None, None, None, None, None, None
+
+
+def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
+              oversample: int = 4, side: int = EXTERIOR, kind: int = S) -> torch.Tensor:
+    """Differentiable layer_potential (gradients for density and nodes via the HIP adjoint)."""
+    return _LayerPotential.apply(nodes, density, float(k), int(p), float(r), int(oversample),
+                                 int(side), int(kind))

@@ -1,0 +1,161 @@
+"""GPU parity of the hand-written adjoint (through the C ABI) against the oracle.
+
+Density gradients are compared with the oracle's (autograd of the paper's steps,
+itself pinned to the dense transposed QBX matrix) at <= 1e-11 relative max-norm;
+node gradients at <= 1e-10 (derivatives amplify rounding by ~1/h).  Full-size
+workloads: sampled panels through the oracle's restricted gradient, plus
+size-independent properties (linearity / dot-product, translation and rotation
+invariance, central differences of the GPU forward).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import qbx_oracle as O
+from paper_1207_4461_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL_D = 1e-11
+TOL_N = 1e-10
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1207_4461_amd import qbx
+    return qbx
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_vjp(Q, pb, tape=None):
+    gd, gn = Q.layer_potential_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k, pb.p,
+                                   pb.r, pb.oversample, pb.side, pb.kind, tape=tape)
+    torch.cuda.synchronize()
+    return gd.cpu().numpy(), gn.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+CASES = [
+    dict(name="S-ext-p4", n_panels=5, p=4, kind=1, side=1),
+    dict(name="S-int-p0", n_panels=4, p=0, kind=1, side=-1),
+    dict(name="D-ext-p3", n_panels=5, p=3, kind=2, side=1),
+    dict(name="D-both-p1", n_panels=4, p=1, kind=2, side=0),
+    dict(name="SD-both-p6", n_panels=6, p=6, kind=3, side=0),
+    dict(name="SD-both-p12-os2", n_panels=5, p=12, kind=3, side=0, oversample=2, k=7.0),
+    dict(name="SD-both-p20-os3", n_panels=4, p=20, kind=3, side=0, oversample=3, k=2.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_adjoint_small_elementwise(Q, case):
+    c = dict(case)
+    name = c.pop("name")
+    pb = I.small(name=name, **c)
+    say(f"case {name}: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side} os={pb.oversample}")
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent)
+    gd, gn = gpu_vjp(Q, pb)
+    ed, en = rel(gd, rd), rel(gn, rn)
+    say(f"  grad density {ed:.3e}  grad nodes {en:.3e}")
+    assert ed <= TOL_D and en <= TOL_N
+
+
+def test_tape_forward_matches_forward_and_reuse(Q):
+    pb = I.small(n_panels=7, p=9, kind=3, side=0)
+    nodes, dens = dev(pb.nodes), dev(pb.density)
+    u0 = Q.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    tape = torch.empty(Q.tape_bytes(pb.n_panels, pb.p, pb.side, pb.kind), dtype=torch.uint8,
+                       device="cuda")
+    u1 = Q.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                           tape=tape)
+    torch.cuda.synchronize()
+    assert rel(u1.cpu().numpy(), u0.cpu().numpy()) < 1e-14
+    a = gpu_vjp(Q, pb)
+    b = gpu_vjp(Q, pb, tape=tape)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_autograd_function_and_gradcheck(Q):
+    pb = I.small(n_panels=4, p=3, k=3.0, kind=3, side=0)
+    nodes = dev(pb.nodes).requires_grad_(True)
+    dens = dev(pb.density).requires_grad_(True)
+    u = Q.qbx_apply(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    g = dev(pb.cotangent)
+    L = torch.real(torch.sum(torch.conj(g) * u))
+    L.backward()
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent)
+    assert rel(dens.grad.cpu().numpy(), rd) < TOL_D
+    assert rel(nodes.grad.cpu().numpy(), rn) < TOL_N
+    f = lambda X, Dn: Q.qbx_apply(X, Dn, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    assert torch.autograd.gradcheck(f, (nodes.detach().clone().requires_grad_(True),
+                                        dens.detach().clone().requires_grad_(True)),
+                                    eps=1e-7, atol=1e-6, rtol=1e-5)
+
+
+def _panels(pb, n, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, pb.n_panels - 1], rng.choice(pb.n_panels, n, replace=False)]))
+
+
+@pytest.mark.parametrize("cfg,n", [("cfg1", 3), ("cfg2", 2)])
+def test_adjoint_full_size_sampled_panels(Q, cfg, n):
+    pb = getattr(I, cfg)()
+    sel = _panels(pb, n, 11)
+    say(f"{cfg}: P={pb.n_panels} p={pb.p} sampled panels {sel.tolist()}")
+    gd, gn = gpu_vjp(Q, pb)
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent, panels=sel)
+    nk = pb.n_kinds
+    a = gd.reshape(nk, -1, 16)[:, sel]
+    b = rd.reshape(nk, -1, 16)[:, sel]
+    ed = rel(a, b)
+    en = rel(gn[sel], rn[sel])
+    say(f"  grad density {ed:.3e}  grad nodes {en:.3e}")
+    assert ed <= TOL_D and en <= TOL_N
+
+
+@pytest.mark.parametrize("cfg", ["cfg2", "cfg4"])
+def test_adjoint_full_size_properties(Q, cfg):
+    """Linearity (dot-product test), translation and rotation invariance of the node
+    gradient, and a central difference of the GPU forward along a smooth deformation."""
+    pb = getattr(I, cfg)()
+    say(f"{cfg}: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side}")
+    nodes, dens, g = dev(pb.nodes), dev(pb.density), dev(pb.cotangent)
+    u = Q.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    L = float(torch.real(torch.sum(torch.conj(g) * u)))
+    gd, gn = Q.layer_potential_vjp(nodes, dens, g, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                   pb.kind)
+    Ld = float(torch.real(torch.sum(torch.conj(gd) * dens)))
+    say(f"  dot product: L {L:.15e}  <grad, density> {Ld:.15e}")
+    assert abs(L - Ld) <= 1e-12 * abs(L)
+    gnn = gn.cpu().numpy()
+    scale = np.abs(gnn).sum()
+    tr = np.abs(gnn.sum(axis=(0, 1))).max() / scale
+    torque = abs(np.sum(pb.nodes[..., 0] * gnn[..., 1] - pb.nodes[..., 1] * gnn[..., 0])) / scale
+    say(f"  translation {tr:.3e} rotation {torque:.3e}")
+    assert tr < 1e-12 and torque < 1e-12
+    # smooth deformation: X -> X + eps * (sin 3t, cos 2t)
+    t = I.panel_parameters(pb.n_panels)
+    E = np.stack([np.sin(3 * t), np.cos(2 * t)], -1)
+    def Lof(X):
+        uu = Q.layer_potential(dev(X), dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+        return float(torch.real(torch.sum(torch.conj(g) * uu)))
+    h = 1e-6
+    fd = (Lof(pb.nodes + h * E) - Lof(pb.nodes - h * E)) / (2 * h)
+    an = float(np.sum(gnn * E))
+    say(f"  directional derivative: FD {fd:.12e} adjoint {an:.12e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
