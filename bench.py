@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--workload", default="cfg4", choices=["cfg0", "cfg1", "cfg2", "cfg4"])
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=10, help="targets in the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time of the oracle sample")
     return ap.parse_args()
 
 
@@ -77,11 +78,17 @@ def main():
         return qbx.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
                                    workspace=ws)
 
+    tape = torch.empty(qbx.tape_bytes(pb.n_panels, pb.p, pb.side, pb.kind), dtype=torch.uint8,
+                       device=dev)
+
     def step():
-        u = fwd()
-        if mode == "fwdbwd":
-            qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample, pb.side,
-                                    pb.kind, workspace=ws)
+        if mode == "fwd":
+            return fwd()
+        # forward storing the tape, then the adjoint (density and node gradients)
+        u = qbx.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                tape=tape, workspace=ws)
+        qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                pb.kind, tape=tape, workspace=ws)
         return u
 
     for _ in range(args.warmup):
@@ -104,28 +111,38 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = (C.c_double * 3)()
-    nl = (C.c_int * 3)()
+    NC = 4
+    ms = (C.c_double * NC)()
+    nl = (C.c_int * NC)()
     _lib.check(lib.qbx_kernel_timer_read(ms, nl))
     lib.qbx_kernel_timer(0)
     step_ms = dt / args.steps * 1e3
     inter = flops.interactions(pb.n_centers, pb.n_sources, pb.kind)
     value = inter / (dt / args.steps)
 
-    # dominant kernel: the class with the largest total time
-    names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel"]
-    cls = max(range(3), key=lambda c: ms[c])
-    avg_ms = ms[cls] / max(nl[cls], 1)
+    # per pair-kernel class: algorithmic flops per launch / average launch time
     pairs = pb.n_centers * pb.n_sources
-    if cls == 0:
-        fl = flops.flops_forward_pair(pb.p, pb.kind) * pairs
-    else:
-        fl = flops.flops_adjoint_pair(pb.p, pb.kind) * pairs
-    achieved = fl / (avg_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-            "kernel": names[cls], "kernel_avg_ms": round(avg_ms, 4),
-            "launches": int(nl[cls]), "flop_per_launch": fl}
+    names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel",
+             "forward-with-tape pair kernel"]
+    per_pair = [flops.flops_forward_pair(pb.p, pb.kind), flops.flops_adjoint_pair(pb.p, pb.kind),
+                0, flops.flops_tape_pair(pb.p, pb.kind)]
+    kernels = {}
+    for c in range(NC):
+        if nl[c] == 0 or per_pair[c] == 0:
+            continue
+        avg = ms[c] / nl[c]
+        fl = per_pair[c] * pairs
+        kernels[names[c]] = {"avg_ms": round(avg, 4), "launches": int(nl[c]),
+                             "flop_per_launch": fl, "tflops": round(fl / (avg * 1e-3) / 1e12, 3)}
+    cls = max((c for c in range(NC) if nl[c] and per_pair[c]), key=lambda c: ms[c])
+    dom = kernels[names[cls]]
+    achieved = dom["tflops"]
+    avg_ms = dom["avg_ms"]
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": names[cls], "kernel_avg_ms": avg_ms, "launches": dom["launches"],
+            "flop_per_launch": dom["flop_per_launch"],
+            "flop_per_pair": per_pair[cls], "all_pair_kernels": kernels}
     log(f"step {step_ms:.2f} ms, {names[cls]} avg {avg_ms:.3f} ms, {achieved:.2f} TFLOP/s")
 
     # CPU oracle on a bounded sample of the same workload
@@ -134,8 +151,13 @@ def main():
         from oracle import qbx_oracle as O
 
         rng = np.random.default_rng(0)
-        idx = np.sort(rng.choice(pb.n_targets, size=min(args.cpu_sample, pb.n_targets),
-                                 replace=False))
+        # calibrate on 2 targets, then size the sample for about --cpu-seconds
+        t0 = time.perf_counter()
+        O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                          targets=np.arange(2))
+        per = (time.perf_counter() - t0) / 2
+        n = int(min(pb.n_targets, max(2, args.cpu_seconds / max(per, 1e-6))))
+        idx = np.sort(rng.choice(pb.n_targets, size=n, replace=False))
         t0 = time.perf_counter()
         ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
                                 pb.kind, targets=idx).numpy()

@@ -163,8 +163,10 @@ int qbx_kernel_timer(int enable);
 
 /* SYNCHRONOUS: waits for the recorded events and returns, per kernel class
  * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
- * kernel), the summed duration in milliseconds and the number of launches
- * since the timer was enabled.  ms and launches are host arrays of 3. */
+ * kernel, 3 = forward-with-tape pair kernel), the summed duration in
+ * milliseconds and the number of launches since the timer was enabled.
+ * ms and launches are host arrays of QBX_TIMER_CLASSES. */
+#define QBX_TIMER_CLASSES 4
 int qbx_kernel_timer_read(double* ms, int* launches);
 
 #ifdef __cplusplus

@@ -139,7 +139,7 @@ struct TimerRec {
 };
 static bool g_timer_on = false;
 static std::vector<TimerRec> g_timer;
-static hipEvent_t g_pending[3];
+static hipEvent_t g_pending[QBX_TIMER_CLASSES];
 
 void timer_begin(int cls, hipStream_t s) {
   if (!g_timer_on) return;
@@ -217,11 +217,11 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
   if (rc) return rc;
   hipError_t e;
   if (tape) {
-    timer_begin(0, stream);
+    timer_begin(3, stream);
     e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                             at<double2>(ws, L.partial), stream);
-    timer_end(0, stream);
+    timer_end(3, stream);
     if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
     e = launch_finalize_tape(d, at<double2>(ws, L.partial), out, reinterpret_cast<double2*>(tape),
                              stream);
@@ -258,11 +258,11 @@ int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, do
   hipError_t e;
   const double2* tp = reinterpret_cast<const double2*>(tape);
   if (!tp) {
-    timer_begin(0, stream);
+    timer_begin(3, stream);
     e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                             at<double2>(ws, L.partial), stream);
-    timer_end(0, stream);
+    timer_end(3, stream);
     if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
     e = launch_finalize_tape(d, at<double2>(ws, L.partial), nullptr, at<double2>(ws, L.tape),
                              stream);
@@ -358,7 +358,7 @@ int qbx_kernel_timer(int enable) {
 
 int qbx_kernel_timer_read(double* ms, int* launches) {
   if (!ms || !launches) return fail(QBX_EINVAL, "NULL output array");
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < QBX_TIMER_CLASSES; ++c) {
     ms[c] = 0.0;
     launches[c] = 0;
   }

@@ -52,3 +52,49 @@ def flops_forward_pair(p: int, kind: int) -> int:
 def interactions(n_centers: int, n_sources: int, kind: int) -> int:
     """Source-center interactions: centers x sources x operators."""
     return n_centers * n_sources * (2 if kind == 3 else 1)
+
+
+def _pair_sums_flops(p: int, kind: int, tape: bool) -> int:
+    """pair_sums() of the adjoint file: seed, recurrences and derivative sums."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    lmax = p + 1 if D else p
+    f = 184 + 2 + (12 if D else 0)            # seed, 2/z and 2 cos D, cos/sin(D +- psi)
+    for l in range(1, lmax + 1):
+        f += 6 + 1                              # H_{l+1}, H_{l-1} - H_{l+1}, 2l/z
+        if S:
+            f += 4                              # Chebyshev cos, sin
+            if l <= p:
+                f += 15 + (5 if tape else 0)    # K, K_rho, K_theta' (+ K_R)
+        if D:
+            f += 8                              # four Chebyshev sequences
+            up = l <= p - 1
+            f += (3 if up else 1) + 8           # J_{l+1} a - J_{l-1} b; K, K_rho
+            f += (1 if up else 0) + 1 + 2 + 4   # l (J_{l+1} sa - J_{l-1} sb); K_theta'
+            if tape:
+                f += (3 if up else 1) + 4 + 3 + 4   # K_R; K_theta
+            else:
+                f += 1 + 4                      # K_psi
+    if S:
+        f += 16 + (8 if tape else 0)
+    if D:
+        f += 26 + (8 if tape else 0)
+    return f
+
+
+def flops_tape_pair(p: int, kind: int) -> int:
+    """Forward-with-tape pair kernel (center-major): u and the per-center tape."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    outer = 17 + (6 if D else 0)
+    outer += 56 * (int(S) + int(D))             # grad_v combination + 5 weighted sums
+    return outer + _pair_sums_flops(p, kind, True)
+
+
+def flops_adjoint_pair(p: int, kind: int) -> int:
+    """Source-major adjoint pair kernel: density, source-position and normal sums."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    outer = 17 + (6 if D else 0)
+    outer += (40 if S else 0) + (48 if D else 0)
+    return outer + _pair_sums_flops(p, kind, False)
