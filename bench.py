@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg4", choices=["cfg0", "cfg1", "cfg2", "cfg4"])
+    ap.add_argument("--workload", default="cfg4", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4"])
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -60,6 +60,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lib = _lib.load()
+    if args.workload == "cfg3":
+        return bench_batched(args)
     have_bwd = hasattr(qbx, "layer_potential_vjp")
     mode = args.mode or ("fwdbwd" if have_bwd else "fwd")
     if mode == "fwdbwd" and not have_bwd:
@@ -196,6 +198,104 @@ def main():
         "fwd_value": inter / fwd_s,
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """64 random contours (cfg3): one persistent launch per pass vs one launch per contour."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_1207_4461_amd import _lib, flops, inputs as I, qbx
+
+    lib = _lib.load()
+    mode = args.mode or "fwdbwd"
+    pbs = I.cfg3()
+    dev = torch.device("cuda:0")
+    B = qbx.Batch(pbs, oversample=4, device=dev)
+    cot = B.pack_out([pb.cotangent for pb in pbs])
+    inter = sum(flops.interactions(pb.n_centers, pb.n_sources, pb.kind) for pb in pbs)
+    log(f"workload cfg3: {len(pbs)} contours, {sum(pb.n_panels for pb in pbs)} panels, "
+        f"{inter:.3e} interactions per pass, mode={mode}")
+
+    def step_batched():
+        if mode == "fwd":
+            return B.forward()
+        u = B.forward(with_tape=True)
+        B.adjoint(cot, use_tape=True)
+        return u
+
+    per = []
+    for pb in pbs:
+        per.append(dict(
+            nodes=torch.from_numpy(pb.nodes).to(dev),
+            dens=torch.from_numpy(np.ascontiguousarray(pb.density)).to(dev),
+            cot=torch.from_numpy(np.ascontiguousarray(pb.cotangent)).to(dev),
+            ws=torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side, pb.kind),
+                           dtype=torch.uint8, device=dev),
+            tape=torch.empty(qbx.tape_bytes(pb.n_panels, pb.p, pb.side, pb.kind),
+                             dtype=torch.uint8, device=dev)))
+
+    def step_per_contour():
+        for pb, q in zip(pbs, per):
+            if mode == "fwd":
+                qbx.layer_potential(q["nodes"], q["dens"], pb.k, pb.p, pb.r, pb.oversample,
+                                    pb.side, pb.kind, workspace=q["ws"])
+            else:
+                qbx.layer_potential(q["nodes"], q["dens"], pb.k, pb.p, pb.r, pb.oversample,
+                                    pb.side, pb.kind, tape=q["tape"], workspace=q["ws"])
+                qbx.layer_potential_vjp(q["nodes"], q["dens"], q["cot"], pb.k, pb.p, pb.r,
+                                        pb.oversample, pb.side, pb.kind, tape=q["tape"],
+                                        workspace=q["ws"])
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_per = timed(step_per_contour, max(1, args.steps))
+    lib.qbx_kernel_timer(1)
+    t_bat = timed(step_batched, args.steps)
+    NC = 4
+    ms = (C.c_double * NC)()
+    nl = (C.c_int * NC)()
+    _lib.check(lib.qbx_kernel_timer_read(ms, nl))
+    lib.qbx_kernel_timer(0)
+    # algorithmic flops of the persistent launches of one step
+    if mode == "fwd":
+        fl = sum(flops.flops_forward_pair(pb.p, pb.kind) * pb.n_centers * pb.n_sources for pb in pbs)
+    else:
+        fl = sum((flops.flops_tape_pair(pb.p, pb.kind) + flops.flops_adjoint_pair(pb.p, pb.kind))
+                 * pb.n_centers * pb.n_sources for pb in pbs)
+    # one (fwd) or two (fwd+bwd) persistent launches per step; warm-up steps included
+    per_step_ms = ms[2] / max(1, nl[2]) * (1 if mode == "fwd" else 2)
+    achieved = fl / (per_step_ms * 1e-3) / 1e12
+    log(f"batched {t_bat * 1e3:.2f} ms/step, per-contour {t_per * 1e3:.2f} ms/step, "
+        f"persistent kernels {per_step_ms:.2f} ms/step, {achieved:.2f} TFLOP/s")
+    out = {
+        "metric": METRIC, "value": inter / t_bat, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_bat * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cfg3: 64 random star contours, 16..512 panels x 16 nodes, "
+                               "oversample 4, k~U(5,50), p in {8,12,16}, S or D, exterior",
+                   "mode": mode, "interactions_per_step": inter,
+                   "per_contour_ms_per_step": t_per * 1e3,
+                   "batched_speedup_vs_per_contour": t_per / t_bat},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": None, "kernel": "batched persistent kernels (forward-with-tape + "
+                     "adjoint source pass)" if mode != "fwd" else "batched persistent forward",
+                     "kernel_ms_per_step": round(per_step_ms, 3)},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

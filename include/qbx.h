@@ -122,6 +122,67 @@ int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, do
                                 double* grad_density, double* grad_nodes, void* ws,
                                 size_t ws_bytes, hipStream_t stream);
 
+/* ---- batched: many contours in one persistent launch ---------------------- */
+
+/* One contour of a batch.  Offsets locate its blocks inside the caller's packed
+ * arrays (in units of panels for nodes and of complex values otherwise); the
+ * blocks have the per-contour layouts of qbx_layer_potential:
+ *   nodes   + node_offset*32    : [n_panels][16][2]
+ *   density + 2*density_offset  : [n_kinds][16 n_panels] complex
+ *   out     + 2*out_offset      : [n_sides][n_kinds][16 n_panels] complex
+ * (cotangent, grad_density and grad_nodes of the adjoint use the layouts and
+ * offsets of out, density and nodes).  Blocks of different contours must not
+ * overlap.  All contours share `oversample`; p, k, r, side and kind are per
+ * contour with the limits of qbx_layer_potential. */
+typedef struct {
+  int64_t node_offset;
+  int64_t density_offset;
+  int64_t out_offset;
+  int32_t n_panels;
+  int32_t p;
+  int32_t kind;
+  int32_t side;
+  double k;
+  double r;
+} qbx_batch_item;
+
+/* Workspace / tape bytes for a batch (items in HOST memory; 0 if invalid). */
+size_t qbx_batched_workspace_bytes(const qbx_batch_item* items, int n_items, int oversample);
+size_t qbx_batched_tape_bytes(const qbx_batch_item* items, int n_items);
+
+/* Forward for every contour of the batch.  The source grids and centers of all
+ * contours are built by one launch; the pair work of all contours runs in ONE
+ * persistent launch whose wavefronts take (contour, center) tasks, most
+ * expensive contours first, from a device counter.  tape: nullable, the
+ * batch's tape for qbx_layer_potential_batched_adjoint (qbx_batched_tape_bytes).
+ * items is a HOST array; it is copied into the workspace. */
+int qbx_layer_potential_batched(const qbx_batch_item* items, int n_items, const double* nodes,
+                                const double* density, double* out, double* tape, int oversample,
+                                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of the batched forward (the per-contour qbx_layer_potential_adjoint
+ * for every contour), with the source-major pass of all contours in one
+ * persistent launch over (contour, 64-source chunk) tasks.  tape: the batched
+ * forward's tape, or NULL to recompute it. */
+int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items,
+                                        const double* nodes, const double* density,
+                                        const double* cotangent, const double* tape,
+                                        double* grad_density, double* grad_nodes, int oversample,
+                                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- principal value (Section 3.2) --------------------------------------- */
+
+/* pv [n_kinds][T] complex from out [n_sides][n_kinds][T] (the layout of
+ * qbx_layer_potential's output for the same side and kind):
+ *   side = QBX_BOTH: the average of the two one-sided limits (eq. dlp-twosided);
+ *   one side s:      S is continuous across the curve, pv = out; for D the jump
+ *                    relation (eq. dlpjump) gives pv = out - s*mu/2, with mu the
+ *                    D density at the node (density [n_kinds][T], as given to the
+ *                    forward; unused, may be NULL, when no D is present).
+ * Stream-ordered, no allocation. */
+int qbx_principal_value(const double* out, const double* density, int n_panels, int side,
+                        int kind, double* pv, hipStream_t stream);
+
 /* ---- checks ------------------------------------------------------------ */
 
 /* SYNCHRONOUS geometry check (it waits for `stream`): signed area of the

@@ -71,6 +71,13 @@ def load() -> C.CDLL:
         "qbx_debug_hankel01": (i32, [vp, i32, vp, vp, vp]),
         "qbx_debug_besselj": (i32, [vp, i32, i32, vp, vp]),
         "qbx_kernel_timer": (i32, [i32]),
+        "qbx_principal_value": (i32, [vp, vp, i32, i32, i32, vp, vp]),
+        "qbx_batched_workspace_bytes": (sz, [C.POINTER(BatchItem), i32, i32]),
+        "qbx_batched_tape_bytes": (sz, [C.POINTER(BatchItem), i32]),
+        "qbx_layer_potential_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, vp, vp, i32, vp,
+                                              sz, vp]),
+        "qbx_layer_potential_batched_adjoint": (i32, [C.POINTER(BatchItem), i32, vp, vp, vp, vp,
+                                                      vp, vp, i32, vp, sz, vp]),
         "qbx_kernel_timer_read": (i32, [C.POINTER(dbl), C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():

@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqbx.so")
-SOURCES = ["qbx_api.cpp", "qbx_geometry.hip", "qbx_forward.hip", "qbx_adjoint.hip",
-           "qbx_batched.hip"]
+SOURCES = ["qbx_batched_fwd1.hip", "qbx_batched_fwd0.hip", "qbx_batched_adj.hip",
+           "qbx_adjoint.hip", "qbx_forward.hip", "qbx_batched.hip", "qbx_geometry.hip",
+           "qbx_api.cpp"]   # slowest first
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [
@@ -34,8 +35,20 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _up_to_date(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC)
+                                        if h.endswith(".h")]
+    deps.append(os.path.join(os.path.dirname(HERE), "include", "qbx.h"))
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def _compile(src: str, verbose: bool, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not force and _up_to_date(src, obj):
+        return obj
     cmd = [_hipcc(), "-x", "hip", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -45,11 +58,12 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force=False: only those older than their inputs) and link."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), srcs))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), *COMMON, "-shared", "-o", tmp, *objs]
     if verbose:
@@ -62,4 +76,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--incremental" not in sys.argv))

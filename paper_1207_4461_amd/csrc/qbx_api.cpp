@@ -17,8 +17,7 @@ namespace qbx {
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static int fail(int code, const char* fmt, ...) {
+int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -28,11 +27,11 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-static int device_fail(hipError_t e, const char* where) {
+int device_fail(hipError_t e, const char* where) {
   return fail(QBX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
                Dims* d) {
@@ -112,8 +111,8 @@ static T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-static int validate(const qbx_geometry* g, int p, double k, double r, int oversample, int side,
-                    int kind, Dims* d) {
+int validate(const qbx_geometry* g, int p, double k, double r, int oversample, int side,
+             int kind, Dims* d) {
   if (!g) return fail(QBX_EINVAL, "geometry is NULL");
   if (!g->nodes) return fail(QBX_EINVAL, "geometry nodes pointer is NULL");
   if (g->q != kQ) return fail(QBX_EINVAL, "q = %d, only %d nodes per panel are supported", g->q, kQ);
@@ -276,6 +275,23 @@ int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, do
                           grad_density, grad_nodes, stream);
   if (e != hipSuccess) return device_fail(e, "adjoint kernels");
   return QBX_OK;
+}
+
+int qbx_principal_value(const double* out, const double* density, int n_panels, int side,
+                        int kind, double* pv, hipStream_t stream) {
+  if (!out || !pv) return fail(QBX_EINVAL, "out or pv is NULL");
+  if (n_panels < 3) return fail(QBX_EINVAL, "n_panels = %d < 3", n_panels);
+  if (side != QBX_INTERIOR && side != QBX_EXTERIOR && side != QBX_BOTH)
+    return fail(QBX_EINVAL, "side = %d is not -1, 0 or 1", side);
+  if (kind != QBX_S && kind != QBX_D && kind != (QBX_S | QBX_D))
+    return fail(QBX_EINVAL, "kind = %d is not 1 (S), 2 (D) or 3 (S|D)", kind);
+  if (side != QBX_BOTH && (kind & QBX_D) && !density)
+    return fail(QBX_EINVAL, "density is needed for the one-sided D jump");
+  const long T = (long)n_panels * kQ;
+  if (T > (1L << 28)) return fail(QBX_EINVAL, "problem too large");
+  const int nk = kind == 3 ? 2 : 1;
+  hipError_t e = launch_principal_value((int)T, nk, side, kind, out, density, pv, stream);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "principal value kernel");
 }
 
 int qbx_check_geometry(const qbx_geometry* g, int p, double r, int oversample, int side,

@@ -1,0 +1,389 @@
+// Batched QBX: many contours of different panel counts, wavenumbers, orders
+// and kinds in one persistent launch per pass.
+//
+// The host builds a plan: per-contour dimensions and offsets into packed
+// workspace arrays, and two task lists ordered by decreasing cost per task
+// (forward: one task per center, cost ~ sources x pair flops; adjoint: one
+// task per 64-source chunk, cost ~ centers x pair flops), stored as prefix
+// sums over the contours in that order.  The persistent kernels run a fixed
+// grid; every wavefront takes the next task index from a device counter,
+// finds its contour by binary search in the prefix array and runs the same
+// pair-loop body as the per-contour kernels (qbx_pair.h), dispatched on the
+// contour's (kind, p).  Every wavefront leaves once the counter passes the
+// task count.  Geometry, per-center and per-source steps run as ordinary
+// grids over all contours' panels, centers or sources.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "../../include/qbx.h"
+#include "qbx_batched.h"
+
+namespace qbx {
+
+struct BatchPlan {
+  int n;
+  int qs;
+  std::vector<BatchItemDev> items;
+  std::vector<int> order_f, order_a;              // contour order of the two task lists
+  std::vector<long long> pre_f, pre_a;            // task prefix sums in that order
+  std::vector<long long> pre_panel, pre_ctr, pre_src, pre_G;  // prefix sums in item order
+  long long n_panels = 0, n_ctr = 0, n_src = 0, n_G = 0, n_densw = 0, n_jtab = 0, n_tape = 0,
+            n_spart = 0;
+  // workspace offsets
+  size_t o_items, o_ord_f, o_ord_a, o_pre_f, o_pre_a, o_pre_panel, o_pre_ctr, o_pre_src, o_pre_G,
+      o_counter, o_tables, o_geo, o_densw, o_wgt, o_h, o_ctr, o_jtab, o_tape, o_G, o_cg, o_spart,
+      o_sg, total;
+};
+
+static bool build_plan(const qbx_batch_item* items, int n, int oversample, BatchPlan* P) {
+  if (!items || n < 1 || oversample < 1 || oversample > QBX_OVERSAMPLE_MAX) return false;
+  P->n = n;
+  P->qs = kQ * oversample;
+  P->items.resize(n);
+  P->pre_panel.assign(n + 1, 0);
+  P->pre_ctr.assign(n + 1, 0);
+  P->pre_src.assign(n + 1, 0);
+  P->pre_G.assign(n + 1, 0);
+  std::vector<double> cost_f(n), cost_a(n);
+  for (int i = 0; i < n; ++i) {
+    const qbx_batch_item& it = items[i];
+    BatchItemDev& B = P->items[i];
+    if (!(it.k > 0.0) || !std::isfinite(it.k) || !(it.r > 0.0) || !std::isfinite(it.r)) return false;
+    if (it.node_offset < 0 || it.density_offset < 0 || it.out_offset < 0) return false;
+    if (!make_dims(it.n_panels, kQ, it.p, oversample, it.side, it.kind, it.k, it.r, &B.d))
+      return false;
+    const Dims& d = B.d;
+    B.node_off = it.node_offset * 2 * kQ;
+    B.din_off = it.density_offset * 2;
+    B.out_off = it.out_offset * 2;
+    B.panel_off = P->n_panels;
+    B.src_off = P->n_src;
+    B.ctr_off = P->n_ctr;
+    B.densw_off = P->n_densw;
+    B.jtab_off = P->n_jtab;
+    B.tape_off = P->n_tape;
+    B.G_off = P->n_G;
+    B.spart_off = P->n_spart;
+    const int NA = (d.kind & 1 ? 3 : 0) + (d.kind & 2 ? 4 : 0);
+    P->n_panels += d.P;
+    P->n_src += d.N;
+    P->n_ctr += d.Mc;
+    P->n_densw += (long long)d.nk * d.N;
+    P->n_jtab += (long long)d.Mc * d.NJ;
+    P->n_tape += (long long)d.Mc * d.nk * 4;
+    P->n_G += (long long)d.nk * d.Mc;
+    P->n_spart += (long long)NA * d.N;
+    P->pre_panel[i + 1] = P->n_panels;
+    P->pre_ctr[i + 1] = P->n_ctr;
+    P->pre_src[i + 1] = P->n_src;
+    P->pre_G[i + 1] = P->n_G;
+    const double per_pair = (double)(d.p + 8) * d.nk;
+    cost_f[i] = (double)d.N * per_pair;    // one center against all sources
+    cost_a[i] = (double)d.Mc * per_pair;   // 64 sources against all centers
+  }
+  if (P->n_src > (1LL << 31) - 1 || P->n_ctr > (1LL << 31) - 1) return false;
+  auto make_order = [&](const std::vector<double>& cost, std::vector<int>& ord,
+                        std::vector<long long>& pre, bool centers) {
+    ord.resize(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    pre.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      const Dims& d = P->items[ord[i]].d;
+      pre[i + 1] = pre[i] + (centers ? d.Mc : d.chunks);
+    }
+  };
+  make_order(cost_f, P->order_f, P->pre_f, true);
+  make_order(cost_a, P->order_a, P->pre_a, false);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  P->o_items = take(sizeof(BatchItemDev) * n);
+  P->o_ord_f = take(sizeof(int) * n);
+  P->o_ord_a = take(sizeof(int) * n);
+  P->o_pre_f = take(sizeof(long long) * (n + 1));
+  P->o_pre_a = take(sizeof(long long) * (n + 1));
+  P->o_pre_panel = take(sizeof(long long) * (n + 1));
+  P->o_pre_ctr = take(sizeof(long long) * (n + 1));
+  P->o_pre_src = take(sizeof(long long) * (n + 1));
+  P->o_pre_G = take(sizeof(long long) * (n + 1));
+  P->o_counter = take(256);
+  P->o_tables = take(sizeof(double) * table_layout(P->qs).total);
+  P->o_geo = take(sizeof(double4) * P->n_src);
+  P->o_densw = take(sizeof(double2) * P->n_densw);
+  P->o_wgt = take(sizeof(double) * P->n_src);
+  P->o_h = take(sizeof(double) * P->n_panels);
+  P->o_ctr = take(sizeof(CenterRec) * P->n_ctr);
+  P->o_jtab = take(sizeof(double) * P->n_jtab);
+  P->o_tape = take(sizeof(double2) * P->n_tape);
+  P->o_G = take(sizeof(double2) * P->n_G);
+  P->o_cg = take(sizeof(double) * 8 * P->n_ctr);
+  P->o_spart = take(sizeof(double2) * P->n_spart);
+  P->o_sg = take(sizeof(double) * 8 * P->n_src);
+  P->total = o;
+  return true;
+}
+
+template <typename T>
+static T* wsp(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+__global__ void k_zero_int(int* c) {
+  if (threadIdx.x == 0) c[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// geometry of every contour: one block per panel of the batch
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_upsample_batched(
+    const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_panel, int n,
+    const double* __restrict__ nodes, const double* __restrict__ density,
+    const double* __restrict__ tab, double4* __restrict__ geo, double2* __restrict__ densw,
+    double* __restrict__ wgt, double* __restrict__ hpan, CenterRec* __restrict__ ctr,
+    double* __restrict__ jtab) {
+  const int it = find_slot(pre_panel, n, blockIdx.x);
+  const BatchItemDev& B = items[it];
+  const Dims d = B.d;
+  const int m = (int)(blockIdx.x - pre_panel[it]);
+  upsample_panel(d, m, nodes + B.node_off, density + B.din_off, tab, geo + B.src_off,
+                 densw + B.densw_off, wgt + B.src_off, hpan + B.panel_off, ctr + B.ctr_off,
+                 jtab + B.jtab_off);
+}
+
+// ---------------------------------------------------------------------------
+// per-element and per-panel steps over the whole batch
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_make_G_batched(const BatchItemDev* __restrict__ items,
+                                                        const long long* __restrict__ pre_G, int n,
+                                                        long long total,
+                                                        const double* __restrict__ cot,
+                                                        double2* __restrict__ G) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int it = find_slot(pre_G, n, e);
+  const BatchItemDev& B = items[it];
+  make_G_elem((int)(e - pre_G[it]), B.d.Mc, B.d.T, B.d.nk, cot + B.out_off, G + B.G_off);
+}
+
+__global__ __launch_bounds__(256) void k_center_grads_batched(
+    const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_ctr, int n,
+    long long total, const CenterRec* __restrict__ ctr, const double2* __restrict__ tape,
+    const double2* __restrict__ G, double* __restrict__ cg) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int it = find_slot(pre_ctr, n, e);
+  const BatchItemDev& B = items[it];
+  center_grad_elem((int)(e - pre_ctr[it]), B.d.Mc, B.d.nk, B.d.side, B.d.T, ctr + B.ctr_off,
+                   tape + B.tape_off, G + B.G_off, cg + B.ctr_off * 8);
+}
+
+__global__ __launch_bounds__(256) void k_source_finalize_batched(
+    const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_src, int n,
+    long long total, const double4* __restrict__ geo, const double2* __restrict__ densw,
+    const double2* __restrict__ spart, double* __restrict__ sg) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int it = find_slot(pre_src, n, e);
+  const BatchItemDev& B = items[it];
+  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind, 1, geo + B.src_off,
+                       densw + B.densw_off, spart + B.spart_off, sg + B.src_off * 8);
+}
+
+__global__ __launch_bounds__(128) void k_chain_batched(
+    const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_panel, int n,
+    const double* __restrict__ nodes, const double* __restrict__ density,
+    const double* __restrict__ tab, const double* __restrict__ sg, const double* __restrict__ cg,
+    double* __restrict__ grad_density, double* __restrict__ grad_nodes) {
+  const int it = find_slot(pre_panel, n, blockIdx.x);
+  const BatchItemDev& B = items[it];
+  const Dims d = B.d;
+  const int m = (int)(blockIdx.x - pre_panel[it]);
+  chain_panel(d, m, nodes + B.node_off, density + B.din_off, tab, sg + B.src_off * 8,
+              cg + B.ctr_off * 8, grad_density ? grad_density + B.din_off : nullptr,
+              grad_nodes ? grad_nodes + B.node_off : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int g_batch_blocks_per_cu = 2;
+
+static int upload_plan(const BatchPlan& P, void* ws, hipStream_t s) {
+  struct Up {
+    size_t off;
+    const void* src;
+    size_t bytes;
+  } ups[] = {
+      {P.o_items, P.items.data(), sizeof(BatchItemDev) * P.n},
+      {P.o_ord_f, P.order_f.data(), sizeof(int) * P.n},
+      {P.o_ord_a, P.order_a.data(), sizeof(int) * P.n},
+      {P.o_pre_f, P.pre_f.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_a, P.pre_a.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_panel, P.pre_panel.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_ctr, P.pre_ctr.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_src, P.pre_src.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_G, P.pre_G.data(), sizeof(long long) * (P.n + 1)},
+  };
+  for (const Up& u : ups) {
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + u.off, u.src, u.bytes,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return device_fail(e, "upload of the batch plan");
+  }
+  return QBX_OK;
+}
+
+static int persistent_blocks() {
+  static int cus_of[64] = {0};
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+    if (cus_of[dev] == 0) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          v > 0)
+        cus_of[dev] = v;
+      else
+        cus_of[dev] = 256;
+    }
+    cus = cus_of[dev];
+  }
+  return cus * g_batch_blocks_per_cu;
+}
+
+static int batch_prepare(const BatchPlan& P, const double* nodes, const double* density, void* ws,
+                         hipStream_t s) {
+  int rc = upload_plan(P, ws, s);
+  if (rc) return rc;
+  Dims d0 = P.items[0].d;
+  hipError_t e = launch_tables(d0, wsp<double>(ws, P.o_tables), s);
+  if (e != hipSuccess) return device_fail(e, "tables kernel");
+  hipLaunchKernelGGL(k_upsample_batched, dim3((unsigned)P.n_panels), dim3(128), 0, s,
+                     wsp<BatchItemDev>(ws, P.o_items), wsp<long long>(ws, P.o_pre_panel), P.n,
+                     nodes, density, wsp<double>(ws, P.o_tables), wsp<double4>(ws, P.o_geo),
+                     wsp<double2>(ws, P.o_densw), wsp<double>(ws, P.o_wgt),
+                     wsp<double>(ws, P.o_h), wsp<CenterRec>(ws, P.o_ctr),
+                     wsp<double>(ws, P.o_jtab));
+  e = hipGetLastError();
+  return e == hipSuccess ? QBX_OK : device_fail(e, "batched upsample kernel");
+}
+
+static int batch_forward(const BatchPlan& P, double* out, double2* tape, void* ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, wsp<int>(ws, P.o_counter));
+  const dim3 grid((unsigned)persistent_blocks()), block(256);
+  timer_begin(2, s);
+  hipError_t e = launch_forward_batched(
+      tape ? 1 : 0, grid, wsp<BatchItemDev>(ws, P.o_items), wsp<int>(ws, P.o_ord_f),
+      wsp<long long>(ws, P.o_pre_f), P.n, P.pre_f[P.n], wsp<int>(ws, P.o_counter),
+      wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_densw), wsp<CenterRec>(ws, P.o_ctr),
+      wsp<double>(ws, P.o_jtab), out, tape, s);
+  timer_end(2, s);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "batched forward kernel");
+}
+
+hipError_t launch_forward_batched_0(dim3, const BatchItemDev*, const int*, const long long*, int,
+                                    long long, int*, const double4*, const double2*,
+                                    const CenterRec*, const double*, double*, double2*, hipStream_t);
+hipError_t launch_forward_batched_1(dim3, const BatchItemDev*, const int*, const long long*, int,
+                                    long long, int*, const double4*, const double2*,
+                                    const CenterRec*, const double*, double*, double2*, hipStream_t);
+
+hipError_t launch_forward_batched(int mode, dim3 grid, const BatchItemDev* items, const int* order,
+                                  const long long* pre, int n, long long n_tasks, int* counter,
+                                  const double4* geo, const double2* densw, const CenterRec* ctr,
+                                  const double* jtab, double* out, double2* tape, hipStream_t s) {
+  return mode ? launch_forward_batched_1(grid, items, order, pre, n, n_tasks, counter, geo, densw,
+                                         ctr, jtab, out, tape, s)
+              : launch_forward_batched_0(grid, items, order, pre, n, n_tasks, counter, geo, densw,
+                                         ctr, jtab, out, tape, s);
+}
+
+void set_batch_blocks_per_cu(int v) { g_batch_blocks_per_cu = v < 1 ? 1 : (v > 16 ? 16 : v); }
+int get_batch_blocks_per_cu() { return g_batch_blocks_per_cu; }
+
+}  // namespace qbx
+
+using namespace qbx;
+
+extern "C" {
+
+size_t qbx_batched_workspace_bytes(const qbx_batch_item* items, int n_items, int oversample) {
+  BatchPlan P;
+  if (!build_plan(items, n_items, oversample, &P)) return 0;
+  return P.total;
+}
+
+size_t qbx_batched_tape_bytes(const qbx_batch_item* items, int n_items) {
+  BatchPlan P;
+  if (!build_plan(items, n_items, 1, &P)) return 0;
+  return sizeof(double2) * (size_t)P.n_tape;
+}
+
+int qbx_layer_potential_batched(const qbx_batch_item* items, int n_items, const double* nodes,
+                                const double* density, double* out, double* tape, int oversample,
+                                void* ws, size_t ws_bytes, hipStream_t stream) {
+  BatchPlan P;
+  if (!build_plan(items, n_items, oversample, &P))
+    return fail(QBX_EINVAL, "invalid batch (an item's parameters, offsets or oversample)");
+  if (!nodes || !density || !out || !ws) return fail(QBX_EINVAL, "NULL array argument");
+  if (ws_bytes < P.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, P.total);
+  int rc = batch_prepare(P, nodes, density, ws, stream);
+  if (rc) return rc;
+  return batch_forward(P, out, reinterpret_cast<double2*>(tape), ws, stream);
+}
+
+int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items,
+                                        const double* nodes, const double* density,
+                                        const double* cotangent, const double* tape,
+                                        double* grad_density, double* grad_nodes, int oversample,
+                                        void* ws, size_t ws_bytes, hipStream_t stream) {
+  BatchPlan P;
+  if (!build_plan(items, n_items, oversample, &P))
+    return fail(QBX_EINVAL, "invalid batch (an item's parameters, offsets or oversample)");
+  if (!nodes || !density || !cotangent || !ws) return fail(QBX_EINVAL, "NULL array argument");
+  if (ws_bytes < P.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, P.total);
+  if (!grad_density && !grad_nodes) return QBX_OK;
+  int rc = batch_prepare(P, nodes, density, ws, stream);
+  if (rc) return rc;
+  const double2* tp = reinterpret_cast<const double2*>(tape);
+  if (!tp) {
+    // recompute the tape (no forward values are written)
+    rc = batch_forward(P, nullptr, wsp<double2>(ws, P.o_tape), ws, stream);
+    if (rc) return rc;
+    tp = wsp<double2>(ws, P.o_tape);
+  }
+  const long long nG = P.n_G, nC = P.n_ctr, nS = P.n_src;
+  auto blocks = [](long long n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
+  BatchItemDev* it = wsp<BatchItemDev>(ws, P.o_items);
+  hipLaunchKernelGGL(k_make_G_batched, blocks(nG, 256), dim3(256), 0, stream, it,
+                     wsp<long long>(ws, P.o_pre_G), P.n, nG, cotangent, wsp<double2>(ws, P.o_G));
+  hipLaunchKernelGGL(k_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
+                     wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr), tp,
+                     wsp<double2>(ws, P.o_G), wsp<double>(ws, P.o_cg));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, wsp<int>(ws, P.o_counter));
+  timer_begin(2, stream);
+  hipError_t ea = launch_adjoint_batched(
+      dim3((unsigned)persistent_blocks()), it, wsp<int>(ws, P.o_ord_a),
+      wsp<long long>(ws, P.o_pre_a), P.n, P.pre_a[P.n], wsp<int>(ws, P.o_counter),
+      wsp<double4>(ws, P.o_geo), wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
+      wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart), stream);
+  timer_end(2, stream);
+  if (ea != hipSuccess) return device_fail(ea, "batched adjoint kernel");
+  hipLaunchKernelGGL(k_source_finalize_batched, blocks(nS, 256), dim3(256), 0, stream, it,
+                     wsp<long long>(ws, P.o_pre_src), P.n, nS, wsp<double4>(ws, P.o_geo),
+                     wsp<double2>(ws, P.o_densw), wsp<double2>(ws, P.o_spart),
+                     wsp<double>(ws, P.o_sg));
+  hipLaunchKernelGGL(k_chain_batched, dim3((unsigned)P.n_panels), dim3(128), 0, stream, it,
+                     wsp<long long>(ws, P.o_pre_panel), P.n, nodes, density,
+                     wsp<double>(ws, P.o_tables), wsp<double>(ws, P.o_sg), wsp<double>(ws, P.o_cg),
+                     grad_density, grad_nodes);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QBX_OK : device_fail(e, "batched adjoint kernels");
+}
+
+}  // extern "C"

@@ -10,6 +10,7 @@
 //  * Section 3.3 step 4(a): c = x + s r h_m n with h_m the panel length,
 //    radius R = r h_m, and theta = arg(x - c) = arg(-s n).
 #include "qbx_internal.h"
+#include "qbx_panel.h"
 #include "qbx_special.h"
 
 namespace qbx {
@@ -76,9 +77,6 @@ hipError_t launch_tables(const Dims& d, double* tables, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// upsample: one block per panel.
-// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(128) void k_upsample(Dims d, const double* __restrict__ nodes,
                                                   const double* __restrict__ density,
                                                   const double* __restrict__ tab,
@@ -88,90 +86,7 @@ __global__ __launch_bounds__(128) void k_upsample(Dims d, const double* __restri
                                                   double* __restrict__ hpan,
                                                   CenterRec* __restrict__ ctr,
                                                   double* __restrict__ jtab) {
-  const TableLayout L = table_layout(d.qs);
-  const int m = blockIdx.x;
-  const int t = threadIdx.x;
-  __shared__ double X[kQ][2];
-  __shared__ double2 S[2][kQ];
-  __shared__ double red[128];
-  if (t < 2 * kQ) X[t >> 1][t & 1] = nodes[(size_t)m * 2 * kQ + t];
-  if (t < d.nk * kQ) {
-    const int kk = t / kQ, a = t % kQ;
-    const double* src = density + 2 * ((size_t)kk * d.T + (size_t)m * kQ + a);
-    S[kk][a] = make_double2(src[0], src[1]);
-  }
-  __syncthreads();
-  double wsum = 0.0;
-  for (int b = t; b < d.qs; b += blockDim.x) {
-    const double* Vr = tab + L.V + b * kQ;
-    const double* Vdr = tab + L.Vd + b * kQ;
-    double x = 0.0, y = 0.0, dx = 0.0, dy = 0.0;
-    double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
-#pragma unroll
-    for (int a = 0; a < kQ; ++a) {
-      const double v = Vr[a], vd = Vdr[a];
-      x = fma(v, X[a][0], x);
-      y = fma(v, X[a][1], y);
-      dx = fma(vd, X[a][0], dx);
-      dy = fma(vd, X[a][1], dy);
-      sr0 = fma(v, S[0][a].x, sr0);
-      si0 = fma(v, S[0][a].y, si0);
-      if (d.nk > 1) {
-        sr1 = fma(v, S[1][a].x, sr1);
-        si1 = fma(v, S[1][a].y, si1);
-      }
-    }
-    const double speed = sqrt(dx * dx + dy * dy);
-    const double w = tab[L.ws + b] * speed;
-    const double inv = 1.0 / speed;
-    const size_t j = (size_t)m * d.qs + b;
-    geo[j] = make_double4(x, y, dy * inv, -dx * inv);
-    wgt[j] = w;
-    dens[j] = make_double2(w * sr0, w * si0);
-    if (d.nk > 1) dens[(size_t)d.N + j] = make_double2(w * sr1, w * si1);
-    wsum += w;
-  }
-  red[t] = wsum;
-  __syncthreads();
-  for (int off = 64; off > 0; off >>= 1) {
-    if (t < off) red[t] += red[t + off];
-    __syncthreads();
-  }
-  const double hm = red[0];
-  if (t == 0) hpan[m] = hm;
-  if (t < kQ * d.n_sides) {
-    const int a = t % kQ, si = t / kQ;
-    const double sgn = side_sign(d.side, si);
-    const double* Dr = tab + L.Dn + a * kQ;
-    double tx = 0.0, ty = 0.0;
-#pragma unroll
-    for (int c = 0; c < kQ; ++c) {
-      tx = fma(Dr[c], X[c][0], tx);
-      ty = fma(Dr[c], X[c][1], ty);
-    }
-    const double inv = 1.0 / sqrt(tx * tx + ty * ty);
-    const double nx = ty * inv, ny = -tx * inv;
-    const double R = d.r * hm;
-    CenterRec c;
-    c.x = X[a][0];
-    c.y = X[a][1];
-    c.cx = c.x + sgn * R * nx;
-    c.cy = c.y + sgn * R * ny;
-    c.R = R;
-    c.ct = -sgn * nx;
-    c.st = -sgn * ny;
-    c.pad = 0.0;
-    const size_t ci = (size_t)si * d.T + (size_t)m * kQ + a;
-    ctr[ci] = c;
-    double* Jt = jtab + ci * d.NJ;
-    const int nj = d.NJ / 2;
-    bessel_j_miller(d.k * R, nj - 1, Jt);
-    // J'_l = (J_{l-1} - J_{l+1}) / 2 (DLMF 10.6.1), J'_0 = -J_1; the last one
-    // from J_{l-1} - (l/x) J_l (DLMF 10.6.2)
-    Jt[nj] = -Jt[1];
-    for (int l = 1; l + 1 < nj; ++l) Jt[nj + l] = 0.5 * (Jt[l - 1] - Jt[l + 1]);
-    Jt[2 * nj - 1] = (d.k * R > 0.0) ? Jt[nj - 2] - (nj - 1) / (d.k * R) * Jt[nj - 1] : 0.0;
-  }
+  upsample_panel(d, blockIdx.x, nodes, density, tab, geo, dens, wgt, hpan, ctr, jtab);
 }
 
 hipError_t launch_upsample(const Dims& d, const double* nodes, const double* density,

@@ -87,6 +87,10 @@ __host__ __device__ inline double side_sign(int side, int si) {
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
                Dims* d);
+// error reporting shared by the C entry points (qbx_last_error)
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int device_fail(hipError_t e, const char* where);
+size_t align256(size_t x);
 Layout make_layout(const Dims& d);
 
 // ---- launchers (qbx_geometry.hip / qbx_forward.hip) ----
@@ -98,6 +102,8 @@ hipError_t launch_forward(const Dims& d, const double4* geo, const double2* dens
                           const CenterRec* ctr, const double* jtab, double2* partial,
                           hipStream_t s);
 hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s);
+hipError_t launch_principal_value(int T, int nk, int side, int kind, const double* out,
+                                  const double* density, double* pv, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,

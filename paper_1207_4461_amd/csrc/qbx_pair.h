@@ -1,0 +1,458 @@
+// Pair-loop bodies shared by the per-contour kernels (qbx_forward.hip,
+// qbx_adjoint.hip) and the batched persistent kernels (qbx_batched.hip).
+//
+// Forward pair kernels of libqbx: the hot loop of QBX.
+//
+// For center c_i with target x_i (theta_i = arg(x_i - c_i), R_i = |x_i - c_i|)
+// and source x'_j (rho = |x'_j - c_i|, theta' = arg(x'_j - c_i)), the
+// expansion of Section 2 (eq. graf-coefficient) evaluated at the target
+// (Section 3.3 step 4(c)) is, summed over -p..p and paired l <-> -l with
+// H_{-l} = (-1)^l H_l, J_{-l} = (-1)^l J_l,
+//
+//   K_S = H_0 J_0 + 2 sum_{l=1}^{p} H_l(k rho) J_l(k R) cos(l Delta),
+//   Delta = theta_i - theta',
+//
+// and u_S(x_i) = (i/4) sum_j w_j sigma_j K_S.  The double layer
+// (eq. graf-coefficient-dlp) uses d/dn' f_l = (k/2)(conj(nu) f_{l-1} - nu f_{l+1})
+// with nu = n'_x + i n'_y; regrouped the same way,
+//
+//   K_D = k [ H_0 J_1 cos(psi) + sum_{m=1}^{p-1} H_m J_{m+1} cos(m Delta + psi)
+//                              - sum_{m=1}^{p+1} H_m J_{m-1} cos(m Delta - psi) ],
+//   psi = theta_i - arg(nu)   (for p = 0 only the last sum, at m = 1, remains).
+//
+// The storage-free variant of the paper's algorithm (each source adds its
+// contribution to u directly; the coefficients need not be stored) is what
+// the loop computes: one complex accumulator per kind and lane.  H_l comes from
+// the upward recurrence H_{l+1} = (2l/z) H_l - H_{l-1} from the seeds H_0, H_1;
+// cos(l Delta +- psi) from the Chebyshev recurrence c_{l+1} = 2 cos(Delta) c_l - c_{l-1};
+// J_l(k R_i) is a per-center table (Miller's recurrence), read as wave-uniform
+// scalars.
+//
+// Mapping: one wavefront per (center, source split); lanes stride over the
+// split's sources in chunks of 64 (coalesced double4 loads); a butterfly
+// reduction over the 64 lanes at the end; partial sums per split are added
+// in a fixed order by k_finalize (deterministic).
+//
+// Adjoint of the QBX hot path: forward-with-tape, source-major gradient pass,
+// per-center gradients and the chain rule back to the panel nodes.
+//
+// Notation (per pair): v = x'_j - c_i (rho, theta'), the target offset
+// w = x_i - c_i = R e^{i theta}, Delta = theta - theta', psi = theta - arg(nu_j),
+// and the pair kernels of the forward (see qbx_forward.hip)
+//   K_S = sum_l' 2 H_l(k rho) J_l(k R) cos(l Delta),
+//   K_D = k [H_0 J_1 cos psi + sum_{m<p} H_m J_{m+1} cos(m Delta + psi)
+//            - sum_{m<=p+1} H_m J_{m-1} cos(m Delta - psi)].
+// With G_i = conj(g_i) i/4 the loss is L = Re sum_ij G_i w_j sigma_j K_ij.
+//
+// Derivatives of the pair kernels (all from the same recurrences):
+//   d/drho:    H -> k H',  H'_l = (H_{l-1} - H_{l+1})/2   (DLMF 10.6.1)
+//   d/dR:      J -> k J'                                  (DLMF 10.6.1)
+//   d/dtheta': cos(l Delta) -> l sin(l Delta), cos(m Delta +- psi) -> m sin(..)
+//   d/dtheta:  Delta and psi both move: cos(m Delta +- psi) -> -(m +- 1) sin(..)
+//   d/dpsi (D, through the source normal's angle).
+// Source side (sum over centers, source-major pass):
+//   grad(w sigma)_j = sum_i conj(G_i K_ij),
+//   grad x'_j = Re w_j sigma_j sum_i G_i (K_rho v^ + K_theta' theta^ / rho),
+//   grad nu_j = Re w_j mu_j sum_i G_i K_psi (n_y, -n_x).
+// Center side (sum over sources, center-major tape pass): the forward also
+// stores F_R = sum_j w sigma K_R, F_t = sum_j w sigma K_theta and
+// GV = sum_j w sigma (K_rho v^ + K_theta' theta^/rho); then with c fixed the
+// target gradient is dR w^ + dtheta/R theta^_w, and with x fixed the center
+// gradient is -(Re G GV) - (that), which the chain rule through
+// c = x + s R n (R = r h_m) carries to the nodes.
+#pragma once
+
+#include "qbx_internal.h"
+#include "qbx_special.h"
+
+namespace qbx {
+
+struct Cplx {
+  double r, i;
+};
+
+__device__ __forceinline__ void cmac(Cplx& acc, double f, double hr, double hi) {
+  acc.r = fma(f, hr, acc.r);
+  acc.i = fma(f, hi, acc.i);
+}
+
+// per-pair sums (complex): which ones are formed depends on MODE
+//   MODE 0 (tape, center-major): K, K_R, K_theta, K_rho, K_theta'
+//   MODE 1 (source-major):       K, K_rho, K_theta', K_psi (D)
+struct PairOut {
+  Cplx Ks, KRs, Kts, Krs, Ktps;          // single layer
+  Cplx Kd, KRd, Ktd, Krd, Ktpd, Kpsid;   // double layer
+};
+
+template <int P, int KIND, int MODE>
+__device__ __forceinline__ PairOut pair_sums(double z, double iz, double cd, double sd, double cps,
+                                             double sps, double k, const double* __restrict__ J,
+                                             const double* __restrict__ Jd,
+                                             const double* __restrict__ cf) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr bool kTape = MODE == 0;
+  constexpr int LMAX = kD ? P + 1 : P;
+  const H01 h = hankel01(z, iz, cf);
+  double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
+  double hc_r = h.h1r, hc_i = h.h1i;  // H_l
+  const double tz = 2.0 * iz;
+  double tl = tz;
+  const double two_cd = 2.0 * cd;
+  Cplx sK = {0, 0}, sKR = {0, 0}, sKt = {0, 0}, sKr = {0, 0};
+  Cplx dK = {0, 0}, dKR = {0, 0}, dKt = {0, 0}, dKr = {0, 0}, dKtp = {0, 0}, dKpsi = {0, 0};
+  double c_m = 1.0, c_c = cd, s_m = 0.0, s_c = sd;           // cos, sin of l Delta
+  double a_m = cps, a_c = fma(cd, cps, -sd * sps);             // cos(l D + psi)
+  double b_m = cps, b_c = fma(cd, cps, sd * sps);              // cos(l D - psi)
+  double sa_m = sps, sa_c = fma(sd, cps, cd * sps);            // sin(l D + psi)
+  double sb_m = -sps, sb_c = fma(sd, cps, -cd * sps);          // sin(l D - psi)
+#pragma unroll
+  for (int l = 1; l <= LMAX; ++l) {
+    // H_{l+1} and d_l = H_{l-1} - H_{l+1} = 2 H_l'
+    const double hn_r = fma(tl, hc_r, -hm_r);
+    const double hn_i = fma(tl, hc_i, -hm_i);
+    const double d_r = hm_r - hn_r, d_i = hm_i - hn_i;
+    if (kS && l <= P) {
+      const double f = J[l] * c_c;
+      cmac(sK, f, hc_r, hc_i);
+      cmac(sKr, f, d_r, d_i);
+      const double g = (double)l * J[l] * s_c;
+      cmac(sKt, g, hc_r, hc_i);
+      if (kTape) cmac(sKR, Jd[l] * c_c, hc_r, hc_i);
+    }
+    if (kD) {
+      const bool up = l <= P - 1;
+      const double fb = J[l - 1] * b_c;
+      const double f = up ? fma(J[l + 1], a_c, -fb) : -fb;
+      cmac(dK, f, hc_r, hc_i);
+      cmac(dKr, f, d_r, d_i);
+      const double sA = up ? J[l + 1] * sa_c : 0.0;
+      const double sB = J[l - 1] * sb_c;
+      cmac(dKtp, (double)l * (sA - sB), hc_r, hc_i);
+      if (kTape) {
+        const double fbR = Jd[l - 1] * b_c;
+        const double fR = up ? fma(Jd[l + 1], a_c, -fbR) : -fbR;
+        cmac(dKR, fR, hc_r, hc_i);
+        cmac(dKt, fma((double)(l - 1), sB, -(double)(l + 1) * sA), hc_r, hc_i);
+      } else {
+        cmac(dKpsi, -(sA + sB), hc_r, hc_i);
+      }
+    }
+    hm_r = hc_r;
+    hm_i = hc_i;
+    hc_r = hn_r;
+    hc_i = hn_i;
+    tl += tz;
+    if (kS) {
+      const double cn = fma(two_cd, c_c, -c_m);
+      c_m = c_c;
+      c_c = cn;
+      const double sn = fma(two_cd, s_c, -s_m);
+      s_m = s_c;
+      s_c = sn;
+    }
+    if (kD) {
+      double t;
+      t = fma(two_cd, a_c, -a_m); a_m = a_c; a_c = t;
+      t = fma(two_cd, b_c, -b_m); b_m = b_c; b_c = t;
+      t = fma(two_cd, sa_c, -sa_m); sa_m = sa_c; sa_c = t;
+      t = fma(two_cd, sb_c, -sb_m); sb_m = sb_c; sb_c = t;
+    }
+  }
+  PairOut o;
+  const double H0r = h.h0r, H0i = h.h0i, H1r = h.h1r, H1i = h.h1i;
+  if (kS) {
+    o.Ks = {fma(2.0, sK.r, J[0] * H0r), fma(2.0, sK.i, J[0] * H0i)};
+    o.Krs = {k * fma(-J[0], H1r, sKr.r), k * fma(-J[0], H1i, sKr.i)};
+    o.Ktps = {2.0 * sKt.r, 2.0 * sKt.i};
+    o.Kts = {-2.0 * sKt.r, -2.0 * sKt.i};
+    if (kTape) o.KRs = {k * fma(2.0, sKR.r, Jd[0] * H0r), k * fma(2.0, sKR.i, Jd[0] * H0i)};
+  }
+  if (kD) {
+    // the m = 0 terms (H_0 J_1 cos psi and its derivatives) exist only when p >= 1
+    const double f0 = P >= 1 ? J[1] * cps : 0.0, g0 = P >= 1 ? J[1] * sps : 0.0;
+    o.Kd = {k * fma(f0, H0r, dK.r), k * fma(f0, H0i, dK.i)};
+    o.Krd = {k * k * fma(-f0, H1r, 0.5 * dKr.r), k * k * fma(-f0, H1i, 0.5 * dKr.i)};
+    o.Ktpd = {k * dKtp.r, k * dKtp.i};
+    if (kTape) {
+      const double fR0 = P >= 1 ? Jd[1] * cps : 0.0;
+      o.KRd = {k * k * fma(fR0, H0r, dKR.r), k * k * fma(fR0, H0i, dKR.i)};
+      o.Ktd = {k * fma(-g0, H0r, dKt.r), k * fma(-g0, H0i, dKt.i)};
+    } else {
+      o.Kpsid = {k * fma(-g0, H0r, dKpsi.r), k * fma(-g0, H0i, dKpsi.i)};
+    }
+  }
+  return o;
+}
+
+__device__ __forceinline__ void cmul_acc(Cplx& acc, double wr, double wi, Cplx a) {
+  // acc += w * a
+  acc.r = fma(wr, a.r, fma(-wi, a.i, acc.r));
+  acc.i = fma(wr, a.i, fma(wi, a.r, acc.i));
+}
+
+__device__ __forceinline__ void wave_sum(Cplx& a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a.r += __shfl_xor(a.r, off);
+    a.i += __shfl_xor(a.i, off);
+  }
+}
+
+template <int P, int KIND>
+__device__ __forceinline__ void pair_kernel(double z, double iz, double cd, double sd, double cps,
+                                            double sps, const double* __restrict__ J,
+                                            const double* __restrict__ cf, double& s_r,
+                                            double& s_i, double& d_r, double& d_i) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int LMAX = kD ? P + 1 : P;
+  const H01 h = hankel01(z, iz, cf);
+  double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
+  double hc_r = h.h1r, hc_i = h.h1i;  // H_l
+  const double tz = 2.0 * iz;
+  double tl = tz;                     // 2l/z
+  const double two_cd = 2.0 * cd;
+  // l = 0 terms
+  double a0r = 0.0, a0i = 0.0, sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  if (kS) {
+    a0r = J[0] * hm_r;
+    a0i = J[0] * hm_i;
+  }
+  if (kD && P >= 1) {   // the m = 0 term exists only when p >= 1
+    const double f = J[1] * cps;
+    dr = f * hm_r;
+    di = f * hm_i;
+  }
+  double c_m = 1.0, c_c = cd;                            // cos((l-1)D), cos(lD)
+  double a_m = cps, a_c = fma(cd, cps, -sd * sps);       // cos((l-1)D + psi), cos(lD + psi)
+  double b_m = cps, b_c = fma(cd, cps, sd * sps);        // cos((l-1)D - psi), cos(lD - psi)
+#pragma unroll
+  for (int l = 1; l <= LMAX; ++l) {
+    if (kS && l <= P) {
+      const double f = J[l] * c_c;
+      sr = fma(f, hc_r, sr);
+      si = fma(f, hc_i, si);
+    }
+    if (kD) {
+      double f = -J[l - 1] * b_c;
+      if (l <= P - 1) f = fma(J[l + 1], a_c, f);
+      dr = fma(f, hc_r, dr);
+      di = fma(f, hc_i, di);
+    }
+    if (l < LMAX) {
+      const double hn_r = fma(tl, hc_r, -hm_r);
+      const double hn_i = fma(tl, hc_i, -hm_i);
+      hm_r = hc_r;
+      hm_i = hc_i;
+      hc_r = hn_r;
+      hc_i = hn_i;
+      tl += tz;
+      if (kS) {
+        const double cn = fma(two_cd, c_c, -c_m);
+        c_m = c_c;
+        c_c = cn;
+      }
+      if (kD) {
+        const double an = fma(two_cd, a_c, -a_m);
+        a_m = a_c;
+        a_c = an;
+        const double bn = fma(two_cd, b_c, -b_m);
+        b_m = b_c;
+        b_c = bn;
+      }
+    }
+  }
+  s_r = fma(2.0, sr, a0r);
+  s_i = fma(2.0, si, a0i);
+  d_r = dr;
+  d_i = di;
+}
+
+
+// ---------------------------------------------------------------------------
+// forward: one wave, one center, sources of chunks [c0, c1); returns the sums
+// of w sigma K_S and w mu K_D / k reduced over the wave (in every lane)
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void forward_center(const double4* __restrict__ geo,
+                                               const double2* __restrict__ dens, int N,
+                                               const CenterRec* __restrict__ Crec,
+                                               const double* __restrict__ Jtab, double k, int c0,
+                                               int c1, int lane, Cplx& S, Cplx& Dd) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  const double cx = Crec->cx, cy = Crec->cy, ct = Crec->ct, st = Crec->st;
+  const double inv_k = 1.0 / k;
+  double accS_r = 0.0, accS_i = 0.0, accD_r = 0.0, accD_i = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const int j = c * kWave + lane;
+    if (j < N) {
+      // uniform tables re-read (scalar cache) every iteration, see opaque_zero()
+      const int z0 = opaque_zero();
+      const double* __restrict__ J = Jtab + z0;
+      const double* __restrict__ cf = g_seed_table + z0;
+      const double4 g = geo[j];
+      const double vx = g.x - cx, vy = g.y - cy;
+      const double rho = sqrt(fma(vx, vx, vy * vy));
+      const double ir = 1.0 / rho;
+      const double cd = (ct * vx + st * vy) * ir;   // cos(theta_i - theta')
+      const double sd = (st * vx - ct * vy) * ir;   // sin(theta_i - theta')
+      double cps = 0.0, sps = 0.0;
+      if (kD) {
+        cps = ct * g.z + st * g.w;                   // cos(theta_i - arg nu)
+        sps = st * g.z - ct * g.w;                   // sin(theta_i - arg nu)
+      }
+      double s_r, s_i, d_r, d_i;
+      pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, s_r, s_i, d_r, d_i);
+      if (kS) {
+        const double2 w = dens[j];
+        accS_r = fma(w.x, s_r, fma(-w.y, s_i, accS_r));
+        accS_i = fma(w.x, s_i, fma(w.y, s_r, accS_i));
+      }
+      if (kD) {
+        const double2 w = dens[(kS ? (size_t)N : 0) + j];
+        accD_r = fma(w.x, d_r, fma(-w.y, d_i, accD_r));
+        accD_i = fma(w.x, d_i, fma(w.y, d_r, accD_i));
+      }
+    }
+  }
+  S = {accS_r, accS_i};
+  Dd = {accD_r, accD_i};
+  if (kS) wave_sum(S);
+  if (kD) wave_sum(Dd);
+}
+
+// ---------------------------------------------------------------------------
+// forward with tape: one wave, one center, chunks [c0, c1); A[kind][0..4] =
+// sums of w*density times K, K_R, K_theta, and the two components of grad_v K,
+// reduced over the wave
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
+                                            const double2* __restrict__ dens, int N,
+                                            const CenterRec* __restrict__ Crec,
+                                            const double* __restrict__ Jtab, int NJ, double k,
+                                            int c0, int c1, int lane, Cplx (&A)[2][5]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const double cx = Crec->cx, cy = Crec->cy, ct = Crec->ct, st = Crec->st;
+  const double inv_k = 1.0 / k;
+  const int nj = NJ / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) A[a][b] = {0.0, 0.0};
+  for (int c = c0; c < c1; ++c) {
+    const int j = c * kWave + lane;
+    if (j < N) {
+      const int z0 = opaque_zero();
+      const double* __restrict__ J = Jtab + z0;
+      const double* __restrict__ cf = g_seed_table + z0;
+      const double4 g = geo[j];
+      const double vx = g.x - cx, vy = g.y - cy;
+      const double rho = sqrt(fma(vx, vx, vy * vy));
+      const double ir = 1.0 / rho;
+      const double ux = vx * ir, uy = vy * ir;          // v^ ; theta^ = (-uy, ux)
+      const double cd = ct * ux + st * uy;
+      const double sd = st * ux - ct * uy;
+      double cps = 0.0, sps = 0.0;
+      if (kD) {
+        cps = ct * g.z + st * g.w;
+        sps = st * g.z - ct * g.w;
+      }
+      const PairOut o = pair_sums<P, KIND, 0>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+      int kk = 0;
+      if (kS) {
+        const double2 w = dens[j];
+        const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
+        const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
+        cmul_acc(A[kk][0], w.x, w.y, o.Ks);
+        cmul_acc(A[kk][1], w.x, w.y, o.KRs);
+        cmul_acc(A[kk][2], w.x, w.y, o.Kts);
+        cmul_acc(A[kk][3], w.x, w.y, ex);
+        cmul_acc(A[kk][4], w.x, w.y, ey);
+        ++kk;
+      }
+      if (kD) {
+        const double2 w = dens[(kS ? (size_t)N : 0) + j];
+        const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
+        const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
+        cmul_acc(A[kk][0], w.x, w.y, o.Kd);
+        cmul_acc(A[kk][1], w.x, w.y, o.KRd);
+        cmul_acc(A[kk][2], w.x, w.y, o.Ktd);
+        cmul_acc(A[kk][3], w.x, w.y, ex);
+        cmul_acc(A[kk][4], w.x, w.y, ey);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) wave_sum(A[kk][b]);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, source side: one lane, one source g, centers [i0, i1); A as in the
+// partial layout of the source-major pass
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void adjoint_source(const double4 g, const CenterRec* __restrict__ ctr,
+                                               const double* __restrict__ jtab, int NJ,
+                                               const double2* __restrict__ G, int Mc, int i0,
+                                               int i1, double k,
+                                               Cplx (&A)[((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0)]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
+  const double inv_k = 1.0 / k;
+  const int nj = NJ / 2;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) A[a] = {0.0, 0.0};
+  for (int ci = i0; ci < i1; ++ci) {
+    const int z0 = opaque_zero();
+    const CenterRec* __restrict__ C = ctr + ci + z0;
+    const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
+    const double* __restrict__ cf = g_seed_table + z0;
+    const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
+    const double vx = g.x - cx, vy = g.y - cy;
+    const double rho = sqrt(fma(vx, vx, vy * vy));
+    const double ir = 1.0 / rho;
+    const double ux = vx * ir, uy = vy * ir;
+    const double cd = ct * ux + st * uy;
+    const double sd = st * ux - ct * uy;
+    double cps = 0.0, sps = 0.0;
+    if (kD) {
+      cps = ct * g.z + st * g.w;
+      sps = st * g.z - ct * g.w;
+    }
+    const PairOut o = pair_sums<P, KIND, 1>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+    int a = 0;
+    int kk = 0;
+    if (kS) {
+      const double2 Gs = G[(size_t)ci + z0];
+      // conj(G K)
+      A[0].r += Gs.x * o.Ks.r - Gs.y * o.Ks.i;
+      A[0].i -= Gs.x * o.Ks.i + Gs.y * o.Ks.r;
+      const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
+      const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
+      cmul_acc(A[1], Gs.x, Gs.y, ex);
+      cmul_acc(A[2], Gs.x, Gs.y, ey);
+      a = 3;
+      kk = 1;
+    }
+    if (kD) {
+      const double2 Gd = G[(size_t)kk * Mc + ci + z0];
+      A[a].r += Gd.x * o.Kd.r - Gd.y * o.Kd.i;
+      A[a].i -= Gd.x * o.Kd.i + Gd.y * o.Kd.r;
+      const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
+      const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
+      cmul_acc(A[a + 1], Gd.x, Gd.y, ex);
+      cmul_acc(A[a + 2], Gd.x, Gd.y, ey);
+      cmul_acc(A[a + 3], Gd.x, Gd.y, o.Kpsid);
+    }
+  }
+}
+
+}  // namespace qbx

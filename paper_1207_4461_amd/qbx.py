@@ -96,6 +96,24 @@ def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int
     return out
 
 
+def principal_value(out: torch.Tensor, density: Optional[torch.Tensor], side: int,
+                    kind: int) -> torch.Tensor:
+    """Principal value [n_kinds, 16P] from the one-sided limits ``out`` (Section 3.2):
+    the average of both limits for side=BOTH, else the one limit with the D jump removed."""
+    lib = _lib.load()
+    nk = n_kinds(kind)
+    T = int(out.shape[-1])
+    _need(out, "out", torch.complex128, (n_sides(side), nk, T))
+    if density is not None:
+        _need(density, "density", torch.complex128, (nk, T))
+    pv = torch.empty((nk, T), dtype=torch.complex128, device=out.device)
+    _lib.check(lib.qbx_principal_value(out.data_ptr(),
+                                       density.data_ptr() if density is not None else None,
+                                       T // Q, int(side), int(kind), pv.data_ptr(),
+                                       _stream(out.device)))
+    return pv
+
+
 def check_geometry(nodes: torch.Tensor, p: int, r: float = 0.5, oversample: int = 4,
                    side: int = EXTERIOR) -> Tuple[int, float, float]:
     """Synchronous check: (status, signed area, min |x'-c|/R).  status is 0, QBX_EORIENT
@@ -203,3 +221,86 @@ def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: f
     """Differentiable layer_potential (gradients for density and nodes via the HIP adjoint)."""
     return _LayerPotential.apply(nodes, density, float(k), int(p), float(r), int(oversample),
                                  int(side), int(kind))
+
+
+class Batch:
+    """Many contours packed for the batched C entry points (one persistent launch per pass).
+
+    ``problems``: sequence of objects with attributes nodes [P,16,2] (numpy or tensor),
+    density [n_kinds, 16P] complex, k, p, r, side, kind.  All share ``oversample``.
+    Packing (host -> device copies, item table, workspace) happens once here."""
+
+    def __init__(self, problems, oversample: int = 4, device="cuda"):
+        lib = _lib.load()
+        self.oversample = int(oversample)
+        self.problems = list(problems)
+        n = len(self.problems)
+        self.items = (_lib.BatchItem * n)()
+        node_off = dens_off = out_off = 0
+        nodes, dens = [], []
+        self.slices = []
+        for i, pb in enumerate(self.problems):
+            P = int(pb.nodes.shape[0])
+            nk, ns = n_kinds(pb.kind), n_sides(pb.side)
+            T = P * Q
+            it = self.items[i]
+            it.node_offset, it.density_offset, it.out_offset = node_off, dens_off, out_off
+            it.n_panels, it.p, it.kind, it.side = P, int(pb.p), int(pb.kind), int(pb.side)
+            it.k, it.r = float(pb.k), float(pb.r)
+            self.slices.append(((node_off, P), (dens_off, nk, T), (out_off, ns, nk, T)))
+            nodes.append(torch.as_tensor(pb.nodes, dtype=torch.float64).reshape(-1))
+            dens.append(torch.as_tensor(pb.density, dtype=torch.complex128).reshape(-1))
+            node_off += P
+            dens_off += nk * T
+            out_off += ns * nk * T
+        dev = torch.device(device)
+        self.nodes = torch.cat(nodes).to(dev).contiguous()
+        self.density = torch.cat(dens).to(dev).contiguous()
+        self.n_out = out_off
+        self.device = dev
+        nb = lib.qbx_batched_workspace_bytes(self.items, n, self.oversample)
+        if nb == 0:
+            raise _lib.QBXError(_lib.QBX_EINVAL, "invalid batch")
+        self.ws = torch.empty(int(nb), dtype=torch.uint8, device=dev)
+        self.tape = torch.empty(int(lib.qbx_batched_tape_bytes(self.items, n)), dtype=torch.uint8,
+                                device=dev)
+        self._lib = lib
+
+    def forward(self, with_tape: bool = False) -> torch.Tensor:
+        """Packed one-sided limits (concatenated per-contour out blocks)."""
+        out = torch.empty(self.n_out, dtype=torch.complex128, device=self.device)
+        _lib.check(self._lib.qbx_layer_potential_batched(
+            self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
+            C.c_void_p(self.density.data_ptr()), C.c_void_p(out.data_ptr()),
+            C.c_void_p(self.tape.data_ptr()) if with_tape else None, self.oversample,
+            C.c_void_p(self.ws.data_ptr()), C.c_size_t(self.ws.numel()),
+            C.c_void_p(_stream(self.device))))
+        return out
+
+    def adjoint(self, cotangent: torch.Tensor, use_tape: bool = False):
+        """(grad_density, grad_nodes) packed like density and nodes."""
+        gd = torch.empty_like(self.density)
+        gn = torch.empty_like(self.nodes)
+        _lib.check(self._lib.qbx_layer_potential_batched_adjoint(
+            self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
+            C.c_void_p(self.density.data_ptr()), C.c_void_p(cotangent.data_ptr()),
+            C.c_void_p(self.tape.data_ptr()) if use_tape else None, C.c_void_p(gd.data_ptr()),
+            C.c_void_p(gn.data_ptr()), self.oversample, C.c_void_p(self.ws.data_ptr()),
+            C.c_size_t(self.ws.numel()), C.c_void_p(_stream(self.device))))
+        return gd, gn
+
+    def split_out(self, out: torch.Tensor):
+        res = []
+        for (_, (o, ns, nk, T)) in ((s[0], s[2]) for s in self.slices):
+            res.append(out[o:o + ns * nk * T].reshape(ns, nk, T))
+        return res
+
+    def split_density(self, d: torch.Tensor):
+        return [d[o:o + nk * T].reshape(nk, T) for (_, (o, nk, T), _) in self.slices]
+
+    def split_nodes(self, x: torch.Tensor):
+        return [x[o * 32:(o + P) * 32].reshape(P, Q, 2) for ((o, P), _, _) in self.slices]
+
+    def pack_out(self, per_contour):
+        return torch.cat([torch.as_tensor(a, dtype=torch.complex128).reshape(-1)
+                          for a in per_contour]).to(self.device).contiguous()

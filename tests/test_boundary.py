@@ -116,3 +116,42 @@ def test_signed_area_host_and_orientation(lib):
 def test_debug_hooks_validate(lib):
     assert lib.qbx_debug_hankel01(None, 4, None, None, None) == _lib.QBX_EINVAL
     assert lib.qbx_debug_besselj(BAD, 4, 99, BAD, None) == _lib.QBX_EINVAL
+
+
+def test_principal_value_validation(lib):
+    assert lib.qbx_principal_value(None, None, 8, 0, 1, BAD, None) == _lib.QBX_EINVAL
+    assert lib.qbx_principal_value(BAD, None, 2, 0, 1, BAD, None) == _lib.QBX_EINVAL
+    assert lib.qbx_principal_value(BAD, None, 8, 3, 1, BAD, None) == _lib.QBX_EINVAL
+    assert lib.qbx_principal_value(BAD, None, 8, 1, 2, BAD, None) == _lib.QBX_EINVAL
+
+
+def _items(n=3):
+    its = (_lib.BatchItem * n)()
+    for i in range(n):
+        it = its[i]
+        it.node_offset, it.density_offset, it.out_offset = 8 * i, 128 * i, 256 * i
+        it.n_panels, it.p, it.kind, it.side, it.k, it.r = 8, 6, 1, 0, 3.0, 0.5
+    return its
+
+
+def test_batched_validation(lib):
+    its = _items()
+    n = lib.qbx_batched_workspace_bytes(its, 3, 4)
+    assert n > 0 and n % 256 == 0
+    assert lib.qbx_batched_tape_bytes(its, 3) > 0
+    assert lib.qbx_batched_workspace_bytes(its, 0, 4) == 0
+    assert lib.qbx_batched_workspace_bytes(its, 3, 0) == 0
+    for field, bad in (("n_panels", 2), ("p", 25), ("kind", 0), ("side", 5), ("k", -1.0),
+                       ("r", 0.0), ("node_offset", -1)):
+        its = _items()
+        setattr(its[1], field, bad)
+        assert lib.qbx_batched_workspace_bytes(its, 3, 4) == 0
+        assert lib.qbx_layer_potential_batched(its, 3, BAD, BAD, BAD, None, 4, BAD, 1 << 40,
+                                               None) == _lib.QBX_EINVAL
+    its = _items()
+    assert lib.qbx_layer_potential_batched(its, 3, None, BAD, BAD, None, 4, BAD, 1 << 40,
+                                           None) == _lib.QBX_EINVAL
+    assert lib.qbx_layer_potential_batched(its, 3, BAD, BAD, BAD, None, 4, BAD, 10,
+                                           None) == _lib.QBX_EWORKSPACE
+    assert lib.qbx_layer_potential_batched_adjoint(its, 3, BAD, BAD, None, None, BAD, BAD, 4, BAD,
+                                                   1 << 40, None) == _lib.QBX_EINVAL

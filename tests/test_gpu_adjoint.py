@@ -52,6 +52,7 @@ CASES = [
     dict(name="S-ext-p4", n_panels=5, p=4, kind=1, side=1),
     dict(name="S-int-p0", n_panels=4, p=0, kind=1, side=-1),
     dict(name="D-ext-p3", n_panels=5, p=3, kind=2, side=1),
+    dict(name="SD-both-p0", n_panels=4, p=0, kind=3, side=0),
     dict(name="D-both-p1", n_panels=4, p=1, kind=2, side=0),
     dict(name="SD-both-p6", n_panels=6, p=6, kind=3, side=0),
     dict(name="SD-both-p12-os2", n_panels=5, p=12, kind=3, side=0, oversample=2, k=7.0),

@@ -71,6 +71,8 @@ SMALL = [
     dict(name="S-ext-p0", n_panels=5, p=0, kind=I.S_KIND, side=I.EXTERIOR),
     dict(name="S-int-p5", n_panels=6, p=5, kind=I.S_KIND, side=I.INTERIOR),
     dict(name="D-ext-p3", n_panels=4, p=3, kind=I.D_KIND, side=I.EXTERIOR),
+    dict(name="D-int-p0", n_panels=4, p=0, kind=I.D_KIND, side=I.INTERIOR),
+    dict(name="SD-both-p0", n_panels=5, p=0, kind=3, side=I.BOTH),
     dict(name="D-both-p1", n_panels=5, p=1, kind=I.D_KIND, side=I.BOTH),
     dict(name="SD-both-p7", n_panels=7, p=7, kind=3, side=I.BOTH),
     dict(name="SD-both-p24", n_panels=9, p=24, kind=3, side=I.BOTH, k=2.0),
@@ -151,3 +153,22 @@ def test_check_geometry(Q):
     # centers pushed far out: their disks swallow other parts of the curve
     rc, _, ratio = Q.check_geometry(nodes, pb.p, 8.0, pb.oversample, I.BOTH)
     assert rc == -4 and ratio < 1.0
+
+
+def test_principal_value(Q):
+    """PV of D from both limits (eq. dlp-twosided) equals each one-sided limit minus
+    its jump (eq. dlpjump) to QBX accuracy; the average is exact arithmetic."""
+    pb = I.small(n_panels=24, p=10, k=4.0, kind=3, side=I.BOTH)
+    nodes = torch.from_numpy(pb.nodes).cuda()
+    dens = torch.from_numpy(np.ascontiguousarray(pb.density)).cuda()
+    u = Q.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, I.BOTH, 3)
+    pv = Q.principal_value(u, dens, I.BOTH, 3).cpu().numpy()
+    un = u.cpu().numpy()
+    assert np.array_equal(pv, 0.5 * (un[0] + un[1]))
+    for s in (I.EXTERIOR, I.INTERIOR):
+        u1 = Q.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, s, 3)
+        pv1 = Q.principal_value(u1, dens, s, 3).cpu().numpy()
+        for kk in range(2):
+            err = np.abs(pv1[kk] - pv[kk]).max() / np.abs(pv[kk]).max()
+            say(f"  side {s} kind {kk}: one-sided PV vs two-sided {err:.3e}")
+            assert err < 1e-6
