@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the QBX hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg4] [--mode fwdbwd]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload star4096] [--mode fwdbwd]
 
 A step is one pass of the whole hot path over one batch of synthetic input that
 already sits in HBM: source grid and centers (upsampling), the pair kernels,
@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg4", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--workload", default="star4096",
+                    choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -60,7 +61,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lib = _lib.load()
-    if args.workload == "cfg3":
+    if args.workload == "random64":
         return bench_batched(args)
     have_bwd = hasattr(qbx, "layer_potential_vjp")
     mode = args.mode or ("fwdbwd" if have_bwd else "fwd")
@@ -203,7 +204,7 @@ def main():
 
 
 def bench_batched(args):
-    """64 random contours (cfg3): one persistent launch per pass vs one launch per contour."""
+    """64 random contours (random64): one persistent launch per pass vs one launch per contour."""
     import ctypes as C
 
     import numpy as np
@@ -213,12 +214,12 @@ def bench_batched(args):
 
     lib = _lib.load()
     mode = args.mode or "fwdbwd"
-    pbs = I.cfg3()
+    pbs = I.random64()
     dev = torch.device("cuda:0")
     B = qbx.Batch(pbs, oversample=4, device=dev)
     cot = B.pack_out([pb.cotangent for pb in pbs])
     inter = sum(flops.interactions(pb.n_centers, pb.n_sources, pb.kind) for pb in pbs)
-    log(f"workload cfg3: {len(pbs)} contours, {sum(pb.n_panels for pb in pbs)} panels, "
+    log(f"workload random64: {len(pbs)} contours, {sum(pb.n_panels for pb in pbs)} panels, "
         f"{inter:.3e} interactions per pass, mode={mode}")
 
     def step_batched():
@@ -285,7 +286,7 @@ def bench_batched(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_bat * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cfg3: 64 random star contours, 16..512 panels x 16 nodes, "
+        "config": {"workload": "random64: 64 random star contours, 16..512 panels x 16 nodes, "
                                "oversample 4, k~U(5,50), p in {8,12,16}, S or D, exterior",
                    "mode": mode, "interactions_per_step": inter,
                    "per_contour_ms_per_step": t_per * 1e3,

@@ -186,39 +186,39 @@ def make_problem(name: str, curve: Curve, n_panels: int, k: float, p: int, side:
 
 # The five workloads (sizes, shapes and parameters of the paper's tests scaled to
 # one MI355X).  Curves are in t in [0, 2*pi).
-def cfg0(seed: int = 0) -> Problem:
+def ellipse32(seed: int = 0) -> Problem:
     """Ellipse (1, 0.5), 32 panels, k=10, p=8, exterior, S only."""
     return make_problem("ellipse-32", ellipse(1.0, 0.5), 32, 10.0, 8, EXTERIOR, S_KIND, seed,
                         with_cotangent=True)
 
 
-def cfg1(seed: int = 1) -> Problem:
+def star256(seed: int = 1) -> Problem:
     """Starfish 1+0.25cos5t, 256 panels, k=20, p=12, both sides, S and D."""
     return make_problem("starfish5-256", star((5, 0.25, 0.0)), 256, 20.0, 12, BOTH,
                         S_KIND | D_KIND, seed, with_cotangent=True)
 
 
-def cfg1_green(seed: int = 1, x0=(3.0, 1.0)) -> Problem:
-    """cfg1's geometry with the Green's-identity pair: S density du/dn, D density u."""
-    prob = cfg1(seed)
+def star256_green(seed: int = 1, x0=(3.0, 1.0)) -> Problem:
+    """star256's geometry with the Green's-identity pair: S density du/dn, D density u."""
+    prob = star256(seed)
     u, dudn = green_pair(prob.curve, prob.n_panels, prob.k, x0)
     prob.density = np.stack([dudn, u])
     return prob
 
 
-def cfg2(seed: int = 2) -> Problem:
+def star1024(seed: int = 2) -> Problem:
     """Starfish 1+0.3cos7t, 1024 panels, k=40, p=16, exterior, S, fwd+bwd."""
     return make_problem("starfish7-1024", star((7, 0.3, 0.0)), 1024, 40.0, 16, EXTERIOR, S_KIND,
                         seed, with_cotangent=True)
 
 
-def cfg4(seed: int = 4) -> Problem:
+def star4096(seed: int = 4) -> Problem:
     """Starfish 1+0.25cos5t+0.05cos13t, 4096 panels, k=100, p=20, both sides, S+D."""
     return make_problem("starfish5-13-4096", star((5, 0.25, 0.0), (13, 0.05, 0.0)), 4096, 100.0,
                         20, BOTH, S_KIND | D_KIND, seed, max_mode=60, with_cotangent=True)
 
 
-def cfg3(seed: int = 3, n_contours: int = 64) -> List[Problem]:
+def random64(seed: int = 3, n_contours: int = 64) -> List[Problem]:
     """64 random star contours r = 1 + sum_{m=2..8} a_m cos(mt+phi_m), a_m~U(0,.05),
     phi_m~U(0,2pi); panels ~U{16..512}; k~U(5,50); p in {8,12,16}; S or D (prob 1/2);
     exterior centers.  Everything is drawn from one generator."""
@@ -249,5 +249,6 @@ def small(name: str = "small", n_panels: int = 6, k: float = 3.0, p: int = 5, si
 
 
 CONFIGS: Dict[str, Callable[..., object]] = {
-    "cfg0": cfg0, "cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4,
+    "ellipse32": ellipse32, "star256": star256, "star1024": star1024, "random64": random64,
+    "star4096": star4096,
 }

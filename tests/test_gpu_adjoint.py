@@ -112,7 +112,7 @@ def _panels(pb, n, seed):
     return np.unique(np.concatenate([[0, pb.n_panels - 1], rng.choice(pb.n_panels, n, replace=False)]))
 
 
-@pytest.mark.parametrize("cfg,n", [("cfg1", 3), ("cfg2", 2)])
+@pytest.mark.parametrize("cfg,n", [("star256", 3), ("star1024", 2)])
 def test_adjoint_full_size_sampled_panels(Q, cfg, n):
     pb = getattr(I, cfg)()
     sel = _panels(pb, n, 11)
@@ -129,7 +129,7 @@ def test_adjoint_full_size_sampled_panels(Q, cfg, n):
     assert ed <= TOL_D and en <= TOL_N
 
 
-@pytest.mark.parametrize("cfg", ["cfg2", "cfg4"])
+@pytest.mark.parametrize("cfg", ["star1024", "star4096"])
 def test_adjoint_full_size_properties(Q, cfg):
     """Linearity (dot-product test), translation and rotation invariance of the node
     gradient, and a central difference of the GPU forward along a smooth deformation."""

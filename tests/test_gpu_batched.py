@@ -82,8 +82,8 @@ def test_batched_adjoint_matches_per_contour_and_oracle(Q):
         assert rel(a, pd.cpu().numpy()) < 1e-12 and rel(x, pn.cpu().numpy()) < 1e-11
 
 
-def test_cfg3_batch_full(Q):
-    pbs = I.cfg3()
+def test_random64_batch_full(Q):
+    pbs = I.random64()
     B = Q.Batch(pbs, oversample=4)
     out = B.forward(with_tape=True)
     outs = B.split_out(out)
@@ -97,7 +97,7 @@ def test_cfg3_batch_full(Q):
                                        pb.p, pb.r, pb.oversample, pb.side, pb.kind)
         worst_d = max(worst_d, rel(B.split_density(gd)[i].cpu().numpy(), pd.cpu().numpy()))
         worst_n = max(worst_n, rel(B.split_nodes(gn)[i].cpu().numpy(), pn.cpu().numpy()))
-    say(f"  cfg3 batch vs per-contour: forward {worst_f:.2e} grad density {worst_d:.2e} "
+    say(f"  random64 batch vs per-contour: forward {worst_f:.2e} grad density {worst_d:.2e} "
         f"grad nodes {worst_n:.2e}")
     assert worst_f < 1e-13 and worst_d < 1e-12 and worst_n < 1e-11
     # oracle on sampled targets of three contours (smallest, largest, one D)

@@ -95,12 +95,12 @@ def test_forward_small_elementwise(Q, case):
     assert_parity(u, ref, what=name)
 
 
-def test_forward_cfg0_full(Q):
-    pb = I.cfg0()
-    say(f"cfg0 full: P={pb.n_panels} p={pb.p}")
+def test_forward_ellipse32_full(Q):
+    pb = I.ellipse32()
+    say(f"ellipse32 full: P={pb.n_panels} p={pb.p}")
     ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
                             pb.kind).numpy()
-    assert_parity(gpu_forward(Q, pb), ref, what="cfg0")
+    assert_parity(gpu_forward(Q, pb), ref, what="ellipse32")
 
 
 def _sampled(pb, n, seed):
@@ -110,7 +110,7 @@ def _sampled(pb, n, seed):
     return np.unique(np.concatenate([[0, pb.n_targets - 1], idx]))
 
 
-@pytest.mark.parametrize("cfg,n", [("cfg1", 96), ("cfg2", 48), ("cfg4", 16)])
+@pytest.mark.parametrize("cfg,n", [("star256", 96), ("star1024", 48), ("star4096", 16)])
 def test_forward_full_size_sampled(Q, cfg, n):
     pb = getattr(I, cfg)()
     idx = _sampled(pb, n, 7)
@@ -122,9 +122,9 @@ def test_forward_full_size_sampled(Q, cfg, n):
 
 
 def test_green_identity_on_gpu(Q):
-    """S^-[du/dn] - D^-[u] = u and S^+[du/dn] - D^+[u] = 0 on the cfg1 contour (to QBX
+    """S^-[du/dn] - D^-[u] = u and S^+[du/dn] - D^+[u] = 0 on the star256 contour (to QBX
     accuracy), computed entirely by the GPU path."""
-    pb = I.cfg1_green()
+    pb = I.star256_green()
     u = gpu_forward(Q, pb)
     ug, _ = I.green_pair(pb.curve, pb.n_panels, pb.k)
     sc = np.abs(ug).max()
@@ -142,10 +142,10 @@ def test_repeat_is_bitwise_deterministic(Q):
 
 
 def test_check_geometry(Q):
-    pb = I.cfg1()
+    pb = I.star256()
     nodes = torch.from_numpy(pb.nodes).cuda()
     rc, area, ratio = Q.check_geometry(nodes, pb.p, pb.r, pb.oversample, I.BOTH)
-    say(f"  cfg1: area {area} min ratio {ratio}")
+    say(f"  star256: area {area} min ratio {ratio}")
     assert rc == 0 and abs(area - np.pi * (1 + 0.25**2 / 2)) < 1e-10 and ratio > 1.0
     rev = torch.from_numpy(np.ascontiguousarray(pb.nodes[::-1, ::-1])).cuda()
     rc, area, _ = Q.check_geometry(rev, pb.p, pb.r, pb.oversample, I.BOTH)
