@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="time the launch shapes on the workload first (untimed) and use the best")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time of the oracle sample")
@@ -72,6 +74,12 @@ def main():
     nodes = torch.from_numpy(pb.nodes).to(dev)
     dens = torch.from_numpy(np.ascontiguousarray(pb.density)).to(dev)
     cot = torch.from_numpy(np.ascontiguousarray(pb.cotangent)).to(dev)
+    tuning = qbx.get_tuning()
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuning = qbx.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                              passes=1)
+        log(f"autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     ws = torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side, pb.kind),
                      dtype=torch.uint8, device=dev)
     log(f"workload {args.workload} ({pb.name}): P={pb.n_panels} p={pb.p} k={pb.k} "
@@ -195,7 +203,7 @@ def main():
                                f"side={'both' if pb.side == 0 else pb.side}, "
                                f"kind={'S+D' if pb.kind == 3 else ('S' if pb.kind == 1 else 'D')}",
                    "mode": mode, "centers": pb.n_centers, "sources": pb.n_sources,
-                   "interactions_per_step": inter},
+                   "interactions_per_step": inter, "tuning": tuning},
         "fwd_value": inter / fwd_s,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -263,6 +271,11 @@ def bench_batched(args):
         return (time.perf_counter() - t0) / steps
 
     t_per = timed(step_per_contour, max(1, args.steps))
+    tuning = qbx.get_tuning()
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuning = B.autotune(passes=1)
+        log(f"batched autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     lib.qbx_kernel_timer(1)
     t_bat = timed(step_batched, args.steps)
     NC = 4
@@ -289,7 +302,7 @@ def bench_batched(args):
         "config": {"workload": "random64: 64 random star contours, 16..512 panels x 16 nodes, "
                                "oversample 4, k~U(5,50), p in {8,12,16}, S or D, exterior",
                    "mode": mode, "interactions_per_step": inter,
-                   "per_contour_ms_per_step": t_per * 1e3,
+                   "tuning": tuning, "per_contour_ms_per_step": t_per * 1e3,
                    "batched_speedup_vs_per_contour": t_per / t_bat},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),

@@ -214,6 +214,60 @@ int qbx_debug_hankel01(const double* z, int n, double* h0, double* h1, hipStream
  * x [n], out [n][L+1]. L <= QBX_PMAX + 3. */
 int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t stream);
 
+/* ---- launch tuning and the autotuner --------------------------------------- */
+
+/* Launch-shape parameters.  They change how the pair work is cut into
+ * wavefront tasks (and so the order of the floating-point sums, nothing else).
+ * Process-wide: every later call reads them.  Workspace sizes depend on them,
+ * so query the *_workspace_bytes functions after changing them (a call whose
+ * workspace became too small fails with QBX_EWORKSPACE).  Not thread-safe
+ * against concurrent calls.
+ *   forward_waves       per-contour plain forward: wavefronts aimed for per
+ *                       launch; each center's source sum is split (in runs of
+ *                       at least four 64-source chunks) until that many exist
+ *   tape_waves          the same for the forward-with-tape kernel
+ *   adjoint_waves       per-contour adjoint source pass: wavefronts aimed for;
+ *                       the centers are split (at least 16 per split)
+ *   batch_adjoint_tasks batched adjoint: tasks per (kind, p) class (64 sources
+ *                       x a split of the centers, at least 16 centers each)
+ *   batch_grid_scale    batched persistent kernels: workgroups launched =
+ *                       workgroups resident on the device x this
+ * Limits: the three wave targets and batch_adjoint_tasks in [256, 1 << 22],
+ * batch_grid_scale in [0.125, 8].  Defaults 16384 and 1.0. */
+typedef struct {
+  int32_t forward_waves;
+  int32_t tape_waves;
+  int32_t adjoint_waves;
+  int32_t batch_adjoint_tasks;
+  double batch_grid_scale;
+} qbx_tuning;
+
+/* Set / read the process-wide tuning (QBX_EINVAL for values out of range). */
+int qbx_set_tuning(const qbx_tuning* t);
+int qbx_get_tuning(qbx_tuning* t);
+
+/* Autotuner for one contour problem (the arguments of qbx_layer_potential).
+ * SYNCHRONOUS, and unlike every other entry point it ALLOCATES (and frees)
+ * device memory of its own: workspace, output, tape and gradients.  For each
+ * of forward_waves, tape_waves and adjoint_waves it times the candidates
+ * 2048 .. 131072 (doubling; candidates that give the same launch shape are
+ * timed once) with hipEvents on `stream`, the minimum over `passes` runs
+ * (1..20) after one warm-up, keeps the fastest, installs the result with
+ * qbx_set_tuning and writes it to *best (nullable).  The batched fields are
+ * left as they were.  On error the previous tuning is restored. */
+int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, double r,
+                 int oversample, int side, int kind, int passes, qbx_tuning* best,
+                 hipStream_t stream);
+
+/* Autotuner for a batch (the arguments of qbx_layer_potential_batched; items
+ * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
+ * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2} on the batched
+ * forward-with-tape, then batch_adjoint_tasks in 2048 .. 65536 (doubling) on
+ * the batched adjoint, keeps the fastest of each and installs them. */
+int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
+                         const double* density, int oversample, int passes, qbx_tuning* best,
+                         hipStream_t stream);
+
 /* ---- kernel timing (profiling hook) ----------------------------------- */
 
 /* enable != 0: from now on every launch of a pair kernel (the forward and

@@ -44,6 +44,13 @@ class BatchItem(C.Structure):
                 ("kind", C.c_int32), ("side", C.c_int32), ("k", C.c_double), ("r", C.c_double)]
 
 
+class Tuning(C.Structure):
+    """qbx_tuning of include/qbx.h."""
+    _fields_ = [("forward_waves", C.c_int32), ("tape_waves", C.c_int32),
+                ("adjoint_waves", C.c_int32), ("batch_adjoint_tasks", C.c_int32),
+                ("batch_grid_scale", C.c_double)]
+
+
 _lib = None
 
 
@@ -79,6 +86,11 @@ def load() -> C.CDLL:
         "qbx_layer_potential_batched_adjoint": (i32, [C.POINTER(BatchItem), i32, vp, vp, vp, vp,
                                                       vp, vp, i32, vp, sz, vp]),
         "qbx_kernel_timer_read": (i32, [C.POINTER(dbl), C.POINTER(i32)]),
+        "qbx_set_tuning": (i32, [C.POINTER(Tuning)]),
+        "qbx_get_tuning": (i32, [C.POINTER(Tuning)]),
+        "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, C.POINTER(Tuning), vp]),
+        "qbx_autotune_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, i32, i32,
+                                       C.POINTER(Tuning), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

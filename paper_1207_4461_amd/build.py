@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqbx.so")
 SOURCES = ["qbx_batched_fwd1.hip", "qbx_batched_fwd0.hip", "qbx_batched_adj.hip",
            "qbx_adjoint.hip", "qbx_forward.hip", "qbx_batched.hip", "qbx_geometry.hip",
-           "qbx_api.cpp"]   # slowest first
+           "qbx_api.cpp", "qbx_autotune.cpp"]   # slowest first
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -8,7 +8,7 @@ namespace qbx {
 
 // ---------------------------------------------------------------------------
 // forward with tape (center-major, one wave per center and source split)
-// partial layout: [n_split][nk][Mc][5] complex = U, F_R, F_t, GV_x, GV_y
+// partial layout: [n_tsplit][nk][Mc][5] complex = U, F_R, F_t, GV_x, GV_y
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_forward_tape(const double4* __restrict__ geo,
@@ -152,11 +152,11 @@ template <int P>
 static hipError_t launch_forward_tape_p(const Dims& d, const double4* geo, const double2* dens,
                                         const CenterRec* ctr, const double* jtab,
                                         double2* partial, hipStream_t s) {
-  const long waves = (long)d.Mc * d.n_split;
+  const long waves = (long)d.Mc * d.n_tsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_LAUNCH(KD)                                                                          \
   hipLaunchKernelGGL((k_forward_tape<P, KD>), grid, block, 0, s, geo, dens, d.N, ctr, jtab, d.NJ, \
-                     d.Mc, d.n_split, d.chunks, d.chunks_per_split, d.k, partial)
+                     d.Mc, d.n_tsplit, d.chunks, d.tape_chunks_per_split, d.k, partial)
   if (d.kind == 1)
     QBX_LAUNCH(1);
   else if (d.kind == 2)
@@ -186,41 +186,23 @@ static hipError_t launch_adjoint_src_p(const Dims& d, const double4* geo, const 
   return hipGetLastError();
 }
 
-#define QBX_P_SWITCH(FN, ...)                                                              \
-  switch (d.p) {                                                                           \
-    case 0: return FN<0>(__VA_ARGS__);   case 1: return FN<1>(__VA_ARGS__);                \
-    case 2: return FN<2>(__VA_ARGS__);   case 3: return FN<3>(__VA_ARGS__);                \
-    case 4: return FN<4>(__VA_ARGS__);   case 5: return FN<5>(__VA_ARGS__);                \
-    case 6: return FN<6>(__VA_ARGS__);   case 7: return FN<7>(__VA_ARGS__);                \
-    case 8: return FN<8>(__VA_ARGS__);   case 9: return FN<9>(__VA_ARGS__);                \
-    case 10: return FN<10>(__VA_ARGS__); case 11: return FN<11>(__VA_ARGS__);              \
-    case 12: return FN<12>(__VA_ARGS__); case 13: return FN<13>(__VA_ARGS__);              \
-    case 14: return FN<14>(__VA_ARGS__); case 15: return FN<15>(__VA_ARGS__);              \
-    case 16: return FN<16>(__VA_ARGS__); case 17: return FN<17>(__VA_ARGS__);              \
-    case 18: return FN<18>(__VA_ARGS__); case 19: return FN<19>(__VA_ARGS__);              \
-    case 20: return FN<20>(__VA_ARGS__); case 21: return FN<21>(__VA_ARGS__);              \
-    case 22: return FN<22>(__VA_ARGS__); case 23: return FN<23>(__VA_ARGS__);              \
-    case 24: return FN<24>(__VA_ARGS__);                                                   \
-    default: return hipErrorInvalidValue;                                                  \
-  }
-
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,
                                hipStream_t s) {
-  QBX_P_SWITCH(launch_forward_tape_p, d, geo, dens, ctr, jtab, partial, s)
+  QBX_P_SWITCH(d.p, launch_forward_tape_p, d, geo, dens, ctr, jtab, partial, s)
 }
 
 hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const CenterRec* ctr,
                               const double* jtab, const double2* G, double2* partial,
                               hipStream_t s) {
-  QBX_P_SWITCH(launch_adjoint_src_p, d, geo, ctr, jtab, G, partial, s)
+  QBX_P_SWITCH(d.p, launch_adjoint_src_p, d, geo, ctr, jtab, G, partial, s)
 }
 
 hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
                                 hipStream_t s) {
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_finalize_tape, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
-                     d.n_split, partial, out, tape);
+                     d.n_tsplit, partial, out, tape);
   return hipGetLastError();
 }
 

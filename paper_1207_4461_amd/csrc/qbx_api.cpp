@@ -2,6 +2,7 @@
 // error reporting behind the C ABI of include/qbx.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -33,6 +34,25 @@ int device_fail(hipError_t e, const char* where) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// launch tunables of the per-contour path (qbx_set_tuning): wavefronts aimed
+// for per launch of the plain forward, the forward-with-tape and the adjoint
+// source pass
+static int g_forward_waves = 16384;
+static int g_tape_waves = 16384;
+static int g_adjoint_waves = 16384;
+
+void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves) {
+  g_forward_waves = forward_waves;
+  g_tape_waves = tape_waves;
+  g_adjoint_waves = adjoint_waves;
+}
+
+void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves) {
+  *forward_waves = g_forward_waves;
+  *tape_waves = g_tape_waves;
+  *adjoint_waves = g_adjoint_waves;
+}
+
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
                Dims* d) {
   if (n_panels < 3 || q != kQ || p < 0 || p > kPMax || oversample < 1 ||
@@ -58,9 +78,9 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   d->k = k;
   d->r = r;
   d->chunks = (int)((N + kWave - 1) / kWave);
-  // enough wavefronts to fill 256 CUs several times over, but at least four
-  // 64-source chunks per wavefront
-  const long want_waves = 16384;
+  // forward: enough wavefronts to fill 256 CUs several times over, but at
+  // least four 64-source chunks per wavefront
+  const long want_waves = g_forward_waves;
   long split = (want_waves + Mc - 1) / Mc;
   long max_split = d->chunks / 4;
   if (max_split < 1) max_split = 1;
@@ -68,8 +88,14 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   if (split < 1) split = 1;
   d->chunks_per_split = (int)((d->chunks + split - 1) / split);
   d->n_split = (d->chunks + d->chunks_per_split - 1) / d->chunks_per_split;
+  // forward-with-tape: the same rule with its own target
+  long tsplit = (g_tape_waves + Mc - 1) / Mc;
+  if (tsplit > max_split) tsplit = max_split;
+  if (tsplit < 1) tsplit = 1;
+  d->tape_chunks_per_split = (int)((d->chunks + tsplit - 1) / tsplit);
+  d->n_tsplit = (d->chunks + d->tape_chunks_per_split - 1) / d->tape_chunks_per_split;
   // adjoint: one wave per 64 sources and center split, >= 16 centers per split
-  long cs = (want_waves + d->chunks - 1) / d->chunks;
+  long cs = ((long)g_adjoint_waves + d->chunks - 1) / d->chunks;
   long max_cs = Mc / 16;
   if (max_cs < 1) max_cs = 1;
   if (cs > max_cs) cs = max_cs;
@@ -94,7 +120,9 @@ Layout make_layout(const Dims& d) {
   L.h = take(sizeof(double) * (size_t)d.P);
   L.ctr = take(sizeof(CenterRec) * (size_t)d.Mc);
   L.jtab = take(sizeof(double) * (size_t)d.Mc * d.NJ);
-  L.partial = take(sizeof(double2) * (size_t)d.n_split * d.nk * d.Mc * 5);
+  // forward partials [n_split][nk][Mc], tape partials [n_tsplit][nk][Mc][5]
+  const size_t n_part = std::max((size_t)d.n_split, (size_t)d.n_tsplit * 5);
+  L.partial = take(sizeof(double2) * n_part * d.nk * d.Mc);
   L.tape = take(sizeof(double2) * (size_t)d.Mc * d.nk * 4);
   L.G = take(sizeof(double2) * (size_t)d.nk * d.Mc);
   L.cg = take(sizeof(double) * (size_t)d.Mc * 8);
@@ -363,6 +391,34 @@ int qbx_signed_area_host(const double* nodes, int n_panels, double* area) {
   if (area) *area = A;
   if (!std::isfinite(A)) return fail(QBX_EINVAL, "non-finite node coordinates");
   if (A < 0.0) return fail(QBX_EORIENT, "signed area %g < 0: contour is clockwise", A);
+  return QBX_OK;
+}
+
+int qbx_set_tuning(const qbx_tuning* t) {
+  if (!t) return fail(QBX_EINVAL, "tuning is NULL");
+  const int lo = 256, hi = 1 << 22;
+  auto in = [&](int v) { return v >= lo && v <= hi; };
+  if (!in(t->forward_waves) || !in(t->tape_waves) || !in(t->adjoint_waves) ||
+      !in(t->batch_adjoint_tasks))
+    return fail(QBX_EINVAL, "tuning wave / task targets must lie in [%d, %d]", lo, hi);
+  if (!(t->batch_grid_scale >= 0.125 && t->batch_grid_scale <= 8.0))
+    return fail(QBX_EINVAL, "batch_grid_scale = %g outside [0.125, 8]", t->batch_grid_scale);
+  set_contour_tuning(t->forward_waves, t->tape_waves, t->adjoint_waves);
+  set_batch_tuning(t->batch_grid_scale, (double)t->batch_adjoint_tasks);
+  return QBX_OK;
+}
+
+int qbx_get_tuning(qbx_tuning* t) {
+  if (!t) return fail(QBX_EINVAL, "tuning is NULL");
+  int fw, tw, aw;
+  get_contour_tuning(&fw, &tw, &aw);
+  double gs, at;
+  get_batch_tuning(&gs, &at);
+  t->forward_waves = fw;
+  t->tape_waves = tw;
+  t->adjoint_waves = aw;
+  t->batch_adjoint_tasks = (int32_t)at;
+  t->batch_grid_scale = gs;
   return QBX_OK;
 }
 

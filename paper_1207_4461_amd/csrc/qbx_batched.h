@@ -32,13 +32,23 @@ __device__ __forceinline__ int find_slot(const long long* __restrict__ pre, int 
   return lo;
 }
 
+// Arguments of one persistent launch: the contours of one (kind, p) class in
+// decreasing cost order (order[0..n)), the prefix sums of their task counts
+// (pre[0..n]) and the class's task counter.
+struct BatchTasks {
+  const BatchItemDev* items;
+  const int* order;
+  const long long* pre;
+  int n;
+  long long n_tasks;
+  int* counter;
+};
+
 // ---------------------------------------------------------------------------
 // persistent forward: MODE 0 writes out, MODE 1 writes out and the tape
 // ---------------------------------------------------------------------------
-// Not inlined: each (kind, p) body is compiled as its own function (one task is
-// a whole center or source chunk, so the call costs nothing measurable).
 template <int MODE, int P, int KIND>
-__device__ __attribute__((noinline)) void forward_task(const BatchItemDev& B, int ci, int lane,
+__device__ __forceinline__ void forward_task(const BatchItemDev& B, int ci, int lane,
                                              const double4* __restrict__ geo,
                                              const double2* __restrict__ densw,
                                              const CenterRec* __restrict__ ctr,
@@ -88,10 +98,12 @@ __device__ __attribute__((noinline)) void forward_task(const BatchItemDev& B, in
 }
 
 // ---------------------------------------------------------------------------
-// persistent adjoint source pass: one task = 64 sources of one contour
+// persistent adjoint source pass: one task = 64 sources of one contour against
+// one split of its centers; tasks are split-major, so neighbouring wavefronts
+// read the same centers
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
-__device__ __attribute__((noinline)) void adjoint_task(const BatchItemDev& B, int chunk, int lane,
+__device__ __forceinline__ void adjoint_task(const BatchItemDev& B, int task, int lane,
                                              const double4* __restrict__ geo,
                                              const CenterRec* __restrict__ ctr,
                                              const double* __restrict__ jtab,
@@ -99,30 +111,50 @@ __device__ __attribute__((noinline)) void adjoint_task(const BatchItemDev& B, in
                                              double2* __restrict__ spart) {
   constexpr int NA = ((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0);
   const Dims& d = B.d;
-  const int j = chunk * kWave + lane;
+  const int sp = task / d.chunks;
+  const int j = (task - sp * d.chunks) * kWave + lane;
   if (j >= d.N) return;
+  const int c0 = sp * d.centers_per_split;
+  const int c1 = min(c0 + d.centers_per_split, d.Mc);
   Cplx A[NA];
   adjoint_source<P, KIND>(geo[B.src_off + j], ctr + B.ctr_off, jtab + B.jtab_off, d.NJ,
-                          G + B.G_off, d.Mc, 0, d.Mc, d.k, A);
-  double2* q = spart + B.spart_off;
+                          G + B.G_off, d.Mc, c0, c1, d.k, A);
+  double2* q = spart + B.spart_off + (size_t)sp * NA * d.N;
 #pragma unroll
   for (int b = 0; b < NA; ++b) q[(size_t)b * d.N + j] = make_double2(A[b].r, A[b].i);
 }
 
-#define QBX_BATCH_CASES(X, K)                                                                \
-  X(K, 0) X(K, 1) X(K, 2) X(K, 3) X(K, 4) X(K, 5) X(K, 6) X(K, 7) X(K, 8) X(K, 9) X(K, 10)  \
-  X(K, 11) X(K, 12) X(K, 13) X(K, 14) X(K, 15) X(K, 16) X(K, 17) X(K, 18) X(K, 19)           \
-  X(K, 20) X(K, 21) X(K, 22) X(K, 23) X(K, 24)
-
-
-// launchers of the persistent kernels (one translation unit each)
-hipError_t launch_forward_batched(int mode, dim3 grid, const BatchItemDev* items, const int* order,
-                                  const long long* pre, int n, long long n_tasks, int* counter,
+// launchers of the persistent kernels of one (kind, p) class (one translation
+// unit each); `grid_scale` multiplies the resident-block count of the kernel.
+hipError_t launch_forward_batched(int mode, int kind, int p, const BatchTasks& t,
                                   const double4* geo, const double2* densw, const CenterRec* ctr,
-                                  const double* jtab, double* out, double2* tape, hipStream_t s);
-hipError_t launch_adjoint_batched(dim3 grid, const BatchItemDev* items, const int* order,
-                                  const long long* pre, int n, long long n_tasks, int* counter,
-                                  const double4* geo, const CenterRec* ctr, const double* jtab,
-                                  const double2* G, double2* spart, hipStream_t s);
+                                  const double* jtab, double* out, double2* tape, double grid_scale,
+                                  hipStream_t s);
+hipError_t launch_adjoint_batched(int kind, int p, const BatchTasks& t, const double4* geo,
+                                  const CenterRec* ctr, const double* jtab, const double2* G,
+                                  double2* spart, double grid_scale, hipStream_t s);
+
+// number of workgroups of `block` threads of `kernel` resident on the whole
+// device (the per-CU figure is cached by the caller in *per_cu), times
+// grid_scale, and at most what `n_tasks` wavefront tasks need
+template <typename K>
+inline unsigned persistent_grid(K kernel, int* per_cu, int block, long long n_tasks,
+                                double grid_scale) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  if (*per_cu < 1) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel, block, 0) != hipSuccess || v < 1)
+      v = 1;
+    *per_cu = v;
+  }
+  double g = (double)cus * *per_cu * (grid_scale > 0.0 ? grid_scale : 1.0);
+  const long long need = (n_tasks * kWave + block - 1) / block;
+  if (g > (double)need) g = (double)need;
+  return g < 1.0 ? 1u : (unsigned)g;
+}
 
 }  // namespace qbx

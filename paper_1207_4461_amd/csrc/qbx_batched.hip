@@ -1,18 +1,22 @@
 // Batched QBX: many contours of different panel counts, wavenumbers, orders
-// and kinds in one persistent launch per pass.
+// and kinds, with the pair work of all contours of one (kind, p) class in one
+// persistent launch.
 //
 // The host builds a plan: per-contour dimensions and offsets into packed
-// workspace arrays, and two task lists ordered by decreasing cost per task
-// (forward: one task per center, cost ~ sources x pair flops; adjoint: one
-// task per 64-source chunk, cost ~ centers x pair flops), stored as prefix
-// sums over the contours in that order.  The persistent kernels run a fixed
-// grid; every wavefront takes the next task index from a device counter,
-// finds its contour by binary search in the prefix array and runs the same
-// pair-loop body as the per-contour kernels (qbx_pair.h), dispatched on the
-// contour's (kind, p).  Every wavefront leaves once the counter passes the
-// task count.  Geometry, per-center and per-source steps run as ordinary
-// grids over all contours' panels, centers or sources.
+// workspace arrays, and, per (kind, p) class present in the batch, two task
+// lists ordered by decreasing cost per task (forward: one task per center,
+// cost ~ sources; adjoint: one task per 64-source chunk, cost ~ centers),
+// stored as prefix sums over the class's contours in that order.  Each class
+// runs a persistent kernel compiled for its (kind, p) -- the register budget of
+// the per-contour kernel of that class, not of the largest case -- on a grid of
+// resident workgroups; every wavefront takes the next task index from the
+// class's device counter, finds its contour by binary search in the prefix
+// array and runs the pair-loop body of the per-contour kernels (qbx_pair.h).
+// Every wavefront leaves once the counter passes the task count.  Geometry,
+// per-center and per-source steps run as ordinary grids over all contours'
+// panels, centers or sources.
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <vector>
 
@@ -21,12 +25,21 @@
 
 namespace qbx {
 
+// the contours of one (kind, p) class: their slice of the order and prefix
+// arrays (order at ord_at, n entries; prefix sums at pre_at, n + 1 entries)
+struct BatchClass {
+  int kind, p, n;
+  int ord_at, pre_at;
+  long long tasks_f, tasks_a;
+};
+
 struct BatchPlan {
   int n;
   int qs;
   std::vector<BatchItemDev> items;
-  std::vector<int> order_f, order_a;              // contour order of the two task lists
-  std::vector<long long> pre_f, pre_a;            // task prefix sums in that order
+  std::vector<BatchClass> cls;                    // heaviest class first
+  std::vector<int> order_f, order_a;              // per class: contours by decreasing task cost
+  std::vector<long long> pre_f, pre_a;            // per class: task prefix sums in that order
   std::vector<long long> pre_panel, pre_ctr, pre_src, pre_G;  // prefix sums in item order
   long long n_panels = 0, n_ctr = 0, n_src = 0, n_G = 0, n_densw = 0, n_jtab = 0, n_tape = 0,
             n_spart = 0;
@@ -35,6 +48,10 @@ struct BatchPlan {
       o_counter, o_tables, o_geo, o_densw, o_wgt, o_h, o_ctr, o_jtab, o_tape, o_G, o_cg, o_spart,
       o_sg, total;
 };
+
+// launch tunables (qbx_set_tuning)
+static double g_batch_grid_scale = 1.0;       // persistent grid = resident blocks x this
+static double g_batch_adjoint_tasks = 16384;  // adjoint tasks per (kind, p) class
 
 static bool build_plan(const qbx_batch_item* items, int n, int oversample, BatchPlan* P) {
   if (!items || n < 1 || oversample < 1 || oversample > QBX_OVERSAMPLE_MAX) return false;
@@ -64,8 +81,6 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     B.jtab_off = P->n_jtab;
     B.tape_off = P->n_tape;
     B.G_off = P->n_G;
-    B.spart_off = P->n_spart;
-    const int NA = (d.kind & 1 ? 3 : 0) + (d.kind & 2 ? 4 : 0);
     P->n_panels += d.P;
     P->n_src += d.N;
     P->n_ctr += d.Mc;
@@ -73,7 +88,6 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     P->n_jtab += (long long)d.Mc * d.NJ;
     P->n_tape += (long long)d.Mc * d.nk * 4;
     P->n_G += (long long)d.nk * d.Mc;
-    P->n_spart += (long long)NA * d.N;
     P->pre_panel[i + 1] = P->n_panels;
     P->pre_ctr[i + 1] = P->n_ctr;
     P->pre_src[i + 1] = P->n_src;
@@ -83,19 +97,74 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     cost_a[i] = (double)d.Mc * per_pair;   // 64 sources against all centers
   }
   if (P->n_src > (1LL << 31) - 1 || P->n_ctr > (1LL << 31) - 1) return false;
-  auto make_order = [&](const std::vector<double>& cost, std::vector<int>& ord,
-                        std::vector<long long>& pre, bool centers) {
-    ord.resize(n);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    pre.assign(n + 1, 0);
-    for (int i = 0; i < n; ++i) {
-      const Dims& d = P->items[ord[i]].d;
-      pre[i + 1] = pre[i] + (centers ? d.Mc : d.chunks);
+  // classes, heaviest (total forward cost) first
+  std::vector<double> cls_cost;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < n; ++i) {
+    const Dims& d = P->items[i].d;
+    size_t c = 0;
+    while (c < P->cls.size() && !(P->cls[c].kind == d.kind && P->cls[c].p == d.p)) ++c;
+    if (c == P->cls.size()) {
+      P->cls.push_back(BatchClass{d.kind, d.p, 0, 0, 0, 0, 0});
+      cls_cost.push_back(0.0);
+      members.emplace_back();
     }
-  };
-  make_order(cost_f, P->order_f, P->pre_f, true);
-  make_order(cost_a, P->order_a, P->pre_a, false);
+    members[c].push_back(i);
+    cls_cost[c] += cost_f[i] * d.Mc;
+  }
+  std::vector<int> rank(P->cls.size());
+  std::iota(rank.begin(), rank.end(), 0);
+  std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return cls_cost[a] > cls_cost[b]; });
+  std::vector<BatchClass> sorted;
+  std::vector<std::vector<int>> sorted_members;
+  for (int r : rank) {
+    sorted.push_back(P->cls[r]);
+    sorted_members.push_back(members[r]);
+  }
+  P->cls = sorted;
+  P->order_f.clear();
+  P->order_a.clear();
+  P->pre_f.clear();
+  P->pre_a.clear();
+  for (size_t c = 0; c < P->cls.size(); ++c) {
+    BatchClass& C = P->cls[c];
+    const std::vector<int>& mem = sorted_members[c];
+    C.n = (int)mem.size();
+    C.ord_at = (int)P->order_f.size();
+    C.pre_at = (int)P->pre_f.size();
+    auto append = [&](const std::vector<double>& cost, std::vector<int>& ord,
+                      std::vector<long long>& pre, bool centers) {
+      std::vector<int> o = mem;
+      std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+      long long acc = 0;
+      pre.push_back(0);
+      for (int i : o) {
+        const Dims& d = P->items[i].d;
+        acc += centers ? d.Mc : (long long)d.chunks * d.n_csplit;
+        ord.push_back(i);
+        pre.push_back(acc);
+      }
+      return acc;
+    };
+    // adjoint tasks: (center split, 64-source chunk); the class's work is cut
+    // into about g_batch_adjoint_tasks tasks of at least 16 centers each
+    double work = 0.0;
+    for (int i : mem) work += (double)P->items[i].d.chunks * P->items[i].d.Mc;
+    const long long g = std::max<long long>(16, (long long)std::ceil(work / g_batch_adjoint_tasks));
+    for (int i : mem) {
+      Dims& d = P->items[i].d;
+      d.centers_per_split = (int)std::min<long long>(d.Mc, g);
+      d.n_csplit = (d.Mc + d.centers_per_split - 1) / d.centers_per_split;
+    }
+    C.tasks_f = append(cost_f, P->order_f, P->pre_f, true);
+    C.tasks_a = append(cost_a, P->order_a, P->pre_a, false);
+  }
+  for (int i = 0; i < n; ++i) {
+    BatchItemDev& B = P->items[i];
+    const int NA = (B.d.kind & 1 ? 3 : 0) + (B.d.kind & 2 ? 4 : 0);
+    B.spart_off = P->n_spart;
+    P->n_spart += (long long)B.d.n_csplit * NA * B.d.N;
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -105,13 +174,13 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   P->o_items = take(sizeof(BatchItemDev) * n);
   P->o_ord_f = take(sizeof(int) * n);
   P->o_ord_a = take(sizeof(int) * n);
-  P->o_pre_f = take(sizeof(long long) * (n + 1));
-  P->o_pre_a = take(sizeof(long long) * (n + 1));
+  P->o_pre_f = take(sizeof(long long) * P->pre_f.size());
+  P->o_pre_a = take(sizeof(long long) * P->pre_a.size());
   P->o_pre_panel = take(sizeof(long long) * (n + 1));
   P->o_pre_ctr = take(sizeof(long long) * (n + 1));
   P->o_pre_src = take(sizeof(long long) * (n + 1));
   P->o_pre_G = take(sizeof(long long) * (n + 1));
-  P->o_counter = take(256);
+  P->o_counter = take(sizeof(int) * 2 * P->cls.size());
   P->o_tables = take(sizeof(double) * table_layout(P->qs).total);
   P->o_geo = take(sizeof(double4) * P->n_src);
   P->o_densw = take(sizeof(double2) * P->n_densw);
@@ -133,8 +202,8 @@ static T* wsp(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-__global__ void k_zero_int(int* c) {
-  if (threadIdx.x == 0) c[0] = 0;
+__global__ void k_zero_ints(int* c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,7 +259,7 @@ __global__ __launch_bounds__(256) void k_source_finalize_batched(
   if (e >= total) return;
   const int it = find_slot(pre_src, n, e);
   const BatchItemDev& B = items[it];
-  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind, 1, geo + B.src_off,
+  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind, B.d.n_csplit, geo + B.src_off,
                        densw + B.densw_off, spart + B.spart_off, sg + B.src_off * 8);
 }
 
@@ -211,7 +280,6 @@ __global__ __launch_bounds__(128) void k_chain_batched(
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int g_batch_blocks_per_cu = 2;
 
 static int upload_plan(const BatchPlan& P, void* ws, hipStream_t s) {
   struct Up {
@@ -222,8 +290,8 @@ static int upload_plan(const BatchPlan& P, void* ws, hipStream_t s) {
       {P.o_items, P.items.data(), sizeof(BatchItemDev) * P.n},
       {P.o_ord_f, P.order_f.data(), sizeof(int) * P.n},
       {P.o_ord_a, P.order_a.data(), sizeof(int) * P.n},
-      {P.o_pre_f, P.pre_f.data(), sizeof(long long) * (P.n + 1)},
-      {P.o_pre_a, P.pre_a.data(), sizeof(long long) * (P.n + 1)},
+      {P.o_pre_f, P.pre_f.data(), sizeof(long long) * P.pre_f.size()},
+      {P.o_pre_a, P.pre_a.data(), sizeof(long long) * P.pre_a.size()},
       {P.o_pre_panel, P.pre_panel.data(), sizeof(long long) * (P.n + 1)},
       {P.o_pre_ctr, P.pre_ctr.data(), sizeof(long long) * (P.n + 1)},
       {P.o_pre_src, P.pre_src.data(), sizeof(long long) * (P.n + 1)},
@@ -235,23 +303,6 @@ static int upload_plan(const BatchPlan& P, void* ws, hipStream_t s) {
     if (e != hipSuccess) return device_fail(e, "upload of the batch plan");
   }
   return QBX_OK;
-}
-
-static int persistent_blocks() {
-  static int cus_of[64] = {0};
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
-    if (cus_of[dev] == 0) {
-      int v = 0;
-      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-          v > 0)
-        cus_of[dev] = v;
-      else
-        cus_of[dev] = 256;
-    }
-    cus = cus_of[dev];
-  }
-  return cus * g_batch_blocks_per_cu;
 }
 
 static int batch_prepare(const BatchPlan& P, const double* nodes, const double* density, void* ws,
@@ -271,38 +322,67 @@ static int batch_prepare(const BatchPlan& P, const double* nodes, const double* 
   return e == hipSuccess ? QBX_OK : device_fail(e, "batched upsample kernel");
 }
 
+static BatchTasks class_tasks(const BatchPlan& P, void* ws, size_t c, bool adjoint) {
+  const BatchClass& C = P.cls[c];
+  BatchTasks t;
+  t.items = wsp<BatchItemDev>(ws, P.o_items);
+  t.order = wsp<int>(ws, adjoint ? P.o_ord_a : P.o_ord_f) + C.ord_at;
+  t.pre = wsp<long long>(ws, adjoint ? P.o_pre_a : P.o_pre_f) + C.pre_at;
+  t.n = C.n;
+  t.n_tasks = adjoint ? C.tasks_a : C.tasks_f;
+  t.counter = wsp<int>(ws, P.o_counter) + (adjoint ? P.cls.size() : 0) + c;
+  return t;
+}
+
+static int zero_counters(const BatchPlan& P, void* ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(256), 0, s, wsp<int>(ws, P.o_counter),
+                     (int)(2 * P.cls.size()));
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QBX_OK : device_fail(e, "counter reset kernel");
+}
+
 static int batch_forward(const BatchPlan& P, double* out, double2* tape, void* ws, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, wsp<int>(ws, P.o_counter));
-  const dim3 grid((unsigned)persistent_blocks()), block(256);
+  int rc = zero_counters(P, ws, s);
+  if (rc) return rc;
   timer_begin(2, s);
-  hipError_t e = launch_forward_batched(
-      tape ? 1 : 0, grid, wsp<BatchItemDev>(ws, P.o_items), wsp<int>(ws, P.o_ord_f),
-      wsp<long long>(ws, P.o_pre_f), P.n, P.pre_f[P.n], wsp<int>(ws, P.o_counter),
-      wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_densw), wsp<CenterRec>(ws, P.o_ctr),
-      wsp<double>(ws, P.o_jtab), out, tape, s);
+  for (size_t c = 0; c < P.cls.size(); ++c) {
+    const BatchTasks t = class_tasks(P, ws, c, false);
+    hipError_t e = launch_forward_batched(
+        tape ? 1 : 0, P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
+        wsp<double2>(ws, P.o_densw), wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab), out,
+        tape, g_batch_grid_scale, s);
+    if (e != hipSuccess) {
+      timer_end(2, s);
+      return device_fail(e, "batched forward kernel");
+    }
+  }
   timer_end(2, s);
-  return e == hipSuccess ? QBX_OK : device_fail(e, "batched forward kernel");
+  return QBX_OK;
 }
 
-hipError_t launch_forward_batched_0(dim3, const BatchItemDev*, const int*, const long long*, int,
-                                    long long, int*, const double4*, const double2*,
-                                    const CenterRec*, const double*, double*, double2*, hipStream_t);
-hipError_t launch_forward_batched_1(dim3, const BatchItemDev*, const int*, const long long*, int,
-                                    long long, int*, const double4*, const double2*,
-                                    const CenterRec*, const double*, double*, double2*, hipStream_t);
+hipError_t launch_forward_batched_0(int, int, const BatchTasks&, const double4*, const double2*,
+                                    const CenterRec*, const double*, double*, double2*, double,
+                                    hipStream_t);
+hipError_t launch_forward_batched_1(int, int, const BatchTasks&, const double4*, const double2*,
+                                    const CenterRec*, const double*, double*, double2*, double,
+                                    hipStream_t);
 
-hipError_t launch_forward_batched(int mode, dim3 grid, const BatchItemDev* items, const int* order,
-                                  const long long* pre, int n, long long n_tasks, int* counter,
+hipError_t launch_forward_batched(int mode, int kind, int p, const BatchTasks& t,
                                   const double4* geo, const double2* densw, const CenterRec* ctr,
-                                  const double* jtab, double* out, double2* tape, hipStream_t s) {
-  return mode ? launch_forward_batched_1(grid, items, order, pre, n, n_tasks, counter, geo, densw,
-                                         ctr, jtab, out, tape, s)
-              : launch_forward_batched_0(grid, items, order, pre, n, n_tasks, counter, geo, densw,
-                                         ctr, jtab, out, tape, s);
+                                  const double* jtab, double* out, double2* tape, double grid_scale,
+                                  hipStream_t s) {
+  return mode ? launch_forward_batched_1(kind, p, t, geo, densw, ctr, jtab, out, tape, grid_scale, s)
+              : launch_forward_batched_0(kind, p, t, geo, densw, ctr, jtab, out, tape, grid_scale, s);
 }
 
-void set_batch_blocks_per_cu(int v) { g_batch_blocks_per_cu = v < 1 ? 1 : (v > 16 ? 16 : v); }
-int get_batch_blocks_per_cu() { return g_batch_blocks_per_cu; }
+void set_batch_tuning(double grid_scale, double adjoint_tasks) {
+  g_batch_grid_scale = std::min(8.0, std::max(0.125, grid_scale));
+  g_batch_adjoint_tasks = std::min(4194304.0, std::max(256.0, adjoint_tasks));
+}
+void get_batch_tuning(double* grid_scale, double* adjoint_tasks) {
+  *grid_scale = g_batch_grid_scale;
+  *adjoint_tasks = g_batch_adjoint_tasks;
+}
 
 }  // namespace qbx
 
@@ -365,15 +445,21 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
   hipLaunchKernelGGL(k_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
                      wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr), tp,
                      wsp<double2>(ws, P.o_G), wsp<double>(ws, P.o_cg));
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, wsp<int>(ws, P.o_counter));
+  rc = zero_counters(P, ws, stream);
+  if (rc) return rc;
   timer_begin(2, stream);
-  hipError_t ea = launch_adjoint_batched(
-      dim3((unsigned)persistent_blocks()), it, wsp<int>(ws, P.o_ord_a),
-      wsp<long long>(ws, P.o_pre_a), P.n, P.pre_a[P.n], wsp<int>(ws, P.o_counter),
-      wsp<double4>(ws, P.o_geo), wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
-      wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart), stream);
+  for (size_t c = 0; c < P.cls.size(); ++c) {
+    const BatchTasks t = class_tasks(P, ws, c, true);
+    hipError_t ea = launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
+                                           wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
+                                           wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
+                                           g_batch_grid_scale, stream);
+    if (ea != hipSuccess) {
+      timer_end(2, stream);
+      return device_fail(ea, "batched adjoint kernel");
+    }
+  }
   timer_end(2, stream);
-  if (ea != hipSuccess) return device_fail(ea, "batched adjoint kernel");
   hipLaunchKernelGGL(k_source_finalize_batched, blocks(nS, 256), dim3(256), 0, stream, it,
                      wsp<long long>(ws, P.o_pre_src), P.n, nS, wsp<double4>(ws, P.o_geo),
                      wsp<double2>(ws, P.o_densw), wsp<double2>(ws, P.o_spart),

@@ -1,48 +1,59 @@
-// Persistent batched forward-with-tape kernel (see qbx_batched.hip).
+// Persistent batched forward kernels, mode 1 (values and the tape),
+// one kernel per (kind, p) class (see qbx_batched.hip).
 #include "qbx_batched.h"
 
 namespace qbx {
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_forward_batched(
-    const BatchItemDev* __restrict__ items, const int* __restrict__ order,
-    const long long* __restrict__ pre, int n, long long n_tasks, int* __restrict__ counter,
-    const double4* __restrict__ geo, const double2* __restrict__ densw,
-    const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, double* __restrict__ out,
-    double2* __restrict__ tape) {
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_forward_batched_1(BatchTasks t,
+                                                          const double4* __restrict__ geo,
+                                                          const double2* __restrict__ densw,
+                                                          const CenterRec* __restrict__ ctr,
+                                                          const double* __restrict__ jtab,
+                                                          double* __restrict__ out,
+                                                          double2* __restrict__ tape) {
   const int lane = threadIdx.x & 63;
   for (;;) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1);
-    t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-    if (t >= n_tasks) break;
-    const int slot = find_slot(pre, n, t);
-    const BatchItemDev& B = items[order[slot]];
-    const int ci = (int)(t - pre[slot]);
-    const int key = __builtin_amdgcn_readfirstlane(B.d.kind * 32 + B.d.p);
-    switch (key) {
-#define QBX_FWD_CASE(K, PP)                                                                   \
-  case K * 32 + PP:                                                                           \
-    forward_task<MODE, PP, K>(B, ci, lane, geo, densw, ctr, jtab, out, tape);                 \
-    break;
-      QBX_BATCH_CASES(QBX_FWD_CASE, 1)
-      QBX_BATCH_CASES(QBX_FWD_CASE, 2)
-      QBX_BATCH_CASES(QBX_FWD_CASE, 3)
-#undef QBX_FWD_CASE
-      default:
-        break;
-    }
+    // every lane takes part in the atomic (lane 0 adds 1, the others 0): a
+    // divergent `if (lane == 0)` here could be merged by the compiler with the
+    // lane-0 stores that end the previous task, letting the other lanes reach
+    // the shuffle below without lane 0
+    int task = atomicAdd(t.counter, lane == 0 ? 1 : 0);
+    task = __builtin_amdgcn_readfirstlane(__shfl(task, 0));
+    if (task >= t.n_tasks) break;   // every wave leaves once the counter passes the end
+    const int slot = find_slot(t.pre, t.n, task);
+    const BatchItemDev& B = t.items[t.order[slot]];
+    forward_task<1, P, KIND>(B, (int)(task - t.pre[slot]), lane, geo, densw, ctr, jtab, out, tape);
   }
 }
 
-hipError_t launch_forward_batched_1(dim3 grid, const BatchItemDev* items, const int* order,
-                                       const long long* pre, int n, long long n_tasks,
-                                       int* counter, const double4* geo, const double2* densw,
-                                       const CenterRec* ctr, const double* jtab, double* out,
-                                       double2* tape, hipStream_t s) {
-  hipLaunchKernelGGL((k_forward_batched<1>), grid, dim3(256), 0, s, items, order, pre, n,
-                     n_tasks, counter, geo, densw, ctr, jtab, out, tape);
+template <int P>
+static hipError_t launch_p(int kind, const BatchTasks& t, const double4* geo,
+                           const double2* densw, const CenterRec* ctr, const double* jtab,
+                           double* out, double2* tape, double grid_scale, hipStream_t s) {
+  static int per_cu[4] = {0, 0, 0, 0};
+#define QBX_LAUNCH(KD)                                                                        \
+  {                                                                                           \
+    const unsigned g = persistent_grid(k_forward_batched_1<P, KD>, &per_cu[KD], 256, t.n_tasks, \
+                                       grid_scale);                                           \
+    hipLaunchKernelGGL((k_forward_batched_1<P, KD>), dim3(g), dim3(256), 0, s, t, geo, densw,  \
+                       ctr, jtab, out, tape);                                                 \
+  }
+  if (kind == 1)
+    QBX_LAUNCH(1)
+  else if (kind == 2)
+    QBX_LAUNCH(2)
+  else
+    QBX_LAUNCH(3)
+#undef QBX_LAUNCH
   return hipGetLastError();
+}
+
+hipError_t launch_forward_batched_1(int kind, int p, const BatchTasks& t, const double4* geo,
+                                    const double2* densw, const CenterRec* ctr,
+                                    const double* jtab, double* out, double2* tape,
+                                    double grid_scale, hipStream_t s) {
+  QBX_P_SWITCH(p, launch_p, kind, t, geo, densw, ctr, jtab, out, tape, grid_scale, s)
 }
 
 }  // namespace qbx

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/qbx.h"
+
 namespace qbx {
 
 constexpr int kQ = 16;      // nodes per panel
@@ -37,6 +39,9 @@ struct Dims {
   int chunks;            // ceil(N / 64)
   int n_split;           // source splits per center
   int chunks_per_split;  // 64-source chunks per split
+  // forward-with-tape launch shape (source splits)
+  int n_tsplit;
+  int tape_chunks_per_split;
   // adjoint source-major launch shape
   int n_csplit;           // center splits per 64-source chunk
   int centers_per_split;  // centers per split
@@ -51,7 +56,7 @@ struct Layout {
   size_t h;        // double[P] panel lengths
   size_t ctr;      // CenterRec[Mc]
   size_t jtab;     // double[Mc][NJ]
-  size_t partial;  // double2[n_split][nk][Mc][5] (the plain forward uses the first part)
+  size_t partial;  // forward: double2[n_split][nk][Mc]; forward-with-tape: double2[n_tsplit][nk][Mc][5]
   size_t tape;     // double2[Mc][nk][4] tape recomputed by the adjoint when none is given
   size_t G;        // double2[nk][Mc] conj(cotangent) i/4
   size_t cg;       // double[Mc][8] per-center gradients
@@ -123,6 +128,35 @@ hipError_t launch_debug_hankel01(const double* z, int n, double* h0, double* h1,
 hipError_t launch_debug_besselj(const double* x, int n, int L, double* out, hipStream_t s);
 
 }  // namespace qbx
+
+namespace qbx {
+// tunables of the per-contour (qbx_api.cpp) and batched (qbx_batched.hip) paths
+void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves);
+void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves);
+void set_batch_tuning(double grid_scale, double adjoint_tasks);
+void get_batch_tuning(double* grid_scale, double* adjoint_tasks);
+int validate(const qbx_geometry* g, int p, double k, double r, int oversample, int side,
+             int kind, Dims* d);
+}  // namespace qbx
+
+// return FN<p>(args...) for the runtime order PV in [0, 24]
+#define QBX_P_SWITCH(PV, FN, ...)                                                            \
+  switch (PV) {                                                                             \
+    case 0: return FN<0>(__VA_ARGS__);   case 1: return FN<1>(__VA_ARGS__);                \
+    case 2: return FN<2>(__VA_ARGS__);   case 3: return FN<3>(__VA_ARGS__);                \
+    case 4: return FN<4>(__VA_ARGS__);   case 5: return FN<5>(__VA_ARGS__);                \
+    case 6: return FN<6>(__VA_ARGS__);   case 7: return FN<7>(__VA_ARGS__);                \
+    case 8: return FN<8>(__VA_ARGS__);   case 9: return FN<9>(__VA_ARGS__);                \
+    case 10: return FN<10>(__VA_ARGS__); case 11: return FN<11>(__VA_ARGS__);              \
+    case 12: return FN<12>(__VA_ARGS__); case 13: return FN<13>(__VA_ARGS__);              \
+    case 14: return FN<14>(__VA_ARGS__); case 15: return FN<15>(__VA_ARGS__);              \
+    case 16: return FN<16>(__VA_ARGS__); case 17: return FN<17>(__VA_ARGS__);              \
+    case 18: return FN<18>(__VA_ARGS__); case 19: return FN<19>(__VA_ARGS__);              \
+    case 20: return FN<20>(__VA_ARGS__); case 21: return FN<21>(__VA_ARGS__);              \
+    case 22: return FN<22>(__VA_ARGS__); case 23: return FN<23>(__VA_ARGS__);              \
+    case 24: return FN<24>(__VA_ARGS__);                                                   \
+    default: return hipErrorInvalidValue;                                                  \
+  }
 
 namespace qbx {
 // kernel timer (qbx_kernel_timer): records an event pair around a launch of

@@ -223,6 +223,47 @@ def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: f
                                  int(side), int(kind))
 
 
+def _tuning_dict(t) -> dict:
+    return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
+
+
+def get_tuning() -> dict:
+    """The process-wide launch tuning (qbx_get_tuning)."""
+    lib = _lib.load()
+    t = _lib.Tuning()
+    _lib.check(lib.qbx_get_tuning(C.byref(t)))
+    return _tuning_dict(t)
+
+
+def set_tuning(**fields) -> dict:
+    """Change fields of the launch tuning (qbx_set_tuning); returns the new tuning."""
+    lib = _lib.load()
+    t = _lib.Tuning()
+    _lib.check(lib.qbx_get_tuning(C.byref(t)))
+    for f, v in fields.items():
+        if f not in dict(_lib.Tuning._fields_):
+            raise KeyError(f)
+        setattr(t, f, v)
+    _lib.check(lib.qbx_set_tuning(C.byref(t)))
+    return _tuning_dict(t)
+
+
+def autotune(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
+             oversample: int = 4, side: int = EXTERIOR, kind: int = S, passes: int = 2) -> dict:
+    """Time the per-contour launch shapes on this problem and install the fastest
+    (qbx_autotune); returns the resulting tuning."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    _need(density, "density", torch.complex128, (n_kinds(kind), P * Q))
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    t = _lib.Tuning()
+    _lib.check(lib.qbx_autotune(C.byref(geo), density.data_ptr(), float(k), int(p), float(r),
+                                int(oversample), int(side), int(kind), int(passes), C.byref(t),
+                                _stream(nodes.device)))
+    return _tuning_dict(t)
+
+
 class Batch:
     """Many contours packed for the batched C entry points (one persistent launch per pass).
 
@@ -258,16 +299,35 @@ class Batch:
         self.density = torch.cat(dens).to(dev).contiguous()
         self.n_out = out_off
         self.device = dev
-        nb = lib.qbx_batched_workspace_bytes(self.items, n, self.oversample)
-        if nb == 0:
-            raise _lib.QBXError(_lib.QBX_EINVAL, "invalid batch")
-        self.ws = torch.empty(int(nb), dtype=torch.uint8, device=dev)
+        self._lib = lib
+        self.ws = torch.empty(0, dtype=torch.uint8, device=dev)
+        self._ensure_workspace()
         self.tape = torch.empty(int(lib.qbx_batched_tape_bytes(self.items, n)), dtype=torch.uint8,
                                 device=dev)
-        self._lib = lib
+
+    def _ensure_workspace(self) -> None:
+        # the workspace size depends on the launch tuning, which may change
+        nb = int(self._lib.qbx_batched_workspace_bytes(self.items, len(self.problems),
+                                                       self.oversample))
+        if nb == 0:
+            raise _lib.QBXError(_lib.QBX_EINVAL, "invalid batch")
+        if self.ws.numel() < nb:
+            self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    def autotune(self, passes: int = 2) -> dict:
+        """Time the batched launch shapes on this batch and install the fastest
+        (qbx_autotune_batched); returns the resulting tuning."""
+        t = _lib.Tuning()
+        _lib.check(self._lib.qbx_autotune_batched(
+            self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
+            C.c_void_p(self.density.data_ptr()), self.oversample, int(passes), C.byref(t),
+            C.c_void_p(_stream(self.device))))
+        self._ensure_workspace()
+        return _tuning_dict(t)
 
     def forward(self, with_tape: bool = False) -> torch.Tensor:
         """Packed one-sided limits (concatenated per-contour out blocks)."""
+        self._ensure_workspace()
         out = torch.empty(self.n_out, dtype=torch.complex128, device=self.device)
         _lib.check(self._lib.qbx_layer_potential_batched(
             self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
@@ -279,6 +339,7 @@ class Batch:
 
     def adjoint(self, cotangent: torch.Tensor, use_tape: bool = False):
         """(grad_density, grad_nodes) packed like density and nodes."""
+        self._ensure_workspace()
         gd = torch.empty_like(self.density)
         gn = torch.empty_like(self.nodes)
         _lib.check(self._lib.qbx_layer_potential_batched_adjoint(

@@ -155,3 +155,42 @@ def test_batched_validation(lib):
                                            None) == _lib.QBX_EWORKSPACE
     assert lib.qbx_layer_potential_batched_adjoint(its, 3, BAD, BAD, None, None, BAD, BAD, 4, BAD,
                                                    1 << 40, None) == _lib.QBX_EINVAL
+
+
+def test_tuning_roundtrip_and_validation(lib):
+    t0 = _lib.Tuning()
+    assert lib.qbx_get_tuning(C.byref(t0)) == _lib.QBX_OK
+    assert t0.forward_waves >= 256 and 0.125 <= t0.batch_grid_scale <= 8
+    t = _lib.Tuning(t0.forward_waves, t0.tape_waves, t0.adjoint_waves, t0.batch_adjoint_tasks,
+                    t0.batch_grid_scale)
+    try:
+        n_before = lib.qbx_workspace_bytes(256, 16, 8, 4, 1, 1)
+        t.forward_waves = 1 << 20          # more source splits -> larger partial buffers
+        assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
+        t1 = _lib.Tuning()
+        lib.qbx_get_tuning(C.byref(t1))
+        assert t1.forward_waves == 1 << 20
+        assert lib.qbx_workspace_bytes(256, 16, 8, 4, 1, 1) > n_before
+        for field, bad in (("forward_waves", 255), ("tape_waves", 1 << 23), ("adjoint_waves", 0),
+                           ("batch_adjoint_tasks", -5), ("batch_grid_scale", 0.1),
+                           ("batch_grid_scale", 9.0), ("batch_grid_scale", float("nan"))):
+            tb = _lib.Tuning(t0.forward_waves, t0.tape_waves, t0.adjoint_waves,
+                             t0.batch_adjoint_tasks, t0.batch_grid_scale)
+            setattr(tb, field, bad)
+            assert lib.qbx_set_tuning(C.byref(tb)) == _lib.QBX_EINVAL
+        assert lib.qbx_set_tuning(None) == _lib.QBX_EINVAL
+        assert lib.qbx_get_tuning(None) == _lib.QBX_EINVAL
+    finally:
+        assert lib.qbx_set_tuning(C.byref(t0)) == _lib.QBX_OK
+
+
+def test_autotune_validation(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 30, 0.5, 4, 1, 1, 2, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune(C.byref(g), None, 1.0, 4, 0.5, 4, 1, 1, 2, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 0, None, None) == _lib.QBX_EINVAL
+    its = _items()
+    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 0, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched(its, 0, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL
+    its[0].p = 99
+    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL

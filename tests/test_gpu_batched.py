@@ -111,3 +111,28 @@ def test_random64_batch_full(Q):
         e = rel(outs[i].cpu().numpy()[:, :, idx], ref)
         say(f"  contour {i} (P={pb.n_panels}, p={pb.p}, kind={pb.kind}, k={pb.k:.1f}): oracle {e:.2e}")
         assert e < 1e-11
+
+
+def test_batched_autotune_keeps_results(Q):
+    """The autotuner only changes launch shapes: results after tuning match the
+    per-contour path as before, and the installed tuning is the one returned."""
+    pbs = mixed_batch()
+    B = Q.Batch(pbs, oversample=4)
+    before = Q.get_tuning()
+    try:
+        tuned = B.autotune(passes=1)
+        say(f"  tuned: {tuned}")
+        assert Q.get_tuning() == tuned
+        assert tuned["batch_adjoint_tasks"] in (2048, 4096, 8192, 16384, 32768, 65536)
+        assert tuned["batch_grid_scale"] in (0.5, 1.0, 2.0)
+        outs = [o.cpu().numpy() for o in B.split_out(B.forward(with_tape=True))]
+        cot = B.pack_out([pb.cotangent for pb in pbs])
+        gd, gn = B.adjoint(cot, use_tape=True)
+        for pb, u, g1, g2 in zip(pbs, outs, B.split_density(gd), B.split_nodes(gn)):
+            assert rel(u, per_contour_forward(Q, pb)) < 1e-13
+            rd, rn = Q.layer_potential_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k,
+                                           pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+            assert rel(g1.cpu().numpy(), rd.cpu().numpy()) < 1e-12
+            assert rel(g2.cpu().numpy(), rn.cpu().numpy()) < 1e-11
+    finally:
+        Q.set_tuning(**before)

@@ -172,3 +172,28 @@ def test_principal_value(Q):
             err = np.abs(pv1[kk] - pv[kk]).max() / np.abs(pv[kk]).max()
             say(f"  side {s} kind {kk}: one-sided PV vs two-sided {err:.3e}")
             assert err < 1e-6
+
+
+def test_autotune_keeps_results(Q):
+    """Per-contour autotuner: installs the fastest launch shapes it timed; results
+    stay within the parity bar (only the summation order may change)."""
+    pb = I.small(n_panels=24, p=10, k=6.0, kind=3, side=I.BOTH)
+    nodes = torch.from_numpy(pb.nodes).cuda()
+    dens = torch.from_numpy(np.ascontiguousarray(pb.density)).cuda()
+    before = Q.get_tuning()
+    try:
+        tuned = Q.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                           passes=1)
+        say(f"  tuned: {tuned}")
+        assert Q.get_tuning() == tuned
+        for f in ("forward_waves", "tape_waves", "adjoint_waves"):
+            assert tuned[f] in (2048, 4096, 8192, 16384, 32768, 65536, 131072)
+        ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                pb.kind).numpy()
+        assert_parity(gpu_forward(Q, pb), ref, what="after autotune")
+        # extreme settings give the same values up to summation order
+        for fw in (256, 1 << 22):
+            Q.set_tuning(forward_waves=fw, tape_waves=fw, adjoint_waves=fw)
+            assert_parity(gpu_forward(Q, pb), ref, what=f"waves={fw}")
+    finally:
+        Q.set_tuning(**before)
