@@ -270,6 +270,17 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    if args.autotune:
+        # the per-contour loop runs with the launch shapes tuned on its largest contour
+        big = max(range(len(pbs)), key=lambda i: pbs[i].n_panels)
+        q = per[big]
+        t0 = time.perf_counter()
+        tc = qbx.autotune(q["nodes"], q["dens"], pbs[big].k, pbs[big].p, pbs[big].r,
+                          pbs[big].oversample, pbs[big].side, pbs[big].kind, passes=1)
+        log(f"per-contour autotune on contour {big} {time.perf_counter() - t0:.1f} s: {tc}")
+        for pb, q in zip(pbs, per):   # workspace sizes follow the tuning
+            q["ws"] = torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side,
+                                                      pb.kind), dtype=torch.uint8, device=dev)
     t_per = timed(step_per_contour, max(1, args.steps))
     tuning = qbx.get_tuning()
     if args.autotune:

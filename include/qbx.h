@@ -261,8 +261,8 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
 
 /* Autotuner for a batch (the arguments of qbx_layer_potential_batched; items
  * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
- * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2} on the batched
- * forward-with-tape, then batch_adjoint_tasks in 2048 .. 65536 (doubling) on
+ * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2, 4} on the batched
+ * forward-with-tape, then batch_adjoint_tasks in 2048 .. 262144 (doubling) on
  * the batched adjoint, keeps the fastest of each and installs them. */
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
                          const double* density, int oversample, int passes, qbx_tuning* best,

@@ -161,8 +161,8 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
     return fail(QBX_EINVAL, "invalid batch (an item's parameters, offsets or oversample)");
   qbx_tuning saved;
   qbx_get_tuning(&saved);
-  static const int kTaskCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536};
-  static const double kScaleCandidates[] = {0.5, 1.0, 2.0};
+  static const int kTaskCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144};
+  static const double kScaleCandidates[] = {0.5, 1.0, 2.0, 4.0};
   size_t ws_bytes = 0;
   for (int c : kTaskCandidates) {
     qbx_tuning t = saved;
