@@ -65,7 +65,25 @@
 #include "qbx_internal.h"
 #include "qbx_special.h"
 
+// Unroll factors of the order loops (full unrolling by default).  Full
+// unrolling keeps every recurrence in registers with compile-time indices but
+// lets the scheduler interleave all orders, which raises the live register set.
+#ifndef QBX_FWD_UNROLL
+#define QBX_FWD_UNROLL 64
+#endif
+#ifndef QBX_SUMS_UNROLL
+#define QBX_SUMS_UNROLL 64
+#endif
+#define QBX_PRAGMA(x) _Pragma(#x)
+#define QBX_UNROLL_BY(n) QBX_PRAGMA(unroll n)
+
 namespace qbx {
+
+// Empty asm that takes the values as in/out operands: every order's recurrence
+// state and running sums must be final at this point, so the compiler cannot
+// run whole recurrence chains ahead and keep all orders live at once.
+#define QBX_PIN2(a, b) asm volatile("" : "+v"(a), "+v"(b))
+#define QBX_PIN4(a, b, c, d) asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d))
 
 struct Cplx {
   double r, i;
@@ -106,7 +124,7 @@ __device__ __forceinline__ PairOut pair_sums(double z, double iz, double cd, dou
   double b_m = cps, b_c = fma(cd, cps, sd * sps);              // cos(l D - psi)
   double sa_m = sps, sa_c = fma(sd, cps, cd * sps);            // sin(l D + psi)
   double sb_m = -sps, sb_c = fma(sd, cps, -cd * sps);          // sin(l D - psi)
-#pragma unroll
+QBX_UNROLL_BY(QBX_SUMS_UNROLL)
   for (int l = 1; l <= LMAX; ++l) {
     // H_{l+1} and d_l = H_{l-1} - H_{l+1} = 2 H_l'
     const double hn_r = fma(tl, hc_r, -hm_r);
@@ -157,6 +175,21 @@ __device__ __forceinline__ PairOut pair_sums(double z, double iz, double cd, dou
       t = fma(two_cd, b_c, -b_m); b_m = b_c; b_c = t;
       t = fma(two_cd, sa_c, -sa_m); sa_m = sa_c; sa_c = t;
       t = fma(two_cd, sb_c, -sb_m); sb_m = sb_c; sb_c = t;
+    }
+    QBX_PIN4(hm_r, hm_i, hc_r, hc_i);
+    if (kS) {
+      QBX_PIN4(c_m, c_c, s_m, s_c);
+      QBX_PIN4(sK.r, sK.i, sKt.r, sKt.i);
+      QBX_PIN2(sKr.r, sKr.i);
+      if (kTape) QBX_PIN2(sKR.r, sKR.i);
+    }
+    if (kD) {
+      QBX_PIN4(a_m, a_c, b_m, b_c);
+      QBX_PIN4(sa_m, sa_c, sb_m, sb_c);
+      QBX_PIN4(dK.r, dK.i, dKr.r, dKr.i);
+      QBX_PIN2(dKtp.r, dKtp.i);
+      if (kTape) QBX_PIN4(dKR.r, dKR.i, dKt.r, dKt.i);
+      else QBX_PIN2(dKpsi.r, dKpsi.i);
     }
   }
   PairOut o;
@@ -227,7 +260,7 @@ __device__ __forceinline__ void pair_kernel(double z, double iz, double cd, doub
   double c_m = 1.0, c_c = cd;                            // cos((l-1)D), cos(lD)
   double a_m = cps, a_c = fma(cd, cps, -sd * sps);       // cos((l-1)D + psi), cos(lD + psi)
   double b_m = cps, b_c = fma(cd, cps, sd * sps);        // cos((l-1)D - psi), cos(lD - psi)
-#pragma unroll
+QBX_UNROLL_BY(QBX_FWD_UNROLL)
   for (int l = 1; l <= LMAX; ++l) {
     if (kS && l <= P) {
       const double f = J[l] * c_c;
@@ -261,6 +294,15 @@ __device__ __forceinline__ void pair_kernel(double z, double iz, double cd, doub
         b_m = b_c;
         b_c = bn;
       }
+    }
+    QBX_PIN4(hm_r, hm_i, hc_r, hc_i);
+    if (kS) {
+      QBX_PIN2(c_m, c_c);
+      QBX_PIN2(sr, si);
+    }
+    if (kD) {
+      QBX_PIN4(a_m, a_c, b_m, b_c);
+      QBX_PIN2(dr, di);
     }
   }
   s_r = fma(2.0, sr, a0r);
