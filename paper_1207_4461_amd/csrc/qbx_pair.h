@@ -336,8 +336,9 @@ __device__ __forceinline__ void forward_center(const double4* __restrict__ geo,
       const double* __restrict__ cf = g_seed_table + z0;
       const double4 g = geo[j];
       const double vx = g.x - cx, vy = g.y - cy;
-      const double rho = sqrt(fma(vx, vx, vy * vy));
-      const double ir = 1.0 / rho;
+      const double rho2 = fma(vx, vx, vy * vy);
+      const double ir = rsqrt_refined(rho2);
+      const double rho = rho2 * ir;
       const double cd = (ct * vx + st * vy) * ir;   // cos(theta_i - theta')
       const double sd = (st * vx - ct * vy) * ir;   // sin(theta_i - theta')
       double cps = 0.0, sps = 0.0;
@@ -394,8 +395,9 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
       const double* __restrict__ cf = g_seed_table + z0;
       const double4 g = geo[j];
       const double vx = g.x - cx, vy = g.y - cy;
-      const double rho = sqrt(fma(vx, vx, vy * vy));
-      const double ir = 1.0 / rho;
+      const double rho2 = fma(vx, vx, vy * vy);
+      const double ir = rsqrt_refined(rho2);
+      const double rho = rho2 * ir;
       const double ux = vx * ir, uy = vy * ir;          // v^ ; theta^ = (-uy, ux)
       const double cd = ct * ux + st * uy;
       const double sd = st * ux - ct * uy;
@@ -459,8 +461,9 @@ __device__ __forceinline__ void adjoint_source(const double4 g, const CenterRec*
     const double* __restrict__ cf = g_seed_table + z0;
     const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
     const double vx = g.x - cx, vy = g.y - cy;
-    const double rho = sqrt(fma(vx, vx, vy * vy));
-    const double ir = 1.0 / rho;
+    const double rho2 = fma(vx, vx, vy * vy);
+    const double ir = rsqrt_refined(rho2);
+    const double rho = rho2 * ir;
     const double ux = vx * ir, uy = vy * ir;
     const double cd = ct * ux + st * uy;
     const double sd = st * ux - ct * uy;
