@@ -31,6 +31,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources of libqbx (names and contents)."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1207_4461_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a copy of known
+    size), or None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json:"):
+                d = json.loads(line.split(":", 1)[1])
+                if d.get("source_sha256") != kernel_source_hash():
+                    return None
+                return d["bytes_per_launch"]
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +72,9 @@ def parse():
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
     ap.add_argument("--autotune", type=int, default=1,
                     help="time the launch shapes on the workload first (untimed) and use the best")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB: run one plain device-to-device copy of this size first, the "
+                         "reference for scaling the HBM byte counters of a --pmc profile")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time of the oracle sample")
@@ -63,6 +97,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lib = _lib.load()
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
     if args.workload == "random64":
         return bench_batched(args)
     have_bwd = hasattr(qbx, "layer_potential_vjp")
@@ -149,8 +192,10 @@ def main():
     dom = kernels[names[cls]]
     achieved = dom["tflops"]
     avg_ms = dom["avg_ms"]
+    kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape"]
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+            "traffic": measured_traffic(kernel_names[cls], args.workload),
             "kernel": names[cls], "kernel_avg_ms": avg_ms, "launches": dom["launches"],
             "flop_per_launch": dom["flop_per_launch"],
             "flop_per_pair": per_pair[cls], "all_pair_kernels": kernels}
