@@ -170,6 +170,56 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
                                         double* grad_density, double* grad_nodes, int oversample,
                                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- kernel level: explicit sources and centers ------------------------------ */
+
+/* The QBX sums for sources and expansion centers given directly (no panels, no
+ * interpolation): the pair loops of qbx_layer_potential applied to caller data,
+ * e.g. one shard of the centers, or sources of another smooth rule.  For center
+ * i at c_i with radius R_i and target direction e^{i theta_i} (its target is
+ * x_i = c_i + R_i e^{i theta_i}):
+ *   out[kind][i] = (i/4) sum_{l=-p..p} a_l J_l(k R_i) e^{i l theta_i},
+ *   S: a_l = sum_j q_j H^(1)_l(k|x'_j - c_i|) e^{-i l theta'_ij}
+ *      (Section 2, eq. graf-coefficient; Section 3.3 step 4(c)),
+ *   D: the same with nu_j . grad_{x'_j} applied to the source factor
+ *      (Section 3.2, eq. graf-coefficient-dlp), linear in the given normal nu_j.
+ * Arguments (device arrays):
+ *   src_xy  [n_src][2]            source points x'_j
+ *   src_nu  [n_src][2]            source normals (D only; may be NULL for S)
+ *   src_q   [n_kinds][n_src]      complex weighted densities q_j (quadrature weight
+ *                                 times density), S first, then D
+ *   ctr_xy  [n_ctr][2], ctr_r [n_ctr] (> 0), ctr_dir [n_ctr] complex unit e^{i theta}
+ *   out     [n_kinds][n_ctr]      complex
+ *   tape    nullable, qbx_explicit_tape_bytes(): per-center sums for the adjoint
+ * The caller is responsible for Graf's condition |x_i - c_i| < |x'_j - c_i|.
+ * Errors: QBX_EINVAL (n_src or n_ctr < 1, p, kind, k, NULL arrays, src_nu NULL
+ * with D), QBX_EWORKSPACE, QBX_EDEVICE. */
+size_t qbx_explicit_workspace_bytes(int n_src, int n_ctr, int p, int kind);
+size_t qbx_explicit_tape_bytes(int n_ctr, int kind);
+int qbx_apply_explicit(int n_src, const double* src_xy, const double* src_nu, const double* src_q,
+                       int n_ctr, const double* ctr_xy, const double* ctr_r, const double* ctr_dir,
+                       double k, int p, int kind, double* out, double* tape, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* Vector-Jacobian product of qbx_apply_explicit for L = Re sum conj(cotangent) out
+ * (cotangent [n_kinds][n_ctr] complex); every gradient pointer is nullable and the
+ * gradients are written, not accumulated:
+ *   grad_q        [n_kinds][n_src] complex = (d out / d q)^H cotangent
+ *   grad_src_xy   [n_src][2]   dL/dx'_j
+ *   grad_src_nu   [n_src][2]   dL/d(nu_x, nu_y) (D; ignored without D)
+ *   grad_ctr_xy   [n_ctr][2]   dL/dc_i with R_i and theta_i held (the target moves
+ *                              with its center)
+ *   grad_ctr_r    [n_ctr]      dL/dR_i
+ *   grad_ctr_theta[n_ctr]      dL/dtheta_i (the direction as an angle)
+ * tape: the forward's tape, or NULL to recompute it (needed for the center
+ * gradients only). */
+int qbx_apply_explicit_adjoint(int n_src, const double* src_xy, const double* src_nu,
+                               const double* src_q, int n_ctr, const double* ctr_xy,
+                               const double* ctr_r, const double* ctr_dir, double k, int p,
+                               int kind, const double* cotangent, const double* tape,
+                               double* grad_q, double* grad_src_xy, double* grad_src_nu,
+                               double* grad_ctr_xy, double* grad_ctr_r, double* grad_ctr_theta,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- principal value (Section 3.2) --------------------------------------- */
 
 /* pv [n_kinds][T] complex from out [n_sides][n_kinds][T] (the layout of

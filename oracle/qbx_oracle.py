@@ -347,6 +347,49 @@ def layer_potential(nodes, density, k: float, p: int, r: float = 0.5, oversample
     return u
 
 
+def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float, p: int,
+                   kind: int, mode: str = "fast") -> torch.Tensor:
+    """The same expansion for sources and centers given directly (no panels):
+    coefficients of Section 2, eq. graf-coefficient (S) and Section 3.2, eq.
+    graf-coefficient-dlp (D, the source factor differentiated along the given normal,
+    linear in it), evaluated at x_i = c_i + R_i e^{i theta_i} (Section 3.3 step 4(c)).
+    src_q [n_kinds, n_src] are the weighted densities.  Returns [n_kinds, n_ctr].
+    Differentiable in every argument (autograd)."""
+    src_xy = _as_t(src_xy, _F64)
+    src_q = _as_t(src_q, _C128)
+    ctr_xy = _as_t(ctr_xy, _F64)
+    ctr_r = _as_t(ctr_r, _F64)
+    ctr_theta = _as_t(ctr_theta, _F64)
+    kinds = kinds_of(kind)
+    nu = _as_t(src_nu, _F64) if src_nu is not None else torch.zeros_like(src_xy)
+    src = {"x": src_xy[:, 0], "y": src_xy[:, 1], "nx": nu[:, 0], "ny": nu[:, 1]}
+    dens = {kk: src_q[i] for i, kk in enumerate(kinds)}
+    ctr = {"cx": ctr_xy[:, 0], "cy": ctr_xy[:, 1]}
+    a = coefficients(src, dens, ctr, k, p, kind, mode)
+    return torch.stack([evaluate(a[kk], ctr_r, ctr_theta, k, p, mode) for kk in kinds])
+
+
+def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float, p: int,
+                       kind: int, cotangent) -> Dict[str, np.ndarray]:
+    """Gradients of L = Re sum conj(g) out of apply_explicit (autograd; complex
+    inputs in the PyTorch convention dL/dRe + i dL/dIm)."""
+    leaves = {
+        "src_xy": _as_t(src_xy, _F64).clone().requires_grad_(True),
+        "src_nu": (_as_t(src_nu, _F64) if src_nu is not None
+                   else torch.zeros(np.shape(src_xy), dtype=_F64)).clone().requires_grad_(True),
+        "q": _as_t(src_q, _C128).clone().requires_grad_(True),
+        "ctr_xy": _as_t(ctr_xy, _F64).clone().requires_grad_(True),
+        "ctr_r": _as_t(ctr_r, _F64).clone().requires_grad_(True),
+        "ctr_theta": _as_t(ctr_theta, _F64).clone().requires_grad_(True),
+    }
+    out = apply_explicit(leaves["src_xy"], leaves["src_nu"], leaves["q"], leaves["ctr_xy"],
+                         leaves["ctr_r"], leaves["ctr_theta"], k, p, kind)
+    g = _as_t(cotangent, _C128)
+    torch.real(torch.conj(g) * out).sum().backward()
+    return {key: (val.grad.numpy() if val.grad is not None else np.zeros(tuple(val.shape)))
+            for key, val in leaves.items()}
+
+
 def graf_min_ratio(nodes, k, p, r=0.5, oversample=4, side=EXTERIOR) -> float:
     """min over centers and sources of rho_ij / R_i (Graf's condition needs > 1)."""
     with torch.no_grad():

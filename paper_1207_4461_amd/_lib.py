@@ -86,6 +86,12 @@ def load() -> C.CDLL:
         "qbx_layer_potential_batched_adjoint": (i32, [C.POINTER(BatchItem), i32, vp, vp, vp, vp,
                                                       vp, vp, i32, vp, sz, vp]),
         "qbx_kernel_timer_read": (i32, [C.POINTER(dbl), C.POINTER(i32)]),
+        "qbx_explicit_workspace_bytes": (sz, [i32, i32, i32, i32]),
+        "qbx_explicit_tape_bytes": (sz, [i32, i32]),
+        "qbx_apply_explicit": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp, vp, vp,
+                                     sz, vp]),
+        "qbx_apply_explicit_adjoint": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp,
+                                             vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "qbx_set_tuning": (i32, [C.POINTER(Tuning)]),
         "qbx_get_tuning": (i32, [C.POINTER(Tuning)]),
         "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, C.POINTER(Tuning), vp]),

@@ -206,6 +206,12 @@ hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* o
   return hipGetLastError();
 }
 
+hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s) {
+  const int n = d.Mc * d.nk;
+  hipLaunchKernelGGL(k_make_G, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk, cot, G);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

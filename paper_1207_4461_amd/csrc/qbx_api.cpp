@@ -53,6 +53,36 @@ void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves)
   *adjoint_waves = g_adjoint_waves;
 }
 
+// source splits of the forward kernels and center splits of the adjoint source
+// pass, from the tuning targets (see qbx_set_tuning)
+void set_launch_shape(Dims* d) {
+  d->chunks = (int)(((long)d->N + kWave - 1) / kWave);
+  // forward: enough wavefronts to fill 256 CUs several times over, but at
+  // least four 64-source chunks per wavefront
+  const long want_waves = g_forward_waves;
+  long split = (want_waves + d->Mc - 1) / d->Mc;
+  long max_split = d->chunks / 4;
+  if (max_split < 1) max_split = 1;
+  if (split > max_split) split = max_split;
+  if (split < 1) split = 1;
+  d->chunks_per_split = (int)((d->chunks + split - 1) / split);
+  d->n_split = (d->chunks + d->chunks_per_split - 1) / d->chunks_per_split;
+  // forward-with-tape: the same rule with its own target
+  long tsplit = (g_tape_waves + d->Mc - 1) / d->Mc;
+  if (tsplit > max_split) tsplit = max_split;
+  if (tsplit < 1) tsplit = 1;
+  d->tape_chunks_per_split = (int)((d->chunks + tsplit - 1) / tsplit);
+  d->n_tsplit = (d->chunks + d->tape_chunks_per_split - 1) / d->tape_chunks_per_split;
+  // adjoint: one wave per 64 sources and center split, >= 16 centers per split
+  long cs = ((long)g_adjoint_waves + d->chunks - 1) / d->chunks;
+  long max_cs = d->Mc / 16;
+  if (max_cs < 1) max_cs = 1;
+  if (cs > max_cs) cs = max_cs;
+  if (cs < 1) cs = 1;
+  d->centers_per_split = (int)(((long)d->Mc + cs - 1) / cs);
+  d->n_csplit = (int)(((long)d->Mc + d->centers_per_split - 1) / d->centers_per_split);
+}
+
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
                Dims* d) {
   if (n_panels < 3 || q != kQ || p < 0 || p > kPMax || oversample < 1 ||
@@ -77,31 +107,7 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   d->kind = kind;
   d->k = k;
   d->r = r;
-  d->chunks = (int)((N + kWave - 1) / kWave);
-  // forward: enough wavefronts to fill 256 CUs several times over, but at
-  // least four 64-source chunks per wavefront
-  const long want_waves = g_forward_waves;
-  long split = (want_waves + Mc - 1) / Mc;
-  long max_split = d->chunks / 4;
-  if (max_split < 1) max_split = 1;
-  if (split > max_split) split = max_split;
-  if (split < 1) split = 1;
-  d->chunks_per_split = (int)((d->chunks + split - 1) / split);
-  d->n_split = (d->chunks + d->chunks_per_split - 1) / d->chunks_per_split;
-  // forward-with-tape: the same rule with its own target
-  long tsplit = (g_tape_waves + Mc - 1) / Mc;
-  if (tsplit > max_split) tsplit = max_split;
-  if (tsplit < 1) tsplit = 1;
-  d->tape_chunks_per_split = (int)((d->chunks + tsplit - 1) / tsplit);
-  d->n_tsplit = (d->chunks + d->tape_chunks_per_split - 1) / d->tape_chunks_per_split;
-  // adjoint: one wave per 64 sources and center split, >= 16 centers per split
-  long cs = ((long)g_adjoint_waves + d->chunks - 1) / d->chunks;
-  long max_cs = Mc / 16;
-  if (max_cs < 1) max_cs = 1;
-  if (cs > max_cs) cs = max_cs;
-  if (cs < 1) cs = 1;
-  d->centers_per_split = (int)((Mc + cs - 1) / cs);
-  d->n_csplit = (int)((Mc + d->centers_per_split - 1) / d->centers_per_split);
+  set_launch_shape(d);
   return true;
 }
 

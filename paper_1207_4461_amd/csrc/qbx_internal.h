@@ -92,6 +92,7 @@ __host__ __device__ inline double side_sign(int side, int si) {
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
                Dims* d);
+void set_launch_shape(Dims* d);
 // error reporting shared by the C entry points (qbx_last_error)
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int device_fail(hipError_t e, const char* where);
@@ -115,6 +116,10 @@ hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2*
                                hipStream_t s);
 hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
                                 hipStream_t s);
+hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const CenterRec* ctr,
+                              const double* jtab, const double2* G, double2* partial,
+                              hipStream_t s);
+hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s);
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

@@ -17,6 +17,16 @@
 
 namespace qbx {
 
+// J_l(x) and J'_l(x), l = 0..nj-1, of one center into Jt[0..2nj): Miller's
+// recurrence, then J'_l = (J_{l-1} - J_{l+1}) / 2 (DLMF 10.6.1) with J'_0 = -J_1
+// and the last one from J_{l-1} - (l/x) J_l (DLMF 10.6.2)
+__device__ __forceinline__ void center_bessel_table(double x, int nj, double* __restrict__ Jt) {
+  bessel_j_miller(x, nj - 1, Jt);
+  Jt[nj] = -Jt[1];
+  for (int l = 1; l + 1 < nj; ++l) Jt[nj + l] = 0.5 * (Jt[l - 1] - Jt[l + 1]);
+  Jt[2 * nj - 1] = (x > 0.0) ? Jt[nj - 2] - (nj - 1) / x * Jt[nj - 1] : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // upsample: one block per panel.
 // ---------------------------------------------------------------------------
@@ -103,14 +113,7 @@ __device__ __forceinline__ void upsample_panel(const Dims& d, int m, const doubl
     c.pad = 0.0;
     const size_t ci = (size_t)si * d.T + (size_t)m * kQ + a;
     ctr[ci] = c;
-    double* Jt = jtab + ci * d.NJ;
-    const int nj = d.NJ / 2;
-    bessel_j_miller(d.k * R, nj - 1, Jt);
-    // J'_l = (J_{l-1} - J_{l+1}) / 2 (DLMF 10.6.1), J'_0 = -J_1; the last one
-    // from J_{l-1} - (l/x) J_l (DLMF 10.6.2)
-    Jt[nj] = -Jt[1];
-    for (int l = 1; l + 1 < nj; ++l) Jt[nj + l] = 0.5 * (Jt[l - 1] - Jt[l + 1]);
-    Jt[2 * nj - 1] = (d.k * R > 0.0) ? Jt[nj - 2] - (nj - 1) / (d.k * R) * Jt[nj - 1] : 0.0;
+    center_bessel_table(d.k * R, d.NJ / 2, jtab + ci * d.NJ);
   }
 }
 

@@ -238,6 +238,45 @@ def random64(seed: int = 3, n_contours: int = 64) -> List[Problem]:
     return out
 
 
+@dataclasses.dataclass
+class ExplicitProblem:
+    """Sources and expansion centers given directly (no panels)."""
+
+    k: float
+    p: int
+    kind: int
+    src_xy: np.ndarray     # [n_src, 2]
+    src_nu: np.ndarray     # [n_src, 2] normals (not unit: lengths in [0.5, 1.5])
+    src_q: np.ndarray      # [n_kinds, n_src] complex weighted densities
+    ctr_xy: np.ndarray     # [n_ctr, 2]
+    ctr_r: np.ndarray      # [n_ctr]
+    ctr_theta: np.ndarray  # [n_ctr]
+    cotangent: np.ndarray  # [n_kinds, n_ctr] complex
+
+
+def explicit_problem(n_src: int, n_ctr: int, k: float, p: int, kind: int,
+                     seed: int) -> ExplicitProblem:
+    """Sources at random parameters on the curve r = 1 + 0.1 cos 3t with random
+    normals, centers at radius 0.5 with radii in [0.05, 0.25] (every source stays
+    at least 0.4 from every center), random target directions."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0.0, 2.0 * math.pi, n_src))
+    r = 1.0 + 0.1 * np.cos(3.0 * t)
+    src_xy = np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+    ang = rng.uniform(0.0, 2.0 * math.pi, n_src)
+    ln = rng.uniform(0.5, 1.5, n_src)
+    src_nu = np.stack([ln * np.cos(ang), ln * np.sin(ang)], axis=1)
+    nk = (1 if kind & S_KIND else 0) + (1 if kind & D_KIND else 0)
+    src_q = complex_normal(rng, (nk, n_src)) * (2.0 * math.pi / n_src)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n_ctr)
+    ctr_xy = 0.5 * np.stack([np.cos(phi), np.sin(phi)], axis=1)
+    ctr_r = rng.uniform(0.05, 0.25, n_ctr)
+    ctr_theta = rng.uniform(-math.pi, math.pi, n_ctr)
+    cot = complex_normal(rng, (nk, n_ctr))
+    return ExplicitProblem(float(k), int(p), int(kind), src_xy, src_nu, src_q, ctr_xy, ctr_r,
+                           ctr_theta, cot)
+
+
 def small(name: str = "small", n_panels: int = 6, k: float = 3.0, p: int = 5, side: int = BOTH,
           kind: int = S_KIND | D_KIND, seed: int = 11, oversample: int = 4,
           curve: Optional[Curve] = None, r: float = 0.5) -> Problem:

@@ -223,6 +223,73 @@ def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: f
                                  int(side), int(kind))
 
 
+def explicit_workspace_bytes(n_src: int, n_ctr: int, p: int, kind: int = S) -> int:
+    return int(_lib.load().qbx_explicit_workspace_bytes(int(n_src), int(n_ctr), int(p), int(kind)))
+
+
+def explicit_tape_bytes(n_ctr: int, kind: int = S) -> int:
+    return int(_lib.load().qbx_explicit_tape_bytes(int(n_ctr), int(kind)))
+
+
+def _explicit_args(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, kind):
+    n_src = int(src_xy.shape[0])
+    n_ctr = int(ctr_xy.shape[0])
+    _need(src_xy, "src_xy", torch.float64, (n_src, 2))
+    if kind & D:
+        _need(src_nu, "src_nu", torch.float64, (n_src, 2))
+    _need(src_q, "src_q", torch.complex128, (n_kinds(kind), n_src))
+    _need(ctr_xy, "ctr_xy", torch.float64, (n_ctr, 2))
+    _need(ctr_r, "ctr_r", torch.float64, (n_ctr,))
+    _need(ctr_dir, "ctr_dir", torch.complex128, (n_ctr,))
+    nu = src_nu.data_ptr() if (kind & D) else None
+    return n_src, n_ctr, (n_src, src_xy.data_ptr(), nu, src_q.data_ptr(), n_ctr,
+                          ctr_xy.data_ptr(), ctr_r.data_ptr(), ctr_dir.data_ptr())
+
+
+def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, k: float, p: int,
+                   kind: int = S, tape: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """qbx_apply_explicit: out[n_kinds, n_ctr] complex128 for explicit sources
+    (points, normals, weighted densities) and centers (point, radius, unit e^{i theta})."""
+    lib = _lib.load()
+    n_src, n_ctr, a = _explicit_args(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, kind)
+    dev = src_xy.device
+    out = torch.empty((n_kinds(kind), n_ctr), dtype=torch.complex128, device=dev)
+    ws = _workspace(explicit_workspace_bytes(n_src, n_ctr, p, kind), dev, workspace)
+    tp = None
+    if tape is not None:
+        if tape.device != dev or tape.numel() * tape.element_size() < explicit_tape_bytes(n_ctr, kind):
+            raise ValueError("tape too small or on the wrong device")
+        tp = tape.data_ptr()
+    _lib.check(lib.qbx_apply_explicit(*a, float(k), int(p), int(kind), out.data_ptr(), tp,
+                                      ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out
+
+
+def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, cotangent, k: float, p: int,
+                       kind: int = S, tape: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None) -> dict:
+    """qbx_apply_explicit_adjoint: dict with q (complex [n_kinds, n_src]), src_xy, src_nu
+    (D), ctr_xy, ctr_r, ctr_theta."""
+    lib = _lib.load()
+    n_src, n_ctr, a = _explicit_args(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, kind)
+    dev = src_xy.device
+    _need(cotangent, "cotangent", torch.complex128, (n_kinds(kind), n_ctr))
+    g = {"q": torch.empty_like(src_q), "src_xy": torch.empty_like(src_xy),
+         "ctr_xy": torch.empty_like(ctr_xy), "ctr_r": torch.empty_like(ctr_r),
+         "ctr_theta": torch.empty_like(ctr_r)}
+    if kind & D:
+        g["src_nu"] = torch.empty_like(src_xy)
+    ws = _workspace(explicit_workspace_bytes(n_src, n_ctr, p, kind), dev, workspace)
+    _lib.check(lib.qbx_apply_explicit_adjoint(
+        *a, float(k), int(p), int(kind), cotangent.data_ptr(),
+        tape.data_ptr() if tape is not None else None, g["q"].data_ptr(), g["src_xy"].data_ptr(),
+        g["src_nu"].data_ptr() if "src_nu" in g else None, g["ctr_xy"].data_ptr(),
+        g["ctr_r"].data_ptr(), g["ctr_theta"].data_ptr(), ws.data_ptr(), ws.numel(),
+        _stream(dev)))
+    return g
+
+
 def _tuning_dict(t) -> dict:
     return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
 

@@ -194,3 +194,29 @@ def test_autotune_validation(lib):
     assert lib.qbx_autotune_batched(its, 0, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL
     its[0].p = 99
     assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL
+
+
+def _explicit(lib, n_src=100, n_ctr=20, p=6, kind=1, k=3.0, xy=BAD, nu=BAD, q=BAD, cxy=BAD,
+              cr=BAD, cd=BAD, out=BAD, ws=BAD, nbytes=1 << 40):
+    return lib.qbx_apply_explicit(n_src, xy, nu, q, n_ctr, cxy, cr, cd, k, p, kind, out, None, ws,
+                                  nbytes, None)
+
+
+def test_explicit_sizes_and_validation(lib):
+    n1 = lib.qbx_explicit_workspace_bytes(1000, 100, 8, 1)
+    n2 = lib.qbx_explicit_workspace_bytes(1000, 100, 8, 3)
+    assert 0 < n1 < n2 and n1 % 256 == 0
+    assert lib.qbx_explicit_workspace_bytes(0, 100, 8, 1) == 0
+    assert lib.qbx_explicit_workspace_bytes(10, 0, 8, 1) == 0
+    assert lib.qbx_explicit_workspace_bytes(10, 10, 25, 1) == 0
+    assert lib.qbx_explicit_workspace_bytes(10, 10, 8, 0) == 0
+    assert lib.qbx_explicit_tape_bytes(10, 3) == 10 * 2 * 4 * 16
+    assert lib.qbx_explicit_tape_bytes(0, 3) == 0
+    for kw in (dict(n_src=0), dict(n_ctr=0), dict(p=-1), dict(p=25), dict(kind=4), dict(k=0.0),
+               dict(k=float("nan")), dict(xy=None), dict(q=None), dict(cxy=None), dict(cr=None),
+               dict(cd=None), dict(out=None), dict(ws=None), dict(kind=2, nu=None)):
+        assert _explicit(lib, **kw) == _lib.QBX_EINVAL, kw
+    assert _explicit(lib, kind=1, nu=None, nbytes=10) == _lib.QBX_EWORKSPACE
+    assert lib.qbx_apply_explicit_adjoint(10, BAD, BAD, BAD, 5, BAD, BAD, BAD, 1.0, 4, 1, None,
+                                          None, BAD, BAD, BAD, BAD, BAD, BAD, BAD, 1 << 40,
+                                          None) == _lib.QBX_EINVAL

@@ -385,3 +385,42 @@ def test_planted_mistakes_are_caught(monkeypatch):
     ref = 0.25j * sps.hankel1(0, 7.0 * math.dist((0.35, 0.05), (0.9, -0.35)))
     got = _graf((0.9, -0.35), (0.1, 0.2), (0.35, 0.05), 7.0, 40, "S")
     assert abs(got - ref) / abs(ref) > 1e-3
+
+
+def test_explicit_oracle_single_pair_is_graf():
+    """apply_explicit on one source and one center is the truncated Graf sum, which
+    converges to (i/4) q H0(k|x - x'|) at the target x = c + R e^{i theta} (S) and to
+    (i/4) q nu . grad_x' H0(k|x - x'|) (D)."""
+    k = 4.0
+    xs = np.array([[0.9, -0.35]])
+    nu = np.array([[0.6, 0.8]])
+    q = np.array([[0.7 - 0.2j], [0.3 + 0.5j]])
+    c = np.array([[0.1, 0.2]])
+    R, th = np.array([0.3]), np.array([0.7])
+    x = c[0] + R[0] * np.array([math.cos(th[0]), math.sin(th[0])])
+    d = x - xs[0]
+    r = np.hypot(*d)
+    out = O.apply_explicit(xs, nu, q, c, R, th, k, 40, 3).numpy()[:, 0]
+    ref_s = 0.25j * q[0, 0] * sps.hankel1(0, k * r)
+    # grad_{x'} H0(k|x - x'|) = k H1(k r) (x - x') / r
+    ref_d = 0.25j * q[1, 0] * k * sps.hankel1(1, k * r) * float(nu[0] @ d) / r
+    assert abs(out[0] - ref_s) < 1e-13 * abs(ref_s)
+    assert abs(out[1] - ref_d) < 1e-12 * abs(ref_d)
+    # linear in the normal
+    out2 = O.apply_explicit(xs, 2.5 * nu, q, c, R, th, k, 40, 3).numpy()[:, 0]
+    assert abs(out2[1] - 2.5 * out[1]) < 1e-13 * abs(out[1])
+
+
+def test_explicit_oracle_matches_layer_potential():
+    """The contour path is the explicit sums on the contour's own sources and centers."""
+    pb = I.small(n_panels=6, p=7, k=3.0, kind=3, side=I.EXTERIOR)
+    u, aux = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                               pb.kind, return_aux=True)
+    src = aux["src"]
+    fine = O.interpolate_density(torch.from_numpy(pb.density), pb.oversample)
+    q = src["w"].to(torch.complex128)[None, :] * fine
+    ctr = aux["sides"][I.EXTERIOR]["ctr"]
+    out = O.apply_explicit(torch.stack([src["x"], src["y"]], 1), torch.stack([src["nx"], src["ny"]], 1),
+                           q, torch.stack([ctr["cx"], ctr["cy"]], 1), ctr["R"], ctr["theta"],
+                           pb.k, pb.p, pb.kind)
+    assert rel(out.numpy(), u[0].numpy()) < 1e-14
