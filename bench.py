@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
     ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
+    ap.add_argument("--backward", default="fused", choices=["fused", "tape"],
+                    help="fwdbwd step: plain forward + fused adjoint (default), or forward "
+                         "with tape + source-major adjoint")
     ap.add_argument("--autotune", type=int, default=1,
                     help="time the launch shapes on the workload first (untimed) and use the best")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -138,7 +141,13 @@ def main():
     def step():
         if mode == "fwd":
             return fwd()
-        # forward storing the tape, then the adjoint (density and node gradients)
+        if args.backward == "fused":
+            # forward, then the adjoint without a tape (one fused pass over the pairs)
+            u = fwd()
+            qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                    pb.kind, workspace=ws)
+            return u
+        # forward storing the tape, then the source-major adjoint
         u = qbx.layer_potential(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
                                 tape=tape, workspace=ws)
         qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample, pb.side,
@@ -165,7 +174,7 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    NC = 4
+    NC = 5
     ms = (C.c_double * NC)()
     nl = (C.c_int * NC)()
     _lib.check(lib.qbx_kernel_timer_read(ms, nl))
@@ -177,9 +186,9 @@ def main():
     # per pair-kernel class: algorithmic flops per launch / average launch time
     pairs = pb.n_centers * pb.n_sources
     names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel",
-             "forward-with-tape pair kernel"]
+             "forward-with-tape pair kernel", "fused adjoint pair kernel"]
     per_pair = [flops.flops_forward_pair(pb.p, pb.kind), flops.flops_adjoint_pair(pb.p, pb.kind),
-                0, flops.flops_tape_pair(pb.p, pb.kind)]
+                0, flops.flops_tape_pair(pb.p, pb.kind), flops.flops_fused_pair(pb.p, pb.kind)]
     kernels = {}
     for c in range(NC):
         if nl[c] == 0 or per_pair[c] == 0:
@@ -192,7 +201,7 @@ def main():
     dom = kernels[names[cls]]
     achieved = dom["tflops"]
     avg_ms = dom["avg_ms"]
-    kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape"]
+    kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape", "k_adjoint_fused"]
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(kernel_names[cls], args.workload),
@@ -247,7 +256,8 @@ def main():
                                f"oversample {pb.oversample}, k={pb.k}, p={pb.p}, "
                                f"side={'both' if pb.side == 0 else pb.side}, "
                                f"kind={'S+D' if pb.kind == 3 else ('S' if pb.kind == 1 else 'D')}",
-                   "mode": mode, "centers": pb.n_centers, "sources": pb.n_sources,
+                   "mode": mode, "backward": args.backward if mode == "fwdbwd" else None,
+                   "centers": pb.n_centers, "sources": pb.n_sources,
                    "interactions_per_step": inter, "tuning": tuning},
         "fwd_value": inter / fwd_s,
         "roofline": roof,
@@ -334,7 +344,7 @@ def bench_batched(args):
         log(f"batched autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     lib.qbx_kernel_timer(1)
     t_bat = timed(step_batched, args.steps)
-    NC = 4
+    NC = 5
     ms = (C.c_double * NC)()
     nl = (C.c_int * NC)()
     _lib.check(lib.qbx_kernel_timer_read(ms, nl))

@@ -114,8 +114,12 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
  *   grad_nodes   [n_panels][16][2] real = dL/d nodes,
  * through every step: source interpolation, weights, normals, panel lengths,
  * centers, radii and the expansion sums.  cotangent has the layout of out.
- * tape: the forward's tape, or NULL to recompute it.  Either gradient pointer
- * may be NULL when not wanted.  The gradients are written, not accumulated. */
+ * tape: the forward's tape; the pair work is then one source-major pass.  With
+ * tape NULL and grad_nodes wanted, one fused pass evaluates each pair once for
+ * both gradient sides; with tape NULL and only grad_density wanted, only the
+ * source-major pass runs.  Every path sums in a fixed order: repeated calls
+ * give identical bits.  Either gradient pointer may be
+ * NULL when not wanted.  The gradients are written, not accumulated. */
 int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, double k, int p,
                                 double r, int oversample, int side, int kind,
                                 const double* cotangent, const double* tape,
@@ -328,10 +332,10 @@ int qbx_kernel_timer(int enable);
 
 /* SYNCHRONOUS: waits for the recorded events and returns, per kernel class
  * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
- * kernel, 3 = forward-with-tape pair kernel), the summed duration in
- * milliseconds and the number of launches since the timer was enabled.
- * ms and launches are host arrays of QBX_TIMER_CLASSES. */
-#define QBX_TIMER_CLASSES 4
+ * kernels, 3 = forward-with-tape pair kernel, 4 = fused adjoint pair kernel),
+ * the summed duration in milliseconds and the number of launches since the
+ * timer was enabled.  ms and launches are host arrays of QBX_TIMER_CLASSES. */
+#define QBX_TIMER_CLASSES 5
 int qbx_kernel_timer_read(double* ms, int* launches);
 
 #ifdef __cplusplus

@@ -125,6 +125,116 @@ __global__ __launch_bounds__(256) void k_adjoint_src(const double4* __restrict__
     partial[((size_t)cs * NA + b) * N + j] = make_double2(A[b].r, A[b].i);
 }
 
+// ---------------------------------------------------------------------------
+// fused adjoint (no tape): workgroup (center block cb, source block sb).  The
+// four waves take the block's 64-source chunks together; wave w owns the
+// block's centers c = w, w + 4, ...  Per pair one evaluation of the tape-mode
+// sums feeds
+//   * the source side, accumulated in the lane over the wave's centers; at the
+//     end of each chunk the four waves' sums are added in a fixed order through
+//     LDS and written to spart[cb][NA][N] (layout of the source-major pass);
+//   * the center side, contracted with G and q (four reals), summed over the
+//     wave and added into the LDS sums of the center, which only its owning
+//     wave touches; written at the end to cpart[sb][ci][4].
+// Every sum has a fixed order, so the result is reproducible bit for bit.
+// Lanes past the last source take part with zero densities (the wave sums need
+// every lane) and write nothing.
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_adjoint_fused(
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
+    const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ,
+    const double2* __restrict__ G, int Mc, int cblock, int n_sb, int chunks,
+    int chunks_per_sb, double k, double2* __restrict__ spart, double* __restrict__ cpart) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  __shared__ double acc[kFusedCenters * 4];
+  __shared__ double2 xsrc[4][NA][kWave];
+  const int cb = blockIdx.x / n_sb;
+  const int sb = blockIdx.x - cb * n_sb;
+  const int i0 = cb * cblock;
+  const int nc = min(cblock, Mc - i0);
+  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) acc[t] = 0.0;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const double inv_k = 1.0 / k;
+  const int nj = NJ / 2;
+  const int ch0 = sb * chunks_per_sb;
+  const int ch1 = min(ch0 + chunks_per_sb, chunks);
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int j = ch * kWave + lane;
+    const bool valid = j < N;
+    const int jj = valid ? j : N - 1;
+    const double4 g = geo[jj];
+    double2 q[2];
+    q[0] = valid ? dens[jj] : make_double2(0.0, 0.0);
+    q[1] = (NK == 2 && valid) ? dens[(size_t)N + jj] : make_double2(0.0, 0.0);
+    Cplx A[NA];
+#pragma unroll
+    for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
+    for (int c = wave; c < nc; c += 4) {
+      const int ci = i0 + c;
+      const int z0 = opaque_zero();
+      const CenterRec* __restrict__ C = ctr + ci + z0;
+      const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
+      const double* __restrict__ cf = g_seed_table + z0;
+      double2 Gk[2];
+      Gk[0] = G[(size_t)ci + z0];
+      Gk[1] = NK == 2 ? G[(size_t)Mc + ci + z0] : Gk[0];
+      double cres[4];
+      fused_pair<P, KIND>(g, q, C->cx, C->cy, C->ct, C->st, J, nj, cf, k, inv_k, Gk, A, cres);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cres[b] += __shfl_xor(cres[b], off);
+      }
+      // every lane holds the four sums; lanes 0..3 add one each, the others add
+      // zero (no divergent branch inside the loop); only this wave touches
+      // these four slots
+      const int b = lane & 3;
+      const double v = lane < 4 ? (b == 0 ? cres[0] : b == 1 ? cres[1] : b == 2 ? cres[2] : cres[3])
+                                : 0.0;
+      atomicAdd(&acc[c * 4 + b], v);
+    }
+    // the four waves' source sums of this chunk, added in wave order
+#pragma unroll
+    for (int b = 0; b < NA; ++b) xsrc[wave][b][lane] = make_double2(A[b].r, A[b].i);
+    __syncthreads();
+    for (int b = wave; b < NA; b += 4) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        sr += xsrc[w][b][lane].x;
+        si += xsrc[w][b][lane].y;
+      }
+      if (valid) spart[((size_t)cb * NA + b) * N + j] = make_double2(sr, si);
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x)
+    cpart[((size_t)sb * Mc + i0) * 4 + t] = acc[t];
+}
+
+// per center: the fused center-side sums over the source blocks, then the
+// gradient assembly of center_grad_from_sums
+__global__ __launch_bounds__(256) void k_fused_center_grads(int Mc, int n_sb, int side, int T,
+                                                            const CenterRec* __restrict__ ctr,
+                                                            const double* __restrict__ cpart,
+                                                            double* __restrict__ cg) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= Mc) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sb = 0; sb < n_sb; ++sb) {
+    const double* q = cpart + ((size_t)sb * Mc + ci) * 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s[b] += q[b];
+  }
+  center_grad_from_sums(ci, side, T, ctr, s[0], s[1], s[2], s[3], cg);
+}
+
 // per source: sg[j] = {grad(w sigma) re, im, grad(w mu) re, im, g_x', g_y', g_nx, g_ny}
 __global__ __launch_bounds__(256) void k_source_finalize(int N, int nk, int kind, int n_csplit,
                                                          const double4* __restrict__ geo,
@@ -206,6 +316,60 @@ hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* o
   return hipGetLastError();
 }
 
+template <int P>
+static hipError_t launch_adjoint_fused_p(const Dims& d, const double4* geo, const double2* dens,
+                                         const CenterRec* ctr, const double* jtab,
+                                         const double2* G, double2* spart, double* cpart,
+                                         hipStream_t s) {
+  const dim3 grid((unsigned)(d.n_cb * d.n_sb)), block(256);
+#define QBX_LAUNCH(KD)                                                                        \
+  hipLaunchKernelGGL((k_adjoint_fused<P, KD>), grid, block, 0, s, geo, dens, d.N, ctr, jtab,   \
+                     d.NJ, G, d.Mc, d.fused_cblock, d.n_sb, d.chunks, d.chunks_per_sb, d.k,    \
+                     spart, cpart)
+  if (d.kind == 1)
+    QBX_LAUNCH(1);
+  else if (d.kind == 2)
+    QBX_LAUNCH(2);
+  else
+    QBX_LAUNCH(3);
+#undef QBX_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double* density,
+                                const double* tables, const double4* geo, const double2* dens,
+                                const CenterRec* ctr, const double* jtab, const double* cot,
+                                double2* G, double* cpart, double* cg, double2* spartial,
+                                double* sg, double* grad_density, double* grad_nodes,
+                                hipStream_t s) {
+  const int n = d.Mc * d.nk;
+  hipLaunchKernelGGL(k_make_G, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk, cot, G);
+  timer_begin(4, s);
+  hipError_t e;
+  switch (d.p) {
+#define QBX_CASE(PP) \
+  case PP:           \
+    e = launch_adjoint_fused_p<PP>(d, geo, dens, ctr, jtab, G, spartial, cpart, s); \
+    break;
+    QBX_CASE(0) QBX_CASE(1) QBX_CASE(2) QBX_CASE(3) QBX_CASE(4) QBX_CASE(5) QBX_CASE(6)
+    QBX_CASE(7) QBX_CASE(8) QBX_CASE(9) QBX_CASE(10) QBX_CASE(11) QBX_CASE(12) QBX_CASE(13)
+    QBX_CASE(14) QBX_CASE(15) QBX_CASE(16) QBX_CASE(17) QBX_CASE(18) QBX_CASE(19) QBX_CASE(20)
+    QBX_CASE(21) QBX_CASE(22) QBX_CASE(23) QBX_CASE(24)
+#undef QBX_CASE
+    default:
+      e = hipErrorInvalidValue;
+  }
+  timer_end(4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fused_center_grads, dim3((d.Mc + 255) / 256), dim3(256), 0, s, d.Mc,
+                     d.n_sb, d.side, d.T, ctr, cpart, cg);
+  hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.nk, d.kind,
+                     d.n_cb, geo, dens, spartial, sg);
+  hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
+                     grad_density, grad_nodes);
+  return hipGetLastError();
+}
+
 hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s) {
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_make_G, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk, cot, G);
@@ -220,8 +384,11 @@ hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double*
                                hipStream_t s) {
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_make_G, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk, cot, G);
-  hipLaunchKernelGGL(k_center_grads, dim3((d.Mc + 255) / 256), dim3(256), 0, s, d.Mc, d.nk, d.side,
-                     d.T, ctr, tape, G, cg);
+  // without a tape only the density gradient is asked for (the node gradient
+  // needs the center side): the chain step then reads no center data
+  if (tape)
+    hipLaunchKernelGGL(k_center_grads, dim3((d.Mc + 255) / 256), dim3(256), 0, s, d.Mc, d.nk,
+                       d.side, d.T, ctr, tape, G, cg);
   timer_begin(1, s);
   hipError_t e = launch_adjoint_src(d, geo, ctr, jtab, G, spartial, s);
   timer_end(1, s);

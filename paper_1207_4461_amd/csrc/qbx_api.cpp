@@ -40,6 +40,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int g_forward_waves = 16384;
 static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
+static int g_fused_tiles = 2048;   // fused adjoint workgroups aimed for
 
 void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves) {
   g_forward_waves = forward_waves;
@@ -81,6 +82,16 @@ void set_launch_shape(Dims* d) {
   if (cs < 1) cs = 1;
   d->centers_per_split = (int)(((long)d->Mc + cs - 1) / cs);
   d->n_csplit = (int)(((long)d->Mc + d->centers_per_split - 1) / d->centers_per_split);
+  // fused adjoint: tiles of up to kFusedCenters centers; enough source blocks for
+  // about g_fused_tiles tiles
+  d->fused_cblock = d->Mc < kFusedCenters ? d->Mc : kFusedCenters;
+  d->n_cb = (d->Mc + d->fused_cblock - 1) / d->fused_cblock;
+  long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
+  long max_sb = d->chunks;
+  if (sbs > max_sb) sbs = max_sb;
+  if (sbs < 1) sbs = 1;
+  d->chunks_per_sb = (int)((d->chunks + sbs - 1) / sbs);
+  d->n_sb = (d->chunks + d->chunks_per_sb - 1) / d->chunks_per_sb;
 }
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
@@ -133,7 +144,8 @@ Layout make_layout(const Dims& d) {
   L.G = take(sizeof(double2) * (size_t)d.nk * d.Mc);
   L.cg = take(sizeof(double) * (size_t)d.Mc * 8);
   const int NA = (d.kind & 1 ? 3 : 0) + (d.kind & 2 ? 4 : 0);
-  L.spart = take(sizeof(double2) * (size_t)d.n_csplit * NA * d.N);
+  L.spart = take(sizeof(double2) * (size_t)std::max(d.n_csplit, d.n_cb) * NA * d.N);
+  L.cpart = take(sizeof(double) * (size_t)d.n_sb * d.Mc * 4);
   L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
   L.total = o;
@@ -290,17 +302,15 @@ int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, do
   if (rc) return rc;
   hipError_t e;
   const double2* tp = reinterpret_cast<const double2*>(tape);
-  if (!tp) {
-    timer_begin(3, stream);
-    e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
-                            at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
-                            at<double2>(ws, L.partial), stream);
-    timer_end(3, stream);
-    if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
-    e = launch_finalize_tape(d, at<double2>(ws, L.partial), nullptr, at<double2>(ws, L.tape),
-                             stream);
-    if (e != hipSuccess) return device_fail(e, "finalize (tape) kernel");
-    tp = at<double2>(ws, L.tape);
+  if (!tp && grad_nodes) {
+    // no tape: one fused pass evaluates each pair once for both gradient sides
+    e = launch_adjoint_fused(d, g->nodes, density, at<double>(ws, L.tables),
+                             at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab), cotangent,
+                             at<double2>(ws, L.G), at<double>(ws, L.cpart), at<double>(ws, L.cg),
+                             at<double2>(ws, L.spart), at<double>(ws, L.sg), grad_density,
+                             grad_nodes, stream);
+    return e == hipSuccess ? QBX_OK : device_fail(e, "fused adjoint kernels");
   }
   e = launch_adjoint_rest(d, g->nodes, density, at<double>(ws, L.tables), at<double4>(ws, L.geo),
                           at<double2>(ws, L.dens), at<CenterRec>(ws, L.ctr),

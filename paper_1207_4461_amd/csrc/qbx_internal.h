@@ -45,6 +45,9 @@ struct Dims {
   // adjoint source-major launch shape
   int n_csplit;           // center splits per 64-source chunk
   int centers_per_split;  // centers per split
+  // fused adjoint launch shape: workgroup tiles of fused_cblock centers x
+  // chunks_per_sb 64-source chunks, n_cb x n_sb tiles
+  int fused_cblock, n_cb, n_sb, chunks_per_sb;
 };
 
 // Byte offsets of the workspace arrays (all 256-byte aligned).
@@ -60,7 +63,8 @@ struct Layout {
   size_t tape;     // double2[Mc][nk][4] tape recomputed by the adjoint when none is given
   size_t G;        // double2[nk][Mc] conj(cotangent) i/4
   size_t cg;       // double[Mc][8] per-center gradients
-  size_t spart;    // double2[n_csplit][NA][N] source-pass partial sums
+  size_t spart;    // double2[max(n_csplit, n_cb)][NA][N] source-pass partial sums
+  size_t cpart;    // double[n_sb][Mc][4] fused adjoint: center-side partial sums
   size_t sg;       // double[N][8] per-source gradients
   size_t scratch;  // double[16 + Mc] small reductions
   size_t total;
@@ -120,6 +124,16 @@ hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const CenterRec
                               const double* jtab, const double2* G, double2* partial,
                               hipStream_t s);
 hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s);
+// adjoint without a tape: one pass over the pairs for both gradient sides
+hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double* density,
+                                const double* tables, const double4* geo, const double2* dens,
+                                const CenterRec* ctr, const double* jtab, const double* cot,
+                                double2* G, double* cpart, double* cg, double2* spartial,
+                                double* sg, double* grad_density, double* grad_nodes,
+                                hipStream_t s);
+// centers per fused tile: 48 KB of LDS center sums plus 28 KB for the waves'
+// source sums keep two workgroups per CU
+constexpr int kFusedCenters = 1536;
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

@@ -438,6 +438,77 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
 }
 
 // ---------------------------------------------------------------------------
+// fused adjoint pair: one evaluation of the tape-mode pair sums feeds both the
+// source side (accumulated into A, the layout of the source-major pass, with
+// K_psi = K_theta + K_theta' for D: the target angle moves Delta and psi, the
+// source angle only Delta) and the center side, returned contracted with the
+// cotangent and summed over kinds: cres = Re(G q) of K_R, K_theta, grad_v K.
+// q: weighted densities of the source per kind; Gk: G of the center per kind.
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2], double cx,
+                                           double cy, double ct, double st,
+                                           const double* __restrict__ J, int nj,
+                                           const double* __restrict__ cf, double k, double inv_k,
+                                           const double2 (&Gk)[2],
+                                           Cplx (&A)[((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0)],
+                                           double (&cres)[4]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  const double vx = g.x - cx, vy = g.y - cy;
+  const double rho2 = fma(vx, vx, vy * vy);
+  const double ir = rsqrt_refined(rho2);
+  const double rho = rho2 * ir;
+  const double ux = vx * ir, uy = vy * ir;
+  const double cd = ct * ux + st * uy;
+  const double sd = st * ux - ct * uy;
+  double cps = 0.0, sps = 0.0;
+  if (kD) {
+    cps = ct * g.z + st * g.w;
+    sps = st * g.z - ct * g.w;
+  }
+  const PairOut o = pair_sums<P, KIND, 0>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+  double cR = 0.0, cT = 0.0, cX = 0.0, cY = 0.0;
+  int a = 0, kk = 0;
+  if (kS) {
+    const double2 G = Gk[0], w = q[0];
+    const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
+    const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
+    A[0].r += G.x * o.Ks.r - G.y * o.Ks.i;   // conj(G K)
+    A[0].i -= G.x * o.Ks.i + G.y * o.Ks.r;
+    cmul_acc(A[1], G.x, G.y, ex);
+    cmul_acc(A[2], G.x, G.y, ey);
+    const double gr = G.x * w.x - G.y * w.y, gi = G.x * w.y + G.y * w.x;   // G q
+    cR = fma(gr, o.KRs.r, fma(-gi, o.KRs.i, cR));
+    cT = fma(gr, o.Kts.r, fma(-gi, o.Kts.i, cT));
+    cX = fma(gr, ex.r, fma(-gi, ex.i, cX));
+    cY = fma(gr, ey.r, fma(-gi, ey.i, cY));
+    a = 3;
+    kk = 1;
+  }
+  if (kD) {
+    const double2 G = Gk[kk], w = q[kk];
+    const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
+    const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
+    const Cplx kpsi = {o.Ktd.r + o.Ktpd.r, o.Ktd.i + o.Ktpd.i};
+    A[a].r += G.x * o.Kd.r - G.y * o.Kd.i;
+    A[a].i -= G.x * o.Kd.i + G.y * o.Kd.r;
+    cmul_acc(A[a + 1], G.x, G.y, ex);
+    cmul_acc(A[a + 2], G.x, G.y, ey);
+    cmul_acc(A[a + 3], G.x, G.y, kpsi);
+    const double gr = G.x * w.x - G.y * w.y, gi = G.x * w.y + G.y * w.x;
+    cR = fma(gr, o.KRd.r, fma(-gi, o.KRd.i, cR));
+    cT = fma(gr, o.Ktd.r, fma(-gi, o.Ktd.i, cT));
+    cX = fma(gr, ex.r, fma(-gi, ex.i, cX));
+    cY = fma(gr, ey.r, fma(-gi, ey.i, cY));
+  }
+  cres[0] = cR;
+  cres[1] = cT;
+  cres[2] = cX;
+  cres[3] = cY;
+}
+
+// ---------------------------------------------------------------------------
 // adjoint, source side: one lane, one source g, centers [i0, i1); A as in the
 // partial layout of the source-major pass
 // ---------------------------------------------------------------------------

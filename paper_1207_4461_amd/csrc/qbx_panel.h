@@ -259,8 +259,30 @@ __device__ __forceinline__ void make_G_elem(int e, int Mc, int T, int nk, const 
   G[e] = make_double2(0.25 * gi, 0.25 * gr);   // (i/4)(gr - i gi)
 }
 
-// per-center gradients from the tape: cg[ci] = {g_x, g_y, g_R, g_nx, g_ny}
-// (target position, panel-scaled radius R, target normal), before the chain rule
+// per-center gradients cg[ci] = {g_x, g_y, g_R, g_nx, g_ny} (target position,
+// panel-scaled radius R, target normal), before the chain rule, from the
+// center-side sums contracted with G: dR = Re G sum q K_R, dt = Re G sum q K_theta,
+// (gvx, gvy) = Re G sum q grad_v K
+__device__ __forceinline__ void center_grad_from_sums(int ci, int side, int T,
+                                                      const CenterRec* __restrict__ ctr,
+                                                      double dR, double dt, double gvx,
+                                                      double gvy, double* __restrict__ cg) {
+  const CenterRec c = ctr[ci];
+  const double sgn = side_sign(side, ci / T);
+  // target offset direction w^ = (ct, st), theta^_w = (-st, ct)
+  const double gwx = dR * c.ct - dt / c.R * c.st;
+  const double gwy = dR * c.st + dt / c.R * c.ct;
+  const double gcx = -gvx - gwx, gcy = -gvy - gwy;
+  const double nx = -sgn * c.ct, ny = -sgn * c.st;   // outward normal at the target
+  double* o = cg + (size_t)ci * 8;
+  o[0] = -gvx;                          // x moves c along: grad_x = g_w + g_c
+  o[1] = -gvy;
+  o[2] = sgn * (nx * gcx + ny * gcy);   // c = x + s R n
+  o[3] = sgn * c.R * gcx;
+  o[4] = sgn * c.R * gcy;
+}
+
+// the same from the tape (per center and kind: sum q K_R, K_theta, grad_v K)
 __device__ __forceinline__ void center_grad_elem(int ci, int Mc, int nk, int side, int T,
                                                  const CenterRec* __restrict__ ctr,
                                                  const double2* __restrict__ tape,
@@ -276,19 +298,7 @@ __device__ __forceinline__ void center_grad_elem(int ci, int Mc, int nk, int sid
     gvx += g.x * tp[2].x - g.y * tp[2].y;
     gvy += g.x * tp[3].x - g.y * tp[3].y;
   }
-  const CenterRec c = ctr[ci];
-  const double sgn = side_sign(side, ci / T);
-  // target offset direction w^ = (ct, st), theta^_w = (-st, ct)
-  const double gwx = dR * c.ct - dt / c.R * c.st;
-  const double gwy = dR * c.st + dt / c.R * c.ct;
-  const double gcx = -gvx - gwx, gcy = -gvy - gwy;
-  const double nx = -sgn * c.ct, ny = -sgn * c.st;   // outward normal at the target
-  double* o = cg + (size_t)ci * 8;
-  o[0] = -gvx;                          // x moves c along: grad_x = g_w + g_c
-  o[1] = -gvy;
-  o[2] = sgn * (nx * gcx + ny * gcy);   // c = x + s R n
-  o[3] = sgn * c.R * gcx;
-  o[4] = sgn * c.R * gcy;
+  center_grad_from_sums(ci, side, T, ctr, dR, dt, gvx, gvy, cg);
 }
 
 // per source: sg[j] = {grad(w sigma) re, im, grad(w mu) re, im, g_x', g_y', g_nx, g_ny}

@@ -1,8 +1,10 @@
 """Algorithmic FP64 operation counts of the pair kernels, per (center, source) pair.
 
-Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, divide and
-rint = 1 each.  The counts follow the kernels' formulas for the common branch
-(z = k*rho >= 6, the asymptotic seed), line by line:
+Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, reciprocal square
+root, divide and rint = 1 each, however the kernel computes them (the kernels refine
+a hardware reciprocal square root by Newton steps; those steps are not counted).
+The counts follow the kernels' formulas for the common branch (z = k*rho >= 6, the
+asymptotic seed), line by line:
 
 forward pair (one center, one source, order p):
   geometry      v = x'-c (2), rho = sqrt(vx^2+vy^2) (4), 1/rho (1), cos/sin of
@@ -17,7 +19,7 @@ forward pair (one center, one source, order p):
                 + two Chebyshev sequences (4)                                = 11
   accumulation  w sigma K (8 per kind)
 
-Totals (derived in flops_forward_pair below; exact for the kernel code):
+Totals (derived in flops_forward_pair below):
   S:   210 + 12 p        D:   229 + 16 p        S+D: 243 + 23 p
 """
 from __future__ import annotations
@@ -98,3 +100,16 @@ def flops_adjoint_pair(p: int, kind: int) -> int:
     outer = 17 + (6 if D else 0)
     outer += (40 if S else 0) + (48 if D else 0)
     return outer + _pair_sums_flops(p, kind, False)
+
+
+def flops_fused_pair(p: int, kind: int) -> int:
+    """Fused adjoint pair kernel: the tape-mode sums once, then the source side (as the
+    source-major pass, K_psi = K_theta + K_theta') and the center side contracted with
+    G q (four reals)."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    outer = 17 + (6 if D else 0)
+    # per kind: conj(G K) 4, grad_v K components 16, two complex MACs 16, G q 6,
+    # four Re(G q X) 16; D adds K_psi 2 and its complex MAC 8
+    outer += (58 if S else 0) + (68 if D else 0)
+    return outer + _pair_sums_flops(p, kind, True)

@@ -192,15 +192,12 @@ class _LayerPotential(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, nodes, density, k, p, r, oversample, side, kind):
-        tape = None
-        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
-            P = int(nodes.shape[0])
-            tape = torch.empty(tape_bytes(P, p, side, kind), dtype=torch.uint8,
-                               device=nodes.device)
-        out = layer_potential(nodes.detach(), density.detach(), k, p, r, oversample, side, kind,
-                              tape=tape)
+        # no tape: the backward runs the fused pass (each pair evaluated once for
+        # both gradient sides), cheaper than a forward with tape plus a
+        # source-major pass, and it keeps no per-center state between the calls
+        out = layer_potential(nodes.detach(), density.detach(), k, p, r, oversample, side, kind)
         ctx.save_for_backward(nodes, density)
-        ctx.tape = tape
+        ctx.tape = None
         ctx.args = (k, p, r, oversample, side, kind)
         return out
 
