@@ -285,11 +285,13 @@ def bench_batched(args):
     log(f"workload random64: {len(pbs)} contours, {sum(pb.n_panels for pb in pbs)} panels, "
         f"{inter:.3e} interactions per pass, mode={mode}")
 
+    fused = args.backward == "fused"
+
     def step_batched():
         if mode == "fwd":
             return B.forward()
-        u = B.forward(with_tape=True)
-        B.adjoint(cot, use_tape=True)
+        u = B.forward(with_tape=not fused)
+        B.adjoint(cot, use_tape=not fused)
         return u
 
     per = []
@@ -309,10 +311,11 @@ def bench_batched(args):
                 qbx.layer_potential(q["nodes"], q["dens"], pb.k, pb.p, pb.r, pb.oversample,
                                     pb.side, pb.kind, workspace=q["ws"])
             else:
+                tp = None if fused else q["tape"]
                 qbx.layer_potential(q["nodes"], q["dens"], pb.k, pb.p, pb.r, pb.oversample,
-                                    pb.side, pb.kind, tape=q["tape"], workspace=q["ws"])
+                                    pb.side, pb.kind, tape=tp, workspace=q["ws"])
                 qbx.layer_potential_vjp(q["nodes"], q["dens"], q["cot"], pb.k, pb.p, pb.r,
-                                        pb.oversample, pb.side, pb.kind, tape=q["tape"],
+                                        pb.oversample, pb.side, pb.kind, tape=tp,
                                         workspace=q["ws"])
 
     def timed(fn, steps):
@@ -352,6 +355,9 @@ def bench_batched(args):
     # algorithmic flops of the persistent launches of one step
     if mode == "fwd":
         fl = sum(flops.flops_forward_pair(pb.p, pb.kind) * pb.n_centers * pb.n_sources for pb in pbs)
+    elif fused:
+        fl = sum((flops.flops_forward_pair(pb.p, pb.kind) + flops.flops_fused_pair(pb.p, pb.kind))
+                 * pb.n_centers * pb.n_sources for pb in pbs)
     else:
         fl = sum((flops.flops_tape_pair(pb.p, pb.kind) + flops.flops_adjoint_pair(pb.p, pb.kind))
                  * pb.n_centers * pb.n_sources for pb in pbs)
@@ -367,13 +373,17 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": "random64: 64 random star contours, 16..512 panels x 16 nodes, "
                                "oversample 4, k~U(5,50), p in {8,12,16}, S or D, exterior",
-                   "mode": mode, "interactions_per_step": inter,
+                   "mode": mode, "backward": args.backward if mode == "fwdbwd" else None,
+                   "interactions_per_step": inter,
                    "tuning": tuning, "per_contour_ms_per_step": t_per * 1e3,
                    "batched_speedup_vs_per_contour": t_per / t_bat},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": None, "kernel": "batched persistent kernels (forward-with-tape + "
-                     "adjoint source pass)" if mode != "fwd" else "batched persistent forward",
+                     "traffic": None,
+                     "kernel": ("batched persistent kernels (forward + fused adjoint)" if fused
+                                else "batched persistent kernels (forward-with-tape + adjoint "
+                                     "source pass)") if mode != "fwd"
+                     else "batched persistent forward",
                      "kernel_ms_per_step": round(per_step_ms, 3)},
         "cpu_baseline": None,
     }

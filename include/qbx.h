@@ -165,9 +165,12 @@ int qbx_layer_potential_batched(const qbx_batch_item* items, int n_items, const 
                                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of the batched forward (the per-contour qbx_layer_potential_adjoint
- * for every contour), with the source-major pass of all contours in one
- * persistent launch over (contour, 64-source chunk) tasks.  tape: the batched
- * forward's tape, or NULL to recompute it. */
+ * for every contour).  tape: the batched forward's tape; then the source-major
+ * pass of all contours of a (kind, p) class runs in one persistent launch over
+ * (contour, center split, 64-source chunk) tasks.  tape NULL with grad_nodes:
+ * the fused pass, one persistent launch per class whose workgroups take
+ * (contour, center block, source block) tiles; tape NULL with only
+ * grad_density: the source-major pass alone.  Reproducible bit for bit. */
 int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items,
                                         const double* nodes, const double* density,
                                         const double* cotangent, const double* tape,
@@ -286,14 +289,20 @@ int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t st
  *                       x a split of the centers, at least 16 centers each)
  *   batch_grid_scale    batched persistent kernels: workgroups launched =
  *                       workgroups resident on the device x this
- * Limits: the three wave targets and batch_adjoint_tasks in [256, 1 << 22],
- * batch_grid_scale in [0.125, 8].  Defaults 16384 and 1.0. */
+ *   fused_tiles         adjoint without a tape: workgroup tiles (a block of
+ *                       centers x a block of 64-source chunks) aimed for
+ *   batch_fused_chunks  batched adjoint without a tape: 64-source chunks per tile
+ * Limits: the three wave targets, batch_adjoint_tasks and fused_tiles in
+ * [256, 1 << 22], batch_grid_scale in [0.125, 8], batch_fused_chunks in
+ * [1, 64].  Defaults 16384, 1.0, 2048 and 2. */
 typedef struct {
   int32_t forward_waves;
   int32_t tape_waves;
   int32_t adjoint_waves;
   int32_t batch_adjoint_tasks;
   double batch_grid_scale;
+  int32_t fused_tiles;
+  int32_t batch_fused_chunks;
 } qbx_tuning;
 
 /* Set / read the process-wide tuning (QBX_EINVAL for values out of range). */
@@ -304,11 +313,12 @@ int qbx_get_tuning(qbx_tuning* t);
  * SYNCHRONOUS, and unlike every other entry point it ALLOCATES (and frees)
  * device memory of its own: workspace, output, tape and gradients.  For each
  * of forward_waves, tape_waves and adjoint_waves it times the candidates
- * 2048 .. 131072 (doubling; candidates that give the same launch shape are
- * timed once) with hipEvents on `stream`, the minimum over `passes` runs
- * (1..20) after one warm-up, keeps the fastest, installs the result with
- * qbx_set_tuning and writes it to *best (nullable).  The batched fields are
- * left as they were.  On error the previous tuning is restored. */
+ * 2048 .. 131072, and for fused_tiles 512 .. 16384 (doubling; candidates that
+ * give the same launch shape are timed once), with hipEvents on `stream`, the
+ * minimum over `passes` runs (1..20) after one warm-up, keeps the fastest,
+ * installs the result with qbx_set_tuning and writes it to *best (nullable).
+ * The batched fields are left as they were.  On error the previous tuning is
+ * restored. */
 int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, double r,
                  int oversample, int side, int kind, int passes, qbx_tuning* best,
                  hipStream_t stream);
@@ -317,7 +327,8 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
  * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
  * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2, 4} on the batched
  * forward-with-tape, then batch_adjoint_tasks in 2048 .. 262144 (doubling) on
- * the batched adjoint, keeps the fastest of each and installs them. */
+ * the batched adjoint with the tape and batch_fused_chunks in {1, 2, 4, 8} on
+ * the batched adjoint without it, keeps the fastest of each and installs them. */
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
                          const double* density, int oversample, int passes, qbx_tuning* best,
                          hipStream_t stream);

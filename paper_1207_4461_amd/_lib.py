@@ -48,7 +48,8 @@ class Tuning(C.Structure):
     """qbx_tuning of include/qbx.h."""
     _fields_ = [("forward_waves", C.c_int32), ("tape_waves", C.c_int32),
                 ("adjoint_waves", C.c_int32), ("batch_adjoint_tasks", C.c_int32),
-                ("batch_grid_scale", C.c_double)]
+                ("batch_grid_scale", C.c_double), ("fused_tiles", C.c_int32),
+                ("batch_fused_chunks", C.c_int32)]
 
 
 _lib = None

@@ -126,19 +126,8 @@ __global__ __launch_bounds__(256) void k_adjoint_src(const double4* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// fused adjoint (no tape): workgroup (center block cb, source block sb).  The
-// four waves take the block's 64-source chunks together; wave w owns the
-// block's centers c = w, w + 4, ...  Per pair one evaluation of the tape-mode
-// sums feeds
-//   * the source side, accumulated in the lane over the wave's centers; at the
-//     end of each chunk the four waves' sums are added in a fixed order through
-//     LDS and written to spart[cb][NA][N] (layout of the source-major pass);
-//   * the center side, contracted with G and q (four reals), summed over the
-//     wave and added into the LDS sums of the center, which only its owning
-//     wave touches; written at the end to cpart[sb][ci][4].
-// Every sum has a fixed order, so the result is reproducible bit for bit.
-// Lanes past the last source take part with zero densities (the wave sums need
-// every lane) and write nothing.
+// fused adjoint (no tape): one workgroup per tile (center block cb, source
+// block sb); the tile body and its ordering are in qbx_pair.h (fused_tile)
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_adjoint_fused(
@@ -146,76 +135,16 @@ __global__ __launch_bounds__(256) void k_adjoint_fused(
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ,
     const double2* __restrict__ G, int Mc, int cblock, int n_sb, int chunks,
     int chunks_per_sb, double k, double2* __restrict__ spart, double* __restrict__ cpart) {
-  constexpr bool kS = (KIND & 1) != 0;
-  constexpr bool kD = (KIND & 2) != 0;
-  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
-  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
-  __shared__ double acc[kFusedCenters * 4];
+  constexpr int NA = ((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0);
+  __shared__ double acc[fused_centers(KIND) * 4];
   __shared__ double2 xsrc[4][NA][kWave];
   const int cb = blockIdx.x / n_sb;
   const int sb = blockIdx.x - cb * n_sb;
   const int i0 = cb * cblock;
-  const int nc = min(cblock, Mc - i0);
-  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) acc[t] = 0.0;
-  __syncthreads();
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const double inv_k = 1.0 / k;
-  const int nj = NJ / 2;
   const int ch0 = sb * chunks_per_sb;
-  const int ch1 = min(ch0 + chunks_per_sb, chunks);
-  for (int ch = ch0; ch < ch1; ++ch) {
-    const int j = ch * kWave + lane;
-    const bool valid = j < N;
-    const int jj = valid ? j : N - 1;
-    const double4 g = geo[jj];
-    double2 q[2];
-    q[0] = valid ? dens[jj] : make_double2(0.0, 0.0);
-    q[1] = (NK == 2 && valid) ? dens[(size_t)N + jj] : make_double2(0.0, 0.0);
-    Cplx A[NA];
-#pragma unroll
-    for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
-    for (int c = wave; c < nc; c += 4) {
-      const int ci = i0 + c;
-      const int z0 = opaque_zero();
-      const CenterRec* __restrict__ C = ctr + ci + z0;
-      const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
-      const double* __restrict__ cf = g_seed_table + z0;
-      double2 Gk[2];
-      Gk[0] = G[(size_t)ci + z0];
-      Gk[1] = NK == 2 ? G[(size_t)Mc + ci + z0] : Gk[0];
-      double cres[4];
-      fused_pair<P, KIND>(g, q, C->cx, C->cy, C->ct, C->st, J, nj, cf, k, inv_k, Gk, A, cres);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cres[b] += __shfl_xor(cres[b], off);
-      }
-      // every lane holds the four sums; lanes 0..3 add one each, the others add
-      // zero (no divergent branch inside the loop); only this wave touches
-      // these four slots
-      const int b = lane & 3;
-      const double v = lane < 4 ? (b == 0 ? cres[0] : b == 1 ? cres[1] : b == 2 ? cres[2] : cres[3])
-                                : 0.0;
-      atomicAdd(&acc[c * 4 + b], v);
-    }
-    // the four waves' source sums of this chunk, added in wave order
-#pragma unroll
-    for (int b = 0; b < NA; ++b) xsrc[wave][b][lane] = make_double2(A[b].r, A[b].i);
-    __syncthreads();
-    for (int b = wave; b < NA; b += 4) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        sr += xsrc[w][b][lane].x;
-        si += xsrc[w][b][lane].y;
-      }
-      if (valid) spart[((size_t)cb * NA + b) * N + j] = make_double2(sr, si);
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x)
-    cpart[((size_t)sb * Mc + i0) * 4 + t] = acc[t];
+  fused_tile<P, KIND>(geo, dens, N, ctr, jtab, NJ, G, Mc, i0, min(cblock, Mc - i0), ch0,
+                      min(ch0 + chunks_per_sb, chunks), k, spart + (size_t)cb * NA * N,
+                      cpart + (size_t)sb * Mc * 4, acc, xsrc);
 }
 
 // per center: the fused center-side sums over the source blocks, then the

@@ -42,16 +42,19 @@ static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
 static int g_fused_tiles = 2048;   // fused adjoint workgroups aimed for
 
-void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves) {
+void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves, int fused_tiles) {
   g_forward_waves = forward_waves;
   g_tape_waves = tape_waves;
   g_adjoint_waves = adjoint_waves;
+  g_fused_tiles = fused_tiles;
 }
 
-void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves) {
+void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves,
+                        int* fused_tiles) {
   *forward_waves = g_forward_waves;
   *tape_waves = g_tape_waves;
   *adjoint_waves = g_adjoint_waves;
+  *fused_tiles = g_fused_tiles;
 }
 
 // source splits of the forward kernels and center splits of the adjoint source
@@ -82,9 +85,9 @@ void set_launch_shape(Dims* d) {
   if (cs < 1) cs = 1;
   d->centers_per_split = (int)(((long)d->Mc + cs - 1) / cs);
   d->n_csplit = (int)(((long)d->Mc + d->centers_per_split - 1) / d->centers_per_split);
-  // fused adjoint: tiles of up to kFusedCenters centers; enough source blocks for
+  // fused adjoint: tiles of up to fused_centers(kind) centers; enough source blocks for
   // about g_fused_tiles tiles
-  d->fused_cblock = d->Mc < kFusedCenters ? d->Mc : kFusedCenters;
+  d->fused_cblock = d->Mc < fused_centers(d->kind) ? d->Mc : fused_centers(d->kind);
   d->n_cb = (d->Mc + d->fused_cblock - 1) / d->fused_cblock;
   long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
   long max_sb = d->chunks;
@@ -415,26 +418,30 @@ int qbx_set_tuning(const qbx_tuning* t) {
   const int lo = 256, hi = 1 << 22;
   auto in = [&](int v) { return v >= lo && v <= hi; };
   if (!in(t->forward_waves) || !in(t->tape_waves) || !in(t->adjoint_waves) ||
-      !in(t->batch_adjoint_tasks))
-    return fail(QBX_EINVAL, "tuning wave / task targets must lie in [%d, %d]", lo, hi);
+      !in(t->batch_adjoint_tasks) || !in(t->fused_tiles))
+    return fail(QBX_EINVAL, "tuning wave / task / tile targets must lie in [%d, %d]", lo, hi);
   if (!(t->batch_grid_scale >= 0.125 && t->batch_grid_scale <= 8.0))
     return fail(QBX_EINVAL, "batch_grid_scale = %g outside [0.125, 8]", t->batch_grid_scale);
-  set_contour_tuning(t->forward_waves, t->tape_waves, t->adjoint_waves);
-  set_batch_tuning(t->batch_grid_scale, (double)t->batch_adjoint_tasks);
+  if (t->batch_fused_chunks < 1 || t->batch_fused_chunks > 64)
+    return fail(QBX_EINVAL, "batch_fused_chunks = %d outside [1, 64]", t->batch_fused_chunks);
+  set_contour_tuning(t->forward_waves, t->tape_waves, t->adjoint_waves, t->fused_tiles);
+  set_batch_tuning(t->batch_grid_scale, (double)t->batch_adjoint_tasks, t->batch_fused_chunks);
   return QBX_OK;
 }
 
 int qbx_get_tuning(qbx_tuning* t) {
   if (!t) return fail(QBX_EINVAL, "tuning is NULL");
-  int fw, tw, aw;
-  get_contour_tuning(&fw, &tw, &aw);
+  int fw, tw, aw, ft, fc;
+  get_contour_tuning(&fw, &tw, &aw, &ft);
   double gs, at;
-  get_batch_tuning(&gs, &at);
+  get_batch_tuning(&gs, &at, &fc);
   t->forward_waves = fw;
   t->tape_waves = tw;
   t->adjoint_waves = aw;
   t->batch_adjoint_tasks = (int32_t)at;
   t->batch_grid_scale = gs;
+  t->fused_tiles = ft;
+  t->batch_fused_chunks = fc;
   return QBX_OK;
 }
 

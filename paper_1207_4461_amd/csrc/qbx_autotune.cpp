@@ -63,6 +63,7 @@ double time_min(const std::function<int()>& fn, int passes, hipStream_t s, Event
 }
 
 const int kWaveCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536, 131072};
+const int kTileCandidates[] = {512, 1024, 2048, 4096, 8192, 16384};
 
 }  // namespace
 }  // namespace qbx
@@ -84,8 +85,10 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
   // a workspace large enough for every candidate
   size_t ws_bytes = 0;
   for (int c : kWaveCandidates) {
-    set_contour_tuning(c, c, c);
-    ws_bytes = std::max(ws_bytes, qbx_workspace_bytes(d.P, kQ, p, oversample, side, kind));
+    for (int f : kTileCandidates) {
+      set_contour_tuning(c, c, c, f);
+      ws_bytes = std::max(ws_bytes, qbx_workspace_bytes(d.P, kQ, p, oversample, side, kind));
+    }
   }
   qbx_set_tuning(&saved);
   const size_t out_bytes = sizeof(double) * 2 * (size_t)d.n_sides * d.nk * d.T;
@@ -116,24 +119,38 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
                                        static_cast<double*>(gd), static_cast<double*>(gn), ws,
                                        ws_bytes, stream);
   };
+  // the adjoint without a tape: the fused pass
+  auto adj_fused = [&] {
+    return qbx_layer_potential_adjoint(g, density, k, p, r, oversample, side, kind, o, nullptr,
+                                       static_cast<double*>(gd), static_cast<double*>(gn), ws,
+                                       ws_bytes, stream);
+  };
   qbx_tuning cur = saved;
-  // which = 0 forward, 1 tape, 2 adjoint
-  for (int which = 0; which < 3; ++which) {
-    std::set<int> shapes;
+  // which = 0 forward, 1 tape, 2 adjoint with the tape, 3 fused adjoint
+  for (int which = 0; which < 4; ++which) {
+    std::set<long long> shapes;
     double t_best = 1e300;
-    int v_best = which == 0 ? saved.forward_waves : which == 1 ? saved.tape_waves
-                                                                : saved.adjoint_waves;
-    for (int c : kWaveCandidates) {
+    int* field = which == 0 ? &cur.forward_waves : which == 1 ? &cur.tape_waves
+                 : which == 2 ? &cur.adjoint_waves : &cur.fused_tiles;
+    int v_best = *field;
+    const int* cands = which == 3 ? kTileCandidates : kWaveCandidates;
+    const int n_cands = which == 3 ? (int)(sizeof(kTileCandidates) / sizeof(int))
+                                   : (int)(sizeof(kWaveCandidates) / sizeof(int));
+    for (int ic = 0; ic < n_cands; ++ic) {
+      const int c = cands[ic];
       qbx_tuning t = cur;
-      (which == 0 ? t.forward_waves : which == 1 ? t.tape_waves : t.adjoint_waves) = c;
+      (which == 0 ? t.forward_waves : which == 1 ? t.tape_waves
+       : which == 2 ? t.adjoint_waves : t.fused_tiles) = c;
       qbx_set_tuning(&t);
       Dims dc;
       make_dims(d.P, kQ, p, oversample, side, kind, k, r, &dc);
-      const int shape = which == 0 ? dc.n_split : which == 1 ? dc.n_tsplit : dc.n_csplit;
+      const long long shape = which == 0 ? dc.n_split : which == 1 ? dc.n_tsplit
+                              : which == 2 ? dc.n_csplit : (long long)dc.chunks_per_sb;
       if (!shapes.insert(shape).second) continue;
       const double ms = time_min(which == 0 ? std::function<int()>(fwd)
                                  : which == 1 ? std::function<int()>(fwd_tape)
-                                              : std::function<int()>(adj),
+                                 : which == 2 ? std::function<int()>(adj)
+                                              : std::function<int()>(adj_fused),
                                  passes, stream, ev, &rc);
       if (ms < 0.0) {
         qbx_set_tuning(&saved);
@@ -144,7 +161,7 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
         v_best = c;
       }
     }
-    (which == 0 ? cur.forward_waves : which == 1 ? cur.tape_waves : cur.adjoint_waves) = v_best;
+    *field = v_best;
     qbx_set_tuning(&cur);
   }
   if (best) *best = cur;
@@ -163,12 +180,16 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
   qbx_get_tuning(&saved);
   static const int kTaskCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144};
   static const double kScaleCandidates[] = {0.5, 1.0, 2.0, 4.0};
+  static const int kChunkCandidates[] = {1, 2, 4, 8};
   size_t ws_bytes = 0;
   for (int c : kTaskCandidates) {
-    qbx_tuning t = saved;
-    t.batch_adjoint_tasks = c;
-    qbx_set_tuning(&t);
-    ws_bytes = std::max(ws_bytes, qbx_batched_workspace_bytes(items, n_items, oversample));
+    for (int f : kChunkCandidates) {
+      qbx_tuning t = saved;
+      t.batch_adjoint_tasks = c;
+      t.batch_fused_chunks = f;
+      qbx_set_tuning(&t);
+      ws_bytes = std::max(ws_bytes, qbx_batched_workspace_bytes(items, n_items, oversample));
+    }
   }
   qbx_set_tuning(&saved);
   // extents of the caller's packed arrays, from the items
@@ -234,6 +255,26 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
     if (ms < t_best) {
       t_best = ms;
       cur.batch_adjoint_tasks = c;
+    }
+  }
+  auto adj_fused = [&] {
+    return qbx_layer_potential_batched_adjoint(items, n_items, nodes, density, o, nullptr,
+                                               static_cast<double*>(gd), static_cast<double*>(gn),
+                                               oversample, ws, ws_bytes, stream);
+  };
+  t_best = 1e300;
+  for (int c : kChunkCandidates) {
+    qbx_tuning t = cur;
+    t.batch_fused_chunks = c;
+    qbx_set_tuning(&t);
+    const double ms = time_min(adj_fused, passes, stream, ev, &rc);
+    if (ms < 0.0) {
+      qbx_set_tuning(&saved);
+      return rc ? rc : fail(QBX_EDEVICE, "autotuner timing failed");
+    }
+    if (ms < t_best) {
+      t_best = ms;
+      cur.batch_fused_chunks = c;
     }
   }
   qbx_set_tuning(&cur);

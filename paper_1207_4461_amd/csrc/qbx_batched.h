@@ -20,6 +20,7 @@ struct BatchItemDev {
   long long G_off;       // double2 into G
   long long spart_off;   // double2 into the source-pass sums
   long long panel_off;   // first panel of this contour in the batch
+  long long cpart_off;   // doubles into the fused adjoint's center-side partial sums
 };
 
 __device__ __forceinline__ int find_slot(const long long* __restrict__ pre, int n, long long t) {
@@ -133,6 +134,12 @@ hipError_t launch_forward_batched(int mode, int kind, int p, const BatchTasks& t
 hipError_t launch_adjoint_batched(int kind, int p, const BatchTasks& t, const double4* geo,
                                   const CenterRec* ctr, const double* jtab, const double2* G,
                                   double2* spart, double grid_scale, hipStream_t s);
+// fused adjoint (no tape): persistent workgroups over (contour, center block,
+// source block) tiles of one (kind, p) class
+hipError_t launch_adjoint_fused_batched(int kind, int p, const BatchTasks& t, const double4* geo,
+                                        const double2* densw, const CenterRec* ctr,
+                                        const double* jtab, const double2* G, double2* spart,
+                                        double* cpart, double grid_scale, hipStream_t s);
 
 // number of workgroups of `block` threads of `kernel` resident on the whole
 // device (the per-CU figure is cached by the caller in *per_cu), times

@@ -30,7 +30,7 @@ namespace qbx {
 struct BatchClass {
   int kind, p, n;
   int ord_at, pre_at;
-  long long tasks_f, tasks_a;
+  long long tasks_f, tasks_a, tasks_x;   // forward, adjoint source pass, fused adjoint tiles
 };
 
 struct BatchPlan {
@@ -38,20 +38,21 @@ struct BatchPlan {
   int qs;
   std::vector<BatchItemDev> items;
   std::vector<BatchClass> cls;                    // heaviest class first
-  std::vector<int> order_f, order_a;              // per class: contours by decreasing task cost
-  std::vector<long long> pre_f, pre_a;            // per class: task prefix sums in that order
+  std::vector<int> order_f, order_a, order_x;     // per class: contours by decreasing task cost
+  std::vector<long long> pre_f, pre_a, pre_x;     // per class: task prefix sums in that order
   std::vector<long long> pre_panel, pre_ctr, pre_src, pre_G;  // prefix sums in item order
   long long n_panels = 0, n_ctr = 0, n_src = 0, n_G = 0, n_densw = 0, n_jtab = 0, n_tape = 0,
-            n_spart = 0;
+            n_spart = 0, n_cpart = 0;
   // workspace offsets
-  size_t o_items, o_ord_f, o_ord_a, o_pre_f, o_pre_a, o_pre_panel, o_pre_ctr, o_pre_src, o_pre_G,
-      o_counter, o_tables, o_geo, o_densw, o_wgt, o_h, o_ctr, o_jtab, o_tape, o_G, o_cg, o_spart,
+  size_t o_items, o_ord_f, o_ord_a, o_ord_x, o_pre_f, o_pre_a, o_pre_x, o_pre_panel, o_pre_ctr, o_pre_src, o_pre_G,
+      o_counter, o_tables, o_geo, o_densw, o_wgt, o_h, o_ctr, o_jtab, o_tape, o_G, o_cg, o_spart, o_cpart,
       o_sg, total;
 };
 
 // launch tunables (qbx_set_tuning)
 static double g_batch_grid_scale = 1.0;       // persistent grid = resident blocks x this
 static double g_batch_adjoint_tasks = 16384;  // adjoint tasks per (kind, p) class
+static int g_batch_fused_chunks = 2;          // 64-source chunks per fused adjoint tile
 
 static bool build_plan(const qbx_batch_item* items, int n, int oversample, BatchPlan* P) {
   if (!items || n < 1 || oversample < 1 || oversample > QBX_OVERSAMPLE_MAX) return false;
@@ -62,7 +63,7 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   P->pre_ctr.assign(n + 1, 0);
   P->pre_src.assign(n + 1, 0);
   P->pre_G.assign(n + 1, 0);
-  std::vector<double> cost_f(n), cost_a(n);
+  std::vector<double> cost_f(n), cost_a(n), cost_x(n);
   for (int i = 0; i < n; ++i) {
     const qbx_batch_item& it = items[i];
     BatchItemDev& B = P->items[i];
@@ -124,6 +125,8 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   P->cls = sorted;
   P->order_f.clear();
   P->order_a.clear();
+  P->order_x.clear();
+  P->pre_x.clear();
   P->pre_f.clear();
   P->pre_a.clear();
   for (size_t c = 0; c < P->cls.size(); ++c) {
@@ -158,12 +161,37 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     }
     C.tasks_f = append(cost_f, P->order_f, P->pre_f, true);
     C.tasks_a = append(cost_a, P->order_a, P->pre_a, false);
+    // fused adjoint tiles: up to fused_centers(kind) centers x g_batch_fused_chunks
+    // 64-source chunks; tile cost ~ centers of the tile
+    for (int i : mem) {
+      Dims& d = P->items[i].d;
+      d.fused_cblock = d.Mc < fused_centers(d.kind) ? d.Mc : fused_centers(d.kind);
+      d.n_cb = (d.Mc + d.fused_cblock - 1) / d.fused_cblock;
+      d.chunks_per_sb = d.chunks < g_batch_fused_chunks ? d.chunks : g_batch_fused_chunks;
+      d.n_sb = (d.chunks + d.chunks_per_sb - 1) / d.chunks_per_sb;
+      cost_x[i] = (double)d.fused_cblock;
+    }
+    {
+      std::vector<int> o = mem;
+      std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return cost_x[a] > cost_x[b]; });
+      long long acc = 0;
+      P->pre_x.push_back(0);
+      for (int i : o) {
+        const Dims& d = P->items[i].d;
+        acc += (long long)d.n_cb * d.n_sb;
+        P->order_x.push_back(i);
+        P->pre_x.push_back(acc);
+      }
+      C.tasks_x = acc;
+    }
   }
   for (int i = 0; i < n; ++i) {
     BatchItemDev& B = P->items[i];
     const int NA = (B.d.kind & 1 ? 3 : 0) + (B.d.kind & 2 ? 4 : 0);
     B.spart_off = P->n_spart;
-    P->n_spart += (long long)B.d.n_csplit * NA * B.d.N;
+    P->n_spart += (long long)std::max(B.d.n_csplit, B.d.n_cb) * NA * B.d.N;
+    B.cpart_off = P->n_cpart;
+    P->n_cpart += (long long)B.d.n_sb * B.d.Mc * 4;
   }
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -174,13 +202,15 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   P->o_items = take(sizeof(BatchItemDev) * n);
   P->o_ord_f = take(sizeof(int) * n);
   P->o_ord_a = take(sizeof(int) * n);
+  P->o_ord_x = take(sizeof(int) * n);
   P->o_pre_f = take(sizeof(long long) * P->pre_f.size());
   P->o_pre_a = take(sizeof(long long) * P->pre_a.size());
+  P->o_pre_x = take(sizeof(long long) * P->pre_x.size());
   P->o_pre_panel = take(sizeof(long long) * (n + 1));
   P->o_pre_ctr = take(sizeof(long long) * (n + 1));
   P->o_pre_src = take(sizeof(long long) * (n + 1));
   P->o_pre_G = take(sizeof(long long) * (n + 1));
-  P->o_counter = take(sizeof(int) * 2 * P->cls.size());
+  P->o_counter = take(sizeof(int) * 3 * P->cls.size());
   P->o_tables = take(sizeof(double) * table_layout(P->qs).total);
   P->o_geo = take(sizeof(double4) * P->n_src);
   P->o_densw = take(sizeof(double2) * P->n_densw);
@@ -192,6 +222,7 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   P->o_G = take(sizeof(double2) * P->n_G);
   P->o_cg = take(sizeof(double) * 8 * P->n_ctr);
   P->o_spart = take(sizeof(double2) * P->n_spart);
+  P->o_cpart = take(sizeof(double) * P->n_cpart);
   P->o_sg = take(sizeof(double) * 8 * P->n_src);
   P->total = o;
   return true;
@@ -251,15 +282,39 @@ __global__ __launch_bounds__(256) void k_center_grads_batched(
                    tape + B.tape_off, G + B.G_off, cg + B.ctr_off * 8);
 }
 
+// per center of the batch: the fused center-side sums over the contour's source
+// blocks, then the gradient assembly
+__global__ __launch_bounds__(256) void k_fused_center_grads_batched(
+    const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_ctr, int n,
+    long long total, const CenterRec* __restrict__ ctr, const double* __restrict__ cpart,
+    double* __restrict__ cg) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int it = find_slot(pre_ctr, n, e);
+  const BatchItemDev& B = items[it];
+  const Dims& d = B.d;
+  const int ci = (int)(e - pre_ctr[it]);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sb = 0; sb < d.n_sb; ++sb) {
+    const double* q = cpart + B.cpart_off + ((size_t)sb * d.Mc + ci) * 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s[b] += q[b];
+  }
+  center_grad_from_sums(ci, d.side, d.T, ctr + B.ctr_off, s[0], s[1], s[2], s[3],
+                        cg + B.ctr_off * 8);
+}
+
 __global__ __launch_bounds__(256) void k_source_finalize_batched(
     const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_src, int n,
-    long long total, const double4* __restrict__ geo, const double2* __restrict__ densw,
+    long long total, int fused, const double4* __restrict__ geo, const double2* __restrict__ densw,
     const double2* __restrict__ spart, double* __restrict__ sg) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int it = find_slot(pre_src, n, e);
   const BatchItemDev& B = items[it];
-  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind, B.d.n_csplit, geo + B.src_off,
+  // the source sums come in n_cb parts from the fused pass, n_csplit otherwise
+  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind,
+                       fused ? B.d.n_cb : B.d.n_csplit, geo + B.src_off,
                        densw + B.densw_off, spart + B.spart_off, sg + B.src_off * 8);
 }
 
@@ -290,8 +345,10 @@ static int upload_plan(const BatchPlan& P, void* ws, hipStream_t s) {
       {P.o_items, P.items.data(), sizeof(BatchItemDev) * P.n},
       {P.o_ord_f, P.order_f.data(), sizeof(int) * P.n},
       {P.o_ord_a, P.order_a.data(), sizeof(int) * P.n},
+      {P.o_ord_x, P.order_x.data(), sizeof(int) * P.n},
       {P.o_pre_f, P.pre_f.data(), sizeof(long long) * P.pre_f.size()},
       {P.o_pre_a, P.pre_a.data(), sizeof(long long) * P.pre_a.size()},
+      {P.o_pre_x, P.pre_x.data(), sizeof(long long) * P.pre_x.size()},
       {P.o_pre_panel, P.pre_panel.data(), sizeof(long long) * (P.n + 1)},
       {P.o_pre_ctr, P.pre_ctr.data(), sizeof(long long) * (P.n + 1)},
       {P.o_pre_src, P.pre_src.data(), sizeof(long long) * (P.n + 1)},
@@ -322,21 +379,23 @@ static int batch_prepare(const BatchPlan& P, const double* nodes, const double* 
   return e == hipSuccess ? QBX_OK : device_fail(e, "batched upsample kernel");
 }
 
-static BatchTasks class_tasks(const BatchPlan& P, void* ws, size_t c, bool adjoint) {
+// which = 0 forward, 1 adjoint source pass, 2 fused adjoint tiles
+static BatchTasks class_tasks(const BatchPlan& P, void* ws, size_t c, int which) {
   const BatchClass& C = P.cls[c];
   BatchTasks t;
   t.items = wsp<BatchItemDev>(ws, P.o_items);
-  t.order = wsp<int>(ws, adjoint ? P.o_ord_a : P.o_ord_f) + C.ord_at;
-  t.pre = wsp<long long>(ws, adjoint ? P.o_pre_a : P.o_pre_f) + C.pre_at;
+  t.order = wsp<int>(ws, which == 0 ? P.o_ord_f : which == 1 ? P.o_ord_a : P.o_ord_x) + C.ord_at;
+  t.pre = wsp<long long>(ws, which == 0 ? P.o_pre_f : which == 1 ? P.o_pre_a : P.o_pre_x) +
+          C.pre_at;
   t.n = C.n;
-  t.n_tasks = adjoint ? C.tasks_a : C.tasks_f;
-  t.counter = wsp<int>(ws, P.o_counter) + (adjoint ? P.cls.size() : 0) + c;
+  t.n_tasks = which == 0 ? C.tasks_f : which == 1 ? C.tasks_a : C.tasks_x;
+  t.counter = wsp<int>(ws, P.o_counter) + (size_t)which * P.cls.size() + c;
   return t;
 }
 
 static int zero_counters(const BatchPlan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(256), 0, s, wsp<int>(ws, P.o_counter),
-                     (int)(2 * P.cls.size()));
+                     (int)(3 * P.cls.size()));
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? QBX_OK : device_fail(e, "counter reset kernel");
 }
@@ -346,7 +405,7 @@ static int batch_forward(const BatchPlan& P, double* out, double2* tape, void* w
   if (rc) return rc;
   timer_begin(2, s);
   for (size_t c = 0; c < P.cls.size(); ++c) {
-    const BatchTasks t = class_tasks(P, ws, c, false);
+    const BatchTasks t = class_tasks(P, ws, c, 0);
     hipError_t e = launch_forward_batched(
         tape ? 1 : 0, P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
         wsp<double2>(ws, P.o_densw), wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab), out,
@@ -375,13 +434,15 @@ hipError_t launch_forward_batched(int mode, int kind, int p, const BatchTasks& t
               : launch_forward_batched_0(kind, p, t, geo, densw, ctr, jtab, out, tape, grid_scale, s);
 }
 
-void set_batch_tuning(double grid_scale, double adjoint_tasks) {
+void set_batch_tuning(double grid_scale, double adjoint_tasks, int fused_chunks) {
   g_batch_grid_scale = std::min(8.0, std::max(0.125, grid_scale));
   g_batch_adjoint_tasks = std::min(4194304.0, std::max(256.0, adjoint_tasks));
+  g_batch_fused_chunks = std::min(64, std::max(1, fused_chunks));
 }
-void get_batch_tuning(double* grid_scale, double* adjoint_tasks) {
+void get_batch_tuning(double* grid_scale, double* adjoint_tasks, int* fused_chunks) {
   *grid_scale = g_batch_grid_scale;
   *adjoint_tasks = g_batch_adjoint_tasks;
+  *fused_chunks = g_batch_fused_chunks;
 }
 
 }  // namespace qbx
@@ -431,37 +492,46 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
   int rc = batch_prepare(P, nodes, density, ws, stream);
   if (rc) return rc;
   const double2* tp = reinterpret_cast<const double2*>(tape);
-  if (!tp) {
-    // recompute the tape (no forward values are written)
-    rc = batch_forward(P, nullptr, wsp<double2>(ws, P.o_tape), ws, stream);
-    if (rc) return rc;
-    tp = wsp<double2>(ws, P.o_tape);
-  }
+  const bool fused = !tp && grad_nodes;   // no tape: one fused pass for both sides
   const long long nG = P.n_G, nC = P.n_ctr, nS = P.n_src;
   auto blocks = [](long long n, int b) { return dim3((unsigned)((n + b - 1) / b)); };
   BatchItemDev* it = wsp<BatchItemDev>(ws, P.o_items);
   hipLaunchKernelGGL(k_make_G_batched, blocks(nG, 256), dim3(256), 0, stream, it,
                      wsp<long long>(ws, P.o_pre_G), P.n, nG, cotangent, wsp<double2>(ws, P.o_G));
-  hipLaunchKernelGGL(k_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
-                     wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr), tp,
-                     wsp<double2>(ws, P.o_G), wsp<double>(ws, P.o_cg));
+  // with a tape, its center sums; without one and only the density gradient
+  // wanted, no center side at all (the chain step then reads no center data)
+  if (tp)
+    hipLaunchKernelGGL(k_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
+                       wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr), tp,
+                       wsp<double2>(ws, P.o_G), wsp<double>(ws, P.o_cg));
   rc = zero_counters(P, ws, stream);
   if (rc) return rc;
   timer_begin(2, stream);
   for (size_t c = 0; c < P.cls.size(); ++c) {
-    const BatchTasks t = class_tasks(P, ws, c, true);
-    hipError_t ea = launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
-                                           wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
-                                           wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
-                                           g_batch_grid_scale, stream);
+    const BatchTasks t = class_tasks(P, ws, c, fused ? 2 : 1);
+    hipError_t ea =
+        fused ? launch_adjoint_fused_batched(P.cls[c].kind, P.cls[c].p, t,
+                                             wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_densw),
+                                             wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
+                                             wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
+                                             wsp<double>(ws, P.o_cpart), g_batch_grid_scale, stream)
+              : launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
+                                       wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
+                                       wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
+                                       g_batch_grid_scale, stream);
     if (ea != hipSuccess) {
       timer_end(2, stream);
       return device_fail(ea, "batched adjoint kernel");
     }
   }
   timer_end(2, stream);
+  if (fused)
+    hipLaunchKernelGGL(k_fused_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
+                       wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr),
+                       wsp<double>(ws, P.o_cpart), wsp<double>(ws, P.o_cg));
   hipLaunchKernelGGL(k_source_finalize_batched, blocks(nS, 256), dim3(256), 0, stream, it,
-                     wsp<long long>(ws, P.o_pre_src), P.n, nS, wsp<double4>(ws, P.o_geo),
+                     wsp<long long>(ws, P.o_pre_src), P.n, nS, fused ? 1 : 0,
+                     wsp<double4>(ws, P.o_geo),
                      wsp<double2>(ws, P.o_densw), wsp<double2>(ws, P.o_spart),
                      wsp<double>(ws, P.o_sg));
   hipLaunchKernelGGL(k_chain_batched, dim3((unsigned)P.n_panels), dim3(128), 0, stream, it,

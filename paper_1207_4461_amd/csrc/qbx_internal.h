@@ -131,9 +131,11 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
                                 double2* G, double* cpart, double* cg, double2* spartial,
                                 double* sg, double* grad_density, double* grad_nodes,
                                 hipStream_t s);
-// centers per fused tile: 48 KB of LDS center sums plus 28 KB for the waves'
-// source sums keep two workgroups per CU
-constexpr int kFusedCenters = 1536;
+// centers per fused tile, by kind: the LDS center sums (32 B a center) plus the
+// waves' source sums (4 x NA x 64 x 16 B) let as many workgroups share a CU as
+// the kernel's registers allow -- S+D (two waves per SIMD): 48 + 28 KB; S or D
+// (three or four): 24 + 12 or 16 KB
+__host__ __device__ constexpr int fused_centers(int kind) { return kind == 3 ? 1536 : 768; }
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,
@@ -150,10 +152,11 @@ hipError_t launch_debug_besselj(const double* x, int n, int L, double* out, hipS
 
 namespace qbx {
 // tunables of the per-contour (qbx_api.cpp) and batched (qbx_batched.hip) paths
-void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves);
-void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves);
-void set_batch_tuning(double grid_scale, double adjoint_tasks);
-void get_batch_tuning(double* grid_scale, double* adjoint_tasks);
+void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves, int fused_tiles);
+void get_contour_tuning(int* forward_waves, int* tape_waves, int* adjoint_waves,
+                        int* fused_tiles);
+void set_batch_tuning(double grid_scale, double adjoint_tasks, int fused_chunks);
+void get_batch_tuning(double* grid_scale, double* adjoint_tasks, int* fused_chunks);
 int validate(const qbx_geometry* g, int p, double k, double r, int oversample, int side,
              int kind, Dims* d);
 }  // namespace qbx

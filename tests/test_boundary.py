@@ -161,8 +161,9 @@ def test_tuning_roundtrip_and_validation(lib):
     t0 = _lib.Tuning()
     assert lib.qbx_get_tuning(C.byref(t0)) == _lib.QBX_OK
     assert t0.forward_waves >= 256 and 0.125 <= t0.batch_grid_scale <= 8
-    t = _lib.Tuning(t0.forward_waves, t0.tape_waves, t0.adjoint_waves, t0.batch_adjoint_tasks,
-                    t0.batch_grid_scale)
+    fields = [f for f, _ in _lib.Tuning._fields_]
+    t = _lib.Tuning(*[getattr(t0, f) for f in fields])
+    assert t0.fused_tiles >= 256 and 1 <= t0.batch_fused_chunks <= 64
     try:
         n_before = lib.qbx_workspace_bytes(256, 16, 8, 4, 1, 1)
         t.forward_waves = 1 << 20          # more source splits -> larger partial buffers
@@ -171,11 +172,17 @@ def test_tuning_roundtrip_and_validation(lib):
         lib.qbx_get_tuning(C.byref(t1))
         assert t1.forward_waves == 1 << 20
         assert lib.qbx_workspace_bytes(256, 16, 8, 4, 1, 1) > n_before
+        t.fused_tiles = 1 << 14
+        t.batch_fused_chunks = 7
+        assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
+        lib.qbx_get_tuning(C.byref(t1))
+        assert (t1.fused_tiles, t1.batch_fused_chunks) == (1 << 14, 7)
         for field, bad in (("forward_waves", 255), ("tape_waves", 1 << 23), ("adjoint_waves", 0),
                            ("batch_adjoint_tasks", -5), ("batch_grid_scale", 0.1),
-                           ("batch_grid_scale", 9.0), ("batch_grid_scale", float("nan"))):
-            tb = _lib.Tuning(t0.forward_waves, t0.tape_waves, t0.adjoint_waves,
-                             t0.batch_adjoint_tasks, t0.batch_grid_scale)
+                           ("batch_grid_scale", 9.0), ("batch_grid_scale", float("nan")),
+                           ("fused_tiles", 100), ("fused_tiles", 1 << 23),
+                           ("batch_fused_chunks", 0), ("batch_fused_chunks", 65)):
+            tb = _lib.Tuning(*[getattr(t0, f) for f in fields])
             setattr(tb, field, bad)
             assert lib.qbx_set_tuning(C.byref(tb)) == _lib.QBX_EINVAL
         assert lib.qbx_set_tuning(None) == _lib.QBX_EINVAL

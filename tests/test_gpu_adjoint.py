@@ -196,3 +196,21 @@ def test_fused_adjoint_is_bitwise_deterministic(Q):
     a = gpu_vjp(Q, pb)
     b = gpu_vjp(Q, pb)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_fused_adjoint_tile_shapes(Q):
+    """The fused pass at the extreme tile targets (one source block per center
+    block, and one 64-source chunk per tile) gives the oracle's gradients."""
+    pb = I.small(n_panels=30, p=8, k=4.0, kind=3, side=0)
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent)
+    before = Q.get_tuning()
+    try:
+        for ft in (256, 1 << 22):
+            Q.set_tuning(fused_tiles=ft)
+            gd, gn = gpu_vjp(Q, pb)
+            ed, en = rel(gd, rd), rel(gn, rn)
+            say(f"  fused_tiles={ft}: grad density {ed:.3e}  grad nodes {en:.3e}")
+            assert ed <= TOL_D and en <= TOL_N
+    finally:
+        Q.set_tuning(**before)

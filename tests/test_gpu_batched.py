@@ -67,8 +67,12 @@ def test_batched_adjoint_matches_per_contour_and_oracle(Q):
     cot = B.pack_out([pb.cotangent for pb in pbs])
     B.forward(with_tape=True)
     gd_t, gn_t = B.adjoint(cot, use_tape=True)
-    gd, gn = B.adjoint(cot, use_tape=False)
-    assert torch.equal(gd, gd_t) and torch.equal(gn, gn_t)
+    gd, gn = B.adjoint(cot, use_tape=False)          # the fused pass
+    gd2, gn2 = B.adjoint(cot, use_tape=False)
+    assert torch.equal(gd, gd2) and torch.equal(gn, gn2)
+    et = (rel(gd.cpu().numpy(), gd_t.cpu().numpy()), rel(gn.cpu().numpy(), gn_t.cpu().numpy()))
+    say(f"  batched fused vs tape: density {et[0]:.2e} nodes {et[1]:.2e}")
+    assert et[0] < 1e-13 and et[1] < 1e-12
     for pb, a, x in zip(pbs, B.split_density(gd), B.split_nodes(gn)):
         rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
                        pb.cotangent)
@@ -82,6 +86,27 @@ def test_batched_adjoint_matches_per_contour_and_oracle(Q):
         assert rel(a, pd.cpu().numpy()) < 1e-12 and rel(x, pn.cpu().numpy()) < 1e-11
 
 
+def test_batched_fused_tile_depths(Q):
+    """The batched fused pass at the extreme tile depths (1 and 64 source chunks
+    per tile) gives the per-contour gradients."""
+    pbs = mixed_batch()
+    B = Q.Batch(pbs, oversample=4)
+    cot = B.pack_out([pb.cotangent for pb in pbs])
+    ref = [Q.layer_potential_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k, pb.p,
+                                 pb.r, pb.oversample, pb.side, pb.kind) for pb in pbs]
+    before = Q.get_tuning()
+    try:
+        for depth in (1, 64):
+            Q.set_tuning(batch_fused_chunks=depth)
+            gd, gn = B.adjoint(cot, use_tape=False)
+            ed = max(rel(a.cpu().numpy(), r[0].cpu().numpy()) for a, r in zip(B.split_density(gd), ref))
+            en = max(rel(x.cpu().numpy(), r[1].cpu().numpy()) for x, r in zip(B.split_nodes(gn), ref))
+            say(f"  depth {depth}: density {ed:.2e} nodes {en:.2e}")
+            assert ed < 1e-12 and en < 1e-11
+    finally:
+        Q.set_tuning(**before)
+
+
 def test_random64_batch_full(Q):
     pbs = I.random64()
     B = Q.Batch(pbs, oversample=4)
@@ -89,16 +114,19 @@ def test_random64_batch_full(Q):
     outs = B.split_out(out)
     cot = B.pack_out([pb.cotangent for pb in pbs])
     gd, gn = B.adjoint(cot, use_tape=True)
+    gdf, gnf = B.adjoint(cot, use_tape=False)        # the fused pass, as timed
     worst_f = worst_d = worst_n = 0.0
     for i, pb in enumerate(pbs):
         u = outs[i].cpu().numpy()
         worst_f = max(worst_f, rel(u, per_contour_forward(Q, pb)))
         pd, pn = Q.layer_potential_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k,
                                        pb.p, pb.r, pb.oversample, pb.side, pb.kind)
-        worst_d = max(worst_d, rel(B.split_density(gd)[i].cpu().numpy(), pd.cpu().numpy()))
-        worst_n = max(worst_n, rel(B.split_nodes(gn)[i].cpu().numpy(), pn.cpu().numpy()))
-    say(f"  random64 batch vs per-contour: forward {worst_f:.2e} grad density {worst_d:.2e} "
-        f"grad nodes {worst_n:.2e}")
+        pd, pn = pd.cpu().numpy(), pn.cpu().numpy()
+        for a, b in ((gd, gn), (gdf, gnf)):
+            worst_d = max(worst_d, rel(B.split_density(a)[i].cpu().numpy(), pd))
+            worst_n = max(worst_n, rel(B.split_nodes(b)[i].cpu().numpy(), pn))
+    say(f"  random64 batch (tape and fused) vs per-contour: forward {worst_f:.2e} "
+        f"grad density {worst_d:.2e} grad nodes {worst_n:.2e}")
     assert worst_f < 1e-13 and worst_d < 1e-12 and worst_n < 1e-11
     # oracle on sampled targets of three contours (smallest, largest, one D)
     order = np.argsort([pb.n_panels for pb in pbs])
@@ -125,6 +153,7 @@ def test_batched_autotune_keeps_results(Q):
         assert Q.get_tuning() == tuned
         assert tuned["batch_adjoint_tasks"] in [2048 << i for i in range(8)]
         assert tuned["batch_grid_scale"] in (0.5, 1.0, 2.0, 4.0)
+        assert tuned["batch_fused_chunks"] in (1, 2, 4, 8)
         outs = [o.cpu().numpy() for o in B.split_out(B.forward(with_tape=True))]
         cot = B.pack_out([pb.cotangent for pb in pbs])
         gd, gn = B.adjoint(cot, use_tape=True)
