@@ -92,21 +92,19 @@ __global__ __launch_bounds__(256) void k_center_grads(int Mc, int nk, int side, 
 
 // ---------------------------------------------------------------------------
 // source-major adjoint pass: one wave per (64 sources, center split), loop over
-// centers; partial layout [n_csplit][NA][N] complex with
-//   S: 0 = sum conj(G K), 1,2 = sum G (K_rho v^ + K_theta' theta^/rho)
-//   D: +0 = sum conj(G K), +1,+2 = as above, +3 = sum G K_psi
+// centers; partial layout [n_csplit][src_slots(KIND)][N] (see src_slots)
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
-__global__ __launch_bounds__(256) void k_adjoint_src(const double4* __restrict__ geo, int N,
+__global__ __launch_bounds__(256) void k_adjoint_src(const double4* __restrict__ geo,
+                                                     const double2* __restrict__ dens, int N,
                                                      const CenterRec* __restrict__ ctr,
                                                      const double* __restrict__ jtab, int NJ,
                                                      const double2* __restrict__ G, int Mc,
                                                      int n_csplit, int centers_per_split,
                                                      int chunks, double k,
                                                      double2* __restrict__ partial) {
-  constexpr bool kS = (KIND & 1) != 0;
-  constexpr bool kD = (KIND & 2) != 0;
-  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
+  constexpr int NA = src_slots(KIND);
+  constexpr int NK = KIND == 3 ? 2 : 1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * 4 + wave;
@@ -118,8 +116,11 @@ __global__ __launch_bounds__(256) void k_adjoint_src(const double4* __restrict__
   const double4 g = geo[j];
   const int i0 = cs * centers_per_split;
   const int i1 = min(i0 + centers_per_split, Mc);
+  double2 q[2];
+  q[0] = dens[j];
+  q[1] = dens[(size_t)(NK - 1) * N + j];
   Cplx A[NA];
-  adjoint_source<P, KIND>(g, ctr, jtab, NJ, G, Mc, i0, i1, k, A);
+  adjoint_source<P, KIND>(g, q, ctr, jtab, NJ, G, Mc, i0, i1, k, A);
 #pragma unroll
   for (int b = 0; b < NA; ++b)
     partial[((size_t)cs * NA + b) * N + j] = make_double2(A[b].r, A[b].i);
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_adjoint_fused(
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ,
     const double2* __restrict__ G, int Mc, int cblock, int n_sb, int chunks,
     int chunks_per_sb, double k, double2* __restrict__ spart, double* __restrict__ cpart) {
-  constexpr int NA = ((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0);
+  constexpr int NA = src_slots(KIND);
   __shared__ double acc[fused_centers(KIND) * 4];
   __shared__ double2 xsrc[4][NA][kWave];
   const int cb = blockIdx.x / n_sb;
@@ -165,13 +166,12 @@ __global__ __launch_bounds__(256) void k_fused_center_grads(int Mc, int n_sb, in
 }
 
 // per source: sg[j] = {grad(w sigma) re, im, grad(w mu) re, im, g_x', g_y', g_nx, g_ny}
-__global__ __launch_bounds__(256) void k_source_finalize(int N, int nk, int kind, int n_csplit,
+__global__ __launch_bounds__(256) void k_source_finalize(int N, int kind, int n_csplit,
                                                          const double4* __restrict__ geo,
-                                                         const double2* __restrict__ dens,
                                                          const double2* __restrict__ partial,
                                                          double* __restrict__ sg) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < N) source_finalize_elem(j, N, nk, kind, n_csplit, geo, dens, partial, sg);
+  if (j < N) source_finalize_elem(j, N, kind, n_csplit, geo, partial, sg);
 }
 
 __global__ __launch_bounds__(128) void k_chain(Dims d, const double* __restrict__ nodes,
@@ -207,14 +207,14 @@ static hipError_t launch_forward_tape_p(const Dims& d, const double4* geo, const
 }
 
 template <int P>
-static hipError_t launch_adjoint_src_p(const Dims& d, const double4* geo, const CenterRec* ctr,
-                                       const double* jtab, const double2* G, double2* partial,
-                                       hipStream_t s) {
+static hipError_t launch_adjoint_src_p(const Dims& d, const double4* geo, const double2* dens,
+                                       const CenterRec* ctr, const double* jtab, const double2* G,
+                                       double2* partial, hipStream_t s) {
   const long waves = (long)d.chunks * d.n_csplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-#define QBX_LAUNCH(KD)                                                                             \
-  hipLaunchKernelGGL((k_adjoint_src<P, KD>), grid, block, 0, s, geo, d.N, ctr, jtab, d.NJ, G, d.Mc, \
-                     d.n_csplit, d.centers_per_split, d.chunks, d.k, partial)
+#define QBX_LAUNCH(KD)                                                                       \
+  hipLaunchKernelGGL((k_adjoint_src<P, KD>), grid, block, 0, s, geo, dens, d.N, ctr, jtab,    \
+                     d.NJ, G, d.Mc, d.n_csplit, d.centers_per_split, d.chunks, d.k, partial)
   if (d.kind == 1)
     QBX_LAUNCH(1);
   else if (d.kind == 2)
@@ -231,10 +231,10 @@ hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2*
   QBX_P_SWITCH(d.p, launch_forward_tape_p, d, geo, dens, ctr, jtab, partial, s)
 }
 
-hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const CenterRec* ctr,
-                              const double* jtab, const double2* G, double2* partial,
-                              hipStream_t s) {
-  QBX_P_SWITCH(d.p, launch_adjoint_src_p, d, geo, ctr, jtab, G, partial, s)
+hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const double2* dens,
+                              const CenterRec* ctr, const double* jtab, const double2* G,
+                              double2* partial, hipStream_t s) {
+  QBX_P_SWITCH(d.p, launch_adjoint_src_p, d, geo, dens, ctr, jtab, G, partial, s)
 }
 
 hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
@@ -292,8 +292,8 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fused_center_grads, dim3((d.Mc + 255) / 256), dim3(256), 0, s, d.Mc,
                      d.n_sb, d.side, d.T, ctr, cpart, cg);
-  hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.nk, d.kind,
-                     d.n_cb, geo, dens, spartial, sg);
+  hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.kind,
+                     d.n_cb, geo, spartial, sg);
   hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
                      grad_density, grad_nodes);
   return hipGetLastError();
@@ -319,11 +319,11 @@ hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double*
     hipLaunchKernelGGL(k_center_grads, dim3((d.Mc + 255) / 256), dim3(256), 0, s, d.Mc, d.nk,
                        d.side, d.T, ctr, tape, G, cg);
   timer_begin(1, s);
-  hipError_t e = launch_adjoint_src(d, geo, ctr, jtab, G, spartial, s);
+  hipError_t e = launch_adjoint_src(d, geo, dens, ctr, jtab, G, spartial, s);
   timer_end(1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.nk, d.kind,
-                     d.n_csplit, geo, dens, spartial, sg);
+  hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.kind,
+                     d.n_csplit, geo, spartial, sg);
   hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
                      grad_density, grad_nodes);
   return hipGetLastError();

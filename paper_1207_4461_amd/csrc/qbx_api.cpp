@@ -146,8 +146,7 @@ Layout make_layout(const Dims& d) {
   L.tape = take(sizeof(double2) * (size_t)d.Mc * d.nk * 4);
   L.G = take(sizeof(double2) * (size_t)d.nk * d.Mc);
   L.cg = take(sizeof(double) * (size_t)d.Mc * 8);
-  const int NA = (d.kind & 1 ? 3 : 0) + (d.kind & 2 ? 4 : 0);
-  L.spart = take(sizeof(double2) * (size_t)std::max(d.n_csplit, d.n_cb) * NA * d.N);
+  L.spart = take(sizeof(double2) * (size_t)std::max(d.n_csplit, d.n_cb) * src_slots(d.kind) * d.N);
   L.cpart = take(sizeof(double) * (size_t)d.n_sb * d.Mc * 4);
   L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));

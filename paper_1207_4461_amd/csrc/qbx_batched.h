@@ -106,23 +106,28 @@ __device__ __forceinline__ void forward_task(const BatchItemDev& B, int ci, int 
 template <int P, int KIND>
 __device__ __forceinline__ void adjoint_task(const BatchItemDev& B, int task, int lane,
                                              const double4* __restrict__ geo,
+                                             const double2* __restrict__ densw,
                                              const CenterRec* __restrict__ ctr,
                                              const double* __restrict__ jtab,
                                              const double2* __restrict__ G,
                                              double2* __restrict__ spart) {
-  constexpr int NA = ((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0);
+  constexpr int NA = src_slots(KIND);
+  constexpr int NK = KIND == 3 ? 2 : 1;
   const Dims& d = B.d;
   const int sp = task / d.chunks;
   const int j = (task - sp * d.chunks) * kWave + lane;
   if (j >= d.N) return;
   const int c0 = sp * d.centers_per_split;
   const int c1 = min(c0 + d.centers_per_split, d.Mc);
+  double2 q[2];
+  q[0] = densw[B.densw_off + j];
+  q[1] = densw[B.densw_off + (size_t)(NK - 1) * d.N + j];
   Cplx A[NA];
-  adjoint_source<P, KIND>(geo[B.src_off + j], ctr + B.ctr_off, jtab + B.jtab_off, d.NJ,
+  adjoint_source<P, KIND>(geo[B.src_off + j], q, ctr + B.ctr_off, jtab + B.jtab_off, d.NJ,
                           G + B.G_off, d.Mc, c0, c1, d.k, A);
-  double2* q = spart + B.spart_off + (size_t)sp * NA * d.N;
+  double2* out = spart + B.spart_off + (size_t)sp * NA * d.N;
 #pragma unroll
-  for (int b = 0; b < NA; ++b) q[(size_t)b * d.N + j] = make_double2(A[b].r, A[b].i);
+  for (int b = 0; b < NA; ++b) out[(size_t)b * d.N + j] = make_double2(A[b].r, A[b].i);
 }
 
 // launchers of the persistent kernels of one (kind, p) class (one translation
@@ -132,8 +137,9 @@ hipError_t launch_forward_batched(int mode, int kind, int p, const BatchTasks& t
                                   const double* jtab, double* out, double2* tape, double grid_scale,
                                   hipStream_t s);
 hipError_t launch_adjoint_batched(int kind, int p, const BatchTasks& t, const double4* geo,
-                                  const CenterRec* ctr, const double* jtab, const double2* G,
-                                  double2* spart, double grid_scale, hipStream_t s);
+                                  const double2* densw, const CenterRec* ctr, const double* jtab,
+                                  const double2* G, double2* spart, double grid_scale,
+                                  hipStream_t s);
 // fused adjoint (no tape): persistent workgroups over (contour, center block,
 // source block) tiles of one (kind, p) class
 hipError_t launch_adjoint_fused_batched(int kind, int p, const BatchTasks& t, const double4* geo,

@@ -187,9 +187,8 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
   }
   for (int i = 0; i < n; ++i) {
     BatchItemDev& B = P->items[i];
-    const int NA = (B.d.kind & 1 ? 3 : 0) + (B.d.kind & 2 ? 4 : 0);
     B.spart_off = P->n_spart;
-    P->n_spart += (long long)std::max(B.d.n_csplit, B.d.n_cb) * NA * B.d.N;
+    P->n_spart += (long long)std::max(B.d.n_csplit, B.d.n_cb) * src_slots(B.d.kind) * B.d.N;
     B.cpart_off = P->n_cpart;
     P->n_cpart += (long long)B.d.n_sb * B.d.Mc * 4;
   }
@@ -306,16 +305,16 @@ __global__ __launch_bounds__(256) void k_fused_center_grads_batched(
 
 __global__ __launch_bounds__(256) void k_source_finalize_batched(
     const BatchItemDev* __restrict__ items, const long long* __restrict__ pre_src, int n,
-    long long total, int fused, const double4* __restrict__ geo, const double2* __restrict__ densw,
+    long long total, int fused, const double4* __restrict__ geo,
     const double2* __restrict__ spart, double* __restrict__ sg) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int it = find_slot(pre_src, n, e);
   const BatchItemDev& B = items[it];
   // the source sums come in n_cb parts from the fused pass, n_csplit otherwise
-  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.nk, B.d.kind,
-                       fused ? B.d.n_cb : B.d.n_csplit, geo + B.src_off,
-                       densw + B.densw_off, spart + B.spart_off, sg + B.src_off * 8);
+  source_finalize_elem((int)(e - pre_src[it]), B.d.N, B.d.kind,
+                       fused ? B.d.n_cb : B.d.n_csplit, geo + B.src_off, spart + B.spart_off,
+                       sg + B.src_off * 8);
 }
 
 __global__ __launch_bounds__(128) void k_chain_batched(
@@ -516,6 +515,7 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
                                              wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
                                              wsp<double>(ws, P.o_cpart), g_batch_grid_scale, stream)
               : launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
+                                       wsp<double2>(ws, P.o_densw),
                                        wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
                                        wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
                                        g_batch_grid_scale, stream);
@@ -531,8 +531,7 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
                        wsp<double>(ws, P.o_cpart), wsp<double>(ws, P.o_cg));
   hipLaunchKernelGGL(k_source_finalize_batched, blocks(nS, 256), dim3(256), 0, stream, it,
                      wsp<long long>(ws, P.o_pre_src), P.n, nS, fused ? 1 : 0,
-                     wsp<double4>(ws, P.o_geo),
-                     wsp<double2>(ws, P.o_densw), wsp<double2>(ws, P.o_spart),
+                     wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_spart),
                      wsp<double>(ws, P.o_sg));
   hipLaunchKernelGGL(k_chain_batched, dim3((unsigned)P.n_panels), dim3(128), 0, stream, it,
                      wsp<long long>(ws, P.o_pre_panel), P.n, nodes, density,

@@ -7,6 +7,7 @@ namespace qbx {
 template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_adjoint_batched(BatchTasks t,
                                                          const double4* __restrict__ geo,
+                                                         const double2* __restrict__ densw,
                                                          const CenterRec* __restrict__ ctr,
                                                          const double* __restrict__ jtab,
                                                          const double2* __restrict__ G,
@@ -22,21 +23,21 @@ __global__ __launch_bounds__(256) void k_adjoint_batched(BatchTasks t,
     if (task >= t.n_tasks) break;   // every wave leaves once the counter passes the end
     const int slot = find_slot(t.pre, t.n, task);
     const BatchItemDev& B = t.items[t.order[slot]];
-    adjoint_task<P, KIND>(B, (int)(task - t.pre[slot]), lane, geo, ctr, jtab, G, spart);
+    adjoint_task<P, KIND>(B, (int)(task - t.pre[slot]), lane, geo, densw, ctr, jtab, G, spart);
   }
 }
 
 template <int P>
 static hipError_t launch_p(int kind, const BatchTasks& t, const double4* geo,
-                           const CenterRec* ctr, const double* jtab, const double2* G,
-                           double2* spart, double grid_scale, hipStream_t s) {
+                           const double2* densw, const CenterRec* ctr, const double* jtab,
+                           const double2* G, double2* spart, double grid_scale, hipStream_t s) {
   static int per_cu[4] = {0, 0, 0, 0};
 #define QBX_LAUNCH(KD)                                                                        \
   {                                                                                           \
     const unsigned g = persistent_grid(k_adjoint_batched<P, KD>, &per_cu[KD], 256, t.n_tasks, \
                                        grid_scale);                                           \
-    hipLaunchKernelGGL((k_adjoint_batched<P, KD>), dim3(g), dim3(256), 0, s, t, geo, ctr, jtab, \
-                       G, spart);                                                             \
+    hipLaunchKernelGGL((k_adjoint_batched<P, KD>), dim3(g), dim3(256), 0, s, t, geo, densw,   \
+                       ctr, jtab, G, spart);                                                  \
   }
   if (kind == 1)
     QBX_LAUNCH(1)
@@ -49,9 +50,10 @@ static hipError_t launch_p(int kind, const BatchTasks& t, const double4* geo,
 }
 
 hipError_t launch_adjoint_batched(int kind, int p, const BatchTasks& t, const double4* geo,
-                                  const CenterRec* ctr, const double* jtab, const double2* G,
-                                  double2* spart, double grid_scale, hipStream_t s) {
-  QBX_P_SWITCH(p, launch_p, kind, t, geo, ctr, jtab, G, spart, grid_scale, s)
+                                  const double2* densw, const CenterRec* ctr, const double* jtab,
+                                  const double2* G, double2* spart, double grid_scale,
+                                  hipStream_t s) {
+  QBX_P_SWITCH(p, launch_p, kind, t, geo, densw, ctr, jtab, G, spart, grid_scale, s)
 }
 
 }  // namespace qbx

@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void k_adjoint_fused_batched(BatchTasks t,
                                                                const double2* __restrict__ G,
                                                                double2* __restrict__ spart,
                                                                double* __restrict__ cpart) {
-  constexpr int NA = ((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0);
+  constexpr int NA = src_slots(KIND);
   __shared__ double acc[fused_centers(KIND) * 4];
   __shared__ double2 xsrc[4][NA][kWave];
   __shared__ long long s_task;

@@ -59,67 +59,52 @@ __global__ __launch_bounds__(256) void k_explicit_centers(int Mc, int NJ, double
   center_bessel_table(k * c.R, NJ / 2, jtab + (size_t)i * NJ);
 }
 
-// per source, from the source-major partial sums (layout of the adjoint pass:
-// S: conj(sum G K), sum G dK/dv_x, sum G dK/dv_y; D: the same and sum G dK/dpsi):
+// per source, from the source-major partial sums (the src_slots layout):
 //   grad_q[kind][j]  = sum_i conj(G_i K_ij)                      (complex)
-//   grad_src_xy[j]   = Re q_j sum_i G_i grad_v K_ij, summed over kinds
-//   grad_src_nu[j]   = Re q_j sum_i G_i dK_ij/d(n_x, n_y)  (D)
+//   grad_src_xy[j]   = sum_i Re G_i q_j grad_v K_ij, over the kinds
+//   grad_src_nu[j]   = sum_i Re G_i q_j dK_ij/d(n_x, n_y)  (D)
 // K_D is linear in the normal: K = cps a + sps b with (cps, sps) the normal in
 // the frame of the target direction, so dK/dn = (K n_x + K_psi n_y,
 // K n_y - K_psi n_x) / |n|^2 with K_psi = dK/dpsi; n is per source, so the
 // factor comes out of the sum over centers.
 __global__ __launch_bounds__(256) void k_explicit_source_grads(
-    int N, int nk, int kind, int n_csplit, const double4* __restrict__ geo,
+    int N, int kind, int n_csplit, const double4* __restrict__ geo,
     const double2* __restrict__ dens, const double2* __restrict__ partial,
     double* __restrict__ grad_q, double* __restrict__ grad_src_xy,
     double* __restrict__ grad_src_nu) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   const bool hasS = kind & 1, hasD = kind & 2;
-  const int NA = (hasS ? 3 : 0) + (hasD ? 4 : 0);
-  double s[7][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  const int nk = hasS && hasD ? 2 : 1;
+  const int NA = src_slots(kind);
+  double s[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   for (int cs = 0; cs < n_csplit; ++cs)
     for (int b = 0; b < NA; ++b) {
       const double2 v = partial[((size_t)cs * NA + b) * N + j];
       s[b][0] += v.x;
       s[b][1] += v.y;
     }
-  double gx = 0.0, gy = 0.0;
-  int a = 0, kk = 0;
-  if (hasS) {
-    const double2 w = dens[j];
-    if (grad_q) {
-      grad_q[2 * (size_t)j] = s[0][0];
-      grad_q[2 * (size_t)j + 1] = s[0][1];
-    }
-    gx += w.x * s[1][0] - w.y * s[1][1];
-    gy += w.x * s[2][0] - w.y * s[2][1];
-    a = 3;
-    kk = 1;
-  }
-  if (hasD) {
-    const double2 w = dens[(size_t)kk * N + j];
-    if (grad_q) {
+  if (grad_q) {
+    for (int kk = 0; kk < nk; ++kk) {
       const size_t o = (size_t)kk * N + j;
-      grad_q[2 * o] = s[a][0];
-      grad_q[2 * o + 1] = s[a][1];
+      grad_q[2 * o] = s[kk][0];
+      grad_q[2 * o + 1] = s[kk][1];
     }
-    gx += w.x * s[a + 1][0] - w.y * s[a + 1][1];
-    gy += w.x * s[a + 2][0] - w.y * s[a + 2][1];
-    if (grad_src_nu) {
-      // s[a] = conj(sum G K): Re(q sum G K) = Re(q conj(s[a]))
-      const double A = w.x * s[a][0] + w.y * s[a][1];
-      const double B = w.x * s[a + 3][0] - w.y * s[a + 3][1];
-      const double4 g = geo[j];
-      const double n2 = fma(g.z, g.z, g.w * g.w);
-      const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
-      grad_src_nu[2 * (size_t)j] = fma(g.z, A, g.w * B) * inv;
-      grad_src_nu[2 * (size_t)j + 1] = fma(g.w, A, -g.z * B) * inv;
-    }
+  }
+  if (hasD && grad_src_nu) {
+    // s[nk - 1] = conj(sum G K): Re(q sum G K) = Re(q conj(s[nk - 1]))
+    const double2 w = dens[(size_t)(nk - 1) * N + j];
+    const double A = w.x * s[nk - 1][0] + w.y * s[nk - 1][1];
+    const double B = s[nk + 1][0];
+    const double4 g = geo[j];
+    const double n2 = fma(g.z, g.z, g.w * g.w);
+    const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
+    grad_src_nu[2 * (size_t)j] = fma(g.z, A, g.w * B) * inv;
+    grad_src_nu[2 * (size_t)j + 1] = fma(g.w, A, -g.z * B) * inv;
   }
   if (grad_src_xy) {
-    grad_src_xy[2 * (size_t)j] = gx;
-    grad_src_xy[2 * (size_t)j + 1] = gy;
+    grad_src_xy[2 * (size_t)j] = s[nk][0];
+    grad_src_xy[2 * (size_t)j + 1] = s[nk][1];
   }
 }
 
@@ -304,13 +289,13 @@ int qbx_apply_explicit_adjoint(int n_src, const double* src_xy, const double* sr
   }
   if (want_src) {
     timer_begin(1, stream);
-    e = launch_adjoint_src(d, at<double4>(ws, L.geo), at<CenterRec>(ws, L.ctr),
-                           at<double>(ws, L.jtab), at<double2>(ws, L.G),
-                           at<double2>(ws, L.spart), stream);
+    e = launch_adjoint_src(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                           at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                           at<double2>(ws, L.G), at<double2>(ws, L.spart), stream);
     timer_end(1, stream);
     if (e != hipSuccess) return device_fail(e, "explicit adjoint source pass");
     hipLaunchKernelGGL(k_explicit_source_grads, dim3((d.N + 255) / 256), dim3(256), 0, stream,
-                       d.N, d.nk, d.kind, d.n_csplit, at<double4>(ws, L.geo),
+                       d.N, d.kind, d.n_csplit, at<double4>(ws, L.geo),
                        at<double2>(ws, L.dens), at<double2>(ws, L.spart), grad_q, grad_src_xy,
                        grad_src_nu);
     e = hipGetLastError();

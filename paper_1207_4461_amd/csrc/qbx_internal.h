@@ -63,7 +63,7 @@ struct Layout {
   size_t tape;     // double2[Mc][nk][4] tape recomputed by the adjoint when none is given
   size_t G;        // double2[nk][Mc] conj(cotangent) i/4
   size_t cg;       // double[Mc][8] per-center gradients
-  size_t spart;    // double2[max(n_csplit, n_cb)][NA][N] source-pass partial sums
+  size_t spart;    // double2[max(n_csplit, n_cb)][src_slots(kind)][N] source-side partial sums
   size_t cpart;    // double[n_sb][Mc][4] fused adjoint: center-side partial sums
   size_t sg;       // double[N][8] per-source gradients
   size_t scratch;  // double[16 + Mc] small reductions
@@ -120,9 +120,9 @@ hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2*
                                hipStream_t s);
 hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
                                 hipStream_t s);
-hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const CenterRec* ctr,
-                              const double* jtab, const double2* G, double2* partial,
-                              hipStream_t s);
+hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const double2* dens,
+                              const CenterRec* ctr, const double* jtab, const double2* G,
+                              double2* partial, hipStream_t s);
 hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s);
 // adjoint without a tape: one pass over the pairs for both gradient sides
 hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double* density,
@@ -131,11 +131,25 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
                                 double2* G, double* cpart, double* cg, double2* spartial,
                                 double* sg, double* grad_density, double* grad_nodes,
                                 hipStream_t s);
+// double2 slots per source of the adjoint's source-side partial sums:
+//   0 .. nk-1    sum_i conj(G_i K_ij), one per kind (the density gradients)
+//   nk           sum_i Re(G_i q_j grad_v K_ij), both components, over the kinds
+//   nk + 1 (D)   (sum_i Re(G_i q_j dK_ij/dpsi), 0)
+__host__ __device__ constexpr int src_slots(int kind) {
+  return (kind == 3 ? 2 : 1) + 1 + ((kind & 2) ? 1 : 0);
+}
 // centers per fused tile, by kind: the LDS center sums (32 B a center) plus the
-// waves' source sums (4 x NA x 64 x 16 B) let as many workgroups share a CU as
-// the kernel's registers allow -- S+D (two waves per SIMD): 48 + 28 KB; S or D
-// (three or four): 24 + 12 or 16 KB
-__host__ __device__ constexpr int fused_centers(int kind) { return kind == 3 ? 1536 : 768; }
+// waves' source sums (4 x slots x 64 x 16 B) must let as many workgroups share
+// a CU (160 KB of LDS) as the kernel's registers allow
+#ifndef QBX_FUSED_CENTERS_SD
+#define QBX_FUSED_CENTERS_SD 1024
+#endif
+#ifndef QBX_FUSED_CENTERS_1
+#define QBX_FUSED_CENTERS_1 768
+#endif
+__host__ __device__ constexpr int fused_centers(int kind) {
+  return kind == 3 ? QBX_FUSED_CENTERS_SD : QBX_FUSED_CENTERS_1;
+}
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

@@ -82,6 +82,7 @@ namespace qbx {
 // Empty asm that takes the values as in/out operands: every order's recurrence
 // state and running sums must be final at this point, so the compiler cannot
 // run whole recurrence chains ahead and keep all orders live at once.
+#define QBX_PIN1(a) asm volatile("" : "+v"(a))
 #define QBX_PIN2(a, b) asm volatile("" : "+v"(a), "+v"(b))
 #define QBX_PIN4(a, b, c, d) asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d))
 
@@ -94,22 +95,21 @@ __device__ __forceinline__ void cmac(Cplx& acc, double f, double hr, double hi) 
   acc.i = fma(f, hi, acc.i);
 }
 
-// per-pair sums (complex): which ones are formed depends on MODE
-//   MODE 0 (tape, center-major): K, K_R, K_theta, K_rho, K_theta'
-//   MODE 1 (source-major):       K, K_rho, K_theta', K_psi (D)
+// per-pair sums of the forward with tape (complex; the cotangent is not known
+// yet): K, K_R, K_theta, K_rho, K_theta'
 struct PairOut {
-  Cplx Ks, KRs, Kts, Krs, Ktps;          // single layer
-  Cplx Kd, KRd, Ktd, Krd, Ktpd, Kpsid;   // double layer
+  Cplx Ks, KRs, Kts, Krs, Ktps;   // single layer
+  Cplx Kd, KRd, Ktd, Krd, Ktpd;   // double layer
 };
 
-template <int P, int KIND, int MODE>
+template <int P, int KIND>
 __device__ __forceinline__ PairOut pair_sums(double z, double iz, double cd, double sd, double cps,
                                              double sps, double k, const double* __restrict__ J,
                                              const double* __restrict__ Jd,
                                              const double* __restrict__ cf) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
-  constexpr bool kTape = MODE == 0;
+  constexpr bool kTape = true;
   constexpr int LMAX = kD ? P + 1 : P;
   const H01 h = hankel01(z, iz, cf);
   double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
@@ -118,7 +118,7 @@ __device__ __forceinline__ PairOut pair_sums(double z, double iz, double cd, dou
   double tl = tz;
   const double two_cd = 2.0 * cd;
   Cplx sK = {0, 0}, sKR = {0, 0}, sKt = {0, 0}, sKr = {0, 0};
-  Cplx dK = {0, 0}, dKR = {0, 0}, dKt = {0, 0}, dKr = {0, 0}, dKtp = {0, 0}, dKpsi = {0, 0};
+  Cplx dK = {0, 0}, dKR = {0, 0}, dKt = {0, 0}, dKr = {0, 0}, dKtp = {0, 0};
   double c_m = 1.0, c_c = cd, s_m = 0.0, s_c = sd;           // cos, sin of l Delta
   double a_m = cps, a_c = fma(cd, cps, -sd * sps);             // cos(l D + psi)
   double b_m = cps, b_c = fma(cd, cps, sd * sps);              // cos(l D - psi)
@@ -147,14 +147,10 @@ QBX_UNROLL_BY(QBX_SUMS_UNROLL)
       const double sA = up ? J[l + 1] * sa_c : 0.0;
       const double sB = J[l - 1] * sb_c;
       cmac(dKtp, (double)l * (sA - sB), hc_r, hc_i);
-      if (kTape) {
-        const double fbR = Jd[l - 1] * b_c;
-        const double fR = up ? fma(Jd[l + 1], a_c, -fbR) : -fbR;
-        cmac(dKR, fR, hc_r, hc_i);
-        cmac(dKt, fma((double)(l - 1), sB, -(double)(l + 1) * sA), hc_r, hc_i);
-      } else {
-        cmac(dKpsi, -(sA + sB), hc_r, hc_i);
-      }
+      const double fbR = Jd[l - 1] * b_c;
+      const double fR = up ? fma(Jd[l + 1], a_c, -fbR) : -fbR;
+      cmac(dKR, fR, hc_r, hc_i);
+      cmac(dKt, fma((double)(l - 1), sB, -(double)(l + 1) * sA), hc_r, hc_i);
     }
     hm_r = hc_r;
     hm_i = hc_i;
@@ -188,8 +184,7 @@ QBX_UNROLL_BY(QBX_SUMS_UNROLL)
       QBX_PIN4(sa_m, sa_c, sb_m, sb_c);
       QBX_PIN4(dK.r, dK.i, dKr.r, dKr.i);
       QBX_PIN2(dKtp.r, dKtp.i);
-      if (kTape) QBX_PIN4(dKR.r, dKR.i, dKt.r, dKt.i);
-      else QBX_PIN2(dKpsi.r, dKpsi.i);
+      QBX_PIN4(dKR.r, dKR.i, dKt.r, dKt.i);
     }
   }
   PairOut o;
@@ -207,13 +202,146 @@ QBX_UNROLL_BY(QBX_SUMS_UNROLL)
     o.Kd = {k * fma(f0, H0r, dK.r), k * fma(f0, H0i, dK.i)};
     o.Krd = {k * k * fma(-f0, H1r, 0.5 * dKr.r), k * k * fma(-f0, H1i, 0.5 * dKr.i)};
     o.Ktpd = {k * dKtp.r, k * dKtp.i};
-    if (kTape) {
-      const double fR0 = P >= 1 ? Jd[1] * cps : 0.0;
-      o.KRd = {k * k * fma(fR0, H0r, dKR.r), k * k * fma(fR0, H0i, dKR.i)};
-      o.Ktd = {k * fma(-g0, H0r, dKt.r), k * fma(-g0, H0i, dKt.i)};
-    } else {
-      o.Kpsid = {k * fma(-g0, H0r, dKpsi.r), k * fma(-g0, H0i, dKpsi.i)};
+    const double fR0 = P >= 1 ? Jd[1] * cps : 0.0;
+    o.KRd = {k * k * fma(fR0, H0r, dKR.r), k * k * fma(fR0, H0i, dKR.i)};
+    o.Ktd = {k * fma(-g0, H0r, dKt.r), k * fma(-g0, H0i, dKt.i)};
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// per-pair sums of the adjoint once the cotangent is known.  Every gradient
+// but the density's uses a derivative sum X only through Re(w X), w = G_i q_j
+// (one weight per kind), and Re(w H_l) obeys the Hankel recurrence itself (its
+// coefficients are real).  So the derivative sums run over the real sequences
+// Re(w_S H_l), Re(w_D H_l) -- one multiply-add per order instead of two -- and
+// only K, which the density gradient needs whole, uses the complex H_l.
+//   kFused = false (source-major pass): K, Re w K_rho, Re w K_theta', Re w K_psi
+//   kFused = true  (fused pass):        also Re w K_R; then K_theta = -K_theta'
+//                                       (S) and K_psi - K_theta' (D)
+// ---------------------------------------------------------------------------
+struct ProjOut {
+  Cplx Ks, Kd;
+  double rs, ts, Rs;          // S: Re w K_rho, Re w K_theta', Re w K_R
+  double rd, td, psid, Rd;    // D: Re w K_rho, Re w K_theta', Re w K_psi, Re w K_R
+};
+
+template <int P, int KIND, bool kFused>
+__device__ __forceinline__ ProjOut pair_sums_proj(double z, double iz, double cd, double sd,
+                                                  double cps, double sps, double k,
+                                                  const double* __restrict__ J,
+                                                  const double* __restrict__ Jd,
+                                                  const double* __restrict__ cf, double2 wS,
+                                                  double2 wD) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int LMAX = kD ? P + 1 : P;
+  const H01 h = hankel01(z, iz, cf);
+  double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
+  double hc_r = h.h1r, hc_i = h.h1i;  // H_l
+  // Re(w H_0), Re(w H_1) per kind
+  const double ps0 = kS ? fma(wS.x, h.h0r, -wS.y * h.h0i) : 0.0;
+  const double ps1 = kS ? fma(wS.x, h.h1r, -wS.y * h.h1i) : 0.0;
+  const double pd0 = kD ? fma(wD.x, h.h0r, -wD.y * h.h0i) : 0.0;
+  const double pd1 = kD ? fma(wD.x, h.h1r, -wD.y * h.h1i) : 0.0;
+  double sm = ps0, sc = ps1;          // Re(w_S H_{l-1}), Re(w_S H_l)
+  double dm = pd0, dc = pd1;          // Re(w_D H_{l-1}), Re(w_D H_l)
+  const double tz = 2.0 * iz;
+  double tl = tz;
+  const double two_cd = 2.0 * cd;
+  Cplx sK = {0, 0}, dK = {0, 0};
+  double sKr = 0, sKt = 0, sKR = 0, dKr = 0, dKtp = 0, dKq = 0, dKR = 0;
+  double c_m = 1.0, c_c = cd, s_m = 0.0, s_c = sd;           // cos, sin of l Delta
+  double a_m = cps, a_c = fma(cd, cps, -sd * sps);             // cos(l D + psi)
+  double b_m = cps, b_c = fma(cd, cps, sd * sps);              // cos(l D - psi)
+  double sa_m = sps, sa_c = fma(sd, cps, cd * sps);            // sin(l D + psi)
+  double sb_m = -sps, sb_c = fma(sd, cps, -cd * sps);          // sin(l D - psi)
+QBX_UNROLL_BY(QBX_SUMS_UNROLL)
+  for (int l = 1; l <= LMAX; ++l) {
+    const double hn_r = fma(tl, hc_r, -hm_r);
+    const double hn_i = fma(tl, hc_i, -hm_i);
+    const double sn = kS ? fma(tl, sc, -sm) : 0.0;
+    const double dn = kD ? fma(tl, dc, -dm) : 0.0;
+    if (kS && l <= P) {
+      const double f = J[l] * c_c;
+      cmac(sK, f, hc_r, hc_i);
+      sKr = fma(f, sm - sn, sKr);                    // 2 H_l' = H_{l-1} - H_{l+1}
+      sKt = fma((double)l * J[l] * s_c, sc, sKt);
+      if (kFused) sKR = fma(Jd[l] * c_c, sc, sKR);
     }
+    if (kD) {
+      const bool up = l <= P - 1;
+      const double fb = J[l - 1] * b_c;
+      const double f = up ? fma(J[l + 1], a_c, -fb) : -fb;
+      cmac(dK, f, hc_r, hc_i);
+      dKr = fma(f, dm - dn, dKr);
+      const double sA = up ? J[l + 1] * sa_c : 0.0;
+      const double sB = J[l - 1] * sb_c;
+      dKtp = fma((double)l * (sA - sB), dc, dKtp);
+      dKq = fma(sA + sB, dc, dKq);
+      if (kFused) {
+        const double fbR = Jd[l - 1] * b_c;
+        const double fR = up ? fma(Jd[l + 1], a_c, -fbR) : -fbR;
+        dKR = fma(fR, dc, dKR);
+      }
+    }
+    hm_r = hc_r;
+    hm_i = hc_i;
+    hc_r = hn_r;
+    hc_i = hn_i;
+    sm = sc;
+    sc = sn;
+    dm = dc;
+    dc = dn;
+    tl += tz;
+    if (kS) {
+      const double cn = fma(two_cd, c_c, -c_m);
+      c_m = c_c;
+      c_c = cn;
+      const double snn = fma(two_cd, s_c, -s_m);
+      s_m = s_c;
+      s_c = snn;
+    }
+    if (kD) {
+      double t;
+      t = fma(two_cd, a_c, -a_m); a_m = a_c; a_c = t;
+      t = fma(two_cd, b_c, -b_m); b_m = b_c; b_c = t;
+      t = fma(two_cd, sa_c, -sa_m); sa_m = sa_c; sa_c = t;
+      t = fma(two_cd, sb_c, -sb_m); sb_m = sb_c; sb_c = t;
+    }
+    QBX_PIN4(hm_r, hm_i, hc_r, hc_i);
+    if (kS) {
+      QBX_PIN4(c_m, c_c, s_m, s_c);
+      QBX_PIN4(sm, sc, sK.r, sK.i);
+      QBX_PIN2(sKr, sKt);
+      if (kFused) QBX_PIN1(sKR);
+    }
+    if (kD) {
+      QBX_PIN4(a_m, a_c, b_m, b_c);
+      QBX_PIN4(sa_m, sa_c, sb_m, sb_c);
+      QBX_PIN4(dm, dc, dK.r, dK.i);
+      QBX_PIN2(dKr, dKtp);
+      QBX_PIN1(dKq);
+      if (kFused) QBX_PIN1(dKR);
+    }
+  }
+  ProjOut o;
+  const double H0r = h.h0r, H0i = h.h0i;
+  if (kS) {
+    o.Ks = {fma(2.0, sK.r, J[0] * H0r), fma(2.0, sK.i, J[0] * H0i)};
+    o.rs = k * fma(-J[0], ps1, sKr);
+    o.ts = 2.0 * sKt;
+    o.Rs = kFused ? k * fma(2.0, sKR, Jd[0] * ps0) : 0.0;
+  }
+  if (kD) {
+    // the m = 0 terms (H_0 J_1 cos psi and its derivatives) exist only when p >= 1
+    const double f0 = P >= 1 ? J[1] * cps : 0.0, g0 = P >= 1 ? J[1] * sps : 0.0;
+    o.Kd = {k * fma(f0, H0r, dK.r), k * fma(f0, H0i, dK.i)};
+    o.rd = k * k * fma(-f0, pd1, 0.5 * dKr);
+    o.td = k * dKtp;
+    o.psid = k * fma(-g0, pd0, -dKq);
+    const double fR0 = P >= 1 ? Jd[1] * cps : 0.0;
+    o.Rd = kFused ? k * k * fma(fR0, pd0, dKR) : 0.0;
   }
   return o;
 }
@@ -406,7 +534,7 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
         cps = ct * g.z + st * g.w;
         sps = st * g.z - ct * g.w;
       }
-      const PairOut o = pair_sums<P, KIND, 0>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+      const PairOut o = pair_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
       int kk = 0;
       if (kS) {
         const double2 w = dens[j];
@@ -450,11 +578,11 @@ __device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2
                                            double cy, double ct, double st,
                                            const double* __restrict__ J, int nj,
                                            const double* __restrict__ cf, double k, double inv_k,
-                                           const double2 (&Gk)[2],
-                                           Cplx (&A)[((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0)],
+                                           const double2 (&Gk)[2], Cplx (&A)[src_slots(KIND)],
                                            double (&cres)[4]) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = kS && kD ? 2 : 1;
   const double vx = g.x - cx, vy = g.y - cy;
   const double rho2 = fma(vx, vx, vy * vy);
   const double ir = rsqrt_refined(rho2);
@@ -467,45 +595,39 @@ __device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2
     cps = ct * g.z + st * g.w;
     sps = st * g.z - ct * g.w;
   }
-  const PairOut o = pair_sums<P, KIND, 0>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
-  double cR = 0.0, cT = 0.0, cX = 0.0, cY = 0.0;
-  int a = 0, kk = 0;
+  // w = G q per kind
+  const double2 GS = Gk[0], GD = Gk[NK - 1], qS = q[0], qD = q[NK - 1];
+  const double2 wS = make_double2(GS.x * qS.x - GS.y * qS.y, GS.x * qS.y + GS.y * qS.x);
+  const double2 wD = make_double2(GD.x * qD.x - GD.y * qD.y, GD.x * qD.y + GD.y * qD.x);
+  const ProjOut o =
+      pair_sums_proj<P, KIND, true>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf, wS, wD);
+  // grad_v of Re(w K) over both kinds: K_rho v^ + K_theta' theta^ / rho
+  double r = 0.0, t = 0.0, cR = 0.0, cT = 0.0;
   if (kS) {
-    const double2 G = Gk[0], w = q[0];
-    const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
-    const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
-    A[0].r += G.x * o.Ks.r - G.y * o.Ks.i;   // conj(G K)
-    A[0].i -= G.x * o.Ks.i + G.y * o.Ks.r;
-    cmul_acc(A[1], G.x, G.y, ex);
-    cmul_acc(A[2], G.x, G.y, ey);
-    const double gr = G.x * w.x - G.y * w.y, gi = G.x * w.y + G.y * w.x;   // G q
-    cR = fma(gr, o.KRs.r, fma(-gi, o.KRs.i, cR));
-    cT = fma(gr, o.Kts.r, fma(-gi, o.Kts.i, cT));
-    cX = fma(gr, ex.r, fma(-gi, ex.i, cX));
-    cY = fma(gr, ey.r, fma(-gi, ey.i, cY));
-    a = 3;
-    kk = 1;
+    A[0].r += GS.x * o.Ks.r - GS.y * o.Ks.i;   // conj(G K)
+    A[0].i -= GS.x * o.Ks.i + GS.y * o.Ks.r;
+    r = o.rs;
+    t = o.ts;
+    cR = o.Rs;
+    cT = -o.ts;                                 // K_theta = -K_theta'
   }
   if (kD) {
-    const double2 G = Gk[kk], w = q[kk];
-    const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
-    const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
-    const Cplx kpsi = {o.Ktd.r + o.Ktpd.r, o.Ktd.i + o.Ktpd.i};
-    A[a].r += G.x * o.Kd.r - G.y * o.Kd.i;
-    A[a].i -= G.x * o.Kd.i + G.y * o.Kd.r;
-    cmul_acc(A[a + 1], G.x, G.y, ex);
-    cmul_acc(A[a + 2], G.x, G.y, ey);
-    cmul_acc(A[a + 3], G.x, G.y, kpsi);
-    const double gr = G.x * w.x - G.y * w.y, gi = G.x * w.y + G.y * w.x;
-    cR = fma(gr, o.KRd.r, fma(-gi, o.KRd.i, cR));
-    cT = fma(gr, o.Ktd.r, fma(-gi, o.Ktd.i, cT));
-    cX = fma(gr, ex.r, fma(-gi, ex.i, cX));
-    cY = fma(gr, ey.r, fma(-gi, ey.i, cY));
+    A[NK - 1].r += GD.x * o.Kd.r - GD.y * o.Kd.i;
+    A[NK - 1].i -= GD.x * o.Kd.i + GD.y * o.Kd.r;
+    r += o.rd;
+    t += o.td;
+    cR += o.Rd;
+    cT += o.psid - o.td;                        // K_theta = K_psi - K_theta'
+    A[NK + 1].r += o.psid;
   }
+  t *= ir;
+  const double ex = fma(r, ux, -t * uy), ey = fma(r, uy, t * ux);
+  A[NK].r += ex;
+  A[NK].i += ey;
   cres[0] = cR;
   cres[1] = cT;
-  cres[2] = cX;
-  cres[3] = cY;
+  cres[2] = ex;
+  cres[3] = ey;
 }
 
 // ---------------------------------------------------------------------------
@@ -513,9 +635,10 @@ __device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2
 // 64-source chunks [ch0, ch1) of one contour.  The four waves take each chunk
 // together; wave w owns the tile's centers c = w, w + 4, ...  Per pair one
 // evaluation of the tape-mode sums (fused_pair) feeds
-//   * the source side, accumulated in the lane over the wave's centers; at the
-//     end of each chunk the four waves' sums are added in wave order through
-//     LDS and written to spart_cb[NA][N] (the tile's center block);
+//   * the source side (the src_slots layout), accumulated in the lane over the
+//     wave's centers; at the end of each chunk the four waves' sums are added
+//     in wave order through LDS and written to spart_cb[slots][N] (the tile's
+//     center block);
 //   * the center side, four reals summed over the wave and added into the LDS
 //     sums of the center, which only its owning wave touches; written at the
 //     end to cpart_sb[ci][4] (the tile's source block).
@@ -530,10 +653,10 @@ __device__ __forceinline__ void fused_tile(
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ,
     const double2* __restrict__ G, int Mc, int i0, int nc, int ch0, int ch1, double k,
     double2* __restrict__ spart_cb, double* __restrict__ cpart_sb, double* acc,
-    double2 (*xsrc)[((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0)][kWave]) {
+    double2 (*xsrc)[src_slots(KIND)][kWave]) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
-  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
+  constexpr int NA = src_slots(KIND);
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
   __syncthreads();
   for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) acc[t] = 0.0;
@@ -597,22 +720,22 @@ __device__ __forceinline__ void fused_tile(
 }
 
 // ---------------------------------------------------------------------------
-// adjoint, source side: one lane, one source g, centers [i0, i1); A as in the
-// partial layout of the source-major pass
+// adjoint, source side: one lane, one source g with densities q, centers
+// [i0, i1); A in the src_slots layout
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
-__device__ __forceinline__ void adjoint_source(const double4 g, const CenterRec* __restrict__ ctr,
+__device__ __forceinline__ void adjoint_source(const double4 g, const double2 (&q)[2],
+                                               const CenterRec* __restrict__ ctr,
                                                const double* __restrict__ jtab, int NJ,
                                                const double2* __restrict__ G, int Mc, int i0,
-                                               int i1, double k,
-                                               Cplx (&A)[((KIND & 1) ? 3 : 0) + ((KIND & 2) ? 4 : 0)]) {
+                                               int i1, double k, Cplx (&A)[src_slots(KIND)]) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
-  constexpr int NA = (kS ? 3 : 0) + (kD ? 4 : 0);
+  constexpr int NK = kS && kD ? 2 : 1;
   const double inv_k = 1.0 / k;
   const int nj = NJ / 2;
 #pragma unroll
-  for (int a = 0; a < NA; ++a) A[a] = {0.0, 0.0};
+  for (int a = 0; a < src_slots(KIND); ++a) A[a] = {0.0, 0.0};
   for (int ci = i0; ci < i1; ++ci) {
     const int z0 = opaque_zero();
     const CenterRec* __restrict__ C = ctr + ci + z0;
@@ -631,31 +754,30 @@ __device__ __forceinline__ void adjoint_source(const double4 g, const CenterRec*
       cps = ct * g.z + st * g.w;
       sps = st * g.z - ct * g.w;
     }
-    const PairOut o = pair_sums<P, KIND, 1>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
-    int a = 0;
-    int kk = 0;
+    const double2 GS = G[(size_t)ci + z0];
+    const double2 GD = NK == 2 ? G[(size_t)Mc + ci + z0] : GS;
+    const double2 qS = q[0], qD = q[NK - 1];
+    const double2 wS = make_double2(GS.x * qS.x - GS.y * qS.y, GS.x * qS.y + GS.y * qS.x);
+    const double2 wD = make_double2(GD.x * qD.x - GD.y * qD.y, GD.x * qD.y + GD.y * qD.x);
+    const ProjOut o = pair_sums_proj<P, KIND, false>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J,
+                                                     J + nj, cf, wS, wD);
+    double r = 0.0, t = 0.0;
     if (kS) {
-      const double2 Gs = G[(size_t)ci + z0];
-      // conj(G K)
-      A[0].r += Gs.x * o.Ks.r - Gs.y * o.Ks.i;
-      A[0].i -= Gs.x * o.Ks.i + Gs.y * o.Ks.r;
-      const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
-      const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
-      cmul_acc(A[1], Gs.x, Gs.y, ex);
-      cmul_acc(A[2], Gs.x, Gs.y, ey);
-      a = 3;
-      kk = 1;
+      A[0].r += GS.x * o.Ks.r - GS.y * o.Ks.i;   // conj(G K)
+      A[0].i -= GS.x * o.Ks.i + GS.y * o.Ks.r;
+      r = o.rs;
+      t = o.ts;
     }
     if (kD) {
-      const double2 Gd = G[(size_t)kk * Mc + ci + z0];
-      A[a].r += Gd.x * o.Kd.r - Gd.y * o.Kd.i;
-      A[a].i -= Gd.x * o.Kd.i + Gd.y * o.Kd.r;
-      const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
-      const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
-      cmul_acc(A[a + 1], Gd.x, Gd.y, ex);
-      cmul_acc(A[a + 2], Gd.x, Gd.y, ey);
-      cmul_acc(A[a + 3], Gd.x, Gd.y, o.Kpsid);
+      A[NK - 1].r += GD.x * o.Kd.r - GD.y * o.Kd.i;
+      A[NK - 1].i -= GD.x * o.Kd.i + GD.y * o.Kd.r;
+      r += o.rd;
+      t += o.td;
+      A[NK + 1].r += o.psid;
     }
+    t *= ir;
+    A[NK].r += fma(r, ux, -t * uy);
+    A[NK].i += fma(r, uy, t * ux);
   }
 }
 

@@ -302,14 +302,14 @@ __device__ __forceinline__ void center_grad_elem(int ci, int Mc, int nk, int sid
 }
 
 // per source: sg[j] = {grad(w sigma) re, im, grad(w mu) re, im, g_x', g_y', g_nx, g_ny}
-__device__ __forceinline__ void source_finalize_elem(int j, int N, int nk, int kind, int n_csplit,
+__device__ __forceinline__ void source_finalize_elem(int j, int N, int kind, int n_csplit,
                                                      const double4* __restrict__ geo,
-                                                     const double2* __restrict__ dens,
                                                      const double2* __restrict__ partial,
                                                      double* __restrict__ sg) {
   const bool hasS = kind & 1, hasD = kind & 2;
-  const int NA = (hasS ? 3 : 0) + (hasD ? 4 : 0);
-  double s[7][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  const int nk = hasS && hasD ? 2 : 1;
+  const int NA = src_slots(kind);
+  double s[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   for (int cs = 0; cs < n_csplit; ++cs)
     for (int b = 0; b < NA; ++b) {
       const double2 v = partial[((size_t)cs * NA + b) * N + j];
@@ -317,23 +317,18 @@ __device__ __forceinline__ void source_finalize_elem(int j, int N, int nk, int k
       s[b][1] += v.y;
     }
   double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int a = 0, kk = 0;
   if (hasS) {
-    const double2 w = dens[j];
     o[0] = s[0][0];
     o[1] = s[0][1];
-    o[4] += w.x * s[1][0] - w.y * s[1][1];
-    o[5] += w.x * s[2][0] - w.y * s[2][1];
-    a = 3;
-    kk = 1;
   }
   if (hasD) {
-    const double2 w = dens[(size_t)kk * N + j];
-    o[2] = s[a][0];
-    o[3] = s[a][1];
-    o[4] += w.x * s[a + 1][0] - w.y * s[a + 1][1];
-    o[5] += w.x * s[a + 2][0] - w.y * s[a + 2][1];
-    const double rp = w.x * s[a + 3][0] - w.y * s[a + 3][1];
+    o[2] = s[nk - 1][0];
+    o[3] = s[nk - 1][1];
+  }
+  o[4] = s[nk][0];
+  o[5] = s[nk][1];
+  if (hasD) {
+    const double rp = s[nk + 1][0];
     const double4 g = geo[j];
     o[6] = rp * g.w;    // Re(w mu Psi) (n_y, -n_x)
     o[7] = -rp * g.z;

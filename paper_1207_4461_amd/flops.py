@@ -56,8 +56,9 @@ def interactions(n_centers: int, n_sources: int, kind: int) -> int:
     return n_centers * n_sources * (2 if kind == 3 else 1)
 
 
-def _pair_sums_flops(p: int, kind: int, tape: bool) -> int:
-    """pair_sums() of the adjoint file: seed, recurrences and derivative sums."""
+def _pair_sums_flops(p: int, kind: int) -> int:
+    """pair_sums() of the forward with tape: seed, recurrences and the complex
+    derivative sums K, K_rho, K_theta', K_R, K_theta."""
     S = bool(kind & 1)
     D = bool(kind & 2)
     lmax = p + 1 if D else p
@@ -67,20 +68,46 @@ def _pair_sums_flops(p: int, kind: int, tape: bool) -> int:
         if S:
             f += 4                              # Chebyshev cos, sin
             if l <= p:
-                f += 15 + (5 if tape else 0)    # K, K_rho, K_theta' (+ K_R)
+                f += 20                         # K, K_rho, K_theta', K_R
         if D:
             f += 8                              # four Chebyshev sequences
             up = l <= p - 1
             f += (3 if up else 1) + 8           # J_{l+1} a - J_{l-1} b; K, K_rho
             f += (1 if up else 0) + 1 + 2 + 4   # l (J_{l+1} sa - J_{l-1} sb); K_theta'
-            if tape:
-                f += (3 if up else 1) + 4 + 3 + 4   # K_R; K_theta
-            else:
-                f += 1 + 4                      # K_psi
+            f += (3 if up else 1) + 4 + 3 + 4   # K_R; K_theta
     if S:
-        f += 16 + (8 if tape else 0)
+        f += 24
     if D:
-        f += 26 + (8 if tape else 0)
+        f += 34
+    return f
+
+
+def _proj_sums_flops(p: int, kind: int, fused: bool) -> int:
+    """pair_sums_proj(): K complex, the derivative sums over the real sequences
+    Re(w H_l) (one per kind)."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    lmax = p + 1 if D else p
+    f = 184 + 2 + (12 if D else 0)
+    f += 6 * (int(S) + int(D))                  # Re(w H_0), Re(w H_1) per kind
+    for l in range(1, lmax + 1):
+        f += 5                                  # H_{l+1} (complex), 2l/z
+        if S:
+            f += 2 + 4                          # Re(w_S H_{l+1}); Chebyshev cos, sin
+            if l <= p:
+                # f = J c; K (4); K_rho (sub, fma); K_theta' (l J s, fma); K_R (Jd c, fma)
+                f += 1 + 4 + 3 + 4 + (3 if fused else 0)
+        if D:
+            up = l <= p - 1
+            f += 2 + 8                          # Re(w_D H_{l+1}); four Chebyshev sequences
+            # f (3 or 1); K (4); K_rho (3); sA, sB (2 or 1); K_theta' (4); K_psi (3)
+            f += (3 if up else 1) + 4 + 3 + (2 if up else 1) + 4 + 3
+            if fused:
+                f += 5 if up else 3             # K_R
+    if S:
+        f += 6 + 3 + 1 + (4 if fused else 0)
+    if D:
+        f += 2 + 6 + 5 + 1 + 3 + (5 if fused else 0)
     return f
 
 
@@ -90,26 +117,31 @@ def flops_tape_pair(p: int, kind: int) -> int:
     D = bool(kind & 2)
     outer = 17 + (6 if D else 0)
     outer += 56 * (int(S) + int(D))             # grad_v combination + 5 weighted sums
-    return outer + _pair_sums_flops(p, kind, True)
+    return outer + _pair_sums_flops(p, kind)
+
+
+def _proj_outer(kind: int) -> int:
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    nk = int(S) + int(D)
+    outer = 17 + (6 if D else 0)                # geometry (and the normal's angle)
+    outer += 6 * nk                             # w = G q per kind
+    outer += 8 * nk                             # conj(G K) per kind
+    outer += 2 * (nk - 1) + 1 + 6 + 2           # sum over kinds, grad_v, accumulate
+    outer += 1 if D else 0                      # K_psi
+    return outer
 
 
 def flops_adjoint_pair(p: int, kind: int) -> int:
     """Source-major adjoint pair kernel: density, source-position and normal sums."""
-    S = bool(kind & 1)
-    D = bool(kind & 2)
-    outer = 17 + (6 if D else 0)
-    outer += (40 if S else 0) + (48 if D else 0)
-    return outer + _pair_sums_flops(p, kind, False)
+    return _proj_outer(kind) + _proj_sums_flops(p, kind, False)
 
 
 def flops_fused_pair(p: int, kind: int) -> int:
-    """Fused adjoint pair kernel: the tape-mode sums once, then the source side (as the
-    source-major pass, K_psi = K_theta + K_theta') and the center side contracted with
-    G q (four reals)."""
+    """Fused adjoint pair kernel: the source-side sums as the source-major pass,
+    plus Re w K_R and Re w K_theta for the center side (K_theta = -K_theta' for
+    S, K_psi - K_theta' for D)."""
     S = bool(kind & 1)
     D = bool(kind & 2)
-    outer = 17 + (6 if D else 0)
-    # per kind: conj(G K) 4, grad_v K components 16, two complex MACs 16, G q 6,
-    # four Re(G q X) 16; D adds K_psi 2 and its complex MAC 8
-    outer += (58 if S else 0) + (68 if D else 0)
-    return outer + _pair_sums_flops(p, kind, True)
+    center = (1 if D else 0) + (2 if S and D else 0)
+    return _proj_outer(kind) + center + _proj_sums_flops(p, kind, True)
