@@ -8,6 +8,8 @@ Two regimes (z = k*rho > 0):
   at Chebyshev points in s = (Z0/z)^2 in (0, 1] from 40-digit mpmath values of
   J_nu + i Y_nu and stored as monomial coefficients in s:
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
+  A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
+  (used when every lane of a wavefront is that far).
 * Z1 <= z < Z0: the entire functions J_0, J_1, R_0 = Y_0 - (2/pi) L J_0 and
   R_1 = Y_1 + 2/(pi z) - (2/pi) L J_1, L = ln(z/2) + gamma (the log terms of
   DLMF 10.8.1/10.8.2 split off), each interpolated at Chebyshev points of [Z1, Z0]
@@ -34,6 +36,8 @@ import numpy as np
 
 Z0 = 6.0
 DEG = 12          # degree in s of the P, Q fits
+ZF = 20.0
+DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
 Z1 = 4.0          # below: ascending series; [Z1, Z0): interpolated entire parts
 NSER = 17         # series terms for z < Z1
 DEG_MID = 15      # degree of the mid-range fits in x = (z - ZC)/ZH in [-1, 1]
@@ -125,6 +129,10 @@ def main():
         fits[f"P{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, Z0 / mpmath.sqrt(s))[0], DEG)
         fits[f"Q{nu}"] = cheb_fit_monomial(
             lambda s, nu=nu: pq(nu, Z0 / mpmath.sqrt(s))[1] * (Z0 / mpmath.sqrt(s)) / Z0, DEG)
+        fits[f"FP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZF / mpmath.sqrt(s))[0],
+                                            DEG_FAR)
+        fits[f"FQ{nu}"] = cheb_fit_monomial(
+            lambda s, nu=nu: pq(nu, ZF / mpmath.sqrt(s))[1] * (ZF / mpmath.sqrt(s)) / ZF, DEG_FAR)
     zc, zh = mpmath.mpf(ZC), mpmath.mpf(ZH)
     fits["MJ0"] = cheb_fit_monomial_pm1(lambda x: mpmath.besselj(0, zc + zh * x), DEG_MID)
     def Lg(z):
@@ -171,6 +179,14 @@ def main():
             ref = complex(mpmath.besselj(nu, z) + 1j * mpmath.bessely(nu, z))
             worst_mid = max(worst_mid, abs(complex(Jv, Yv) - ref) / abs(ref))
     g = float(mpmath.euler)
+    worst_far = 0.0
+    for z in np.concatenate([np.geomspace(ZF, 2e4, 1500), rng.uniform(ZF, 80, 500)]):
+        s = (ZF / z) ** 2
+        for nu in (0, 1):
+            P = horner(dbl[f"FP{nu}"], s)
+            Qv = (ZF / z) * horner(dbl[f"FQ{nu}"], s)
+            pr, qr = pq(nu, z)
+            worst_far = max(worst_far, abs(complex(P - float(pr), Qv - float(qr))))
     worst_big = worst_small = 0.0
     for z in zs_big:
         s = (Z0 / z) ** 2
@@ -192,6 +208,7 @@ def main():
             ref = complex(mpmath.besselj(nu, z) + 1j * mpmath.bessely(nu, z))
             worst_small = max(worst_small, abs(complex(Jv, Yv) - ref) / abs(ref))
     print(f"fit error of P,Q (absolute, |P+iQ| ~ 1) for z >= {Z0}: {worst_big:.3e}")
+    print(f"far fit error of P,Q for z >= {ZF} (degree {DEG_FAR}): {worst_far:.3e}")
     print(f"mid-range relative error of H for {Z1} <= z < {Z0}: {worst_mid:.3e}")
     print(f"series relative error of H for z < {Z1}: {worst_small:.3e}")
 
@@ -221,6 +238,7 @@ def main():
     out.append("// Coefficients of the Hankel seeds H_0, H_1 (see qbx_special.h).\n#pragma once\n\n")
     out.append("namespace qbx {\nnamespace seed {\n\n")
     out.append(f"constexpr double kZ0 = {Z0:.17e};\nconstexpr double kZ1 = {Z1:.17e};\n")
+    out.append(f"constexpr double kZF = {ZF:.17e};\n")
     out.append(f"constexpr double kZC = {ZC:.17e};\nconstexpr double kInvZH = {1.0 / ZH:.17e};\n")
     out.append(f"constexpr double kPio4Hi = {parts[0]:.17e};\n")
     out.append(f"constexpr double kPio4Mid = {parts[1]:.17e};\n")
@@ -241,6 +259,7 @@ def main():
     block("SER", [[float(a) for a in aJ0], [float(a) for a in bJ1], [float(a) for a in cY0],
                   [float(a) for a in dY1]])
     block("TRIG", [sin_c + [0.0], cos_c])
+    block("FAR", [dbl["FP0"], dbl["FQ0"], dbl["FP1"], dbl["FQ1"]])
     for name, (o, n) in offs.items():
         out.append(f"constexpr int k{name}Off = {o};\nconstexpr int k{name}Len = {n};\n")
     out.append(f"constexpr int kTableLen = {len(table)};\n")

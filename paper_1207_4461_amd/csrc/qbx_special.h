@@ -19,6 +19,8 @@ namespace qbx {
 // gen_seed_coeffs.py from 40-digit reference values and exact rationals).
 //  * z >= Z0 = 6: H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} (P_nu + i Q_nu)
 //    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
+//    when every active lane of the wavefront has z >= ZF = 20 (a wave-uniform
+//    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead;
 //    e^{i(z - pi/4)} by a three-part Cody-Waite reduction z = m pi/4 + r, m odd,
 //    |r| <= pi/4, and Taylor polynomials of sin r / r and cos r (DLMF 4.19.1);
 //    the phase of H_1 is that of H_0 turned by -pi/2.
@@ -92,10 +94,22 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
   constexpr double kInvTwoPi = 0.15915494309189533577;
   H01 h;
   if (z >= seed::kZ0) {
-    const double t = seed::kZ0 * iz;
-    const double s = t * t;
-    const D4 pq = horner4<seed::kLARGELen>(cf + seed::kLARGEOff, s);
-    const double P0 = pq.a, Q0 = t * pq.b, P1 = pq.c, Q1 = t * pq.d;
+    double P0, Q0, P1, Q1;
+    if (__all(z >= seed::kZF)) {
+      const double t = seed::kZF * iz;
+      const D4 pq = horner4<seed::kFARLen>(cf + seed::kFAROff, t * t);
+      P0 = pq.a;
+      Q0 = t * pq.b;
+      P1 = pq.c;
+      Q1 = t * pq.d;
+    } else {
+      const double t = seed::kZ0 * iz;
+      const D4 pq = horner4<seed::kLARGELen>(cf + seed::kLARGEOff, t * t);
+      P0 = pq.a;
+      Q0 = t * pq.b;
+      P1 = pq.c;
+      Q1 = t * pq.d;
+    }
     // z - pi/4 = r + q pi/2 with r = z - (2q+1) pi/4
     const double q = rint(fma(z, kTwoOverPi, -0.5));
     const double m = fma(2.0, q, 1.0);
