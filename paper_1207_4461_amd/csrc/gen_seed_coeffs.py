@@ -10,6 +10,8 @@ Two regimes (z = k*rho > 0):
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
   A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
   (used when every lane of a wavefront is that far).
+* sin and cos of the reduced phase: polynomials in r^2 interpolated at Chebyshev
+  points of [0, R_TRIG^2] (40-digit values).
 * Z1 <= z < Z0: the entire functions J_0, J_1, R_0 = Y_0 - (2/pi) L J_0 and
   R_1 = Y_1 + 2/(pi z) - (2/pi) L J_1, L = ln(z/2) + gamma (the log terms of
   DLMF 10.8.1/10.8.2 split off), each interpolated at Chebyshev points of [Z1, Z0]
@@ -38,6 +40,9 @@ Z0 = 6.0
 DEG = 12          # degree in s of the P, Q fits
 ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
+R_TRIG = 0.7854   # reduced argument bound (pi/4 plus the reduction's rounding)
+DEG_SIN = 6       # degree in r^2 of sin(r)/r
+DEG_COS = 7       # degree in r^2 of cos(r)
 Z1 = 4.0          # below: ascending series; [Z1, Z0): interpolated entire parts
 NSER = 17         # series terms for z < Z1
 DEG_MID = 15      # degree of the mid-range fits in x = (z - ZC)/ZH in [-1, 1]
@@ -229,9 +234,25 @@ def main():
         parts.append(float(hi))
         rem = rem - hi
     parts.append(float(rem))
-    # Taylor coefficients of sin(r)/r and cos(r) in u = r^2, |r| <= pi/4
-    sin_c = [(-1) ** k / math.factorial(2 * k + 1) for k in range(9)]
-    cos_c = [(-1) ** k / math.factorial(2 * k) for k in range(10)]
+    # sin(r)/r and cos(r) as polynomials in u = r^2 for |r| <= R_TRIG (just past
+    # pi/4, the bound of the reduced argument): Chebyshev interpolation in u at
+    # 40 digits, degrees DEG_SIN and DEG_COS
+    umax = mpmath.mpf(R_TRIG) ** 2
+
+    def on_u(f):
+        return lambda s: f(s * umax)
+
+    sin_c = [float(a * umax ** -i) for i, a in enumerate(cheb_fit_monomial(
+        on_u(lambda u: mpmath.sin(mpmath.sqrt(u)) / mpmath.sqrt(u) if u > 0 else mpmath.mpf(1)),
+        DEG_SIN))]
+    cos_c = [float(a * umax ** -i) for i, a in enumerate(cheb_fit_monomial(
+        on_u(lambda u: mpmath.cos(mpmath.sqrt(u))), DEG_COS))]
+    worst_trig = 0.0
+    for r in np.linspace(-R_TRIG, R_TRIG, 4001):
+        u = r * r
+        sv, cv = r * horner(sin_c, u), horner(cos_c, u)
+        worst_trig = max(worst_trig, abs(sv - float(mpmath.sin(r))), abs(cv - float(mpmath.cos(r))))
+    print(f"sin/cos error for |r| <= {R_TRIG} (degrees {DEG_SIN}, {DEG_COS} in r^2): {worst_trig:.3e}")
 
     out = []
     out.append("// Generated by gen_seed_coeffs.py -- do not edit.\n")
@@ -258,10 +279,11 @@ def main():
     block("MID", [dbl["MJ0"], dbl["MY0"], dbl["MJ1"], dbl["MY1"]])
     block("SER", [[float(a) for a in aJ0], [float(a) for a in bJ1], [float(a) for a in cY0],
                   [float(a) for a in dY1]])
-    block("TRIG", [sin_c + [0.0], cos_c])
+    block("TRIG", [sin_c + [0.0] * (len(cos_c) - len(sin_c)), cos_c])
     block("FAR", [dbl["FP0"], dbl["FQ0"], dbl["FP1"], dbl["FQ1"]])
     for name, (o, n) in offs.items():
         out.append(f"constexpr int k{name}Off = {o};\nconstexpr int k{name}Len = {n};\n")
+    out.append(f"constexpr int kTRIGLenA = {len(sin_c)};   // sin(r)/r coefficients in TRIG\n")
     out.append(f"constexpr int kTableLen = {len(table)};\n")
     body = ", \\\n    ".join(f"{v:.17e}" for v in table)
     out.append(f"#define QBX_SEED_TABLE_VALUES \\\n    {body}\n")

@@ -687,18 +687,19 @@ __device__ __forceinline__ void fused_tile(
       Gk[1] = NK == 2 ? G[(size_t)Mc + ci + z0] : Gk[0];
       double cres[4];
       fused_pair<P, KIND>(g, q, C->cx, C->cy, C->ct, C->st, J, nj, cf, k, inv_k, Gk, A, cres);
+      // the four sums over the wave, reduce-scatter: the xor-32 and xor-16
+      // exchanges leave in lane L a four-lane partial of sum (L >> 4) & 3, the
+      // xor 8..1 butterfly completes it across each group of 16 lanes
+      const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
+      const double k0 = h32 ? cres[2] : cres[0], k1 = h32 ? cres[3] : cres[1];
+      const double e0 = h32 ? cres[0] : cres[2], e1 = h32 ? cres[1] : cres[3];
+      const double p0 = k0 + __shfl_xor(e0, 32), p1 = k1 + __shfl_xor(e1, 32);
+      double v = (h16 ? p1 : p0) + __shfl_xor(h16 ? p0 : p1, 16);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cres[b] += __shfl_xor(cres[b], off);
-      }
-      // every lane holds the four sums; lanes 0..3 add one each, the others add
-      // zero (no divergent branch inside the loop); only this wave touches
-      // these four slots
-      const int b = lane & 3;
-      const double v = lane < 4 ? (b == 0 ? cres[0] : b == 1 ? cres[1] : b == 2 ? cres[2] : cres[3])
-                                : 0.0;
-      atomicAdd(&acc[c * 4 + b], v);
+      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      // lanes 0, 16, 32, 48 add sums 0..3 to the center's slots, which only
+      // this wave touches
+      if ((lane & 15) == 0) acc[c * 4 + (lane >> 4)] += v;
     }
     // the four waves' source sums of this chunk, added in wave order
 #pragma unroll

@@ -33,17 +33,17 @@ struct H01 {
   double h0r, h0i, h1r, h1i;
 };
 
-// 1/sqrt(x) for a normal positive x: the hardware estimate refined by two
-// Newton steps y <- y + (y/2)(1 - x y^2) (each roughly doubles the correct
-// bits); the result is within about one ulp.  The pair loops use it for 1/rho,
-// rho = x (1/sqrt x) and the 1/sqrt(z) of the Hankel asymptotic form, where the
-// correctly rounded sqrt and division sequences cost about three times as much.
+// 1/sqrt(x) for a normal positive x: the hardware estimate y (relative error
+// below 2^-23) refined by one third-order step of the series
+// (1 - e)^{-1/2} = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2: y <- y + y e (1/2 + 3e/8);
+// the first dropped term, 5e^3/16, is below 2^-66, so the result is within
+// about one ulp.  The pair loops use it for 1/rho, rho = x (1/sqrt x) and the
+// 1/sqrt(z) of the Hankel asymptotic form, where the correctly rounded sqrt and
+// division sequences cost about three times as much.
 __device__ __forceinline__ double rsqrt_refined(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 struct D4 {
@@ -53,8 +53,12 @@ struct D4 {
 // Four interleaved polynomials c[4i + 0..3], i < LEN, at x, accumulated in the
 // power basis (x^i shared by the four): each step is one multiply for x^i and one
 // fused multiply-add per polynomial with the wave-uniform coefficient as a
-// multiplicand.  The polynomials are well conditioned on their ranges (|x| <= 1,
-// decaying coefficients), so the summation order costs no accuracy.
+// multiplicand, which the hardware takes straight from a scalar register.
+// (Horner's rule would save the multiplies, but its coefficient is the addend,
+// and the compiler then copies every coefficient into the accumulator
+// register first: three instructions a step.)  The polynomials are well
+// conditioned on their ranges (decaying coefficients), so the summation order
+// costs no accuracy.
 template <int LEN>
 __host__ __device__ __forceinline__ D4 horner4(const double* __restrict__ c, double x) {
   D4 r = {c[0], c[1], c[2], c[3]};
@@ -70,8 +74,9 @@ __host__ __device__ __forceinline__ D4 horner4(const double* __restrict__ c, dou
   return r;
 }
 
-// two interleaved polynomials c[2i + 0..1], same scheme
-template <int LEN>
+// two interleaved polynomials c[2i + 0..1], i < LEN, same scheme; the first
+// stops at degree LA - 1 (its higher slots are zero padding)
+template <int LEN, int LA>
 __host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, double x, double& a,
                                                  double& b) {
   a = c[0];
@@ -79,7 +84,7 @@ __host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, d
   double pw = x;
 #pragma unroll
   for (int i = 1; i < LEN; ++i) {
-    a = fma(c[2 * i], pw, a);
+    if (i < LA) a = fma(c[2 * i], pw, a);
     b = fma(c[2 * i + 1], pw, b);
     if (i + 1 < LEN) pw *= x;
   }
@@ -118,7 +123,7 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
     r = fma(-m, seed::kPio4Lo, r);
     const double u = r * r;
     double sn, cs;
-    horner2<seed::kTRIGLen>(cf + seed::kTRIGOff, u, sn, cs);
+    horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, u, sn, cs);
     sn *= r;
     const int qi = ((int)q) & 3;
     // e^{i q pi/2} (cs + i sn)
