@@ -292,9 +292,10 @@ int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t st
  *   fused_tiles         adjoint without a tape: workgroup tiles (a block of
  *                       centers x a block of 64-source chunks) aimed for
  *   batch_fused_chunks  batched adjoint without a tape: 64-source chunks per tile
+ *                       (four waves share a tile, one chunk each at a time)
  * Limits: the three wave targets, batch_adjoint_tasks and fused_tiles in
  * [256, 1 << 22], batch_grid_scale in [0.125, 8], batch_fused_chunks in
- * [1, 64].  Defaults 16384, 1.0, 2048 and 2. */
+ * [1, 64].  Defaults 16384, 1.0, 16384 and 4. */
 typedef struct {
   int32_t forward_waves;
   int32_t tape_waves;
@@ -313,7 +314,7 @@ int qbx_get_tuning(qbx_tuning* t);
  * SYNCHRONOUS, and unlike every other entry point it ALLOCATES (and frees)
  * device memory of its own: workspace, output, tape and gradients.  For each
  * of forward_waves, tape_waves and adjoint_waves it times the candidates
- * 2048 .. 131072, and for fused_tiles 512 .. 16384 (doubling; candidates that
+ * 2048 .. 131072, and for fused_tiles 2048 .. 32768 (doubling; candidates that
  * give the same launch shape are timed once), with hipEvents on `stream`, the
  * minimum over `passes` runs (1..20) after one warm-up, keeps the fastest,
  * installs the result with qbx_set_tuning and writes it to *best (nullable).
@@ -327,7 +328,7 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
  * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
  * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2, 4} on the batched
  * forward-with-tape, then batch_adjoint_tasks in 2048 .. 262144 (doubling) on
- * the batched adjoint with the tape and batch_fused_chunks in {1, 2, 4, 8} on
+ * the batched adjoint with the tape and batch_fused_chunks in {4, 8, 16, 32} on
  * the batched adjoint without it, keeps the fastest of each and installs them. */
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
                          const double* density, int oversample, int passes, qbx_tuning* best,

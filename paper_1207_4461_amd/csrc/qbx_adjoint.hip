@@ -137,15 +137,14 @@ __global__ __launch_bounds__(256) void k_adjoint_fused(
     const double2* __restrict__ G, int Mc, int cblock, int n_sb, int chunks,
     int chunks_per_sb, double k, double2* __restrict__ spart, double* __restrict__ cpart) {
   constexpr int NA = src_slots(KIND);
-  __shared__ double acc[fused_centers(KIND) * 4];
-  __shared__ double2 xsrc[4][NA][kWave];
+  __shared__ double acc[4 * fused_centers(KIND) * 4];
   const int cb = blockIdx.x / n_sb;
   const int sb = blockIdx.x - cb * n_sb;
   const int i0 = cb * cblock;
   const int ch0 = sb * chunks_per_sb;
   fused_tile<P, KIND>(geo, dens, N, ctr, jtab, NJ, G, Mc, i0, min(cblock, Mc - i0), ch0,
                       min(ch0 + chunks_per_sb, chunks), k, spart + (size_t)cb * NA * N,
-                      cpart + (size_t)sb * Mc * 4, acc, xsrc);
+                      cpart + (size_t)sb * Mc * 4, acc);
 }
 
 // per center: the fused center-side sums over the source blocks, then the

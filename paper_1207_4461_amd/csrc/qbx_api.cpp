@@ -40,7 +40,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int g_forward_waves = 16384;
 static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
-static int g_fused_tiles = 2048;   // fused adjoint workgroups aimed for
+static int g_fused_tiles = 16384;  // fused adjoint workgroups aimed for
 
 void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves, int fused_tiles) {
   g_forward_waves = forward_waves;
@@ -86,11 +86,11 @@ void set_launch_shape(Dims* d) {
   d->centers_per_split = (int)(((long)d->Mc + cs - 1) / cs);
   d->n_csplit = (int)(((long)d->Mc + d->centers_per_split - 1) / d->centers_per_split);
   // fused adjoint: tiles of up to fused_centers(kind) centers; enough source blocks for
-  // about g_fused_tiles tiles
+  // about g_fused_tiles tiles, each of at least four chunks (one per wave)
   d->fused_cblock = d->Mc < fused_centers(d->kind) ? d->Mc : fused_centers(d->kind);
   d->n_cb = (d->Mc + d->fused_cblock - 1) / d->fused_cblock;
   long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
-  long max_sb = d->chunks;
+  long max_sb = (d->chunks + 3) / 4;
   if (sbs > max_sb) sbs = max_sb;
   if (sbs < 1) sbs = 1;
   d->chunks_per_sb = (int)((d->chunks + sbs - 1) / sbs);

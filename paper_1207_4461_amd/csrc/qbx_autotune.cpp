@@ -63,7 +63,7 @@ double time_min(const std::function<int()>& fn, int passes, hipStream_t s, Event
 }
 
 const int kWaveCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536, 131072};
-const int kTileCandidates[] = {512, 1024, 2048, 4096, 8192, 16384};
+const int kTileCandidates[] = {2048, 4096, 8192, 16384, 32768};
 
 }  // namespace
 }  // namespace qbx
@@ -180,7 +180,7 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
   qbx_get_tuning(&saved);
   static const int kTaskCandidates[] = {2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144};
   static const double kScaleCandidates[] = {0.5, 1.0, 2.0, 4.0};
-  static const int kChunkCandidates[] = {1, 2, 4, 8};
+  static const int kChunkCandidates[] = {4, 8, 16, 32};
   size_t ws_bytes = 0;
   for (int c : kTaskCandidates) {
     for (int f : kChunkCandidates) {

@@ -52,7 +52,7 @@ struct BatchPlan {
 // launch tunables (qbx_set_tuning)
 static double g_batch_grid_scale = 1.0;       // persistent grid = resident blocks x this
 static double g_batch_adjoint_tasks = 16384;  // adjoint tasks per (kind, p) class
-static int g_batch_fused_chunks = 2;          // 64-source chunks per fused adjoint tile
+static int g_batch_fused_chunks = 4;          // 64-source chunks per fused adjoint tile
 
 static bool build_plan(const qbx_batch_item* items, int n, int oversample, BatchPlan* P) {
   if (!items || n < 1 || oversample < 1 || oversample > QBX_OVERSAMPLE_MAX) return false;

@@ -16,8 +16,7 @@ __global__ __launch_bounds__(256) void k_adjoint_fused_batched(BatchTasks t,
                                                                double2* __restrict__ spart,
                                                                double* __restrict__ cpart) {
   constexpr int NA = src_slots(KIND);
-  __shared__ double acc[fused_centers(KIND) * 4];
-  __shared__ double2 xsrc[4][NA][kWave];
+  __shared__ double acc[4 * fused_centers(KIND) * 4];
   __shared__ long long s_task;
   for (;;) {
     // one task per workgroup: thread 0 takes it, the barrier hands it to all
@@ -38,7 +37,7 @@ __global__ __launch_bounds__(256) void k_adjoint_fused_batched(BatchTasks t,
                         jtab + B.jtab_off, d.NJ, G + B.G_off, d.Mc, i0,
                         min(d.fused_cblock, d.Mc - i0), ch0, min(ch0 + d.chunks_per_sb, d.chunks),
                         d.k, spart + B.spart_off + (size_t)cb * NA * d.N,
-                        cpart + B.cpart_off + (size_t)sb * d.Mc * 4, acc, xsrc);
+                        cpart + B.cpart_off + (size_t)sb * d.Mc * 4, acc);
   }
 }
 

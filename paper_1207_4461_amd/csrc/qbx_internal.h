@@ -138,18 +138,13 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
 __host__ __device__ constexpr int src_slots(int kind) {
   return (kind == 3 ? 2 : 1) + 1 + ((kind & 2) ? 1 : 0);
 }
-// centers per fused tile, by kind: the LDS center sums (32 B a center) plus the
-// waves' source sums (4 x slots x 64 x 16 B) must let as many workgroups share
-// a CU (160 KB of LDS) as the kernel's registers allow
-#ifndef QBX_FUSED_CENTERS_SD
-#define QBX_FUSED_CENTERS_SD 1024
+// centers per fused tile: each of the four waves keeps its own LDS sums of
+// the tile's centers (4 x 32 B a center), small enough that as many workgroups
+// share a CU (160 KB of LDS) as the kernel's registers allow
+#ifndef QBX_FUSED_CENTERS
+#define QBX_FUSED_CENTERS 256
 #endif
-#ifndef QBX_FUSED_CENTERS_1
-#define QBX_FUSED_CENTERS_1 768
-#endif
-__host__ __device__ constexpr int fused_centers(int kind) {
-  return kind == 3 ? QBX_FUSED_CENTERS_SD : QBX_FUSED_CENTERS_1;
-}
+__host__ __device__ constexpr int fused_centers(int) { return QBX_FUSED_CENTERS; }
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

@@ -632,40 +632,40 @@ __device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2
 
 // ---------------------------------------------------------------------------
 // fused adjoint tile: one workgroup of four waves, centers [i0, i0 + nc) x
-// 64-source chunks [ch0, ch1) of one contour.  The four waves take each chunk
-// together; wave w owns the tile's centers c = w, w + 4, ...  Per pair one
-// evaluation of the tape-mode sums (fused_pair) feeds
+// 64-source chunks [ch0, ch1) of one contour.  Wave w takes the chunks
+// ch0 + w, ch0 + w + 4, ... and runs through all the tile's centers in the same
+// order as the other three, so the center data one wave brings into the scalar
+// cache serves the others.  Per pair one evaluation (fused_pair) feeds
 //   * the source side (the src_slots layout), accumulated in the lane over the
-//     wave's centers; at the end of each chunk the four waves' sums are added
-//     in wave order through LDS and written to spart_cb[slots][N] (the tile's
-//     center block);
-//   * the center side, four reals summed over the wave and added into the LDS
-//     sums of the center, which only its owning wave touches; written at the
-//     end to cpart_sb[ci][4] (the tile's source block).
+//     tile's centers and written to spart_cb[slots][N] (the tile's center
+//     block) when the chunk is done;
+//   * the center side, four reals summed over the wave (reduce-scatter) and
+//     added into this wave's LDS sums of the center, acc[w][c][4]; at the end
+//     the four waves' sums are added in wave order and written to
+//     cpart_sb[ci][4] (the tile's source block).
 // Every sum has a fixed order, so the result is reproducible bit for bit.
 // Lanes past the last source take part with zero densities (the wave sums need
-// every lane) and write nothing.  acc: LDS, >= 4 nc doubles; xsrc: LDS.
-// Starts and ends with a workgroup barrier.
+// every lane) and write nothing.  acc: LDS, 4 x 4 nc doubles.  Starts and ends
+// with a workgroup barrier.
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
 __device__ __forceinline__ void fused_tile(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ,
     const double2* __restrict__ G, int Mc, int i0, int nc, int ch0, int ch1, double k,
-    double2* __restrict__ spart_cb, double* __restrict__ cpart_sb, double* acc,
-    double2 (*xsrc)[src_slots(KIND)][kWave]) {
+    double2* __restrict__ spart_cb, double* __restrict__ cpart_sb, double* acc) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NA = src_slots(KIND);
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
-  __syncthreads();
-  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) acc[t] = 0.0;
-  __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  double* __restrict__ wacc = acc + (size_t)wave * nc * 4;
+  __syncthreads();
+  for (int t = lane; t < nc * 4; t += kWave) wacc[t] = 0.0;
   const double inv_k = 1.0 / k;
   const int nj = NJ / 2;
-  for (int ch = ch0; ch < ch1; ++ch) {
+  for (int ch = ch0 + wave; ch < ch1; ch += 4) {
     const int j = ch * kWave + lane;
     const bool valid = j < N;
     const int jj = valid ? j : N - 1;
@@ -676,7 +676,7 @@ __device__ __forceinline__ void fused_tile(
     Cplx A[NA];
 #pragma unroll
     for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
-    for (int c = wave; c < nc; c += 4) {
+    for (int c = 0; c < nc; ++c) {
       const int ci = i0 + c;
       const int z0 = opaque_zero();
       const CenterRec* __restrict__ C = ctr + ci + z0;
@@ -697,26 +697,19 @@ __device__ __forceinline__ void fused_tile(
       double v = (h16 ? p1 : p0) + __shfl_xor(h16 ? p0 : p1, 16);
 #pragma unroll
       for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      // lanes 0, 16, 32, 48 add sums 0..3 to the center's slots, which only
-      // this wave touches
-      if ((lane & 15) == 0) acc[c * 4 + (lane >> 4)] += v;
+      // lanes 0, 16, 32, 48 add sums 0..3 to this wave's slots of the center
+      if ((lane & 15) == 0) wacc[c * 4 + (lane >> 4)] += v;
     }
-    // the four waves' source sums of this chunk, added in wave order
+    if (valid) {
 #pragma unroll
-    for (int b = 0; b < NA; ++b) xsrc[wave][b][lane] = make_double2(A[b].r, A[b].i);
-    __syncthreads();
-    for (int b = wave; b < NA; b += 4) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        sr += xsrc[w][b][lane].x;
-        si += xsrc[w][b][lane].y;
-      }
-      if (valid) spart_cb[(size_t)b * N + j] = make_double2(sr, si);
+      for (int b = 0; b < NA; ++b) spart_cb[(size_t)b * N + j] = make_double2(A[b].r, A[b].i);
     }
-    __syncthreads();
   }
-  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) cpart_sb[(size_t)i0 * 4 + t] = acc[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) {
+    const size_t w4 = (size_t)nc * 4;
+    cpart_sb[(size_t)i0 * 4 + t] = ((acc[t] + acc[w4 + t]) + acc[2 * w4 + t]) + acc[3 * w4 + t];
+  }
   __syncthreads();
 }
 

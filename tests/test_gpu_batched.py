@@ -153,7 +153,7 @@ def test_batched_autotune_keeps_results(Q):
         assert Q.get_tuning() == tuned
         assert tuned["batch_adjoint_tasks"] in [2048 << i for i in range(8)]
         assert tuned["batch_grid_scale"] in (0.5, 1.0, 2.0, 4.0)
-        assert tuned["batch_fused_chunks"] in (1, 2, 4, 8)
+        assert tuned["batch_fused_chunks"] in (4, 8, 16, 32)
         outs = [o.cpu().numpy() for o in B.split_out(B.forward(with_tape=True))]
         cot = B.pack_out([pb.cotangent for pb in pbs])
         gd, gn = B.adjoint(cot, use_tape=True)

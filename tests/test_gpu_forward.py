@@ -192,7 +192,7 @@ def test_autotune_keeps_results(Q):
         assert Q.get_tuning() == tuned
         for f in ("forward_waves", "tape_waves", "adjoint_waves"):
             assert tuned[f] in (2048, 4096, 8192, 16384, 32768, 65536, 131072)
-        assert tuned["fused_tiles"] in (512, 1024, 2048, 4096, 8192, 16384)
+        assert tuned["fused_tiles"] in (2048, 4096, 8192, 16384, 32768)
         ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
                                 pb.kind).numpy()
         assert_parity(gpu_forward(Q, pb), ref, what="after autotune")
