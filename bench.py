@@ -84,6 +84,17 @@ def parse():
     return ap.parse_args()
 
 
+def tune_fields(mode: str, backward: str) -> int:
+    """The launch shapes the timed steps use: the forward's, and the adjoint's
+    of the chosen backward."""
+    from paper_1207_4461_amd import qbx
+    if mode == "fwd":
+        return qbx.TUNE_FORWARD
+    if backward == "fused":
+        return qbx.TUNE_FORWARD | qbx.TUNE_FUSED
+    return qbx.TUNE_TAPE | qbx.TUNE_ADJOINT
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -124,7 +135,7 @@ def main():
     if args.autotune:
         t0 = time.perf_counter()
         tuning = qbx.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
-                              passes=1)
+                              passes=1, fields=tune_fields(mode, args.backward))
         log(f"autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     ws = torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side, pb.kind),
                      dtype=torch.uint8, device=dev)
@@ -334,7 +345,8 @@ def bench_batched(args):
         q = per[big]
         t0 = time.perf_counter()
         tc = qbx.autotune(q["nodes"], q["dens"], pbs[big].k, pbs[big].p, pbs[big].r,
-                          pbs[big].oversample, pbs[big].side, pbs[big].kind, passes=1)
+                          pbs[big].oversample, pbs[big].side, pbs[big].kind, passes=1,
+                          fields=tune_fields(mode, args.backward))
         log(f"per-contour autotune on contour {big} {time.perf_counter() - t0:.1f} s: {tc}")
         for pb, q in zip(pbs, per):   # workspace sizes follow the tuning
             q["ws"] = torch.empty(qbx.workspace_bytes(pb.n_panels, pb.p, pb.oversample, pb.side,
@@ -343,7 +355,7 @@ def bench_batched(args):
     tuning = qbx.get_tuning()
     if args.autotune:
         t0 = time.perf_counter()
-        tuning = B.autotune(passes=1)
+        tuning = B.autotune(passes=1, fields=tune_fields(mode, args.backward))
         log(f"batched autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     lib.qbx_kernel_timer(1)
     t_bat = timed(step_batched, args.steps)

@@ -310,29 +310,38 @@ typedef struct {
 int qbx_set_tuning(const qbx_tuning* t);
 int qbx_get_tuning(qbx_tuning* t);
 
+/* The passes an autotuner times (`fields`, a nonzero combination): */
+#define QBX_TUNE_FORWARD 1   /* forward_waves; batched: batch_grid_scale */
+#define QBX_TUNE_TAPE 2      /* tape_waves (the forward with tape) */
+#define QBX_TUNE_ADJOINT 4   /* adjoint_waves; batched: batch_adjoint_tasks */
+#define QBX_TUNE_FUSED 8     /* fused_tiles; batched: batch_fused_chunks */
+#define QBX_TUNE_ALL 15
+
 /* Autotuner for one contour problem (the arguments of qbx_layer_potential).
  * SYNCHRONOUS, and unlike every other entry point it ALLOCATES (and frees)
  * device memory of its own: workspace, output, tape and gradients.  For each
- * of forward_waves, tape_waves and adjoint_waves it times the candidates
- * 2048 .. 131072, and for fused_tiles 2048 .. 32768 (doubling; candidates that
- * give the same launch shape are timed once), with hipEvents on `stream`, the
- * minimum over `passes` runs (1..20) after one warm-up, keeps the fastest,
- * installs the result with qbx_set_tuning and writes it to *best (nullable).
- * The batched fields are left as they were.  On error the previous tuning is
- * restored. */
+ * field selected in `fields` -- forward_waves, tape_waves and adjoint_waves
+ * over 2048 .. 131072, fused_tiles over 2048 .. 32768 (doubling; candidates
+ * that give the same launch shape are timed once) -- it times its pass with
+ * hipEvents on `stream`, the minimum over `passes` runs (1..20) after one
+ * warm-up, keeps the fastest, installs the result with qbx_set_tuning and
+ * writes it to *best (nullable).  Other fields are left as they were.  On
+ * error the previous tuning is restored. */
 int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, double r,
-                 int oversample, int side, int kind, int passes, qbx_tuning* best,
+                 int oversample, int side, int kind, int passes, int fields, qbx_tuning* best,
                  hipStream_t stream);
 
 /* Autotuner for a batch (the arguments of qbx_layer_potential_batched; items
  * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
- * qbx_autotune.  Times batch_grid_scale in {0.5, 1, 2, 4} on the batched
- * forward-with-tape, then batch_adjoint_tasks in 2048 .. 262144 (doubling) on
- * the batched adjoint with the tape and batch_fused_chunks in {4, 8, 16, 32} on
- * the batched adjoint without it, keeps the fastest of each and installs them. */
+ * qbx_autotune.  Times, as selected in `fields`, batch_grid_scale in
+ * {0.5, 1, 2, 4} on the batched forward, batch_adjoint_tasks in
+ * 2048 .. 262144 (doubling) on the batched adjoint with the tape and
+ * batch_fused_chunks in {4, 8, 16, 32} on the batched adjoint without it
+ * (QBX_TUNE_TAPE selects nothing here), keeps the fastest of each and
+ * installs them. */
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
-                         const double* density, int oversample, int passes, qbx_tuning* best,
-                         hipStream_t stream);
+                         const double* density, int oversample, int passes, int fields,
+                         qbx_tuning* best, hipStream_t stream);
 
 /* ---- kernel timing (profiling hook) ----------------------------------- */
 

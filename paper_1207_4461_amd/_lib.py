@@ -11,6 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqbx.so")
 
+QBX_TUNE_FORWARD, QBX_TUNE_TAPE, QBX_TUNE_ADJOINT, QBX_TUNE_FUSED, QBX_TUNE_ALL = 1, 2, 4, 8, 15
 QBX_OK = 0
 QBX_EINVAL = -1
 QBX_EWORKSPACE = -2
@@ -95,8 +96,9 @@ def load() -> C.CDLL:
                                              vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "qbx_set_tuning": (i32, [C.POINTER(Tuning)]),
         "qbx_get_tuning": (i32, [C.POINTER(Tuning)]),
-        "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, C.POINTER(Tuning), vp]),
-        "qbx_autotune_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, i32, i32,
+        "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, i32, C.POINTER(Tuning),
+                               vp]),
+        "qbx_autotune_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, i32, i32, i32,
                                        C.POINTER(Tuning), vp]),
     }
     for name, (res, args) in sig.items():

@@ -73,13 +73,15 @@ using namespace qbx;
 extern "C" {
 
 int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, double r,
-                 int oversample, int side, int kind, int passes, qbx_tuning* best,
+                 int oversample, int side, int kind, int passes, int fields, qbx_tuning* best,
                  hipStream_t stream) {
   Dims d;
   int rc = validate(g, p, k, r, oversample, side, kind, &d);
   if (rc) return rc;
   if (!density) return fail(QBX_EINVAL, "density is NULL");
   if (passes < 1 || passes > 20) return fail(QBX_EINVAL, "passes = %d outside [1, 20]", passes);
+  if (fields <= 0 || (fields & ~QBX_TUNE_ALL))
+    return fail(QBX_EINVAL, "fields = %d: a nonzero combination of the QBX_TUNE_ bits", fields);
   qbx_tuning saved;
   qbx_get_tuning(&saved);
   // a workspace large enough for every candidate
@@ -128,6 +130,14 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
   qbx_tuning cur = saved;
   // which = 0 forward, 1 tape, 2 adjoint with the tape, 3 fused adjoint
   for (int which = 0; which < 4; ++which) {
+    if (!(fields & (1 << which))) continue;
+    if (which == 2 && !(fields & QBX_TUNE_TAPE)) {
+      // the adjoint with the tape reads one: write it once
+      if ((rc = fwd_tape()) != QBX_OK) {
+        qbx_set_tuning(&saved);
+        return rc;
+      }
+    }
     std::set<long long> shapes;
     double t_best = 1e300;
     int* field = which == 0 ? &cur.forward_waves : which == 1 ? &cur.tape_waves
@@ -169,11 +179,13 @@ int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, 
 }
 
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
-                         const double* density, int oversample, int passes, qbx_tuning* best,
-                         hipStream_t stream) {
+                         const double* density, int oversample, int passes, int fields,
+                         qbx_tuning* best, hipStream_t stream) {
   if (!items || n_items < 1 || !nodes || !density)
     return fail(QBX_EINVAL, "NULL or empty batch arguments");
   if (passes < 1 || passes > 20) return fail(QBX_EINVAL, "passes = %d outside [1, 20]", passes);
+  if (fields <= 0 || (fields & ~QBX_TUNE_ALL))
+    return fail(QBX_EINVAL, "fields = %d: a nonzero combination of the QBX_TUNE_ bits", fields);
   if (qbx_batched_workspace_bytes(items, n_items, oversample) == 0)
     return fail(QBX_EINVAL, "invalid batch (an item's parameters, offsets or oversample)");
   qbx_tuning saved;
@@ -216,6 +228,10 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
     return device_fail(e, "autotuner events");
   double* o = static_cast<double*>(out);
   double* tp = static_cast<double*>(tape);
+  auto fwd = [&] {
+    return qbx_layer_potential_batched(items, n_items, nodes, density, o, nullptr, oversample, ws,
+                                       ws_bytes, stream);
+  };
   auto fwd_tape = [&] {
     return qbx_layer_potential_batched(items, n_items, nodes, density, o, tp, oversample, ws,
                                        ws_bytes, stream);
@@ -225,59 +241,48 @@ int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double*
                                                static_cast<double*>(gd), static_cast<double*>(gn),
                                                oversample, ws, ws_bytes, stream);
   };
-  qbx_tuning cur = saved;
-  int rc = QBX_OK;
-  double t_best = 1e300;
-  for (double sc : kScaleCandidates) {
-    qbx_tuning t = cur;
-    t.batch_grid_scale = sc;
-    qbx_set_tuning(&t);
-    const double ms = time_min(fwd_tape, passes, stream, ev, &rc);
-    if (ms < 0.0) {
-      qbx_set_tuning(&saved);
-      return rc ? rc : fail(QBX_EDEVICE, "autotuner timing failed");
-    }
-    if (ms < t_best) {
-      t_best = ms;
-      cur.batch_grid_scale = sc;
-    }
-  }
-  t_best = 1e300;
-  for (int c : kTaskCandidates) {
-    qbx_tuning t = cur;
-    t.batch_adjoint_tasks = c;
-    qbx_set_tuning(&t);
-    const double ms = time_min(adj, passes, stream, ev, &rc);
-    if (ms < 0.0) {
-      qbx_set_tuning(&saved);
-      return rc ? rc : fail(QBX_EDEVICE, "autotuner timing failed");
-    }
-    if (ms < t_best) {
-      t_best = ms;
-      cur.batch_adjoint_tasks = c;
-    }
-  }
   auto adj_fused = [&] {
     return qbx_layer_potential_batched_adjoint(items, n_items, nodes, density, o, nullptr,
                                                static_cast<double*>(gd), static_cast<double*>(gn),
                                                oversample, ws, ws_bytes, stream);
   };
-  t_best = 1e300;
-  for (int c : kChunkCandidates) {
-    qbx_tuning t = cur;
-    t.batch_fused_chunks = c;
-    qbx_set_tuning(&t);
-    const double ms = time_min(adj_fused, passes, stream, ev, &rc);
-    if (ms < 0.0) {
-      qbx_set_tuning(&saved);
-      return rc ? rc : fail(QBX_EDEVICE, "autotuner timing failed");
+  qbx_tuning cur = saved;
+  int rc = QBX_OK;
+  // times fn at each candidate written by set(t, i) into the current tuning and
+  // keeps the fastest in cur
+  auto sweep = [&](int n, const std::function<void(qbx_tuning&, int)>& set,
+                   const std::function<int()>& fn) -> int {
+    double t_best = 1e300;
+    int i_best = -1;
+    for (int i = 0; i < n; ++i) {
+      qbx_tuning t = cur;
+      set(t, i);
+      qbx_set_tuning(&t);
+      const double ms = time_min(fn, passes, stream, ev, &rc);
+      if (ms < 0.0) return rc ? rc : fail(QBX_EDEVICE, "autotuner timing failed");
+      if (ms < t_best) {
+        t_best = ms;
+        i_best = i;
+      }
     }
-    if (ms < t_best) {
-      t_best = ms;
-      cur.batch_fused_chunks = c;
-    }
+    set(cur, i_best);
+    qbx_set_tuning(&cur);
+    return QBX_OK;
+  };
+  if (fields & QBX_TUNE_FORWARD)
+    rc = sweep(4, [&](qbx_tuning& t, int i) { t.batch_grid_scale = kScaleCandidates[i]; }, fwd);
+  if (!rc && (fields & QBX_TUNE_ADJOINT)) {
+    rc = fwd_tape();   // the adjoint with the tape reads one
+    if (!rc)
+      rc = sweep(8, [&](qbx_tuning& t, int i) { t.batch_adjoint_tasks = kTaskCandidates[i]; }, adj);
   }
-  qbx_set_tuning(&cur);
+  if (!rc && (fields & QBX_TUNE_FUSED))
+    rc = sweep(4, [&](qbx_tuning& t, int i) { t.batch_fused_chunks = kChunkCandidates[i]; },
+               adj_fused);
+  if (rc) {
+    qbx_set_tuning(&saved);
+    return rc;
+  }
   if (best) *best = cur;
   return QBX_OK;
 }

@@ -2,17 +2,20 @@
 
 Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, reciprocal square
 root, divide and rint = 1 each, however the kernel computes them (the kernels refine
-a hardware reciprocal square root by Newton steps; those steps are not counted).
-The counts follow the kernels' formulas for the common branch (z = k*rho >= 6, the
-asymptotic seed), line by line:
+a hardware reciprocal square root by a third-order step; that step is not counted).
+The counts follow the kernels' formulas for the common branch (every lane of the
+wavefront at z = k*rho >= 20: the asymptotic seed with the short far fits), line by
+line:
 
 forward pair (one center, one source, order p):
   geometry      v = x'-c (2), rho = sqrt(vx^2+vy^2) (4), 1/rho (1), cos/sin of
                 theta_i - theta' (8), z and 1/z (2)                        = 17
   D geometry    cos/sin(theta_i - arg nu) (6)
-  seed H0, H1   4 interleaved degree-12 polynomials in (6/z)^2 (107),
-                Cody-Waite reduction (11), sin/cos polynomials (45), scale
-                and rotations (20), (6/z)^2 (2)                             = 184 (+1 for Q scaling)
+  seed H0, H1   20/z and (20/z)^2 (2), 4 interleaved degree-6 polynomials (53),
+                Q scaling (2), Cody-Waite reduction (12), sin/cos polynomials in
+                r^2 of degree 6 and 7 (33), 1/sqrt(z) and the amplitude (4),
+                rotation by P + iQ (12)                                      = 118
+                (the long fits of 6 <= z < 20 cost 172)
   recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
   S per order   J_l cos(l D) (1) + accumulate (4) + Chebyshev cos (2)        =  7
   D per order   J_{l+1} cos(lD+psi) - J_{l-1} cos(lD-psi) (3) + accumulate (4)
@@ -20,9 +23,11 @@ forward pair (one center, one source, order p):
   accumulation  w sigma K (8 per kind)
 
 Totals (derived in flops_forward_pair below):
-  S:   210 + 12 p        D:   229 + 16 p        S+D: 243 + 23 p
+  S:   144 + 12 p        D:   163 + 16 p        S+D: 177 + 23 p
 """
 from __future__ import annotations
+
+SEED = 118   # H_0, H_1 on the common branch (see above)
 
 
 def flops_forward_pair(p: int, kind: int) -> int:
@@ -33,7 +38,7 @@ def flops_forward_pair(p: int, kind: int) -> int:
     if D:
         outer += 6                          # cos psi, sin psi
     outer += 8 * (int(S) + int(D))          # w*density*K accumulation
-    seed = 184
+    seed = SEED
     setup = 2                               # 2/z, 2 cos D
     if S:
         setup += 2 + 4                      # H0 J0 term, final 2*sum + term
@@ -62,7 +67,7 @@ def _pair_sums_flops(p: int, kind: int) -> int:
     S = bool(kind & 1)
     D = bool(kind & 2)
     lmax = p + 1 if D else p
-    f = 184 + 2 + (12 if D else 0)            # seed, 2/z and 2 cos D, cos/sin(D +- psi)
+    f = SEED + 2 + (12 if D else 0)           # seed, 2/z and 2 cos D, cos/sin(D +- psi)
     for l in range(1, lmax + 1):
         f += 6 + 1                              # H_{l+1}, H_{l-1} - H_{l+1}, 2l/z
         if S:
@@ -88,7 +93,7 @@ def _proj_sums_flops(p: int, kind: int, fused: bool) -> int:
     S = bool(kind & 1)
     D = bool(kind & 2)
     lmax = p + 1 if D else p
-    f = 184 + 2 + (12 if D else 0)
+    f = SEED + 2 + (12 if D else 0)
     f += 6 * (int(S) + int(D))                  # Re(w H_0), Re(w H_1) per kind
     for l in range(1, lmax + 1):
         f += 5                                  # H_{l+1} (complex), 2l/z

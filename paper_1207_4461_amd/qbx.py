@@ -312,10 +312,16 @@ def set_tuning(**fields) -> dict:
     return _tuning_dict(t)
 
 
+TUNE_FORWARD, TUNE_TAPE, TUNE_ADJOINT, TUNE_FUSED, TUNE_ALL = (
+    _lib.QBX_TUNE_FORWARD, _lib.QBX_TUNE_TAPE, _lib.QBX_TUNE_ADJOINT, _lib.QBX_TUNE_FUSED,
+    _lib.QBX_TUNE_ALL)
+
+
 def autotune(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
-             oversample: int = 4, side: int = EXTERIOR, kind: int = S, passes: int = 2) -> dict:
-    """Time the per-contour launch shapes on this problem and install the fastest
-    (qbx_autotune); returns the resulting tuning."""
+             oversample: int = 4, side: int = EXTERIOR, kind: int = S, passes: int = 2,
+             fields: int = TUNE_ALL) -> dict:
+    """Time the per-contour launch shapes of the passes in ``fields`` (TUNE_* bits)
+    on this problem and install the fastest (qbx_autotune); returns the tuning."""
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
@@ -323,7 +329,8 @@ def autotune(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: fl
     geo = _lib.Geometry(P, Q, nodes.data_ptr())
     t = _lib.Tuning()
     _lib.check(lib.qbx_autotune(C.byref(geo), density.data_ptr(), float(k), int(p), float(r),
-                                int(oversample), int(side), int(kind), int(passes), C.byref(t),
+                                int(oversample), int(side), int(kind), int(passes), int(fields),
+                                C.byref(t),
                                 _stream(nodes.device)))
     return _tuning_dict(t)
 
@@ -378,13 +385,15 @@ class Batch:
         if self.ws.numel() < nb:
             self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
 
-    def autotune(self, passes: int = 2) -> dict:
-        """Time the batched launch shapes on this batch and install the fastest
-        (qbx_autotune_batched); returns the resulting tuning."""
+    def autotune(self, passes: int = 2, fields: int = TUNE_ALL) -> dict:
+        """Time the batched launch shapes of the passes in ``fields`` (TUNE_* bits)
+        on this batch and install the fastest (qbx_autotune_batched); returns the
+        resulting tuning."""
         t = _lib.Tuning()
         _lib.check(self._lib.qbx_autotune_batched(
             self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
-            C.c_void_p(self.density.data_ptr()), self.oversample, int(passes), C.byref(t),
+            C.c_void_p(self.density.data_ptr()), self.oversample, int(passes), int(fields),
+            C.byref(t),
             C.c_void_p(_stream(self.device))))
         self._ensure_workspace()
         return _tuning_dict(t)

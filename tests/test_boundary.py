@@ -193,14 +193,19 @@ def test_tuning_roundtrip_and_validation(lib):
 
 def test_autotune_validation(lib):
     g = _lib.Geometry(8, 16, BAD)
-    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 30, 0.5, 4, 1, 1, 2, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune(C.byref(g), None, 1.0, 4, 0.5, 4, 1, 1, 2, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 0, None, None) == _lib.QBX_EINVAL
+    ALL = _lib.QBX_TUNE_ALL
+    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 30, 0.5, 4, 1, 1, 2, ALL, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune(C.byref(g), None, 1.0, 4, 0.5, 4, 1, 1, 2, ALL, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 0, ALL, None, None) == _lib.QBX_EINVAL
+    for bad in (0, 16, -1):   # fields: a nonzero combination of the four bits
+        assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 2, bad, None,
+                                None) == _lib.QBX_EINVAL
     its = _items()
-    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 0, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune_batched(its, 0, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 0, ALL, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched(its, 0, BAD, BAD, 4, 2, ALL, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, 0, None, None) == _lib.QBX_EINVAL
     its[0].p = 99
-    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, None, None) == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, ALL, None, None) == _lib.QBX_EINVAL
 
 
 def _explicit(lib, n_src=100, n_ctr=20, p=6, kind=1, k=3.0, xy=BAD, nu=BAD, q=BAD, cxy=BAD,

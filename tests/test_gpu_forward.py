@@ -202,3 +202,28 @@ def test_autotune_keeps_results(Q):
             assert_parity(gpu_forward(Q, pb), ref, what=f"waves={fw}")
     finally:
         Q.set_tuning(**before)
+
+
+def test_autotune_fields_mask(Q):
+    """qbx_autotune times only the passes selected in `fields`: the other tuning
+    fields keep their values (the adjoint alone writes the tape it needs first)."""
+    pb = I.small(n_panels=16, p=6, k=5.0, kind=3, side=I.BOTH)
+    nodes = torch.from_numpy(pb.nodes).cuda()
+    dens = torch.from_numpy(np.ascontiguousarray(pb.density)).cuda()
+    before = Q.get_tuning()
+    try:
+        odd = dict(forward_waves=777, tape_waves=999, adjoint_waves=1111, fused_tiles=3333)
+        for fields, changed in ((Q.TUNE_FORWARD, "forward_waves"), (Q.TUNE_ADJOINT, "adjoint_waves"),
+                                (Q.TUNE_FUSED, "fused_tiles")):
+            Q.set_tuning(**odd)
+            tuned = Q.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                               passes=1, fields=fields)
+            say(f"  fields={fields}: {tuned}")
+            for f, v in odd.items():
+                if f != changed:
+                    assert tuned[f] == v, (fields, f)
+        with pytest.raises(Exception):
+            Q.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind, passes=1,
+                       fields=0)
+    finally:
+        Q.set_tuning(**before)
