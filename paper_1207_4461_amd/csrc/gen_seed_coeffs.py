@@ -10,8 +10,10 @@ Two regimes (z = k*rho > 0):
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
   A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
   (used when every lane of a wavefront is that far).
-* sin and cos of the reduced phase: polynomials in r^2 interpolated at Chebyshev
-  points of [0, R_TRIG^2] (40-digit values).
+* the phase e^{i(z - pi/4)} = T_n e^{ir}: n = rint(z N / 2 pi), r = z - 2 pi n / N by a
+  three-part Cody-Waite reduction, T_n = e^{i(2 pi n/N - pi/4)} from a table of N
+  entries (40-digit values rounded once), and sin r, cos r as polynomials in r^2
+  interpolated at Chebyshev points of [0, R_TRIG^2].
 * Z1 <= z < Z0: the entire functions J_0, J_1, R_0 = Y_0 - (2/pi) L J_0 and
   R_1 = Y_1 + 2/(pi z) - (2/pi) L J_1, L = ln(z/2) + gamma (the log terms of
   DLMF 10.8.1/10.8.2 split off), each interpolated at Chebyshev points of [Z1, Z0]
@@ -40,9 +42,10 @@ Z0 = 6.0
 DEG = 12          # degree in s of the P, Q fits
 ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
-R_TRIG = 0.7854   # reduced argument bound (pi/4 plus the reduction's rounding)
-DEG_SIN = 6       # degree in r^2 of sin(r)/r
-DEG_COS = 7       # degree in r^2 of cos(r)
+PHASE_N = 256     # phase table entries e^{i(2 pi n/N - pi/4)}
+R_TRIG = 0.01228  # reduced argument bound (pi/N plus the reduction's rounding)
+DEG_SIN = 3       # degree in r^2 of sin(r)/r
+DEG_COS = 3       # degree in r^2 of cos(r)
 Z1 = 4.0          # below: ascending series; [Z1, Z0): interpolated entire parts
 NSER = 17         # series terms for z < Z1
 DEG_MID = 15      # degree of the mid-range fits in x = (z - ZC)/ZH in [-1, 1]
@@ -222,20 +225,24 @@ def main():
         body = ",\n    ".join(f"{v:.17e}" for v in vals)
         return f"constexpr double {name}[{len(vals)}] = {{\n    {body}}};\n"
 
-    # pi/4 split for the Cody-Waite reduction z - m*pi/4 (m < 2^20): the first two
-    # parts carry 32 significant bits each, so m*part is exact in double
-    pio4 = mpmath.pi / 4
+    # delta = 2 pi / N split for the Cody-Waite reduction z - n delta (n < 2^24):
+    # the first two parts carry 29 significant bits each, so n*part is exact
+    delta = 2 * mpmath.pi / PHASE_N
     parts = []
-    rem = pio4
+    rem = delta
     for _ in range(2):
         e = mpmath.floor(mpmath.log(abs(rem), 2))
-        scale = mpmath.mpf(2) ** (31 - e)
+        scale = mpmath.mpf(2) ** (28 - e)
         hi = mpmath.floor(rem * scale) / scale
         parts.append(float(hi))
         rem = rem - hi
     parts.append(float(rem))
+    phase = []
+    for n in range(PHASE_N):
+        a = n * delta - mpmath.pi / 4
+        phase += [float(mpmath.cos(a)), float(mpmath.sin(a))]
     # sin(r)/r and cos(r) as polynomials in u = r^2 for |r| <= R_TRIG (just past
-    # pi/4, the bound of the reduced argument): Chebyshev interpolation in u at
+    # pi/N, the bound of the reduced argument): Chebyshev interpolation in u at
     # 40 digits, degrees DEG_SIN and DEG_COS
     umax = mpmath.mpf(R_TRIG) ** 2
 
@@ -253,6 +260,21 @@ def main():
         sv, cv = r * horner(sin_c, u), horner(cos_c, u)
         worst_trig = max(worst_trig, abs(sv - float(mpmath.sin(r))), abs(cv - float(mpmath.cos(r))))
     print(f"sin/cos error for |r| <= {R_TRIG} (degrees {DEG_SIN}, {DEG_COS} in r^2): {worst_trig:.3e}")
+    # the whole phase in double against 40 digits, z up to 2^24 delta
+    worst_phase = 0.0
+    for z in np.concatenate([rng.uniform(6, 60, 3000), np.geomspace(6, 4e5, 3000)]):
+        n = float(np.rint(z * float(PHASE_N / (2 * mpmath.pi))))
+        r = z - n * parts[0]        # n * parts[0] and n * parts[1] are exact
+        r = r - n * parts[1]
+        r = r - n * parts[2]
+        i = int(n) & (PHASE_N - 1)
+        u = r * r
+        sv, cv = r * horner(sin_c, u), horner(cos_c, u)
+        er = phase[2 * i] * cv - phase[2 * i + 1] * sv
+        ei = phase[2 * i] * sv + phase[2 * i + 1] * cv
+        ref = mpmath.exp(1j * (mpmath.mpf(z) - mpmath.pi / 4))
+        worst_phase = max(worst_phase, abs(complex(er, ei) - complex(ref)))
+    print(f"phase e^(i(z - pi/4)) error for 6 <= z <= 4e5 (double evaluation): {worst_phase:.3e}")
 
     out = []
     out.append("// Generated by gen_seed_coeffs.py -- do not edit.\n")
@@ -261,9 +283,11 @@ def main():
     out.append(f"constexpr double kZ0 = {Z0:.17e};\nconstexpr double kZ1 = {Z1:.17e};\n")
     out.append(f"constexpr double kZF = {ZF:.17e};\n")
     out.append(f"constexpr double kZC = {ZC:.17e};\nconstexpr double kInvZH = {1.0 / ZH:.17e};\n")
-    out.append(f"constexpr double kPio4Hi = {parts[0]:.17e};\n")
-    out.append(f"constexpr double kPio4Mid = {parts[1]:.17e};\n")
-    out.append(f"constexpr double kPio4Lo = {parts[2]:.17e};\n")
+    out.append(f"constexpr int kPhaseN = {PHASE_N};\n")
+    out.append(f"constexpr double kInvDelta = {float(PHASE_N / (2 * mpmath.pi)):.17e};\n")
+    out.append(f"constexpr double kDeltaHi = {parts[0]:.17e};\n")
+    out.append(f"constexpr double kDeltaMid = {parts[1]:.17e};\n")
+    out.append(f"constexpr double kDeltaLo = {parts[2]:.17e};\n")
     # one packed table; four polynomials of a regime interleaved so that a wave reads
     # the coefficients of one Horner step with a single scalar load
     table, offs = [], {}
@@ -287,6 +311,9 @@ def main():
     out.append(f"constexpr int kTableLen = {len(table)};\n")
     body = ", \\\n    ".join(f"{v:.17e}" for v in table)
     out.append(f"#define QBX_SEED_TABLE_VALUES \\\n    {body}\n")
+    body = ", \\\n    ".join(f"{v:.17e}" for v in phase)
+    out.append(f"// e^(i(2 pi n/N - pi/4)), n = 0..N-1, as (cos, sin) pairs\n")
+    out.append(f"#define QBX_PHASE_TABLE_VALUES \\\n    {body}\n")
     out.append("\n}  // namespace seed\n}  // namespace qbx\n")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "qbx_seed_coeffs.h")
     with open(path, "w") as f:

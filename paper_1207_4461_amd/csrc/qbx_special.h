@@ -21,13 +21,16 @@ namespace qbx {
 //    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
 //    when every active lane of the wavefront has z >= ZF = 20 (a wave-uniform
 //    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead;
-//    e^{i(z - pi/4)} by a three-part Cody-Waite reduction z = m pi/4 + r, m odd,
-//    |r| <= pi/4, and Taylor polynomials of sin r / r and cos r (DLMF 4.19.1);
-//    the phase of H_1 is that of H_0 turned by -pi/2.
+//    e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta), delta = 2 pi / 256,
+//    r = z - n delta by a three-part Cody-Waite reduction (|r| <= delta / 2),
+//    T_n = e^{i(n delta - pi/4)} from a 256-entry table gathered per lane, and
+//    short polynomials for sin r / r and cos r; the phase of H_1 is that of H_0
+//    turned by -pi/2.
 //  * z < Z0: Y_nu = (2/pi)(ln(z/2) + gamma) J_nu - nu 2/(pi z) + R_nu with J_nu, R_nu
 //    entire (DLMF 10.8.1, 10.8.2): for z < Z1 = 4 their ascending series in
 //    w = z^2/4 (DLMF 10.2.2), for Z1 <= z < Z0 polynomial fits in (z - 5).
-// Error <~ 2e-15 |H| for every z in (0, 2^20) (range of the reduction).
+// Error <~ 2e-15 |H| for every z in (0, 4e5) (the reduction is exact for
+// n < 2^24).
 // ---------------------------------------------------------------------------
 struct H01 {
   double h0r, h0i, h1r, h1i;
@@ -90,6 +93,12 @@ __host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, d
   }
 }
 
+// Device copies of the seed coefficient table and of the phase table (one per
+// translation unit).  The phase table is read with a per-lane index.
+static __constant__ double g_seed_table[seed::kTableLen] = {QBX_SEED_TABLE_VALUES};
+static __constant__ __align__(16) double g_phase_table[2 * seed::kPhaseN] = {
+    QBX_PHASE_TABLE_VALUES};
+
 // iz = 1/z (callers already hold it); cf = the coefficient table seed::kTable
 // (QBX_SEED_TABLE_VALUES), read with wave-uniform loads
 __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __restrict__ cf) {
@@ -115,24 +124,18 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
       P1 = pq.c;
       Q1 = t * pq.d;
     }
-    // z - pi/4 = r + q pi/2 with r = z - (2q+1) pi/4
-    const double q = rint(fma(z, kTwoOverPi, -0.5));
-    const double m = fma(2.0, q, 1.0);
-    double r = fma(-m, seed::kPio4Hi, z);
-    r = fma(-m, seed::kPio4Mid, r);
-    r = fma(-m, seed::kPio4Lo, r);
-    const double u = r * r;
+    // e^{i(z - pi/4)} = T_n e^{ir}
+    const double n = rint(z * seed::kInvDelta);
+    double r = fma(-n, seed::kDeltaHi, z);
+    r = fma(-n, seed::kDeltaMid, r);
+    r = fma(-n, seed::kDeltaLo, r);
+    const double* __restrict__ T = g_phase_table + 2 * ((int)n & (seed::kPhaseN - 1));
+    const double tc = T[0], ts = T[1];
     double sn, cs;
-    horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, u, sn, cs);
+    horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn, cs);
     sn *= r;
-    const int qi = ((int)q) & 3;
-    // e^{i q pi/2} (cs + i sn)
-    double er = (qi & 1) ? -sn : cs;
-    double ei = (qi & 1) ? cs : sn;
-    if (qi & 2) {
-      er = -er;
-      ei = -ei;
-    }
+    double er = fma(tc, cs, -ts * sn);
+    double ei = fma(tc, sn, ts * cs);
     const double A = kSqrtTwoOverPi * rsqrt_refined(z);
     er *= A;
     ei *= A;
@@ -165,8 +168,6 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
   return h;
 }
 
-// Device copy of the seed coefficient table (one per translation unit).
-static __constant__ double g_seed_table[seed::kTableLen] = {QBX_SEED_TABLE_VALUES};
 
 // An SGPR zero the compiler cannot see through: offsetting a table pointer by it
 // inside a loop keeps the (uniform, scalar-cached) table loads in the loop instead

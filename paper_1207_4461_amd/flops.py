@@ -12,10 +12,10 @@ forward pair (one center, one source, order p):
                 theta_i - theta' (8), z and 1/z (2)                        = 17
   D geometry    cos/sin(theta_i - arg nu) (6)
   seed H0, H1   20/z and (20/z)^2 (2), 4 interleaved degree-6 polynomials (53),
-                Q scaling (2), Cody-Waite reduction (12), sin/cos polynomials in
-                r^2 of degree 6 and 7 (33), 1/sqrt(z) and the amplitude (4),
-                rotation by P + iQ (12)                                      = 118
-                (the long fits of 6 <= z < 20 cost 172)
+                Q scaling (2), phase: reduction by 2 pi/256 (8), degree-3 sin/cos
+                polynomials in r^2 (16), times the table entry (6), 1/sqrt(z) and
+                the amplitude (4), rotation by P + iQ (12)                   = 103
+                (the long fits of 6 <= z < 20 cost 157)
   recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
   S per order   J_l cos(l D) (1) + accumulate (4) + Chebyshev cos (2)        =  7
   D per order   J_{l+1} cos(lD+psi) - J_{l-1} cos(lD-psi) (3) + accumulate (4)
@@ -23,11 +23,11 @@ forward pair (one center, one source, order p):
   accumulation  w sigma K (8 per kind)
 
 Totals (derived in flops_forward_pair below):
-  S:   144 + 12 p        D:   163 + 16 p        S+D: 177 + 23 p
+  S:   129 + 12 p        D:   148 + 16 p        S+D: 162 + 23 p
 """
 from __future__ import annotations
 
-SEED = 118   # H_0, H_1 on the common branch (see above)
+SEED = 103   # H_0, H_1 on the common branch (see above)
 
 
 def flops_forward_pair(p: int, kind: int) -> int:
