@@ -85,9 +85,9 @@ void set_launch_shape(Dims* d) {
   if (cs < 1) cs = 1;
   d->centers_per_split = (int)(((long)d->Mc + cs - 1) / cs);
   d->n_csplit = (int)(((long)d->Mc + d->centers_per_split - 1) / d->centers_per_split);
-  // fused adjoint: tiles of up to fused_centers(kind) centers; enough source blocks for
+  // fused adjoint: tiles of fused_tile_height centers; enough source blocks for
   // about g_fused_tiles tiles, each of at least four chunks (one per wave)
-  d->fused_cblock = d->Mc < fused_centers(d->kind) ? d->Mc : fused_centers(d->kind);
+  d->fused_cblock = fused_tile_height(d->Mc, d->N, d->kind);
   d->n_cb = (d->Mc + d->fused_cblock - 1) / d->fused_cblock;
   long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
   long max_sb = (d->chunks + 3) / 4;

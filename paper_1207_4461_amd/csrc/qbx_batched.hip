@@ -161,11 +161,11 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     }
     C.tasks_f = append(cost_f, P->order_f, P->pre_f, true);
     C.tasks_a = append(cost_a, P->order_a, P->pre_a, false);
-    // fused adjoint tiles: up to fused_centers(kind) centers x g_batch_fused_chunks
+    // fused adjoint tiles: fused_tile_height centers x g_batch_fused_chunks
     // 64-source chunks; tile cost ~ centers of the tile
     for (int i : mem) {
       Dims& d = P->items[i].d;
-      d.fused_cblock = d.Mc < fused_centers(d.kind) ? d.Mc : fused_centers(d.kind);
+      d.fused_cblock = fused_tile_height(d.Mc, d.N, d.kind);
       d.n_cb = (d.Mc + d.fused_cblock - 1) / d.fused_cblock;
       d.chunks_per_sb = d.chunks < g_batch_fused_chunks ? d.chunks : g_batch_fused_chunks;
       d.n_sb = (d.chunks + d.chunks_per_sb - 1) / d.chunks_per_sb;

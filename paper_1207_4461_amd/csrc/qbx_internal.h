@@ -145,6 +145,19 @@ __host__ __device__ constexpr int src_slots(int kind) {
 #define QBX_FUSED_CENTERS 256
 #endif
 __host__ __device__ constexpr int fused_centers(int) { return QBX_FUSED_CENTERS; }
+// centers per fused tile (taken in sub-blocks of fused_centers()): the
+// source-side partial sums are one row of sources per tile of centers, so they
+// take sources x centers / height x 16 B a slot.  The height starts at one
+// sub-block (fine-grained tiles) and doubles while those sums would pass
+// kFusedPartBudget bytes.
+constexpr double kFusedPartBudget = 2147483648.0;
+__host__ __device__ inline int fused_tile_height(int Mc, int N, int kind) {
+  long long h = fused_centers(kind);
+  while (h < Mc &&
+         (double)((Mc + h - 1) / h) * src_slots(kind) * (double)N * 16.0 > kFusedPartBudget)
+    h *= 2;
+  return h < Mc ? (int)h : Mc;
+}
 hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double* density,
                                const double* tables, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, const double* cot,

@@ -632,21 +632,22 @@ __device__ __forceinline__ void fused_pair(const double4 g, const double2 (&q)[2
 
 // ---------------------------------------------------------------------------
 // fused adjoint tile: one workgroup of four waves, centers [i0, i0 + nc) x
-// 64-source chunks [ch0, ch1) of one contour.  Wave w takes the chunks
-// ch0 + w, ch0 + w + 4, ... and runs through all the tile's centers in the same
+// 64-source chunks [ch0, ch1) of one contour, taken in sub-blocks of
+// fused_centers() centers.  For each sub-block, wave w takes the chunks
+// ch0 + w, ch0 + w + 4, ... and runs through the sub-block's centers in the same
 // order as the other three, so the center data one wave brings into the scalar
 // cache serves the others.  Per pair one evaluation (fused_pair) feeds
 //   * the source side (the src_slots layout), accumulated in the lane over the
-//     tile's centers and written to spart_cb[slots][N] (the tile's center
-//     block) when the chunk is done;
+//     sub-block's centers and added (in sub-block order, by the one wave that
+//     owns the chunk) into spart_cb[slots][N], the tile's row;
 //   * the center side, four reals summed over the wave (reduce-scatter) and
 //     added into this wave's LDS sums of the center, acc[w][c][4]; at the end
-//     the four waves' sums are added in wave order and written to
-//     cpart_sb[ci][4] (the tile's source block).
+//     of the sub-block the four waves' sums are added in wave order and written
+//     to cpart_sb[ci][4] (the tile's source block).
 // Every sum has a fixed order, so the result is reproducible bit for bit.
 // Lanes past the last source take part with zero densities (the wave sums need
-// every lane) and write nothing.  acc: LDS, 4 x 4 nc doubles.  Starts and ends
-// with a workgroup barrier.
+// every lane) and write nothing.  acc: LDS, 4 x 4 fused_centers() doubles.
+// Starts and ends with a workgroup barrier.
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
 __device__ __forceinline__ void fused_tile(
@@ -658,59 +659,69 @@ __device__ __forceinline__ void fused_tile(
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NA = src_slots(KIND);
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  constexpr int kSub = fused_centers(KIND);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  double* __restrict__ wacc = acc + (size_t)wave * nc * 4;
-  __syncthreads();
-  for (int t = lane; t < nc * 4; t += kWave) wacc[t] = 0.0;
+  double* __restrict__ wacc = acc + (size_t)wave * kSub * 4;
   const double inv_k = 1.0 / k;
   const int nj = NJ / 2;
-  for (int ch = ch0 + wave; ch < ch1; ch += 4) {
-    const int j = ch * kWave + lane;
-    const bool valid = j < N;
-    const int jj = valid ? j : N - 1;
-    const double4 g = geo[jj];
-    double2 q[2];
-    q[0] = valid ? dens[jj] : make_double2(0.0, 0.0);
-    q[1] = (NK == 2 && valid) ? dens[(size_t)N + jj] : make_double2(0.0, 0.0);
-    Cplx A[NA];
-#pragma unroll
-    for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
-    for (int c = 0; c < nc; ++c) {
-      const int ci = i0 + c;
-      const int z0 = opaque_zero();
-      const CenterRec* __restrict__ C = ctr + ci + z0;
-      const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
-      const double* __restrict__ cf = g_seed_table + z0;
-      double2 Gk[2];
-      Gk[0] = G[(size_t)ci + z0];
-      Gk[1] = NK == 2 ? G[(size_t)Mc + ci + z0] : Gk[0];
-      double cres[4];
-      fused_pair<P, KIND>(g, q, C->cx, C->cy, C->ct, C->st, J, nj, cf, k, inv_k, Gk, A, cres);
-      // the four sums over the wave, reduce-scatter: the xor-32 and xor-16
-      // exchanges leave in lane L a four-lane partial of sum (L >> 4) & 3, the
-      // xor 8..1 butterfly completes it across each group of 16 lanes
-      const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
-      const double k0 = h32 ? cres[2] : cres[0], k1 = h32 ? cres[3] : cres[1];
-      const double e0 = h32 ? cres[0] : cres[2], e1 = h32 ? cres[1] : cres[3];
-      const double p0 = k0 + __shfl_xor(e0, 32), p1 = k1 + __shfl_xor(e1, 32);
-      double v = (h16 ? p1 : p0) + __shfl_xor(h16 ? p0 : p1, 16);
-#pragma unroll
-      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      // lanes 0, 16, 32, 48 add sums 0..3 to this wave's slots of the center
-      if ((lane & 15) == 0) wacc[c * 4 + (lane >> 4)] += v;
-    }
-    if (valid) {
-#pragma unroll
-      for (int b = 0; b < NA; ++b) spart_cb[(size_t)b * N + j] = make_double2(A[b].r, A[b].i);
-    }
-  }
   __syncthreads();
-  for (int t = threadIdx.x; t < nc * 4; t += blockDim.x) {
-    const size_t w4 = (size_t)nc * 4;
-    cpart_sb[(size_t)i0 * 4 + t] = ((acc[t] + acc[w4 + t]) + acc[2 * w4 + t]) + acc[3 * w4 + t];
+  for (int g0 = 0; g0 < nc; g0 += kSub) {
+    const int ng = min(kSub, nc - g0);
+    for (int t = lane; t < ng * 4; t += kWave) wacc[t] = 0.0;
+    for (int ch = ch0 + wave; ch < ch1; ch += 4) {
+      const int j = ch * kWave + lane;
+      const bool valid = j < N;
+      const int jj = valid ? j : N - 1;
+      const double4 g = geo[jj];
+      double2 q[2];
+      q[0] = valid ? dens[jj] : make_double2(0.0, 0.0);
+      q[1] = (NK == 2 && valid) ? dens[(size_t)N + jj] : make_double2(0.0, 0.0);
+      Cplx A[NA];
+#pragma unroll
+      for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
+      for (int c = 0; c < ng; ++c) {
+        const int ci = i0 + g0 + c;
+        const int z0 = opaque_zero();
+        const CenterRec* __restrict__ C = ctr + ci + z0;
+        const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
+        const double* __restrict__ cf = g_seed_table + z0;
+        double2 Gk[2];
+        Gk[0] = G[(size_t)ci + z0];
+        Gk[1] = NK == 2 ? G[(size_t)Mc + ci + z0] : Gk[0];
+        double cres[4];
+        fused_pair<P, KIND>(g, q, C->cx, C->cy, C->ct, C->st, J, nj, cf, k, inv_k, Gk, A, cres);
+        // the four sums over the wave, reduce-scatter: the xor-32 and xor-16
+        // exchanges leave in lane L a four-lane partial of sum (L >> 4) & 3, the
+        // xor 8..1 butterfly completes it across each group of 16 lanes
+        const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
+        const double k0 = h32 ? cres[2] : cres[0], k1 = h32 ? cres[3] : cres[1];
+        const double e0 = h32 ? cres[0] : cres[2], e1 = h32 ? cres[1] : cres[3];
+        const double p0 = k0 + __shfl_xor(e0, 32), p1 = k1 + __shfl_xor(e1, 32);
+        double v = (h16 ? p1 : p0) + __shfl_xor(h16 ? p0 : p1, 16);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        // lanes 0, 16, 32, 48 add sums 0..3 to this wave's slots of the center
+        if ((lane & 15) == 0) wacc[c * 4 + (lane >> 4)] += v;
+      }
+      // the chunk belongs to this wave: its row gathers the sub-blocks in order
+      if (valid) {
+#pragma unroll
+        for (int b = 0; b < NA; ++b) {
+          double2* o = spart_cb + (size_t)b * N + j;
+          const double2 prev = g0 == 0 ? make_double2(0.0, 0.0) : *o;
+          *o = make_double2(prev.x + A[b].r, prev.y + A[b].i);
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ng * 4; t += blockDim.x) {
+      const size_t w4 = (size_t)kSub * 4;
+      cpart_sb[(size_t)(i0 + g0) * 4 + t] =
+          ((acc[t] + acc[w4 + t]) + acc[2 * w4 + t]) + acc[3 * w4 + t];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
