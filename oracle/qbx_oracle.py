@@ -30,6 +30,9 @@ gradients of the discrete map:
   i/4 of the Helmholtz kernel (i/4) H_0 (Section 1) applied at evaluation.
 * Section 3.2: both one-sided limits are returned; the principal value of D is
   their average (eq. dlp-twosided).
+* Section 3.2: target derivatives by analytic differentiation of the local
+  expansion (``evaluate_gradient``, ``layer_potential_gradient``), through the
+  ladder relations of the regular waves J_l e^{i l theta} in x and y.
 
 Two modes:
 * ``mode="dense"``: every order l evaluated by its own library call
@@ -298,6 +301,33 @@ def evaluate(a: torch.Tensor, R: torch.Tensor, theta: torch.Tensor, k: float, p:
     return 0.25j * u
 
 
+def evaluate_gradient(a: torch.Tensor, R: torch.Tensor, theta: torch.Tensor, k: float, p: int,
+                      mode: str = "fast") -> torch.Tensor:
+    """Target gradient of the local expansion at x = c + R e^{i theta} (Section 3.2:
+    derivatives with respect to the target by analytic differentiation of the local
+    Bessel expansion).  With the regular waves beta_l(v) = J_l(k|v|) e^{i l arg v},
+    the ladder relations (DLMF 10.6.1, written in x and y) are
+        d/dx beta_l = (k/2)(beta_{l-1} - beta_{l+1}),
+        d/dy beta_l = (ik/2)(beta_{l-1} + beta_{l+1}),
+    so for u = (i/4) sum_{|l|<=p} a_l beta_l
+        grad u = (i/4)(k/2) sum_l a_l (beta_{l-1} - beta_{l+1}, i (beta_{l-1} + beta_{l+1})).
+    Returns [C, 2] complex (du/dx, du/dy)."""
+    x = k * R
+    beta = {}
+    for L in range(-p - 1, p + 2):
+        if mode == "fast":
+            J = besselj(abs(L), x) * (1.0 if L >= 0 or (-L) % 2 == 0 else -1.0)
+        else:
+            J = torch.from_numpy(np.asarray(sps.jv(L, x.detach().numpy())))
+        beta[L] = J * torch.exp(1j * L * theta)
+    gx = torch.zeros(a.shape[0], dtype=_C128)
+    gy = torch.zeros(a.shape[0], dtype=_C128)
+    for L in range(-p, p + 1):
+        gx = gx + a[:, L + p] * (beta[L - 1] - beta[L + 1])
+        gy = gy + a[:, L + p] * 1j * (beta[L - 1] + beta[L + 1])
+    return 0.25j * 0.5 * k * torch.stack([gx, gy], dim=1)
+
+
 # ---------------------------------------------------------------------------
 # top level
 # ---------------------------------------------------------------------------
@@ -345,6 +375,38 @@ def layer_potential(nodes, density, k: float, p: int, r: float = 0.5, oversample
     if return_aux:
         return u, {"src": src, "sides": aux}
     return u
+
+
+def layer_potential_gradient(nodes, density, k: float, p: int, r: float = 0.5,
+                             oversample: int = 4, side: int = EXTERIOR, kind: int = S_KIND,
+                             targets=None, mode: str = "fast"):
+    """One-sided QBX limits of the target gradient and of the normal derivative
+    (S' = n . grad S, D' = n . grad D, as defined at the start of Section 4), from
+    the same coefficients as ``layer_potential``.
+
+    Returns (grad [n_sides, n_kinds, T, 2] complex, dn [n_sides, n_kinds, T] complex),
+    exterior first for BOTH; n is the outward unit normal at the target."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    kinds = kinds_of(kind)
+    src = source_grid(nodes, oversample)
+    fine = interpolate_density(density, oversample)
+    dens = {kk: src["w"].to(_C128) * fine[i] for i, kk in enumerate(kinds)}
+    n_tgt = src["n_tgt"]
+    if targets is not None:
+        idx = torch.as_tensor(np.asarray(targets), dtype=torch.long)
+        n_tgt = n_tgt[idx]
+    grads = []
+    for s in sides_of(side):
+        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
+        if targets is not None:
+            ctr = {key: val[idx] for key, val in ctr.items()}
+        a = coefficients(src, dens, ctr, k, p, kind, mode)
+        grads.append(torch.stack([evaluate_gradient(a[kk], ctr["R"], ctr["theta"], k, p, mode)
+                                  for kk in kinds]))
+    g = torch.stack(grads)
+    dn = g[..., 0] * n_tgt[:, 0].to(_C128) + g[..., 1] * n_tgt[:, 1].to(_C128)
+    return g, dn
 
 
 def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float, p: int,
