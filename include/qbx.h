@@ -106,6 +106,23 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
                         double r, int oversample, int side, int kind, double* out,
                         double* tape, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Target derivatives (Section 3.2: the local expansion at each center is
+ * differentiated analytically with respect to the target), with the arguments
+ * of qbx_layer_potential:
+ *   grad  [n_sides][n_kinds][T][2] complex, nullable: (du/dx, du/dy), the
+ *         one-sided limits of grad S sigma and grad D mu at every target;
+ *   dn    [n_sides][n_kinds][T] complex, nullable: n . grad u, the one-sided
+ *         limits of S' and D' (defined at the start of Section 4), n the
+ *         outward unit normal at the target.
+ * At least one of grad and dn must be given (QBX_EINVAL otherwise).  The
+ * principal value of grad S (and of S') is the average of its two one-sided
+ * limits (grad S = grad S^+- +- n sigma / 2); D' has no jump.  The pair work is
+ * the forward-with-tape pass.  Stream-ordered, no allocation; the workspace
+ * is qbx_workspace_bytes(). */
+int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, double k, int p,
+                                 double r, int oversample, int side, int kind, double* grad,
+                                 double* dn, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- adjoint ----------------------------------------------------------- */
 
 /* Vector-Jacobian product of qbx_layer_potential for the real scalar

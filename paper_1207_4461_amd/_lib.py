@@ -70,6 +70,8 @@ def load() -> C.CDLL:
         "qbx_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
         "qbx_tape_bytes": (sz, [i32, i32, i32, i32, i32]),
         "qbx_layer_potential": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]),
+        "qbx_layer_potential_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
+                                               sz, vp]),
         "qbx_layer_potential_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
                                               vp, vp, sz, vp]),
         "qbx_check_geometry": (i32, [gp, i32, dbl, i32, i32, C.POINTER(dbl), C.POINTER(dbl), vp,

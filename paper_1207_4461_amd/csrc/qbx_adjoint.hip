@@ -69,6 +69,55 @@ __global__ __launch_bounds__(256) void k_finalize_tape(int Mc, int T, int nk, in
 }
 
 // ---------------------------------------------------------------------------
+// target derivatives from the tape pass's partial sums (Section 3.2: the local
+// expansion differentiated at the target).  With F_R = sum_j q_j dK/dR and
+// F_t = sum_j q_j dK/dtheta (R, theta the target's polar coordinates about its
+// center, w^ = e^{i theta}),
+//   grad u = (i/4) (F_R w^ + (F_t / R) theta^),   n . grad u = -s (i/4) F_R,
+// since the center lies at x + s R n (s = +1 exterior), so that w^ = -s n.
+// grad: [n_sides][nk][T][2] complex; dn: [n_sides][nk][T] complex; either may
+// be null.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize_gradient(int Mc, int T, int nk, int n_split,
+                                                           int side,
+                                                           const CenterRec* __restrict__ ctr,
+                                                           const double2* __restrict__ partial,
+                                                           double* __restrict__ grad,
+                                                           double* __restrict__ dn) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Mc * nk) return;
+  const int kk = e / Mc, ci = e - kk * Mc;
+  double fr = 0.0, fi = 0.0, tr = 0.0, ti = 0.0;   // F_R, F_theta
+  for (int sp = 0; sp < n_split; ++sp) {
+    const double2* q = partial + (((size_t)sp * nk + kk) * Mc + ci) * 5;
+    fr += q[1].x;
+    fi += q[1].y;
+    tr += q[2].x;
+    ti += q[2].y;
+  }
+  const int si = ci / T, t = ci - si * T;
+  const double s = side != 0 ? (double)side : (si == 0 ? 1.0 : -1.0);
+  const size_t o = ((size_t)si * nk + kk) * T + t;
+  // (i/4) z = (-Im z / 4, Re z / 4)
+  if (dn) {
+    dn[2 * o] = 0.25 * s * fi;
+    dn[2 * o + 1] = -0.25 * s * fr;
+  }
+  if (grad) {
+    const CenterRec c = ctr[ci];
+    const double ir = 1.0 / c.R;
+    // F_R w^ + (F_t / R) theta^, theta^ = (-sin, cos)
+    const double gxr = fma(fr, c.ct, -tr * ir * c.st), gxi = fma(fi, c.ct, -ti * ir * c.st);
+    const double gyr = fma(fr, c.st, tr * ir * c.ct), gyi = fma(fi, c.st, ti * ir * c.ct);
+    double* q = grad + 4 * o;
+    q[0] = -0.25 * gxi;
+    q[1] = 0.25 * gxr;
+    q[2] = -0.25 * gyi;
+    q[3] = 0.25 * gyr;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // G_i = conj(g_i) i/4 per center and kind: G[kk][ci]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_make_G(int Mc, int T, int nk, const double* __restrict__ cot,
@@ -241,6 +290,14 @@ hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* o
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_finalize_tape, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
                      d.n_tsplit, partial, out, tape);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_gradient(const Dims& d, const CenterRec* ctr, const double2* partial,
+                                    double* grad, double* dn, hipStream_t s) {
+  const int n = d.Mc * d.nk;
+  hipLaunchKernelGGL(k_finalize_gradient, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
+                     d.n_tsplit, d.side, ctr, partial, grad, dn);
   return hipGetLastError();
 }
 

@@ -285,6 +285,32 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
   return QBX_OK;
 }
 
+int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, double k, int p,
+                                 double r, int oversample, int side, int kind, double* grad,
+                                 double* dn, void* ws, size_t ws_bytes, hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!grad && !dn) return fail(QBX_EINVAL, "grad and dn are both NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  timer_begin(3, stream);
+  hipError_t e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                    at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                    at<double2>(ws, L.partial), stream);
+  timer_end(3, stream);
+  if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
+  e = launch_finalize_gradient(d, at<CenterRec>(ws, L.ctr), at<double2>(ws, L.partial), grad, dn,
+                               stream);
+  if (e != hipSuccess) return device_fail(e, "gradient finalize kernel");
+  return QBX_OK;
+}
+
 int qbx_layer_potential_adjoint(const qbx_geometry* g, const double* density, double k, int p,
                                 double r, int oversample, int side, int kind,
                                 const double* cotangent, const double* tape, double* grad_density,

@@ -93,6 +93,21 @@ def test_null_geometry_and_adjoint_args(lib):
                                   None) == _lib.QBX_EINVAL
 
 
+def test_gradient_entry_point_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    call = lambda **kw: lib.qbx_layer_potential_gradient(
+        C.byref(g), kw.get("dens", BAD), kw.get("k", 3.0), kw.get("p", 6), 0.5, 4, 1, 1,
+        kw.get("grad", BAD), kw.get("dn", BAD), kw.get("ws", BAD), kw.get("nbytes", 1 << 40), None)
+    assert call(grad=None, dn=None) == _lib.QBX_EINVAL       # nothing to compute
+    assert call(dens=None) == _lib.QBX_EINVAL
+    assert call(ws=None) == _lib.QBX_EINVAL
+    assert call(p=25) == _lib.QBX_EINVAL and call(k=-1.0) == _lib.QBX_EINVAL
+    need = lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1)
+    assert call(nbytes=need - 1, dn=None) == _lib.QBX_EWORKSPACE
+    assert lib.qbx_layer_potential_gradient(None, BAD, 1.0, 4, 0.5, 4, 1, 1, BAD, BAD, BAD,
+                                            1 << 40, None) == _lib.QBX_EINVAL
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert len(lib.qbx_strerror(code)) > 3
