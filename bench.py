@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
-    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd"])
+    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad"],
+                    help="grad: the target derivatives (grad S, grad D, S', D') instead")
     ap.add_argument("--backward", default="fused", choices=["fused", "tape"],
                     help="fwdbwd step: plain forward + fused adjoint (default), or forward "
                          "with tape + source-major adjoint")
@@ -90,6 +91,8 @@ def tune_fields(mode: str, backward: str) -> int:
     from paper_1207_4461_amd import qbx
     if mode == "fwd":
         return qbx.TUNE_FORWARD
+    if mode == "grad":
+        return qbx.TUNE_FORWARD | qbx.TUNE_TAPE   # the derivative pass has the tape's shape
     if backward == "fused":
         return qbx.TUNE_FORWARD | qbx.TUNE_FUSED
     return qbx.TUNE_TAPE | qbx.TUNE_ADJOINT
@@ -152,6 +155,9 @@ def main():
     def step():
         if mode == "fwd":
             return fwd()
+        if mode == "grad":
+            return qbx.layer_potential_gradient(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
+                                                pb.side, pb.kind, workspace=ws)
         if args.backward == "fused":
             # forward, then the adjoint without a tape (one fused pass over the pairs)
             u = fwd()
@@ -185,7 +191,7 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    NC = 5
+    NC = _lib.QBX_TIMER_CLASSES
     ms = (C.c_double * NC)()
     nl = (C.c_int * NC)()
     _lib.check(lib.qbx_kernel_timer_read(ms, nl))
@@ -197,9 +203,11 @@ def main():
     # per pair-kernel class: algorithmic flops per launch / average launch time
     pairs = pb.n_centers * pb.n_sources
     names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel",
-             "forward-with-tape pair kernel", "fused adjoint pair kernel"]
+             "forward-with-tape pair kernel", "fused adjoint pair kernel",
+             "target-derivative pair kernel"]
     per_pair = [flops.flops_forward_pair(pb.p, pb.kind), flops.flops_adjoint_pair(pb.p, pb.kind),
-                0, flops.flops_tape_pair(pb.p, pb.kind), flops.flops_fused_pair(pb.p, pb.kind)]
+                0, flops.flops_tape_pair(pb.p, pb.kind), flops.flops_fused_pair(pb.p, pb.kind),
+                flops.flops_grad_pair(pb.p, pb.kind)]
     kernels = {}
     for c in range(NC):
         if nl[c] == 0 or per_pair[c] == 0:
@@ -212,7 +220,8 @@ def main():
     dom = kernels[names[cls]]
     achieved = dom["tflops"]
     avg_ms = dom["avg_ms"]
-    kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape", "k_adjoint_fused"]
+    kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape", "k_adjoint_fused",
+                    "k_forward_grad"]
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(kernel_names[cls], args.workload),
@@ -235,17 +244,26 @@ def main():
         n = int(min(pb.n_targets, max(2, args.cpu_seconds / max(per, 1e-6))))
         idx = np.sort(rng.choice(pb.n_targets, size=n, replace=False))
         t0 = time.perf_counter()
-        ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
-                                pb.kind, targets=idx).numpy()
+        if mode == "grad":
+            ref = O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                             pb.oversample, pb.side, pb.kind,
+                                             targets=idx)[1].numpy()
+        else:
+            ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                    pb.side, pb.kind, targets=idx).numpy()
         tc = time.perf_counter() - t0
         ncent = len(idx) * pb.n_sides
         cpu_inter = flops.interactions(ncent, pb.n_sources, pb.kind)
-        u = fwd().cpu().numpy()[:, :, idx]
+        if mode == "grad":
+            u = step()[1].cpu().numpy()[:, :, idx]
+        else:
+            u = fwd().cpu().numpy()[:, :, idx]
         err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
                         for s in range(u.shape[0]) for k in range(u.shape[1])))
         cpu = {"value": cpu_inter / tc, "unit": "interactions/s", "cores": torch.get_num_threads(),
                "kind": "oracle",
-               "sample": f"forward at {len(idx)} random targets x {pb.n_sides} sides "
+               "sample": f"{'normal derivative' if mode == 'grad' else 'forward'} at "
+                         f"{len(idx)} random targets x {pb.n_sides} sides "
                          f"({ncent} centers) against all {pb.n_sources} sources, "
                          f"{tc:.1f} s; GPU/oracle max rel err on the sample {err:.2e}"}
         log(f"cpu oracle: {cpu_inter / tc:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
@@ -359,7 +377,7 @@ def bench_batched(args):
         log(f"batched autotune {time.perf_counter() - t0:.1f} s: {tuning}")
     lib.qbx_kernel_timer(1)
     t_bat = timed(step_batched, args.steps)
-    NC = 5
+    NC = _lib.QBX_TIMER_CLASSES
     ms = (C.c_double * NC)()
     nl = (C.c_int * NC)()
     _lib.check(lib.qbx_kernel_timer_read(ms, nl))

@@ -116,9 +116,10 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
  *         outward unit normal at the target.
  * At least one of grad and dn must be given (QBX_EINVAL otherwise).  The
  * principal value of grad S (and of S') is the average of its two one-sided
- * limits (grad S = grad S^+- +- n sigma / 2); D' has no jump.  The pair work is
- * the forward-with-tape pass.  Stream-ordered, no allocation; the workspace
- * is qbx_workspace_bytes(). */
+ * limits (grad S = grad S^+- +- n sigma / 2); D' has no jump.  The pair pass
+ * forms only q dK/dR and q dK/dtheta per center (launch shape of the forward
+ * with tape).  Stream-ordered, no allocation; the workspace is
+ * qbx_workspace_bytes(). */
 int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, double k, int p,
                                  double r, int oversample, int side, int kind, double* grad,
                                  double* dn, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -370,10 +371,11 @@ int qbx_kernel_timer(int enable);
 
 /* SYNCHRONOUS: waits for the recorded events and returns, per kernel class
  * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
- * kernels, 3 = forward-with-tape pair kernel, 4 = fused adjoint pair kernel),
+ * kernels, 3 = forward-with-tape pair kernel, 4 = fused adjoint pair kernel,
+ * 5 = target-derivative pair kernel),
  * the summed duration in milliseconds and the number of launches since the
  * timer was enabled.  ms and launches are host arrays of QBX_TIMER_CLASSES. */
-#define QBX_TIMER_CLASSES 5
+#define QBX_TIMER_CLASSES 6
 int qbx_kernel_timer_read(double* ms, int* launches);
 
 #ifdef __cplusplus

@@ -69,7 +69,40 @@ __global__ __launch_bounds__(256) void k_finalize_tape(int Mc, int T, int nk, in
 }
 
 // ---------------------------------------------------------------------------
-// target derivatives from the tape pass's partial sums (Section 3.2: the local
+// target derivatives, pair pass: one wave per (center, source split), the
+// launch shape of the tape pass; partial layout [n_split][nk][Mc][2] with
+// q K_R and q K_theta summed over the split's sources
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_forward_grad(const double4* __restrict__ geo,
+                                                      const double2* __restrict__ dens, int N,
+                                                      const CenterRec* __restrict__ ctr,
+                                                      const double* __restrict__ jtab, int NJ,
+                                                      int Mc, int n_split, int chunks,
+                                                      int chunks_per_split, double k,
+                                                      double2* __restrict__ partial) {
+  constexpr int NK = KIND == 3 ? 2 : 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + wave;
+  const int ci = gw / n_split;
+  const int sp = gw - ci * n_split;
+  if (ci >= Mc) return;
+  Cplx A[2][2];
+  const int c0 = sp * chunks_per_split;
+  const int c1 = min(c0 + chunks_per_split, chunks);
+  grad_center<P, KIND>(geo, dens, N, ctr + ci, jtab + (size_t)ci * NJ, NJ, k, c0, c1, lane, A);
+  if (lane == 0) {
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        partial[(((size_t)sp * NK + kk) * Mc + ci) * 2 + b] = make_double2(A[kk][b].r, A[kk][b].i);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// target derivatives from the pair pass's partial sums (Section 3.2: the local
 // expansion differentiated at the target).  With F_R = sum_j q_j dK/dR and
 // F_t = sum_j q_j dK/dtheta (R, theta the target's polar coordinates about its
 // center, w^ = e^{i theta}),
@@ -89,11 +122,11 @@ __global__ __launch_bounds__(256) void k_finalize_gradient(int Mc, int T, int nk
   const int kk = e / Mc, ci = e - kk * Mc;
   double fr = 0.0, fi = 0.0, tr = 0.0, ti = 0.0;   // F_R, F_theta
   for (int sp = 0; sp < n_split; ++sp) {
-    const double2* q = partial + (((size_t)sp * nk + kk) * Mc + ci) * 5;
-    fr += q[1].x;
-    fi += q[1].y;
-    tr += q[2].x;
-    ti += q[2].y;
+    const double2* q = partial + (((size_t)sp * nk + kk) * Mc + ci) * 2;
+    fr += q[0].x;
+    fi += q[0].y;
+    tr += q[1].x;
+    ti += q[1].y;
   }
   const int si = ci / T, t = ci - si * T;
   const double s = side != 0 ? (double)side : (si == 0 ? 1.0 : -1.0);
@@ -291,6 +324,31 @@ hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* o
   hipLaunchKernelGGL(k_finalize_tape, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
                      d.n_tsplit, partial, out, tape);
   return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_forward_grad_p(const Dims& d, const double4* geo, const double2* dens,
+                                       const CenterRec* ctr, const double* jtab,
+                                       double2* partial, hipStream_t s) {
+  const long waves = (long)d.Mc * d.n_tsplit;
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_LAUNCH(KD)                                                                          \
+  hipLaunchKernelGGL((k_forward_grad<P, KD>), grid, block, 0, s, geo, dens, d.N, ctr, jtab, d.NJ, \
+                     d.Mc, d.n_tsplit, d.chunks, d.tape_chunks_per_split, d.k, partial)
+  if (d.kind == 1)
+    QBX_LAUNCH(1);
+  else if (d.kind == 2)
+    QBX_LAUNCH(2);
+  else
+    QBX_LAUNCH(3);
+#undef QBX_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_grad(const Dims& d, const double4* geo, const double2* dens,
+                               const CenterRec* ctr, const double* jtab, double2* partial,
+                               hipStream_t s) {
+  QBX_P_SWITCH(d.p, launch_forward_grad_p, d, geo, dens, ctr, jtab, partial, s)
 }
 
 hipError_t launch_finalize_gradient(const Dims& d, const CenterRec* ctr, const double2* partial,

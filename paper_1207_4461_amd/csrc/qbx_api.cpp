@@ -299,12 +299,12 @@ int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, d
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
-  timer_begin(3, stream);
-  hipError_t e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+  timer_begin(5, stream);
+  hipError_t e = launch_forward_grad(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                                     at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                                     at<double2>(ws, L.partial), stream);
-  timer_end(3, stream);
-  if (e != hipSuccess) return device_fail(e, "forward (tape) kernel");
+  timer_end(5, stream);
+  if (e != hipSuccess) return device_fail(e, "target-derivative kernel");
   e = launch_finalize_gradient(d, at<CenterRec>(ws, L.ctr), at<double2>(ws, L.partial), grad, dn,
                                stream);
   if (e != hipSuccess) return device_fail(e, "gradient finalize kernel");

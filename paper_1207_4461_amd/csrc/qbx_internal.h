@@ -120,7 +120,11 @@ hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2*
                                hipStream_t s);
 hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* out, double2* tape,
                                 hipStream_t s);
-// target gradient and normal derivative from the tape pass's partial sums
+// target derivatives: the pair pass (partial [n_tsplit][nk][Mc][2]), then the
+// gradient and normal derivative from its sums
+hipError_t launch_forward_grad(const Dims& d, const double4* geo, const double2* dens,
+                               const CenterRec* ctr, const double* jtab, double2* partial,
+                               hipStream_t s);
 hipError_t launch_finalize_gradient(const Dims& d, const CenterRec* ctr, const double2* partial,
                                     double* grad, double* dn, hipStream_t s);
 hipError_t launch_adjoint_src(const Dims& d, const double4* geo, const double2* dens,

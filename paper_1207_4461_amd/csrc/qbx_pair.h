@@ -210,6 +210,95 @@ QBX_UNROLL_BY(QBX_SUMS_UNROLL)
 }
 
 // ---------------------------------------------------------------------------
+// per-pair sums of the target derivatives: K_R = dK/dR and K_theta = dK/dtheta
+// at fixed source (the same terms as the tape's, without K, K_rho or grad_v K)
+// ---------------------------------------------------------------------------
+struct GradOut {
+  Cplx KRs, Kts, KRd, Ktd;
+};
+
+template <int P, int KIND>
+__device__ __forceinline__ GradOut grad_sums(double z, double iz, double cd, double sd, double cps,
+                                             double sps, double k, const double* __restrict__ J,
+                                             const double* __restrict__ Jd,
+                                             const double* __restrict__ cf) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int LMAX = kD ? P + 1 : P;
+  const H01 h = hankel01(z, iz, cf);
+  double hm_r = h.h0r, hm_i = h.h0i;  // H_{l-1}
+  double hc_r = h.h1r, hc_i = h.h1i;  // H_l
+  const double tz = 2.0 * iz;
+  double tl = tz;
+  const double two_cd = 2.0 * cd;
+  Cplx sKR = {0, 0}, sKt = {0, 0}, dKR = {0, 0}, dKt = {0, 0};
+  double c_m = 1.0, c_c = cd, s_m = 0.0, s_c = sd;           // cos, sin of l Delta
+  double a_m = cps, a_c = fma(cd, cps, -sd * sps);             // cos(l D + psi)
+  double b_m = cps, b_c = fma(cd, cps, sd * sps);              // cos(l D - psi)
+  double sa_m = sps, sa_c = fma(sd, cps, cd * sps);            // sin(l D + psi)
+  double sb_m = -sps, sb_c = fma(sd, cps, -cd * sps);          // sin(l D - psi)
+QBX_UNROLL_BY(QBX_SUMS_UNROLL)
+  for (int l = 1; l <= LMAX; ++l) {
+    if (kS && l <= P) {
+      cmac(sKR, Jd[l] * c_c, hc_r, hc_i);
+      cmac(sKt, (double)l * J[l] * s_c, hc_r, hc_i);
+    }
+    if (kD) {
+      const bool up = l <= P - 1;
+      const double fbR = Jd[l - 1] * b_c;
+      cmac(dKR, up ? fma(Jd[l + 1], a_c, -fbR) : -fbR, hc_r, hc_i);
+      const double sA = up ? J[l + 1] * sa_c : 0.0;
+      const double sB = J[l - 1] * sb_c;
+      cmac(dKt, fma((double)(l - 1), sB, -(double)(l + 1) * sA), hc_r, hc_i);
+    }
+    if (l < LMAX) {
+      const double hn_r = fma(tl, hc_r, -hm_r);
+      const double hn_i = fma(tl, hc_i, -hm_i);
+      hm_r = hc_r;
+      hm_i = hc_i;
+      hc_r = hn_r;
+      hc_i = hn_i;
+      tl += tz;
+      if (kS) {
+        double t;
+        t = fma(two_cd, c_c, -c_m); c_m = c_c; c_c = t;
+        t = fma(two_cd, s_c, -s_m); s_m = s_c; s_c = t;
+      }
+      if (kD) {
+        double t;
+        t = fma(two_cd, a_c, -a_m); a_m = a_c; a_c = t;
+        t = fma(two_cd, b_c, -b_m); b_m = b_c; b_c = t;
+        t = fma(two_cd, sa_c, -sa_m); sa_m = sa_c; sa_c = t;
+        t = fma(two_cd, sb_c, -sb_m); sb_m = sb_c; sb_c = t;
+      }
+    }
+    QBX_PIN4(hm_r, hm_i, hc_r, hc_i);
+    if (kS) {
+      QBX_PIN4(c_m, c_c, s_m, s_c);
+      QBX_PIN4(sKR.r, sKR.i, sKt.r, sKt.i);
+    }
+    if (kD) {
+      QBX_PIN4(a_m, a_c, b_m, b_c);
+      QBX_PIN4(sa_m, sa_c, sb_m, sb_c);
+      QBX_PIN4(dKR.r, dKR.i, dKt.r, dKt.i);
+    }
+  }
+  GradOut o;
+  const double H0r = h.h0r, H0i = h.h0i;
+  if (kS) {
+    o.KRs = {k * fma(2.0, sKR.r, Jd[0] * H0r), k * fma(2.0, sKR.i, Jd[0] * H0i)};
+    o.Kts = {-2.0 * sKt.r, -2.0 * sKt.i};
+  }
+  if (kD) {
+    // the m = 0 terms exist only when p >= 1
+    const double g0 = P >= 1 ? J[1] * sps : 0.0, fR0 = P >= 1 ? Jd[1] * cps : 0.0;
+    o.KRd = {k * k * fma(fR0, H0r, dKR.r), k * k * fma(fR0, H0i, dKR.i)};
+    o.Ktd = {k * fma(-g0, H0r, dKt.r), k * fma(-g0, H0i, dKt.i)};
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
 // per-pair sums of the adjoint once the cotangent is known.  Every gradient
 // but the density's uses a derivative sum X only through Re(w X), w = G_i q_j
 // (one weight per kind), and Re(w H_l) obeys the Hankel recurrence itself (its
@@ -563,6 +652,62 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
   for (int kk = 0; kk < NK; ++kk)
 #pragma unroll
     for (int b = 0; b < 5; ++b) wave_sum(A[kk][b]);
+}
+
+// ---------------------------------------------------------------------------
+// target derivatives: one wave, one center, chunks [c0, c1); A[kind][0..1] =
+// sums of w*density times K_R and K_theta, reduced over the wave
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
+                                            const double2* __restrict__ dens, int N,
+                                            const CenterRec* __restrict__ Crec,
+                                            const double* __restrict__ Jtab, int NJ, double k,
+                                            int c0, int c1, int lane, Cplx (&A)[2][2]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const double cx = Crec->cx, cy = Crec->cy, ct = Crec->ct, st = Crec->st;
+  const double inv_k = 1.0 / k;
+  const int nj = NJ / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
+  for (int c = c0; c < c1; ++c) {
+    const int j = c * kWave + lane;
+    if (j < N) {
+      const int z0 = opaque_zero();
+      const double* __restrict__ J = Jtab + z0;
+      const double* __restrict__ cf = g_seed_table + z0;
+      const double4 g = geo[j];
+      const double vx = g.x - cx, vy = g.y - cy;
+      const double rho2 = fma(vx, vx, vy * vy);
+      const double ir = rsqrt_refined(rho2);
+      const double rho = rho2 * ir;
+      const double cd = (ct * vx + st * vy) * ir;
+      const double sd = (st * vx - ct * vy) * ir;
+      double cps = 0.0, sps = 0.0;
+      if (kD) {
+        cps = ct * g.z + st * g.w;
+        sps = st * g.z - ct * g.w;
+      }
+      const GradOut o = grad_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+      if (kS) {
+        const double2 w = dens[j];
+        cmul_acc(A[0][0], w.x, w.y, o.KRs);
+        cmul_acc(A[0][1], w.x, w.y, o.Kts);
+      }
+      if (kD) {
+        const double2 w = dens[(kS ? (size_t)N : 0) + j];
+        cmul_acc(A[NK - 1][0], w.x, w.y, o.KRd);
+        cmul_acc(A[NK - 1][1], w.x, w.y, o.Ktd);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    wave_sum(A[kk][0]);
+    wave_sum(A[kk][1]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -150,3 +150,26 @@ def flops_fused_pair(p: int, kind: int) -> int:
     D = bool(kind & 2)
     center = (1 if D else 0) + (2 if S and D else 0)
     return _proj_outer(kind) + center + _proj_sums_flops(p, kind, True)
+
+
+def flops_grad_pair(p: int, kind: int) -> int:
+    """Target-derivative pair kernel: the sums of q K_R and q K_theta per kind."""
+    S = bool(kind & 1)
+    D = bool(kind & 2)
+    lmax = p + 1 if D else p
+    f = 17 + (6 if D else 0)                    # geometry (and the normal's angle)
+    f += 16 * (int(S) + int(D))                 # two complex MACs with q per kind
+    f += SEED + 2 + (12 if D else 0)            # seed, 2/z and 2 cos D, cos/sin(D +- psi)
+    for l in range(1, lmax + 1):
+        if S and l <= p:
+            f += 5 + 6                          # K_R (Jd c, MAC); K_theta (l J s, MAC)
+        if D:
+            up = l <= p - 1
+            f += (7 if up else 5) + (9 if up else 6)   # K_R; K_theta
+        if l < lmax:
+            f += 5 + (4 if S else 0) + (8 if D else 0)   # H_{l+1} and 2l/z; Chebyshev
+    if S:
+        f += 10
+    if D:
+        f += 20
+    return f

@@ -108,6 +108,13 @@ def test_gradient_entry_point_validates(lib):
                                             1 << 40, None) == _lib.QBX_EINVAL
 
 
+def test_timer_class_count_matches_header():
+    """qbx_kernel_timer_read writes QBX_TIMER_CLASSES entries into caller arrays: the
+    binding's constant must be the header's."""
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "qbx.h")).read()
+    assert int(re.search(r"#define QBX_TIMER_CLASSES (\d+)", hdr).group(1)) == _lib.QBX_TIMER_CLASSES
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert len(lib.qbx_strerror(code)) > 3
