@@ -50,10 +50,11 @@
 //   d/dtheta': cos(l Delta) -> l sin(l Delta), cos(m Delta +- psi) -> m sin(..)
 //   d/dtheta:  Delta and psi both move: cos(m Delta +- psi) -> -(m +- 1) sin(..)
 //   d/dpsi (D, through the source normal's angle).
-// Source side (sum over centers, source-major pass):
+// Source side (sum over centers, source-major or fused pass):
 //   grad(w sigma)_j = sum_i conj(G_i K_ij),
-//   grad x'_j = Re w_j sigma_j sum_i G_i (K_rho v^ + K_theta' theta^ / rho),
-//   grad nu_j = Re w_j mu_j sum_i G_i K_psi (n_y, -n_x).
+//   grad x'_j = sum_i Re G_i w_j sigma_j (K_rho v^ + K_theta' theta^ / rho),
+//   grad nu_j = sum_i Re G_i w_j mu_j K_psi (n_y, -n_x),
+// with the derivative sums projected on G_i w_j sigma_j per pair (pair_sums_proj).
 // Center side (sum over sources, center-major tape pass): the forward also
 // stores F_R = sum_j w sigma K_R, F_t = sum_j w sigma K_theta and
 // GV = sum_j w sigma (K_rho v^ + K_theta' theta^/rho); then with c fixed the
@@ -711,11 +712,11 @@ __device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
 }
 
 // ---------------------------------------------------------------------------
-// fused adjoint pair: one evaluation of the tape-mode pair sums feeds both the
-// source side (accumulated into A, the layout of the source-major pass, with
-// K_psi = K_theta + K_theta' for D: the target angle moves Delta and psi, the
-// source angle only Delta) and the center side, returned contracted with the
-// cotangent and summed over kinds: cres = Re(G q) of K_R, K_theta, grad_v K.
+// fused adjoint pair: one evaluation of the projected pair sums feeds both the
+// source side (accumulated into A, the src_slots layout of the source-major
+// pass; for D, K_theta = K_psi - K_theta': the target angle moves Delta and psi,
+// the source angle only Delta) and the center side, four reals summed over
+// kinds: cres = Re(G q) of K_R, K_theta and the two components of grad_v K.
 // q: weighted densities of the source per kind; Gk: G of the center per kind.
 // ---------------------------------------------------------------------------
 template <int P, int KIND>
