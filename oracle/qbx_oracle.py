@@ -33,6 +33,9 @@ gradients of the discrete map:
 * Section 3.2: target derivatives by analytic differentiation of the local
   expansion (``evaluate_gradient``, ``layer_potential_gradient``), through the
   ladder relations of the regular waves J_l e^{i l theta} in x and y.
+* Section 5: the near/far split (``layer_potential_split``): QBX only for
+  sources on panels near the target's panel, the smooth rule applied directly
+  at the target for all others.
 
 Two modes:
 * ``mode="dense"``: every order l evaluated by its own library call
@@ -407,6 +410,102 @@ def layer_potential_gradient(nodes, density, k: float, p: int, r: float = 0.5,
     g = torch.stack(grads)
     dn = g[..., 0] * n_tgt[:, 0].to(_C128) + g[..., 1] * n_tgt[:, 1].to(_C128)
     return g, dn
+
+
+# ---------------------------------------------------------------------------
+# Section 5: direct evaluation for distant panels, QBX for the near ones
+# ---------------------------------------------------------------------------
+def panel_bounds(nodes) -> Tuple[np.ndarray, np.ndarray]:
+    """Per panel: b_m, the mean of its 16 nodes (added in node order, then times
+    1/16), and rad2_m = max_a |X_{m,a} - b_m|^2.  Returns (b [P, 2], rad2 [P])."""
+    X = np.asarray(nodes.detach().numpy() if isinstance(nodes, torch.Tensor) else nodes,
+                   dtype=np.float64)
+    sx, sy = X[:, 0, 0].copy(), X[:, 0, 1].copy()
+    for a in range(1, Q):
+        sx = sx + X[:, a, 0]
+        sy = sy + X[:, a, 1]
+    bx, by = sx * 0.0625, sy * 0.0625
+    dx = X[:, :, 0] - bx[:, None]
+    dy = X[:, :, 1] - by[:, None]
+    rad2 = (dx * dx + dy * dy).max(axis=1)
+    return np.stack([bx, by], axis=1), rad2
+
+
+def near_panels(nodes, gamma: float) -> np.ndarray:
+    """near[m, m'] (bool [P, P]): source panel m' is near target panel m when
+    |b_m - b_m'|^2 < gamma^2 max(rad2_m, rad2_m') (no fused multiply-add anywhere,
+    so any IEEE double implementation takes the same decisions)."""
+    b, rad2 = panel_bounds(nodes)
+    g2 = float(gamma) * float(gamma)
+    dx = b[:, None, 0] - b[None, :, 0]
+    dy = b[:, None, 1] - b[None, :, 1]
+    return (dx * dx + dy * dy) < g2 * np.maximum(rad2[:, None], rad2[None, :])
+
+
+def direct_sum(src, dens, tx, ty, k: float, kind: int, sel) -> Dict[str, torch.Tensor]:
+    """Smooth-rule sums over the sources ``sel`` at the targets (tx, ty) [C], without
+    the i/4: S: sum_j w_j sigma_j H_0(k rho_j); D: sum_j w_j mu_j dH_0(k|x - x'_j|)/dn'_j
+    = sum_j w_j mu_j k H_1(k rho_j) (x - x'_j).n_j / rho_j.  sel: [C, N] bool."""
+    dx = tx[:, None] - src["x"][None, :]
+    dy = ty[:, None] - src["y"][None, :]
+    rho = torch.sqrt(dx * dx + dy * dy)
+    # rho of an excluded pair may be 0: evaluate there at 1 and drop the term
+    z = k * torch.where(sel, rho, torch.ones_like(rho))
+    out = {}
+    if kind & S_KIND:
+        out["S"] = torch.where(sel, hankel1(0, z) * dens["S"][None, :], 0.0).sum(dim=1)
+    if kind & D_KIND:
+        ndot = (dx * src["nx"][None, :] + dy * src["ny"][None, :]) / torch.where(sel, rho, 1.0)
+        term = k * hankel1(1, z) * ndot * dens["D"][None, :]
+        out["D"] = torch.where(sel, term, 0.0).sum(dim=1)
+    return out
+
+
+def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, oversample: int = 4,
+                          side: int = EXTERIOR, kind: int = S_KIND, gamma: float = 6.0,
+                          targets=None, mode: str = "fast"):
+    """One-sided limits with the near/far split of Section 5: for the targets of
+    panel m, the sources of panels near m (``near_panels``) enter through the QBX
+    expansion about each target's center (coefficients summed over those sources
+    only, evaluated as in ``layer_potential``), and all other sources through the
+    smooth rule applied directly at the target, (i/4) ``direct_sum``.  Same
+    arguments and layout as ``layer_potential``.
+
+    The near sources alone form an open patch whose ends lie about gamma*rad from
+    the target; their local expansion converges like (R/d_end)^(p+1), so the split
+    adds an error of that size to the QBX error (gamma = 6 suits p = 20; p = 10
+    needs gamma near 16 for 1e-12)."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    kinds = kinds_of(kind)
+    P = nodes.shape[0]
+    src = source_grid(nodes, oversample)
+    qs = Q * oversample
+    fine = interpolate_density(density, oversample)
+    dens = {kk: src["w"].to(_C128) * fine[i] for i, kk in enumerate(kinds)}
+    near = near_panels(nodes, gamma)
+    tidx = np.arange(P * Q) if targets is None else np.asarray(targets, dtype=np.int64)
+    xy = nodes.reshape(-1, 2)
+    src_panel = np.arange(P * qs) // qs
+    sides = sides_of(side)
+    ctrs = [expansion_centers(nodes, src["h"], src["n_tgt"], r, s) for s in sides]
+    u = torch.zeros(len(sides), len(kinds), len(tidx), dtype=_C128)
+    for m in np.unique(tidx // Q):
+        rows = np.nonzero(tidx // Q == m)[0]
+        ti = torch.as_tensor(tidx[rows], dtype=torch.long)
+        near_src = near[m][src_panel]
+        ni = torch.as_tensor(np.nonzero(near_src)[0], dtype=torch.long)
+        sub = {key: src[key][ni] for key in ("x", "y", "nx", "ny")}
+        dsub = {kk: dens[kk][ni] for kk in kinds}
+        far = torch.as_tensor(np.broadcast_to(~near_src, (len(rows), near_src.size)).copy())
+        dsum = direct_sum(src, dens, xy[ti, 0], xy[ti, 1], k, kind, far)   # same for both sides
+        for si in range(len(sides)):
+            ctr = {key: val[ti] for key, val in ctrs[si].items()}
+            a = coefficients(sub, dsub, ctr, k, p, kind, mode)
+            for i, kk in enumerate(kinds):
+                u[si, i, torch.as_tensor(rows)] = (evaluate(a[kk], ctr["R"], ctr["theta"], k, p, mode)
+                                                   + 0.25j * dsum[kk])
+    return u
 
 
 def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float, p: int,
