@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("QBX source-center interactions/s, fwd & fwd+bwd, FP64 @≤1e-11 rel; "
           "% FP64 peak")
+SPLIT_METRIC = ("QBX layer potential with the near/far split of Section 5, FP64 @<=1e-11 rel "
+                "to the split oracle: the workload's centers x sources per second")
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
 
 
@@ -69,8 +71,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
-    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad"],
-                    help="grad: the target derivatives (grad S, grad D, S', D') instead")
+    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad", "split"],
+                    help="grad: the target derivatives (grad S, grad D, S', D') instead; "
+                         "split: the forward with the near/far split (QBX for near panels "
+                         "only, the smooth rule applied directly for the rest)")
+    ap.add_argument("--gamma", type=float, default=6.0,
+                    help="split mode: panels within gamma panel radii count as near")
     ap.add_argument("--backward", default="fused", choices=["fused", "tape"],
                     help="fwdbwd step: plain forward + fused adjoint (default), or forward "
                          "with tape + source-major adjoint")
@@ -135,7 +141,7 @@ def main():
     dens = torch.from_numpy(np.ascontiguousarray(pb.density)).to(dev)
     cot = torch.from_numpy(np.ascontiguousarray(pb.cotangent)).to(dev)
     tuning = qbx.get_tuning()
-    if args.autotune:
+    if args.autotune and mode != "split":   # the split's launch shapes are fixed
         t0 = time.perf_counter()
         tuning = qbx.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
                               passes=1, fields=tune_fields(mode, args.backward))
@@ -158,6 +164,9 @@ def main():
         if mode == "grad":
             return qbx.layer_potential_gradient(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
                                                 pb.side, pb.kind, workspace=ws)
+        if mode == "split":
+            return qbx.layer_potential_split(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
+                                             pb.side, pb.kind, gamma=args.gamma, workspace=ws)
         if args.backward == "fused":
             # forward, then the adjoint without a tape (one fused pass over the pairs)
             u = fwd()
@@ -204,24 +213,29 @@ def main():
     pairs = pb.n_centers * pb.n_sources
     names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel",
              "forward-with-tape pair kernel", "fused adjoint pair kernel",
-             "target-derivative pair kernel"]
+             "target-derivative pair kernel", "split near pass", "split far pass"]
     per_pair = [flops.flops_forward_pair(pb.p, pb.kind), flops.flops_adjoint_pair(pb.p, pb.kind),
                 0, flops.flops_tape_pair(pb.p, pb.kind), flops.flops_fused_pair(pb.p, pb.kind),
-                flops.flops_grad_pair(pb.p, pb.kind)]
+                flops.flops_grad_pair(pb.p, pb.kind), flops.flops_forward_pair(pb.p, pb.kind),
+                flops.flops_far_pair(pb.kind)]
+    pairs_of = [pairs] * 6 + [0, 0]
+    if mode == "split":
+        pairs_of[6], pairs_of[7] = flops.split_pairs(pb.nodes, pb.oversample, pb.n_sides,
+                                                     args.gamma)
     kernels = {}
     for c in range(NC):
         if nl[c] == 0 or per_pair[c] == 0:
             continue
         avg = ms[c] / nl[c]
-        fl = per_pair[c] * pairs
-        kernels[names[c]] = {"avg_ms": round(avg, 4), "launches": int(nl[c]),
+        fl = per_pair[c] * pairs_of[c]
+        kernels[names[c]] = {"avg_ms": round(avg, 4), "launches": int(nl[c]), "pairs": pairs_of[c],
                              "flop_per_launch": fl, "tflops": round(fl / (avg * 1e-3) / 1e12, 3)}
     cls = max((c for c in range(NC) if nl[c] and per_pair[c]), key=lambda c: ms[c])
     dom = kernels[names[cls]]
     achieved = dom["tflops"]
     avg_ms = dom["avg_ms"]
     kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape", "k_adjoint_fused",
-                    "k_forward_grad"]
+                    "k_forward_grad", "k_split_near", "k_split_far"]
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(kernel_names[cls], args.workload),
@@ -237,39 +251,44 @@ def main():
 
         rng = np.random.default_rng(0)
         # calibrate on 2 targets, then size the sample for about --cpu-seconds
+        def oracle_at(idx):
+            if mode == "grad":
+                return O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                                  pb.oversample, pb.side, pb.kind,
+                                                  targets=idx)[1].numpy()
+            if mode == "split":
+                return O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                               pb.oversample, pb.side, pb.kind, gamma=args.gamma,
+                                               targets=idx).numpy()
+            return O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                     pb.side, pb.kind, targets=idx).numpy()
+
         t0 = time.perf_counter()
-        O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
-                          targets=np.arange(2))
+        oracle_at(np.arange(2))
         per = (time.perf_counter() - t0) / 2
         n = int(min(pb.n_targets, max(2, args.cpu_seconds / max(per, 1e-6))))
         idx = np.sort(rng.choice(pb.n_targets, size=n, replace=False))
         t0 = time.perf_counter()
-        if mode == "grad":
-            ref = O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
-                                             pb.oversample, pb.side, pb.kind,
-                                             targets=idx)[1].numpy()
-        else:
-            ref = O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
-                                    pb.side, pb.kind, targets=idx).numpy()
+        ref = oracle_at(idx)
         tc = time.perf_counter() - t0
         ncent = len(idx) * pb.n_sides
         cpu_inter = flops.interactions(ncent, pb.n_sources, pb.kind)
         if mode == "grad":
             u = step()[1].cpu().numpy()[:, :, idx]
         else:
-            u = fwd().cpu().numpy()[:, :, idx]
+            u = step().cpu().numpy()[:, :, idx] if mode == "split" else fwd().cpu().numpy()[:, :, idx]
         err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
                         for s in range(u.shape[0]) for k in range(u.shape[1])))
         cpu = {"value": cpu_inter / tc, "unit": "interactions/s", "cores": torch.get_num_threads(),
                "kind": "oracle",
-               "sample": f"{'normal derivative' if mode == 'grad' else 'forward'} at "
+               "sample": f"{ {'grad': 'normal derivative', 'split': 'split forward'}.get(mode, 'forward')} at "
                          f"{len(idx)} random targets x {pb.n_sides} sides "
                          f"({ncent} centers) against all {pb.n_sources} sources, "
                          f"{tc:.1f} s; GPU/oracle max rel err on the sample {err:.2e}"}
         log(f"cpu oracle: {cpu_inter / tc:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if mode != "split" else SPLIT_METRIC,
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -286,6 +305,7 @@ def main():
                                f"side={'both' if pb.side == 0 else pb.side}, "
                                f"kind={'S+D' if pb.kind == 3 else ('S' if pb.kind == 1 else 'D')}",
                    "mode": mode, "backward": args.backward if mode == "fwdbwd" else None,
+                   "gamma": args.gamma if mode == "split" else None,
                    "centers": pb.n_centers, "sources": pb.n_sources,
                    "interactions_per_step": inter, "tuning": tuning},
         "fwd_value": inter / fwd_s,

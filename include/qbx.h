@@ -124,6 +124,29 @@ int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, d
                                  double r, int oversample, int side, int kind, double* grad,
                                  double* dn, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Near/far split of the forward (Section 5: QBX is needed only where a panel
+ * is close to the target; distant panels are summed directly by the smooth
+ * source rule).  Source panel m' is near target panel m when
+ *   |b_m - b_m'|^2 < gamma^2 max(rad2_m, rad2_m'),
+ * b_m the mean of the panel's 16 nodes (added in node order, times 1/16) and
+ * rad2_m = max_a |X_{m,a} - b_m|^2, every operation rounded on its own (no
+ * fused multiply-add), so the decision is reproducible bit for bit.  Near
+ * sources enter through the QBX expansion exactly as in qbx_layer_potential;
+ * every other source x' adds (i/4) w sigma H_0(k|x - x'|) (S) or
+ * (i/4) w mu dH_0(k|x - x'|)/dn' (D) at the target x itself.
+ *   gamma > 0 (QBX_EINVAL otherwise); gamma^2 above the largest double makes
+ *   every panel near, which is qbx_layer_potential.  Accuracy: the near
+ *   sources alone form an open patch whose ends lie about gamma * sqrt(rad2)
+ *   from the target, so the expansion adds an error near
+ *   (r h / (gamma sqrt(rad2)))^(p+1); gamma = 6 suits p = 20, p = 10 needs
+ *   about 16 for 1e-12.
+ * Other arguments and out as qbx_layer_potential; no tape (this variant has
+ * no adjoint).  Stream-ordered, no allocation; the workspace is
+ * qbx_workspace_bytes(). */
+int qbx_layer_potential_split(const qbx_geometry* g, const double* density, double k, int p,
+                              double r, int oversample, int side, int kind, double gamma,
+                              double* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- adjoint ----------------------------------------------------------- */
 
 /* Vector-Jacobian product of qbx_layer_potential for the real scalar
@@ -372,10 +395,11 @@ int qbx_kernel_timer(int enable);
 /* SYNCHRONOUS: waits for the recorded events and returns, per kernel class
  * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
  * kernels, 3 = forward-with-tape pair kernel, 4 = fused adjoint pair kernel,
- * 5 = target-derivative pair kernel),
+ * 5 = target-derivative pair kernel, 6 = near pass of the split forward,
+ * 7 = far pass of the split forward),
  * the summed duration in milliseconds and the number of launches since the
  * timer was enabled.  ms and launches are host arrays of QBX_TIMER_CLASSES. */
-#define QBX_TIMER_CLASSES 6
+#define QBX_TIMER_CLASSES 8
 int qbx_kernel_timer_read(double* ms, int* launches);
 
 #ifdef __cplusplus

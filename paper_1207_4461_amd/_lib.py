@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqbx.so")
 
 QBX_TUNE_FORWARD, QBX_TUNE_TAPE, QBX_TUNE_ADJOINT, QBX_TUNE_FUSED, QBX_TUNE_ALL = 1, 2, 4, 8, 15
-QBX_TIMER_CLASSES = 6   # entries qbx_kernel_timer_read writes
+QBX_TIMER_CLASSES = 8   # entries qbx_kernel_timer_read writes
 QBX_OK = 0
 QBX_EINVAL = -1
 QBX_EWORKSPACE = -2
@@ -73,6 +73,8 @@ def load() -> C.CDLL:
         "qbx_layer_potential": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]),
         "qbx_layer_potential_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
                                                sz, vp]),
+        "qbx_layer_potential_split": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl, vp, vp,
+                                            sz, vp]),
         "qbx_layer_potential_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
                                               vp, vp, sz, vp]),
         "qbx_check_geometry": (i32, [gp, i32, dbl, i32, i32, C.POINTER(dbl), C.POINTER(dbl), vp,

@@ -41,6 +41,7 @@ static int g_forward_waves = 16384;
 static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
 static int g_fused_tiles = 16384;  // fused adjoint workgroups aimed for
+static const int kSplitFarWaves = 16384;  // far-pass wavefronts aimed for
 
 void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves, int fused_tiles) {
   g_forward_waves = forward_waves;
@@ -95,6 +96,14 @@ void set_launch_shape(Dims* d) {
   if (sbs < 1) sbs = 1;
   d->chunks_per_sb = (int)((d->chunks + sbs - 1) / sbs);
   d->n_sb = (d->chunks + d->chunks_per_sb - 1) / d->chunks_per_sb;
+  // split forward, far pass: 64 targets a wave; enough source splits (runs of
+  // whole panels) for about kSplitFarWaves waves
+  const long n_tb = ((long)d->T + kWave - 1) / kWave;
+  long fs = (kSplitFarWaves + n_tb - 1) / n_tb;
+  if (fs > d->P) fs = d->P;
+  if (fs < 1) fs = 1;
+  d->panels_per_fsplit = (int)((d->P + fs - 1) / fs);
+  d->n_fsplit = (d->P + d->panels_per_fsplit - 1) / d->panels_per_fsplit;
 }
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
@@ -150,6 +159,8 @@ Layout make_layout(const Dims& d) {
   L.cpart = take(sizeof(double) * (size_t)d.n_sb * d.Mc * 4);
   L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
+  L.bnd = take(sizeof(double4) * (size_t)d.P);
+  L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T);
   L.total = o;
   return L;
 }
@@ -282,6 +293,40 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
   if (e != hipSuccess) return device_fail(e, "forward kernel");
   e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
   if (e != hipSuccess) return device_fail(e, "finalize kernel");
+  return QBX_OK;
+}
+
+int qbx_layer_potential_split(const qbx_geometry* g, const double* density, double k, int p,
+                              double r, int oversample, int side, int kind, double gamma,
+                              double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!(gamma > 0.0)) return fail(QBX_EINVAL, "near-panel factor gamma = %g must be > 0", gamma);
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!out) return fail(QBX_EINVAL, "out is NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  const double g2 = gamma * gamma;
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  timer_begin(6, stream);
+  e = launch_split_near(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                        at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab), at<double4>(ws, L.bnd),
+                        g2, at<double2>(ws, L.partial), stream);
+  timer_end(6, stream);
+  if (e != hipSuccess) return device_fail(e, "split near kernel");
+  timer_begin(7, stream);
+  e = launch_split_far(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens), g->nodes,
+                       at<double4>(ws, L.bnd), g2, at<double2>(ws, L.fpart), stream);
+  timer_end(7, stream);
+  if (e != hipSuccess) return device_fail(e, "split far kernel");
+  e = launch_split_finalize(d, at<double2>(ws, L.partial), at<double2>(ws, L.fpart), out, stream);
+  if (e != hipSuccess) return device_fail(e, "split finalize kernel");
   return QBX_OK;
 }
 

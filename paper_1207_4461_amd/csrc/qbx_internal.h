@@ -48,6 +48,9 @@ struct Dims {
   // fused adjoint launch shape: workgroup tiles of fused_cblock centers x
   // chunks_per_sb 64-source chunks, n_cb x n_sb tiles
   int fused_cblock, n_cb, n_sb, chunks_per_sb;
+  // split forward, far pass: waves of 64 targets x panels_per_fsplit source
+  // panels, n_fsplit source splits
+  int n_fsplit, panels_per_fsplit;
 };
 
 // Byte offsets of the workspace arrays (all 256-byte aligned).
@@ -67,6 +70,8 @@ struct Layout {
   size_t cpart;    // double[n_sb][Mc][4] fused adjoint: center-side partial sums
   size_t sg;       // double[N][8] per-source gradients
   size_t scratch;  // double[16 + Mc] small reductions
+  size_t bnd;      // double4[P] split forward: panel mean and squared radius
+  size_t fpart;    // double2[n_fsplit][nk][T] split forward: far sums
   size_t total;
 };
 
@@ -114,6 +119,18 @@ hipError_t launch_forward(const Dims& d, const double4* geo, const double2* dens
 hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s);
 hipError_t launch_principal_value(int T, int nk, int side, int kind, const double* out,
                                   const double* density, double* pv, hipStream_t s);
+// ---- split forward (qbx_split.hip) ----
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s);
+// partial [nk][Mc]: QBX sums over the sources of near panels
+hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
+                             const CenterRec* ctr, const double* jtab, const double4* bnd,
+                             double g2, double2* partial, hipStream_t s);
+// partial [n_fsplit][nk][T]: direct sums over the sources of far panels
+hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
+                            const double* nodes, const double4* bnd, double g2, double2* partial,
+                            hipStream_t s);
+hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const double2* farp,
+                                 double* out, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,

@@ -531,6 +531,49 @@ QBX_UNROLL_BY(QBX_FWD_UNROLL)
 
 
 // ---------------------------------------------------------------------------
+// forward, one pair: source j for the center (cx, cy) whose target lies in
+// direction (ct, st); adds w sigma K_S and w mu K_D / k to the lane's sums
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void forward_source(const double4* __restrict__ geo,
+                                               const double2* __restrict__ dens, int N, int j,
+                                               double cx, double cy, double ct, double st,
+                                               double k, double inv_k,
+                                               const double* __restrict__ Jtab, double& accS_r,
+                                               double& accS_i, double& accD_r, double& accD_i) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  // uniform tables re-read (scalar cache) every iteration, see opaque_zero()
+  const int z0 = opaque_zero();
+  const double* __restrict__ J = Jtab + z0;
+  const double* __restrict__ cf = g_seed_table + z0;
+  const double4 g = geo[j];
+  const double vx = g.x - cx, vy = g.y - cy;
+  const double rho2 = fma(vx, vx, vy * vy);
+  const double ir = rsqrt_refined(rho2);
+  const double rho = rho2 * ir;
+  const double cd = (ct * vx + st * vy) * ir;   // cos(theta_i - theta')
+  const double sd = (st * vx - ct * vy) * ir;   // sin(theta_i - theta')
+  double cps = 0.0, sps = 0.0;
+  if (kD) {
+    cps = ct * g.z + st * g.w;                   // cos(theta_i - arg nu)
+    sps = st * g.z - ct * g.w;                   // sin(theta_i - arg nu)
+  }
+  double s_r, s_i, d_r, d_i;
+  pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, s_r, s_i, d_r, d_i);
+  if (kS) {
+    const double2 w = dens[j];
+    accS_r = fma(w.x, s_r, fma(-w.y, s_i, accS_r));
+    accS_i = fma(w.x, s_i, fma(w.y, s_r, accS_i));
+  }
+  if (kD) {
+    const double2 w = dens[(kS ? (size_t)N : 0) + j];
+    accD_r = fma(w.x, d_r, fma(-w.y, d_i, accD_r));
+    accD_i = fma(w.x, d_i, fma(w.y, d_r, accD_i));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // forward: one wave, one center, sources of chunks [c0, c1); returns the sums
 // of w sigma K_S and w mu K_D / k reduced over the wave (in every lane)
 // ---------------------------------------------------------------------------
@@ -547,36 +590,9 @@ __device__ __forceinline__ void forward_center(const double4* __restrict__ geo,
   double accS_r = 0.0, accS_i = 0.0, accD_r = 0.0, accD_i = 0.0;
   for (int c = c0; c < c1; ++c) {
     const int j = c * kWave + lane;
-    if (j < N) {
-      // uniform tables re-read (scalar cache) every iteration, see opaque_zero()
-      const int z0 = opaque_zero();
-      const double* __restrict__ J = Jtab + z0;
-      const double* __restrict__ cf = g_seed_table + z0;
-      const double4 g = geo[j];
-      const double vx = g.x - cx, vy = g.y - cy;
-      const double rho2 = fma(vx, vx, vy * vy);
-      const double ir = rsqrt_refined(rho2);
-      const double rho = rho2 * ir;
-      const double cd = (ct * vx + st * vy) * ir;   // cos(theta_i - theta')
-      const double sd = (st * vx - ct * vy) * ir;   // sin(theta_i - theta')
-      double cps = 0.0, sps = 0.0;
-      if (kD) {
-        cps = ct * g.z + st * g.w;                   // cos(theta_i - arg nu)
-        sps = st * g.z - ct * g.w;                   // sin(theta_i - arg nu)
-      }
-      double s_r, s_i, d_r, d_i;
-      pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, s_r, s_i, d_r, d_i);
-      if (kS) {
-        const double2 w = dens[j];
-        accS_r = fma(w.x, s_r, fma(-w.y, s_i, accS_r));
-        accS_i = fma(w.x, s_i, fma(w.y, s_r, accS_i));
-      }
-      if (kD) {
-        const double2 w = dens[(kS ? (size_t)N : 0) + j];
-        accD_r = fma(w.x, d_r, fma(-w.y, d_i, accD_r));
-        accD_i = fma(w.x, d_i, fma(w.y, d_r, accD_i));
-      }
-    }
+    if (j < N)
+      forward_source<P, KIND>(geo, dens, N, j, cx, cy, ct, st, k, inv_k, Jtab, accS_r, accS_i,
+                              accD_r, accD_i);
   }
   S = {accS_r, accS_i};
   Dd = {accD_r, accD_i};

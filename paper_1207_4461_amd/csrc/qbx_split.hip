@@ -1,0 +1,238 @@
+// Near/far split of the forward (Section 5: QBX only for the panels near a
+// target, direct evaluation by the smooth source rule for all others).
+//
+// Near relation.  Per panel, b_m is the mean of its 16 nodes (added in node
+// order, then times 1/16) and rad2_m = max_a |X_{m,a} - b_m|^2.  Source panel m'
+// is near target panel m when
+//     |b_m - b_m'|^2 < gamma^2 max(rad2_m, rad2_m').
+// Every product and sum of the test is rounded on its own (contraction off), so
+// the near pass, the far pass and any IEEE double evaluation of the same formula
+// take the same decisions.  A panel is always near itself (gamma > 0).
+//
+// Near pass (k_split_near): one wave per center, as the plain forward, but the
+// wave first tests 64 source panels at a time against its target's panel and
+// runs the QBX pair kernel (forward_source) over the sources of the near ones
+// only.  Far pass (k_split_far): the 64 lanes are 64 consecutive targets and the
+// sources of a run of panels are wave-uniform (scalar loads); a far pair adds
+//     S: w sigma H_0(k rho),    D: w mu k H_1(k rho) (x - x').n' / rho,
+// rho = |x - x'|, the normal derivative of H_0(k|x - x'|) at the source.  These
+// sums do not depend on the side, so both sides share one far pass.  The
+// finalize adds, per center, the near sum and the far sums of its target in a
+// fixed order and applies i/4.
+#include "qbx_pair.h"
+
+namespace qbx {
+
+__device__ __forceinline__ bool panels_near(double4 a, double4 b, double g2) {
+#pragma clang fp contract(off)
+  const double dx = a.x - b.x;
+  const double dy = a.y - b.y;
+  const double d2 = dx * dx + dy * dy;
+  return d2 < g2 * fmax(a.z, b.z);
+}
+
+// bnd[m] = {b_x, b_y, rad2, 0}
+__global__ __launch_bounds__(256) void k_panel_bounds(int NP, const double* __restrict__ nodes,
+                                                      double4* __restrict__ bnd) {
+#pragma clang fp contract(off)
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= NP) return;
+  const double* X = nodes + (size_t)m * 2 * kQ;
+  double sx = X[0], sy = X[1];
+  for (int a = 1; a < kQ; ++a) {
+    sx = sx + X[2 * a];
+    sy = sy + X[2 * a + 1];
+  }
+  const double bx = sx * 0.0625, by = sy * 0.0625;
+  double r2 = 0.0;
+  for (int a = 0; a < kQ; ++a) {
+    const double dx = X[2 * a] - bx;
+    const double dy = X[2 * a + 1] - by;
+    r2 = fmax(r2, dx * dx + dy * dy);
+  }
+  bnd[m] = make_double4(bx, by, r2, 0.0);
+}
+
+// partial[kk][ci]: QBX sums of center ci over the sources of near panels
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_split_near(const double4* __restrict__ geo,
+                                                    const double2* __restrict__ dens, int N,
+                                                    int qs, const CenterRec* __restrict__ ctr,
+                                                    const double* __restrict__ jtab, int NJ,
+                                                    int Mc, int T, const double4* __restrict__ bnd,
+                                                    int NP, double g2, double k,
+                                                    double2* __restrict__ partial) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ci = blockIdx.x * 4 + wave;
+  if (ci >= Mc) return;
+  const int m = (ci % T) / kQ;                 // the target's panel
+  const double4 bm = bnd[m];
+  const CenterRec* C = ctr + ci;
+  const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
+  const double inv_k = 1.0 / k;
+  const double* Jtab = jtab + (size_t)ci * NJ;
+  double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mp = w0 + lane;
+    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
+    unsigned long long mask = __ballot(nr);
+    while (mask) {
+      const int pan = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      for (int s0 = 0; s0 < qs; s0 += kWave) {
+        if (s0 + lane < qs)
+          forward_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k,
+                                  Jtab, sr, si, dr, di);
+      }
+    }
+  }
+  Cplx S = {sr, si}, Dd = {dr, di};
+  if (kS) wave_sum(S);
+  if (kD) wave_sum(Dd);
+  if (lane == 0) {
+    int kk = 0;
+    if (kS) partial[(size_t)(kk++) * Mc + ci] = make_double2(S.r, S.i);
+    if (kD) partial[(size_t)kk * Mc + ci] = make_double2(k * Dd.r, k * Dd.i);
+  }
+}
+
+// partial[sp][kk][t]: direct sums of target t over the far sources of panels
+// [sp * ppw, (sp + 1) * ppw); wave gw = sp * n_tb + tb covers targets tb*64 ..
+template <int KIND>
+__global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ geo,
+                                                   const double2* __restrict__ dens, int N, int qs,
+                                                   const double* __restrict__ nodes, int T,
+                                                   const double4* __restrict__ bnd, int NP,
+                                                   double g2, double k, int n_tb, int n_fsplit,
+                                                   int ppw, double2* __restrict__ partial) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + wave;
+  const int sp = gw / n_tb;
+  const int tb = gw - sp * n_tb;
+  if (sp >= n_fsplit) return;
+  const int t = tb * kWave + lane;
+  const bool valid = t < T;
+  const int tt = valid ? t : T - 1;
+  const double tx = nodes[2 * (size_t)tt], ty = nodes[2 * (size_t)tt + 1];
+  const double4 bt = bnd[tt / kQ];
+  const int p0 = sp * ppw;
+  const int p1 = min(NP, p0 + ppw);
+  const double inv_k = 1.0 / k;
+  double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  for (int pm = p0; pm < p1; ++pm) {
+    const bool far = valid && !panels_near(bt, bnd[pm], g2);
+    if (far) {
+      const int j0 = pm * qs;
+      for (int b = 0; b < qs; ++b) {
+        const int z0 = opaque_zero();
+        const double* __restrict__ cf = g_seed_table + z0;
+        const int j = j0 + b;
+        const double4 g = geo[j];
+        const double dx = tx - g.x, dy = ty - g.y;
+        const double rho2 = fma(dx, dx, dy * dy);
+        const double ir = rsqrt_refined(rho2);
+        const double rho = rho2 * ir;
+        const H01 h = hankel01(k * rho, ir * inv_k, cf);
+        if (kS) {
+          const double2 w = dens[j];
+          sr = fma(w.x, h.h0r, fma(-w.y, h.h0i, sr));
+          si = fma(w.x, h.h0i, fma(w.y, h.h0r, si));
+        }
+        if (kD) {
+          const double2 w = dens[(kS ? (size_t)N : 0) + j];
+          const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
+          const double wr = w.x * f, wi = w.y * f;
+          dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
+          di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+        }
+      }
+    }
+  }
+  if (valid) {
+    int kk = 0;
+    if (kS) partial[((size_t)sp * NK + kk++) * T + t] = make_double2(sr, si);
+    if (kD) partial[((size_t)sp * NK + kk) * T + t] = make_double2(k * dr, k * di);
+  }
+}
+
+// out[si][kk][t] = (i/4) (near[kk][ci] + sum over far splits of far[sp][kk][t])
+__global__ __launch_bounds__(256) void k_split_finalize(int Mc, int T, int nk, int n_fsplit,
+                                                        const double2* __restrict__ nearp,
+                                                        const double2* __restrict__ farp,
+                                                        double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Mc * nk) return;
+  const int kk = e / Mc, ci = e - kk * Mc;
+  const int si = ci / T, t = ci - si * T;
+  const double2 v0 = nearp[(size_t)kk * Mc + ci];
+  double r = v0.x, im = v0.y;
+  for (int sp = 0; sp < n_fsplit; ++sp) {
+    const double2 v = farp[((size_t)sp * nk + kk) * T + t];
+    r += v.x;
+    im += v.y;
+  }
+  const size_t o = ((size_t)si * nk + kk) * T + t;
+  out[2 * o] = -0.25 * im;
+  out[2 * o + 1] = 0.25 * r;
+}
+
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s) {
+  hipLaunchKernelGGL(k_panel_bounds, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, nodes, bnd);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_split_near_p(const Dims& d, const double4* geo, const double2* dens,
+                                      const CenterRec* ctr, const double* jtab,
+                                      const double4* bnd, double g2, double2* partial,
+                                      hipStream_t s) {
+  const dim3 grid((unsigned)((d.Mc + 3) / 4)), block(256);
+#define QBX_NEAR_ARGS geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, d.k, partial
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_near<P, 1>), grid, block, 0, s, QBX_NEAR_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_near<P, 2>), grid, block, 0, s, QBX_NEAR_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_near<P, 3>), grid, block, 0, s, QBX_NEAR_ARGS); break;
+  }
+#undef QBX_NEAR_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
+                             const CenterRec* ctr, const double* jtab, const double4* bnd,
+                             double g2, double2* partial, hipStream_t s) {
+  QBX_P_SWITCH(d.p, launch_split_near_p, d, geo, dens, ctr, jtab, bnd, g2, partial, s)
+}
+
+hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
+                            const double* nodes, const double4* bnd, double g2, double2* partial,
+                            hipStream_t s) {
+  const int n_tb = (d.T + kWave - 1) / kWave;
+  const long waves = (long)n_tb * d.n_fsplit;
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_FAR_ARGS \
+  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, partial
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_far<1>), grid, block, 0, s, QBX_FAR_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_far<2>), grid, block, 0, s, QBX_FAR_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_far<3>), grid, block, 0, s, QBX_FAR_ARGS); break;
+  }
+#undef QBX_FAR_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const double2* farp,
+                                 double* out, hipStream_t s) {
+  const int n = d.Mc * d.nk;
+  hipLaunchKernelGGL(k_split_finalize, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
+                     d.n_fsplit, nearp, farp, out);
+  return hipGetLastError();
+}
+
+}  // namespace qbx

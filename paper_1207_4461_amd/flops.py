@@ -173,3 +173,45 @@ def flops_grad_pair(p: int, kind: int) -> int:
     if D:
         f += 20
     return f
+
+
+def flops_far_pair(kind: int) -> int:
+    """Far pass of the split forward, per (target, source) pair on a far panel:
+    x - x' (2), rho (4), 1/rho (1), z and 1/z (2), seed H0, H1 (103); S: w sigma H_0
+    (8); D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).
+    S: 120, D: 126, S+D: 134."""
+    f = 2 + 4 + 1 + 2 + SEED
+    if kind & 1:
+        f += 8
+    if kind & 2:
+        f += 4 + 2 + 8
+    return f
+
+
+def near_panel_counts(nodes, gamma: float):
+    """Per target panel, the number of source panels the split counts as near:
+    |b_m - b_m'|^2 < gamma^2 max(rad2_m, rad2_m'), b the mean of the panel's 16
+    nodes and rad2 its largest squared node distance from b (the relation the
+    kernels test)."""
+    import numpy as np
+
+    X = np.asarray(nodes, dtype=np.float64)
+    sx, sy = X[:, 0, 0].copy(), X[:, 0, 1].copy()
+    for a in range(1, X.shape[1]):
+        sx = sx + X[:, a, 0]
+        sy = sy + X[:, a, 1]
+    bx, by = sx * 0.0625, sy * 0.0625
+    dx, dy = X[:, :, 0] - bx[:, None], X[:, :, 1] - by[:, None]
+    rad2 = (dx * dx + dy * dy).max(axis=1)
+    ex, ey = bx[:, None] - bx[None, :], by[:, None] - by[None, :]
+    g2 = float(gamma) * float(gamma)
+    return ((ex * ex + ey * ey) < g2 * np.maximum(rad2[:, None], rad2[None, :])).sum(axis=1)
+
+
+def split_pairs(nodes, oversample: int, n_sides: int, gamma: float):
+    """(center-source pairs of the near pass, target-source pairs of the far pass)."""
+    cnt = near_panel_counts(nodes, gamma)
+    P, qs = len(cnt), 16 * oversample
+    near = int(cnt.sum()) * 16 * n_sides * qs
+    far = int((P - cnt).sum()) * 16 * qs
+    return near, far

@@ -96,6 +96,31 @@ def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int
     return out
 
 
+def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
+                          r: float = 0.5, oversample: int = 4, side: int = EXTERIOR, kind: int = S,
+                          gamma: float = 6.0,
+                          workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Near/far split forward (qbx_layer_potential_split): QBX for the sources of
+    panels within gamma panel radii of the target's panel, the smooth rule applied
+    directly for all others.  out[n_sides, n_kinds, 16*P] complex128, exterior
+    first.  Forward only (no adjoint)."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    out = torch.empty((n_sides(side), nk, P * Q), dtype=torch.complex128, device=dev)
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    rc = lib.qbx_layer_potential_split(C.byref(geo), density.data_ptr(), float(k), int(p),
+                                       float(r), int(oversample), int(side), int(kind),
+                                       float(gamma), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                       _stream(dev))
+    _lib.check(rc)
+    return out
+
+
 def layer_potential_gradient(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
                              r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
                              kind: int = S, want_grad: bool = True, want_dn: bool = True,

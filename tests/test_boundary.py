@@ -108,6 +108,21 @@ def test_gradient_entry_point_validates(lib):
                                             1 << 40, None) == _lib.QBX_EINVAL
 
 
+def test_split_entry_point_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    call = lambda **kw: lib.qbx_layer_potential_split(
+        C.byref(g), kw.get("dens", BAD), kw.get("k", 3.0), kw.get("p", 6), 0.5, 4, 1, 1,
+        kw.get("gamma", 6.0), kw.get("out", BAD), kw.get("ws", BAD), kw.get("nbytes", 1 << 40),
+        None)
+    for bad in (dict(gamma=0.0), dict(gamma=-1.0), dict(gamma=float("nan")), dict(dens=None),
+                dict(out=None), dict(ws=None), dict(p=25), dict(k=0.0)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    need = lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1)
+    assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE
+    assert lib.qbx_layer_potential_split(None, BAD, 1.0, 4, 0.5, 4, 1, 1, 6.0, BAD, BAD, 1 << 40,
+                                         None) == _lib.QBX_EINVAL
+
+
 def test_timer_class_count_matches_header():
     """qbx_kernel_timer_read writes QBX_TIMER_CLASSES entries into caller arrays: the
     binding's constant must be the header's."""

@@ -1,0 +1,124 @@
+"""GPU parity of the near/far split forward (qbx_layer_potential_split, through the
+C ABI) against the oracle's split (Section 5), and its relation to the plain QBX
+forward.  Bar: 1e-11 relative max-norm per output array against the oracle.  The
+near/far decisions are bit-identical on both sides (same IEEE formula, no fused
+multiply-add), so the two sides sum the same pairs by the same rule."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import qbx_oracle as O
+from paper_1207_4461_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def Q():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1207_4461_amd import qbx
+    return qbx
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_split(Q, pb, gamma):
+    u = Q.layer_potential_split(dev(pb.nodes), dev(pb.density), pb.k, pb.p, pb.r, pb.oversample,
+                                pb.side, pb.kind, gamma=gamma)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+CASES = [
+    dict(name="S-ext-p4-g3", n_panels=9, p=4, kind=1, side=1, gamma=3.0),
+    dict(name="D-int-p6-g4", n_panels=10, p=6, kind=2, side=-1, gamma=4.0),
+    dict(name="SD-both-p0-g2", n_panels=7, p=0, kind=3, side=0, gamma=2.0),
+    dict(name="SD-both-p12-g6", n_panels=13, p=12, kind=3, side=0, gamma=6.0),
+    dict(name="SD-both-p20-os1-g6", n_panels=11, p=20, kind=3, side=0, oversample=1, gamma=6.0),
+    dict(name="SD-both-p9-os3-g5", n_panels=9, p=9, kind=3, side=0, oversample=3, k=7.0, gamma=5.0),
+    dict(name="S-ext-p24-os2-g0.5", n_panels=8, p=24, kind=1, side=1, oversample=2, k=2.0,
+         gamma=0.5),
+    dict(name="SD-both-p5-allnear", n_panels=6, p=5, kind=3, side=0, gamma=1e150),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_split_small_elementwise(Q, case):
+    c = dict(case)
+    name, gamma = c.pop("name"), c.pop("gamma")
+    pb = I.small(name=name, **c)
+    near = O.near_panels(pb.nodes, gamma)
+    say(f"case {name}: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side} os={pb.oversample}"
+        f" gamma={gamma}: near panels per panel {near.sum(axis=1).min()}..{near.sum(axis=1).max()}")
+    ref = O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                  pb.kind, gamma=gamma).numpy()
+    u = gpu_split(Q, pb, gamma)
+    for si in range(ref.shape[0]):
+        for ki in range(ref.shape[1]):
+            e = rel(u[si, ki], ref[si, ki])
+            say(f"  side {si} kind {ki}: {e:.3e}")
+            assert e <= TOL
+
+
+def test_split_all_near_is_the_plain_forward(Q):
+    pb = I.small(n_panels=9, p=11, k=6.0, kind=3, side=I.BOTH)
+    u = gpu_split(Q, pb, 1e150)
+    v = Q.layer_potential(dev(pb.nodes), dev(pb.density), pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                          pb.kind).cpu().numpy()
+    e = rel(u, v)
+    say(f"  all-near split vs plain forward {e:.2e}")
+    assert e < 1e-13
+
+
+@pytest.mark.parametrize("cfg,n", [("star256", 24), ("star1024", 16), ("star4096", 5)])
+def test_split_full_size_sampled(Q, cfg, n):
+    """The workloads at full size (gamma = 6) on sampled targets against the oracle,
+    and the whole output against the plain QBX forward on the GPU (they differ by the
+    far sources' QBX truncation and the near patch's end effect only)."""
+    pb = getattr(I, cfg)()
+    idx = np.unique(np.concatenate([[0, pb.n_targets - 1],
+                                    np.random.default_rng(9).choice(pb.n_targets, n, replace=False)]))
+    near = O.near_panels(pb.nodes, 6.0)
+    say(f"{cfg}: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side}, {len(idx)} targets, "
+        f"near panels per panel {near.sum(axis=1).min()}..{near.sum(axis=1).max()}")
+    u = gpu_split(Q, pb, 6.0)
+    u2 = gpu_split(Q, pb, 6.0)
+    assert np.array_equal(u, u2)                      # fixed summation order
+    ref = O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                  pb.kind, gamma=6.0, targets=idx).numpy()
+    e = rel(u[:, :, idx], ref)
+    v = Q.layer_potential(dev(pb.nodes), dev(pb.density), pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                          pb.kind).cpu().numpy()
+    gap = rel(u, v)
+    say(f"  vs oracle split {e:.3e}; vs plain QBX forward {gap:.3e}")
+    assert e <= TOL
+    assert gap < 1e-8
+
+
+def test_split_green_identity_on_gpu(Q):
+    curve = I.star((5, 0.25, 0.0))
+    P, k, p, x0 = 45, 5.0, 20, (3.0, 1.0)
+    nodes = I.panel_nodes(curve, P)
+    u, dudn = I.green_pair(curve, P, k, x0)
+    v = Q.layer_potential_split(dev(nodes), dev(np.stack([dudn, u])), k, p, 0.5, 4, I.BOTH, 3,
+                                gamma=6.0).cpu().numpy()
+    sc = np.abs(u).max()
+    e_in = np.abs(v[1, 0] - v[1, 1] - u).max() / sc
+    e_out = np.abs(v[0, 0] - v[0, 1]).max() / sc
+    say(f"  interior {e_in:.3e} exterior {e_out:.3e}")
+    assert e_in < 1e-8 and e_out < 1e-8
