@@ -33,6 +33,9 @@ gradients of the discrete map:
 * Section 3.2: target derivatives by analytic differentiation of the local
   expansion (``evaluate_gradient``, ``layer_potential_gradient``), through the
   ladder relations of the regular waves J_l e^{i l theta} in x and y.
+* Section 4.3: the Dirichlet problem by the combined-field representation,
+  solved densely (``dirichlet_solve``) and evaluated off the curve
+  (``representation``).
 * Section 5: the near/far split (``layer_potential_split``): QBX only for
   sources on panels near the target's panel, the smooth rule applied directly
   at the target for all others.
@@ -602,6 +605,41 @@ def qbx_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4, sid
         P = nodes.shape[0]
         U = np.kron(np.eye(P), V)
         return K @ U
+
+
+# ---------------------------------------------------------------------------
+# Section 4.3: the Dirichlet problem by the combined-field representation
+# ---------------------------------------------------------------------------
+def dirichlet_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4,
+                     side: int = EXTERIOR, alpha: complex = 1j) -> np.ndarray:
+    """The Nystrom matrix of eq. dirichlet-inteq, alpha S - D with the one-sided QBX
+    limits taken from the domain's side (exterior: +, interior: -), which carry the
+    -+ sigma/2 of the jump relations (eq. dlpjump).  [T, T], tiny inputs only."""
+    S = qbx_matrix(nodes, k, p, r, oversample, side, "S")
+    D = qbx_matrix(nodes, k, p, r, oversample, side, "D")
+    return alpha * S - D
+
+
+def dirichlet_solve(nodes, f, k: float, p: int, r: float = 0.5, oversample: int = 4,
+                    side: int = EXTERIOR, alpha: complex = 1j) -> np.ndarray:
+    """sigma [T] at the nodes solving (alpha S - D) sigma = f by a dense direct solve (the
+    discrete solution that the paper's GMRES iteration converges to)."""
+    A = dirichlet_matrix(nodes, k, p, r, oversample, side, alpha)
+    return np.linalg.solve(A, np.asarray(f, dtype=np.complex128))
+
+
+def representation(nodes, sigma, k: float, points, oversample: int = 4,
+                   alpha: complex = 1j) -> np.ndarray:
+    """u(y) = -D sigma(y) + alpha S sigma(y) at points y [n, 2] away from the curve, by the
+    smooth source rule (Section 4.3 evaluates the representation at observation
+    points inside the domain)."""
+    nodes = _as_t(nodes, _F64)
+    src = source_grid(nodes, oversample)
+    q = src["w"].to(_C128) * interpolate_density(_as_t(sigma, _C128)[None], oversample)[0]
+    pts = torch.as_tensor(np.asarray(points, dtype=np.float64))
+    sel = torch.ones(pts.shape[0], q.shape[0], dtype=torch.bool)
+    d = direct_sum(src, {"S": q, "D": q}, pts[:, 0], pts[:, 1], k, S_KIND | D_KIND, sel)
+    return (0.25j * (alpha * d["S"] - d["D"])).numpy()
 
 
 # ---------------------------------------------------------------------------
