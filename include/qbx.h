@@ -147,6 +147,42 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
                               double r, int oversample, int side, int kind, double gamma,
                               double* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- integral equation ------------------------------------------------ */
+
+/* Workspace bytes of qbx_solve_dirichlet (0 for invalid arguments; side must
+ * be -1 or 1, 1 <= restart <= 200). */
+size_t qbx_solve_workspace_bytes(int n_panels, int q, int p, int oversample, int side,
+                                 int restart);
+
+/* Nystrom solve of the Dirichlet problem by the combined-field representation
+ * u = -D sigma + alpha S sigma (Section 4.3, eq. dirichlet-inteq):
+ *   -+ sigma/2 + alpha S sigma - D sigma = f   at the nodes
+ * (upper sign: side = 1, the exterior problem; side = -1 the interior one).
+ * S and D are principal values, the averages of the two one-sided QBX limits
+ * (eq. dlp-twosided): Section 3.5 shows that only the averaged D keeps the
+ * spectral clustering that lets GMRES converge below the discretization error.
+ * As in the paper the unknowns are sqrt(w) sigma (w the 16-point rule's weight
+ * at the node) and GMRES(restart) iterates until the relative residual of that
+ * scaled system is below tol (the paper uses 1e-14) or max_iter products have
+ * been taken.  Each product is one S+D call for both sides of
+ * qbx_layer_potential, or of qbx_layer_potential_split when gamma > 0
+ * (gamma = 0: plain QBX).
+ *   f      device [16 P] complex, the Dirichlet data at the nodes
+ *   alpha  alpha_re + i alpha_im (the paper takes alpha = i)
+ *   sigma  device [16 P] complex, out: the density
+ *   iterations, residual: host, nullable; the matrix-vector products taken and
+ *          the true relative residual |W^(1/2) (f - A sigma)| / |W^(1/2) f| of
+ *          the returned sigma (check it: the call returns QBX_OK also when
+ *          max_iter ends the iteration first).
+ * SYNCHRONOUS on `stream` (the Arnoldi coefficients come back to the host after
+ * every product).  No allocation; the workspace is qbx_solve_workspace_bytes().
+ * Errors as qbx_layer_potential, plus QBX_EINVAL for side 0, restart, max_iter,
+ * tol <= 0, gamma < 0 or a non-finite alpha. */
+int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p, double r,
+                        int oversample, int side, double alpha_re, double alpha_im, double gamma,
+                        double tol, int restart, int max_iter, double* sigma, int* iterations,
+                        double* residual, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- adjoint ----------------------------------------------------------- */
 
 /* Vector-Jacobian product of qbx_layer_potential for the real scalar

@@ -34,8 +34,8 @@ gradients of the discrete map:
   expansion (``evaluate_gradient``, ``layer_potential_gradient``), through the
   ladder relations of the regular waves J_l e^{i l theta} in x and y.
 * Section 4.3: the Dirichlet problem by the combined-field representation,
-  solved densely (``dirichlet_solve``) and evaluated off the curve
-  (``representation``).
+  with S and D as two-sided averages (Section 3.5), solved densely
+  (``dirichlet_solve``) and evaluated off the curve (``representation``).
 * Section 5: the near/far split (``layer_potential_split``): QBX only for
   sources on panels near the target's panel, the smooth rule applied directly
   at the target for all others.
@@ -612,18 +612,24 @@ def qbx_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4, sid
 # ---------------------------------------------------------------------------
 def dirichlet_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4,
                      side: int = EXTERIOR, alpha: complex = 1j) -> np.ndarray:
-    """The Nystrom matrix of eq. dirichlet-inteq, alpha S - D with the one-sided QBX
-    limits taken from the domain's side (exterior: +, interior: -), which carry the
-    -+ sigma/2 of the jump relations (eq. dlpjump).  [T, T], tiny inputs only."""
-    S = qbx_matrix(nodes, k, p, r, oversample, side, "S")
-    D = qbx_matrix(nodes, k, p, r, oversample, side, "D")
-    return alpha * S - D
+    """The Nystrom matrix of eq. dirichlet-inteq, -+ I/2 + alpha S - D (upper sign: the
+    exterior problem), with S and D the principal values taken as the averages of the two
+    one-sided QBX limits (eq. dlp-twosided).  Section 3.5: the one-sided QBX limit of D
+    damps high-frequency densities but not the sigma/2 of its jump, so only the
+    two-sided average keeps the discrete spectrum clustering like the continuous one
+    (and GMRES converging below the discretization error).  [T, T], tiny inputs only."""
+    S = 0.5 * (qbx_matrix(nodes, k, p, r, oversample, EXTERIOR, "S")
+               + qbx_matrix(nodes, k, p, r, oversample, INTERIOR, "S"))
+    D = 0.5 * (qbx_matrix(nodes, k, p, r, oversample, EXTERIOR, "D")
+               + qbx_matrix(nodes, k, p, r, oversample, INTERIOR, "D"))
+    half = -0.5 if side == EXTERIOR else 0.5
+    return half * np.eye(S.shape[0]) + alpha * S - D
 
 
 def dirichlet_solve(nodes, f, k: float, p: int, r: float = 0.5, oversample: int = 4,
                     side: int = EXTERIOR, alpha: complex = 1j) -> np.ndarray:
-    """sigma [T] at the nodes solving (alpha S - D) sigma = f by a dense direct solve (the
-    discrete solution that the paper's GMRES iteration converges to)."""
+    """sigma [T] at the nodes solving (-+ I/2 + alpha S - D) sigma = f by a dense direct
+    solve (the discrete solution that the paper's GMRES iteration converges to)."""
     A = dirichlet_matrix(nodes, k, p, r, oversample, side, alpha)
     return np.linalg.solve(A, np.asarray(f, dtype=np.complex128))
 

@@ -73,6 +73,9 @@ def load() -> C.CDLL:
         "qbx_layer_potential": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]),
         "qbx_layer_potential_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
                                                sz, vp]),
+        "qbx_solve_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
+        "qbx_solve_dirichlet": (i32, [gp, vp, dbl, i32, dbl, i32, i32, dbl, dbl, dbl, dbl, i32,
+                                      i32, vp, C.POINTER(i32), C.POINTER(dbl), vp, sz, vp]),
         "qbx_layer_potential_split": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl, vp, vp,
                                             sz, vp]),
         "qbx_layer_potential_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,

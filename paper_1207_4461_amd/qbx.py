@@ -121,6 +121,39 @@ def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, 
     return out
 
 
+def solve_workspace_bytes(n_panels: int, p: int, oversample: int, side: int, restart: int) -> int:
+    n = _lib.load().qbx_solve_workspace_bytes(n_panels, Q, p, oversample, side, restart)
+    if n == 0:
+        raise ValueError("invalid solve parameters")
+    return n
+
+
+def solve_dirichlet(nodes: torch.Tensor, f: torch.Tensor, k: float, p: int, r: float = 0.5,
+                    oversample: int = 4, side: int = EXTERIOR, alpha: complex = 1j,
+                    gamma: float = 0.0, tol: float = 1e-14, restart: int = 100,
+                    max_iter: int = 1000, workspace: Optional[torch.Tensor] = None):
+    """Dirichlet problem by the combined-field representation u = -D sigma + alpha S sigma
+    (qbx_solve_dirichlet): sigma [16P] complex128 with (alpha S - D) sigma = f on the
+    domain's side (EXTERIOR or INTERIOR), by GMRES on the sqrt(w)-scaled system; gamma > 0
+    uses the near/far split for the products.  Returns (sigma, iterations, residual)."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    _need(f, "f", torch.complex128, (P * Q,))
+    dev = nodes.device
+    sigma = torch.empty(P * Q, dtype=torch.complex128, device=dev)
+    ws = _workspace(solve_workspace_bytes(P, p, oversample, side, restart), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    it, res = C.c_int(), C.c_double()
+    a = complex(alpha)
+    _lib.check(lib.qbx_solve_dirichlet(C.byref(geo), f.data_ptr(), float(k), int(p), float(r),
+                                       int(oversample), int(side), a.real, a.imag, float(gamma),
+                                       float(tol), int(restart), int(max_iter), sigma.data_ptr(),
+                                       C.byref(it), C.byref(res), ws.data_ptr(), ws.numel(),
+                                       _stream(dev)))
+    return sigma, it.value, res.value
+
+
 def layer_potential_gradient(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
                              r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
                              kind: int = S, want_grad: bool = True, want_dn: bool = True,

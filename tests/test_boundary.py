@@ -123,6 +123,30 @@ def test_split_entry_point_validates(lib):
                                          None) == _lib.QBX_EINVAL
 
 
+def test_solve_entry_point_validates(lib):
+    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 0, 50) == 0           # both sides
+    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 0) == 0            # restart
+    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 201) == 0
+    n = lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 50)
+    assert n > lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 3)
+    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 100) > n
+    g = _lib.Geometry(8, 16, BAD)
+    it, res = C.c_int(), C.c_double()
+
+    def call(**kw):
+        return lib.qbx_solve_dirichlet(
+            C.byref(g), kw.get("f", BAD), 3.0, 6, 0.5, 4, kw.get("side", 1), 0.0, 1.0,
+            kw.get("gamma", 0.0), kw.get("tol", 1e-14), kw.get("restart", 50),
+            kw.get("max_iter", 100), kw.get("sigma", BAD), C.byref(it), C.byref(res),
+            kw.get("ws", BAD), kw.get("nbytes", 1 << 40), None)
+
+    for bad in (dict(side=0), dict(f=None), dict(sigma=None), dict(ws=None), dict(tol=0.0),
+                dict(tol=float("nan")), dict(restart=0), dict(restart=201), dict(max_iter=0),
+                dict(gamma=-1.0)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(nbytes=n - 1) == _lib.QBX_EWORKSPACE
+
+
 def test_timer_class_count_matches_header():
     """qbx_kernel_timer_read writes QBX_TIMER_CLASSES entries into caller arrays: the
     binding's constant must be the header's."""

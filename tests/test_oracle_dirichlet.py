@@ -1,8 +1,9 @@
 """Pins of the oracle's Dirichlet solve (Section 4.3: the combined-field representation
-u = -D sigma + alpha S sigma, eq. dirichlet-inteq, Nystrom at the nodes) against exact
+u = -D sigma + alpha S sigma, eq. dirichlet-inteq, Nystrom at the nodes, S and D as
+two-sided averages per Section 3.5) against exact
 solutions it does not produce: fields of point charges (H_0 sources) placed outside the
 domain, evaluated at observation points inside it.  The error falls under refinement;
-planted mistakes (the D term's sign, the side of the one-sided limits) are caught."""
+planted mistakes (the D term's sign, the sign of sigma/2) are caught."""
 import numpy as np
 import scipy.special as sps
 
@@ -38,10 +39,10 @@ def solve_error(side, P, p, oversample=2):
 
 
 def test_point_charges_exterior_and_interior():
-    for side, bound in ((I.EXTERIOR, 3e-5), (I.INTERIOR, 1e-6)):
+    for side, bound, bound8 in ((I.EXTERIOR, 3e-5, 1e-6), (I.INTERIOR, 1e-4, 5e-6)):
         e8, e12 = solve_error(side, 8, 6), solve_error(side, 12, 6)
         assert e12 < bound and e8 > 5 * e12, (side, e8, e12)
-    assert solve_error(I.INTERIOR, 12, 8) < 1e-8
+        assert solve_error(side, 12, 8) < bound8
 
 
 def test_planted_dirichlet_mistakes_are_caught(monkeypatch):
