@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("QBX source-center interactions/s, fwd & fwd+bwd, FP64 @≤1e-11 rel; "
           "% FP64 peak")
+SOLVE_METRIC = ("Dirichlet combined-field solve (Section 4.3), GMRES to 1e-14 over QBX products, "
+                "FP64: centers x sources of all products per second")
 SPLIT_METRIC = ("QBX layer potential with the near/far split of Section 5, FP64 @<=1e-11 rel "
                 "to the split oracle: the workload's centers x sources per second")
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
@@ -71,12 +73,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
-    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad", "split"],
+    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad", "split", "solve"],
                     help="grad: the target derivatives (grad S, grad D, S', D') instead; "
                          "split: the forward with the near/far split (QBX for near panels "
-                         "only, the smooth rule applied directly for the rest)")
+                         "only, the smooth rule applied directly for the rest); solve: the "
+                         "exterior Dirichlet problem with point-charge data, GMRES to 1e-14 "
+                         "(products by the split when --gamma > 0)")
     ap.add_argument("--gamma", type=float, default=6.0,
-                    help="split mode: panels within gamma panel radii count as near")
+                    help="split and solve modes: panels within gamma panel radii count as "
+                         "near (solve: 0 for plain QBX products)")
     ap.add_argument("--backward", default="fused", choices=["fused", "tape"],
                     help="fwdbwd step: plain forward + fused adjoint (default), or forward "
                          "with tape + source-major adjoint")
@@ -85,6 +90,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: run one plain device-to-device copy of this size first, the "
                          "reference for scaling the HBM byte counters of a --pmc profile")
+    ap.add_argument("--restart", type=int, default=300,
+                    help="solve mode: Krylov vectors kept between GMRES restarts")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time of the oracle sample")
@@ -131,6 +138,8 @@ def main():
         del src, dst
     if args.workload == "random64":
         return bench_batched(args)
+    if args.mode == "solve":
+        return bench_solve(args)
     have_bwd = hasattr(qbx, "layer_potential_vjp")
     mode = args.mode or ("fwdbwd" if have_bwd else "fwd")
     if mode == "fwdbwd" and not have_bwd:
@@ -313,6 +322,120 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_solve(args):
+    """The exterior Dirichlet problem on the workload's curve: data of two point charges
+    inside it, GMRES to 1e-14 (qbx_solve_dirichlet), the field checked at three exterior
+    points against the exact one.  A step is one whole solve."""
+    import ctypes as C
+
+    import numpy as np
+    import scipy.special as sps
+    import torch
+
+    from paper_1207_4461_amd import _lib, flops, inputs as I, qbx
+
+    lib = _lib.load()
+    pb = getattr(I, args.workload)()
+    dev = torch.device("cuda:0")
+    P, k, p = pb.n_panels, pb.k, pb.p
+    charges = [(0.1, 0.2, 1.0), (-0.3, 0.1, 0.5 - 0.2j)]
+    obs = np.array([(2.0, 0.5), (-1.5, 1.7), (0.3, -2.2)])
+
+    def field(pts):
+        return sum(c * sps.hankel1(0, k * np.hypot(pts[:, 0] - cx, pts[:, 1] - cy))
+                   for cx, cy, c in charges)
+
+    nodes = torch.from_numpy(pb.nodes).to(dev)
+    f = torch.from_numpy(field(pb.nodes.reshape(-1, 2))).to(dev)
+    restart = args.restart
+    ws = torch.empty(qbx.solve_workspace_bytes(P, p, pb.oversample, I.EXTERIOR, restart),
+                     dtype=torch.uint8, device=dev)
+    gamma = args.gamma
+
+    def solve():
+        return qbx.solve_dirichlet(nodes, f, k, p, pb.r, pb.oversample, I.EXTERIOR, 1j, gamma,
+                                   1e-14, restart, 3000, workspace=ws)
+
+    log(f"solve on {args.workload}: P={P} p={p} k={k} gamma={gamma}")
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    lib.qbx_kernel_timer(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sigma, iters, res = solve()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    NC = _lib.QBX_TIMER_CLASSES
+    ms = (C.c_double * NC)()
+    nl = (C.c_int * NC)()
+    _lib.check(lib.qbx_kernel_timer_read(ms, nl))
+    lib.qbx_kernel_timer(0)
+    cls = 7 if gamma > 0 else 0
+    products = nl[cls] // args.steps
+    n_ctr = 2 * pb.n_targets
+    inter = flops.interactions(n_ctr, pb.n_sources, 3) * products
+    if gamma > 0:
+        pairs = flops.split_pairs(pb.nodes, pb.oversample, 2, gamma)[1]
+        fl = flops.flops_far_pair(3) * pairs
+        kname = "split far pass"
+    else:
+        fl = flops.flops_forward_pair(p, 3) * n_ctr * pb.n_sources
+        kname = "forward pair kernel"
+    avg = ms[cls] / nl[cls]
+    achieved = fl / (avg * 1e-3) / 1e12
+    # the field off the curve: the nodes' own 16-point rule as explicit sources
+    t = I.panel_parameters(P).reshape(-1)
+    d = pb.curve.deriv(t)
+    speed = np.hypot(d[:, 0], d[:, 1])
+    _, om = np.polynomial.legendre.leggauss(16)
+    w = torch.from_numpy(np.tile(om, P) * (np.pi / P) * speed).to(dev)
+    nrm = torch.from_numpy(np.ascontiguousarray(np.stack([d[:, 1], -d[:, 0]], 1) / speed[:, None])).to(dev)
+    q = w * sigma
+    eps = 1e-3
+    out = qbx.apply_explicit(nodes.reshape(-1, 2), nrm, torch.stack([q, q]),
+                             torch.from_numpy(obs - np.array([eps, 0.0])).to(dev),
+                             torch.full((3,), eps, dtype=torch.float64, device=dev),
+                             torch.ones(3, dtype=torch.complex128, device=dev), k, 8, kind=3)
+    u = (1j * out[0] - out[1]).cpu().numpy()
+    ex = field(obs)
+    err = float(np.abs(u - ex).max() / np.abs(ex).max())
+    log(f"solve {dt:.3f} s, {iters} Krylov products ({products} in all), residual {res:.2e}, "
+        f"field error {err:.2e}; {kname} {avg:.2f} ms, {achieved:.2f} TFLOP/s")
+    cpu = None
+    if args.cpu_baseline:
+        from oracle import qbx_oracle as O
+
+        idx = np.sort(np.random.default_rng(0).choice(pb.n_targets, 8, replace=False))
+        sg = sigma.cpu().numpy()
+        t0 = time.perf_counter()
+        O.layer_potential(pb.nodes, np.stack([sg, sg]), k, p, pb.r, pb.oversample, I.BOTH, 3,
+                          targets=idx)
+        tc = time.perf_counter() - t0
+        cpu = {"value": flops.interactions(2 * len(idx), pb.n_sources, 3) / tc,
+               "unit": "interactions/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": f"one S+D product of the oracle (plain QBX, both sides) at {len(idx)} "
+                         f"random targets against all {pb.n_sources} sources, {tc:.1f} s"}
+    outj = {
+        "metric": SOLVE_METRIC, "value": inter / dt, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} curve ({P} panels x 16 nodes, oversample "
+                               f"{pb.oversample}, k={k}, p={p}): exterior Dirichlet problem, "
+                               "data of 2 point charges inside, alpha = i",
+                   "mode": "solve", "gamma": gamma, "restart": restart,
+                   "krylov_products": iters, "products": products, "residual": res,
+                   "field_rel_error": err},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": None, "kernel": kname, "kernel_avg_ms": round(avg, 4),
+                     "launches": int(nl[cls]), "flop_per_launch": fl},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(outj), flush=True)
 
 
 def bench_batched(args):

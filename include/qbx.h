@@ -150,7 +150,7 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
 /* ---- integral equation ------------------------------------------------ */
 
 /* Workspace bytes of qbx_solve_dirichlet (0 for invalid arguments; side must
- * be -1 or 1, 1 <= restart <= 200). */
+ * be -1 or 1, 1 <= restart <= 1000). */
 size_t qbx_solve_workspace_bytes(int n_panels, int q, int p, int oversample, int side,
                                  int restart);
 

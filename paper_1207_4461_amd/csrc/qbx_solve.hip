@@ -31,7 +31,7 @@ namespace qbx {
 
 using cplx = std::complex<double>;
 constexpr int kDotBlocks = 256;      // first-stage blocks of the multi-dot
-constexpr int kMaxRestart = 200;
+constexpr int kMaxRestart = 1000;   // Krylov vectors kept (16 B x nodes each)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -126,7 +126,7 @@ def test_split_entry_point_validates(lib):
 def test_solve_entry_point_validates(lib):
     assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 0, 50) == 0           # both sides
     assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 0) == 0            # restart
-    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 201) == 0
+    assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 1001) == 0
     n = lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 50)
     assert n > lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 3)
     assert lib.qbx_solve_workspace_bytes(8, 16, 6, 4, 1, 100) > n
@@ -141,7 +141,7 @@ def test_solve_entry_point_validates(lib):
             kw.get("ws", BAD), kw.get("nbytes", 1 << 40), None)
 
     for bad in (dict(side=0), dict(f=None), dict(sigma=None), dict(ws=None), dict(tol=0.0),
-                dict(tol=float("nan")), dict(restart=0), dict(restart=201), dict(max_iter=0),
+                dict(tol=float("nan")), dict(restart=0), dict(restart=1001), dict(max_iter=0),
                 dict(gamma=-1.0)):
         assert call(**bad) == _lib.QBX_EINVAL, bad
     assert call(nbytes=n - 1) == _lib.QBX_EWORKSPACE
