@@ -204,10 +204,13 @@ def interpolate_density(density: torch.Tensor, oversample: int) -> torch.Tensor:
 # Section 3.3 step 4(a): expansion centers
 # ---------------------------------------------------------------------------
 def expansion_centers(nodes: torch.Tensor, h: torch.Tensor, n_tgt: torch.Tensor, r: float,
-                      side: int) -> Dict[str, torch.Tensor]:
-    """c = x + side*r*h_m*n (side=+1 exterior, -1 interior); R = r*h_m; theta = arg(x - c)."""
+                      side: int, center_rule: str = "h") -> Dict[str, torch.Tensor]:
+    """c = x + side*R*n (side=+1 exterior, -1 interior) with R = r*h_m, or with
+    R = r*sqrt(h_m) for center_rule="sqrt" (Section 3.1 names r = sqrt(h) as the choice
+    that makes the error vanish as h -> 0 at fixed p); theta = arg(x - c)."""
     x = nodes.reshape(-1, 2)
-    R = (r * h)[:, None].expand(-1, Q).reshape(-1)
+    hr = torch.sqrt(h) if center_rule == "sqrt" else h
+    R = (r * hr)[:, None].expand(-1, Q).reshape(-1)
     c = x + float(side) * R[:, None] * n_tgt
     d = x - c
     return {"cx": c[:, 0], "cy": c[:, 1], "R": R, "theta": torch.atan2(d[:, 1], d[:, 0])}
@@ -353,23 +356,28 @@ def kinds_of(kind: int) -> Sequence[str]:
 
 def layer_potential(nodes, density, k: float, p: int, r: float = 0.5, oversample: int = 4,
                     side: int = EXTERIOR, kind: int = S_KIND, targets=None, mode: str = "fast",
-                    return_aux: bool = False):
+                    return_aux: bool = False, dipole: str = "normal", center_rule: str = "h"):
     """One-sided QBX limits at the targets.
 
     nodes [P,16,2] float64, density [n_kinds, P*16] complex128 (S first, then D).
     ``targets``: optional index array into the P*16 targets (sampled evaluation).
+    ``dipole="tangential"``: the D slot computes the tangential dipole R of eq. riesz-def,
+    the source derivative along the unit tangent t = (x', y')/|x'| (counter-clockwise)
+    in place of the normal.  ``center_rule``: see ``expansion_centers``.
     Returns u [n_sides, n_kinds, T] complex128 (exterior first for BOTH)."""
     nodes = _as_t(nodes, _F64)
     density = _as_t(density, _C128)
     kinds = kinds_of(kind)
     src = source_grid(nodes, oversample)
+    if dipole == "tangential":
+        src = dict(src, nx=-src["ny"], ny=src["nx"])
     fine = interpolate_density(density, oversample)
     dens = {}
     for i, kk in enumerate(kinds):
         dens[kk] = src["w"].to(_C128) * fine[i]
     outs, aux = [], {}
     for s in sides_of(side):
-        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
+        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s, center_rule)
         if targets is not None:
             idx = torch.as_tensor(np.asarray(targets), dtype=torch.long)
             ctr = {key: val[idx] for key, val in ctr.items()}
