@@ -374,7 +374,8 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(O, "_hankel_orders_fast", orig_rec)
 
     # (3) centers on the wrong side
-    monkeypatch.setattr(O, "expansion_centers", lambda n, h, nt, r, s: orig_centers(n, h, nt, r, -s))
+    monkeypatch.setattr(O, "expansion_centers",
+                        lambda n, h, nt, r, s, *rule: orig_centers(n, h, nt, r, -s, *rule))
     assert green_residual() > 1e-2
     monkeypatch.setattr(O, "expansion_centers", orig_centers)
 
