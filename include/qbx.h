@@ -106,6 +106,28 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
                         double r, int oversample, int side, int kind, double* out,
                         double* tape, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Options of qbx_layer_potential_ext; zero-initialised, they are the defaults
+ * of qbx_layer_potential. */
+typedef struct {
+  int32_t dipole;       /* 0: the D slot is the double layer (source derivative along
+                           the outward normal); 1: it is the tangential dipole
+                           R sigma(x) = int t(x') . grad_x' G(x, x') sigma(x') ds'
+                           (eq. riesz-def), t the counter-clockwise unit tangent   */
+  int32_t center_rule;  /* 0: center distance R = r h_m; 1: R = r sqrt(h_m), the
+                           choice Section 3.1 names for an error that vanishes as
+                           h -> 0 at fixed p                                       */
+} qbx_forward_options;
+
+/* qbx_layer_potential with the options above (opt may be NULL: the defaults).
+ * R has no jump across the curve (R sigma = -S[d sigma/ds] by parts), so its two
+ * one-sided limits agree up to the QBX error.  Forward only: the adjoint and
+ * the tape assume the defaults.  QBX_EINVAL for an option outside {0, 1};
+ * otherwise as qbx_layer_potential.  The workspace is qbx_workspace_bytes(). */
+int qbx_layer_potential_ext(const qbx_geometry* g, const double* density, double k, int p,
+                            double r, int oversample, int side, int kind,
+                            const qbx_forward_options* opt, double* out, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* Target derivatives (Section 3.2: the local expansion at each center is
  * differentiated analytically with respect to the target), with the arguments
  * of qbx_layer_potential:

@@ -39,6 +39,11 @@ class Geometry(C.Structure):
     _fields_ = [("n_panels", C.c_int32), ("q", C.c_int32), ("nodes", C.c_void_p)]
 
 
+class ForwardOptions(C.Structure):
+    """qbx_forward_options of include/qbx.h."""
+    _fields_ = [("dipole", C.c_int32), ("center_rule", C.c_int32)]
+
+
 class BatchItem(C.Structure):
     """qbx_batch_item of include/qbx.h."""
     _fields_ = [("node_offset", C.c_int64), ("density_offset", C.c_int64),
@@ -76,6 +81,8 @@ def load() -> C.CDLL:
         "qbx_solve_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
         "qbx_solve_dirichlet": (i32, [gp, vp, dbl, i32, dbl, i32, i32, dbl, dbl, dbl, dbl, i32,
                                       i32, vp, C.POINTER(i32), C.POINTER(dbl), vp, sz, vp]),
+        "qbx_layer_potential_ext": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32,
+                                          C.POINTER(ForwardOptions), vp, vp, sz, vp]),
         "qbx_layer_potential_split": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl, vp, vp,
                                             sz, vp]),
         "qbx_layer_potential_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,

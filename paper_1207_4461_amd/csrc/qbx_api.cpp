@@ -128,6 +128,8 @@ bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, d
   d->NJ = 2 * (p + 4);   // J_0..J_{p+3}, then J'_0..J'_{p+3}
   d->side = side;
   d->kind = kind;
+  d->dipole = 0;
+  d->center_rule = 0;
   d->k = k;
   d->r = r;
   set_launch_shape(d);
@@ -289,6 +291,40 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
   timer_begin(0, stream);
   e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens), at<CenterRec>(ws, L.ctr),
                      at<double>(ws, L.jtab), at<double2>(ws, L.partial), stream);
+  timer_end(0, stream);
+  if (e != hipSuccess) return device_fail(e, "forward kernel");
+  e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
+  if (e != hipSuccess) return device_fail(e, "finalize kernel");
+  return QBX_OK;
+}
+
+int qbx_layer_potential_ext(const qbx_geometry* g, const double* density, double k, int p,
+                            double r, int oversample, int side, int kind,
+                            const qbx_forward_options* opt, double* out, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (opt) {
+    if (opt->dipole != 0 && opt->dipole != 1)
+      return fail(QBX_EINVAL, "dipole = %d is not 0 or 1", opt->dipole);
+    if (opt->center_rule != 0 && opt->center_rule != 1)
+      return fail(QBX_EINVAL, "center_rule = %d is not 0 or 1", opt->center_rule);
+    d.dipole = opt->dipole;
+    d.center_rule = opt->center_rule;
+  }
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!out) return fail(QBX_EINVAL, "out is NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  timer_begin(0, stream);
+  hipError_t e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                at<double2>(ws, L.partial), stream);
   timer_end(0, stream);
   if (e != hipSuccess) return device_fail(e, "forward kernel");
   e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);

@@ -34,6 +34,9 @@ struct Dims {
   int NJ;       // J table length per center: J_0..J_{p+3}, J'_0..J'_{p+3}
   int side;     // QBX_INTERIOR / QBX_BOTH / QBX_EXTERIOR
   int kind;     // bit mask S=1, D=2
+  int dipole;       // 0: the D slot differentiates along the source normal; 1: along
+                    // the tangent (the operator R)
+  int center_rule;  // 0: center distance r h_m; 1: r sqrt(h_m)
   double k, r;
   // forward launch shape
   int chunks;            // ceil(N / 64)

@@ -75,7 +75,10 @@ __device__ __forceinline__ void upsample_panel(const Dims& d, int m, const doubl
     const double w = tab[L.ws + b] * speed;
     const double inv = 1.0 / speed;
     const size_t j = (size_t)m * d.qs + b;
-    geo[j] = make_double4(x, y, dy * inv, -dx * inv);
+    // the direction of the D slot's source derivative: the outward normal, or
+    // for the tangential dipole R the unit tangent (counter-clockwise)
+    geo[j] = d.dipole ? make_double4(x, y, dx * inv, dy * inv)
+                      : make_double4(x, y, dy * inv, -dx * inv);
     wgt[j] = w;
     dens[j] = make_double2(w * sr0, w * si0);
     if (d.nk > 1) dens[(size_t)d.N + j] = make_double2(w * sr1, w * si1);
@@ -101,7 +104,7 @@ __device__ __forceinline__ void upsample_panel(const Dims& d, int m, const doubl
     }
     const double inv = 1.0 / sqrt(tx * tx + ty * ty);
     const double nx = ty * inv, ny = -tx * inv;
-    const double R = d.r * hm;
+    const double R = d.center_rule ? d.r * sqrt(hm) : d.r * hm;
     CenterRec c;
     c.x = X[a][0];
     c.y = X[a][1];

@@ -72,8 +72,18 @@ def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.
 def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
                     oversample: int = 4, side: int = EXTERIOR, kind: int = S,
                     tape: Optional[torch.Tensor] = None,
-                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """One-sided QBX limits, out[n_sides, n_kinds, 16*P] complex128 (exterior first)."""
+                    workspace: Optional[torch.Tensor] = None, dipole: str = "normal",
+                    center_rule: str = "h") -> torch.Tensor:
+    """One-sided QBX limits, out[n_sides, n_kinds, 16*P] complex128 (exterior first).
+    dipole="tangential": the D slot is the tangential dipole R; center_rule="sqrt":
+    center distance r sqrt(h) (both through qbx_layer_potential_ext, forward only)."""
+    if dipole not in ("normal", "tangential") or center_rule not in ("h", "sqrt"):
+        raise ValueError("dipole must be 'normal' or 'tangential', center_rule 'h' or 'sqrt'")
+    if dipole != "normal" or center_rule != "h":
+        if tape is not None:
+            raise ValueError("a tape is only written with the default options")
+        return _layer_potential_ext(nodes, density, k, p, r, oversample, side, kind, workspace,
+                                    int(dipole == "tangential"), int(center_rule == "sqrt"))
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
@@ -93,6 +103,25 @@ def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int
                                  int(oversample), int(side), int(kind), out.data_ptr(), tp,
                                  ws.data_ptr(), ws.numel(), _stream(dev))
     _lib.check(rc)
+    return out
+
+
+def _layer_potential_ext(nodes, density, k, p, r, oversample, side, kind, workspace, dipole,
+                         center_rule):
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    out = torch.empty((n_sides(side), nk, P * Q), dtype=torch.complex128, device=dev)
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    opt = _lib.ForwardOptions(dipole, center_rule)
+    _lib.check(lib.qbx_layer_potential_ext(C.byref(geo), density.data_ptr(), float(k), int(p),
+                                           float(r), int(oversample), int(side), int(kind),
+                                           C.byref(opt), out.data_ptr(), ws.data_ptr(),
+                                           ws.numel(), _stream(dev)))
     return out
 
 

@@ -147,6 +147,23 @@ def test_solve_entry_point_validates(lib):
     assert call(nbytes=n - 1) == _lib.QBX_EWORKSPACE
 
 
+def test_ext_entry_point_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+
+    def call(dipole=0, rule=0, dens=BAD, out=BAD, ws=BAD, nbytes=1 << 40, use_opt=True):
+        opt = _lib.ForwardOptions(dipole, rule)
+        return lib.qbx_layer_potential_ext(C.byref(g), dens, 3.0, 6, 0.5, 4, 1, 2,
+                                           C.byref(opt) if use_opt else None, out, ws, nbytes,
+                                           None)
+
+    for bad in (dict(dipole=2), dict(dipole=-1), dict(rule=2), dict(dens=None), dict(out=None),
+                dict(ws=None)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    need = lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 2)
+    assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE
+    assert call(nbytes=need - 1, use_opt=False) == _lib.QBX_EWORKSPACE
+
+
 def test_timer_class_count_matches_header():
     """qbx_kernel_timer_read writes QBX_TIMER_CLASSES entries into caller arrays: the
     binding's constant must be the header's."""
