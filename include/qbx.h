@@ -169,6 +169,19 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
                               double r, int oversample, int side, int kind, double gamma,
                               double* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Vector-Jacobian product of qbx_layer_potential_split with respect to the
+ * density (PyTorch convention, the conjugate-transposed operator A^H applied
+ * to the cotangent): the same near relation and rules as the forward, so
+ * <g, A sigma> = <A^H g, sigma> holds to rounding.  cotangent has the shape of
+ * out; grad_density [n_kinds][T] complex.  Node gradients are not formed.
+ * Errors as qbx_layer_potential_split, plus QBX_EINVAL for a NULL cotangent or
+ * grad_density.  Stream-ordered, no allocation; qbx_workspace_bytes(). */
+int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* density, double k,
+                                      int p, double r, int oversample, int side, int kind,
+                                      double gamma, const double* cotangent,
+                                      double* grad_density, void* ws, size_t ws_bytes,
+                                      hipStream_t stream);
+
 /* ---- integral equation ------------------------------------------------ */
 
 /* Workspace bytes of qbx_solve_dirichlet (0 for invalid arguments; side must

@@ -104,6 +104,12 @@ void set_launch_shape(Dims* d) {
   if (fs < 1) fs = 1;
   d->panels_per_fsplit = (int)((d->P + fs - 1) / fs);
   d->n_fsplit = (d->P + d->panels_per_fsplit - 1) / d->panels_per_fsplit;
+  // its density adjoint, far part: 64 sources a wave, target splits alike
+  long as = (kSplitFarWaves + d->chunks - 1) / d->chunks;
+  if (as > d->P) as = d->P;
+  if (as < 1) as = 1;
+  d->panels_per_asplit = (int)((d->P + as - 1) / as);
+  d->n_asplit = (d->P + d->panels_per_asplit - 1) / d->panels_per_asplit;
 }
 
 bool make_dims(int n_panels, int q, int p, int oversample, int side, int kind, double k, double r,
@@ -163,6 +169,9 @@ Layout make_layout(const Dims& d) {
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
   L.bnd = take(sizeof(double4) * (size_t)d.P);
   L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T);
+  L.gfar = take(sizeof(double2) * (size_t)d.nk * d.T);
+  L.aacc = take(sizeof(double2) * (size_t)d.nk * d.N);
+  L.apart = take(sizeof(double2) * (size_t)d.n_asplit * d.nk * d.N);
   L.total = o;
   return L;
 }
@@ -363,6 +372,38 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   if (e != hipSuccess) return device_fail(e, "split far kernel");
   e = launch_split_finalize(d, at<double2>(ws, L.partial), at<double2>(ws, L.fpart), out, stream);
   if (e != hipSuccess) return device_fail(e, "split finalize kernel");
+  return QBX_OK;
+}
+
+int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* density, double k,
+                                      int p, double r, int oversample, int side, int kind,
+                                      double gamma, const double* cotangent,
+                                      double* grad_density, void* ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!(gamma > 0.0)) return fail(QBX_EINVAL, "near-panel factor gamma = %g must be > 0", gamma);
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!cotangent) return fail(QBX_EINVAL, "cotangent is NULL");
+  if (!grad_density) return fail(QBX_EINVAL, "grad_density is NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
+  if (e != hipSuccess) return device_fail(e, "cotangent kernel");
+  e = launch_split_adjoint_density(d, g->nodes, at<double>(ws, L.tables), at<double4>(ws, L.geo),
+                                   at<double>(ws, L.wgt), at<CenterRec>(ws, L.ctr),
+                                   at<double>(ws, L.jtab), at<double4>(ws, L.bnd), gamma * gamma,
+                                   at<double2>(ws, L.G), at<double2>(ws, L.gfar),
+                                   at<double2>(ws, L.aacc), at<double2>(ws, L.apart),
+                                   grad_density, stream);
+  if (e != hipSuccess) return device_fail(e, "split adjoint kernels");
   return QBX_OK;
 }
 

@@ -54,6 +54,9 @@ struct Dims {
   // split forward, far pass: waves of 64 targets x panels_per_fsplit source
   // panels, n_fsplit source splits
   int n_fsplit, panels_per_fsplit;
+  // its density adjoint, far part: waves of 64 sources x panels_per_asplit
+  // target panels, n_asplit target splits
+  int n_asplit, panels_per_asplit;
 };
 
 // Byte offsets of the workspace arrays (all 256-byte aligned).
@@ -75,6 +78,9 @@ struct Layout {
   size_t scratch;  // double[16 + Mc] small reductions
   size_t bnd;      // double4[P] split forward: panel mean and squared radius
   size_t fpart;    // double2[n_fsplit][nk][T] split forward: far sums
+  size_t gfar;     // double2[nk][T] split adjoint: cotangent weights of both sides
+  size_t aacc;     // double2[nk][N] split adjoint: near sums per source
+  size_t apart;    // double2[n_asplit][nk][N] split adjoint: far sums per source
   size_t total;
 };
 
@@ -134,6 +140,13 @@ hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* de
                             hipStream_t s);
 hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const double2* farp,
                                  double* out, hipStream_t s);
+// the split's adjoint with respect to the density (G from launch_make_G)
+hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
+                                        const double4* geo, const double* wgt,
+                                        const CenterRec* ctr, const double* jtab,
+                                        const double4* bnd, double g2, const double2* G,
+                                        double2* Gf, double2* acc, double2* partial,
+                                        double* grad_density, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,

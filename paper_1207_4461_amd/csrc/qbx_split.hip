@@ -183,6 +183,250 @@ __global__ __launch_bounds__(256) void k_split_finalize(int Mc, int T, int nk, i
   out[2 * o + 1] = 0.25 * r;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the split with respect to the density.  With G_i = conj(g_i) i/4
+// (per kind and center) the gradient of L = Re <g, u> with respect to q_j =
+// w_j sigma_j is conj(sum_i G_i K_ij), K the pair kernel of whichever rule
+// (QBX or direct) the pair takes; the density gradient is then the transposed
+// interpolation of w_j conj(...) (PyTorch's convention, A^H g).
+// ---------------------------------------------------------------------------
+
+// acc[kk][j] = sum over the centers i of target panels near j's panel of G_i K_ij
+// (QBX pairs).  One wave per 64-source chunk: the wave scans the target panels
+// near any of its chunk's source panels, and each lane adds the centers of a
+// scanned panel only when that panel is near its own source panel.
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_split_near_adj(
+    const double4* __restrict__ geo, int N, int qs, const CenterRec* __restrict__ ctr,
+    const double* __restrict__ jtab, int NJ, int Mc, int T, int n_sides,
+    const double4* __restrict__ bnd, int NP, double g2, double k,
+    const double2* __restrict__ G, double2* __restrict__ acc) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + wave;
+  if (c * kWave >= N) return;
+  const int j = c * kWave + lane;
+  const bool valid = j < N;
+  const int jj = valid ? j : N - 1;
+  const double4 bj = bnd[jj / qs];
+  const int pa = (c * kWave) / qs;
+  const int pb = min(c * kWave + kWave - 1, N - 1) / qs;
+  const double4 g = geo[jj];
+  const double inv_k = 1.0 / k;
+  double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mt = w0 + lane;
+    bool any = false;
+    if (mt < NP) {
+      const double4 bt = bnd[mt];
+      for (int ps = pa; ps <= pb; ++ps) any = any || panels_near(bt, bnd[ps], g2);
+    }
+    unsigned long long mask = __ballot(any);
+    while (mask) {
+      const int m = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      if (valid && panels_near(bnd[m], bj, g2)) {
+        for (int si_ = 0; si_ < n_sides; ++si_) {
+          for (int a = 0; a < kQ; ++a) {
+            const int ci = si_ * T + m * kQ + a;
+            const int z0 = opaque_zero();
+            const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
+            const double* __restrict__ cf = g_seed_table + z0;
+            const CenterRec* C = ctr + ci;
+            const double vx = g.x - C->cx, vy = g.y - C->cy;
+            const double rho2 = fma(vx, vx, vy * vy);
+            const double ir = rsqrt_refined(rho2);
+            const double rho = rho2 * ir;
+            const double cd = (C->ct * vx + C->st * vy) * ir;
+            const double sd = (C->st * vx - C->ct * vy) * ir;
+            double cps = 0.0, sps = 0.0;
+            if (kD) {
+              cps = C->ct * g.z + C->st * g.w;
+              sps = C->st * g.z - C->ct * g.w;
+            }
+            double ks_r, ks_i, kd_r, kd_i;
+            pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, ks_r, ks_i, kd_r,
+                                 kd_i);
+            int kk = 0;
+            if (kS) {
+              const double2 Gi = G[(size_t)(kk++) * Mc + ci];
+              sr = fma(Gi.x, ks_r, fma(-Gi.y, ks_i, sr));
+              si = fma(Gi.x, ks_i, fma(Gi.y, ks_r, si));
+            }
+            if (kD) {
+              const double2 Gi = G[(size_t)kk * Mc + ci];
+              dr = fma(Gi.x, kd_r, fma(-Gi.y, kd_i, dr));
+              di = fma(Gi.x, kd_i, fma(Gi.y, kd_r, di));
+            }
+          }
+        }
+      }
+    }
+  }
+  if (valid) {
+    int kk = 0;
+    if (kS) acc[(size_t)(kk++) * N + j] = make_double2(sr, si);
+    if (kD) acc[(size_t)kk * N + j] = make_double2(k * dr, k * di);
+  }
+}
+
+// Gf[kk][t] = sum over the sides of G[kk][si T + t]: the far sums do not depend on
+// the side, so their transpose takes the two sides' cotangents together
+__global__ __launch_bounds__(256) void k_split_gfar(int T, int nk, int n_sides,
+                                                   const double2* __restrict__ G,
+                                                   double2* __restrict__ Gf) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T * nk) return;
+  const int kk = e / T, t = e - kk * T;
+  const size_t Mc = (size_t)n_sides * T;
+  double2 v = G[kk * Mc + t];
+  if (n_sides == 2) {
+    const double2 w = G[kk * Mc + T + t];
+    v = make_double2(v.x + w.x, v.y + w.y);
+  }
+  Gf[e] = v;
+}
+
+// partial[sp][kk][j]: sum over the targets t of far panels in split sp of
+// Gf_t K_far(t, j); lanes are 64 consecutive sources, targets wave-uniform
+template <int KIND>
+__global__ __launch_bounds__(256) void k_split_far_adj(
+    const double4* __restrict__ geo, int N, int qs, const double* __restrict__ nodes, int T,
+    const double4* __restrict__ bnd, int NP, double g2, double k,
+    const double2* __restrict__ Gf, int n_sb, int n_asplit, int ppw,
+    double2* __restrict__ partial) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + wave;
+  const int sp = gw / n_sb;
+  const int sb = gw - sp * n_sb;
+  if (sp >= n_asplit) return;
+  const int j = sb * kWave + lane;
+  const bool valid = j < N;
+  const int jj = valid ? j : N - 1;
+  const double4 g = geo[jj];
+  const double4 bj = bnd[jj / qs];
+  const int p0 = sp * ppw;
+  const int p1 = min(NP, p0 + ppw);
+  const double inv_k = 1.0 / k;
+  double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  for (int mt = p0; mt < p1; ++mt) {
+    const bool far = valid && !panels_near(bnd[mt], bj, g2);
+    if (far) {
+      for (int a = 0; a < kQ; ++a) {
+        const int t = mt * kQ + a;
+        const int z0 = opaque_zero();
+        const double* __restrict__ cf = g_seed_table + z0;
+        const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
+        const double rho2 = fma(dx, dx, dy * dy);
+        const double ir = rsqrt_refined(rho2);
+        const double rho = rho2 * ir;
+        const H01 h = hankel01(k * rho, ir * inv_k, cf);
+        int kk = 0;
+        if (kS) {
+          const double2 Gt = Gf[(size_t)(kk++) * T + t];
+          sr = fma(Gt.x, h.h0r, fma(-Gt.y, h.h0i, sr));
+          si = fma(Gt.x, h.h0i, fma(Gt.y, h.h0r, si));
+        }
+        if (kD) {
+          const double2 Gt = Gf[(size_t)kk * T + t];
+          const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
+          const double wr = Gt.x * f, wi = Gt.y * f;
+          dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
+          di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+        }
+      }
+    }
+  }
+  if (valid) {
+    int kk = 0;
+    if (kS) partial[((size_t)sp * NK + kk++) * N + j] = make_double2(sr, si);
+    if (kD) partial[((size_t)sp * NK + kk) * N + j] = make_double2(k * dr, k * di);
+  }
+}
+
+// grad_density[kk][16 m + a] = sum_b V[b][a] w_j conj(acc[kk][j] + sum_sp partial[sp][kk][j]),
+// j = m qs + b: one thread per node and kind
+__global__ __launch_bounds__(256) void k_split_density_grad(
+    int T, int N, int qs, int nk, int n_asplit, const double* __restrict__ tab,
+    const double* __restrict__ wgt, const double2* __restrict__ acc,
+    const double2* __restrict__ partial, double* __restrict__ grad_density) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T * nk) return;
+  const TableLayout L = table_layout(qs);
+  const int kk = e / T, t = e - kk * T;
+  const int m = t / kQ, a = t - m * kQ;
+  double gr = 0.0, gi = 0.0;
+  for (int b = 0; b < qs; ++b) {
+    const size_t j = (size_t)m * qs + b;
+    double2 v = acc[(size_t)kk * N + j];
+    for (int sp = 0; sp < n_asplit; ++sp) {
+      const double2 q = partial[((size_t)sp * nk + kk) * N + j];
+      v.x += q.x;
+      v.y += q.y;
+    }
+    const double c = tab[L.V + b * kQ + a] * wgt[j];
+    gr = fma(c, v.x, gr);
+    gi = fma(-c, v.y, gi);      // conj
+  }
+  grad_density[2 * (size_t)e] = gr;
+  grad_density[2 * (size_t)e + 1] = gi;
+}
+
+template <int P>
+static hipError_t launch_split_near_adj_p(const Dims& d, const double4* geo, const CenterRec* ctr,
+                                          const double* jtab, const double4* bnd, double g2,
+                                          const double2* G, double2* acc, hipStream_t s) {
+  const int chunks = (d.N + kWave - 1) / kWave;
+  const dim3 grid((unsigned)((chunks + 3) / 4)), block(256);
+#define QBX_NADJ_ARGS geo, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, d.k, G, acc
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_near_adj<P, 1>), grid, block, 0, s, QBX_NADJ_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_near_adj<P, 2>), grid, block, 0, s, QBX_NADJ_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_near_adj<P, 3>), grid, block, 0, s, QBX_NADJ_ARGS); break;
+  }
+#undef QBX_NADJ_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
+                                        const double4* geo, const double* wgt,
+                                        const CenterRec* ctr, const double* jtab,
+                                        const double4* bnd, double g2, const double2* G,
+                                        double2* Gf, double2* acc, double2* partial,
+                                        double* grad_density, hipStream_t s) {
+  hipError_t e;
+  {
+    auto launch = [&]() -> hipError_t {
+      QBX_P_SWITCH(d.p, launch_split_near_adj_p, d, geo, ctr, jtab, bnd, g2, G, acc, s)
+    };
+    e = launch();
+    if (e != hipSuccess) return e;
+  }
+  const int nt = d.T * d.nk;
+  hipLaunchKernelGGL(k_split_gfar, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.nk, d.n_sides,
+                     G, Gf);
+  const int n_sb = (d.N + kWave - 1) / kWave;
+  const long waves = (long)n_sb * d.n_asplit;
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_FADJ_ARGS \
+  geo, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit, d.panels_per_asplit, partial
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_far_adj<1>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_far_adj<2>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_far_adj<3>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+  }
+#undef QBX_FADJ_ARGS
+  hipLaunchKernelGGL(k_split_density_grad, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.N, d.qs,
+                     d.nk, d.n_asplit, tables, wgt, acc, partial, grad_density);
+  return hipGetLastError();
+}
+
 hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s) {
   hipLaunchKernelGGL(k_panel_bounds, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, nodes, bnd);
   return hipGetLastError();

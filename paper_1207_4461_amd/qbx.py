@@ -150,6 +150,30 @@ def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, 
     return out
 
 
+def layer_potential_split_vjp(nodes: torch.Tensor, density: torch.Tensor,
+                              cotangent: torch.Tensor, k: float, p: int, r: float = 0.5,
+                              oversample: int = 4, side: int = EXTERIOR, kind: int = S,
+                              gamma: float = 6.0,
+                              workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Density gradient of L = Re <cotangent, layer_potential_split(...)>
+    (qbx_layer_potential_split_adjoint): [n_kinds, 16P] complex128."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    _need(cotangent, "cotangent", torch.complex128, (n_sides(side), nk, P * Q))
+    dev = nodes.device
+    gd = torch.empty((nk, P * Q), dtype=torch.complex128, device=dev)
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    _lib.check(lib.qbx_layer_potential_split_adjoint(
+        C.byref(geo), density.data_ptr(), float(k), int(p), float(r), int(oversample), int(side),
+        int(kind), float(gamma), cotangent.data_ptr(), gd.data_ptr(), ws.data_ptr(), ws.numel(),
+        _stream(dev)))
+    return gd
+
+
 def solve_workspace_bytes(n_panels: int, p: int, oversample: int, side: int, restart: int) -> int:
     n = _lib.load().qbx_solve_workspace_bytes(n_panels, Q, p, oversample, side, restart)
     if n == 0:

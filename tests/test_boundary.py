@@ -164,6 +164,20 @@ def test_ext_entry_point_validates(lib):
     assert call(nbytes=need - 1, use_opt=False) == _lib.QBX_EWORKSPACE
 
 
+def test_split_adjoint_entry_point_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+
+    def call(**kw):
+        return lib.qbx_layer_potential_split_adjoint(
+            C.byref(g), kw.get("dens", BAD), 3.0, 6, 0.5, 4, 1, 1, kw.get("gamma", 6.0),
+            kw.get("cot", BAD), kw.get("gd", BAD), kw.get("ws", BAD), kw.get("nbytes", 1 << 40),
+            None)
+
+    for bad in (dict(gamma=0.0), dict(dens=None), dict(cot=None), dict(gd=None), dict(ws=None)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(nbytes=lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1) - 1) == _lib.QBX_EWORKSPACE
+
+
 def test_timer_class_count_matches_header():
     """qbx_kernel_timer_read writes QBX_TIMER_CLASSES entries into caller arrays: the
     binding's constant must be the header's."""

@@ -122,3 +122,64 @@ def test_split_green_identity_on_gpu(Q):
     e_out = np.abs(v[0, 0] - v[0, 1]).max() / sc
     say(f"  interior {e_in:.3e} exterior {e_out:.3e}")
     assert e_in < 1e-8 and e_out < 1e-8
+
+
+def oracle_split_density_grad(pb, gamma):
+    dens = torch.tensor(pb.density, dtype=torch.complex128, requires_grad=True)
+    u = O.layer_potential_split(pb.nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                gamma=gamma)
+    L = torch.real(torch.sum(torch.conj(torch.as_tensor(pb.cotangent)) * u))
+    L.backward()
+    return dens.grad.numpy()
+
+
+ADJ_CASES = [
+    dict(name="S-ext-p4-g3", n_panels=9, p=4, kind=1, side=1, gamma=3.0),
+    dict(name="D-int-p6-g4", n_panels=10, p=6, kind=2, side=-1, gamma=4.0),
+    dict(name="SD-both-p12-g6", n_panels=13, p=12, kind=3, side=0, gamma=6.0),
+    dict(name="SD-both-p20-os1-g6", n_panels=11, p=20, kind=3, side=0, oversample=1, gamma=6.0),
+    dict(name="SD-both-p9-os3-g5", n_panels=9, p=9, kind=3, side=0, oversample=3, k=7.0, gamma=5.0),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[c["name"] for c in ADJ_CASES])
+def test_split_density_adjoint_small(Q, case):
+    c = dict(case)
+    name, gamma = c.pop("name"), c.pop("gamma")
+    pb = I.small(name=name, **c)
+    ref = oracle_split_density_grad(pb, gamma)
+    gd = Q.layer_potential_split_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k,
+                                     pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                     gamma=gamma).cpu().numpy()
+    e = rel(gd, ref)
+    say(f"  {name}: density gradient vs oracle autograd {e:.3e}")
+    assert e <= TOL
+
+
+def test_split_density_adjoint_all_near_is_the_plain_adjoint(Q):
+    pb = I.small(n_panels=9, p=11, k=6.0, kind=3, side=I.BOTH)
+    a = Q.layer_potential_split_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k, pb.p,
+                                    pb.r, pb.oversample, pb.side, pb.kind, gamma=1e150)
+    b, _ = Q.layer_potential_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent), pb.k, pb.p,
+                                 pb.r, pb.oversample, pb.side, pb.kind, want_nodes=False)
+    e = rel(a.cpu().numpy(), b.cpu().numpy())
+    say(f"  all-near split adjoint vs plain adjoint {e:.2e}")
+    assert e < 1e-13
+
+
+@pytest.mark.parametrize("cfg", ["star1024", "star4096"])
+def test_split_density_adjoint_dot_product(Q, cfg):
+    """<g, A sigma> = <A^H g, sigma> for the split operator at full size."""
+    pb = getattr(I, cfg)()
+    nodes, dens = dev(pb.nodes), dev(pb.density)
+    rng = np.random.default_rng(3)
+    g = dev(rng.standard_normal((pb.n_sides, pb.n_kinds, pb.n_targets))
+            + 1j * rng.standard_normal((pb.n_sides, pb.n_kinds, pb.n_targets)))
+    args = (pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    u = Q.layer_potential_split(nodes, dens, *args, gamma=6.0)
+    gd = Q.layer_potential_split_vjp(nodes, dens, g, *args, gamma=6.0)
+    lhs = complex(torch.sum(torch.conj(g) * u))
+    rhs = complex(torch.sum(torch.conj(gd) * dens))
+    e = abs(lhs - rhs) / abs(lhs)
+    say(f"  {cfg}: <g, A s> {lhs:.12e}  <A^H g, s> {rhs:.12e}  rel {e:.2e}")
+    assert e < 1e-12
