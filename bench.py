@@ -73,10 +73,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star4096",
                     choices=["ellipse32", "star256", "star1024", "random64", "star4096"])
-    ap.add_argument("--mode", default=None, choices=["fwd", "fwdbwd", "grad", "split", "solve"],
+    ap.add_argument("--mode", default=None,
+                    choices=["fwd", "fwdbwd", "grad", "split", "splitbwd", "solve"],
                     help="grad: the target derivatives (grad S, grad D, S', D') instead; "
                          "split: the forward with the near/far split (QBX for near panels "
-                         "only, the smooth rule applied directly for the rest); solve: the "
+                         "only, the smooth rule applied directly for the rest); splitbwd: "
+                         "that forward and its density adjoint; solve: the "
                          "exterior Dirichlet problem with point-charge data, GMRES to 1e-14 "
                          "(products by the split when --gamma > 0)")
     ap.add_argument("--gamma", type=float, default=6.0,
@@ -150,7 +152,7 @@ def main():
     dens = torch.from_numpy(np.ascontiguousarray(pb.density)).to(dev)
     cot = torch.from_numpy(np.ascontiguousarray(pb.cotangent)).to(dev)
     tuning = qbx.get_tuning()
-    if args.autotune and mode != "split":   # the split's launch shapes are fixed
+    if args.autotune and mode not in ("split", "splitbwd"):   # the split's shapes are fixed
         t0 = time.perf_counter()
         tuning = qbx.autotune(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
                               passes=1, fields=tune_fields(mode, args.backward))
@@ -173,9 +175,13 @@ def main():
         if mode == "grad":
             return qbx.layer_potential_gradient(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
                                                 pb.side, pb.kind, workspace=ws)
-        if mode == "split":
-            return qbx.layer_potential_split(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
-                                             pb.side, pb.kind, gamma=args.gamma, workspace=ws)
+        if mode in ("split", "splitbwd"):
+            u = qbx.layer_potential_split(nodes, dens, pb.k, pb.p, pb.r, pb.oversample,
+                                          pb.side, pb.kind, gamma=args.gamma, workspace=ws)
+            if mode == "splitbwd":
+                qbx.layer_potential_split_vjp(nodes, dens, cot, pb.k, pb.p, pb.r, pb.oversample,
+                                              pb.side, pb.kind, gamma=args.gamma, workspace=ws)
+            return u
         if args.backward == "fused":
             # forward, then the adjoint without a tape (one fused pass over the pairs)
             u = fwd()
@@ -222,15 +228,17 @@ def main():
     pairs = pb.n_centers * pb.n_sources
     names = ["forward pair kernel", "adjoint source pass", "batched persistent kernel",
              "forward-with-tape pair kernel", "fused adjoint pair kernel",
-             "target-derivative pair kernel", "split near pass", "split far pass"]
+             "target-derivative pair kernel", "split near pass", "split far pass",
+             "split far-pass adjoint"]
     per_pair = [flops.flops_forward_pair(pb.p, pb.kind), flops.flops_adjoint_pair(pb.p, pb.kind),
                 0, flops.flops_tape_pair(pb.p, pb.kind), flops.flops_fused_pair(pb.p, pb.kind),
                 flops.flops_grad_pair(pb.p, pb.kind), flops.flops_forward_pair(pb.p, pb.kind),
-                flops.flops_far_pair(pb.kind)]
-    pairs_of = [pairs] * 6 + [0, 0]
-    if mode == "split":
+                flops.flops_far_pair(pb.kind), flops.flops_far_pair(pb.kind)]
+    pairs_of = [pairs] * 6 + [0, 0, 0]
+    if mode in ("split", "splitbwd"):
         pairs_of[6], pairs_of[7] = flops.split_pairs(pb.nodes, pb.oversample, pb.n_sides,
                                                      args.gamma)
+        pairs_of[8] = pairs_of[7]
     kernels = {}
     for c in range(NC):
         if nl[c] == 0 or per_pair[c] == 0:
@@ -244,7 +252,7 @@ def main():
     achieved = dom["tflops"]
     avg_ms = dom["avg_ms"]
     kernel_names = ["k_forward", "k_adjoint_src", "", "k_forward_tape", "k_adjoint_fused",
-                    "k_forward_grad", "k_split_near", "k_split_far"]
+                    "k_forward_grad", "k_split_near", "k_split_far", "k_split_far_adj"]
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(kernel_names[cls], args.workload),
@@ -265,7 +273,7 @@ def main():
                 return O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
                                                   pb.oversample, pb.side, pb.kind,
                                                   targets=idx)[1].numpy()
-            if mode == "split":
+            if mode in ("split", "splitbwd"):
                 return O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r,
                                                pb.oversample, pb.side, pb.kind, gamma=args.gamma,
                                                targets=idx).numpy()
@@ -285,19 +293,20 @@ def main():
         if mode == "grad":
             u = step()[1].cpu().numpy()[:, :, idx]
         else:
-            u = step().cpu().numpy()[:, :, idx] if mode == "split" else fwd().cpu().numpy()[:, :, idx]
+            u = (step().cpu().numpy()[:, :, idx] if mode in ("split", "splitbwd")
+                 else fwd().cpu().numpy()[:, :, idx])
         err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
                         for s in range(u.shape[0]) for k in range(u.shape[1])))
         cpu = {"value": cpu_inter / tc, "unit": "interactions/s", "cores": torch.get_num_threads(),
                "kind": "oracle",
-               "sample": f"{ {'grad': 'normal derivative', 'split': 'split forward'}.get(mode, 'forward')} at "
+               "sample": f"{ {'grad': 'normal derivative', 'split': 'split forward', 'splitbwd': 'split forward'}.get(mode, 'forward')} at "
                          f"{len(idx)} random targets x {pb.n_sides} sides "
                          f"({ncent} centers) against all {pb.n_sources} sources, "
                          f"{tc:.1f} s; GPU/oracle max rel err on the sample {err:.2e}"}
         log(f"cpu oracle: {cpu_inter / tc:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
 
     out = {
-        "metric": METRIC if mode != "split" else SPLIT_METRIC,
+        "metric": METRIC if mode not in ("split", "splitbwd") else SPLIT_METRIC,
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -314,7 +323,7 @@ def main():
                                f"side={'both' if pb.side == 0 else pb.side}, "
                                f"kind={'S+D' if pb.kind == 3 else ('S' if pb.kind == 1 else 'D')}",
                    "mode": mode, "backward": args.backward if mode == "fwdbwd" else None,
-                   "gamma": args.gamma if mode == "split" else None,
+                   "gamma": args.gamma if mode in ("split", "splitbwd") else None,
                    "centers": pb.n_centers, "sources": pb.n_sources,
                    "interactions_per_step": inter, "tuning": tuning},
         "fwd_value": inter / fwd_s,

@@ -467,10 +467,10 @@ int qbx_kernel_timer(int enable);
  * (0 = forward pair kernel, 1 = adjoint source pass, 2 = batched persistent
  * kernels, 3 = forward-with-tape pair kernel, 4 = fused adjoint pair kernel,
  * 5 = target-derivative pair kernel, 6 = near pass of the split forward,
- * 7 = far pass of the split forward),
+ * 7 = far pass of the split forward, 8 = far pass of the split's density adjoint),
  * the summed duration in milliseconds and the number of launches since the
  * timer was enabled.  ms and launches are host arrays of QBX_TIMER_CLASSES. */
-#define QBX_TIMER_CLASSES 8
+#define QBX_TIMER_CLASSES 9
 int qbx_kernel_timer_read(double* ms, int* launches);
 
 #ifdef __cplusplus

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqbx.so")
 
 QBX_TUNE_FORWARD, QBX_TUNE_TAPE, QBX_TUNE_ADJOINT, QBX_TUNE_FUSED, QBX_TUNE_ALL = 1, 2, 4, 8, 15
-QBX_TIMER_CLASSES = 8   # entries qbx_kernel_timer_read writes
+QBX_TIMER_CLASSES = 9   # entries qbx_kernel_timer_read writes
 QBX_OK = 0
 QBX_EINVAL = -1
 QBX_EWORKSPACE = -2

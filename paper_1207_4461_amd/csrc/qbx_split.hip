@@ -416,11 +416,13 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS \
   geo, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit, d.panels_per_asplit, partial
+  timer_begin(8, s);
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far_adj<1>), grid, block, 0, s, QBX_FADJ_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_far_adj<2>), grid, block, 0, s, QBX_FADJ_ARGS); break;
     default: hipLaunchKernelGGL((k_split_far_adj<3>), grid, block, 0, s, QBX_FADJ_ARGS); break;
   }
+  timer_end(8, s);
 #undef QBX_FADJ_ARGS
   hipLaunchKernelGGL(k_split_density_grad, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.N, d.qs,
                      d.nk, d.n_asplit, tables, wgt, acc, partial, grad_density);

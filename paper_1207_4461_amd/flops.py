@@ -176,7 +176,8 @@ def flops_grad_pair(p: int, kind: int) -> int:
 
 
 def flops_far_pair(kind: int) -> int:
-    """Far pass of the split forward, per (target, source) pair on a far panel:
+    """Far pass of the split forward, per (target, source) pair on a far panel (its
+    density adjoint has the same count, with the cotangent weight in place of q):
     x - x' (2), rho (4), 1/rho (1), z and 1/z (2), seed H0, H1 (103); S: w sigma H_0
     (8); D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).
     S: 120, D: 126, S+D: 134."""
