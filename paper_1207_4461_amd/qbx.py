@@ -349,9 +349,41 @@ class _LayerPotential(torch.autograd.Function):
         return gn, gd, None, None, None, None, None, None
 
 
+class _SplitLayerPotential(torch.autograd.Function):
+    """out = layer_potential_split(nodes, density, ...) with its density adjoint as backward
+    (the split forms no node gradient)."""
+
+    @staticmethod
+    def forward(ctx, nodes, density, k, p, r, oversample, side, kind, gamma):
+        out = layer_potential_split(nodes.detach(), density.detach(), k, p, r, oversample, side,
+                                    kind, gamma=gamma)
+        ctx.save_for_backward(nodes, density)
+        ctx.args = (k, p, r, oversample, side, kind, gamma)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        nodes, density = ctx.saved_tensors
+        k, p, r, oversample, side, kind, gamma = ctx.args
+        gd = None
+        if ctx.needs_input_grad[1]:
+            gd = layer_potential_split_vjp(nodes.detach(), density.detach(),
+                                           grad_out.contiguous().to(torch.complex128), k, p, r,
+                                           oversample, side, kind, gamma=gamma)
+        return None, gd, None, None, None, None, None, None, None
+
+
 def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
-              oversample: int = 4, side: int = EXTERIOR, kind: int = S) -> torch.Tensor:
-    """Differentiable layer_potential (gradients for density and nodes via the HIP adjoint)."""
+              oversample: int = 4, side: int = EXTERIOR, kind: int = S,
+              gamma: Optional[float] = None) -> torch.Tensor:
+    """Differentiable layer_potential (gradients for density and nodes via the HIP adjoint).
+    With gamma: the near/far split (layer_potential_split) and its density adjoint; the
+    nodes must then not require a gradient (the split forms none)."""
+    if gamma is not None:
+        if nodes.requires_grad:
+            raise ValueError("the near/far split has no node gradient: detach the nodes")
+        return _SplitLayerPotential.apply(nodes, density, float(k), int(p), float(r),
+                                          int(oversample), int(side), int(kind), float(gamma))
     return _LayerPotential.apply(nodes, density, float(k), int(p), float(r), int(oversample),
                                  int(side), int(kind))
 

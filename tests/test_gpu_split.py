@@ -183,3 +183,20 @@ def test_split_density_adjoint_dot_product(Q, cfg):
     e = abs(lhs - rhs) / abs(lhs)
     say(f"  {cfg}: <g, A s> {lhs:.12e}  <A^H g, s> {rhs:.12e}  rel {e:.2e}")
     assert e < 1e-12
+
+
+def test_split_autograd_function(Q):
+    pb = I.small(n_panels=10, p=8, k=4.0, kind=3, side=I.BOTH)
+    nodes = dev(pb.nodes)
+    dens = dev(pb.density).requires_grad_(True)
+    u = Q.qbx_apply(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind, gamma=4.0)
+    L = torch.real(torch.sum(torch.conj(dev(pb.cotangent)) * u))
+    L.backward()
+    ref = oracle_split_density_grad(pb, 4.0)
+    assert rel(dens.grad.cpu().numpy(), ref) <= TOL
+    f = lambda Dn: Q.qbx_apply(nodes, Dn, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                               gamma=4.0)
+    assert torch.autograd.gradcheck(f, (dens.detach().clone().requires_grad_(True),),
+                                    eps=1e-7, atol=1e-6, rtol=1e-5)
+    with pytest.raises(ValueError):
+        Q.qbx_apply(nodes.clone().requires_grad_(True), dens, pb.k, pb.p, gamma=4.0)
