@@ -9,7 +9,8 @@ Two regimes (z = k*rho > 0):
   J_nu + i Y_nu and stored as monomial coefficients in s:
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
   A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
-  (used when every lane of a wavefront is that far).
+  (used when every lane of a wavefront is that far), and a third, shorter still,
+  in s = (ZV/z)^2 serves z >= ZV in the direct (far-panel) passes of the split.
 * the phase e^{i(z - pi/4)} = T_n e^{ir}: n = rint(z N / 2 pi), r = z - 2 pi n / N by a
   three-part Cody-Waite reduction, T_n = e^{i(2 pi n/N - pi/4)} from a table of N
   entries (40-digit values rounded once), and sin r, cos r as polynomials in r^2
@@ -42,6 +43,8 @@ Z0 = 6.0
 DEG = 12          # degree in s of the P, Q fits
 ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
+ZV = 60.0
+DEG_VFAR = 4      # degree in s = (ZV/z)^2 of the fits for z >= ZV
 PHASE_N = 256     # phase table entries e^{i(2 pi n/N - pi/4)}
 R_TRIG = 0.01228  # reduced argument bound (pi/N plus the reduction's rounding)
 DEG_SIN = 3       # degree in r^2 of sin(r)/r
@@ -141,6 +144,10 @@ def main():
                                             DEG_FAR)
         fits[f"FQ{nu}"] = cheb_fit_monomial(
             lambda s, nu=nu: pq(nu, ZF / mpmath.sqrt(s))[1] * (ZF / mpmath.sqrt(s)) / ZF, DEG_FAR)
+        fits[f"VP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZV / mpmath.sqrt(s))[0],
+                                            DEG_VFAR)
+        fits[f"VQ{nu}"] = cheb_fit_monomial(
+            lambda s, nu=nu: pq(nu, ZV / mpmath.sqrt(s))[1] * (ZV / mpmath.sqrt(s)) / ZV, DEG_VFAR)
     zc, zh = mpmath.mpf(ZC), mpmath.mpf(ZH)
     fits["MJ0"] = cheb_fit_monomial_pm1(lambda x: mpmath.besselj(0, zc + zh * x), DEG_MID)
     def Lg(z):
@@ -195,6 +202,14 @@ def main():
             Qv = (ZF / z) * horner(dbl[f"FQ{nu}"], s)
             pr, qr = pq(nu, z)
             worst_far = max(worst_far, abs(complex(P - float(pr), Qv - float(qr))))
+    worst_vfar = 0.0
+    for z in np.concatenate([np.geomspace(ZV, 2e4, 1500), rng.uniform(ZV, 200, 500)]):
+        s = (ZV / z) ** 2
+        for nu in (0, 1):
+            P = horner(dbl[f"VP{nu}"], s)
+            Qv = (ZV / z) * horner(dbl[f"VQ{nu}"], s)
+            pr, qr = pq(nu, z)
+            worst_vfar = max(worst_vfar, abs(complex(P - float(pr), Qv - float(qr))))
     worst_big = worst_small = 0.0
     for z in zs_big:
         s = (Z0 / z) ** 2
@@ -217,6 +232,7 @@ def main():
             worst_small = max(worst_small, abs(complex(Jv, Yv) - ref) / abs(ref))
     print(f"fit error of P,Q (absolute, |P+iQ| ~ 1) for z >= {Z0}: {worst_big:.3e}")
     print(f"far fit error of P,Q for z >= {ZF} (degree {DEG_FAR}): {worst_far:.3e}")
+    print(f"very-far fit error of P,Q for z >= {ZV} (degree {DEG_VFAR}): {worst_vfar:.3e}")
     print(f"mid-range relative error of H for {Z1} <= z < {Z0}: {worst_mid:.3e}")
     print(f"series relative error of H for z < {Z1}: {worst_small:.3e}")
 
@@ -282,6 +298,7 @@ def main():
     out.append("namespace qbx {\nnamespace seed {\n\n")
     out.append(f"constexpr double kZ0 = {Z0:.17e};\nconstexpr double kZ1 = {Z1:.17e};\n")
     out.append(f"constexpr double kZF = {ZF:.17e};\n")
+    out.append(f"constexpr double kZV = {ZV:.17e};\n")
     out.append(f"constexpr double kZC = {ZC:.17e};\nconstexpr double kInvZH = {1.0 / ZH:.17e};\n")
     out.append(f"constexpr int kPhaseN = {PHASE_N};\n")
     out.append(f"constexpr double kInvDelta = {float(PHASE_N / (2 * mpmath.pi)):.17e};\n")
@@ -305,6 +322,7 @@ def main():
                   [float(a) for a in dY1]])
     block("TRIG", [sin_c + [0.0] * (len(cos_c) - len(sin_c)), cos_c])
     block("FAR", [dbl["FP0"], dbl["FQ0"], dbl["FP1"], dbl["FQ1"]])
+    block("VFAR", [dbl["VP0"], dbl["VQ0"], dbl["VP1"], dbl["VQ1"]])
     for name, (o, n) in offs.items():
         out.append(f"constexpr int k{name}Off = {o};\nconstexpr int k{name}Len = {n};\n")
     out.append(f"constexpr int kTRIGLenA = {len(sin_c)};   // sin(r)/r coefficients in TRIG\n")

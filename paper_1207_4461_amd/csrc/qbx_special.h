@@ -99,11 +99,47 @@ static __constant__ double g_seed_table[seed::kTableLen] = {QBX_SEED_TABLE_VALUE
 static __constant__ __align__(16) double g_phase_table[2 * seed::kPhaseN] = {
     QBX_PHASE_TABLE_VALUES};
 
+// H_0, H_1 from the amplitude functions P0, Q0, P1, Q1 of the asymptotic form:
+// with E = sqrt(2/(pi z)) e^{i(z - pi/4)}, H_0 = E (P0 + i Q0), H_1 = E (Q1 - i P1)
+__device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, double P1, double Q1,
+                                             const double* __restrict__ cf) {
+  constexpr double kSqrtTwoOverPi = 0.79788456080286535588;
+  H01 h;
+  // e^{i(z - pi/4)} = T_n e^{ir}
+  const double n = rint(z * seed::kInvDelta);
+  double r = fma(-n, seed::kDeltaHi, z);
+  r = fma(-n, seed::kDeltaMid, r);
+  r = fma(-n, seed::kDeltaLo, r);
+  const double* __restrict__ T = g_phase_table + 2 * ((int)n & (seed::kPhaseN - 1));
+  const double tc = T[0], ts = T[1];
+  double sn, cs;
+  horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn, cs);
+  sn *= r;
+  double er = fma(tc, cs, -ts * sn);
+  double ei = fma(tc, sn, ts * cs);
+  const double A = kSqrtTwoOverPi * rsqrt_refined(z);
+  er *= A;
+  ei *= A;
+  h.h0r = fma(er, P0, -ei * Q0);     // E (P0 + i Q0)
+  h.h0i = fma(er, Q0, ei * P0);
+  h.h1r = fma(er, Q1, ei * P1);      // E (Q1 - i P1)
+  h.h1i = fma(ei, Q1, -er * P1);
+  return h;
+}
+
+// H_0(z), H_1(z) for z >= seed::kZV with the shortest fits (degree 4 in
+// (kZV/z)^2), no branches: the direct passes of the near/far split take it when
+// every lane of the wave is that far
+__device__ __forceinline__ H01 hankel01_vfar(double z, double iz, const double* __restrict__ cf) {
+  const double t = seed::kZV * iz;
+  const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
+  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf);
+}
+
 // iz = 1/z (callers already hold it); cf = the coefficient table seed::kTable
 // (QBX_SEED_TABLE_VALUES), read with wave-uniform loads
 __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __restrict__ cf) {
   constexpr double kTwoOverPi = 0.63661977236758134308;
-  constexpr double kSqrtTwoOverPi = 0.79788456080286535588;
   constexpr double kEuler = 0.57721566490153286061;
   constexpr double kInvTwoPi = 0.15915494309189533577;
   H01 h;
@@ -124,25 +160,7 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
       P1 = pq.c;
       Q1 = t * pq.d;
     }
-    // e^{i(z - pi/4)} = T_n e^{ir}
-    const double n = rint(z * seed::kInvDelta);
-    double r = fma(-n, seed::kDeltaHi, z);
-    r = fma(-n, seed::kDeltaMid, r);
-    r = fma(-n, seed::kDeltaLo, r);
-    const double* __restrict__ T = g_phase_table + 2 * ((int)n & (seed::kPhaseN - 1));
-    const double tc = T[0], ts = T[1];
-    double sn, cs;
-    horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn, cs);
-    sn *= r;
-    double er = fma(tc, cs, -ts * sn);
-    double ei = fma(tc, sn, ts * cs);
-    const double A = kSqrtTwoOverPi * rsqrt_refined(z);
-    er *= A;
-    ei *= A;
-    h.h0r = fma(er, P0, -ei * Q0);     // E (P0 + i Q0)
-    h.h0i = fma(er, Q0, ei * P0);
-    h.h1r = fma(er, Q1, ei * P1);      // E (Q1 - i P1)
-    h.h1i = fma(ei, Q1, -er * P1);
+    h = hankel01_asym(z, P0, Q0, P1, Q1, cf);
   } else {
     const double L = log(0.5 * z) + kEuler;
     double J0, J1, R0, R1;   // Y0 = (2/pi) L J0 + R0,  Y1 = (2/pi)(L J1 - 1/z) + R1

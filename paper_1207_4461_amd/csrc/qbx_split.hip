@@ -15,7 +15,8 @@
 // only.  Far pass (k_split_far): the 64 lanes are 64 consecutive targets and the
 // sources of a run of panels are wave-uniform (scalar loads); a far pair adds
 //     S: w sigma H_0(k rho),    D: w mu k H_1(k rho) (x - x').n' / rho,
-// rho = |x - x'|, the normal derivative of H_0(k|x - x'|) at the source.  These
+// rho = |x - x'|, the normal derivative of H_0(k|x - x'|) at the source (the
+// seeds from the shortest fits when every lane of the wave has k rho >= 60).  These
 // sums do not depend on the side, so both sides share one far pass.  The
 // finalize adds, per center, the near sum and the far sums of its target in a
 // fixed order and applies i/4.
@@ -138,8 +139,8 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
         const double dx = tx - g.x, dy = ty - g.y;
         const double rho2 = fma(dx, dx, dy * dy);
         const double ir = rsqrt_refined(rho2);
-        const double rho = rho2 * ir;
-        const H01 h = hankel01(k * rho, ir * inv_k, cf);
+        const double z = k * (rho2 * ir), iz = ir * inv_k;
+        const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
         if (kS) {
           const double2 w = dens[j];
           sr = fma(w.x, h.h0r, fma(-w.y, h.h0i, sr));
@@ -325,8 +326,8 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
         const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
         const double rho2 = fma(dx, dx, dy * dy);
         const double ir = rsqrt_refined(rho2);
-        const double rho = rho2 * ir;
-        const H01 h = hankel01(k * rho, ir * inv_k, cf);
+        const double z = k * (rho2 * ir), iz = ir * inv_k;
+        const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
         int kk = 0;
         if (kS) {
           const double2 Gt = Gf[(size_t)(kk++) * T + t];

@@ -175,13 +175,18 @@ def flops_grad_pair(p: int, kind: int) -> int:
     return f
 
 
+SEED_VFAR = 85   # H_0, H_1 from the degree-4 fits of k rho >= 60 (the direct passes only)
+
+
 def flops_far_pair(kind: int) -> int:
     """Far pass of the split forward, per (target, source) pair on a far panel (its
     density adjoint has the same count, with the cotangent weight in place of q):
-    x - x' (2), rho (4), 1/rho (1), z and 1/z (2), seed H0, H1 (103); S: w sigma H_0
-    (8); D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).
-    S: 120, D: 126, S+D: 134."""
-    f = 2 + 4 + 1 + 2 + SEED
+    x - x' (2), rho (4), 1/rho (1), z and 1/z (2), seed H0, H1 on the branch a wave
+    takes when all its lanes have k rho >= 60 (85: the 53 flops of the degree-6 fits
+    become 35 with degree 4); S: w sigma H_0 (8); D: (x - x').n'/rho (4), w mu times
+    it (2), times H_1 (8).  S: 102, D: 108, S+D: 116.  Waves with a lane nearer run
+    the z >= 20 fits, 18 flops more, so the count is a lower bound."""
+    f = 2 + 4 + 1 + 2 + SEED_VFAR
     if kind & 1:
         f += 8
     if kind & 2:
