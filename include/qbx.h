@@ -162,9 +162,9 @@ int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, d
  *   from the target, so the expansion adds an error near
  *   (r h / (gamma sqrt(rad2)))^(p+1); gamma = 6 suits p = 20, p = 10 needs
  *   about 16 for 1e-12.
- * Other arguments and out as qbx_layer_potential; no tape (this variant has
- * no adjoint).  Stream-ordered, no allocation; the workspace is
- * qbx_workspace_bytes(). */
+ * Other arguments and out as qbx_layer_potential; no tape (the density
+ * adjoint, qbx_layer_potential_split_adjoint, recomputes what it needs).
+ * Stream-ordered, no allocation; the workspace is qbx_workspace_bytes(). */
 int qbx_layer_potential_split(const qbx_geometry* g, const double* density, double k, int p,
                               double r, int oversample, int side, int kind, double gamma,
                               double* out, void* ws, size_t ws_bytes, hipStream_t stream);

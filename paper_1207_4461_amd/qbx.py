@@ -132,7 +132,8 @@ def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, 
     """Near/far split forward (qbx_layer_potential_split): QBX for the sources of
     panels within gamma panel radii of the target's panel, the smooth rule applied
     directly for all others.  out[n_sides, n_kinds, 16*P] complex128, exterior
-    first.  Forward only (no adjoint)."""
+    first.  Its density adjoint is layer_potential_split_vjp (qbx_apply with gamma);
+    it has no node gradient."""
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
