@@ -218,6 +218,21 @@ int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p,
                         double tol, int restart, int max_iter, double* sigma, int* iterations,
                         double* residual, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The adjoint system of qbx_solve_dirichlet, (-+ 1/2 + conj(alpha) S^H - D^H)
+ * lambda = rhs (S, D the same two-sided averages), by the same GMRES on
+ * W^(-1/2) A^H W^(1/2); each product is one density adjoint for both sides
+ * (qbx_layer_potential_adjoint, or qbx_layer_potential_split_adjoint when
+ * gamma > 0).  For L = Re <g, sigma> with A sigma = f, lambda = A^-H g is the
+ * gradient with respect to f, and -grad_x Re <lambda, A(x) sigma> the one with
+ * respect to the nodes.  Arguments, workspace, errors and the synchronous
+ * behaviour as qbx_solve_dirichlet; residual is that of the scaled adjoint
+ * system. */
+int qbx_solve_dirichlet_adjoint(const qbx_geometry* g, const double* rhs, double k, int p,
+                                double r, int oversample, int side, double alpha_re,
+                                double alpha_im, double gamma, double tol, int restart,
+                                int max_iter, double* lambda, int* iterations, double* residual,
+                                void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- adjoint ----------------------------------------------------------- */
 
 /* Vector-Jacobian product of qbx_layer_potential for the real scalar

@@ -161,6 +161,34 @@ __global__ __launch_bounds__(256) void k_axpby(int T, double s, const double2* x
               : make_double2(s * x[t].x, s * x[t].y);
 }
 
+// adjoint products: cot[si][kk][t] = u_t / 2 for both sides and kinds, u = sw v
+__global__ __launch_bounds__(256) void k_adj_cot(int T, const double2* __restrict__ v,
+                                                 const double* __restrict__ sw,
+                                                 double2* __restrict__ cot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double h = 0.5 * sw[t];
+  const double2 u = make_double2(h * v[t].x, h * v[t].y);
+  cot[t] = u;
+  cot[T + t] = u;
+  cot[2 * T + t] = u;
+  cot[3 * T + t] = u;
+}
+
+// y = (half u + conj(alpha) S^H u - D^H u) / sw, u = sw v, gd = [S^H u; D^H u] (averaged
+// over the sides by the cotangent's halves)
+__global__ __launch_bounds__(256) void k_adj_combine(int T, const double2* __restrict__ v,
+                                                     const double* __restrict__ sw,
+                                                     const double2* __restrict__ gd, double half,
+                                                     double2 alpha, double2* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double2 a = cmul(make_double2(alpha.x, -alpha.y), gd[t]);
+  const double2 d = gd[T + t];
+  const double inv = 1.0 / sw[t];
+  y[t] = make_double2(fma(half, v[t].x, inv * (a.x - d.x)), fma(half, v[t].y, inv * (a.y - d.y)));
+}
+
 __global__ __launch_bounds__(256) void k_zero(int n, double2* __restrict__ y) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) y[t] = make_double2(0.0, 0.0);
@@ -183,7 +211,7 @@ static SolveLayout make_solve_layout(const Dims& d, int restart) {
   L.fws = take(L.fws_bytes);
   L.tables = take(sizeof(double) * table_layout(d.qs).total);
   L.sw = take(sizeof(double) * T);
-  L.dens = take(sizeof(double2) * 2 * T);
+  L.dens = take(sizeof(double2) * 6 * T);   // density [2][T], then adjoint cotangent [4][T]
   L.out = take(sizeof(double2) * 4 * T);
   L.V = take(sizeof(double2) * (size_t)(restart + 1) * T);
   L.w = take(sizeof(double2) * T);
@@ -206,6 +234,7 @@ struct Gmres {
   int p, oversample;
   double half;     // -1/2 for the exterior problem, +1/2 for the interior one
   double2 alpha;
+  bool adjoint;    // products by A^H instead of A
   int T, grid;
 
   template <typename X>
@@ -215,8 +244,10 @@ struct Gmres {
   int check(hipError_t e, const char* what) const {
     return e == hipSuccess ? QBX_OK : device_fail(e, what);
   }
-  // y = W^{1/2} (-+ 1/2 + alpha S - D) W^{-1/2} v
+  // y = W^{1/2} (-+ 1/2 + alpha S - D) W^{-1/2} v, or for the adjoint system
+  // y = W^{-1/2} (-+ 1/2 + conj(alpha) S^H - D^H) W^{1/2} v
   int matvec(const double2* v, double2* y) const {
+    if (adjoint) return matvec_adjoint(v, y);
     hipLaunchKernelGGL(k_to_density, dim3(grid), dim3(256), 0, s, T, v, at<double>(L.sw),
                        at<double2>(L.dens));
     int rc = check(hipGetLastError(), "solve density kernel");
@@ -233,6 +264,25 @@ struct Gmres {
     hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), 0, s, T, v, at<double>(L.sw),
                        at<double2>(L.out), half, alpha, y);
     return check(hipGetLastError(), "solve combine kernel");
+  }
+  int matvec_adjoint(const double2* v, double2* y) const {
+    double2* cot = at<double2>(L.dens) + 2 * (size_t)T;
+    hipLaunchKernelGGL(k_adj_cot, dim3(grid), dim3(256), 0, s, T, v, at<double>(L.sw), cot);
+    int rc = check(hipGetLastError(), "solve cotangent kernel");
+    if (rc) return rc;
+    double* gd = at<double>(L.out);
+    const double* dens = at<double>(L.dens);   // zeros: the density gradient does not read it
+    const double* c = reinterpret_cast<const double*>(cot);
+    if (gamma > 0.0)
+      rc = qbx_layer_potential_split_adjoint(g, dens, k, p, r, oversample, QBX_BOTH, 3, gamma, c,
+                                             gd, ws + L.fws, L.fws_bytes, s);
+    else
+      rc = qbx_layer_potential_adjoint(g, dens, k, p, r, oversample, QBX_BOTH, 3, c, nullptr, gd,
+                                       nullptr, ws + L.fws, L.fws_bytes, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_adj_combine, dim3(grid), dim3(256), 0, s, T, v, at<double>(L.sw),
+                       at<double2>(L.out), half, alpha, y);
+    return check(hipGetLastError(), "solve adjoint combine kernel");
   }
   // h[0..nv) = V_i^H w on the device, and a host copy
   int dots(const double2* Vb, int nv, const double2* w, cplx* host) const {
@@ -280,16 +330,24 @@ size_t qbx_solve_workspace_bytes(int n_panels, int q, int p, int oversample, int
   return make_solve_layout(d, restart).total;
 }
 
-int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p, double r,
-                        int oversample, int side, double alpha_re, double alpha_im, double gamma,
-                        double tol, int restart, int max_iter, double* sigma, int* iterations,
-                        double* residual, void* ws, size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace qbx {
+
+// GMRES on the scaled system (adjoint = false: A sigma = f, b = W^{1/2} f and
+// sigma = W^{-1/2} x; adjoint = true: A^H lambda = f, b = W^{-1/2} f and
+// lambda = W^{1/2} x)
+static int solve(const qbx_geometry* g, const double* f, double k, int p, double r,
+                 int oversample, int side, double alpha_re, double alpha_im, double gamma,
+                 double tol, int restart, int max_iter, bool adjoint, double* sigma,
+                 int* iterations, double* residual, void* ws, size_t ws_bytes,
+                 hipStream_t stream) {
   if (side != QBX_EXTERIOR && side != QBX_INTERIOR)
     return fail(QBX_EINVAL, "side = %d must be -1 (interior) or 1 (exterior)", side);
   Dims d;   // of the forward, which takes both one-sided limits
   int rc = validate(g, p, k, r, oversample, QBX_BOTH, 3, &d);
   if (rc) return rc;
-  if (!f || !sigma) return fail(QBX_EINVAL, "f or sigma is NULL");
+  if (!f || !sigma) return fail(QBX_EINVAL, "right-hand side or solution is NULL");
   if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(QBX_EINVAL, "tol = %g must be > 0", tol);
   if (restart < 1 || restart > kMaxRestart)
@@ -302,21 +360,24 @@ int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p,
   if (ws_bytes < L.total)
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   Gmres G{g, d, L, static_cast<char*>(ws), stream, k, r, gamma, p, oversample,
-          side == QBX_EXTERIOR ? -0.5 : 0.5, make_double2(alpha_re, alpha_im), d.T,
+          side == QBX_EXTERIOR ? -0.5 : 0.5, make_double2(alpha_re, alpha_im), adjoint, d.T,
           (d.T + 255) / 256};
   const int T = d.T, m = restart;
   double2* b = G.at<double2>(L.b);
   double2* x = G.at<double2>(L.x);
   double2* w = G.at<double2>(L.w);
   double* sw = G.at<double>(L.sw);
-  // weights and the scaled right-hand side b = W^{1/2} f
+  // weights and the scaled right-hand side
   hipError_t e = launch_tables(d, G.at<double>(L.tables), stream);
   if (e != hipSuccess) return device_fail(e, "tables kernel");
   hipLaunchKernelGGL(k_sqrt_weights, dim3(G.grid), dim3(256), 0, stream, T, d.qs, g->nodes,
                      G.at<double>(L.tables), sw);
   hipLaunchKernelGGL(k_scale_weights, dim3(G.grid), dim3(256), 0, stream, T,
-                     reinterpret_cast<const double2*>(f), sw, 0, b);
+                     reinterpret_cast<const double2*>(f), sw, adjoint ? 1 : 0, b);
   hipLaunchKernelGGL(k_zero, dim3(G.grid), dim3(256), 0, stream, T, x);
+  if (adjoint)
+    hipLaunchKernelGGL(k_zero, dim3((2 * T + 255) / 256), dim3(256), 0, stream, 2 * T,
+                       G.at<double2>(L.dens));
   if ((rc = G.check(hipGetLastError(), "solve set-up kernels"))) return rc;
   double bnorm;
   if ((rc = G.norm(b, &bnorm))) return rc;
@@ -403,13 +464,34 @@ int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p,
     if ((rc = G.norm(w, &rn))) return rc;
     res = rn / bnorm;
   }
-  hipLaunchKernelGGL(k_scale_weights, dim3(G.grid), dim3(256), 0, stream, T, x, sw, 1,
-                     reinterpret_cast<double2*>(sigma));
+  hipLaunchKernelGGL(k_scale_weights, dim3(G.grid), dim3(256), 0, stream, T, x, sw,
+                     adjoint ? 0 : 1, reinterpret_cast<double2*>(sigma));
   if ((rc = G.check(hipGetLastError(), "solve output kernel"))) return rc;
   if ((rc = G.check(hipStreamSynchronize(stream), "solve sync"))) return rc;
   if (iterations) *iterations = it;
   if (residual) *residual = res;
   return QBX_OK;
+}
+
+}  // namespace qbx
+
+extern "C" {
+
+int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p, double r,
+                        int oversample, int side, double alpha_re, double alpha_im, double gamma,
+                        double tol, int restart, int max_iter, double* sigma, int* iterations,
+                        double* residual, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return solve(g, f, k, p, r, oversample, side, alpha_re, alpha_im, gamma, tol, restart, max_iter,
+               false, sigma, iterations, residual, ws, ws_bytes, stream);
+}
+
+int qbx_solve_dirichlet_adjoint(const qbx_geometry* g, const double* rhs, double k, int p,
+                                double r, int oversample, int side, double alpha_re,
+                                double alpha_im, double gamma, double tol, int restart,
+                                int max_iter, double* lambda, int* iterations, double* residual,
+                                void* ws, size_t ws_bytes, hipStream_t stream) {
+  return solve(g, rhs, k, p, r, oversample, side, alpha_re, alpha_im, gamma, tol, restart,
+               max_iter, true, lambda, iterations, residual, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -182,30 +182,93 @@ def solve_workspace_bytes(n_panels: int, p: int, oversample: int, side: int, res
     return n
 
 
+def _solve(fn, nodes, rhs, k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter,
+           workspace):
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    _need(rhs, "right-hand side", torch.complex128, (P * Q,))
+    dev = nodes.device
+    x = torch.empty(P * Q, dtype=torch.complex128, device=dev)
+    ws = _workspace(solve_workspace_bytes(P, p, oversample, side, restart), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    it, res = C.c_int(), C.c_double()
+    a = complex(alpha)
+    _lib.check(getattr(lib, fn)(C.byref(geo), rhs.data_ptr(), float(k), int(p), float(r),
+                                int(oversample), int(side), a.real, a.imag, float(gamma),
+                                float(tol), int(restart), int(max_iter), x.data_ptr(),
+                                C.byref(it), C.byref(res), ws.data_ptr(), ws.numel(),
+                                _stream(dev)))
+    return x, it.value, res.value
+
+
 def solve_dirichlet(nodes: torch.Tensor, f: torch.Tensor, k: float, p: int, r: float = 0.5,
                     oversample: int = 4, side: int = EXTERIOR, alpha: complex = 1j,
                     gamma: float = 0.0, tol: float = 1e-14, restart: int = 100,
                     max_iter: int = 1000, workspace: Optional[torch.Tensor] = None):
     """Dirichlet problem by the combined-field representation u = -D sigma + alpha S sigma
-    (qbx_solve_dirichlet): sigma [16P] complex128 with (alpha S - D) sigma = f on the
-    domain's side (EXTERIOR or INTERIOR), by GMRES on the sqrt(w)-scaled system; gamma > 0
+    (qbx_solve_dirichlet): sigma [16P] complex128 with (-+ 1/2 + alpha S - D) sigma = f
+    for the EXTERIOR or INTERIOR problem, by GMRES on the sqrt(w)-scaled system; gamma > 0
     uses the near/far split for the products.  Returns (sigma, iterations, residual)."""
-    lib = _lib.load()
-    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
-    _need(nodes, "nodes", torch.float64, (P, Q, 2))
-    _need(f, "f", torch.complex128, (P * Q,))
-    dev = nodes.device
-    sigma = torch.empty(P * Q, dtype=torch.complex128, device=dev)
-    ws = _workspace(solve_workspace_bytes(P, p, oversample, side, restart), dev, workspace)
-    geo = _lib.Geometry(P, Q, nodes.data_ptr())
-    it, res = C.c_int(), C.c_double()
-    a = complex(alpha)
-    _lib.check(lib.qbx_solve_dirichlet(C.byref(geo), f.data_ptr(), float(k), int(p), float(r),
-                                       int(oversample), int(side), a.real, a.imag, float(gamma),
-                                       float(tol), int(restart), int(max_iter), sigma.data_ptr(),
-                                       C.byref(it), C.byref(res), ws.data_ptr(), ws.numel(),
-                                       _stream(dev)))
-    return sigma, it.value, res.value
+    return _solve("qbx_solve_dirichlet", nodes, f, k, p, r, oversample, side, alpha, gamma, tol,
+                  restart, max_iter, workspace)
+
+
+def solve_dirichlet_adjoint(nodes: torch.Tensor, g: torch.Tensor, k: float, p: int,
+                            r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+                            alpha: complex = 1j, gamma: float = 0.0, tol: float = 1e-14,
+                            restart: int = 100, max_iter: int = 1000,
+                            workspace: Optional[torch.Tensor] = None):
+    """lambda = A^-H g for the operator of solve_dirichlet (qbx_solve_dirichlet_adjoint).
+    Returns (lambda, iterations, residual)."""
+    return _solve("qbx_solve_dirichlet_adjoint", nodes, g, k, p, r, oversample, side, alpha,
+                  gamma, tol, restart, max_iter, workspace)
+
+
+class _DirichletSolve(torch.autograd.Function):
+    """sigma = A(nodes)^-1 f with A of solve_dirichlet; backward: lambda = A^-H grad_sigma
+    is the gradient for f, and -grad_nodes Re <lambda, A(nodes) sigma> (sigma held) the one
+    for the nodes, from the layer potentials' node adjoint with the cotangents
+    conj(alpha) lambda / 2 (S) and -lambda / 2 (D) on both sides."""
+
+    @staticmethod
+    def forward(ctx, nodes, f, k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter):
+        sigma, _, _ = solve_dirichlet(nodes.detach(), f.detach(), k, p, r, oversample, side,
+                                      alpha, gamma, tol, restart, max_iter)
+        ctx.save_for_backward(nodes, sigma)
+        ctx.args = (k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter)
+        return sigma
+
+    @staticmethod
+    def backward(ctx, grad_sigma):
+        nodes, sigma = ctx.saved_tensors
+        k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter = ctx.args
+        lam, _, _ = solve_dirichlet_adjoint(nodes.detach(),
+                                            grad_sigma.contiguous().to(torch.complex128), k, p, r,
+                                            oversample, side, alpha, gamma, tol, restart, max_iter)
+        gn = None
+        if ctx.needs_input_grad[0]:
+            cs = (0.5 * complex(alpha).conjugate()) * lam
+            cd = -0.5 * lam
+            cot = torch.stack([torch.stack([cs, cd]), torch.stack([cs, cd])])
+            _, gnodes = layer_potential_vjp(nodes.detach(), torch.stack([sigma, sigma]), cot, k,
+                                            p, r, oversample, BOTH, S | D, want_density=False)
+            gn = -gnodes
+        gf = lam if ctx.needs_input_grad[1] else None
+        return gn, gf, None, None, None, None, None, None, None, None, None, None
+
+
+def dirichlet_solve_apply(nodes: torch.Tensor, f: torch.Tensor, k: float, p: int,
+                          r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+                          alpha: complex = 1j, gamma: float = 0.0, tol: float = 1e-14,
+                          restart: int = 100, max_iter: int = 1000) -> torch.Tensor:
+    """Differentiable solve_dirichlet: sigma with gradients for f (an adjoint solve) and,
+    with plain QBX products (gamma = 0), for the nodes."""
+    if gamma > 0.0 and nodes.requires_grad:
+        raise ValueError("the near/far split has no node gradient: detach the nodes")
+    return _DirichletSolve.apply(nodes, f, float(k), int(p), float(r), int(oversample), int(side),
+                                 complex(alpha), float(gamma), float(tol), int(restart),
+                                 int(max_iter))
 
 
 def layer_potential_gradient(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,

@@ -119,3 +119,62 @@ def test_split_products_give_the_same_solution(Q):
     ea, ec = rel(b.cpu().numpy(), a.cpu().numpy()), rel(c.cpu().numpy(), a.cpu().numpy())
     say(f"  all-near split vs plain {ea:.2e}; gamma 6 vs plain {ec:.2e}")
     assert ea < 1e-12 and ec < 1e-10
+
+
+@pytest.mark.parametrize("side,P,p,os_", [(I.EXTERIOR, 8, 6, 2), (I.INTERIOR, 12, 8, 2)])
+def test_adjoint_solve_matches_oracle_dense_solve(Q, side, P, p, os_):
+    """lambda = A^-H g against the dense solve with the oracle's matrix conjugate-transposed."""
+    k = 3.0
+    nodes = I.panel_nodes(I.ellipse(1.0, 0.6), P)
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal(P * 16) + 1j * rng.standard_normal(P * 16)
+    A = O.dirichlet_matrix(nodes, k, p, oversample=os_, side=side)
+    ref = np.linalg.solve(A.conj().T, g)
+    lam, it, res = Q.solve_dirichlet_adjoint(dev(nodes), dev(g), k, p, oversample=os_, side=side)
+    e = rel(lam.cpu().numpy(), ref)
+    say(f"  side {side} P={P} p={p}: {it} products, residual {res:.2e}, vs oracle {e:.2e}")
+    assert res < 1e-13 and e <= TOL
+
+
+def test_differentiable_solve_gradients(Q):
+    """Gradient for f by gradcheck (fast mode); for the nodes against a central difference
+    of L = Re <g, sigma(x)> along a smooth deformation, with f held fixed."""
+    curve, P, k, p = I.star((5, 0.25, 0.0)), 10, 3.0, 8
+    X = I.panel_nodes(curve, P)
+    nodes = dev(X)
+    f = dev(charges_field(X.reshape(-1, 2), EXT[0], k))
+    fn = lambda F: Q.dirichlet_solve_apply(nodes, F, k, p, oversample=2)
+    assert torch.autograd.gradcheck(fn, (f.clone().requires_grad_(True),), eps=1e-6, atol=1e-7,
+                                    rtol=1e-6, fast_mode=True)
+    rng = np.random.default_rng(11)
+    g = dev(rng.standard_normal(P * 16) + 1j * rng.standard_normal(P * 16))
+    xn = nodes.clone().requires_grad_(True)
+    L = torch.real(torch.sum(torch.conj(g) * Q.dirichlet_solve_apply(xn, f, k, p, oversample=2)))
+    L.backward()
+    t = I.panel_parameters(P)
+    E = np.stack([np.sin(3 * t), np.cos(2 * t)], -1)
+
+    def Lof(Y):
+        s, _, _ = Q.solve_dirichlet(dev(Y), f, k, p, oversample=2)
+        return float(torch.real(torch.sum(torch.conj(g) * s)))
+
+    h = 1e-6
+    fd = (Lof(X + h * E) - Lof(X - h * E)) / (2 * h)
+    an = float(torch.sum(xn.grad * dev(E)))
+    say(f"  directional derivative: FD {fd:.12e} adjoint {an:.12e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_differentiable_solve_with_split_products(Q):
+    curve, P, k, p = I.star((5, 0.25, 0.0)), 64, 5.0, 20
+    nodes = dev(I.panel_nodes(curve, P))
+    f = dev(charges_field(I.panel_nodes(curve, P).reshape(-1, 2), EXT[0], k))
+    rng = np.random.default_rng(2)
+    g = dev(rng.standard_normal(P * 16) + 1j * rng.standard_normal(P * 16))
+    a, _, _ = Q.solve_dirichlet_adjoint(nodes, g, k, p)
+    b, _, _ = Q.solve_dirichlet_adjoint(nodes, g, k, p, gamma=6.0)
+    e = rel(b.cpu().numpy(), a.cpu().numpy())
+    say(f"  adjoint solve, split products vs plain: {e:.2e}")
+    assert e < 1e-10
+    with pytest.raises(ValueError):
+        Q.dirichlet_solve_apply(nodes.clone().requires_grad_(True), f, k, p, gamma=6.0)
