@@ -145,6 +145,11 @@ def test_solve_entry_point_validates(lib):
                 dict(gamma=-1.0)):
         assert call(**bad) == _lib.QBX_EINVAL, bad
     assert call(nbytes=n - 1) == _lib.QBX_EWORKSPACE
+    # the adjoint system takes the same arguments and checks
+    adj = lambda side=1, nbytes=1 << 40: lib.qbx_solve_dirichlet_adjoint(
+        C.byref(g), BAD, 3.0, 6, 0.5, 4, side, 0.0, 1.0, 0.0, 1e-14, 50, 100, BAD, C.byref(it),
+        C.byref(res), BAD, nbytes, None)
+    assert adj(side=0) == _lib.QBX_EINVAL and adj(nbytes=n - 1) == _lib.QBX_EWORKSPACE
 
 
 def test_ext_entry_point_validates(lib):
