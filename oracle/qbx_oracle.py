@@ -472,6 +472,75 @@ def direct_sum(src, dens, tx, ty, k: float, kind: int, sel) -> Dict[str, torch.T
     return out
 
 
+def direct_gradient(src, dens, tx, ty, k: float, kind: int, sel) -> Dict[str, torch.Tensor]:
+    """Target gradients of ``direct_sum`` (without the i/4), [C, 2] per kind, by the chain
+    rule with u = (x - x')/rho, f = u.n' and H_0' = -H_1, H_1' = H_0 - H_1/z (DLMF 10.6.2):
+    S: grad H_0(k rho) = -k H_1 u;
+    D: grad [k H_1 f] = k [k H_0 f u + (H_1/rho)(n' - 2 f u)]."""
+    dx = tx[:, None] - src["x"][None, :]
+    dy = ty[:, None] - src["y"][None, :]
+    rho = torch.where(sel, torch.sqrt(dx * dx + dy * dy), torch.ones_like(dx))
+    ux, uy = dx / rho, dy / rho
+    z = k * rho
+    H0, H1 = hankel1(0, z), hankel1(1, z)
+    out = {}
+    if kind & S_KIND:
+        q = torch.where(sel, -k * H1 * dens["S"][None, :], 0.0)
+        out["S"] = torch.stack([(q * ux).sum(dim=1), (q * uy).sum(dim=1)], dim=1)
+    if kind & D_KIND:
+        nx, ny = src["nx"][None, :], src["ny"][None, :]
+        f = ux * nx + uy * ny
+        a = torch.where(sel, k * k * H0 * f * dens["D"][None, :], 0.0)
+        b = torch.where(sel, k * (H1 / rho) * dens["D"][None, :], 0.0)
+        gx = a * ux + b * (nx - 2 * f * ux)
+        gy = a * uy + b * (ny - 2 * f * uy)
+        out["D"] = torch.stack([gx.sum(dim=1), gy.sum(dim=1)], dim=1)
+    return out
+
+
+def layer_potential_split_gradient(nodes, density, k: float, p: int, r: float = 0.5,
+                                   oversample: int = 4, side: int = EXTERIOR,
+                                   kind: int = S_KIND, gamma: float = 6.0, targets=None,
+                                   mode: str = "fast"):
+    """Target derivatives with the near/far split (Sections 3.2 and 5): the local
+    expansion of the near sources differentiated as in ``layer_potential_gradient``,
+    plus (i/4) ``direct_gradient`` of the others.  Returns (grad [n_sides, n_kinds, T, 2],
+    dn [n_sides, n_kinds, T]) as ``layer_potential_gradient``."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    kinds = kinds_of(kind)
+    P = nodes.shape[0]
+    src = source_grid(nodes, oversample)
+    qs = Q * oversample
+    fine = interpolate_density(density, oversample)
+    dens = {kk: src["w"].to(_C128) * fine[i] for i, kk in enumerate(kinds)}
+    near = near_panels(nodes, gamma)
+    tidx = np.arange(P * Q) if targets is None else np.asarray(targets, dtype=np.int64)
+    xy = nodes.reshape(-1, 2)
+    src_panel = np.arange(P * qs) // qs
+    sides = sides_of(side)
+    ctrs = [expansion_centers(nodes, src["h"], src["n_tgt"], r, s) for s in sides]
+    g = torch.zeros(len(sides), len(kinds), len(tidx), 2, dtype=_C128)
+    for m in np.unique(tidx // Q):
+        rows = np.nonzero(tidx // Q == m)[0]
+        ti = torch.as_tensor(tidx[rows], dtype=torch.long)
+        near_src = near[m][src_panel]
+        ni = torch.as_tensor(np.nonzero(near_src)[0], dtype=torch.long)
+        sub = {key: src[key][ni] for key in ("x", "y", "nx", "ny")}
+        dsub = {kk: dens[kk][ni] for kk in kinds}
+        far = torch.as_tensor(np.broadcast_to(~near_src, (len(rows), near_src.size)).copy())
+        dg = direct_gradient(src, dens, xy[ti, 0], xy[ti, 1], k, kind, far)
+        for si in range(len(sides)):
+            ctr = {key: val[ti] for key, val in ctrs[si].items()}
+            a = coefficients(sub, dsub, ctr, k, p, kind, mode)
+            for i, kk in enumerate(kinds):
+                g[si, i, torch.as_tensor(rows)] = (
+                    evaluate_gradient(a[kk], ctr["R"], ctr["theta"], k, p, mode) + 0.25j * dg[kk])
+    n_tgt = src["n_tgt"][torch.as_tensor(tidx, dtype=torch.long)]
+    dn = g[..., 0] * n_tgt[:, 0].to(_C128) + g[..., 1] * n_tgt[:, 1].to(_C128)
+    return g, dn
+
+
 def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, oversample: int = 4,
                           side: int = EXTERIOR, kind: int = S_KIND, gamma: float = 6.0,
                           targets=None, mode: str = "fast"):

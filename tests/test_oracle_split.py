@@ -160,3 +160,54 @@ def test_planted_split_mistakes_are_caught(monkeypatch):
             assert rel(split(pb, 6.0), ref) > 1e-4, name
         finally:
             monkeypatch.setattr(O, attr, orig_near if attr == "near_panels" else orig_direct)
+
+
+def _direct_setup():
+    pb = I.small(n_panels=12, p=8, k=5.0, kind=3, side=I.BOTH)
+    src = O.source_grid(torch.as_tensor(pb.nodes), 4)
+    fine = O.interpolate_density(torch.as_tensor(pb.density), 4)
+    dens = {"S": src["w"].to(torch.complex128) * fine[0],
+            "D": src["w"].to(torch.complex128) * fine[1]}
+    tx = torch.tensor([3.0, -2.5, 0.2], dtype=torch.float64)
+    ty = torch.tensor([0.4, 1.7, -2.9], dtype=torch.float64)
+    sel = torch.ones(3, src["x"].shape[0], dtype=torch.bool)
+    return pb, src, dens, tx, ty, sel
+
+
+def test_direct_gradient_is_the_derivative_of_the_direct_sum():
+    """Fourth-order central differences of direct_sum at points off the curve."""
+    pb, src, dens, tx, ty, sel = _direct_setup()
+    gd = O.direct_gradient(src, dens, tx, ty, pb.k, 3, sel)
+    h = 1e-4
+    for kk in ("S", "D"):
+        fd = []
+        for ex, ey in ((1.0, 0.0), (0.0, 1.0)):
+            f = lambda s: O.direct_sum(src, dens, tx + s * ex, ty + s * ey, pb.k, 3, sel)[kk]
+            fd.append(((8 * (f(h) - f(-h)) - (f(2 * h) - f(-2 * h))) / (12 * h)).numpy())
+        assert rel(np.stack(fd, axis=1), gd[kk].numpy()) < 1e-9, kk
+
+
+def test_split_gradient_matches_qbx_gradient():
+    """p = 20: the far sources' truncation is negligible, so the split's target
+    derivatives match the plain QBX ones; the planted sign mistake in the D term of the
+    direct gradient is caught."""
+    pb = I.small(n_panels=28, p=20, k=5.0, kind=3, side=I.BOTH)
+    g0, dn0 = O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                         pb.side, pb.kind)
+    g1, dn1 = O.layer_potential_split_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                               pb.oversample, pb.side, pb.kind, gamma=6.0)
+    assert rel(g1.numpy(), g0.numpy()) < 1e-13 and rel(dn1.numpy(), dn0.numpy()) < 1e-13
+
+
+def test_planted_direct_gradient_mistake_is_caught(monkeypatch):
+    pb, src, dens, tx, ty, sel = _direct_setup()
+    orig = O.hankel1
+
+    def swapped(n, x):             # H_0 and H_1 exchanged inside the gradient
+        return orig(1 - n, x) if n in (0, 1) else orig(n, x)
+
+    good = O.direct_gradient(src, dens, tx, ty, pb.k, 3, sel)["D"]
+    monkeypatch.setattr(O, "hankel1", swapped)
+    bad = O.direct_gradient(src, dens, tx, ty, pb.k, 3, sel)["D"]
+    monkeypatch.setattr(O, "hankel1", orig)
+    assert rel(bad.numpy(), good.numpy()) > 1e-2
