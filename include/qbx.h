@@ -169,6 +169,17 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
                               double r, int oversample, int side, int kind, double gamma,
                               double* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Target derivatives with the near/far split: the outputs, arguments and
+ * errors of qbx_layer_potential_gradient, plus gamma as in
+ * qbx_layer_potential_split.  Near sources enter through the derivative of the
+ * local expansion (Section 3.2); the others through the gradient of the
+ * direct rule at the target, k H_1 and H_0 by the chain rule (shared by both
+ * sides).  Stream-ordered, no allocation; qbx_workspace_bytes(). */
+int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* density, double k,
+                                       int p, double r, int oversample, int side, int kind,
+                                       double gamma, double* grad, double* dn, void* ws,
+                                       size_t ws_bytes, hipStream_t stream);
+
 /* Vector-Jacobian product of qbx_layer_potential_split with respect to the
  * density (PyTorch convention, the conjugate-transposed operator A^H applied
  * to the cotangent): the same near relation and rules as the forward, so

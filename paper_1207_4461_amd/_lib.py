@@ -86,6 +86,8 @@ def load() -> C.CDLL:
         "qbx_solve_dirichlet_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, dbl, dbl, dbl,
                                               dbl, i32, i32, vp, C.POINTER(i32),
                                               C.POINTER(dbl), vp, sz, vp]),
+        "qbx_layer_potential_split_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl,
+                                                     vp, vp, vp, sz, vp]),
         "qbx_layer_potential_split_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl,
                                                     vp, vp, vp, sz, vp]),
         "qbx_layer_potential_split": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl, vp, vp,

@@ -168,7 +168,7 @@ Layout make_layout(const Dims& d) {
   L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
   L.bnd = take(sizeof(double4) * (size_t)d.P);
-  L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T);
+  L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T * 2);
   L.gfar = take(sizeof(double2) * (size_t)d.nk * d.T);
   L.aacc = take(sizeof(double2) * (size_t)d.nk * d.N);
   L.apart = take(sizeof(double2) * (size_t)d.n_asplit * d.nk * d.N);
@@ -372,6 +372,32 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   if (e != hipSuccess) return device_fail(e, "split far kernel");
   e = launch_split_finalize(d, at<double2>(ws, L.partial), at<double2>(ws, L.fpart), out, stream);
   if (e != hipSuccess) return device_fail(e, "split finalize kernel");
+  return QBX_OK;
+}
+
+int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* density, double k,
+                                       int p, double r, int oversample, int side, int kind,
+                                       double gamma, double* grad, double* dn, void* ws,
+                                       size_t ws_bytes, hipStream_t stream) {
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, side, kind, &d);
+  if (rc) return rc;
+  if (!(gamma > 0.0)) return fail(QBX_EINVAL, "near-panel factor gamma = %g must be > 0", gamma);
+  if (!density) return fail(QBX_EINVAL, "density is NULL");
+  if (!grad && !dn) return fail(QBX_EINVAL, "grad and dn are both NULL");
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const Layout L = make_layout(d);
+  if (ws_bytes < L.total)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  rc = prepare(d, L, g->nodes, density, ws, stream);
+  if (rc) return rc;
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  e = launch_split_gradient(d, g->nodes, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                            at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                            at<double4>(ws, L.bnd), gamma * gamma, at<double2>(ws, L.partial),
+                            at<double2>(ws, L.fpart), grad, dn, stream);
+  if (e != hipSuccess) return device_fail(e, "split gradient kernels");
   return QBX_OK;
 }
 

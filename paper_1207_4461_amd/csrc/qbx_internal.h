@@ -77,7 +77,7 @@ struct Layout {
   size_t sg;       // double[N][8] per-source gradients
   size_t scratch;  // double[16 + Mc] small reductions
   size_t bnd;      // double4[P] split forward: panel mean and squared radius
-  size_t fpart;    // double2[n_fsplit][nk][T] split forward: far sums
+  size_t fpart;    // double2[n_fsplit][nk][T][2] split: far sums (forward: first half)
   size_t gfar;     // double2[nk][T] split adjoint: cotangent weights of both sides
   size_t aacc;     // double2[nk][N] split adjoint: near sums per source
   size_t apart;    // double2[n_asplit][nk][N] split adjoint: far sums per source
@@ -140,6 +140,12 @@ hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* de
                             hipStream_t s);
 hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const double2* farp,
                                  double* out, hipStream_t s);
+// the split's target derivatives: near sums [nk][Mc][2], far sums
+// [n_fsplit][nk][T][2], then grad and n . grad (either may be NULL)
+hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
+                                 const double2* dens, const CenterRec* ctr, const double* jtab,
+                                 const double4* bnd, double g2, double2* nearp, double2* farp,
+                                 double* grad, double* dn, hipStream_t s);
 // the split's adjoint with respect to the density (G from launch_make_G)
 hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
                                         const double4* geo, const double* wgt,

@@ -675,6 +675,45 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
 // target derivatives: one wave, one center, chunks [c0, c1); A[kind][0..1] =
 // sums of w*density times K_R and K_theta, reduced over the wave
 // ---------------------------------------------------------------------------
+// target derivatives, one pair: adds q K_R and q K_theta of source j for the
+// center (cx, cy) with target direction (ct, st) to A[kind][0..1]
+template <int P, int KIND>
+__device__ __forceinline__ void grad_source(const double4* __restrict__ geo,
+                                            const double2* __restrict__ dens, int N, int j,
+                                            double cx, double cy, double ct, double st, double k,
+                                            double inv_k, const double* __restrict__ Jtab, int nj,
+                                            Cplx (&A)[2][2]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int z0 = opaque_zero();
+  const double* __restrict__ J = Jtab + z0;
+  const double* __restrict__ cf = g_seed_table + z0;
+  const double4 g = geo[j];
+  const double vx = g.x - cx, vy = g.y - cy;
+  const double rho2 = fma(vx, vx, vy * vy);
+  const double ir = rsqrt_refined(rho2);
+  const double rho = rho2 * ir;
+  const double cd = (ct * vx + st * vy) * ir;
+  const double sd = (st * vx - ct * vy) * ir;
+  double cps = 0.0, sps = 0.0;
+  if (kD) {
+    cps = ct * g.z + st * g.w;
+    sps = st * g.z - ct * g.w;
+  }
+  const GradOut o = grad_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+  if (kS) {
+    const double2 w = dens[j];
+    cmul_acc(A[0][0], w.x, w.y, o.KRs);
+    cmul_acc(A[0][1], w.x, w.y, o.Kts);
+  }
+  if (kD) {
+    const double2 w = dens[(kS ? (size_t)N : 0) + j];
+    cmul_acc(A[NK - 1][0], w.x, w.y, o.KRd);
+    cmul_acc(A[NK - 1][1], w.x, w.y, o.Ktd);
+  }
+}
+
 template <int P, int KIND>
 __device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
                                             const double2* __restrict__ dens, int N,
@@ -691,34 +730,7 @@ __device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
   for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
   for (int c = c0; c < c1; ++c) {
     const int j = c * kWave + lane;
-    if (j < N) {
-      const int z0 = opaque_zero();
-      const double* __restrict__ J = Jtab + z0;
-      const double* __restrict__ cf = g_seed_table + z0;
-      const double4 g = geo[j];
-      const double vx = g.x - cx, vy = g.y - cy;
-      const double rho2 = fma(vx, vx, vy * vy);
-      const double ir = rsqrt_refined(rho2);
-      const double rho = rho2 * ir;
-      const double cd = (ct * vx + st * vy) * ir;
-      const double sd = (st * vx - ct * vy) * ir;
-      double cps = 0.0, sps = 0.0;
-      if (kD) {
-        cps = ct * g.z + st * g.w;
-        sps = st * g.z - ct * g.w;
-      }
-      const GradOut o = grad_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
-      if (kS) {
-        const double2 w = dens[j];
-        cmul_acc(A[0][0], w.x, w.y, o.KRs);
-        cmul_acc(A[0][1], w.x, w.y, o.Kts);
-      }
-      if (kD) {
-        const double2 w = dens[(kS ? (size_t)N : 0) + j];
-        cmul_acc(A[NK - 1][0], w.x, w.y, o.KRd);
-        cmul_acc(A[NK - 1][1], w.x, w.y, o.Ktd);
-      }
-    }
+    if (j < N) grad_source<P, KIND>(geo, dens, N, j, cx, cy, ct, st, k, inv_k, Jtab, nj, A);
   }
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {

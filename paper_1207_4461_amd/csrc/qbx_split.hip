@@ -430,6 +430,232 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Target derivatives with the split (Section 3.2 for the near sources' local
+// expansion, the chain rule for the direct ones).  Near: per center the sums
+// F_R = sum q dK/dR and F_theta = sum q dK/dtheta over the near sources
+// (grad_source); far: per target
+//   S: grad H_0(k rho) = -k H_1 u,   D: grad [k H_1 f] = k [k H_0 f u + (H_1/rho)(n' - 2 f u)],
+// u = (x - x')/rho, f = u . n'; the finalize combines them as grad u = (i/4)
+// (F_R w^ + (F_theta/R) theta^ + far) and n . grad u with n = -s w^.
+// ---------------------------------------------------------------------------
+
+// partial[kk][ci][0..1] = F_R, F_theta over the near sources of center ci
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_split_near_grad(
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
+    const double4* __restrict__ bnd, int NP, double g2, double k, double2* __restrict__ partial) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ci = blockIdx.x * 4 + wave;
+  if (ci >= Mc) return;
+  const int m = (ci % T) / kQ;
+  const double4 bm = bnd[m];
+  const CenterRec* C = ctr + ci;
+  const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
+  const double inv_k = 1.0 / k;
+  const double* Jtab = jtab + (size_t)ci * NJ;
+  Cplx A[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mp = w0 + lane;
+    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
+    unsigned long long mask = __ballot(nr);
+    while (mask) {
+      const int pan = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      for (int s0 = 0; s0 < qs; s0 += kWave) {
+        if (s0 + lane < qs)
+          grad_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
+                               NJ / 2, A);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    wave_sum(A[kk][0]);
+    wave_sum(A[kk][1]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      double2* q = partial + ((size_t)kk * Mc + ci) * 2;
+      q[0] = make_double2(A[kk][0].r, A[kk][0].i);
+      q[1] = make_double2(A[kk][1].r, A[kk][1].i);
+    }
+  }
+}
+
+// partial[sp][kk][t][0..1]: the direct gradient (x, y) of target t over the far
+// sources of panels [sp * ppw, (sp + 1) * ppw), without the factors -k (S), k (D)
+template <int KIND>
+__global__ __launch_bounds__(256) void k_split_far_grad(
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
+    double k, int n_tb, int n_fsplit, int ppw, double2* __restrict__ partial) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + wave;
+  const int sp = gw / n_tb;
+  const int tb = gw - sp * n_tb;
+  if (sp >= n_fsplit) return;
+  const int t = tb * kWave + lane;
+  const bool valid = t < T;
+  const int tt = valid ? t : T - 1;
+  const double tx = nodes[2 * (size_t)tt], ty = nodes[2 * (size_t)tt + 1];
+  const double4 bt = bnd[tt / kQ];
+  const int p0 = sp * ppw;
+  const int p1 = min(NP, p0 + ppw);
+  const double inv_k = 1.0 / k;
+  double sxr = 0.0, sxi = 0.0, syr = 0.0, syi = 0.0;
+  double dxr = 0.0, dxi = 0.0, dyr = 0.0, dyi = 0.0;
+  for (int pm = p0; pm < p1; ++pm) {
+    const bool far = valid && !panels_near(bt, bnd[pm], g2);
+    if (far) {
+      const int j0 = pm * qs;
+      for (int b = 0; b < qs; ++b) {
+        const int z0 = opaque_zero();
+        const double* __restrict__ cf = g_seed_table + z0;
+        const int j = j0 + b;
+        const double4 g = geo[j];
+        const double dx = tx - g.x, dy = ty - g.y;
+        const double rho2 = fma(dx, dx, dy * dy);
+        const double ir = rsqrt_refined(rho2);
+        const double z = k * (rho2 * ir), iz = ir * inv_k;
+        const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
+        const double ux = dx * ir, uy = dy * ir;
+        if (kS) {
+          const double2 w = dens[j];
+          const double hr = fma(w.x, h.h1r, -w.y * h.h1i), hi = fma(w.x, h.h1i, w.y * h.h1r);
+          sxr = fma(hr, ux, sxr);
+          sxi = fma(hi, ux, sxi);
+          syr = fma(hr, uy, syr);
+          syi = fma(hi, uy, syi);
+        }
+        if (kD) {
+          const double2 w = dens[(kS ? (size_t)N : 0) + j];
+          const double f = fma(ux, g.z, uy * g.w);
+          // k H_0 f u + (H_1 / rho)(n' - 2 f u), times w mu
+          const double a_r = k * f * h.h0r, a_i = k * f * h.h0i;
+          const double b_r = h.h1r * ir, b_i = h.h1i * ir;
+          const double vx = fma(-2.0 * f, ux, g.z), vy = fma(-2.0 * f, uy, g.w);
+          const double cxr = fma(a_r, ux, b_r * vx), cxi = fma(a_i, ux, b_i * vx);
+          const double cyr = fma(a_r, uy, b_r * vy), cyi = fma(a_i, uy, b_i * vy);
+          dxr = fma(w.x, cxr, fma(-w.y, cxi, dxr));
+          dxi = fma(w.x, cxi, fma(w.y, cxr, dxi));
+          dyr = fma(w.x, cyr, fma(-w.y, cyi, dyr));
+          dyi = fma(w.x, cyi, fma(w.y, cyr, dyi));
+        }
+      }
+    }
+  }
+  if (valid) {
+    int kk = 0;
+    if (kS) {
+      double2* q = partial + (((size_t)sp * NK + kk++) * T + t) * 2;
+      q[0] = make_double2(-k * sxr, -k * sxi);
+      q[1] = make_double2(-k * syr, -k * syi);
+    }
+    if (kD) {
+      double2* q = partial + (((size_t)sp * NK + kk) * T + t) * 2;
+      q[0] = make_double2(k * dxr, k * dxi);
+      q[1] = make_double2(k * dyr, k * dyi);
+    }
+  }
+}
+
+// grad[si][kk][t][0..1] and dn[si][kk][t] from the near sums of center ci and the
+// far sums of its target
+__global__ __launch_bounds__(256) void k_split_finalize_gradient(
+    int Mc, int T, int nk, int n_fsplit, int side, const CenterRec* __restrict__ ctr,
+    const double2* __restrict__ nearp, const double2* __restrict__ farp, double* __restrict__ grad,
+    double* __restrict__ dn) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Mc * nk) return;
+  const int kk = e / Mc, ci = e - kk * Mc;
+  const int si = ci / T, t = ci - si * T;
+  const double2 F = nearp[((size_t)kk * Mc + ci) * 2], Ft = nearp[((size_t)kk * Mc + ci) * 2 + 1];
+  const CenterRec c = ctr[ci];
+  const double ir = 1.0 / c.R;
+  // F_R w^ + (F_theta / R) theta^, theta^ = (-sin, cos)
+  double gxr = fma(F.x, c.ct, -Ft.x * ir * c.st), gxi = fma(F.y, c.ct, -Ft.y * ir * c.st);
+  double gyr = fma(F.x, c.st, Ft.x * ir * c.ct), gyi = fma(F.y, c.st, Ft.y * ir * c.ct);
+  for (int sp = 0; sp < n_fsplit; ++sp) {
+    const double2* q = farp + (((size_t)sp * nk + kk) * T + t) * 2;
+    gxr += q[0].x;
+    gxi += q[0].y;
+    gyr += q[1].x;
+    gyi += q[1].y;
+  }
+  const double s = side != 0 ? (double)side : (si == 0 ? 1.0 : -1.0);
+  const size_t o = ((size_t)si * nk + kk) * T + t;
+  if (grad) {   // (i/4) z = (-Im z / 4, Re z / 4)
+    double* q = grad + 4 * o;
+    q[0] = -0.25 * gxi;
+    q[1] = 0.25 * gxr;
+    q[2] = -0.25 * gyi;
+    q[3] = 0.25 * gyr;
+  }
+  if (dn) {     // n = -s w^
+    const double nr = -s * fma(c.ct, gxr, c.st * gyr), ni = -s * fma(c.ct, gxi, c.st * gyi);
+    dn[2 * o] = -0.25 * ni;
+    dn[2 * o + 1] = 0.25 * nr;
+  }
+}
+
+template <int P>
+static hipError_t launch_split_near_grad_p(const Dims& d, const double4* geo, const double2* dens,
+                                           const CenterRec* ctr, const double* jtab,
+                                           const double4* bnd, double g2, double2* partial,
+                                           hipStream_t s) {
+  const dim3 grid((unsigned)((d.Mc + 3) / 4)), block(256);
+#define QBX_NGRAD_ARGS geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, d.k, partial
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_near_grad<P, 1>), grid, block, 0, s, QBX_NGRAD_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_near_grad<P, 2>), grid, block, 0, s, QBX_NGRAD_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_near_grad<P, 3>), grid, block, 0, s, QBX_NGRAD_ARGS); break;
+  }
+#undef QBX_NGRAD_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
+                                 const double2* dens, const CenterRec* ctr, const double* jtab,
+                                 const double4* bnd, double g2, double2* nearp, double2* farp,
+                                 double* grad, double* dn, hipStream_t s) {
+  hipError_t e;
+  {
+    auto launch = [&]() -> hipError_t {
+      QBX_P_SWITCH(d.p, launch_split_near_grad_p, d, geo, dens, ctr, jtab, bnd, g2, nearp, s)
+    };
+    e = launch();
+    if (e != hipSuccess) return e;
+  }
+  const int n_tb = (d.T + kWave - 1) / kWave;
+  const long waves = (long)n_tb * d.n_fsplit;
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_FGRAD_ARGS \
+  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, farp
+  switch (d.kind) {
+    case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_far_grad<2>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_far_grad<3>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+  }
+#undef QBX_FGRAD_ARGS
+  const int n = d.Mc * d.nk;
+  hipLaunchKernelGGL(k_split_finalize_gradient, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T,
+                     d.nk, d.n_fsplit, d.side, ctr, nearp, farp, grad, dn);
+  return hipGetLastError();
+}
+
 hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s) {
   hipLaunchKernelGGL(k_panel_bounds, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, nodes, bnd);
   return hipGetLastError();

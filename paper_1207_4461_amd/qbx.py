@@ -151,6 +151,31 @@ def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, 
     return out
 
 
+def layer_potential_split_gradient(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
+                                   r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+                                   kind: int = S, gamma: float = 6.0, want_grad: bool = True,
+                                   want_dn: bool = True,
+                                   workspace: Optional[torch.Tensor] = None):
+    """Target derivatives with the near/far split (qbx_layer_potential_split_gradient):
+    (grad, dn) as layer_potential_gradient."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    shape = (n_sides(side), nk, P * Q)
+    grad = torch.empty(shape + (2,), dtype=torch.complex128, device=dev) if want_grad else None
+    dn = torch.empty(shape, dtype=torch.complex128, device=dev) if want_dn else None
+    ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    _lib.check(lib.qbx_layer_potential_split_gradient(
+        C.byref(geo), density.data_ptr(), float(k), int(p), float(r), int(oversample), int(side),
+        int(kind), float(gamma), grad.data_ptr() if grad is not None else None,
+        dn.data_ptr() if dn is not None else None, ws.data_ptr(), ws.numel(), _stream(dev)))
+    return grad, dn
+
+
 def layer_potential_split_vjp(nodes: torch.Tensor, density: torch.Tensor,
                               cotangent: torch.Tensor, k: float, p: int, r: float = 0.5,
                               oversample: int = 4, side: int = EXTERIOR, kind: int = S,
