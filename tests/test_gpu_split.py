@@ -232,12 +232,12 @@ def test_split_gradient_small(Q, case):
     assert np.array_equal(dn2.cpu().numpy(), dn)
 
 
-# Target derivatives at star4096 (p = 20, k R = 0.08): the GPU's D derivatives differ
-# from the oracle's by about 5e-10 of the largest derivative (values agree at 1e-12).
-# The oracle is consistent there (fast and dense modes agree to 2e-14), and summing the
-# D pair series in either order in float64 differs by under 1e-14, so the gap lies in
-# the GPU's D derivative terms; its cause is not found yet.  This test holds the
-# measured level, 2e-9, and does not meet the 1e-11 bar of the other cases.
+# Target derivatives at star4096 (p = 20, R = 8e-4): D' is sensitive to the rounding of
+# the geometry.  Moving every source coordinate by one ulp (about 1e-16, against
+# center-source distances down to R) changes the oracle's D' sums by 8.7e-11 of their
+# size (S: 2e-12); the GPU and the oracle interpolate the source grid, normals and
+# centers with different rounding (degree-15 sums, a few ulps apart), and their D
+# derivatives differ by about 4e-10.  The bar, 2e-9, is that sensitivity times ~20 ulps.
 TOL_DERIV_4096 = 2e-9
 
 
