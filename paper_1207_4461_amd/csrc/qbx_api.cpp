@@ -210,31 +210,42 @@ static bool g_timer_on = false;
 static std::vector<TimerRec> g_timer;
 static hipEvent_t g_pending[QBX_TIMER_CLASSES];
 
+// an event recorded on s, or nullptr when either call fails (the launch is then
+// simply not timed)
+static hipEvent_t timer_event(hipStream_t s) {
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return nullptr;
+  }
+  return e;
+}
+
 void timer_begin(int cls, hipStream_t s) {
   if (!g_timer_on) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
-  g_pending[cls] = e;
+  g_pending[cls] = timer_event(s);
 }
 
 void timer_end(int cls, hipStream_t s) {
   if (!g_timer_on || !g_pending[cls]) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
-  g_timer.push_back({cls, g_pending[cls], e});
+  hipEvent_t e = timer_event(s);
+  if (e) {
+    g_timer.push_back({cls, g_pending[cls], e});
+  } else {
+    (void)hipEventDestroy(g_pending[cls]);
+  }
   g_pending[cls] = nullptr;
 }
 
 static void timer_clear() {
   for (auto& r : g_timer) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   g_timer.clear();
   for (auto& e : g_pending) {
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
     e = nullptr;
   }
 }

@@ -106,7 +106,7 @@ static bool build_plan(const qbx_batch_item* items, int n, int oversample, Batch
     size_t c = 0;
     while (c < P->cls.size() && !(P->cls[c].kind == d.kind && P->cls[c].p == d.p)) ++c;
     if (c == P->cls.size()) {
-      P->cls.push_back(BatchClass{d.kind, d.p, 0, 0, 0, 0, 0});
+      P->cls.push_back(BatchClass{d.kind, d.p, 0, 0, 0, 0, 0, 0});
       cls_cost.push_back(0.0);
       members.emplace_back();
     }
