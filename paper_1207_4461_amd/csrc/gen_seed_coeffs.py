@@ -10,7 +10,7 @@ Two regimes (z = k*rho > 0):
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
   A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
   (used when every lane of a wavefront is that far), and a third, shorter still,
-  in s = (ZV/z)^2 serves z >= ZV in the direct (far-panel) passes of the split.
+  in s = (ZV/z)^2 serves z >= ZV (again when every lane of the wavefront is).
 * the phase e^{i(z - pi/4)} = T_n e^{ir}: n = rint(z N / 2 pi), r = z - 2 pi n / N by a
   three-part Cody-Waite reduction, T_n = e^{i(2 pi n/N - pi/4)} from a table of N
   entries (40-digit values rounded once), and sin r, cos r as polynomials in r^2

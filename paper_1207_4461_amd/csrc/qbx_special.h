@@ -20,7 +20,8 @@ namespace qbx {
 //  * z >= Z0 = 6: H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} (P_nu + i Q_nu)
 //    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
 //    when every active lane of the wavefront has z >= ZF = 20 (a wave-uniform
-//    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead;
+//    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead,
+//    and when every lane has z >= ZV = 60 the shortest, in s = (ZV/z)^2;
 //    e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta), delta = 2 pi / 256,
 //    r = z - n delta by a three-part Cody-Waite reduction (|r| <= delta / 2),
 //    T_n = e^{i(n delta - pi/4)} from a 256-entry table gathered per lane, and
@@ -128,8 +129,9 @@ __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, dou
 }
 
 // H_0(z), H_1(z) for z >= seed::kZV with the shortest fits (degree 4 in
-// (kZV/z)^2), no branches: the direct passes of the near/far split take it when
-// every lane of the wave is that far
+// (kZV/z)^2), no branches: the same values as hankel01's own z >= kZV tier,
+// which the direct passes of the near/far split call straight when every lane
+// of the wave is that far, without hankel01's per-lane range branches
 __device__ __forceinline__ H01 hankel01_vfar(double z, double iz, const double* __restrict__ cf) {
   const double t = seed::kZV * iz;
   const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
@@ -145,7 +147,14 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
   H01 h;
   if (z >= seed::kZ0) {
     double P0, Q0, P1, Q1;
-    if (__all(z >= seed::kZF)) {
+    if (__all(z >= seed::kZV)) {
+      const double t = seed::kZV * iz;
+      const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
+      P0 = pq.a;
+      Q0 = t * pq.b;
+      P1 = pq.c;
+      Q1 = t * pq.d;
+    } else if (__all(z >= seed::kZF)) {
       const double t = seed::kZF * iz;
       const D4 pq = horner4<seed::kFARLen>(cf + seed::kFAROff, t * t);
       P0 = pq.a;

@@ -4,18 +4,19 @@ Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, reciprocal squar
 root, divide and rint = 1 each, however the kernel computes them (the kernels refine
 a hardware reciprocal square root by a third-order step; that step is not counted).
 The counts follow the kernels' formulas for the common branch (every lane of the
-wavefront at z = k*rho >= 20: the asymptotic seed with the short far fits), line by
+wavefront at z = k*rho >= 60: the asymptotic seed with the shortest fits), line by
 line:
 
 forward pair (one center, one source, order p):
   geometry      v = x'-c (2), rho = sqrt(vx^2+vy^2) (4), 1/rho (1), cos/sin of
                 theta_i - theta' (8), z and 1/z (2)                        = 17
   D geometry    cos/sin(theta_i - arg nu) (6)
-  seed H0, H1   20/z and (20/z)^2 (2), 4 interleaved degree-6 polynomials (53),
+  seed H0, H1   60/z and (60/z)^2 (2), 4 interleaved degree-4 polynomials (35),
                 Q scaling (2), phase: reduction by 2 pi/256 (8), degree-3 sin/cos
                 polynomials in r^2 (16), times the table entry (6), 1/sqrt(z) and
-                the amplitude (4), rotation by P + iQ (12)                   = 103
-                (the long fits of 6 <= z < 20 cost 157)
+                the amplitude (4), rotation by P + iQ (12)                   =  85
+                (waves with a lane at 20 <= z < 60 run degree-6 fits, 103; the long
+                fits of 6 <= z < 20 cost 157: so the counts are lower bounds)
   recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
   S per order   J_l cos(l D) (1) + accumulate (4) + Chebyshev cos (2)        =  7
   D per order   J_{l+1} cos(lD+psi) - J_{l-1} cos(lD-psi) (3) + accumulate (4)
@@ -23,11 +24,11 @@ forward pair (one center, one source, order p):
   accumulation  w sigma K (8 per kind)
 
 Totals (derived in flops_forward_pair below):
-  S:   129 + 12 p        D:   148 + 16 p        S+D: 162 + 23 p
+  S:   111 + 12 p        D:   130 + 16 p        S+D: 144 + 23 p
 """
 from __future__ import annotations
 
-SEED = 103   # H_0, H_1 on the common branch (see above)
+SEED = 85   # H_0, H_1 on the common branch (see above)
 
 
 def flops_forward_pair(p: int, kind: int) -> int:
@@ -175,9 +176,6 @@ def flops_grad_pair(p: int, kind: int) -> int:
     return f
 
 
-SEED_VFAR = 85   # H_0, H_1 from the degree-4 fits of k rho >= 60 (the direct passes only)
-
-
 def flops_far_pair(kind: int) -> int:
     """Far pass of the split forward, per (target, source) pair on a far panel (its
     density adjoint has the same count, with the cotangent weight in place of q):
@@ -186,7 +184,7 @@ def flops_far_pair(kind: int) -> int:
     become 35 with degree 4); S: w sigma H_0 (8); D: (x - x').n'/rho (4), w mu times
     it (2), times H_1 (8).  S: 102, D: 108, S+D: 116.  Waves with a lane nearer run
     the z >= 20 fits, 18 flops more, so the count is a lower bound."""
-    f = 2 + 4 + 1 + 2 + SEED_VFAR
+    f = 2 + 4 + 1 + 2 + SEED
     if kind & 1:
         f += 8
     if kind & 2:
