@@ -116,9 +116,8 @@ def tune_fields(mode: str, backward: str) -> int:
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the hot path runs on a single "
-              "MI355X; how it would shard is described in DESIGN.md); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py: only one GPU is measured (the library runs the hot path on a single "
+              "MI355X and has no multi-GPU sharding); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import ctypes as C
 
@@ -142,10 +141,7 @@ def main():
         return bench_batched(args)
     if args.mode == "solve":
         return bench_solve(args)
-    have_bwd = hasattr(qbx, "layer_potential_vjp")
-    mode = args.mode or ("fwdbwd" if have_bwd else "fwd")
-    if mode == "fwdbwd" and not have_bwd:
-        raise SystemExit("adjoint not available in this build")
+    mode = args.mode or "fwdbwd"
     pb = getattr(I, args.workload)()
     dev = torch.device("cuda:0")
     nodes = torch.from_numpy(pb.nodes).to(dev)
