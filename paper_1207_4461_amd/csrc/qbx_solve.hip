@@ -444,11 +444,13 @@ static int solve(const qbx_geometry* g, const double* f, double k, int p, double
         }
         if ((rc = G.axpby(1.0 / hn, w, 0, nullptr, G.V(j + 1)))) return rc;
       }
-      // x += V y, H y = g (upper triangular)
+      // x += V y, H y = g (upper triangular).  A zero pivot (the operator
+      // singular on the Krylov space: w = 0 with nothing left to rotate) takes
+      // y_i = 0, so the update stays finite and the true residual below shows it
       for (int i = jj - 1; i >= 0; --i) {
         cplx acc = gv[i];
         for (int l = i + 1; l < jj; ++l) acc -= Hs(i, l) * y[l];
-        y[i] = acc / Hs(i, i);
+        y[i] = Hs(i, i) == cplx(0.0) ? cplx(0.0) : acc / Hs(i, i);
       }
       std::vector<double2> ny(jj);
       for (int i = 0; i < jj; ++i) ny[i] = make_double2(-y[i].real(), -y[i].imag());
