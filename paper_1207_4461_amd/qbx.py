@@ -250,6 +250,14 @@ def solve_dirichlet_adjoint(nodes: torch.Tensor, g: torch.Tensor, k: float, p: i
                   gamma, tol, restart, max_iter, workspace)
 
 
+def _require_converged(what: str, iterations: int, residual: float, tol: float) -> None:
+    """Raise when a solve inside the differentiable wrapper stopped (max_iter) with a true
+    relative residual above 100 tol: its value and gradients would not be those of A^-1."""
+    if not residual <= 100.0 * tol:
+        raise RuntimeError(f"{what}: GMRES stopped after {iterations} products at relative "
+                           f"residual {residual:.3g} (tol {tol:.3g}); raise max_iter or restart")
+
+
 class _DirichletSolve(torch.autograd.Function):
     """sigma = A(nodes)^-1 f with A of solve_dirichlet; backward: lambda = A^-H grad_sigma
     is the gradient for f, and -grad_nodes Re <lambda, A(nodes) sigma> (sigma held) the one
@@ -258,8 +266,9 @@ class _DirichletSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, nodes, f, k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter):
-        sigma, _, _ = solve_dirichlet(nodes.detach(), f.detach(), k, p, r, oversample, side,
-                                      alpha, gamma, tol, restart, max_iter)
+        sigma, it, res = solve_dirichlet(nodes.detach(), f.detach(), k, p, r, oversample, side,
+                                         alpha, gamma, tol, restart, max_iter)
+        _require_converged("dirichlet_solve_apply", it, res, tol)
         ctx.save_for_backward(nodes, sigma)
         ctx.args = (k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter)
         return sigma
@@ -268,9 +277,11 @@ class _DirichletSolve(torch.autograd.Function):
     def backward(ctx, grad_sigma):
         nodes, sigma = ctx.saved_tensors
         k, p, r, oversample, side, alpha, gamma, tol, restart, max_iter = ctx.args
-        lam, _, _ = solve_dirichlet_adjoint(nodes.detach(),
-                                            grad_sigma.contiguous().to(torch.complex128), k, p, r,
-                                            oversample, side, alpha, gamma, tol, restart, max_iter)
+        lam, it, res = solve_dirichlet_adjoint(nodes.detach(),
+                                               grad_sigma.contiguous().to(torch.complex128), k,
+                                               p, r, oversample, side, alpha, gamma, tol, restart,
+                                               max_iter)
+        _require_converged("dirichlet_solve_apply backward", it, res, tol)
         gn = None
         if ctx.needs_input_grad[0]:
             cs = (0.5 * complex(alpha).conjugate()) * lam
@@ -288,7 +299,8 @@ def dirichlet_solve_apply(nodes: torch.Tensor, f: torch.Tensor, k: float, p: int
                           alpha: complex = 1j, gamma: float = 0.0, tol: float = 1e-14,
                           restart: int = 100, max_iter: int = 1000) -> torch.Tensor:
     """Differentiable solve_dirichlet: sigma with gradients for f (an adjoint solve) and,
-    with plain QBX products (gamma = 0), for the nodes."""
+    with plain QBX products (gamma = 0), for the nodes.  Raises RuntimeError when either
+    solve ends (max_iter) with a true relative residual above 100 tol."""
     if gamma > 0.0 and nodes.requires_grad:
         raise ValueError("the near/far split has no node gradient: detach the nodes")
     return _DirichletSolve.apply(nodes, f, float(k), int(p), float(r), int(oversample), int(side),

@@ -329,3 +329,12 @@ def test_explicit_sizes_and_validation(lib):
     assert lib.qbx_apply_explicit_adjoint(10, BAD, BAD, BAD, 5, BAD, BAD, BAD, 1.0, 4, 1, None,
                                           None, BAD, BAD, BAD, BAD, BAD, BAD, BAD, 1 << 40,
                                           None) == _lib.QBX_EINVAL
+
+
+def test_differentiable_solve_requires_convergence():
+    """The differentiable Dirichlet solve refuses a GMRES run that max_iter cut short."""
+    from paper_1207_4461_amd import qbx
+    qbx._require_converged("solve", 40, 5e-13, 1e-14)          # within 100 tol
+    for bad in (2e-12, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError, match="GMRES stopped"):
+            qbx._require_converged("solve", 1000, bad, 1e-14)
