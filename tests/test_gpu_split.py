@@ -51,6 +51,7 @@ CASES = [
     dict(name="SD-both-p12-g6", n_panels=13, p=12, kind=3, side=0, gamma=6.0),
     dict(name="SD-both-p20-os1-g6", n_panels=11, p=20, kind=3, side=0, oversample=1, gamma=6.0),
     dict(name="SD-both-p9-os3-g5", n_panels=9, p=9, kind=3, side=0, oversample=3, k=7.0, gamma=5.0),
+    dict(name="SD-both-p3-P3-g1", n_panels=3, p=3, kind=3, side=0, gamma=1.0),
     dict(name="S-ext-p24-os2-g0.5", n_panels=8, p=24, kind=1, side=1, oversample=2, k=2.0,
          gamma=0.5),
     dict(name="SD-both-p5-allnear", n_panels=6, p=5, kind=3, side=0, gamma=1e150),
@@ -139,6 +140,7 @@ ADJ_CASES = [
     dict(name="SD-both-p12-g6", n_panels=13, p=12, kind=3, side=0, gamma=6.0),
     dict(name="SD-both-p20-os1-g6", n_panels=11, p=20, kind=3, side=0, oversample=1, gamma=6.0),
     dict(name="SD-both-p9-os3-g5", n_panels=9, p=9, kind=3, side=0, oversample=3, k=7.0, gamma=5.0),
+    dict(name="SD-both-p3-P3-g1", n_panels=3, p=3, kind=3, side=0, gamma=1.0),
 ]
 
 
@@ -208,6 +210,7 @@ GRAD_CASES = [
     dict(name="SD-both-p12-g6", n_panels=13, p=12, kind=3, side=0, gamma=6.0),
     dict(name="SD-both-p20-os1-g6", n_panels=11, p=20, kind=3, side=0, oversample=1, gamma=6.0),
     dict(name="SD-both-p9-os3-g5", n_panels=9, p=9, kind=3, side=0, oversample=3, k=7.0, gamma=5.0),
+    dict(name="SD-both-p3-P3-g1", n_panels=3, p=3, kind=3, side=0, gamma=1.0),
 ]
 
 
