@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void k_forward_grad(const double4* __restrict_
   Cplx A[2][2];
   const int c0 = sp * chunks_per_split;
   const int c1 = min(c0 + chunks_per_split, chunks);
-  grad_center<P, KIND>(geo, dens, N, ctr + ci, jtab + (size_t)ci * NJ, NJ, k, c0, c1, lane, A);
+  // the order-weighted block follows the Mc tables (launch_order_weighted)
+  grad_center<P, KIND>(geo, dens, N, ctr + ci, jtab + (size_t)ci * NJ, NJ,
+                       jtab + (size_t)Mc * NJ + (size_t)ci * (NJ / 2), k, c0, c1, lane, A);
   if (lane == 0) {
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk)

@@ -156,7 +156,7 @@ Layout make_layout(const Dims& d) {
   L.wgt = take(sizeof(double) * (size_t)d.N);
   L.h = take(sizeof(double) * (size_t)d.P);
   L.ctr = take(sizeof(CenterRec) * (size_t)d.Mc);
-  L.jtab = take(sizeof(double) * (size_t)d.Mc * d.NJ);
+  L.jtab = take(sizeof(double) * (size_t)d.Mc * (d.NJ + d.NJ / 2));
   // forward partials [n_split][nk][Mc], tape partials [n_tsplit][nk][Mc][5]
   const size_t n_part = std::max((size_t)d.n_split, (size_t)d.n_tsplit * 5);
   L.partial = take(sizeof(double2) * n_part * d.nk * d.Mc);
@@ -404,6 +404,8 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
   if (rc) return rc;
   hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
+  if (e != hipSuccess) return device_fail(e, "order-weighted table kernel");
   e = launch_split_gradient(d, g->nodes, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                             at<double4>(ws, L.bnd), gamma * gamma, at<double2>(ws, L.partial),
@@ -458,8 +460,10 @@ int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, d
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
+  hipError_t e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
+  if (e != hipSuccess) return device_fail(e, "order-weighted table kernel");
   timer_begin(5, stream);
-  hipError_t e = launch_forward_grad(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+  e = launch_forward_grad(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                                     at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                                     at<double2>(ws, L.partial), stream);
   timer_end(5, stream);

@@ -77,6 +77,22 @@ hipError_t launch_tables(const Dims& d, double* tables, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_order_weighted(int Mc, int NJ, double* __restrict__ jtab) {
+  const int nj = NJ / 2;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)Mc * nj) return;
+  const size_t ci = e / nj;
+  const int l = (int)(e - ci * nj);
+  jtab[(size_t)Mc * NJ + e] = (double)l * jtab[ci * NJ + l];
+}
+
+hipError_t launch_order_weighted(const Dims& d, double* jtab, hipStream_t s) {
+  const size_t n = (size_t)d.Mc * (d.NJ / 2);
+  hipLaunchKernelGGL(k_order_weighted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.Mc,
+                     d.NJ, jtab);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(128) void k_upsample(Dims d, const double* __restrict__ nodes,
                                                   const double* __restrict__ density,
                                                   const double* __restrict__ tab,

@@ -67,7 +67,7 @@ struct Layout {
   size_t wgt;      // double[N] source quadrature weights w
   size_t h;        // double[P] panel lengths
   size_t ctr;      // CenterRec[Mc]
-  size_t jtab;     // double[Mc][NJ]
+  size_t jtab;     // double[Mc][NJ], then double[Mc][NJ / 2] l J_l (target derivatives)
   size_t partial;  // forward: double2[n_split][nk][Mc]; forward-with-tape: double2[n_tsplit][nk][Mc][5]
   size_t tape;     // double2[Mc][nk][4] tape recomputed by the adjoint when none is given
   size_t G;        // double2[nk][Mc] conj(cotangent) i/4
@@ -161,6 +161,9 @@ hipError_t launch_finalize_tape(const Dims& d, const double2* partial, double* o
                                 hipStream_t s);
 // target derivatives: the pair pass (partial [n_tsplit][nk][Mc][2]), then the
 // gradient and normal derivative from its sums
+// jtab[Mc NJ + ci nj + l] = l J_l(k R_ci), nj = NJ / 2: the order-weighted Bessel values
+// the target-derivative sums take, scaled once per center instead of once per pair
+hipError_t launch_order_weighted(const Dims& d, double* jtab, hipStream_t s);
 hipError_t launch_forward_grad(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,
                                hipStream_t s);

@@ -222,6 +222,7 @@ template <int P, int KIND>
 __device__ __forceinline__ GradOut grad_sums(double z, double iz, double cd, double sd, double cps,
                                              double sps, double k, const double* __restrict__ J,
                                              const double* __restrict__ Jd,
+                                             const double* __restrict__ lJ,
                                              const double* __restrict__ cf) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -242,15 +243,16 @@ QBX_UNROLL_BY(QBX_SUMS_UNROLL)
   for (int l = 1; l <= LMAX; ++l) {
     if (kS && l <= P) {
       cmac(sKR, Jd[l] * c_c, hc_r, hc_i);
-      cmac(sKt, (double)l * J[l] * s_c, hc_r, hc_i);
+      cmac(sKt, lJ[l] * s_c, hc_r, hc_i);                     // lJ[l] = l J_l
     }
     if (kD) {
       const bool up = l <= P - 1;
       const double fbR = Jd[l - 1] * b_c;
       cmac(dKR, up ? fma(Jd[l + 1], a_c, -fbR) : -fbR, hc_r, hc_i);
-      const double sA = up ? J[l + 1] * sa_c : 0.0;
-      const double sB = J[l - 1] * sb_c;
-      cmac(dKt, fma((double)(l - 1), sB, -(double)(l + 1) * sA), hc_r, hc_i);
+      // (l - 1) J_{l-1} sin(l D - psi) - (l + 1) J_{l+1} sin(l D + psi), the
+      // second term only up to l = p - 1
+      const double mB = lJ[l - 1] * sb_c;
+      cmac(dKt, up ? fma(-lJ[l + 1], sa_c, mB) : mB, hc_r, hc_i);
     }
     if (l < LMAX) {
       const double hn_r = fma(tl, hc_r, -hm_r);
@@ -682,7 +684,7 @@ __device__ __forceinline__ void grad_source(const double4* __restrict__ geo,
                                             const double2* __restrict__ dens, int N, int j,
                                             double cx, double cy, double ct, double st, double k,
                                             double inv_k, const double* __restrict__ Jtab, int nj,
-                                            Cplx (&A)[2][2]) {
+                                            const double* __restrict__ Ltab, Cplx (&A)[2][2]) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
@@ -701,7 +703,9 @@ __device__ __forceinline__ void grad_source(const double4* __restrict__ geo,
     cps = ct * g.z + st * g.w;
     sps = st * g.z - ct * g.w;
   }
-  const GradOut o = grad_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+  const double* __restrict__ lJ = Ltab + z0;
+  const GradOut o = grad_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, lJ,
+                                       cf);
   if (kS) {
     const double2 w = dens[j];
     cmul_acc(A[0][0], w.x, w.y, o.KRs);
@@ -718,7 +722,8 @@ template <int P, int KIND>
 __device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
                                             const double2* __restrict__ dens, int N,
                                             const CenterRec* __restrict__ Crec,
-                                            const double* __restrict__ Jtab, int NJ, double k,
+                                            const double* __restrict__ Jtab, int NJ,
+                                            const double* __restrict__ Ltab, double k,
                                             int c0, int c1, int lane, Cplx (&A)[2][2]) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -730,7 +735,8 @@ __device__ __forceinline__ void grad_center(const double4* __restrict__ geo,
   for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
   for (int c = c0; c < c1; ++c) {
     const int j = c * kWave + lane;
-    if (j < N) grad_source<P, KIND>(geo, dens, N, j, cx, cy, ct, st, k, inv_k, Jtab, nj, A);
+    if (j < N)
+      grad_source<P, KIND>(geo, dens, N, j, cx, cy, ct, st, k, inv_k, Jtab, nj, Ltab, A);
   }
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {

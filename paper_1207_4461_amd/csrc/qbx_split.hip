@@ -459,6 +459,7 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
   const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
   const double inv_k = 1.0 / k;
   const double* Jtab = jtab + (size_t)ci * NJ;
+  const double* Ltab = jtab + (size_t)Mc * NJ + (size_t)ci * (NJ / 2);   // l J_l
   Cplx A[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
@@ -472,7 +473,7 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
       for (int s0 = 0; s0 < qs; s0 += kWave) {
         if (s0 + lane < qs)
           grad_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
-                               NJ / 2, A);
+                               NJ / 2, Ltab, A);
       }
     }
   }

@@ -154,7 +154,9 @@ def flops_fused_pair(p: int, kind: int) -> int:
 
 
 def flops_grad_pair(p: int, kind: int) -> int:
-    """Target-derivative pair kernel: the sums of q K_R and q K_theta per kind."""
+    """Target-derivative pair kernel: the sums of q K_R and q K_theta per kind.  The
+    order-weighted values lJ_l = l J_l come from a per-center table, so K_theta costs one
+    multiply per term and kind less than with l applied in the pair."""
     S = bool(kind & 1)
     D = bool(kind & 2)
     lmax = p + 1 if D else p
@@ -163,10 +165,10 @@ def flops_grad_pair(p: int, kind: int) -> int:
     f += SEED + 2 + (12 if D else 0)            # seed, 2/z and 2 cos D, cos/sin(D +- psi)
     for l in range(1, lmax + 1):
         if S and l <= p:
-            f += 5 + 6                          # K_R (Jd c, MAC); K_theta (l J s, MAC)
+            f += 5 + 5                          # K_R (Jd c, MAC); K_theta (lJ s, MAC)
         if D:
             up = l <= p - 1
-            f += (7 if up else 5) + (9 if up else 6)   # K_R; K_theta
+            f += (7 if up else 5) + (7 if up else 5)   # K_R; K_theta from lJ_{l-+1}
         if l < lmax:
             f += 5 + (4 if S else 0) + (8 if D else 0)   # H_{l+1} and 2l/z; Chebyshev
     if S:
