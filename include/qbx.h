@@ -106,6 +106,24 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
                         double r, int oversample, int side, int kind, double* out,
                         double* tape, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the plain forward of
+ * qbx_layer_potential (no tape), same arguments and results, with no
+ * workspace.  Its scratch arrays live in a file-scope device array of
+ * QBX_STATIC_SCRATCH_BYTES that every GPU the library runs on holds from the
+ * module's load until the process ends; the call allocates and frees nothing.
+ * The stream must belong to the current device.  All calls on one GPU share
+ * that array, so calls that overlap on one GPU (other streams, other threads)
+ * race: serialise them.  Errors as qbx_layer_potential, plus QBX_EWORKSPACE
+ * when the problem needs more scratch than the array holds (about 64 MiB: for
+ * example 1024 panels, oversample 4, one side, S, p = 16, fits; 4096 panels,
+ * both sides, S+D does not) and QBX_EDEVICE when the array's address cannot be
+ * looked up. */
+#define QBX_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int qbx_layer_potential_noalloc(const qbx_geometry* g, const double* density, double k, int p,
+                                double r, int oversample, int side, int kind, double* out,
+                                hipStream_t stream);
+
 /* Options of qbx_layer_potential_ext; zero-initialised, they are the defaults
  * of qbx_layer_potential. */
 typedef struct {

@@ -28,6 +28,7 @@ QBX_EXTERIOR = 1
 QBX_Q = 16
 QBX_PMAX = 24
 QBX_OVERSAMPLE_MAX = 8
+QBX_STATIC_SCRATCH_BYTES = 64 << 20   # the no-workspace forward's device array
 
 class QBXError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -76,6 +77,7 @@ def load() -> C.CDLL:
         "qbx_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
         "qbx_tape_bytes": (sz, [i32, i32, i32, i32, i32]),
         "qbx_layer_potential": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]),
+        "qbx_layer_potential_noalloc": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp]),
         "qbx_layer_potential_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,
                                                sz, vp]),
         "qbx_solve_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),

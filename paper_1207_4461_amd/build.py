@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libqbx.so")
 SOURCES = ["qbx_batched_fwd1.hip", "qbx_batched_fwd0.hip", "qbx_batched_adj.hip",
            "qbx_batched_fused.hip",
            "qbx_adjoint.hip", "qbx_forward.hip", "qbx_explicit.hip", "qbx_batched.hip",
-           "qbx_geometry.hip", "qbx_split.hip", "qbx_solve.hip",
+           "qbx_geometry.hip", "qbx_split.hip", "qbx_solve.hip", "qbx_noalloc.hip",
            "qbx_api.cpp", "qbx_autotune.cpp"]   # slowest first
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 

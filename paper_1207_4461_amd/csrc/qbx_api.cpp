@@ -176,6 +176,29 @@ Layout make_layout(const Dims& d) {
   return L;
 }
 
+// The arrays the plain forward alone uses (tables, source grid, centers, J
+// tables without the order-weighted block, forward partial sums), packed; the
+// other offsets are left at 0 and must not be used.
+Layout make_forward_layout(const Dims& d) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.tables = take(sizeof(double) * table_layout(d.qs).total);
+  L.geo = take(sizeof(double4) * (size_t)d.N);
+  L.dens = take(sizeof(double2) * (size_t)d.nk * d.N);
+  L.wgt = take(sizeof(double) * (size_t)d.N);
+  L.h = take(sizeof(double) * (size_t)d.P);
+  L.ctr = take(sizeof(CenterRec) * (size_t)d.Mc);
+  L.jtab = take(sizeof(double) * (size_t)d.Mc * d.NJ);
+  L.partial = take(sizeof(double2) * (size_t)d.n_split * d.nk * d.Mc);
+  L.total = o;
+  return L;
+}
+
 template <typename T>
 static T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
@@ -262,6 +285,21 @@ static int prepare(const Dims& d, const Layout& L, const double* nodes, const do
   return QBX_OK;
 }
 
+int run_forward(const Dims& d, const Layout& L, const double* nodes, const double* density,
+                double* out, void* ws, hipStream_t stream, bool timed) {
+  int rc = prepare(d, L, nodes, density, ws, stream);
+  if (rc) return rc;
+  if (timed) timer_begin(0, stream);
+  hipError_t e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                at<double2>(ws, L.partial), stream);
+  if (timed) timer_end(0, stream);
+  if (e != hipSuccess) return device_fail(e, "forward kernel");
+  e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
+  if (e != hipSuccess) return device_fail(e, "finalize kernel");
+  return QBX_OK;
+}
+
 }  // namespace qbx
 
 using namespace qbx;
@@ -293,10 +331,11 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
   const Layout L = make_layout(d);
   if (ws_bytes < L.total)
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  if (!tape) return run_forward(d, L, g->nodes, density, out, ws, stream);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
   hipError_t e;
-  if (tape) {
+  {
     timer_begin(3, stream);
     e = launch_forward_tape(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
@@ -308,14 +347,6 @@ int qbx_layer_potential(const qbx_geometry* g, const double* density, double k, 
     if (e != hipSuccess) return device_fail(e, "finalize (tape) kernel");
     return QBX_OK;
   }
-  timer_begin(0, stream);
-  e = launch_forward(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens), at<CenterRec>(ws, L.ctr),
-                     at<double>(ws, L.jtab), at<double2>(ws, L.partial), stream);
-  timer_end(0, stream);
-  if (e != hipSuccess) return device_fail(e, "forward kernel");
-  e = launch_finalize(d, at<double2>(ws, L.partial), out, stream);
-  if (e != hipSuccess) return device_fail(e, "finalize kernel");
-  return QBX_OK;
 }
 
 int qbx_layer_potential_ext(const qbx_geometry* g, const double* density, double k, int p,

@@ -116,6 +116,13 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int device_fail(hipError_t e, const char* where);
 size_t align256(size_t x);
 Layout make_layout(const Dims& d);
+// the plain forward's arrays only (tables ... partial), packed from offset 0
+Layout make_forward_layout(const Dims& d);
+// tables, source grid and centers, then the plain forward and its finalize
+// into out, with the arrays of L (make_layout or make_forward_layout) in ws;
+// timed: bracket the pair kernel with the kernel timer's events when it is on
+int run_forward(const Dims& d, const Layout& L, const double* nodes, const double* density,
+                double* out, void* ws, hipStream_t stream, bool timed = true);
 
 // ---- launchers (qbx_geometry.hip / qbx_forward.hip) ----
 hipError_t launch_tables(const Dims& d, double* tables, hipStream_t s);

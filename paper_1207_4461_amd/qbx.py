@@ -106,6 +106,35 @@ def layer_potential(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int
     return out
 
 
+def layer_potential_noalloc(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
+                            r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+                            kind: int = S, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The plain forward of layer_potential through qbx_layer_potential_noalloc: no
+    workspace; the library's static device scratch (shared by every call on the
+    device: calls that overlap on one GPU race).  Pass `out` to allocate nothing
+    here either."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    shape = (n_sides(side), nk, P * Q)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex128, device=dev)
+    else:
+        _need(out, "out", torch.complex128, shape)
+        if out.device != dev:
+            raise ValueError("out must be on the nodes' device")
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    with torch.cuda.device(dev):
+        rc = lib.qbx_layer_potential_noalloc(C.byref(geo), density.data_ptr(), float(k), int(p),
+                                             float(r), int(oversample), int(side), int(kind),
+                                             out.data_ptr(), _stream(dev))
+    _lib.check(rc)
+    return out
+
+
 def _layer_potential_ext(nodes, density, k, p, r, oversample, side, kind, workspace, dipole,
                          center_rule):
     lib = _lib.load()

@@ -338,3 +338,21 @@ def test_differentiable_solve_requires_convergence():
     for bad in (2e-12, float("nan"), float("inf")):
         with pytest.raises(RuntimeError, match="GMRES stopped"):
             qbx._require_converged("solve", 1000, bad, 1e-14)
+
+
+def test_noalloc_entry_point_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    call = lambda gp=C.byref(g), **kw: lib.qbx_layer_potential_noalloc(
+        gp, kw.get("dens", BAD), kw.get("k", 3.0), kw.get("p", 6), 0.5, kw.get("os_", 4),
+        kw.get("side", 1), kw.get("kind", 1), kw.get("out", BAD), None)
+    for bad in (dict(dens=None), dict(out=None), dict(p=25), dict(k=0.0), dict(os_=0),
+                dict(side=2), dict(kind=4)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(gp=None) == _lib.QBX_EINVAL
+    # star4096 (4096 panels, both sides, S+D, p = 20) needs more than the static
+    # scratch holds: refused on the host, before any device call
+    big = _lib.Geometry(4096, 16, BAD)
+    assert lib.qbx_layer_potential_noalloc(C.byref(big), BAD, 100.0, 20, 0.5, 4, 0, 3, BAD,
+                                           None) == _lib.QBX_EWORKSPACE
+    assert b"static scratch" in lib.qbx_last_error()
+    assert _lib.QBX_STATIC_SCRATCH_BYTES == 64 << 20
