@@ -32,7 +32,9 @@ gradients of the discrete map:
   their average (eq. dlp-twosided).
 * Section 3.2: target derivatives by analytic differentiation of the local
   expansion (``evaluate_gradient``, ``layer_potential_gradient``), through the
-  ladder relations of the regular waves J_l e^{i l theta} in x and y.
+  ladder relations of the regular waves J_l e^{i l theta} in x and y; their
+  on-surface values (principal value of grad S, finite part of grad D) from
+  the one-sided limits by the jump relations (``gradient_principal_value``).
 * Section 4.3: the Dirichlet problem by the combined-field representation,
   with S and D as two-sided averages (Section 3.5), solved densely
   (``dirichlet_solve``) and evaluated off the curve (``representation``).
@@ -421,6 +423,72 @@ def layer_potential_gradient(nodes, density, k: float, p: int, r: float = 0.5,
     g = torch.stack(grads)
     dn = g[..., 0] * n_tgt[:, 0].to(_C128) + g[..., 1] * n_tgt[:, 1].to(_C128)
     return g, dn
+
+
+def target_frame(nodes):
+    """Per target: the outward unit normal n (the centers' normal: the 16-node
+    derivative rotated, Section 3.2), the unit tangent t with n = (t_2, -t_1) as
+    Section 3.2 assumes, i.e. t = (-n_2, n_1), the counter-clockwise direction, and
+    the speed |dX/dtau|.  Returns (n [T, 2], t [T, 2], speed [T])."""
+    nodes = _as_t(nodes, _F64)
+    Dn = interpolation_matrices(1)["Dn"]
+    dX = torch.einsum("aq,pqd->pad", Dn, nodes).reshape(-1, 2)
+    speed = torch.sqrt(dX[:, 0] ** 2 + dX[:, 1] ** 2)
+    n = torch.stack([dX[:, 1], -dX[:, 0]], dim=-1) / speed[:, None]
+    t = torch.stack([-n[:, 1], n[:, 0]], dim=-1)
+    return n, t, speed
+
+
+def arclength_derivative(nodes, density):
+    """d sigma / ds at the targets: the derivative in the panel parameter of the
+    degree-15 interpolant through the 16 node values (the same 16-node derivative
+    as the geometry), over the speed |dX/dtau|.  density [..., T] -> [..., T]."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    Dn = interpolation_matrices(1)["Dn"].to(_C128)
+    lead = density.shape[:-1]
+    d = torch.einsum("aq,...pq->...pa", Dn, density.reshape(*lead, -1, Q)).reshape(*lead, -1)
+    return d / target_frame(nodes)[2].to(_C128)
+
+
+def gradient_principal_value(nodes, density, grad, dn, side: int, kind: int):
+    """On-surface derivatives from QBX's one-sided limits, by the jump relations of
+    Section 3.2 (x on the curve, + the exterior, - the interior):
+
+      grad S(x)  = grad S(x^+-) +- (1/2) n sigma(x)     (principal value),
+      d_i D(x)   = d_i D(x^+-)  -+ (1/2) t_i dsigma/ds (finite part, eq. dlpderiv),
+
+    so S' = n . grad S jumps by sigma/2 from each side and D' = n . grad D has no
+    jump.  side = BOTH: the average of the two one-sided limits (the two-sided form
+    that eq. dlp-twosided uses for D); otherwise the one given limit minus its jump.
+    grad [n_sides, n_kinds, T, 2], dn [n_sides, n_kinds, T] (either may be None),
+    density [n_kinds, T] (S density first).  Returns (grad [n_kinds, T, 2],
+    dn [n_kinds, T])."""
+    kinds = kinds_of(kind)
+    g = None if grad is None else _as_t(grad, _C128)
+    d = None if dn is None else _as_t(dn, _C128)
+    if side == BOTH:
+        return (None if g is None else 0.5 * (g[0] + g[1]),
+                None if d is None else 0.5 * (d[0] + d[1]))
+    s = 1.0 if side == EXTERIOR else -1.0
+    n, t, _ = target_frame(nodes)
+    density = _as_t(density, _C128)
+    g_out, d_out = [], []
+    for ki, kk in enumerate(kinds):
+        if kk == "S":
+            sig = density[ki]
+            if g is not None:
+                g_out.append(g[0, ki] + s * 0.5 * n.to(_C128) * sig[:, None])
+            if d is not None:
+                d_out.append(d[0, ki] + s * 0.5 * sig)
+        else:
+            dmu = arclength_derivative(nodes, density[ki])
+            if g is not None:
+                g_out.append(g[0, ki] - s * 0.5 * t.to(_C128) * dmu[:, None])
+            if d is not None:
+                d_out.append(d[0, ki])
+    return (None if g is None else torch.stack(g_out),
+            None if d is None else torch.stack(d_out))
 
 
 # ---------------------------------------------------------------------------

@@ -139,3 +139,109 @@ def test_planted_gradient_mistakes_are_caught(monkeypatch):
         Sm = 0.5j * np.pi * 3.0 * sps.jvp(3, 3.0) * sps.hankel1(3, 3.0) * dens
         assert rel(dn[1, 0], Sm) > 1e-3, bad.__name__
         monkeypatch.setattr(O, "evaluate_gradient", orig)
+
+
+# ---------------------------------------------------------------------------
+# on-surface derivatives from the one-sided limits (Section 3.2 jump relations)
+# ---------------------------------------------------------------------------
+def _circle_pv_closed_forms(t, dens, k, m):
+    """Unit circle, density e^{imt}: grad S principal value and grad D finite part.
+    S'_pv = (S'^+ + S'^-)/2 = (i pi k/4)(J_m' H_m + J_m H_m'), the tangential
+    derivative of S is i m S with S = (i pi/2) J_m H_m; D' = (i pi k^2/2) J_m' H_m' has
+    no jump and the finite-part tangential derivative is i m D_pv with
+    D_pv = (D^+ + D^-)/2 = (i pi k/4)(J_m' H_m + J_m H_m')."""
+    j, jp = sps.jv(m, k), sps.jvp(m, k)
+    h, hp = sps.hankel1(m, k), sps.h1vp(m, k)
+    S = 0.5j * np.pi * j * h * dens
+    Sn = 0.25j * np.pi * k * (jp * h + j * hp) * dens
+    Dpv = 0.25j * np.pi * k * (jp * h + j * hp) * dens
+    Dn = 0.5j * np.pi * k * k * jp * hp * dens
+    n = np.stack([np.cos(t), np.sin(t)], -1)
+    tt = np.stack([-np.sin(t), np.cos(t)], -1)
+    gS = Sn[:, None] * n + (1j * m * S)[:, None] * tt
+    gD = Dn[:, None] * n + (1j * m * Dpv)[:, None] * tt
+    return gS, gD, Sn, Dn
+
+
+def _pv_on_circle(side, P=16, k=3.0, p=10, m=3):
+    nodes = I.panel_nodes(I.ellipse(1.0, 1.0), P)
+    t = I.panel_parameters(P).reshape(-1)
+    dens = np.exp(1j * m * t)
+    d2 = np.stack([dens, dens])
+    g, dn = O.layer_potential_gradient(nodes, d2, k, p, side=side, kind=3)
+    gp, dp = O.gradient_principal_value(nodes, d2, g, dn, side, 3)
+    return t, dens, gp.numpy(), dp.numpy()
+
+
+def test_gradient_principal_value_circle_closed_forms():
+    """From either one-sided limit alone (the jump subtracted) or from their average,
+    the unit circle's closed forms: interior limits are exact at this resolution, the
+    exterior ones carry the QBX error."""
+    k, m = 3.0, 3
+    for side, tol in ((I.INTERIOR, 1e-10), (I.EXTERIOR, 1e-5), (I.BOTH, 1e-5)):
+        t, dens, gp, dp = _pv_on_circle(side, k=k, m=m)
+        gS, gD, Sn, Dn = _circle_pv_closed_forms(t, dens, k, m)
+        e = (rel(gp[0], gS), rel(gp[1], gD), rel(dp[0], Sn), rel(dp[1], Dn))
+        assert max(e) < tol, (side, e)
+
+
+def test_gradient_principal_value_sides_agree_on_starfish():
+    """The exterior and the interior fix-ups give the same on-surface values: each
+    subtracts its own side's jump, so they differ by the QBX error of the one-sided
+    derivatives only.  D' has no jump and is not changed by the fix-up, so the gap
+    between its two raw limits measures that error; every fixed-up quantity's gap
+    stays within a small factor of it and falls with it under refinement, while the
+    raw one-sided limits of the others differ by O(1)."""
+    curve = I.star((5, 0.25, 0.0))
+    gaps = []
+    for P in (40, 64):
+        nodes = I.panel_nodes(curve, P)
+        t = I.panel_parameters(P).reshape(-1)
+        rng = np.random.default_rng(7)
+        dens = np.stack([I.smooth_density(rng, t), I.smooth_density(rng, t)])
+        g, dn = O.layer_potential_gradient(nodes, dens, 4.0, 10, side=I.BOTH, kind=3)
+        ge, de = O.gradient_principal_value(nodes, dens, g[:1], dn[:1], I.EXTERIOR, 3)
+        gi, di = O.gradient_principal_value(nodes, dens, g[1:], dn[1:], I.INTERIOR, 3)
+        ga, da = O.gradient_principal_value(nodes, dens, g, dn, I.BOTH, 3)
+        qbx_err = rel(dn[0, 1].numpy(), dn[1, 1].numpy())          # D': no jump
+        gap = max(rel(ge[0].numpy(), gi[0].numpy()), rel(ge[1].numpy(), gi[1].numpy()),
+                  rel(de[0].numpy(), di[0].numpy()))
+        assert gap < 5 * qbx_err, (P, gap, qbx_err)
+        assert rel(ga.numpy(), ge.numpy()) < 5 * qbx_err
+        assert rel(g[0, 0].numpy(), g[1, 0].numpy()) > 0.05      # raw S limits: O(1) apart
+        assert rel(dn[0, 0].numpy(), dn[1, 0].numpy()) > 0.05
+        gaps.append(gap)
+    assert gaps[1] < 2e-4 and gaps[0] > 5 * gaps[1], gaps
+
+
+def test_planted_principal_value_mistakes_are_caught(monkeypatch):
+    """A reversed tangent, d sigma/dtau in place of d sigma/ds and the other side's
+    jump each break the circle's closed forms."""
+    k, m = 3.0, 3
+    orig_frame, orig_ds = O.target_frame, O.arclength_derivative
+
+    def reversed_tangent(nodes):
+        n, tt, sp = orig_frame(nodes)
+        return n, -tt, sp
+
+    def tau_derivative(nodes, density):
+        return orig_ds(nodes, density) * orig_frame(nodes)[2].to(torch.complex128)
+
+    for name, patch in (("target_frame", reversed_tangent),
+                        ("arclength_derivative", tau_derivative)):
+        monkeypatch.setattr(O, name, patch)
+        t, dens, gp, dp = _pv_on_circle(I.INTERIOR, k=k, m=m)
+        gS, gD, Sn, Dn = _circle_pv_closed_forms(t, dens, k, m)
+        assert rel(gp[1], gD) > 1e-2, name
+        monkeypatch.setattr(O, name, {"target_frame": orig_frame,
+                                      "arclength_derivative": orig_ds}[name])
+    # the interior limits with the exterior's jumps
+    P = 16
+    nodes = I.panel_nodes(I.ellipse(1.0, 1.0), P)
+    t = I.panel_parameters(P).reshape(-1)
+    dens = np.exp(1j * m * t)
+    d2 = np.stack([dens, dens])
+    g, dn = O.layer_potential_gradient(nodes, d2, k, 10, side=I.INTERIOR, kind=3)
+    gp, dp = O.gradient_principal_value(nodes, d2, g, dn, I.EXTERIOR, 3)
+    gS, gD, Sn, Dn = _circle_pv_closed_forms(t, dens, k, m)
+    assert rel(dp.numpy()[0], Sn) > 1e-1 and rel(gp.numpy()[1], gD) > 1e-1
