@@ -363,6 +363,20 @@ int qbx_apply_explicit(int n_src, const double* src_xy, const double* src_nu, co
                        double k, int p, int kind, double* out, double* tape, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* Target derivatives of the same local expansions (Section 3.2: the expansion
+ * about each center differentiated analytically in the target): the gradient
+ * of out with respect to the target x_i = c_i + R_i e^{i theta_i}, the center
+ * held fixed.  grad [n_kinds][n_ctr][2] complex (d/dx, d/dy).  The same pair
+ * pass as qbx_layer_potential_gradient, on the caller's sources and centers:
+ * with the source grid and centers of a contour it gives that entry point's
+ * one-sided limits.  Errors as qbx_apply_explicit, plus QBX_EINVAL for a NULL
+ * grad. */
+int qbx_apply_explicit_gradient(int n_src, const double* src_xy, const double* src_nu,
+                                const double* src_q, int n_ctr, const double* ctr_xy,
+                                const double* ctr_r, const double* ctr_dir, double k, int p,
+                                int kind, double* grad, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* Vector-Jacobian product of qbx_apply_explicit for L = Re sum conj(cotangent) out
  * (cotangent [n_kinds][n_ctr] complex); every gradient pointer is nullable and the
  * gradients are written, not accumulated:
@@ -395,6 +409,30 @@ int qbx_apply_explicit_adjoint(int n_src, const double* src_xy, const double* sr
  * Stream-ordered, no allocation. */
 int qbx_principal_value(const double* out, const double* density, int n_panels, int side,
                         int kind, double* pv, hipStream_t stream);
+
+/* On-surface target derivatives from the one-sided limits of
+ * qbx_layer_potential_gradient (or _split_gradient), by the jump relations of
+ * Section 3.2 (x on the curve; + exterior, - interior):
+ *   grad S(x) = grad S(x^+-) +- n sigma / 2   (principal value; S' = n . grad S
+ *                                              jumps by sigma / 2 from each side)
+ *   grad D(x) = grad D(x^+-) -+ t dmu/ds / 2  (finite part, eq. dlpderiv; D' has
+ *                                              no jump)
+ * with n the outward unit normal at the node and t = (-n_y, n_x) the
+ * counter-clockwise unit tangent, both from the 16-node derivative of the panel
+ * as for the centers, and dmu/ds the derivative along the curve of the
+ * degree-15 interpolant of the D density through its 16 node values.
+ *   side = QBX_BOTH: the average of the two limits (as eq. dlp-twosided does for
+ *                    D); density unused, may be NULL.
+ *   one side:        that limit minus its jump; density [n_kinds][T] as given to
+ *                    the forward.
+ *   grad [n_sides][n_kinds][T][2] complex -> grad_pv [n_kinds][T][2];
+ *   dn   [n_sides][n_kinds][T] complex    -> dn_pv   [n_kinds][T].
+ * Either pair may be NULL, not both; an input and its output are given together.
+ * Stream-ordered, no allocation.  QBX_EINVAL for bad pointers, q, n_panels,
+ * side or kind. */
+int qbx_gradient_principal_value(const qbx_geometry* g, const double* density, int side,
+                                 int kind, const double* grad, const double* dn, double* grad_pv,
+                                 double* dn_pv, hipStream_t stream);
 
 /* ---- checks ------------------------------------------------------------ */
 
@@ -449,9 +487,15 @@ int qbx_debug_besselj(const double* x, int n, int L, double* out, hipStream_t st
  *                       centers x a block of 64-source chunks) aimed for
  *   batch_fused_chunks  batched adjoint without a tape: 64-source chunks per tile
  *                       (four waves share a tile, one chunk each at a time)
+ *   fused_part_bytes    adjoint without a tape (per contour and batched): bound
+ *                       on its source-side partial sums, one row of sources per
+ *                       tile of centers.  The tile height starts at 256 centers
+ *                       and doubles while the rows would take more bytes; a
+ *                       taller tile runs its centers in sub-blocks of 256.
  * Limits: the three wave targets, batch_adjoint_tasks and fused_tiles in
  * [256, 1 << 22], batch_grid_scale in [0.125, 8], batch_fused_chunks in
- * [1, 64].  Defaults 16384, 1.0, 16384 and 4. */
+ * [1, 64], fused_part_bytes in [4096, 2^40].  Defaults 16384, 1.0, 16384, 4
+ * and 2^31. */
 typedef struct {
   int32_t forward_waves;
   int32_t tape_waves;
@@ -460,6 +504,7 @@ typedef struct {
   double batch_grid_scale;
   int32_t fused_tiles;
   int32_t batch_fused_chunks;
+  double fused_part_bytes;
 } qbx_tuning;
 
 /* Set / read the process-wide tuning (QBX_EINVAL for values out of range). */

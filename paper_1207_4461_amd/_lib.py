@@ -57,7 +57,7 @@ class Tuning(C.Structure):
     _fields_ = [("forward_waves", C.c_int32), ("tape_waves", C.c_int32),
                 ("adjoint_waves", C.c_int32), ("batch_adjoint_tasks", C.c_int32),
                 ("batch_grid_scale", C.c_double), ("fused_tiles", C.c_int32),
-                ("batch_fused_chunks", C.c_int32)]
+                ("batch_fused_chunks", C.c_int32), ("fused_part_bytes", C.c_double)]
 
 
 _lib = None
@@ -105,6 +105,7 @@ def load() -> C.CDLL:
         "qbx_debug_besselj": (i32, [vp, i32, i32, vp, vp]),
         "qbx_kernel_timer": (i32, [i32]),
         "qbx_principal_value": (i32, [vp, vp, i32, i32, i32, vp, vp]),
+        "qbx_gradient_principal_value": (i32, [gp, vp, i32, i32, vp, vp, vp, vp, vp]),
         "qbx_batched_workspace_bytes": (sz, [C.POINTER(BatchItem), i32, i32]),
         "qbx_batched_tape_bytes": (sz, [C.POINTER(BatchItem), i32]),
         "qbx_layer_potential_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, vp, vp, i32, vp,
@@ -116,6 +117,8 @@ def load() -> C.CDLL:
         "qbx_explicit_tape_bytes": (sz, [i32, i32]),
         "qbx_apply_explicit": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp, vp, vp,
                                      sz, vp]),
+        "qbx_apply_explicit_gradient": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32,
+                                              vp, vp, sz, vp]),
         "qbx_apply_explicit_adjoint": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp,
                                              vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "qbx_set_tuning": (i32, [C.POINTER(Tuning)]),

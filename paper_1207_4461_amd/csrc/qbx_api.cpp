@@ -42,6 +42,9 @@ static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
 static int g_fused_tiles = 16384;  // fused adjoint workgroups aimed for
 static const int kSplitFarWaves = 16384;  // far-pass wavefronts aimed for
+static double g_fused_part_bytes = 2147483648.0;  // fused adjoint partial-sum bound
+
+double fused_part_budget() { return g_fused_part_bytes; }
 
 void set_contour_tuning(int forward_waves, int tape_waves, int adjoint_waves, int fused_tiles) {
   g_forward_waves = forward_waves;
@@ -283,6 +286,34 @@ static int prepare(const Dims& d, const Layout& L, const double* nodes, const do
                       at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab), stream);
   if (e != hipSuccess) return device_fail(e, "upsample kernel");
   return QBX_OK;
+}
+
+// the 16-node differentiation matrix by the barycentric formula, built once
+const NodeDiff& node_diff() {
+  static const NodeDiff D = [] {
+    NodeDiff r;
+    double t16[kQ], w16[kQ], bw[kQ];
+    for (int a = 0; a < kQ; ++a) gauss_legendre_node(kQ, a, &t16[a], &w16[a]);
+    for (int a = 0; a < kQ; ++a) {
+      double pr = 1.0;
+      for (int c = 0; c < kQ; ++c)
+        if (c != a) pr *= (t16[a] - t16[c]);
+      bw[a] = 1.0 / pr;
+    }
+    for (int b = 0; b < kQ; ++b)
+      for (int a = 0; a < kQ; ++a) {
+        if (a != b) {
+          r.d[b][a] = (bw[a] / bw[b]) / (t16[b] - t16[a]);
+        } else {
+          double v = 0.0;
+          for (int c = 0; c < kQ; ++c)
+            if (c != b) v += 1.0 / (t16[b] - t16[c]);
+          r.d[b][a] = v;
+        }
+      }
+    return r;
+  }();
+  return D;
 }
 
 int run_forward(const Dims& d, const Layout& L, const double* nodes, const double* density,
@@ -560,6 +591,29 @@ int qbx_principal_value(const double* out, const double* density, int n_panels, 
   return e == hipSuccess ? QBX_OK : device_fail(e, "principal value kernel");
 }
 
+int qbx_gradient_principal_value(const qbx_geometry* g, const double* density, int side,
+                                 int kind, const double* grad, const double* dn, double* grad_pv,
+                                 double* dn_pv, hipStream_t stream) {
+  if (!g || !g->nodes) return fail(QBX_EINVAL, "geometry or its nodes is NULL");
+  if (g->q != kQ) return fail(QBX_EINVAL, "q = %d, only %d nodes per panel are supported", g->q, kQ);
+  if (g->n_panels < 3) return fail(QBX_EINVAL, "n_panels = %d < 3", g->n_panels);
+  if (side != QBX_INTERIOR && side != QBX_EXTERIOR && side != QBX_BOTH)
+    return fail(QBX_EINVAL, "side = %d is not -1, 0 or 1", side);
+  if (kind != QBX_S && kind != QBX_D && kind != (QBX_S | QBX_D))
+    return fail(QBX_EINVAL, "kind = %d is not 1 (S), 2 (D) or 3 (S|D)", kind);
+  if (!grad != !grad_pv || !dn != !dn_pv)
+    return fail(QBX_EINVAL, "grad and grad_pv (dn and dn_pv) must be given together");
+  if (!grad && !dn) return fail(QBX_EINVAL, "grad and dn are both NULL");
+  if (side != QBX_BOTH && !density)
+    return fail(QBX_EINVAL, "density is needed for the one-sided jumps");
+  const long T = (long)g->n_panels * kQ;
+  if (T > (1L << 28)) return fail(QBX_EINVAL, "problem too large");
+  const int nk = kind == 3 ? 2 : 1;
+  hipError_t e = launch_gradient_principal_value((int)T, nk, side, kind, node_diff(), g->nodes,
+                                                 density, grad, dn, grad_pv, dn_pv, stream);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "gradient principal value kernel");
+}
+
 int qbx_check_geometry(const qbx_geometry* g, int p, double r, int oversample, int side,
                        double* area, double* min_ratio, void* ws, size_t ws_bytes,
                        hipStream_t stream) {
@@ -595,25 +649,9 @@ int qbx_signed_area_host(const double* nodes, int n_panels, double* area) {
   if (!nodes) return fail(QBX_EINVAL, "nodes is NULL");
   if (n_panels < 3) return fail(QBX_EINVAL, "n_panels = %d < 3", n_panels);
   // 16-point rule on each panel: area = 1/2 sum_a omega_a (x y' - y x')(tau_a)
-  double t16[kQ], w16[kQ], bw[kQ], D[kQ][kQ];
+  double t16[kQ], w16[kQ];
   for (int a = 0; a < kQ; ++a) gauss_legendre_node(kQ, a, &t16[a], &w16[a]);
-  for (int a = 0; a < kQ; ++a) {
-    double pr = 1.0;
-    for (int c = 0; c < kQ; ++c)
-      if (c != a) pr *= (t16[a] - t16[c]);
-    bw[a] = 1.0 / pr;
-  }
-  for (int b = 0; b < kQ; ++b)
-    for (int a = 0; a < kQ; ++a) {
-      if (a != b) {
-        D[b][a] = (bw[a] / bw[b]) / (t16[b] - t16[a]);
-      } else {
-        double v = 0.0;
-        for (int c = 0; c < kQ; ++c)
-          if (c != b) v += 1.0 / (t16[b] - t16[c]);
-        D[b][a] = v;
-      }
-    }
+  const auto& D = node_diff().d;
   double A = 0.0;
   for (int m = 0; m < n_panels; ++m) {
     const double* X = nodes + (size_t)m * 2 * kQ;
@@ -643,7 +681,10 @@ int qbx_set_tuning(const qbx_tuning* t) {
     return fail(QBX_EINVAL, "batch_grid_scale = %g outside [0.125, 8]", t->batch_grid_scale);
   if (t->batch_fused_chunks < 1 || t->batch_fused_chunks > 64)
     return fail(QBX_EINVAL, "batch_fused_chunks = %d outside [1, 64]", t->batch_fused_chunks);
+  if (!(t->fused_part_bytes >= 4096.0 && t->fused_part_bytes <= 1099511627776.0))
+    return fail(QBX_EINVAL, "fused_part_bytes = %g outside [4096, 2^40]", t->fused_part_bytes);
   set_contour_tuning(t->forward_waves, t->tape_waves, t->adjoint_waves, t->fused_tiles);
+  g_fused_part_bytes = t->fused_part_bytes;
   set_batch_tuning(t->batch_grid_scale, (double)t->batch_adjoint_tasks, t->batch_fused_chunks);
   return QBX_OK;
 }
@@ -661,6 +702,7 @@ int qbx_get_tuning(qbx_tuning* t) {
   t->batch_grid_scale = gs;
   t->fused_tiles = ft;
   t->batch_fused_chunks = fc;
+  t->fused_part_bytes = g_fused_part_bytes;
   return QBX_OK;
 }
 

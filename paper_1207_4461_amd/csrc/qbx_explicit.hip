@@ -246,6 +246,33 @@ int qbx_apply_explicit(int n_src, const double* src_xy, const double* src_nu, co
   return e == hipSuccess ? QBX_OK : device_fail(e, "explicit finalize kernel");
 }
 
+int qbx_apply_explicit_gradient(int n_src, const double* src_xy, const double* src_nu,
+                                const double* src_q, int n_ctr, const double* ctr_xy,
+                                const double* ctr_r, const double* ctr_dir, double k, int p,
+                                int kind, double* grad, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  Dims d;
+  Layout L;
+  int rc = explicit_validate(n_src, src_xy, src_nu, src_q, n_ctr, ctr_xy, ctr_r, ctr_dir, k, p,
+                             kind, ws, ws_bytes, &d, &L);
+  if (rc) return rc;
+  if (!grad) return fail(QBX_EINVAL, "grad is NULL");
+  rc = explicit_prepare(d, L, src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, ws, stream);
+  if (rc) return rc;
+  hipError_t e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
+  if (e != hipSuccess) return device_fail(e, "explicit order-weighted table kernel");
+  timer_begin(5, stream);
+  e = launch_forward_grad(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                          at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                          at<double2>(ws, L.partial), stream);
+  timer_end(5, stream);
+  if (e != hipSuccess) return device_fail(e, "explicit target-derivative kernel");
+  // one side and T = n_ctr: out[kind][center][2] = the gradient at the target
+  e = launch_finalize_gradient(d, at<CenterRec>(ws, L.ctr), at<double2>(ws, L.partial), grad,
+                               nullptr, stream);
+  return e == hipSuccess ? QBX_OK : device_fail(e, "explicit gradient finalize kernel");
+}
+
 int qbx_apply_explicit_adjoint(int n_src, const double* src_xy, const double* src_nu,
                                const double* src_q, int n_ctr, const double* ctr_xy,
                                const double* ctr_r, const double* ctr_dir, double k, int p,

@@ -125,6 +125,90 @@ hipError_t launch_principal_value(int T, int nk, int side, int kind, const doubl
   return hipGetLastError();
 }
 
+// On-surface derivatives from one-sided limits (Section 3.2): with both sides the
+// average of the two limits; with one side s (+1 exterior, -1 interior) the
+// limit minus its jump,
+//   grad S = grad S^s + s n sigma / 2,   S' = S'^s + s sigma / 2,
+//   grad D = grad D^s - s t dmu/ds / 2,  D' = D'^s,
+// with n the target's outward unit normal and t = (-n_y, n_x) the
+// counter-clockwise tangent, both from the 16-node derivative X'(tau) as for the
+// centers, and dmu/ds = (dmu/dtau) / |X'(tau)|.
+__global__ __launch_bounds__(256) void k_gradient_principal_value(
+    int T, int nk, int side, int kind, NodeDiff D, const double* __restrict__ nodes,
+    const double2* __restrict__ density, const double2* __restrict__ grad,
+    const double2* __restrict__ dn, double2* __restrict__ grad_pv, double2* __restrict__ dn_pv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T * nk) return;
+  const int kk = e / T, t = e - kk * T;
+  if (side == 0) {
+    const size_t a = (size_t)kk * T + t, b = ((size_t)nk + kk) * T + t;
+    if (grad_pv) {
+      for (int c = 0; c < 2; ++c) {
+        const double2 u = grad[2 * a + c], v = grad[2 * b + c];
+        grad_pv[2 * a + c] = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y + v.y));
+      }
+    }
+    if (dn_pv) {
+      const double2 u = dn[a], v = dn[b];
+      dn_pv[a] = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y + v.y));
+    }
+    return;
+  }
+  const double s = side > 0 ? 1.0 : -1.0;
+  const bool isD = (kind == 2) || (kind == 3 && kk == 1);
+  const int m = t / kQ, row = t - m * kQ;
+  const double* X = nodes + (size_t)m * 2 * kQ;
+  double dx = 0.0, dy = 0.0;
+  for (int a = 0; a < kQ; ++a) {
+    dx = fma(D.d[row][a], X[2 * a], dx);
+    dy = fma(D.d[row][a], X[2 * a + 1], dy);
+  }
+  const double inv = 1.0 / sqrt(dx * dx + dy * dy);
+  const double tx = dx * inv, ty = dy * inv;   // t = X' / |X'|; n = (t_y, -t_x)
+  const size_t o = (size_t)kk * T + t;
+  if (!isD) {
+    const double2 sig = density[o];
+    if (grad_pv) {
+      const double nx = ty, ny = -tx;
+      const double2 gx = grad[2 * o], gy = grad[2 * o + 1];
+      grad_pv[2 * o] = make_double2(fma(0.5 * s * nx, sig.x, gx.x), fma(0.5 * s * nx, sig.y, gx.y));
+      grad_pv[2 * o + 1] =
+          make_double2(fma(0.5 * s * ny, sig.x, gy.x), fma(0.5 * s * ny, sig.y, gy.y));
+    }
+    if (dn_pv) {
+      const double2 v = dn[o];
+      dn_pv[o] = make_double2(fma(0.5 * s, sig.x, v.x), fma(0.5 * s, sig.y, v.y));
+    }
+    return;
+  }
+  if (grad_pv) {
+    const double2* mu = density + (size_t)kk * T + (size_t)m * kQ;
+    double dr = 0.0, di = 0.0;
+    for (int a = 0; a < kQ; ++a) {
+      dr = fma(D.d[row][a], mu[a].x, dr);
+      di = fma(D.d[row][a], mu[a].y, di);
+    }
+    dr *= inv;
+    di *= inv;
+    const double2 gx = grad[2 * o], gy = grad[2 * o + 1];
+    grad_pv[2 * o] = make_double2(fma(-0.5 * s * tx, dr, gx.x), fma(-0.5 * s * tx, di, gx.y));
+    grad_pv[2 * o + 1] = make_double2(fma(-0.5 * s * ty, dr, gy.x), fma(-0.5 * s * ty, di, gy.y));
+  }
+  if (dn_pv) dn_pv[o] = dn[o];
+}
+
+hipError_t launch_gradient_principal_value(int T, int nk, int side, int kind, const NodeDiff& D,
+                                           const double* nodes, const double* density,
+                                           const double* grad, const double* dn,
+                                           double* grad_pv, double* dn_pv, hipStream_t s) {
+  const int n = T * nk;
+  hipLaunchKernelGGL(k_gradient_principal_value, dim3((n + 255) / 256), dim3(256), 0, s, T, nk,
+                     side, kind, D, nodes, reinterpret_cast<const double2*>(density),
+                     reinterpret_cast<const double2*>(grad), reinterpret_cast<const double2*>(dn),
+                     reinterpret_cast<double2*>(grad_pv), reinterpret_cast<double2*>(dn_pv));
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s) {
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_finalize, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,

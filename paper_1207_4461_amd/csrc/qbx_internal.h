@@ -135,6 +135,19 @@ hipError_t launch_forward(const Dims& d, const double4* geo, const double2* dens
 hipError_t launch_finalize(const Dims& d, const double2* partial, double* out, hipStream_t s);
 hipError_t launch_principal_value(int T, int nk, int side, int kind, const double* out,
                                   const double* density, double* pv, hipStream_t s);
+// d[b][a]: derivative in the panel parameter, at node b, of the degree-15
+// Lagrange basis polynomial of node a (16-point Gauss-Legendre nodes)
+struct NodeDiff {
+  double d[kQ][kQ];
+};
+const NodeDiff& node_diff();
+// on-surface target derivatives from one-sided limits (Section 3.2 jumps):
+// grad [n_sides][nk][T][2] -> grad_pv [nk][T][2], dn [n_sides][nk][T] -> dn_pv
+// [nk][T] (either pair may be NULL)
+hipError_t launch_gradient_principal_value(int T, int nk, int side, int kind, const NodeDiff& D,
+                                           const double* nodes, const double* density,
+                                           const double* grad, const double* dn,
+                                           double* grad_pv, double* dn_pv, hipStream_t s);
 // ---- split forward (qbx_split.hip) ----
 hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s);
 // partial [nk][Mc]: QBX sums over the sources of near panels
@@ -201,16 +214,18 @@ __host__ __device__ constexpr int src_slots(int kind) {
 #define QBX_FUSED_CENTERS 256
 #endif
 __host__ __device__ constexpr int fused_centers(int) { return QBX_FUSED_CENTERS; }
+// bound in bytes on the fused adjoint's source-side partial sums (the tuning's
+// fused_part_bytes)
+double fused_part_budget();
 // centers per fused tile (taken in sub-blocks of fused_centers()): the
 // source-side partial sums are one row of sources per tile of centers, so they
 // take sources x centers / height x 16 B a slot.  The height starts at one
 // sub-block (fine-grained tiles) and doubles while those sums would pass
-// kFusedPartBudget bytes.
-constexpr double kFusedPartBudget = 2147483648.0;
-__host__ __device__ inline int fused_tile_height(int Mc, int N, int kind) {
+// fused_part_budget() bytes.
+inline int fused_tile_height(int Mc, int N, int kind) {
+  const double budget = fused_part_budget();
   long long h = fused_centers(kind);
-  while (h < Mc &&
-         (double)((Mc + h - 1) / h) * src_slots(kind) * (double)N * 16.0 > kFusedPartBudget)
+  while (h < Mc && (double)((Mc + h - 1) / h) * src_slots(kind) * (double)N * 16.0 > budget)
     h *= 2;
   return h < Mc ? (int)h : Mc;
 }

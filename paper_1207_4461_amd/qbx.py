@@ -380,6 +380,34 @@ def principal_value(out: torch.Tensor, density: Optional[torch.Tensor], side: in
     return pv
 
 
+def gradient_principal_value(nodes: torch.Tensor, density: Optional[torch.Tensor], side: int,
+                             kind: int, grad: Optional[torch.Tensor] = None,
+                             dn: Optional[torch.Tensor] = None):
+    """On-surface target derivatives (qbx_gradient_principal_value, Section 3.2): from the
+    one-sided limits of layer_potential_gradient, the principal value of grad S (and S')
+    and the finite part of grad D (and D').  Returns (grad [n_kinds, T, 2],
+    dn [n_kinds, T]); an output is None when its input is."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk, T = n_kinds(kind), P * Q
+    if grad is not None:
+        _need(grad, "grad", torch.complex128, (n_sides(side), nk, T, 2))
+    if dn is not None:
+        _need(dn, "dn", torch.complex128, (n_sides(side), nk, T))
+    if density is not None:
+        _need(density, "density", torch.complex128, (nk, T))
+    gp = (torch.empty((nk, T, 2), dtype=torch.complex128, device=nodes.device)
+          if grad is not None else None)
+    dp = torch.empty((nk, T), dtype=torch.complex128, device=nodes.device) if dn is not None else None
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    _lib.check(lib.qbx_gradient_principal_value(C.byref(geo), ptr(density), int(side), int(kind),
+                                                ptr(grad), ptr(dn), ptr(gp), ptr(dp),
+                                                _stream(nodes.device)))
+    return gp, dp
+
+
 def check_geometry(nodes: torch.Tensor, p: int, r: float = 0.5, oversample: int = 4,
                    side: int = EXTERIOR) -> Tuple[int, float, float]:
     """Synchronous check: (status, signed area, min |x'-c|/R).  status is 0, QBX_EORIENT
@@ -559,6 +587,21 @@ def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, k: float, p: i
     _lib.check(lib.qbx_apply_explicit(*a, float(k), int(p), int(kind), out.data_ptr(), tp,
                                       ws.data_ptr(), ws.numel(), _stream(dev)))
     return out
+
+
+def apply_explicit_gradient(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, k: float, p: int,
+                            kind: int = S, workspace: Optional[torch.Tensor] = None
+                            ) -> torch.Tensor:
+    """qbx_apply_explicit_gradient: the target gradient of each center's expansion,
+    [n_kinds, n_ctr, 2] complex128 (d/dx, d/dy at x = c + R e^{i theta})."""
+    lib = _lib.load()
+    n_src, n_ctr, a = _explicit_args(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, kind)
+    dev = src_xy.device
+    grad = torch.empty((n_kinds(kind), n_ctr, 2), dtype=torch.complex128, device=dev)
+    ws = _workspace(explicit_workspace_bytes(n_src, n_ctr, p, kind), dev, workspace)
+    _lib.check(lib.qbx_apply_explicit_gradient(*a, float(k), int(p), int(kind), grad.data_ptr(),
+                                               ws.data_ptr(), ws.numel(), _stream(dev)))
+    return grad
 
 
 def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_dir, cotangent, k: float, p: int,

@@ -274,11 +274,22 @@ def test_tuning_roundtrip_and_validation(lib):
         assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
         lib.qbx_get_tuning(C.byref(t1))
         assert (t1.fused_tiles, t1.batch_fused_chunks) == (1 << 14, 7)
+        # the fused adjoint's partial-sum bound: default 2^31; a smaller bound means
+        # taller tiles and so a smaller workspace (star1024 sizes: 1024 panels, S)
+        assert t0.fused_part_bytes == 2.0 ** 31
+        n_wide = lib.qbx_workspace_bytes(1024, 16, 16, 4, 1, 1)
+        t.fused_part_bytes = 1 << 20
+        assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
+        lib.qbx_get_tuning(C.byref(t1))
+        assert t1.fused_part_bytes == 1 << 20
+        assert lib.qbx_workspace_bytes(1024, 16, 16, 4, 1, 1) < n_wide
         for field, bad in (("forward_waves", 255), ("tape_waves", 1 << 23), ("adjoint_waves", 0),
                            ("batch_adjoint_tasks", -5), ("batch_grid_scale", 0.1),
                            ("batch_grid_scale", 9.0), ("batch_grid_scale", float("nan")),
                            ("fused_tiles", 100), ("fused_tiles", 1 << 23),
-                           ("batch_fused_chunks", 0), ("batch_fused_chunks", 65)):
+                           ("batch_fused_chunks", 0), ("batch_fused_chunks", 65),
+                           ("fused_part_bytes", 4095.0), ("fused_part_bytes", 2.0 ** 41),
+                           ("fused_part_bytes", float("nan"))):
             tb = _lib.Tuning(*[getattr(t0, f) for f in fields])
             setattr(tb, field, bad)
             assert lib.qbx_set_tuning(C.byref(tb)) == _lib.QBX_EINVAL
@@ -356,3 +367,29 @@ def test_noalloc_entry_point_validates(lib):
                                            None) == _lib.QBX_EWORKSPACE
     assert b"static scratch" in lib.qbx_last_error()
     assert _lib.QBX_STATIC_SCRATCH_BYTES == 64 << 20
+
+
+def test_gradient_principal_value_validates(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    call = lambda gp=C.byref(g), **kw: lib.qbx_gradient_principal_value(
+        gp, kw.get("dens", BAD), kw.get("side", 1), kw.get("kind", 3), kw.get("grad", BAD),
+        kw.get("dn", BAD), kw.get("gpv", BAD), kw.get("dpv", BAD), None)
+    for bad in (dict(side=2), dict(kind=0), dict(kind=4), dict(dens=None),
+                dict(grad=None), dict(dpv=None), dict(grad=None, gpv=None, dn=None, dpv=None)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(gp=None) == _lib.QBX_EINVAL
+    assert call(gp=C.byref(_lib.Geometry(2, 16, BAD))) == _lib.QBX_EINVAL
+    assert call(gp=C.byref(_lib.Geometry(8, 8, BAD))) == _lib.QBX_EINVAL
+    assert call(gp=C.byref(_lib.Geometry(8, 16, None))) == _lib.QBX_EINVAL
+
+
+def test_explicit_gradient_validates(lib):
+    call = lambda **kw: lib.qbx_apply_explicit_gradient(
+        kw.get("ns", 10), BAD, kw.get("nu", BAD), BAD, kw.get("nc", 4), BAD, BAD, BAD,
+        kw.get("k", 2.0), kw.get("p", 5), kw.get("kind", 3), kw.get("grad", BAD), BAD,
+        kw.get("nbytes", 1 << 40), None)
+    for bad in (dict(ns=0), dict(nc=0), dict(p=25), dict(kind=4), dict(k=0.0), dict(grad=None),
+                dict(nu=None)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    need = lib.qbx_explicit_workspace_bytes(10, 4, 5, 3)
+    assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE

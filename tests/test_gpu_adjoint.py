@@ -7,6 +7,7 @@ workloads: sampled panels through the oracle's restricted gradient, plus
 size-independent properties (linearity / dot-product, translation and rotation
 invariance, central differences of the GPU forward).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -15,6 +16,7 @@ import torch
 
 from oracle import qbx_oracle as O
 from paper_1207_4461_amd import inputs as I
+from parity_helpers import bar, rel, star4096_golden, ulp_perturbed
 
 pytestmark = pytest.mark.gpu
 TOL_D = 1e-11
@@ -42,10 +44,6 @@ def gpu_vjp(Q, pb, tape=None):
                                    pb.r, pb.oversample, pb.side, pb.kind, tape=tape)
     torch.cuda.synchronize()
     return gd.cpu().numpy(), gn.cpu().numpy()
-
-
-def rel(a, b):
-    return float(np.abs(a - b).max() / np.abs(b).max())
 
 
 CASES = [
@@ -111,6 +109,136 @@ def test_autograd_function_and_gradcheck(Q):
 def _panels(pb, n, seed):
     rng = np.random.default_rng(seed)
     return np.unique(np.concatenate([[0, pb.n_panels - 1], rng.choice(pb.n_panels, n, replace=False)]))
+
+
+def check_star4096_panels(gd, gn, sens, n_kinds, what, tol_d=TOL_D, tol_n=TOL_N):
+    """Element-wise parity of full star4096 gradients with the stored oracle values on
+    three panels.  sens: the same gradients' change under one ulp on every node
+    coordinate ({"density": [per kind], "nodes": x}); the bars are the plain ones or
+    a few times that sensitivity, whichever is larger."""
+    sel, rd, rn = star4096_golden()
+    a = gd.reshape(n_kinds, -1, 16)[:, sel]
+    en = rel(gn[sel], rn)
+    bn = bar(tol_n, sens["nodes"])
+    say(f"  {what}: star4096 panels {sel.tolist()}: grad nodes {en:.3e} (one-ulp "
+        f"sensitivity {sens['nodes']:.2e}, bar {bn:.2e})")
+    assert en <= bn
+    for ki in range(n_kinds):
+        ed = rel(a[ki], rd[ki])
+        bd = bar(tol_d, sens["density"][ki])
+        say(f"    kind {ki}: grad density {ed:.3e} (one-ulp sensitivity "
+            f"{sens['density'][ki]:.2e}, bar {bd:.2e})")
+        assert ed <= bd
+
+
+def ulp_sensitivity(Q, pb, gd, gn, **kw):
+    """How far one ulp on every node coordinate moves the GPU gradients."""
+    pert = dataclasses.replace(pb, nodes=ulp_perturbed(pb.nodes))
+    gd1, gn1 = gpu_vjp(Q, pert, **kw)
+    nk = pb.n_kinds
+    return {"density": [rel(gd1.reshape(nk, -1)[k], gd.reshape(nk, -1)[k]) for k in range(nk)],
+            "nodes": rel(gn1, gn)}
+
+
+def test_adjoint_star4096_sampled_panels(Q):
+    """The fused adjoint at the bench workload's full size (4096 panels, tile height
+    1024 under the default partial-sum bound, so every tile runs four sub-blocks),
+    element by element on three panels against the oracle (bars: see parity_helpers;
+    the S density gradient and the node gradient meet the plain bars)."""
+    pb = I.star4096()
+    say(f"star4096: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side}")
+    gd, gn = gpu_vjp(Q, pb)
+    sens = ulp_sensitivity(Q, pb, gd, gn)
+    check_star4096_panels(gd, gn, sens, pb.n_kinds, "default tuning")
+    sel, rd, rn = star4096_golden()
+    assert rel(gd.reshape(2, -1, 16)[0, sel], rd[0]) <= TOL_D
+    assert rel(gn[sel], rn) <= TOL_N
+
+
+def test_adjoint_star4096_identical_geometry(Q):
+    """The adjoint's pair terms at star4096 with the geometry's rounding taken out: the
+    oracle's source grid and centers (both sides) go through qbx_apply_explicit_adjoint
+    and through the oracle's autograd of the same expansions, for the 64 sources of the
+    last panel against every center.  The gradients for the weighted densities, the
+    source points and normals (all centers summed) and the center data meet the plain
+    bars."""
+    pb = I.star4096()
+    X = torch.from_numpy(pb.nodes)
+    src = O.source_grid(X, pb.oversample)
+    fine = O.interpolate_density(torch.from_numpy(pb.density), pb.oversample)
+    q = src["w"].to(torch.complex128)[None] * fine
+    m = pb.n_panels - 1
+    sidx = torch.arange(m * 64, m * 64 + 64)
+    src_xy = torch.stack([src["x"], src["y"]], -1)[sidx].contiguous()
+    src_nu = torch.stack([src["nx"], src["ny"]], -1)[sidx].contiguous()
+    qs = q[:, sidx].contiguous()
+    parts = [O.expansion_centers(X, src["h"], src["n_tgt"], pb.r, s) for s in (1, -1)]
+    cx, cy, R, th = [torch.cat([c[key] for c in parts]) for key in ("cx", "cy", "R", "theta")]
+    cot = np.stack([np.concatenate([pb.cotangent[0, kk], pb.cotangent[1, kk]])
+                    for kk in range(pb.n_kinds)])
+    ref = {"q": 0.0, "src_xy": 0.0, "src_nu": 0.0}
+    r_ctr = {"ctr_xy": [], "ctr_r": [], "ctr_theta": []}
+    step = 8192
+    for c0 in range(0, len(cx), step):
+        sl = slice(c0, c0 + step)
+        g = O.apply_explicit_vjp(src_xy, src_nu, qs, torch.stack([cx[sl], cy[sl]], -1), R[sl],
+                                 th[sl], pb.k, pb.p, pb.kind, cot[:, sl])
+        for key in ref:
+            ref[key] = ref[key] + g[key]
+        for key in r_ctr:
+            r_ctr[key].append(g[key])
+    r_ctr = {key: np.concatenate(v) for key, v in r_ctr.items()}
+    ctr_dir = torch.exp(1j * th.to(torch.complex128))
+    gg = Q.apply_explicit_vjp(dev(src_xy), dev(src_nu), dev(qs), dev(torch.stack([cx, cy], -1)),
+                              dev(R), dev(ctr_dir), dev(cot), pb.k, pb.p, pb.kind)
+    gg = {key: v.cpu().numpy() for key, v in gg.items()}
+    errs = {key: rel(gg[key], ref[key]) for key in ref}
+    errs.update({key: rel(gg[key], r_ctr[key]) for key in r_ctr})
+    say(f"  identical geometry, panel {m}'s sources x all centers: "
+        + ", ".join(f"{key} {v:.2e}" for key, v in errs.items()))
+    for ki in range(pb.n_kinds):
+        e = rel(gg["q"][ki], ref["q"][ki])
+        say(f"    kind {ki}: grad q {e:.2e}")
+        assert e <= TOL_D
+    assert max(errs.values()) <= TOL_N
+
+
+def _tile_height(Mc, N, kind, budget):
+    slots = (2 if kind == 3 else 1) + 1 + (1 if kind & 2 else 0)
+    h = 256
+    while h < Mc and -(-Mc // h) * slots * N * 16 > budget:
+        h *= 2
+    return min(h, Mc)
+
+
+@pytest.mark.parametrize("case,budgets", [
+    (dict(n_panels=40, p=9, k=6.0, kind=3, side=0), (600000.0, 400000.0, 200000.0)),
+    (dict(n_panels=40, p=14, k=9.0, kind=2, side=-1, oversample=4), (300000.0, 4096.0)),
+    (dict(n_panels=23, p=5, k=4.0, kind=1, side=1, oversample=3), (40000.0,)),
+])
+def test_fused_adjoint_tall_tiles(Q, case, budgets):
+    """Tiles taller than one 256-center sub-block (the path a small partial-sum bound,
+    or the star4096 workload under the default one, takes): the wave owning a chunk
+    adds each sub-block's source sums into its row in turn.  Element-wise against the
+    oracle for tile heights 512, 1024 and the whole center set (a ragged last
+    sub-block), with one and with several source blocks."""
+    pb = I.small(**case)
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent)
+    before = Q.get_tuning()
+    try:
+        for budget in budgets:
+            h = _tile_height(pb.n_centers, pb.n_sources, pb.kind, budget)
+            assert h > 256
+            for ft in (256, 1 << 22):
+                Q.set_tuning(fused_part_bytes=budget, fused_tiles=ft)
+                gd, gn = gpu_vjp(Q, pb)
+                ed, en = rel(gd, rd), rel(gn, rn)
+                say(f"  budget {budget:.0f} (tile height {h} of {pb.n_centers} centers) "
+                    f"fused_tiles {ft}: grad density {ed:.3e}  grad nodes {en:.3e}")
+                assert ed <= TOL_D and en <= TOL_N
+    finally:
+        Q.set_tuning(**before)
 
 
 @pytest.mark.parametrize("cfg,n", [("star256", 3), ("star1024", 2)])

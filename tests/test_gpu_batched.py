@@ -107,6 +107,32 @@ def test_batched_fused_tile_depths(Q):
         Q.set_tuning(**before)
 
 
+def test_batched_fused_tall_tiles(Q):
+    """The batched fused pass with tiles taller than one 256-center sub-block (a small
+    partial-sum bound): 512 centers, and the whole center set with a ragged last
+    sub-block, against the oracle."""
+    specs = [dict(n_panels=20, p=10, kind=3, side=0, k=6.0),
+             dict(n_panels=33, p=7, kind=1, side=1, k=4.0),
+             dict(n_panels=9, p=12, kind=2, side=0, k=7.0)]
+    pbs = [I.small(name=f"t{i}", seed=50 + i, **c) for i, c in enumerate(specs)]
+    refs = [O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                  pb.cotangent) for pb in pbs]
+    before = Q.get_tuning()
+    try:
+        for budget in (200000.0, 4096.0):
+            Q.set_tuning(fused_part_bytes=budget)
+            B = Q.Batch(pbs, oversample=4)
+            cot = B.pack_out([pb.cotangent for pb in pbs])
+            gd, gn = B.adjoint(cot, use_tape=False)
+            for pb, a, x, (rd, rn) in zip(pbs, B.split_density(gd), B.split_nodes(gn), refs):
+                ed, en = rel(a.cpu().numpy(), rd), rel(x.cpu().numpy(), rn)
+                say(f"  budget {budget:.0f} {pb.name} ({pb.n_centers} centers): density "
+                    f"{ed:.2e} nodes {en:.2e}")
+                assert ed < 1e-11 and en < 1e-10
+    finally:
+        Q.set_tuning(**before)
+
+
 def test_random64_batch_full(Q):
     pbs = I.random64()
     B = Q.Batch(pbs, oversample=4)

@@ -57,6 +57,11 @@ def test_star4096_in_bench_configuration(Q):
         Ld = float(torch.real(torch.sum(torch.conj(gd) * dens)))
         say(f"  dot product: {abs(L - Ld) / abs(L):.3e}")
         assert abs(L - Ld) <= 1e-12 * abs(L)
+        # and element by element on three panels against the oracle's stored gradients
+        from test_gpu_adjoint import check_star4096_panels, ulp_sensitivity
+        gd, gn = gd.cpu().numpy(), gn.cpu().numpy()
+        check_star4096_panels(gd, gn, ulp_sensitivity(Q, pb, gd, gn), pb.n_kinds,
+                              "bench tuning")
     finally:
         Q.set_tuning(**before)
 

@@ -2,6 +2,7 @@
 ABI) against the oracle's gradient of the local expansion (Section 3.2), and two
 checks computed entirely on the GPU: Green's identity differentiated and the circle
 closed forms.  Bar: 1e-11 relative max-norm per output array against the oracle."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -11,6 +12,7 @@ import torch
 
 from oracle import qbx_oracle as O
 from paper_1207_4461_amd import inputs as I
+from parity_helpers import bar, ulp_perturbed
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-11
@@ -77,25 +79,76 @@ def test_gradient_small_elementwise(Q, case):
     assert np.array_equal(g2, g) and np.array_equal(dn2, dn)
 
 
-# star4096 (p = 20, R = 8e-4): D' is sensitive to the rounding of the geometry; one ulp
-# on every source coordinate changes the oracle's D' sums by 8.7e-11 (S: 2e-12), and the
-# GPU and the oracle build the source grid, normals and centers a few ulps apart, so
-# their D derivatives differ by about 4e-10.  The bar there, 2e-9, is that sensitivity
-# times ~20 ulps.
-@pytest.mark.parametrize("cfg,n,tol", [("star256", 48, TOL), ("star1024", 24, TOL),
-                                       ("star4096", 5, 2e-9)])
-def test_gradient_full_size_sampled(Q, cfg, n, tol):
+@pytest.mark.parametrize("cfg,n", [("star256", 48), ("star1024", 24), ("star4096", 5)])
+def test_gradient_full_size_sampled(Q, cfg, n):
+    """Sampled targets of the full workloads against the oracle.  Per output array the
+    bar is 1e-11 or, where larger, a few times the array's change under one ulp on every
+    node coordinate (parity_helpers): at star4096 grad D and D' move by about 5e-10
+    under that change.  The identical-geometry test below holds the kernel itself to
+    1e-11 there."""
     pb = getattr(I, cfg)()
     idx = np.unique(np.concatenate([[0, pb.n_targets - 1],
                                     np.random.default_rng(5).choice(pb.n_targets, n, replace=False)]))
     say(f"{cfg}: P={pb.n_panels} p={pb.p} kind={pb.kind} side={pb.side}, {len(idx)} targets")
     rg, rdn = O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
                                          pb.side, pb.kind, targets=idx)
+    rg, rdn = rg.numpy(), rdn.numpy()
     g, dn = gpu_gradient(Q, pb)
-    eg = rel(g[:, :, idx], rg.numpy())
-    ed = rel(dn[:, :, idx], rdn.numpy())
-    say(f"  grad {eg:.3e}  n.grad {ed:.3e}")
-    assert eg <= tol and ed <= tol
+    g1, dn1 = gpu_gradient(Q, dataclasses.replace(pb, nodes=ulp_perturbed(pb.nodes)))
+    for si in range(rg.shape[0]):
+        for ki in range(rg.shape[1]):
+            eg, ed = rel(g[si, ki, idx], rg[si, ki]), rel(dn[si, ki, idx], rdn[si, ki])
+            sg, sd = rel(g1[si, ki], g[si, ki]), rel(dn1[si, ki], dn[si, ki])
+            bg, bd = bar(TOL, sg), bar(TOL, sd)
+            say(f"  side {si} kind {ki}: grad {eg:.3e} (one-ulp sensitivity {sg:.2e}, bar "
+                f"{bg:.2e})  n.grad {ed:.3e} ({sd:.2e}, {bd:.2e})")
+            assert eg <= bg and ed <= bd
+            if cfg != "star4096":
+                assert eg <= TOL and ed <= TOL
+
+
+def test_gradient_star4096_identical_geometry(Q):
+    """The derivative pair pass on the oracle's own geometry at star4096.  The oracle's
+    source grid (points, normals, weights times the interpolated densities) and its
+    centers go through qbx_apply_explicit_gradient, the pair pass and finalize of
+    qbx_layer_potential_gradient, and through the oracle's gradient of the same local
+    expansions.  With the geometry's rounding the same on both sides, grad u and
+    n . grad u must meet the 1e-11 bar; the gap of the end-to-end comparison above
+    (2e-9) is then the geometry's rounding, not a term of the kernel."""
+    pb = I.star4096()
+    X = torch.from_numpy(pb.nodes)
+    src = O.source_grid(X, pb.oversample)
+    fine = O.interpolate_density(torch.from_numpy(pb.density), pb.oversample)
+    q = (src["w"].to(torch.complex128)[None] * fine).contiguous()
+    kinds = O.kinds_of(pb.kind)
+    dens = {kk: q[i] for i, kk in enumerate(kinds)}
+    src_xy = torch.stack([src["x"], src["y"]], -1)
+    src_nu = torch.stack([src["nx"], src["ny"]], -1)
+    idx = np.unique(np.concatenate([[0, pb.n_targets - 1],
+                                    np.random.default_rng(5).choice(pb.n_targets, 10,
+                                                                    replace=False)]))
+    n_t = src["n_tgt"][idx].numpy()
+    g_contour, _ = gpu_gradient(Q, pb)
+    for si, s in enumerate(O.sides_of(pb.side)):
+        ctr = O.expansion_centers(X, src["h"], src["n_tgt"], pb.r, s)
+        ctr = {key: val[torch.as_tensor(idx)] for key, val in ctr.items()}
+        a = O.coefficients(src, dens, ctr, pb.k, pb.p, pb.kind)
+        ref = torch.stack([O.evaluate_gradient(a[kk], ctr["R"], ctr["theta"], pb.k, pb.p)
+                           for kk in kinds]).numpy()
+        ctr_xy = torch.stack([ctr["cx"], ctr["cy"]], -1)
+        ctr_dir = torch.exp(1j * ctr["theta"].to(torch.complex128))
+        g = Q.apply_explicit_gradient(dev(src_xy), dev(src_nu), dev(q), dev(ctr_xy),
+                                      dev(ctr["R"]), dev(ctr_dir), pb.k, pb.p,
+                                      pb.kind).cpu().numpy()
+        for ki, kk in enumerate(kinds):
+            eg = rel(g[ki], ref[ki])
+            dn_g = g[ki, :, 0] * n_t[:, 0] + g[ki, :, 1] * n_t[:, 1]
+            dn_r = ref[ki, :, 0] * n_t[:, 0] + ref[ki, :, 1] * n_t[:, 1]
+            ed = rel(dn_g, dn_r)
+            geo = rel(g_contour[si, ki][idx], g[ki])
+            say(f"  side {s:+d} {kk}: grad {eg:.3e}  n.grad {ed:.3e}  (contour path's own "
+                f"geometry vs this one: {geo:.3e})")
+            assert eg <= TOL and ed <= TOL
 
 
 def test_gradient_green_identity_on_gpu(Q):
@@ -135,3 +188,68 @@ def test_gradient_circle_closed_forms_on_gpu(Q):
     assert rel(dn[0, 0], Sp) < 1e-5 and rel(dn[1, 0], Sm) < 1e-11
     assert rel(dn[0, 1], Dd) < 1e-5 and rel(dn[1, 1], Dd) < 1e-11
     assert rel(dn[1, 0] - dn[0, 0], dens) < 1e-5
+
+
+PV_CASES = [
+    dict(name="SD-ext-p8", n_panels=9, p=8, kind=3, side=1, k=4.0),
+    dict(name="SD-int-p12-os3", n_panels=7, p=12, kind=3, side=-1, k=6.0, oversample=3),
+    dict(name="S-int-p5", n_panels=5, p=5, kind=1, side=-1),
+    dict(name="D-ext-p20", n_panels=6, p=20, kind=2, side=1, k=2.0),
+    dict(name="SD-both-p10", n_panels=8, p=10, kind=3, side=0, k=5.0),
+]
+
+
+@pytest.mark.parametrize("case", PV_CASES, ids=[c["name"] for c in PV_CASES])
+def test_gradient_principal_value_against_oracle(Q, case):
+    """qbx_gradient_principal_value: (a) on the oracle's own one-sided limits it gives the
+    oracle's on-surface values (the jump step alone); (b) after the GPU's own derivative
+    pass it gives the oracle's end to end."""
+    c = dict(case)
+    name = c.pop("name")
+    pb = I.small(name=name, **c)
+    rg, rdn = O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                         pb.side, pb.kind)
+    pg, pdn = O.gradient_principal_value(pb.nodes, pb.density, rg, rdn, pb.side, pb.kind)
+    pg, pdn = pg.numpy(), pdn.numpy()
+    nodes, dens = dev(pb.nodes), dev(pb.density)
+    # (a) the jump step on identical one-sided inputs
+    ag, adn = Q.gradient_principal_value(nodes, dens, pb.side, pb.kind, dev(rg.numpy()),
+                                         dev(rdn.numpy()))
+    ea, eb = rel(ag.cpu().numpy(), pg), rel(adn.cpu().numpy(), pdn)
+    say(f"  {name}: jump step on the oracle's limits: grad {ea:.2e} n.grad {eb:.2e}")
+    assert ea <= 1e-13 and eb <= 1e-13
+    # (b) end to end
+    g, dn = Q.layer_potential_gradient(nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                                       pb.kind)
+    gg, gdn = Q.gradient_principal_value(nodes, dens, pb.side, pb.kind, g, dn)
+    gg, gdn = gg.cpu().numpy(), gdn.cpu().numpy()
+    for ki in range(pg.shape[0]):
+        e1, e2 = rel(gg[ki], pg[ki]), rel(gdn[ki], pdn[ki])
+        say(f"    kind {ki}: grad {e1:.3e}  n.grad {e2:.3e}")
+        assert e1 <= TOL and e2 <= TOL
+    # one output alone
+    only, none = Q.gradient_principal_value(nodes, dens, pb.side, pb.kind, dn=dn)
+    assert only is None and np.array_equal(none.cpu().numpy(), gdn)
+
+
+def test_gradient_principal_value_sides_agree_on_gpu(Q):
+    """On the GPU alone: the exterior and interior limits, each with its own jump taken
+    out, agree to the QBX error that D' (no jump) shows between its two limits."""
+    curve = I.star((5, 0.25, 0.0))
+    P = 64
+    nodes = I.panel_nodes(curve, P)
+    t = I.panel_parameters(P).reshape(-1)
+    rng = np.random.default_rng(7)
+    dens = dev(np.stack([I.smooth_density(rng, t), I.smooth_density(rng, t)]))
+    X = dev(nodes)
+    g, dn = Q.layer_potential_gradient(X, dens, 4.0, 10, 0.5, 4, I.BOTH, 3)
+    ge, de = Q.gradient_principal_value(X, dens, I.EXTERIOR, 3, g[:1].contiguous(),
+                                        dn[:1].contiguous())
+    gi, di = Q.gradient_principal_value(X, dens, I.INTERIOR, 3, g[1:].contiguous(),
+                                        dn[1:].contiguous())
+    qbx_err = rel(dn[0, 1].cpu().numpy(), dn[1, 1].cpu().numpy())
+    gap = max(rel(ge[0].cpu().numpy(), gi[0].cpu().numpy()),
+              rel(ge[1].cpu().numpy(), gi[1].cpu().numpy()),
+              rel(de[0].cpu().numpy(), di[0].cpu().numpy()))
+    say(f"  exterior vs interior fix-up {gap:.2e}; D' limits {qbx_err:.2e}")
+    assert gap < 5 * qbx_err and gap < 2e-4
