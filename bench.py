@@ -66,6 +66,134 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
+def host_cpu() -> dict:
+    """The host the oracle runs on: logical CPUs, CPU model, torch's thread count."""
+    import torch
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "threads": torch.get_num_threads()}
+
+
+def cpu_baseline(args, mode, pb, fwd, step, gpu_vjp):
+    """The oracle (as it stands) on the host cores, on bounded samples of the workload:
+
+    - forward: a random sample of targets (both sides) against all sources, sized for
+      about a third of --cpu-seconds, and the same on one thread;
+    - forward + backward (mode fwdbwd): the oracle's gradient restricted to one
+      panel, exact there (that panel's centers against all sources, every other
+      center against that panel's sources), compared element by element with the
+      GPU adjoint.
+    Rates are the sample's centers x sources x operators per second; `value` is the
+    rate of the mode the headline measures.  The full step's CPU time is the linear
+    extrapolation of that rate to the workload's interactions."""
+    import numpy as np
+    import torch
+
+    from oracle import qbx_oracle as O
+    from paper_1207_4461_amd import flops
+
+    host = host_cpu()
+    rng = np.random.default_rng(0)
+
+    def oracle_at(idx):
+        if mode == "grad":
+            return O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                              pb.oversample, pb.side, pb.kind,
+                                              targets=idx)[1].numpy()
+        if mode in ("split", "splitbwd"):
+            return O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                           pb.oversample, pb.side, pb.kind, gamma=args.gamma,
+                                           targets=idx).numpy()
+        return O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                 pb.side, pb.kind, targets=idx).numpy()
+
+    # calibrate on 2 targets, then size the forward sample
+    t0 = time.perf_counter()
+    oracle_at(np.arange(2))
+    per = (time.perf_counter() - t0) / 2
+    share = args.cpu_seconds / (3.0 if mode == "fwdbwd" else 1.0)
+    n = int(min(pb.n_targets, max(2, share / max(per, 1e-6))))
+    idx = np.sort(rng.choice(pb.n_targets, size=n, replace=False))
+    t0 = time.perf_counter()
+    ref = oracle_at(idx)
+    tc = time.perf_counter() - t0
+    ncent = len(idx) * pb.n_sides
+    fwd_inter = flops.interactions(ncent, pb.n_sources, pb.kind)
+    fwd_rate = fwd_inter / tc
+    if mode == "grad":
+        u = step()[1].cpu().numpy()[:, :, idx]
+    else:
+        u = (step().cpu().numpy()[:, :, idx] if mode in ("split", "splitbwd")
+             else fwd().cpu().numpy()[:, :, idx])
+    err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
+                    for s in range(u.shape[0]) for k in range(u.shape[1])))
+    label = {"grad": "normal derivative", "split": "split forward",
+             "splitbwd": "split forward"}.get(mode, "forward")
+    fwd_sample = (f"{label} at {len(idx)} random targets x {pb.n_sides} sides ({ncent} centers) "
+                  f"against all {pb.n_sources} sources, {tc:.1f} s; GPU/oracle max rel err "
+                  f"{err:.2e}")
+    log(f"cpu oracle {label}: {fwd_rate:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
+
+    # the same forward on one thread (one target, both sides)
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle_at(idx[:1])
+        t1 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(threads)
+    one_core = flops.interactions(pb.n_sides, pb.n_sources, pb.kind) / t1
+    log(f"cpu oracle {label} on 1 thread: {one_core:.3e} interactions/s over {t1:.1f} s")
+
+    inter_step = flops.interactions(pb.n_centers, pb.n_sources, pb.kind)
+    cpu = {"value": fwd_rate, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+           "sample": fwd_sample, "nproc": host["nproc"], "cpu_model": host["cpu_model"],
+           "mode": label, "fwd_value": fwd_rate, "one_thread_fwd_value": one_core}
+    if mode == "fwdbwd":
+        panel = int(rng.integers(0, pb.n_panels))
+        t0 = time.perf_counter()
+        rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                       pb.cotangent, panels=[panel])
+        tb = time.perf_counter() - t0
+        # pairs of the restricted loss: the panel's centers against all sources, every
+        # other center against the panel's sources
+        qs = 16 * pb.oversample
+        pairs = (16 * pb.n_sides * pb.n_sources
+                 + (pb.n_targets - 16) * pb.n_sides * qs)
+        bwd_inter = pairs * pb.n_kinds
+        gd, gn = gpu_vjp()
+        gd = gd.cpu().numpy().reshape(pb.n_kinds, -1, 16)[:, panel]
+        gn = gn.cpu().numpy()[panel]
+        rd = rd.reshape(pb.n_kinds, -1, 16)[:, panel]
+        ed = float(np.abs(gd - rd).max() / np.abs(rd).max())
+        en = float(np.abs(gn - rn[panel]).max() / np.abs(rn[panel]).max())
+        rate = bwd_inter / tb
+        log(f"cpu oracle forward+backward: {rate:.3e} interactions/s over {tb:.1f} s, parity "
+            f"density {ed:.2e} nodes {en:.2e}")
+        cpu.update({
+            "value": rate, "mode": "forward+backward",
+            "sample": (f"forward+backward: the oracle's gradient restricted to panel {panel} "
+                       f"(its {16 * pb.n_sides} centers x all {pb.n_sources} sources, and the "
+                       f"other {(pb.n_targets - 16) * pb.n_sides} centers x its {qs} sources), "
+                       f"{tb:.1f} s; GPU/oracle max rel err on that panel: density "
+                       f"{ed:.2e}, nodes {en:.2e}. Forward: {fwd_sample}"),
+            "bwd_parity": {"panel": panel, "density": ed, "nodes": en}})
+    cpu["extrapolation"] = (f"linear in interactions: the full step ({inter_step:.3e} "
+                            f"interactions) would take {inter_step / cpu['value']:.0f} s on "
+                            f"these {threads} threads, {inter_step / one_core:.0f} s "
+                            f"(forward only) on one")
+    return cpu
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,46 +388,10 @@ def main():
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     if args.cpu_baseline:
-        from oracle import qbx_oracle as O
-
-        rng = np.random.default_rng(0)
-        # calibrate on 2 targets, then size the sample for about --cpu-seconds
-        def oracle_at(idx):
-            if mode == "grad":
-                return O.layer_potential_gradient(pb.nodes, pb.density, pb.k, pb.p, pb.r,
-                                                  pb.oversample, pb.side, pb.kind,
-                                                  targets=idx)[1].numpy()
-            if mode in ("split", "splitbwd"):
-                return O.layer_potential_split(pb.nodes, pb.density, pb.k, pb.p, pb.r,
-                                               pb.oversample, pb.side, pb.kind, gamma=args.gamma,
-                                               targets=idx).numpy()
-            return O.layer_potential(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
-                                     pb.side, pb.kind, targets=idx).numpy()
-
-        t0 = time.perf_counter()
-        oracle_at(np.arange(2))
-        per = (time.perf_counter() - t0) / 2
-        n = int(min(pb.n_targets, max(2, args.cpu_seconds / max(per, 1e-6))))
-        idx = np.sort(rng.choice(pb.n_targets, size=n, replace=False))
-        t0 = time.perf_counter()
-        ref = oracle_at(idx)
-        tc = time.perf_counter() - t0
-        ncent = len(idx) * pb.n_sides
-        cpu_inter = flops.interactions(ncent, pb.n_sources, pb.kind)
-        if mode == "grad":
-            u = step()[1].cpu().numpy()[:, :, idx]
-        else:
-            u = (step().cpu().numpy()[:, :, idx] if mode in ("split", "splitbwd")
-                 else fwd().cpu().numpy()[:, :, idx])
-        err = float(max(np.abs(u[s, k] - ref[s, k]).max() / np.abs(ref[s, k]).max()
-                        for s in range(u.shape[0]) for k in range(u.shape[1])))
-        cpu = {"value": cpu_inter / tc, "unit": "interactions/s", "cores": torch.get_num_threads(),
-               "kind": "oracle",
-               "sample": f"{ {'grad': 'normal derivative', 'split': 'split forward', 'splitbwd': 'split forward'}.get(mode, 'forward')} at "
-                         f"{len(idx)} random targets x {pb.n_sides} sides "
-                         f"({ncent} centers) against all {pb.n_sources} sources, "
-                         f"{tc:.1f} s; GPU/oracle max rel err on the sample {err:.2e}"}
-        log(f"cpu oracle: {cpu_inter / tc:.3e} interactions/s over {tc:.1f} s, parity {err:.2e}")
+        cpu = cpu_baseline(args, mode, pb, fwd, step,
+                           lambda: qbx.layer_potential_vjp(nodes, dens, cot, pb.k, pb.p, pb.r,
+                                                           pb.oversample, pb.side, pb.kind,
+                                                           workspace=ws))
 
     out = {
         "metric": METRIC if mode not in ("split", "splitbwd") else SPLIT_METRIC,
