@@ -11,10 +11,12 @@ Two regimes (z = k*rho > 0):
   A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
   (used when every lane of a wavefront is that far), and a third, shorter still,
   in s = (ZV/z)^2 serves z >= ZV (again when every lane of the wavefront is).
-* the phase e^{i(z - pi/4)} = T_n e^{ir}: n = rint(z N / 2 pi), r = z - 2 pi n / N by a
-  three-part Cody-Waite reduction, T_n = e^{i(2 pi n/N - pi/4)} from a table of N
-  entries (40-digit values rounded once), and sin r, cos r as polynomials in r^2
-  interpolated at Chebyshev points of [0, R_TRIG^2].
+* the phase with the amplitude's constant, sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir}:
+  n = rint(z N / 2 pi), r = z - 2 pi n / N by a three-part Cody-Waite reduction,
+  T_n = sqrt(2/pi) e^{i(2 pi n/N - pi/4)} from a table of N entries (40-digit values
+  rounded once; the factor sqrt(2/pi) of the amplitude sqrt(2/(pi z)) rides in the
+  table, so the kernels multiply by 1/sqrt(z) only), and sin r, cos r as
+  polynomials in r^2 interpolated at Chebyshev points of [0, R_TRIG^2].
 * Z1 <= z < Z0: the entire functions J_0, J_1, R_0 = Y_0 - (2/pi) L J_0 and
   R_1 = Y_1 + 2/(pi z) - (2/pi) L J_1, L = ln(z/2) + gamma (the log terms of
   DLMF 10.8.1/10.8.2 split off), each interpolated at Chebyshev points of [Z1, Z0]
@@ -45,7 +47,7 @@ ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
 ZV = 60.0
 DEG_VFAR = 4      # degree in s = (ZV/z)^2 of the fits for z >= ZV
-PHASE_N = 256     # phase table entries e^{i(2 pi n/N - pi/4)}
+PHASE_N = 256     # phase table entries sqrt(2/pi) e^{i(2 pi n/N - pi/4)}
 R_TRIG = 0.01228  # reduced argument bound (pi/N plus the reduction's rounding)
 DEG_SIN = 3       # degree in r^2 of sin(r)/r
 DEG_COS = 3       # degree in r^2 of cos(r)
@@ -254,9 +256,10 @@ def main():
         rem = rem - hi
     parts.append(float(rem))
     phase = []
+    amp = mpmath.sqrt(2 / mpmath.pi)
     for n in range(PHASE_N):
         a = n * delta - mpmath.pi / 4
-        phase += [float(mpmath.cos(a)), float(mpmath.sin(a))]
+        phase += [float(amp * mpmath.cos(a)), float(amp * mpmath.sin(a))]
     # sin(r)/r and cos(r) as polynomials in u = r^2 for |r| <= R_TRIG (just past
     # pi/N, the bound of the reduced argument): Chebyshev interpolation in u at
     # 40 digits, degrees DEG_SIN and DEG_COS
@@ -288,9 +291,10 @@ def main():
         sv, cv = r * horner(sin_c, u), horner(cos_c, u)
         er = phase[2 * i] * cv - phase[2 * i + 1] * sv
         ei = phase[2 * i] * sv + phase[2 * i + 1] * cv
-        ref = mpmath.exp(1j * (mpmath.mpf(z) - mpmath.pi / 4))
-        worst_phase = max(worst_phase, abs(complex(er, ei) - complex(ref)))
-    print(f"phase e^(i(z - pi/4)) error for 6 <= z <= 4e5 (double evaluation): {worst_phase:.3e}")
+        ref = amp * mpmath.exp(1j * (mpmath.mpf(z) - mpmath.pi / 4))
+        worst_phase = max(worst_phase, abs(complex(er, ei) - complex(ref)) / float(amp))
+    print(f"phase sqrt(2/pi) e^(i(z - pi/4)) relative error for 6 <= z <= 4e5 (double "
+          f"evaluation): {worst_phase:.3e}")
 
     out = []
     out.append("// Generated by gen_seed_coeffs.py -- do not edit.\n")

@@ -430,7 +430,7 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
   const double g2 = gamma * gamma;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
   timer_begin(6, stream);
   e = launch_split_near(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
@@ -464,7 +464,7 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
   e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
   if (e != hipSuccess) return device_fail(e, "order-weighted table kernel");
@@ -494,7 +494,7 @@ int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* densi
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
   e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
   if (e != hipSuccess) return device_fail(e, "cotangent kernel");

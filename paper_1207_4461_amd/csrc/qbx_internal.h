@@ -149,7 +149,10 @@ hipError_t launch_gradient_principal_value(int T, int nk, int side, int kind, co
                                            const double* grad, const double* dn,
                                            double* grad_pv, double* dn_pv, hipStream_t s);
 // ---- split forward (qbx_split.hip) ----
-hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s);
+// per panel {b_x, b_y, rad2, source radius}: the near relation's mean and squared
+// node radius, and max over the panel's sources of |x' - b|
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4* geo,
+                               double4* bnd, hipStream_t s);
 // partial [nk][Mc]: QBX sums over the sources of near panels
 hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
                              const CenterRec* ctr, const double* jtab, const double4* bnd,

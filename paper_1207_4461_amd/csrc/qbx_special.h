@@ -22,9 +22,10 @@ namespace qbx {
 //    when every active lane of the wavefront has z >= ZF = 20 (a wave-uniform
 //    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead,
 //    and when every lane has z >= ZV = 60 the shortest, in s = (ZV/z)^2;
-//    e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta), delta = 2 pi / 256,
-//    r = z - n delta by a three-part Cody-Waite reduction (|r| <= delta / 2),
-//    T_n = e^{i(n delta - pi/4)} from a 256-entry table gathered per lane, and
+//    sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta),
+//    delta = 2 pi / 256, r = z - n delta by a three-part Cody-Waite reduction
+//    (|r| <= delta / 2), T_n = sqrt(2/pi) e^{i(n delta - pi/4)} from a 256-entry
+//    table gathered per lane (the amplitude's constant rides in the table), and
 //    short polynomials for sin r / r and cos r; the phase of H_1 is that of H_0
 //    turned by -pi/2.
 //  * z < Z0: Y_nu = (2/pi)(ln(z/2) + gamma) J_nu - nu 2/(pi z) + R_nu with J_nu, R_nu
@@ -78,13 +79,33 @@ __host__ __device__ __forceinline__ D4 horner4(const double* __restrict__ c, dou
   return r;
 }
 
-// two interleaved polynomials c[2i + 0..1], i < LEN, same scheme; the first
-// stops at degree LA - 1 (its higher slots are zero padding)
+// horner4 with the four constant terms given (c0), for callers that keep them in
+// vector registers across a loop: each polynomial then starts with one fused
+// multiply-add instead of two register copies and one
+template <int LEN>
+__host__ __device__ __forceinline__ D4 horner4_c0(const double* __restrict__ c, double x,
+                                                  const D4& c0) {
+  D4 r = c0;
+  double pw = x;
+#pragma unroll
+  for (int i = 1; i < LEN; ++i) {
+    r.a = fma(c[4 * i], pw, r.a);
+    r.b = fma(c[4 * i + 1], pw, r.b);
+    r.c = fma(c[4 * i + 2], pw, r.c);
+    r.d = fma(c[4 * i + 3], pw, r.d);
+    if (i + 1 < LEN) pw *= x;
+  }
+  return r;
+}
+
+// two interleaved polynomials c[2i + 0..1], i < LEN, same scheme, with the
+// constant terms a0, b0; the first stops at degree LA - 1 (its higher slots are
+// zero padding)
 template <int LEN, int LA>
-__host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, double x, double& a,
-                                                 double& b) {
-  a = c[0];
-  b = c[1];
+__host__ __device__ __forceinline__ void horner2(const double* __restrict__ c, double x, double a0,
+                                                 double b0, double& a, double& b) {
+  a = a0;
+  b = b0;
   double pw = x;
 #pragma unroll
   for (int i = 1; i < LEN; ++i) {
@@ -101,10 +122,13 @@ static __constant__ __align__(16) double g_phase_table[2 * seed::kPhaseN] = {
     QBX_PHASE_TABLE_VALUES};
 
 // H_0, H_1 from the amplitude functions P0, Q0, P1, Q1 of the asymptotic form:
-// with E = sqrt(2/(pi z)) e^{i(z - pi/4)}, H_0 = E (P0 + i Q0), H_1 = E (Q1 - i P1)
+// with E = sqrt(2/(pi z)) e^{i(z - pi/4)}, H_0 = E (P0 + i Q0), H_1 = E (Q1 - i P1).
+// sn0, cn0: the constant terms of the sin r / r and cos r polynomials
+// (cf[kTRIGOff], cf[kTRIGOff + 1]), passed in so that loops can hold them in
+// vector registers.
 __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, double P1, double Q1,
-                                             const double* __restrict__ cf) {
-  constexpr double kSqrtTwoOverPi = 0.79788456080286535588;
+                                             const double* __restrict__ cf, double sn0,
+                                             double cn0) {
   H01 h;
   // e^{i(z - pi/4)} = T_n e^{ir}
   const double n = rint(z * seed::kInvDelta);
@@ -114,11 +138,11 @@ __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, dou
   const double* __restrict__ T = g_phase_table + 2 * ((int)n & (seed::kPhaseN - 1));
   const double tc = T[0], ts = T[1];
   double sn, cs;
-  horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn, cs);
+  horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn0, cn0, sn, cs);
   sn *= r;
   double er = fma(tc, cs, -ts * sn);
   double ei = fma(tc, sn, ts * cs);
-  const double A = kSqrtTwoOverPi * rsqrt_refined(z);
+  const double A = rsqrt_refined(z);   // sqrt(2/pi) is in T_n
   er *= A;
   ei *= A;
   h.h0r = fma(er, P0, -ei * Q0);     // E (P0 + i Q0)
@@ -135,7 +159,43 @@ __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, dou
 __device__ __forceinline__ H01 hankel01_vfar(double z, double iz, const double* __restrict__ cf) {
   const double t = seed::kZV * iz;
   const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
-  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf);
+  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf, cf[seed::kTRIGOff],
+                       cf[seed::kTRIGOff + 1]);
+}
+
+// A copy of a wave-uniform double in a vector register that the compiler cannot
+// see through, so that it stays there across a loop: a loop-invariant addend of a
+// fused multiply-add (the constant term of a polynomial) is then read in place
+// instead of being copied in by two v_mov instructions at every use.
+__device__ __forceinline__ double in_vgpr(double s) {
+  double v;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
+// The constant terms of the z >= kZV fits and of the phase polynomials, held in
+// vector registers by loops over many pairs (12 VGPRs)
+struct VfarC0 {
+  D4 pq;
+  double sn, cn;
+};
+
+__device__ __forceinline__ VfarC0 vfar_c0(const double* __restrict__ cf) {
+  VfarC0 c;
+  c.pq.a = in_vgpr(cf[seed::kVFAROff]);
+  c.pq.b = in_vgpr(cf[seed::kVFAROff + 1]);
+  c.pq.c = in_vgpr(cf[seed::kVFAROff + 2]);
+  c.pq.d = in_vgpr(cf[seed::kVFAROff + 3]);
+  c.sn = in_vgpr(cf[seed::kTRIGOff]);
+  c.cn = in_vgpr(cf[seed::kTRIGOff + 1]);
+  return c;
+}
+
+// hankel01_vfar with t = kZV / z given and the constant terms from c0
+__device__ __forceinline__ H01 hankel01_vfar_c0(double z, double t, const double* __restrict__ cf,
+                                                const VfarC0& c0) {
+  const D4 pq = horner4_c0<seed::kVFARLen>(cf + seed::kVFAROff, t * t, c0.pq);
+  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf, c0.sn, c0.cn);
 }
 
 // iz = 1/z (callers already hold it); cf = the coefficient table seed::kTable
@@ -169,7 +229,7 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
       P1 = pq.c;
       Q1 = t * pq.d;
     }
-    h = hankel01_asym(z, P0, Q0, P1, Q1, cf);
+    h = hankel01_asym(z, P0, Q0, P1, Q1, cf, cf[seed::kTRIGOff], cf[seed::kTRIGOff + 1]);
   } else {
     const double L = log(0.5 * z) + kEuler;
     double J0, J1, R0, R1;   // Y0 = (2/pi) L J0 + R0,  Y1 = (2/pi)(L J1 - 1/z) + R1

@@ -54,6 +54,23 @@ __global__ __launch_bounds__(256) void k_panel_bounds(int NP, const double* __re
   bnd[m] = make_double4(bx, by, r2, 0.0);
 }
 
+// bnd[m].w = max over the panel's sources of |x' - b_m|: with it the far pass
+// bounds |x - x'| from below for a whole panel at once
+__global__ __launch_bounds__(256) void k_panel_source_radius(int NP, int qs,
+                                                             const double4* __restrict__ geo,
+                                                             double4* __restrict__ bnd) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= NP) return;
+  const double4 b = bnd[m];
+  double r2 = 0.0;
+  for (int j = 0; j < qs; ++j) {
+    const double4 g = geo[(size_t)m * qs + j];
+    const double dx = g.x - b.x, dy = g.y - b.y;
+    r2 = fmax(r2, fma(dx, dx, dy * dy));
+  }
+  bnd[m].w = sqrt(r2);
+}
+
 // partial[kk][ci]: QBX sums of center ci over the sources of near panels
 template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_split_near(const double4* __restrict__ geo,
@@ -100,8 +117,36 @@ __global__ __launch_bounds__(256) void k_split_near(const double4* __restrict__ 
   }
 }
 
+// one far pair: w sigma H_0 (S) and w mu H_1 (x - x').n' / rho (D; the factor k is
+// applied once per sum), with the pair's weighted densities wS (S) and wD (D)
+template <bool kS, bool kD>
+__device__ __forceinline__ void far_accumulate_q(const double2& wS, const double2& wD,
+                                                 const double4& g, double dx, double dy,
+                                                 double ir, const H01& h, double& sr, double& si,
+                                                 double& dr, double& di) {
+  if (kS) {
+    sr = fma(wS.x, h.h0r, fma(-wS.y, h.h0i, sr));
+    si = fma(wS.x, h.h0i, fma(wS.y, h.h0r, si));
+  }
+  if (kD) {
+    const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
+    const double wr = wD.x * f, wi = wD.y * f;
+    dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
+    di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+  }
+}
+
 // partial[sp][kk][t]: direct sums of target t over the far sources of panels
 // [sp * ppw, (sp + 1) * ppw); wave gw = sp * n_tb + tb covers targets tb*64 ..
+// Per (wave, far panel) a vote: is every active lane at least kZV / k from every
+// source of the panel (the distance to the panel's mean less its source radius
+// bnd.w, with a relative margin for rounding)?  If so (about 84% of the pairs at
+// 4096 panels) the panel's pairs take the shortest seed fits with no per-pair
+// vote: the coefficient table is addressed once per panel, so its loads stay in
+// scalar registers through the panel's loop, and the fits' constant terms are
+// copied into vector registers once per panel.  Otherwise each pair votes as in
+// hankel01.  (Staging the source panels in LDS instead of reading them by scalar
+// loads was measured 4% slower: it costs vector registers the loop needs.)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ geo,
                                                    const double2* __restrict__ dens, int N, int qs,
@@ -126,32 +171,43 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
   const int p0 = sp * ppw;
   const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
+  const double kt = seed::kZV * inv_k;          // kZV / z = kt / rho
+  const double zv = seed::kZV * (1.0 + 1e-12);
+  const double2* __restrict__ densD = dens + (kS ? (size_t)N : 0);
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
   for (int pm = p0; pm < p1; ++pm) {
-    const bool far = valid && !panels_near(bt, bnd[pm], g2);
+    const double4 bp = bnd[pm];
+    const bool far = valid && !panels_near(bt, bp, g2);
     if (far) {
       const int j0 = pm * qs;
-      for (int b = 0; b < qs; ++b) {
-        const int z0 = opaque_zero();
-        const double* __restrict__ cf = g_seed_table + z0;
-        const int j = j0 + b;
-        const double4 g = geo[j];
-        const double dx = tx - g.x, dy = ty - g.y;
-        const double rho2 = fma(dx, dx, dy * dy);
-        const double ir = rsqrt_refined(rho2);
-        const double z = k * (rho2 * ir), iz = ir * inv_k;
-        const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
-        if (kS) {
-          const double2 w = dens[j];
-          sr = fma(w.x, h.h0r, fma(-w.y, h.h0i, sr));
-          si = fma(w.x, h.h0i, fma(w.y, h.h0r, si));
+      const double ex = tx - bp.x, ey = ty - bp.y;
+      const double e2 = fma(ex, ex, ey * ey);
+      const double lo = e2 * rsqrt_refined(e2) - bp.w;
+      if (__all(k * lo >= zv)) {
+        const double* __restrict__ cf = g_seed_table + opaque_zero();
+        const VfarC0 c0 = vfar_c0(cf);
+        for (int b = 0; b < qs; ++b) {
+          const int j = j0 + b;
+          const double4 g = geo[j];
+          const double dx = tx - g.x, dy = ty - g.y;
+          const double rho2 = fma(dx, dx, dy * dy);
+          const double ir = rsqrt_refined(rho2);
+          const double z = k * (rho2 * ir);
+          const H01 h = hankel01_vfar_c0(z, kt * ir, cf, c0);
+          far_accumulate_q<kS, kD>(dens[j], densD[j], g, dx, dy, ir, h, sr, si, dr, di);
         }
-        if (kD) {
-          const double2 w = dens[(kS ? (size_t)N : 0) + j];
-          const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
-          const double wr = w.x * f, wi = w.y * f;
-          dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
-          di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+      } else {
+        for (int b = 0; b < qs; ++b) {
+          const int z0 = opaque_zero();
+          const double* __restrict__ cf = g_seed_table + z0;
+          const int j = j0 + b;
+          const double4 g = geo[j];
+          const double dx = tx - g.x, dy = ty - g.y;
+          const double rho2 = fma(dx, dx, dy * dy);
+          const double ir = rsqrt_refined(rho2);
+          const double z = k * (rho2 * ir), iz = ir * inv_k;
+          const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
+          far_accumulate_q<kS, kD>(dens[j], densD[j], g, dx, dy, ir, h, sr, si, dr, di);
         }
       }
     }
@@ -292,6 +348,8 @@ __global__ __launch_bounds__(256) void k_split_gfar(int T, int nk, int n_sides,
 
 // partial[sp][kk][j]: sum over the targets t of far panels in split sp of
 // Gf_t K_far(t, j); lanes are 64 consecutive sources, targets wave-uniform
+// The vote of k_split_far per (wave, target panel); here the targets are the
+// panel's nodes, so its node radius bounds them.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far_adj(
     const double4* __restrict__ geo, int N, int qs, const double* __restrict__ nodes, int T,
@@ -315,31 +373,58 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   const int p0 = sp * ppw;
   const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
+  const double kt = seed::kZV * inv_k;          // kZV / z = kt / rho
+  const double zv = seed::kZV * (1.0 + 1e-12);
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  // one far pair: the cotangent weights of target t times H_0 (S) and
+  // H_1 (x - x').n' / rho (D)
+  auto add = [&](int t, double dx, double dy, double ir, const H01& h) {
+    int kk = 0;
+    if (kS) {
+      const double2 Gt = Gf[(size_t)(kk++) * T + t];
+      sr = fma(Gt.x, h.h0r, fma(-Gt.y, h.h0i, sr));
+      si = fma(Gt.x, h.h0i, fma(Gt.y, h.h0r, si));
+    }
+    if (kD) {
+      const double2 Gt = Gf[(size_t)kk * T + t];
+      const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
+      const double wr = Gt.x * f, wi = Gt.y * f;
+      dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
+      di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+    }
+  };
   for (int mt = p0; mt < p1; ++mt) {
-    const bool far = valid && !panels_near(bnd[mt], bj, g2);
+    const double4 bt = bnd[mt];
+    const bool far = valid && !panels_near(bt, bj, g2);
     if (far) {
-      for (int a = 0; a < kQ; ++a) {
-        const int t = mt * kQ + a;
-        const int z0 = opaque_zero();
-        const double* __restrict__ cf = g_seed_table + z0;
-        const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
-        const double rho2 = fma(dx, dx, dy * dy);
-        const double ir = rsqrt_refined(rho2);
-        const double z = k * (rho2 * ir), iz = ir * inv_k;
-        const H01 h = __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf);
-        int kk = 0;
-        if (kS) {
-          const double2 Gt = Gf[(size_t)(kk++) * T + t];
-          sr = fma(Gt.x, h.h0r, fma(-Gt.y, h.h0i, sr));
-          si = fma(Gt.x, h.h0i, fma(Gt.y, h.h0r, si));
+      // every pair of the active lanes with this target panel at z >= kZV: the
+      // distance to the panel's mean less its node radius (the targets are the
+      // nodes) bounds |x - x'| from below
+      const double ex = g.x - bt.x, ey = g.y - bt.y;
+      const double e2 = fma(ex, ex, ey * ey);
+      const double lo = e2 * rsqrt_refined(e2) - bt.z * rsqrt_refined(bt.z);
+      if (__all(k * lo >= zv)) {
+        const double* __restrict__ cf = g_seed_table + opaque_zero();
+        const VfarC0 c0 = vfar_c0(cf);
+        for (int a = 0; a < kQ; ++a) {
+          const int t = mt * kQ + a;
+          const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
+          const double rho2 = fma(dx, dx, dy * dy);
+          const double ir = rsqrt_refined(rho2);
+          const double z = k * (rho2 * ir);
+          add(t, dx, dy, ir, hankel01_vfar_c0(z, kt * ir, cf, c0));
         }
-        if (kD) {
-          const double2 Gt = Gf[(size_t)kk * T + t];
-          const double f = fma(dx, g.z, dy * g.w) * ir;   // (x - x').n' / rho
-          const double wr = Gt.x * f, wi = Gt.y * f;
-          dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
-          di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+      } else {
+        for (int a = 0; a < kQ; ++a) {
+          const int t = mt * kQ + a;
+          const int z0 = opaque_zero();
+          const double* __restrict__ cf = g_seed_table + z0;
+          const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
+          const double rho2 = fma(dx, dx, dy * dy);
+          const double ir = rsqrt_refined(rho2);
+          const double z = k * (rho2 * ir), iz = ir * inv_k;
+          add(t, dx, dy, ir,
+              __all(z >= seed::kZV) ? hankel01_vfar(z, iz, cf) : hankel01(z, iz, cf));
         }
       }
     }
@@ -657,8 +742,11 @@ hipError_t launch_split_gradient(const Dims& d, const double* nodes, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s) {
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4* geo,
+                               double4* bnd, hipStream_t s) {
   hipLaunchKernelGGL(k_panel_bounds, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, nodes, bnd);
+  hipLaunchKernelGGL(k_panel_source_radius, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.qs,
+                     geo, bnd);
   return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ forward pair (one center, one source, order p):
   seed H0, H1   60/z and (60/z)^2 (2), 4 interleaved degree-4 polynomials (35),
                 Q scaling (2), phase: reduction by 2 pi/256 (8), degree-3 sin/cos
                 polynomials in r^2 (16), times the table entry (6), 1/sqrt(z) and
-                the amplitude (4), rotation by P + iQ (12)                   =  85
+                the amplitude (3: the table holds sqrt(2/pi)), rotation by
+                P + iQ (12)                                                  =  84
                 (waves with a lane at 20 <= z < 60 run degree-6 fits, 103; the long
                 fits of 6 <= z < 20 cost 157: so the counts are lower bounds)
   recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
@@ -24,11 +25,11 @@ forward pair (one center, one source, order p):
   accumulation  w sigma K (8 per kind)
 
 Totals (derived in flops_forward_pair below):
-  S:   111 + 12 p        D:   130 + 16 p        S+D: 144 + 23 p
+  S:   110 + 12 p        D:   129 + 16 p        S+D: 143 + 23 p
 """
 from __future__ import annotations
 
-SEED = 85   # H_0, H_1 on the common branch (see above)
+SEED = 84   # H_0, H_1 on the common branch (see above)
 
 
 def flops_forward_pair(p: int, kind: int) -> int:
@@ -181,12 +182,13 @@ def flops_grad_pair(p: int, kind: int) -> int:
 def flops_far_pair(kind: int) -> int:
     """Far pass of the split forward, per (target, source) pair on a far panel (its
     density adjoint has the same count, with the cotangent weight in place of q):
-    x - x' (2), rho (4), 1/rho (1), z and 1/z (2), seed H0, H1 on the branch a wave
-    takes when all its lanes have k rho >= 60 (85: the 53 flops of the degree-6 fits
-    become 35 with degree 4); S: w sigma H_0 (8); D: (x - x').n'/rho (4), w mu times
-    it (2), times H_1 (8).  S: 102, D: 108, S+D: 116.  Waves with a lane nearer run
-    the z >= 20 fits, 18 flops more, so the count is a lower bound."""
-    f = 2 + 4 + 1 + 2 + SEED
+    x - x' (2), rho (4), 1/rho (1), z (1; 60/z is the seed's first multiply, of 1/rho),
+    seed H0, H1 on the branch a wave takes when all its lanes have k rho >= 60 (84:
+    the 53 flops of the degree-6 fits become 35 with degree 4); S: w sigma H_0 (8);
+    D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).  S: 100, D: 106,
+    S+D: 114.  Waves with a lane nearer run the z >= 20 fits, 18 flops more, so the
+    count is a lower bound."""
+    f = 2 + 4 + 1 + 1 + SEED
     if kind & 1:
         f += 8
     if kind & 2:
