@@ -311,11 +311,18 @@ size_t qbx_batched_workspace_bytes(const qbx_batch_item* items, int n_items, int
 size_t qbx_batched_tape_bytes(const qbx_batch_item* items, int n_items);
 
 /* Forward for every contour of the batch.  The source grids and centers of all
- * contours are built by one launch; the pair work of all contours runs in ONE
- * persistent launch whose wavefronts take (contour, center) tasks, most
- * expensive contours first, from a device counter.  tape: nullable, the
- * batch's tape for qbx_layer_potential_batched_adjoint (qbx_batched_tape_bytes).
- * items is a HOST array; it is copied into the workspace. */
+ * contours are built by one launch; the pair work runs in one persistent launch
+ * per (kind, p) class present in the batch (each compiled for its class), whose
+ * wavefronts take (contour, center) tasks, most expensive contours first, from
+ * the class's device counter.  The classes' launches are independent: they are
+ * forked from `stream` onto up to three library streams of the current device
+ * (default priority; created on the device's first batched call and kept until
+ * the process ends) and joined back to `stream` with events, so that they
+ * overlap and one class's tail is filled by the next.  The call stays ordered
+ * on `stream` like every other; the stream must belong to the current device.
+ * tape: nullable, the batch's tape for qbx_layer_potential_batched_adjoint
+ * (qbx_batched_tape_bytes).  items is a HOST array; it is copied into the
+ * workspace. */
 int qbx_layer_potential_batched(const qbx_batch_item* items, int n_items, const double* nodes,
                                 const double* density, double* out, double* tape, int oversample,
                                 void* ws, size_t ws_bytes, hipStream_t stream);
@@ -326,7 +333,8 @@ int qbx_layer_potential_batched(const qbx_batch_item* items, int n_items, const 
  * (contour, center split, 64-source chunk) tasks.  tape NULL with grad_nodes:
  * the fused pass, one persistent launch per class whose workgroups take
  * (contour, center block, source block) tiles; tape NULL with only
- * grad_density: the source-major pass alone.  Reproducible bit for bit. */
+ * grad_density: the source-major pass alone.  The classes' launches overlap as
+ * in the forward.  Reproducible bit for bit. */
 int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items,
                                         const double* nodes, const double* density,
                                         const double* cotangent, const double* tape,

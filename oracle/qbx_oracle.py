@@ -699,21 +699,6 @@ def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float
             for key, val in leaves.items()}
 
 
-def graf_min_ratio(nodes, k, p, r=0.5, oversample=4, side=EXTERIOR) -> float:
-    """min over centers and sources of rho_ij / R_i (Graf's condition needs > 1)."""
-    with torch.no_grad():
-        nodes = _as_t(nodes, _F64)
-        src = source_grid(nodes, oversample)
-        best = math.inf
-        for s in sides_of(side):
-            ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
-            vx = src["x"][None, :] - ctr["cx"][:, None]
-            vy = src["y"][None, :] - ctr["cy"][:, None]
-            rho = torch.sqrt(vx * vx + vy * vy)
-            best = min(best, float((rho / ctr["R"][:, None]).min()))
-        return best
-
-
 def qbx_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
                kind_name: str = "S") -> np.ndarray:
     """Dense QBX operator A [T, P*16] (targets x coarse density) for one side and kind.

@@ -15,11 +15,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqbx.so")
-SOURCES = ["qbx_batched_fwd1.hip", "qbx_batched_fwd0.hip", "qbx_batched_adj.hip",
-           "qbx_batched_fused.hip",
+# (source, object name, extra flags), slowest first; the batched forward source is
+# compiled once per mode
+SOURCES = [("qbx_batched_fwd.hip", "qbx_batched_fwd1", ["-DQBX_FWD_MODE=1"]),
+           ("qbx_batched_fwd.hip", "qbx_batched_fwd0", ["-DQBX_FWD_MODE=0"]),
+           "qbx_batched_adj.hip", "qbx_batched_fused.hip",
            "qbx_adjoint.hip", "qbx_forward.hip", "qbx_explicit.hip", "qbx_batched.hip",
            "qbx_geometry.hip", "qbx_split.hip", "qbx_solve.hip", "qbx_noalloc.hip",
-           "qbx_api.cpp", "qbx_autotune.cpp"]   # slowest first
+           "qbx_api.cpp", "qbx_autotune.cpp"]
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [
@@ -47,11 +50,19 @@ def _up_to_date(src: str, obj: str) -> bool:
     return all(os.path.getmtime(d) < t for d in deps)
 
 
-def _compile(src: str, verbose: bool, force: bool = True) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _entry(e):
+    """(source, object name, extra flags) of a SOURCES entry."""
+    if isinstance(e, str):
+        return e, os.path.splitext(e)[0], []
+    return e
+
+
+def _compile(entry, verbose: bool, force: bool = True) -> str:
+    src, name, flags = _entry(entry)
+    obj = os.path.join(BUILD, name + ".o")
     if not force and _up_to_date(src, obj):
         return obj
-    cmd = [_hipcc(), "-x", "hip", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), "-x", "hip", *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,7 +74,7 @@ def _compile(src: str, verbose: bool, force: bool = True) -> str:
 def build(verbose: bool = False, force: bool = True) -> str:
     """Compile every source (force=False: only those older than their inputs) and link."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, _entry(s)[0]))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, force), srcs))
     tmp = LIB + ".tmp"

@@ -16,6 +16,7 @@
 // per-center and per-source steps run as ordinary grids over all contours'
 // panels, centers or sources.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -399,23 +400,101 @@ static int zero_counters(const BatchPlan& P, void* ws, hipStream_t s) {
   return e == hipSuccess ? QBX_OK : device_fail(e, "counter reset kernel");
 }
 
+// Concurrent classes.  The (kind, p) classes of one pass are independent (disjoint
+// contours, their own task counters and output ranges), so they are spread over
+// the caller's stream and up to kAuxStreams library streams of the current device
+// (default priority), forked from the caller's stream and joined back to it with
+// events.  Each class's persistent kernel fills the GPU on its own; the next
+// class's workgroups take compute units as its tail frees them, instead of every
+// class's tail leaving the GPU idle in turn.  Results do not depend on it: every
+// sum keeps its fixed order.  The streams and events are created on a device's
+// first batched call and kept until the process ends; the enqueueing is
+// serialised by a lock, so calls from several host threads stay well formed.
+namespace {
+constexpr int kAuxStreams = 3;
+constexpr int kMaxDevices = 64;
+struct ClassStreams {
+  hipStream_t aux[kAuxStreams];
+  hipEvent_t fork, join[kAuxStreams];
+  bool ready = false;
+};
+ClassStreams g_class_streams[kMaxDevices];
+std::mutex g_class_streams_mu;
+
+// classes are launched on lane c % (1 + kAuxStreams): lane 0 is the caller's stream
+struct ClassFork {
+  ClassStreams* cs = nullptr;
+  hipStream_t caller;
+  int lanes = 1;
+  std::unique_lock<std::mutex> lock;
+  hipStream_t stream(size_t c) const {
+    const int l = (int)(c % (size_t)lanes);
+    return l == 0 ? caller : cs->aux[l - 1];
+  }
+};
+
+// fork n_classes over the caller's stream and the library streams
+int class_fork(size_t n_classes, hipStream_t caller, ClassFork* f) {
+  f->caller = caller;
+  f->lanes = 1;
+  if (n_classes < 2) return QBX_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return QBX_OK;   // serial on the caller's stream
+  f->lock = std::unique_lock<std::mutex>(g_class_streams_mu);
+  ClassStreams& cs = g_class_streams[dev];
+  if (!cs.ready) {
+    for (int i = 0; i < kAuxStreams; ++i) {
+      if ((e = hipStreamCreateWithFlags(&cs.aux[i], hipStreamNonBlocking)) != hipSuccess)
+        return device_fail(e, "class stream creation");
+      if ((e = hipEventCreateWithFlags(&cs.join[i], hipEventDisableTiming)) != hipSuccess)
+        return device_fail(e, "class event creation");
+    }
+    if ((e = hipEventCreateWithFlags(&cs.fork, hipEventDisableTiming)) != hipSuccess)
+      return device_fail(e, "class event creation");
+    cs.ready = true;
+  }
+  f->cs = &cs;
+  f->lanes = 1 + (int)std::min<size_t>(kAuxStreams, n_classes - 1);
+  if ((e = hipEventRecord(cs.fork, caller)) != hipSuccess)
+    return device_fail(e, "class fork event");
+  for (int i = 0; i + 1 < f->lanes; ++i)
+    if ((e = hipStreamWaitEvent(cs.aux[i], cs.fork, 0)) != hipSuccess)
+      return device_fail(e, "class fork wait");
+  return QBX_OK;
+}
+
+// the caller's stream waits for every library stream used
+int class_join(ClassFork* f) {
+  for (int i = 0; i + 1 < f->lanes; ++i) {
+    hipError_t e = hipEventRecord(f->cs->join[i], f->cs->aux[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(f->caller, f->cs->join[i], 0);
+    if (e != hipSuccess) return device_fail(e, "class join");
+  }
+  return QBX_OK;
+}
+}  // namespace
+
 static int batch_forward(const BatchPlan& P, double* out, double2* tape, void* ws, hipStream_t s) {
   int rc = zero_counters(P, ws, s);
   if (rc) return rc;
   timer_begin(2, s);
-  for (size_t c = 0; c < P.cls.size(); ++c) {
+  ClassFork f;
+  rc = class_fork(P.cls.size(), s, &f);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  for (size_t c = 0; c < P.cls.size() && e == hipSuccess; ++c) {
     const BatchTasks t = class_tasks(P, ws, c, 0);
-    hipError_t e = launch_forward_batched(
-        tape ? 1 : 0, P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
-        wsp<double2>(ws, P.o_densw), wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab), out,
-        tape, g_batch_grid_scale, s);
-    if (e != hipSuccess) {
-      timer_end(2, s);
-      return device_fail(e, "batched forward kernel");
-    }
+    e = launch_forward_batched(tape ? 1 : 0, P.cls[c].kind, P.cls[c].p, t,
+                               wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_densw),
+                               wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab), out, tape,
+                               g_batch_grid_scale, f.stream(c));
   }
+  rc = class_join(&f);
   timer_end(2, s);
-  return QBX_OK;
+  if (e != hipSuccess) return device_fail(e, "batched forward kernel");
+  return rc;
 }
 
 hipError_t launch_forward_batched_0(int, int, const BatchTasks&, const double4*, const double2*,
@@ -506,25 +585,30 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
   rc = zero_counters(P, ws, stream);
   if (rc) return rc;
   timer_begin(2, stream);
-  for (size_t c = 0; c < P.cls.size(); ++c) {
+  ClassFork f;
+  rc = class_fork(P.cls.size(), stream, &f);
+  if (rc) return rc;
+  hipError_t ea = hipSuccess;
+  for (size_t c = 0; c < P.cls.size() && ea == hipSuccess; ++c) {
     const BatchTasks t = class_tasks(P, ws, c, fused ? 2 : 1);
-    hipError_t ea =
-        fused ? launch_adjoint_fused_batched(P.cls[c].kind, P.cls[c].p, t,
-                                             wsp<double4>(ws, P.o_geo), wsp<double2>(ws, P.o_densw),
-                                             wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
-                                             wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
-                                             wsp<double>(ws, P.o_cpart), g_batch_grid_scale, stream)
-              : launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
-                                       wsp<double2>(ws, P.o_densw),
-                                       wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
-                                       wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
-                                       g_batch_grid_scale, stream);
-    if (ea != hipSuccess) {
-      timer_end(2, stream);
-      return device_fail(ea, "batched adjoint kernel");
-    }
+    const hipStream_t sc = f.stream(c);
+    ea = fused ? launch_adjoint_fused_batched(P.cls[c].kind, P.cls[c].p, t,
+                                              wsp<double4>(ws, P.o_geo),
+                                              wsp<double2>(ws, P.o_densw),
+                                              wsp<CenterRec>(ws, P.o_ctr),
+                                              wsp<double>(ws, P.o_jtab), wsp<double2>(ws, P.o_G),
+                                              wsp<double2>(ws, P.o_spart),
+                                              wsp<double>(ws, P.o_cpart), g_batch_grid_scale, sc)
+               : launch_adjoint_batched(P.cls[c].kind, P.cls[c].p, t, wsp<double4>(ws, P.o_geo),
+                                        wsp<double2>(ws, P.o_densw),
+                                        wsp<CenterRec>(ws, P.o_ctr), wsp<double>(ws, P.o_jtab),
+                                        wsp<double2>(ws, P.o_G), wsp<double2>(ws, P.o_spart),
+                                        g_batch_grid_scale, sc);
   }
+  rc = class_join(&f);
   timer_end(2, stream);
+  if (ea != hipSuccess) return device_fail(ea, "batched adjoint kernel");
+  if (rc) return rc;
   if (fused)
     hipLaunchKernelGGL(k_fused_center_grads_batched, blocks(nC, 256), dim3(256), 0, stream, it,
                        wsp<long long>(ws, P.o_pre_ctr), P.n, nC, wsp<CenterRec>(ws, P.o_ctr),

@@ -218,6 +218,15 @@ def star4096(seed: int = 4) -> Problem:
                         20, BOTH, S_KIND | D_KIND, seed, max_mode=60, with_cotangent=True)
 
 
+def paper80(seed: int = 5) -> Problem:
+    """The size of the paper's one timing (Section 5: a single-layer apply at p = 5, 7680
+    sources, 1280 targets): the Section 4.1 starfish r = 1 + sin(5t)/4 in 80 panels,
+    oversample 6 (Section 4.1's factor), one side, k = 0.5 (the value of Section 4's
+    operator tests; the timing sentence gives none)."""
+    return make_problem("starfish5-80-sec5", star((5, 0.25, -0.5 * math.pi)), 80, 0.5, 5,
+                        EXTERIOR, S_KIND, seed, oversample=6, with_cotangent=True)
+
+
 def random64(seed: int = 3, n_contours: int = 64) -> List[Problem]:
     """64 random star contours r = 1 + sum_{m=2..8} a_m cos(mt+phi_m), a_m~U(0,.05),
     phi_m~U(0,2pi); panels ~U{16..512}; k~U(5,50); p in {8,12,16}; S or D (prob 1/2);
@@ -289,5 +298,5 @@ def small(name: str = "small", n_panels: int = 6, k: float = 3.0, p: int = 5, si
 
 CONFIGS: Dict[str, Callable[..., object]] = {
     "ellipse32": ellipse32, "star256": star256, "star1024": star1024, "random64": random64,
-    "star4096": star4096,
+    "star4096": star4096, "paper80": paper80,
 }
