@@ -40,7 +40,8 @@ gradients of the discrete map:
   (``dirichlet_solve``) and evaluated off the curve (``representation``).
 * Section 5: the near/far split (``layer_potential_split``): QBX only for
   sources on panels near the target's panel, the smooth rule applied directly
-  at the target for all others.
+  at the target for all others; and one stored local expansion serving several
+  nearby targets (``expansion_coefficients``, ``evaluate_expansions``).
 
 Two modes:
 * ``mode="dense"``: every order l evaluated by its own library call
@@ -697,6 +698,65 @@ def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float
     torch.real(torch.conj(g) * out).sum().backward()
     return {key: (val.grad.numpy() if val.grad is not None else np.zeros(tuple(val.shape)))
             for key, val in leaves.items()}
+
+
+# ---------------------------------------------------------------------------
+# Section 5: one local expansion for several nearby targets.  The coefficients of
+# eq. graf-coefficient (and eq. graf-coefficient-dlp) are formed once per center and
+# stored; any target inside a center's disk is then evaluated from them by Section 3.3
+# step 4(c) with its own distance and angle from the center.
+# ---------------------------------------------------------------------------
+def expansion_coefficients(nodes, density, k: float, p: int, r: float = 0.5,
+                           oversample: int = 4, side: int = EXTERIOR, kind: int = S_KIND,
+                           mode: str = "fast"):
+    """Local expansion coefficients a_l, l = -p..p, of every center of the contour (the
+    centers of ``layer_potential``, exterior ones first for BOTH), without the i/4.
+    Returns (a [n_kinds, n_centers, 2p+1] complex, centers [n_centers, 2], radii
+    [n_centers])."""
+    nodes = _as_t(nodes, _F64)
+    density = _as_t(density, _C128)
+    kinds = kinds_of(kind)
+    src = source_grid(nodes, oversample)
+    fine = interpolate_density(density, oversample)
+    dens = {kk: src["w"].to(_C128) * fine[i] for i, kk in enumerate(kinds)}
+    coef, xy, rad = [], [], []
+    for s in sides_of(side):
+        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
+        a = coefficients(src, dens, ctr, k, p, kind, mode)
+        coef.append(torch.stack([a[kk] for kk in kinds]))
+        xy.append(torch.stack([ctr["cx"], ctr["cy"]], dim=-1))
+        rad.append(ctr["R"])
+    return torch.cat(coef, dim=1), torch.cat(xy), torch.cat(rad)
+
+
+def evaluate_expansions(coef, centers, targets, center_index, k: float, p: int,
+                        mode: str = "fast") -> torch.Tensor:
+    """u(x_t) = (i/4) sum_{l=-p..p} a_l J_l(k|x_t - c|) e^{i l arg(x_t - c)} with c the
+    center ``center_index[t]`` (Section 3.3 step 4(c) at a target of the caller's
+    choice inside the center's disk).  coef [n_kinds, n_centers, 2p+1]; returns
+    [n_kinds, n_targets]."""
+    coef = _as_t(coef, _C128)
+    centers = _as_t(centers, _F64)
+    targets = _as_t(targets, _F64)
+    idx = torch.as_tensor(np.asarray(center_index), dtype=torch.long)
+    d = targets - centers[idx]
+    R = torch.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2)
+    theta = torch.atan2(d[:, 1], d[:, 0])
+    return torch.stack([evaluate(coef[i, idx], R, theta, k, p, mode)
+                        for i in range(coef.shape[0])])
+
+
+def assign_centers(centers, radii, targets, slack: float = 1.0) -> np.ndarray:
+    """For every target, the nearest center whose disk holds it (|x - c| <= slack R),
+    or -1 if no disk does."""
+    c = np.asarray(centers, dtype=np.float64)
+    R = np.asarray(radii, dtype=np.float64)
+    t = np.asarray(targets, dtype=np.float64)
+    d2 = (t[:, None, 0] - c[None, :, 0]) ** 2 + (t[:, None, 1] - c[None, :, 1]) ** 2
+    inside = d2 <= (slack * R[None, :]) ** 2
+    d2 = np.where(inside, d2, np.inf)
+    best = np.argmin(d2, axis=1)
+    return np.where(np.isfinite(d2[np.arange(len(t)), best]), best, -1)
 
 
 def qbx_matrix(nodes, k: float, p: int, r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
