@@ -341,6 +341,49 @@ int qbx_layer_potential_batched_adjoint(const qbx_batch_item* items, int n_items
                                         double* grad_density, double* grad_nodes, int oversample,
                                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- stored local expansions: one center, several targets (Section 5) ------ */
+
+/* Workspace bytes of qbx_expansion_coefficients (0 if the parameters are invalid). */
+size_t qbx_expansion_workspace_bytes(int n_panels, int q, int p, int oversample, int side,
+                                     int kind);
+
+/* The local expansion coefficients of every center of the contour, formed once and
+ * stored, so that a center's expansion can serve several nearby targets (Section 5
+ * names this as an optimization): a_l, l = -p..p, of eq. graf-coefficient (S) and
+ * eq. graf-coefficient-dlp (D), the same sums qbx_layer_potential evaluates at each
+ * center's own target, without the factor i/4.
+ *   coef   [n_kinds][Mc][2p+1] complex, index l + p; Mc = n_sides * T centers in
+ *          the order of qbx_layer_potential's outputs (exterior first for BOTH)
+ *   ctr_xy [Mc][2], ctr_r [Mc]: the centers and their radii (each nullable)
+ * Arguments and errors as qbx_layer_potential; the workspace is
+ * qbx_expansion_workspace_bytes. */
+int qbx_expansion_coefficients(const qbx_geometry* g, const double* density, double k, int p,
+                               double r, int oversample, int side, int kind, double* coef,
+                               double* ctr_xy, double* ctr_r, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* The stored expansions evaluated at any targets (Section 3.3, step 4(c), at a
+ * target of the caller's choice):
+ *   out[kind][t] = (i/4) sum_{l=-p..p} a_l J_l(k|x_t - c|) e^{i l arg(x_t - c)},
+ * c = ctr_xy[center_index[t]], a the coefficients coef[kind][center_index[t]] of
+ * qbx_expansion_coefficients (same n_ctr, p, kind).  The expansion converges for a
+ * target closer to its center than every source; the center's disk (radius
+ * ctr_r) holds such targets (qbx_assign_centers picks them).  A center index
+ * outside [0, n_ctr) gives NaN.  target_xy [n_targets][2], center_index
+ * [n_targets] (int32), out [n_kinds][n_targets] complex.  Stream-ordered, no
+ * workspace.  QBX_EINVAL for bad sizes, p, k, kind or NULL arrays. */
+int qbx_evaluate_expansions(int n_ctr, const double* ctr_xy, const double* coef, double k,
+                            int p, int kind, int n_targets, const double* target_xy,
+                            const int32_t* center_index, double* out, hipStream_t stream);
+
+/* For every target, the nearest center whose disk holds it, |x_t - c| <= slack *
+ * R_c (ties to the lower index), or -1 when no disk does.  ctr_xy [n_ctr][2],
+ * ctr_r [n_ctr], target_xy [n_targets][2], center_index [n_targets] (int32, out).
+ * Stream-ordered.  QBX_EINVAL for bad sizes, slack <= 0 or NULL arrays. */
+int qbx_assign_centers(int n_ctr, const double* ctr_xy, const double* ctr_r, int n_targets,
+                       const double* target_xy, double slack, int32_t* center_index,
+                       hipStream_t stream);
+
 /* ---- kernel level: explicit sources and centers ------------------------------ */
 
 /* The QBX sums for sources and expansion centers given directly (no panels, no

@@ -708,9 +708,10 @@ def apply_explicit_vjp(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float
 # ---------------------------------------------------------------------------
 def expansion_coefficients(nodes, density, k: float, p: int, r: float = 0.5,
                            oversample: int = 4, side: int = EXTERIOR, kind: int = S_KIND,
-                           mode: str = "fast"):
+                           mode: str = "fast", centers=None):
     """Local expansion coefficients a_l, l = -p..p, of every center of the contour (the
     centers of ``layer_potential``, exterior ones first for BOTH), without the i/4.
+    ``centers``: optional index array into those centers (sampled evaluation).
     Returns (a [n_kinds, n_centers, 2p+1] complex, centers [n_centers, 2], radii
     [n_centers])."""
     nodes = _as_t(nodes, _F64)
@@ -719,14 +720,14 @@ def expansion_coefficients(nodes, density, k: float, p: int, r: float = 0.5,
     src = source_grid(nodes, oversample)
     fine = interpolate_density(density, oversample)
     dens = {kk: src["w"].to(_C128) * fine[i] for i, kk in enumerate(kinds)}
-    coef, xy, rad = [], [], []
-    for s in sides_of(side):
-        ctr = expansion_centers(nodes, src["h"], src["n_tgt"], r, s)
-        a = coefficients(src, dens, ctr, k, p, kind, mode)
-        coef.append(torch.stack([a[kk] for kk in kinds]))
-        xy.append(torch.stack([ctr["cx"], ctr["cy"]], dim=-1))
-        rad.append(ctr["R"])
-    return torch.cat(coef, dim=1), torch.cat(xy), torch.cat(rad)
+    parts = [expansion_centers(nodes, src["h"], src["n_tgt"], r, s) for s in sides_of(side)]
+    ctr = {key: torch.cat([c[key] for c in parts]) for key in parts[0]}
+    if centers is not None:
+        idx = torch.as_tensor(np.asarray(centers), dtype=torch.long)
+        ctr = {key: val[idx] for key, val in ctr.items()}
+    a = coefficients(src, dens, ctr, k, p, kind, mode)
+    return (torch.stack([a[kk] for kk in kinds]), torch.stack([ctr["cx"], ctr["cy"]], dim=-1),
+            ctr["R"])
 
 
 def evaluate_expansions(coef, centers, targets, center_index, k: float, p: int,

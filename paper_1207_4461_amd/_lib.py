@@ -117,6 +117,11 @@ def load() -> C.CDLL:
         "qbx_explicit_tape_bytes": (sz, [i32, i32]),
         "qbx_apply_explicit": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp, vp, vp,
                                      sz, vp]),
+        "qbx_expansion_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
+        "qbx_expansion_coefficients": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp, vp,
+                                             sz, vp]),
+        "qbx_evaluate_expansions": (i32, [i32, vp, vp, dbl, i32, i32, i32, vp, vp, vp, vp]),
+        "qbx_assign_centers": (i32, [i32, vp, vp, i32, vp, dbl, vp, vp]),
         "qbx_apply_explicit_gradient": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32,
                                               vp, vp, sz, vp]),
         "qbx_apply_explicit_adjoint": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, dbl, i32, i32, vp,

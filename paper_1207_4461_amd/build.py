@@ -22,6 +22,7 @@ SOURCES = [("qbx_batched_fwd.hip", "qbx_batched_fwd1", ["-DQBX_FWD_MODE=1"]),
            "qbx_batched_adj.hip", "qbx_batched_fused.hip",
            "qbx_adjoint.hip", "qbx_forward.hip", "qbx_explicit.hip", "qbx_batched.hip",
            "qbx_geometry.hip", "qbx_split.hip", "qbx_solve.hip", "qbx_noalloc.hip",
+           "qbx_expansions.hip",
            "qbx_api.cpp", "qbx_autotune.cpp"]
 ARCH = os.environ.get("QBX_OFFLOAD_ARCH", "gfx950")
 

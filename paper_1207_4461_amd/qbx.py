@@ -135,6 +135,72 @@ def layer_potential_noalloc(nodes: torch.Tensor, density: torch.Tensor, k: float
     return out
 
 
+def expansion_coefficients(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int,
+                           r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
+                           kind: int = S, workspace: Optional[torch.Tensor] = None):
+    """qbx_expansion_coefficients: the stored local expansions of every center,
+    (coef [n_kinds, Mc, 2p+1] complex128 without the i/4, centers [Mc, 2], radii [Mc])."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    nk = n_kinds(kind)
+    _need(density, "density", torch.complex128, (nk, P * Q))
+    dev = nodes.device
+    Mc = n_sides(side) * P * Q
+    coef = torch.empty((nk, Mc, 2 * p + 1), dtype=torch.complex128, device=dev)
+    ctr = torch.empty((Mc, 2), dtype=torch.float64, device=dev)
+    rad = torch.empty(Mc, dtype=torch.float64, device=dev)
+    nbytes = int(lib.qbx_expansion_workspace_bytes(P, Q, int(p), int(oversample), int(side),
+                                                   int(kind)))
+    if nbytes == 0:
+        raise _lib.QBXError(_lib.QBX_EINVAL, "invalid problem parameters")
+    ws = _workspace(nbytes, dev, workspace)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    _lib.check(lib.qbx_expansion_coefficients(C.byref(geo), density.data_ptr(), float(k), int(p),
+                                              float(r), int(oversample), int(side), int(kind),
+                                              coef.data_ptr(), ctr.data_ptr(), rad.data_ptr(),
+                                              ws.data_ptr(), ws.numel(), _stream(dev)))
+    return coef, ctr, rad
+
+
+def evaluate_expansions(coef: torch.Tensor, centers: torch.Tensor, targets: torch.Tensor,
+                        center_index: torch.Tensor, k: float, p: int, kind: int = S
+                        ) -> torch.Tensor:
+    """qbx_evaluate_expansions: [n_kinds, n_targets] complex128, each target from the
+    expansion of center_index[t] (int32)."""
+    lib = _lib.load()
+    nk = n_kinds(kind)
+    Mc = int(centers.shape[0])
+    _need(coef, "coef", torch.complex128, (nk, Mc, 2 * p + 1))
+    _need(centers, "centers", torch.float64, (Mc, 2))
+    nt = int(targets.shape[0])
+    _need(targets, "targets", torch.float64, (nt, 2))
+    _need(center_index, "center_index", torch.int32, (nt,))
+    out = torch.empty((nk, nt), dtype=torch.complex128, device=coef.device)
+    _lib.check(lib.qbx_evaluate_expansions(Mc, centers.data_ptr(), coef.data_ptr(), float(k),
+                                           int(p), int(kind), nt, targets.data_ptr(),
+                                           center_index.data_ptr(), out.data_ptr(),
+                                           _stream(coef.device)))
+    return out
+
+
+def assign_centers(centers: torch.Tensor, radii: torch.Tensor, targets: torch.Tensor,
+                   slack: float = 1.0) -> torch.Tensor:
+    """qbx_assign_centers: per target, the nearest center whose disk (radius x slack)
+    holds it, or -1 (int32)."""
+    lib = _lib.load()
+    Mc = int(centers.shape[0])
+    _need(centers, "centers", torch.float64, (Mc, 2))
+    _need(radii, "radii", torch.float64, (Mc,))
+    nt = int(targets.shape[0])
+    _need(targets, "targets", torch.float64, (nt, 2))
+    idx = torch.empty(nt, dtype=torch.int32, device=centers.device)
+    _lib.check(lib.qbx_assign_centers(Mc, centers.data_ptr(), radii.data_ptr(), nt,
+                                      targets.data_ptr(), float(slack), idx.data_ptr(),
+                                      _stream(centers.device)))
+    return idx
+
+
 def _layer_potential_ext(nodes, density, k, p, r, oversample, side, kind, workspace, dipole,
                          center_rule):
     lib = _lib.load()

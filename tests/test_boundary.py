@@ -393,3 +393,31 @@ def test_explicit_gradient_validates(lib):
         assert call(**bad) == _lib.QBX_EINVAL, bad
     need = lib.qbx_explicit_workspace_bytes(10, 4, 5, 3)
     assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE
+
+
+def test_expansion_entry_points_validate(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    call = lambda gp=C.byref(g), **kw: lib.qbx_expansion_coefficients(
+        gp, kw.get("dens", BAD), kw.get("k", 3.0), kw.get("p", 6), 0.5, 4, kw.get("side", 1),
+        kw.get("kind", 3), kw.get("coef", BAD), None, None, kw.get("ws", BAD),
+        kw.get("nbytes", 1 << 40), None)
+    for bad in (dict(dens=None), dict(coef=None), dict(ws=None), dict(p=25), dict(k=0.0),
+                dict(side=2), dict(kind=4)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(gp=None) == _lib.QBX_EINVAL
+    need = lib.qbx_expansion_workspace_bytes(8, 16, 6, 4, 1, 3)
+    assert need > 0 and lib.qbx_expansion_workspace_bytes(8, 16, 25, 4, 1, 3) == 0
+    assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE
+    ev = lambda **kw: lib.qbx_evaluate_expansions(
+        kw.get("nc", 10), kw.get("cxy", BAD), BAD, kw.get("k", 2.0), kw.get("p", 4),
+        kw.get("kind", 1), kw.get("nt", 5), BAD, kw.get("idx", BAD), BAD, None)
+    for bad in (dict(nc=0), dict(nt=-1), dict(p=25), dict(k=-1.0), dict(kind=0), dict(cxy=None),
+                dict(idx=None)):
+        assert ev(**bad) == _lib.QBX_EINVAL, bad
+    assert ev(nt=0, cxy=None) == _lib.QBX_OK     # nothing to do
+    asg = lambda **kw: lib.qbx_assign_centers(kw.get("nc", 10), BAD, kw.get("r", BAD),
+                                              kw.get("nt", 5), BAD, kw.get("slack", 1.0),
+                                              BAD, None)
+    for bad in (dict(nc=0), dict(nt=-1), dict(slack=0.0), dict(slack=float("nan")),
+                dict(r=None)):
+        assert asg(**bad) == _lib.QBX_EINVAL, bad

@@ -157,3 +157,24 @@ def test_planted_expansion_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(O, "evaluate", reversed_angle)
     inside, rep, uex, _ = _green(24)
     assert np.abs(rep[inside] - uex[inside]).max() / np.abs(uex).max() > 1e-2
+
+
+def test_coefficient_bars_hold_between_library_and_recurrence_hankel():
+    """The bars the GPU coefficients are held to (expansion_bars.py) accept the oracle's
+    two ways of forming H_l (upward recurrence from H_0, H_1 against scipy at every
+    order) on a case whose top orders cancel by ~1e10, and reject a planted sign
+    mistake in one order."""
+    import pytest
+    from expansion_bars import check_coefficients
+    pb = I.small(n_panels=7, p=12, k=7.0, kind=3, side=I.BOTH, oversample=3)
+    fast, C, R = O.expansion_coefficients(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample,
+                                          pb.side, pb.kind)
+    exact, _, _ = O.expansion_coefficients(pb.nodes, pb.density, pb.k, pb.p, pb.r,
+                                           pb.oversample, pb.side, pb.kind, mode="exact")
+    fast, exact, C, R = fast.numpy(), exact.numpy(), C.numpy(), R.numpy()
+    assert rel(fast[:, :, -1], exact[:, :, -1]) > 1e-12   # the plain bar would not hold
+    check_coefficients(fast, exact, pb, C, R)
+    planted = fast.copy()
+    planted[1, :, pb.p - 1] *= -1.0   # a^D_{-1} with the wrong sign
+    with pytest.raises(AssertionError):
+        check_coefficients(planted, exact, pb, C, R)
