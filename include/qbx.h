@@ -198,18 +198,26 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
                                        double gamma, double* grad, double* dn, void* ws,
                                        size_t ws_bytes, hipStream_t stream);
 
-/* Vector-Jacobian product of qbx_layer_potential_split with respect to the
- * density (PyTorch convention, the conjugate-transposed operator A^H applied
- * to the cotangent): the same near relation and rules as the forward, so
- * <g, A sigma> = <A^H g, sigma> holds to rounding.  cotangent has the shape of
- * out; grad_density [n_kinds][T] complex.  Node gradients are not formed.
+/* Vector-Jacobian product of qbx_layer_potential_split (PyTorch convention):
+ * the gradients of L = Re <cotangent, out> with respect to the density (the
+ * conjugate-transposed operator A^H applied to the cotangent) and, when
+ * grad_nodes is not NULL, to the node coordinates.  The same near relation and
+ * rules as the forward: each pair's term is differentiated under the rule it
+ * takes (the QBX pair of Sections 2 and 3.2 for near pairs, the smooth rule for
+ * far ones), through the source grid, weights, normals, centers, radii and the
+ * targets themselves; the near relation is piecewise constant in the nodes and
+ * contributes nothing.  <g, A sigma> = <A^H g, sigma> holds to rounding.
+ *   cotangent     device, the shape of out
+ *   grad_density  device [n_kinds][T] complex, or NULL
+ *   grad_nodes    device [P][16][2], or NULL (density only: a cheaper path)
  * Errors as qbx_layer_potential_split, plus QBX_EINVAL for a NULL cotangent or
- * grad_density.  Stream-ordered, no allocation; qbx_workspace_bytes(). */
+ * when both outputs are NULL.  Stream-ordered, no allocation;
+ * qbx_workspace_bytes(). */
 int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* density, double k,
                                       int p, double r, int oversample, int side, int kind,
                                       double gamma, const double* cotangent,
-                                      double* grad_density, void* ws, size_t ws_bytes,
-                                      hipStream_t stream);
+                                      double* grad_density, double* grad_nodes, void* ws,
+                                      size_t ws_bytes, hipStream_t stream);
 
 /* ---- integral equation ------------------------------------------------ */
 

@@ -528,14 +528,15 @@ def direct_sum(src, dens, tx, ty, k: float, kind: int, sel) -> Dict[str, torch.T
     = sum_j w_j mu_j k H_1(k rho_j) (x - x'_j).n_j / rho_j.  sel: [C, N] bool."""
     dx = tx[:, None] - src["x"][None, :]
     dy = ty[:, None] - src["y"][None, :]
-    rho = torch.sqrt(dx * dx + dy * dy)
-    # rho of an excluded pair may be 0: evaluate there at 1 and drop the term
-    z = k * torch.where(sel, rho, torch.ones_like(rho))
+    # rho of an excluded pair may be 0: evaluate there at 1 and drop the term (the
+    # square root is taken after the choice, so its derivative stays finite)
+    rho = torch.sqrt(torch.where(sel, dx * dx + dy * dy, torch.ones_like(dx)))
+    z = k * rho
     out = {}
     if kind & S_KIND:
         out["S"] = torch.where(sel, hankel1(0, z) * dens["S"][None, :], 0.0).sum(dim=1)
     if kind & D_KIND:
-        ndot = (dx * src["nx"][None, :] + dy * src["ny"][None, :]) / torch.where(sel, rho, 1.0)
+        ndot = (dx * src["nx"][None, :] + dy * src["ny"][None, :]) / rho
         term = k * hankel1(1, z) * ndot * dens["D"][None, :]
         out["D"] = torch.where(sel, term, 0.0).sum(dim=1)
     return out
@@ -655,6 +656,30 @@ def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, over
                 u[si, i, torch.as_tensor(rows)] = (evaluate(a[kk], ctr["R"], ctr["theta"], k, p, mode)
                                                    + 0.25j * dsum[kk])
     return u
+
+
+def split_vjp(nodes, density, k: float, p: int, r: float, oversample: int, side: int, kind: int,
+              cotangent, gamma: float = 6.0):
+    """Gradients of L = Re sum conj(g) u, u = ``layer_potential_split``, with respect to the
+    density [n_kinds, P*16] (complex, PyTorch convention) and the nodes [P, 16, 2]: autograd
+    through the split's own steps (source grid, weights, normals, centers, the QBX
+    coefficients of the near sources, the direct rule at the targets for the far ones).
+    The near relation is piecewise constant in the nodes and enters as a fixed choice.
+    Small inputs only (the whole graph is kept)."""
+    X = torch.tensor(np.asarray(nodes, dtype=np.float64), requires_grad=True)
+    d = torch.tensor(np.asarray(density, dtype=np.complex128), requires_grad=True)
+    u = layer_potential_split(X, d, k, p, r, oversample, side, kind, gamma=gamma)
+    g = torch.as_tensor(np.asarray(cotangent, dtype=np.complex128))
+    torch.real(torch.sum(torch.conj(g) * u)).backward()
+    return d.grad.detach().numpy(), X.grad.detach().numpy()
+
+
+def split_loss(nodes, density, k, p, r, oversample, side, kind, cotangent, gamma=6.0) -> float:
+    """L = Re sum conj(g) u for u = ``layer_potential_split`` (the scalar of ``split_vjp``)."""
+    with torch.no_grad():
+        u = layer_potential_split(nodes, density, k, p, r, oversample, side, kind,
+                                  gamma=gamma).numpy()
+    return float(np.real(np.sum(np.conj(np.asarray(cotangent)) * u)))
 
 
 def apply_explicit(src_xy, src_nu, src_q, ctr_xy, ctr_r, ctr_theta, k: float, p: int,

@@ -91,7 +91,7 @@ def load() -> C.CDLL:
         "qbx_layer_potential_split_gradient": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl,
                                                      vp, vp, vp, sz, vp]),
         "qbx_layer_potential_split_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl,
-                                                    vp, vp, vp, sz, vp]),
+                                                    vp, vp, vp, vp, sz, vp]),
         "qbx_layer_potential_split": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, dbl, vp, vp,
                                             sz, vp]),
         "qbx_layer_potential_adjoint": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, vp, vp, vp,

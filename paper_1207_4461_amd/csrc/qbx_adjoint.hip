@@ -415,6 +415,14 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
   return hipGetLastError();
 }
 
+hipError_t launch_chain(const Dims& d, const double* nodes, const double* density,
+                        const double* tables, const double* sg, const double* cg,
+                        double* grad_density, double* grad_nodes, hipStream_t s) {
+  hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
+                     grad_density, grad_nodes);
+  return hipGetLastError();
+}
+
 hipError_t launch_make_G(const Dims& d, const double* cot, double2* G, hipStream_t s) {
   const int n = d.Mc * d.nk;
   hipLaunchKernelGGL(k_make_G, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk, cot, G);

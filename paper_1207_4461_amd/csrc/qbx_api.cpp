@@ -174,7 +174,7 @@ Layout make_layout(const Dims& d) {
   L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T * 2);
   L.gfar = take(sizeof(double2) * (size_t)d.nk * d.T);
   L.aacc = take(sizeof(double2) * (size_t)d.nk * d.N);
-  L.apart = take(sizeof(double2) * (size_t)d.n_asplit * d.nk * d.N);
+  L.apart = take(sizeof(double2) * (size_t)d.n_asplit * (d.nk + 2) * d.N);
   L.total = o;
   return L;
 }
@@ -479,15 +479,16 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
 int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* density, double k,
                                       int p, double r, int oversample, int side, int kind,
                                       double gamma, const double* cotangent,
-                                      double* grad_density, void* ws, size_t ws_bytes,
-                                      hipStream_t stream) {
+                                      double* grad_density, double* grad_nodes, void* ws,
+                                      size_t ws_bytes, hipStream_t stream) {
   Dims d;
   int rc = validate(g, p, k, r, oversample, side, kind, &d);
   if (rc) return rc;
   if (!(gamma > 0.0)) return fail(QBX_EINVAL, "near-panel factor gamma = %g must be > 0", gamma);
   if (!density) return fail(QBX_EINVAL, "density is NULL");
   if (!cotangent) return fail(QBX_EINVAL, "cotangent is NULL");
-  if (!grad_density) return fail(QBX_EINVAL, "grad_density is NULL");
+  if (!grad_density && !grad_nodes)
+    return fail(QBX_EINVAL, "grad_density and grad_nodes are both NULL");
   if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
   const Layout L = make_layout(d);
   if (ws_bytes < L.total)
@@ -498,12 +499,22 @@ int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* densi
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
   e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
   if (e != hipSuccess) return device_fail(e, "cotangent kernel");
-  e = launch_split_adjoint_density(d, g->nodes, at<double>(ws, L.tables), at<double4>(ws, L.geo),
-                                   at<double>(ws, L.wgt), at<CenterRec>(ws, L.ctr),
-                                   at<double>(ws, L.jtab), at<double4>(ws, L.bnd), gamma * gamma,
-                                   at<double2>(ws, L.G), at<double2>(ws, L.gfar),
-                                   at<double2>(ws, L.aacc), at<double2>(ws, L.apart),
-                                   grad_density, stream);
+  if (grad_nodes)
+    e = launch_split_adjoint_nodes(d, g->nodes, density, at<double>(ws, L.tables),
+                                   at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                   at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                   at<double4>(ws, L.bnd), gamma * gamma, at<double2>(ws, L.G),
+                                   at<double2>(ws, L.gfar), at<double>(ws, L.cg),
+                                   at<double2>(ws, L.spart), at<double2>(ws, L.fpart),
+                                   at<double2>(ws, L.apart), at<double>(ws, L.sg), grad_density,
+                                   grad_nodes, stream);
+  else
+    e = launch_split_adjoint_density(d, g->nodes, at<double>(ws, L.tables), at<double4>(ws, L.geo),
+                                     at<double>(ws, L.wgt), at<CenterRec>(ws, L.ctr),
+                                     at<double>(ws, L.jtab), at<double4>(ws, L.bnd), gamma * gamma,
+                                     at<double2>(ws, L.G), at<double2>(ws, L.gfar),
+                                     at<double2>(ws, L.aacc), at<double2>(ws, L.apart),
+                                     grad_density, stream);
   if (e != hipSuccess) return device_fail(e, "split adjoint kernels");
   return QBX_OK;
 }

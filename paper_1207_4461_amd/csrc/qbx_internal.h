@@ -80,7 +80,8 @@ struct Layout {
   size_t fpart;    // double2[n_fsplit][nk][T][2] split: far sums (forward: first half)
   size_t gfar;     // double2[nk][T] split adjoint: cotangent weights of both sides
   size_t aacc;     // double2[nk][N] split adjoint: near sums per source
-  size_t apart;    // double2[n_asplit][nk][N] split adjoint: far sums per source
+  size_t apart;    // double2[n_asplit][nk + 2][N] split adjoint: far sums per source
+                   // (density; with the node gradient also position and normal)
   size_t total;
 };
 
@@ -176,7 +177,22 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
                                         const double4* bnd, double g2, const double2* G,
                                         double2* Gf, double2* acc, double2* partial,
                                         double* grad_density, hipStream_t s);
+// the split's adjoint with respect to the nodes (and the density, through the
+// chain rule; either output may be NULL): cg [Mc][8], spart [src_slots][N], fpart
+// [n_fsplit][nk][T][2], apart [n_asplit][nk + 2][N], sg [N][8]
+hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const double* density,
+                                      const double* tables, const double4* geo,
+                                      const double2* dens, const CenterRec* ctr,
+                                      const double* jtab, const double4* bnd, double g2,
+                                      const double2* G, double2* Gf, double* cg, double2* spart,
+                                      double2* fpart, double2* apart, double* sg,
+                                      double* grad_density, double* grad_nodes, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
+// the chain rule to the nodes and node densities from the per-source (sg) and
+// per-center (cg) gradients; one block per panel
+hipError_t launch_chain(const Dims& d, const double* nodes, const double* density,
+                        const double* tables, const double* sg, const double* cg,
+                        double* grad_density, double* grad_nodes, hipStream_t s);
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,
                                hipStream_t s);

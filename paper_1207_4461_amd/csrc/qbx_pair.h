@@ -603,6 +603,60 @@ __device__ __forceinline__ void forward_center(const double4* __restrict__ geo,
 }
 
 // ---------------------------------------------------------------------------
+// forward with tape, one pair: adds w*density times K, K_R, K_theta and the two
+// components of grad_v K of source j for the center (cx, cy) with target
+// direction (ct, st) to A[kind][0..4]
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void tape_source(const double4* __restrict__ geo,
+                                            const double2* __restrict__ dens, int N, int j,
+                                            double cx, double cy, double ct, double st, double k,
+                                            double inv_k, const double* __restrict__ Jtab, int nj,
+                                            Cplx (&A)[2][5]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  const int z0 = opaque_zero();
+  const double* __restrict__ J = Jtab + z0;
+  const double* __restrict__ cf = g_seed_table + z0;
+  const double4 g = geo[j];
+  const double vx = g.x - cx, vy = g.y - cy;
+  const double rho2 = fma(vx, vx, vy * vy);
+  const double ir = rsqrt_refined(rho2);
+  const double rho = rho2 * ir;
+  const double ux = vx * ir, uy = vy * ir;          // v^ ; theta^ = (-uy, ux)
+  const double cd = ct * ux + st * uy;
+  const double sd = st * ux - ct * uy;
+  double cps = 0.0, sps = 0.0;
+  if (kD) {
+    cps = ct * g.z + st * g.w;
+    sps = st * g.z - ct * g.w;
+  }
+  const PairOut o = pair_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
+  int kk = 0;
+  if (kS) {
+    const double2 w = dens[j];
+    const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
+    const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
+    cmul_acc(A[kk][0], w.x, w.y, o.Ks);
+    cmul_acc(A[kk][1], w.x, w.y, o.KRs);
+    cmul_acc(A[kk][2], w.x, w.y, o.Kts);
+    cmul_acc(A[kk][3], w.x, w.y, ex);
+    cmul_acc(A[kk][4], w.x, w.y, ey);
+    ++kk;
+  }
+  if (kD) {
+    const double2 w = dens[(kS ? (size_t)N : 0) + j];
+    const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
+    const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
+    cmul_acc(A[kk][0], w.x, w.y, o.Kd);
+    cmul_acc(A[kk][1], w.x, w.y, o.KRd);
+    cmul_acc(A[kk][2], w.x, w.y, o.Ktd);
+    cmul_acc(A[kk][3], w.x, w.y, ex);
+    cmul_acc(A[kk][4], w.x, w.y, ey);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // forward with tape: one wave, one center, chunks [c0, c1); A[kind][0..4] =
 // sums of w*density times K, K_R, K_theta, and the two components of grad_v K,
 // reduced over the wave
@@ -625,47 +679,7 @@ __device__ __forceinline__ void tape_center(const double4* __restrict__ geo,
     for (int b = 0; b < 5; ++b) A[a][b] = {0.0, 0.0};
   for (int c = c0; c < c1; ++c) {
     const int j = c * kWave + lane;
-    if (j < N) {
-      const int z0 = opaque_zero();
-      const double* __restrict__ J = Jtab + z0;
-      const double* __restrict__ cf = g_seed_table + z0;
-      const double4 g = geo[j];
-      const double vx = g.x - cx, vy = g.y - cy;
-      const double rho2 = fma(vx, vx, vy * vy);
-      const double ir = rsqrt_refined(rho2);
-      const double rho = rho2 * ir;
-      const double ux = vx * ir, uy = vy * ir;          // v^ ; theta^ = (-uy, ux)
-      const double cd = ct * ux + st * uy;
-      const double sd = st * ux - ct * uy;
-      double cps = 0.0, sps = 0.0;
-      if (kD) {
-        cps = ct * g.z + st * g.w;
-        sps = st * g.z - ct * g.w;
-      }
-      const PairOut o = pair_sums<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J, J + nj, cf);
-      int kk = 0;
-      if (kS) {
-        const double2 w = dens[j];
-        const Cplx ex = {fma(o.Krs.r, ux, -o.Ktps.r * ir * uy), fma(o.Krs.i, ux, -o.Ktps.i * ir * uy)};
-        const Cplx ey = {fma(o.Krs.r, uy, o.Ktps.r * ir * ux), fma(o.Krs.i, uy, o.Ktps.i * ir * ux)};
-        cmul_acc(A[kk][0], w.x, w.y, o.Ks);
-        cmul_acc(A[kk][1], w.x, w.y, o.KRs);
-        cmul_acc(A[kk][2], w.x, w.y, o.Kts);
-        cmul_acc(A[kk][3], w.x, w.y, ex);
-        cmul_acc(A[kk][4], w.x, w.y, ey);
-        ++kk;
-      }
-      if (kD) {
-        const double2 w = dens[(kS ? (size_t)N : 0) + j];
-        const Cplx ex = {fma(o.Krd.r, ux, -o.Ktpd.r * ir * uy), fma(o.Krd.i, ux, -o.Ktpd.i * ir * uy)};
-        const Cplx ey = {fma(o.Krd.r, uy, o.Ktpd.r * ir * ux), fma(o.Krd.i, uy, o.Ktpd.i * ir * ux)};
-        cmul_acc(A[kk][0], w.x, w.y, o.Kd);
-        cmul_acc(A[kk][1], w.x, w.y, o.KRd);
-        cmul_acc(A[kk][2], w.x, w.y, o.Ktd);
-        cmul_acc(A[kk][3], w.x, w.y, ex);
-        cmul_acc(A[kk][4], w.x, w.y, ey);
-      }
-    }
+    if (j < N) tape_source<P, KIND>(geo, dens, N, j, cx, cy, ct, st, k, inv_k, Jtab, nj, A);
   }
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk)
@@ -905,6 +919,58 @@ __device__ __forceinline__ void fused_tile(
 }
 
 // ---------------------------------------------------------------------------
+// adjoint, source side, one pair: source g with weighted densities q against the
+// center C (J its Bessel table, GS, GD its cotangent weights per kind); adds to
+// A in the src_slots layout
+// ---------------------------------------------------------------------------
+template <int P, int KIND>
+__device__ __forceinline__ void adjoint_pair(const double4 g, const double2 (&q)[2],
+                                             const CenterRec* __restrict__ C,
+                                             const double* __restrict__ J,
+                                             const double* __restrict__ cf, double2 GS,
+                                             double2 GD, double k, double inv_k, int nj,
+                                             Cplx (&A)[src_slots(KIND)]) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = kS && kD ? 2 : 1;
+  const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
+  const double vx = g.x - cx, vy = g.y - cy;
+  const double rho2 = fma(vx, vx, vy * vy);
+  const double ir = rsqrt_refined(rho2);
+  const double rho = rho2 * ir;
+  const double ux = vx * ir, uy = vy * ir;
+  const double cd = ct * ux + st * uy;
+  const double sd = st * ux - ct * uy;
+  double cps = 0.0, sps = 0.0;
+  if (kD) {
+    cps = ct * g.z + st * g.w;
+    sps = st * g.z - ct * g.w;
+  }
+  const double2 qS = q[0], qD = q[NK - 1];
+  const double2 wS = make_double2(GS.x * qS.x - GS.y * qS.y, GS.x * qS.y + GS.y * qS.x);
+  const double2 wD = make_double2(GD.x * qD.x - GD.y * qD.y, GD.x * qD.y + GD.y * qD.x);
+  const ProjOut o = pair_sums_proj<P, KIND, false>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J,
+                                                   J + nj, cf, wS, wD);
+  double r = 0.0, t = 0.0;
+  if (kS) {
+    A[0].r += GS.x * o.Ks.r - GS.y * o.Ks.i;   // conj(G K)
+    A[0].i -= GS.x * o.Ks.i + GS.y * o.Ks.r;
+    r = o.rs;
+    t = o.ts;
+  }
+  if (kD) {
+    A[NK - 1].r += GD.x * o.Kd.r - GD.y * o.Kd.i;
+    A[NK - 1].i -= GD.x * o.Kd.i + GD.y * o.Kd.r;
+    r += o.rd;
+    t += o.td;
+    A[NK + 1].r += o.psid;
+  }
+  t *= ir;
+  A[NK].r += fma(r, ux, -t * uy);
+  A[NK].i += fma(r, uy, t * ux);
+}
+
+// ---------------------------------------------------------------------------
 // adjoint, source side: one lane, one source g with densities q, centers
 // [i0, i1); A in the src_slots layout
 // ---------------------------------------------------------------------------
@@ -923,46 +989,10 @@ __device__ __forceinline__ void adjoint_source(const double4 g, const double2 (&
   for (int a = 0; a < src_slots(KIND); ++a) A[a] = {0.0, 0.0};
   for (int ci = i0; ci < i1; ++ci) {
     const int z0 = opaque_zero();
-    const CenterRec* __restrict__ C = ctr + ci + z0;
-    const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
-    const double* __restrict__ cf = g_seed_table + z0;
-    const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
-    const double vx = g.x - cx, vy = g.y - cy;
-    const double rho2 = fma(vx, vx, vy * vy);
-    const double ir = rsqrt_refined(rho2);
-    const double rho = rho2 * ir;
-    const double ux = vx * ir, uy = vy * ir;
-    const double cd = ct * ux + st * uy;
-    const double sd = st * ux - ct * uy;
-    double cps = 0.0, sps = 0.0;
-    if (kD) {
-      cps = ct * g.z + st * g.w;
-      sps = st * g.z - ct * g.w;
-    }
     const double2 GS = G[(size_t)ci + z0];
     const double2 GD = NK == 2 ? G[(size_t)Mc + ci + z0] : GS;
-    const double2 qS = q[0], qD = q[NK - 1];
-    const double2 wS = make_double2(GS.x * qS.x - GS.y * qS.y, GS.x * qS.y + GS.y * qS.x);
-    const double2 wD = make_double2(GD.x * qD.x - GD.y * qD.y, GD.x * qD.y + GD.y * qD.x);
-    const ProjOut o = pair_sums_proj<P, KIND, false>(k * rho, ir * inv_k, cd, sd, cps, sps, k, J,
-                                                     J + nj, cf, wS, wD);
-    double r = 0.0, t = 0.0;
-    if (kS) {
-      A[0].r += GS.x * o.Ks.r - GS.y * o.Ks.i;   // conj(G K)
-      A[0].i -= GS.x * o.Ks.i + GS.y * o.Ks.r;
-      r = o.rs;
-      t = o.ts;
-    }
-    if (kD) {
-      A[NK - 1].r += GD.x * o.Kd.r - GD.y * o.Kd.i;
-      A[NK - 1].i -= GD.x * o.Kd.i + GD.y * o.Kd.r;
-      r += o.rd;
-      t += o.td;
-      A[NK + 1].r += o.psid;
-    }
-    t *= ir;
-    A[NK].r += fma(r, ux, -t * uy);
-    A[NK].i += fma(r, uy, t * ux);
+    adjoint_pair<P, KIND>(g, q, ctr + ci + z0, jtab + (size_t)ci * NJ + z0, g_seed_table + z0, GS,
+                          GD, k, inv_k, nj, A);
   }
 }
 

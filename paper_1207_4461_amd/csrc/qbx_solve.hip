@@ -275,7 +275,7 @@ struct Gmres {
     const double* c = reinterpret_cast<const double*>(cot);
     if (gamma > 0.0)
       rc = qbx_layer_potential_split_adjoint(g, dens, k, p, r, oversample, QBX_BOTH, 3, gamma, c,
-                                             gd, ws + L.fws, L.fws_bytes, s);
+                                             gd, nullptr, ws + L.fws, L.fws_bytes, s);
     else
       rc = qbx_layer_potential_adjoint(g, dens, k, p, r, oversample, QBX_BOTH, 3, c, nullptr, gd,
                                        nullptr, ws + L.fws, L.fws_bytes, s);

@@ -21,6 +21,7 @@
 // finalize adds, per center, the near sum and the far sums of its target in a
 // fixed order and applies i/4.
 #include "qbx_pair.h"
+#include "qbx_panel.h"
 
 namespace qbx {
 
@@ -350,15 +351,22 @@ __global__ __launch_bounds__(256) void k_split_gfar(int T, int nk, int n_sides,
 // Gf_t K_far(t, j); lanes are 64 consecutive sources, targets wave-uniform
 // The vote of k_split_far per (wave, target panel); here the targets are the
 // panel's nodes, so its node radius bounds them.
-template <int KIND>
+// GEO adds the far pairs' gradients for the source's position and normal,
+// contracted with its weighted densities q (slots NK and NK + 1 of the split's
+// NK + 2): with u = (x - x')/rho, f = u.n' and H_0' = -H_1 (DLMF 10.6.2),
+//   d/dx' H_0(k rho) = k H_1 u,
+//   d/dx' [k H_1 f] = -k [k H_0 f u + (H_1/rho)(n' - 2 f u)],   d/dn' [k H_1 f] = k H_1 u,
+// each summed as Re(q G_t .) over the split's targets.
+template <int KIND, bool GEO>
 __global__ __launch_bounds__(256) void k_split_far_adj(
-    const double4* __restrict__ geo, int N, int qs, const double* __restrict__ nodes, int T,
-    const double4* __restrict__ bnd, int NP, double g2, double k,
-    const double2* __restrict__ Gf, int n_sb, int n_asplit, int ppw,
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
+    double k, const double2* __restrict__ Gf, int n_sb, int n_asplit, int ppw,
     double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  constexpr int NS = NK + (GEO ? 2 : 0);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int gw = blockIdx.x * 4 + wave;
@@ -376,6 +384,12 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   const double kt = seed::kZV * inv_k;          // kZV / z = kt / rho
   const double zv = seed::kZV * (1.0 + 1e-12);
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  double2 qS = make_double2(0.0, 0.0), qD = qS;
+  if (GEO) {
+    qS = dens[jj];
+    qD = dens[(size_t)(NK - 1) * N + jj];
+  }
+  double gxp = 0.0, gyp = 0.0, gnx = 0.0, gny = 0.0;   // GEO: without the factor k
   // one far pair: the cotangent weights of target t times H_0 (S) and
   // H_1 (x - x').n' / rho (D)
   auto add = [&](int t, double dx, double dy, double ir, const H01& h) {
@@ -384,6 +398,12 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
       const double2 Gt = Gf[(size_t)(kk++) * T + t];
       sr = fma(Gt.x, h.h0r, fma(-Gt.y, h.h0i, sr));
       si = fma(Gt.x, h.h0i, fma(Gt.y, h.h0r, si));
+      if (GEO) {
+        const double cr = qS.x * Gt.x - qS.y * Gt.y, cim = qS.x * Gt.y + qS.y * Gt.x;
+        const double a1 = cr * h.h1r - cim * h.h1i;   // Re(q G H_1)
+        gxp = fma(a1 * ir, dx, gxp);
+        gyp = fma(a1 * ir, dy, gyp);
+      }
     }
     if (kD) {
       const double2 Gt = Gf[(size_t)kk * T + t];
@@ -391,6 +411,17 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
       const double wr = Gt.x * f, wi = Gt.y * f;
       dr = fma(wr, h.h1r, fma(-wi, h.h1i, dr));
       di = fma(wr, h.h1i, fma(wi, h.h1r, di));
+      if (GEO) {
+        const double cr = qD.x * Gt.x - qD.y * Gt.y, cim = qD.x * Gt.y + qD.y * Gt.x;
+        const double a0 = cr * h.h0r - cim * h.h0i;   // Re(q G H_0)
+        const double a1 = cr * h.h1r - cim * h.h1i;   // Re(q G H_1)
+        const double ux = dx * ir, uy = dy * ir;
+        const double b = (k * a0 - 2.0 * a1 * ir) * f;
+        gxp -= fma(b, ux, a1 * ir * g.z);
+        gyp -= fma(b, uy, a1 * ir * g.w);
+        gnx = fma(a1, ux, gnx);
+        gny = fma(a1, uy, gny);
+      }
     }
   };
   for (int mt = p0; mt < p1; ++mt) {
@@ -431,8 +462,12 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   }
   if (valid) {
     int kk = 0;
-    if (kS) partial[((size_t)sp * NK + kk++) * N + j] = make_double2(sr, si);
-    if (kD) partial[((size_t)sp * NK + kk) * N + j] = make_double2(k * dr, k * di);
+    if (kS) partial[((size_t)sp * NS + kk++) * N + j] = make_double2(sr, si);
+    if (kD) partial[((size_t)sp * NS + kk) * N + j] = make_double2(k * dr, k * di);
+    if (GEO) {
+      partial[((size_t)sp * NS + NK) * N + j] = make_double2(k * gxp, k * gyp);
+      partial[((size_t)sp * NS + NK + 1) * N + j] = make_double2(k * gnx, k * gny);
+    }
   }
 }
 
@@ -500,19 +535,235 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   const int n_sb = (d.N + kWave - 1) / kWave;
   const long waves = (long)n_sb * d.n_asplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-#define QBX_FADJ_ARGS \
-  geo, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit, d.panels_per_asplit, partial
+#define QBX_FADJ_ARGS                                                                       \
+  geo, nullptr, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
+      d.panels_per_asplit, partial
   timer_begin(8, s);
   switch (d.kind) {
-    case 1: hipLaunchKernelGGL((k_split_far_adj<1>), grid, block, 0, s, QBX_FADJ_ARGS); break;
-    case 2: hipLaunchKernelGGL((k_split_far_adj<2>), grid, block, 0, s, QBX_FADJ_ARGS); break;
-    default: hipLaunchKernelGGL((k_split_far_adj<3>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    case 1: hipLaunchKernelGGL((k_split_far_adj<1, false>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_split_far_adj<2, false>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    default: hipLaunchKernelGGL((k_split_far_adj<3, false>), grid, block, 0, s, QBX_FADJ_ARGS); break;
   }
   timer_end(8, s);
 #undef QBX_FADJ_ARGS
   hipLaunchKernelGGL(k_split_density_grad, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.N, d.qs,
                      d.nk, d.n_asplit, tables, wgt, acc, partial, grad_density);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Node gradient of the split.  The loss L = Re sum_i conj(g_i) u_i is a sum over
+// pairs, each taken by one rule, so its gradient is the plain adjoint's per-pair
+// terms over the near pairs plus the direct rule's over the far ones:
+//  * center side, near pairs (k_split_near_cg): the tape sums of the near sources
+//    (K_R, K_theta, grad_v K; tape_source) contracted with G_i, then the per-center
+//    gradients of center_grad_from_sums (target, radius, normal);
+//  * source side, near pairs (k_split_near_adj_nodes): the plain adjoint's pair
+//    body (adjoint_pair) over the centers of near target panels;
+//  * far pairs, source side: k_split_far_adj<KIND, true>; target side: the far
+//    target gradients of the split's derivative pass (k_split_far_grad),
+//    contracted with both sides' G (k_split_far_tgrad);
+//  * k_split_source_finalize adds both sides' source terms into the per-source
+//    layout of the plain adjoint, and the plain chain rule (chain_panel) maps
+//    everything to the nodes and node densities.
+// ---------------------------------------------------------------------------
+
+// cg[ci]: center_grad_from_sums of the near sources' tape sums, contracted with G
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_split_near_cg(
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
+    int side, const double4* __restrict__ bnd, int NP, double g2, double k,
+    const double2* __restrict__ G, double* __restrict__ cg) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ci = blockIdx.x * 4 + wave;
+  if (ci >= Mc) return;
+  const int m = (ci % T) / kQ;
+  const double4 bm = bnd[m];
+  const CenterRec* C = ctr + ci;
+  const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
+  const double inv_k = 1.0 / k;
+  const double* Jtab = jtab + (size_t)ci * NJ;
+  Cplx A[2][5];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) A[a][b] = {0.0, 0.0};
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mp = w0 + lane;
+    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
+    unsigned long long mask = __ballot(nr);
+    while (mask) {
+      const int pan = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      for (int s0 = 0; s0 < qs; s0 += kWave) {
+        if (s0 + lane < qs)
+          tape_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
+                               NJ / 2, A);
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int b = 1; b < 5; ++b) wave_sum(A[kk][b]);
+  if (lane == 0) {
+    double dR = 0.0, dt = 0.0, gvx = 0.0, gvy = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const double2 g = G[(size_t)kk * Mc + ci];
+      dR += g.x * A[kk][1].r - g.y * A[kk][1].i;   // Re(G a)
+      dt += g.x * A[kk][2].r - g.y * A[kk][2].i;
+      gvx += g.x * A[kk][3].r - g.y * A[kk][3].i;
+      gvy += g.x * A[kk][4].r - g.y * A[kk][4].i;
+    }
+    center_grad_from_sums(ci, side, T, ctr, dR, dt, gvx, gvy, cg);
+  }
+}
+
+// cg[t][0..1] += Re(Gf_t . far target gradient) summed over kinds and far splits
+// (the first side's center of target t carries the target's own gradient)
+__global__ __launch_bounds__(256) void k_split_far_tgrad(int T, int nk, int n_fsplit,
+                                                         const double2* __restrict__ Gf,
+                                                         const double2* __restrict__ farp,
+                                                         double* __restrict__ cg) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double gx = 0.0, gy = 0.0;
+  for (int kk = 0; kk < nk; ++kk) {
+    double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
+    for (int sp = 0; sp < n_fsplit; ++sp) {
+      const double2* q = farp + (((size_t)sp * nk + kk) * T + t) * 2;
+      xr += q[0].x;
+      xi += q[0].y;
+      yr += q[1].x;
+      yi += q[1].y;
+    }
+    const double2 g = Gf[(size_t)kk * T + t];
+    gx += g.x * xr - g.y * xi;
+    gy += g.x * yr - g.y * yi;
+  }
+  cg[(size_t)t * 8] += gx;
+  cg[(size_t)t * 8 + 1] += gy;
+}
+
+// part[b][j], b < src_slots(KIND): the plain adjoint's source-side sums over the
+// centers of the target panels near j's panel (the scan of k_split_near_adj)
+template <int P, int KIND>
+__global__ __launch_bounds__(256) void k_split_near_adj_nodes(
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
+    int n_sides, const double4* __restrict__ bnd, int NP, double g2, double k,
+    const double2* __restrict__ G, double2* __restrict__ part) {
+  constexpr bool kS = (KIND & 1) != 0;
+  constexpr bool kD = (KIND & 2) != 0;
+  constexpr int NK = kS && kD ? 2 : 1;
+  constexpr int NA = src_slots(KIND);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + wave;
+  if (c * kWave >= N) return;
+  const int j = c * kWave + lane;
+  const bool valid = j < N;
+  const int jj = valid ? j : N - 1;
+  const double4 bj = bnd[jj / qs];
+  const int pa = (c * kWave) / qs;
+  const int pb = min(c * kWave + kWave - 1, N - 1) / qs;
+  const double4 g = geo[jj];
+  double2 q[2];
+  q[0] = dens[jj];
+  q[1] = dens[(size_t)(NK - 1) * N + jj];
+  const double inv_k = 1.0 / k;
+  const int nj = NJ / 2;
+  Cplx A[NA];
+#pragma unroll
+  for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mt = w0 + lane;
+    bool any = false;
+    if (mt < NP) {
+      const double4 bt = bnd[mt];
+      for (int ps = pa; ps <= pb; ++ps) any = any || panels_near(bt, bnd[ps], g2);
+    }
+    unsigned long long mask = __ballot(any);
+    while (mask) {
+      const int m = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      if (valid && panels_near(bnd[m], bj, g2)) {
+        for (int si_ = 0; si_ < n_sides; ++si_) {
+          for (int a = 0; a < kQ; ++a) {
+            const int ci = si_ * T + m * kQ + a;
+            const int z0 = opaque_zero();
+            const double2 GS = G[(size_t)ci + z0];
+            const double2 GD = NK == 2 ? G[(size_t)Mc + ci + z0] : GS;
+            adjoint_pair<P, KIND>(g, q, ctr + ci + z0, jtab + (size_t)ci * NJ + z0,
+                                  g_seed_table + z0, GS, GD, k, inv_k, nj, A);
+          }
+        }
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int b = 0; b < NA; ++b) part[(size_t)b * N + j] = make_double2(A[b].r, A[b].i);
+  }
+}
+
+// sg[j] (the per-source layout of source_finalize_elem) from the near slots and
+// the far splits' sums: density gradients conj(near) + conj(far), source position
+// near + far, normal psi-projection (near) + far normal gradient
+__global__ __launch_bounds__(256) void k_split_source_finalize(
+    int N, int kind, int n_asplit, const double4* __restrict__ geo,
+    const double2* __restrict__ nearp, const double2* __restrict__ farp,
+    double* __restrict__ sg) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const bool hasS = kind & 1, hasD = kind & 2;
+  const int nk = hasS && hasD ? 2 : 1;
+  const int ns = nk + 2;
+  double fd[2][2] = {{0, 0}, {0, 0}}, fx = 0.0, fy = 0.0, fnx = 0.0, fny = 0.0;
+  for (int sp = 0; sp < n_asplit; ++sp) {
+    for (int kk = 0; kk < nk; ++kk) {
+      const double2 v = farp[((size_t)sp * ns + kk) * N + j];
+      fd[kk][0] += v.x;
+      fd[kk][1] += v.y;
+    }
+    const double2 x = farp[((size_t)sp * ns + nk) * N + j];
+    const double2 n = farp[((size_t)sp * ns + nk + 1) * N + j];
+    fx += x.x;
+    fy += x.y;
+    fnx += n.x;
+    fny += n.y;
+  }
+  double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (hasS) {
+    const double2 a = nearp[j];
+    o[0] = a.x + fd[0][0];
+    o[1] = a.y - fd[0][1];
+  }
+  if (hasD) {
+    const double2 a = nearp[(size_t)(nk - 1) * N + j];
+    o[2] = a.x + fd[nk - 1][0];
+    o[3] = a.y - fd[nk - 1][1];
+  }
+  const double2 x = nearp[(size_t)nk * N + j];
+  o[4] = x.x + fx;
+  o[5] = x.y + fy;
+  o[6] = fnx;
+  o[7] = fny;
+  if (hasD) {
+    const double rp = nearp[(size_t)(nk + 1) * N + j].x;
+    const double4 g = geo[j];
+    o[6] += rp * g.w;   // Re(w mu Psi) (n_y, -n_x)
+    o[7] -= rp * g.z;
+  }
+  double* q = sg + (size_t)j * 8;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) q[b] = o[b];
 }
 
 // ---------------------------------------------------------------------------
@@ -795,6 +1046,95 @@ hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const doub
   hipLaunchKernelGGL(k_split_finalize, dim3((n + 255) / 256), dim3(256), 0, s, d.Mc, d.T, d.nk,
                      d.n_fsplit, nearp, farp, out);
   return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_split_nodes_near_p(const Dims& d, const double4* geo,
+                                            const double2* dens, const CenterRec* ctr,
+                                            const double* jtab, const double4* bnd, double g2,
+                                            const double2* G, double* cg, double2* spart,
+                                            hipStream_t s) {
+  const dim3 gc((unsigned)((d.Mc + 3) / 4)), block(256);
+  const int chunks = (d.N + kWave - 1) / kWave;
+  const dim3 gs((unsigned)((chunks + 3) / 4));
+#define QBX_NCG_ARGS \
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.side, bnd, d.P, g2, d.k, G, cg
+#define QBX_NSRC_ARGS \
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, d.k, G, spart
+  switch (d.kind) {
+    case 1:
+      hipLaunchKernelGGL((k_split_near_cg<P, 1>), gc, block, 0, s, QBX_NCG_ARGS);
+      hipLaunchKernelGGL((k_split_near_adj_nodes<P, 1>), gs, block, 0, s, QBX_NSRC_ARGS);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_split_near_cg<P, 2>), gc, block, 0, s, QBX_NCG_ARGS);
+      hipLaunchKernelGGL((k_split_near_adj_nodes<P, 2>), gs, block, 0, s, QBX_NSRC_ARGS);
+      break;
+    default:
+      hipLaunchKernelGGL((k_split_near_cg<P, 3>), gc, block, 0, s, QBX_NCG_ARGS);
+      hipLaunchKernelGGL((k_split_near_adj_nodes<P, 3>), gs, block, 0, s, QBX_NSRC_ARGS);
+      break;
+  }
+#undef QBX_NCG_ARGS
+#undef QBX_NSRC_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const double* density,
+                                      const double* tables, const double4* geo,
+                                      const double2* dens, const CenterRec* ctr,
+                                      const double* jtab, const double4* bnd, double g2,
+                                      const double2* G, double2* Gf, double* cg, double2* spart,
+                                      double2* fpart, double2* apart, double* sg,
+                                      double* grad_density, double* grad_nodes, hipStream_t s) {
+  hipError_t e;
+  {
+    auto launch = [&]() -> hipError_t {
+      QBX_P_SWITCH(d.p, launch_split_nodes_near_p, d, geo, dens, ctr, jtab, bnd, g2, G, cg, spart,
+                   s)
+    };
+    e = launch();
+    if (e != hipSuccess) return e;
+  }
+  const int nt = d.T * d.nk;
+  hipLaunchKernelGGL(k_split_gfar, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.nk, d.n_sides,
+                     G, Gf);
+  // far, target side: the split's far target gradients, contracted with Gf
+  {
+    const int n_tb = (d.T + kWave - 1) / kWave;
+    const long waves = (long)n_tb * d.n_fsplit;
+    const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_FGRAD_ARGS \
+  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, fpart
+    switch (d.kind) {
+      case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+      case 2: hipLaunchKernelGGL((k_split_far_grad<2>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+      default: hipLaunchKernelGGL((k_split_far_grad<3>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
+    }
+#undef QBX_FGRAD_ARGS
+    hipLaunchKernelGGL(k_split_far_tgrad, dim3((d.T + 255) / 256), dim3(256), 0, s, d.T, d.nk,
+                       d.n_fsplit, Gf, fpart, cg);
+  }
+  // far, source side
+  {
+    const int n_sb = (d.N + kWave - 1) / kWave;
+    const long waves = (long)n_sb * d.n_asplit;
+    const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define QBX_FADJ_ARGS                                                                       \
+  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,                \
+      d.panels_per_asplit, apart
+    switch (d.kind) {
+      case 1: hipLaunchKernelGGL((k_split_far_adj<1, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+      case 2: hipLaunchKernelGGL((k_split_far_adj<2, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+      default: hipLaunchKernelGGL((k_split_far_adj<3, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
+    }
+#undef QBX_FADJ_ARGS
+  }
+  hipLaunchKernelGGL(k_split_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N,
+                     d.kind, d.n_asplit, geo, spart, apart, sg);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_chain(d, nodes, density, tables, sg, cg, grad_density, grad_nodes, s);
 }
 
 }  // namespace qbx

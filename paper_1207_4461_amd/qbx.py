@@ -227,8 +227,8 @@ def layer_potential_split(nodes: torch.Tensor, density: torch.Tensor, k: float, 
     """Near/far split forward (qbx_layer_potential_split): QBX for the sources of
     panels within gamma panel radii of the target's panel, the smooth rule applied
     directly for all others.  out[n_sides, n_kinds, 16*P] complex128, exterior
-    first.  Its density adjoint is layer_potential_split_vjp (qbx_apply with gamma);
-    it has no node gradient."""
+    first.  Its adjoint (density and nodes) is layer_potential_split_vjp, and qbx_apply
+    with gamma is the differentiable form."""
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
@@ -274,10 +274,13 @@ def layer_potential_split_gradient(nodes: torch.Tensor, density: torch.Tensor, k
 def layer_potential_split_vjp(nodes: torch.Tensor, density: torch.Tensor,
                               cotangent: torch.Tensor, k: float, p: int, r: float = 0.5,
                               oversample: int = 4, side: int = EXTERIOR, kind: int = S,
-                              gamma: float = 6.0,
-                              workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Density gradient of L = Re <cotangent, layer_potential_split(...)>
-    (qbx_layer_potential_split_adjoint): [n_kinds, 16P] complex128."""
+                              gamma: float = 6.0, want_nodes: bool = False,
+                              want_density: bool = True,
+                              workspace: Optional[torch.Tensor] = None):
+    """Gradients of L = Re <cotangent, layer_potential_split(...)>
+    (qbx_layer_potential_split_adjoint).  Returns the density gradient [n_kinds, 16P]
+    complex128, or with want_nodes the pair (density gradient or None, node gradient
+    [P, 16, 2])."""
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
@@ -285,14 +288,16 @@ def layer_potential_split_vjp(nodes: torch.Tensor, density: torch.Tensor,
     _need(density, "density", torch.complex128, (nk, P * Q))
     _need(cotangent, "cotangent", torch.complex128, (n_sides(side), nk, P * Q))
     dev = nodes.device
-    gd = torch.empty((nk, P * Q), dtype=torch.complex128, device=dev)
+    gd = torch.empty((nk, P * Q), dtype=torch.complex128, device=dev) if (
+        want_density or not want_nodes) else None
+    gn = torch.empty((P, Q, 2), dtype=torch.float64, device=dev) if want_nodes else None
     ws = _workspace(workspace_bytes(P, p, oversample, side, kind), dev, workspace)
     geo = _lib.Geometry(P, Q, nodes.data_ptr())
     _lib.check(lib.qbx_layer_potential_split_adjoint(
         C.byref(geo), density.data_ptr(), float(k), int(p), float(r), int(oversample), int(side),
-        int(kind), float(gamma), cotangent.data_ptr(), gd.data_ptr(), ws.data_ptr(), ws.numel(),
-        _stream(dev)))
-    return gd
+        int(kind), float(gamma), cotangent.data_ptr(), gd.data_ptr() if gd is not None else None,
+        gn.data_ptr() if gn is not None else None, ws.data_ptr(), ws.numel(), _stream(dev)))
+    return (gd, gn) if want_nodes else gd
 
 
 def solve_workspace_bytes(n_panels: int, p: int, oversample: int, side: int, restart: int) -> int:
@@ -382,8 +387,15 @@ class _DirichletSolve(torch.autograd.Function):
             cs = (0.5 * complex(alpha).conjugate()) * lam
             cd = -0.5 * lam
             cot = torch.stack([torch.stack([cs, cd]), torch.stack([cs, cd])])
-            _, gnodes = layer_potential_vjp(nodes.detach(), torch.stack([sigma, sigma]), cot, k,
-                                            p, r, oversample, BOTH, S | D, want_density=False)
+            if gamma > 0.0:
+                _, gnodes = layer_potential_split_vjp(nodes.detach(), torch.stack([sigma, sigma]),
+                                                      cot, k, p, r, oversample, BOTH, S | D,
+                                                      gamma=gamma, want_nodes=True,
+                                                      want_density=False)
+            else:
+                _, gnodes = layer_potential_vjp(nodes.detach(), torch.stack([sigma, sigma]), cot,
+                                                k, p, r, oversample, BOTH, S | D,
+                                                want_density=False)
             gn = -gnodes
         gf = lam if ctx.needs_input_grad[1] else None
         return gn, gf, None, None, None, None, None, None, None, None, None, None
@@ -393,11 +405,10 @@ def dirichlet_solve_apply(nodes: torch.Tensor, f: torch.Tensor, k: float, p: int
                           r: float = 0.5, oversample: int = 4, side: int = EXTERIOR,
                           alpha: complex = 1j, gamma: float = 0.0, tol: float = 1e-14,
                           restart: int = 100, max_iter: int = 1000) -> torch.Tensor:
-    """Differentiable solve_dirichlet: sigma with gradients for f (an adjoint solve) and,
-    with plain QBX products (gamma = 0), for the nodes.  Raises RuntimeError when either
-    solve ends (max_iter) with a true relative residual above 100 tol."""
-    if gamma > 0.0 and nodes.requires_grad:
-        raise ValueError("the near/far split has no node gradient: detach the nodes")
+    """Differentiable solve_dirichlet: sigma with gradients for f (an adjoint solve) and
+    for the nodes (the products' node adjoint, plain or split as gamma says).  Raises
+    RuntimeError when either solve ends (max_iter) with a true relative residual above
+    100 tol."""
     return _DirichletSolve.apply(nodes, f, float(k), int(p), float(r), int(oversample), int(side),
                                  complex(alpha), float(gamma), float(tol), int(restart),
                                  int(max_iter))
@@ -574,8 +585,8 @@ class _LayerPotential(torch.autograd.Function):
 
 
 class _SplitLayerPotential(torch.autograd.Function):
-    """out = layer_potential_split(nodes, density, ...) with its density adjoint as backward
-    (the split forms no node gradient)."""
+    """out = layer_potential_split(nodes, density, ...) with its adjoint as backward
+    (density and node gradients)."""
 
     @staticmethod
     def forward(ctx, nodes, density, k, p, r, oversample, side, kind, gamma):
@@ -589,23 +600,23 @@ class _SplitLayerPotential(torch.autograd.Function):
     def backward(ctx, grad_out):
         nodes, density = ctx.saved_tensors
         k, p, r, oversample, side, kind, gamma = ctx.args
-        gd = None
-        if ctx.needs_input_grad[1]:
-            gd = layer_potential_split_vjp(nodes.detach(), density.detach(),
-                                           grad_out.contiguous().to(torch.complex128), k, p, r,
-                                           oversample, side, kind, gamma=gamma)
-        return None, gd, None, None, None, None, None, None, None
+        want_n, want_d = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gd = gn = None
+        if want_n or want_d:
+            res = layer_potential_split_vjp(nodes.detach(), density.detach(),
+                                            grad_out.contiguous().to(torch.complex128), k, p, r,
+                                            oversample, side, kind, gamma=gamma,
+                                            want_nodes=want_n, want_density=want_d)
+            gd, gn = res if want_n else (res, None)
+        return gn, gd, None, None, None, None, None, None, None
 
 
 def qbx_apply(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
               oversample: int = 4, side: int = EXTERIOR, kind: int = S,
               gamma: Optional[float] = None) -> torch.Tensor:
     """Differentiable layer_potential (gradients for density and nodes via the HIP adjoint).
-    With gamma: the near/far split (layer_potential_split) and its density adjoint; the
-    nodes must then not require a gradient (the split forms none)."""
+    With gamma: the near/far split (layer_potential_split) and its adjoint, also for both."""
     if gamma is not None:
-        if nodes.requires_grad:
-            raise ValueError("the near/far split has no node gradient: detach the nodes")
         return _SplitLayerPotential.apply(nodes, density, float(k), int(p), float(r),
                                           int(oversample), int(side), int(kind), float(gamma))
     return _LayerPotential.apply(nodes, density, float(k), int(p), float(r), int(oversample),

@@ -175,10 +175,11 @@ def test_split_adjoint_entry_point_validates(lib):
     def call(**kw):
         return lib.qbx_layer_potential_split_adjoint(
             C.byref(g), kw.get("dens", BAD), 3.0, 6, 0.5, 4, 1, 1, kw.get("gamma", 6.0),
-            kw.get("cot", BAD), kw.get("gd", BAD), kw.get("ws", BAD), kw.get("nbytes", 1 << 40),
-            None)
+            kw.get("cot", BAD), kw.get("gd", BAD), kw.get("gn", None), kw.get("ws", BAD),
+            kw.get("nbytes", 1 << 40), None)
 
-    for bad in (dict(gamma=0.0), dict(dens=None), dict(cot=None), dict(gd=None), dict(ws=None)):
+    for bad in (dict(gamma=0.0), dict(dens=None), dict(cot=None), dict(gd=None), dict(ws=None),
+                dict(gd=None, gn=None), dict(gn=BAD, ws=None)):
         assert call(**bad) == _lib.QBX_EINVAL, bad
     assert call(nbytes=lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1) - 1) == _lib.QBX_EWORKSPACE
 

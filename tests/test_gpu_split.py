@@ -15,6 +15,7 @@ from parity_helpers import bar, ulp_perturbed
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-11
+NODE_TOL = 1e-10   # node gradients, as for the plain adjoint
 
 
 @pytest.fixture(scope="module")
@@ -188,6 +189,82 @@ def test_split_density_adjoint_dot_product(Q, cfg):
     assert e < 1e-12
 
 
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[c["name"] for c in ADJ_CASES])
+def test_split_node_adjoint_small(Q, case):
+    """Density and node gradients of the split against the oracle's autograd through
+    its split (split_vjp), element by element."""
+    c = dict(case)
+    name, gamma = c.pop("name"), c.pop("gamma")
+    pb = I.small(name=name, **c)
+    rd, rn = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                         pb.kind, pb.cotangent, gamma)
+    gd, gn = Q.layer_potential_split_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent),
+                                         pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                         gamma=gamma, want_nodes=True)
+    ed, en = rel(gd.cpu().numpy(), rd), rel(gn.cpu().numpy(), rn)
+    _, gn_only = Q.layer_potential_split_vjp(dev(pb.nodes), dev(pb.density), dev(pb.cotangent),
+                                             pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                                             gamma=gamma, want_nodes=True, want_density=False)
+    say(f"  {name}: density {ed:.3e}, nodes {en:.3e} vs oracle autograd")
+    assert ed <= TOL and en <= NODE_TOL
+    assert torch.equal(gn_only, gn)
+
+
+def test_split_node_adjoint_all_near_is_the_plain_adjoint(Q):
+    pb = I.small(n_panels=9, p=11, k=6.0, kind=3, side=I.BOTH)
+    args = (pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    nodes, dens, cot = dev(pb.nodes), dev(pb.density), dev(pb.cotangent)
+    a_d, a_n = Q.layer_potential_split_vjp(nodes, dens, cot, *args, gamma=1e150, want_nodes=True)
+    b_d, b_n = Q.layer_potential_vjp(nodes, dens, cot, *args)
+    ed = rel(a_d.cpu().numpy(), b_d.cpu().numpy())
+    en = rel(a_n.cpu().numpy(), b_n.cpu().numpy())
+    say(f"  all-near split vs plain adjoint: density {ed:.2e}, nodes {en:.2e}")
+    assert ed < 1e-13 and en < 1e-12
+
+
+@pytest.mark.parametrize("cfg", ["star256", "star1024"])
+def test_split_node_adjoint_full_size(Q, cfg):
+    """At full size: translation and rotation invariance of the node gradient, the
+    dot-product identity for the density, and a Richardson central difference of the
+    split forward along a smooth deformation (the near relation checked unchanged)."""
+    pb = getattr(I, cfg)()
+    nodes, dens = dev(pb.nodes), dev(pb.density)
+    rng = np.random.default_rng(4)
+    gc = rng.standard_normal((pb.n_sides, pb.n_kinds, pb.n_targets)) \
+        + 1j * rng.standard_normal((pb.n_sides, pb.n_kinds, pb.n_targets))
+    g = dev(gc)
+    args = (pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    gamma = 6.0
+    gd, gn = Q.layer_potential_split_vjp(nodes, dens, g, *args, gamma=gamma, want_nodes=True)
+    gn = gn.cpu().numpy()
+    scale = np.abs(gn).sum()
+    trans = np.abs(gn.sum(axis=(0, 1))).max() / scale
+    torque = abs(np.sum(pb.nodes[..., 0] * gn[..., 1] - pb.nodes[..., 1] * gn[..., 0])) / (
+        scale * np.abs(pb.nodes).max())
+    u = Q.layer_potential_split(nodes, dens, *args, gamma=gamma)
+    lhs = float(torch.real(torch.sum(torch.conj(g) * u)))
+    rhs = float(torch.real(torch.sum(torch.conj(gd) * dens)))
+    t = I.panel_parameters(pb.n_panels)
+    E = np.stack([np.sin(3 * t), np.cos(2 * t)], -1)
+
+    def L(h):
+        X = pb.nodes + h * E
+        v = Q.layer_potential_split(dev(X), dens, *args, gamma=gamma)
+        return float(torch.real(torch.sum(torch.conj(g) * v)))
+
+    near0 = O.near_panels(pb.nodes, gamma)
+    for h in (-2e-5, 2e-5):
+        assert np.array_equal(O.near_panels(pb.nodes + h * E, gamma), near0)
+    fd = lambda h: (L(h) - L(-h)) / (2 * h)
+    rich = (4.0 * fd(5e-6) - fd(1e-5)) / 3.0
+    an = float(np.sum(gn * E))
+    say(f"  {cfg}: translation {trans:.1e} rotation {torque:.1e} dot {abs(lhs - rhs) / abs(lhs):.1e}"
+        f" FD {rich:.10e} adjoint {an:.10e} ({abs(rich - an) / abs(an):.1e})")
+    assert trans < 1e-12 and torque < 1e-12
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    assert abs(rich - an) <= 1e-6 * abs(an)
+
+
 def test_split_autograd_function(Q):
     pb = I.small(n_panels=10, p=8, k=4.0, kind=3, side=I.BOTH)
     nodes = dev(pb.nodes)
@@ -201,8 +278,16 @@ def test_split_autograd_function(Q):
                                gamma=4.0)
     assert torch.autograd.gradcheck(f, (dens.detach().clone().requires_grad_(True),),
                                     eps=1e-7, atol=1e-6, rtol=1e-5)
-    with pytest.raises(ValueError):
-        Q.qbx_apply(nodes.clone().requires_grad_(True), dens, pb.k, pb.p, gamma=4.0)
+    # the nodes too
+    xn = nodes.clone().requires_grad_(True)
+    u = Q.qbx_apply(xn, dens.detach(), pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                    gamma=4.0)
+    torch.real(torch.sum(torch.conj(dev(pb.cotangent)) * u)).backward()
+    _, rn = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                        pb.cotangent, 4.0)
+    e = rel(xn.grad.cpu().numpy(), rn)
+    say(f"  qbx_apply(gamma) node gradient vs oracle autograd {e:.3e}")
+    assert e <= NODE_TOL
 
 
 GRAD_CASES = [

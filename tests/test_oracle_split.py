@@ -211,3 +211,72 @@ def test_planted_direct_gradient_mistake_is_caught(monkeypatch):
     bad = O.direct_gradient(src, dens, tx, ty, pb.k, 3, sel)["D"]
     monkeypatch.setattr(O, "hankel1", orig)
     assert rel(bad.numpy(), good.numpy()) > 1e-2
+
+
+# ---------------------------------------------------------------------------
+# node gradient of the split (split_vjp: autograd through the split's steps)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def split_tiny():
+    pb = I.small(n_panels=8, p=6, k=4.0, kind=3, side=I.BOTH, oversample=2)
+    gamma = 2.0   # three near panels per panel, five far
+    gd, gn = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                         pb.kind, pb.cotangent, gamma)
+    return pb, gamma, gd, gn
+
+
+def _split_L(pb, gamma, X):
+    return O.split_loss(X, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                        pb.cotangent, gamma)
+
+
+def test_split_node_gradient_central_differences(split_tiny):
+    pb, gamma, _, gn = split_tiny
+    assert (O.near_panels(pb.nodes, gamma).sum(1) < pb.n_panels).all()
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        E = rng.standard_normal(pb.nodes.shape)
+        fd = lambda h: (_split_L(pb, gamma, pb.nodes + h * E)
+                        - _split_L(pb, gamma, pb.nodes - h * E)) / (2 * h)
+        rich = (4.0 * fd(1e-6) - fd(2e-6)) / 3.0
+        an = float(np.sum(gn * E))
+        assert abs(rich - an) <= 1e-7 * abs(an)
+    for (m, a, d) in [(0, 0, 0), (3, 8, 1), (7, 15, 0)]:
+        E = np.zeros_like(pb.nodes)
+        E[m, a, d] = 1.0
+        h = 1e-6
+        fd = (_split_L(pb, gamma, pb.nodes + h * E) - _split_L(pb, gamma, pb.nodes - h * E)) / (2 * h)
+        assert abs(fd - gn[m, a, d]) <= 1e-6 * max(1.0, abs(gn[m, a, d]))
+
+
+def test_split_gradient_with_every_panel_near_is_the_qbx_gradient():
+    pb = I.small(n_panels=6, p=6, k=4.0, kind=3, side=I.BOTH, oversample=2)
+    gd, gn = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                         pb.kind, pb.cotangent, 1e3)
+    rd, rn = O.vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind,
+                   pb.cotangent)
+    assert rel(gn, rn) < 1e-12 and rel(gd, rd) < 1e-12
+
+
+def test_split_gradient_invariances(split_tiny):
+    pb, gamma, gd, gn = split_tiny
+    scale = np.abs(gn).sum()
+    assert np.abs(gn.sum(axis=(0, 1))).max() < 1e-13 * scale
+    torque = np.sum(pb.nodes[..., 0] * gn[..., 1] - pb.nodes[..., 1] * gn[..., 0])
+    assert abs(torque) < 1e-13 * scale * np.abs(pb.nodes).max()
+    L = _split_L(pb, gamma, pb.nodes)
+    assert abs(np.real(np.vdot(gd, pb.density)) - L) < 1e-13 * abs(L)
+
+
+def test_planted_split_gradient_mistake_is_caught(split_tiny, monkeypatch):
+    """The far rule with its target held fixed (the target's own motion dropped)."""
+    pb, gamma, _, gn = split_tiny
+    orig = O.direct_sum
+
+    def frozen_target(src, dens, tx, ty, k, kind, sel):
+        return orig(src, dens, tx.detach(), ty.detach(), k, kind, sel)
+
+    monkeypatch.setattr(O, "direct_sum", frozen_target)
+    _, bad = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
+                         pb.kind, pb.cotangent, gamma)
+    assert rel(bad, gn) > 1e-3
