@@ -74,7 +74,9 @@ enum qbx_status {
   QBX_EORIENT = -3,    /* clockwise contour (negative signed area)                   */
   QBX_EGRAF = -4,      /* a source lies inside a center's disk: Graf's condition
                           |x - c| < |x' - c| (Section 2, eq. x-c-closest) fails     */
-  QBX_EDEVICE = -5     /* a HIP call failed; see qbx_last_error()                  */
+  QBX_EDEVICE = -5,    /* a HIP call failed; see qbx_last_error()                  */
+  QBX_EIO = -6         /* an autotuner cache file could not be read or written, or
+                          holds a malformed entry                                    */
 };
 
 typedef struct {
@@ -86,7 +88,12 @@ typedef struct {
 /* ---- sizes ------------------------------------------------------------- */
 
 /* Workspace bytes for qbx_layer_potential / _adjoint with these parameters
- * (0 if the parameters are invalid). */
+ * (0 if the parameters are invalid).  The size depends on the process-wide
+ * tuning (qbx_set_tuning: the launch shapes set the number of partial sums),
+ * so a workspace sized under one tuning can be too small under another, which
+ * the entry points report as QBX_EWORKSPACE: query again after a tuning
+ * change, or size for the largest shapes (qbx_autotune_workspace_bytes covers
+ * every shape the autotuner tries, and more). */
 size_t qbx_workspace_bytes(int n_panels, int q, int p, int oversample, int side, int kind);
 
 /* Bytes of the forward's tape (the per-center data the adjoint reuses). */
@@ -270,6 +277,29 @@ int qbx_solve_dirichlet_adjoint(const qbx_geometry* g, const double* rhs, double
                                 int max_iter, double* lambda, int* iterations, double* residual,
                                 void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes of qbx_solve_dirichlet_node_gradient (0 if invalid). */
+size_t qbx_solve_node_gradient_workspace_bytes(int n_panels, int q, int p, int oversample);
+
+/* Node part of the gradient through the solve.  For sigma = A(x)^-1 f (the
+ * operator of qbx_solve_dirichlet) and a real loss L(sigma), the gradient
+ * with respect to the nodes x is -grad_x Re <lambda, A(x) sigma> with sigma
+ * held fixed and lambda = A^-H dL/dsigma (qbx_solve_dirichlet_adjoint).  The
+ * -+ sigma/2 term does not depend on x, so this is one node adjoint of the
+ * layer potentials (both sides, S and D, density sigma) with the cotangents
+ * -conj(alpha) lambda / 2 for S and lambda / 2 for D on each side (the
+ * averages of the two limits), formed on the device; the split's node
+ * adjoint when gamma > 0.
+ *   sigma, lambda  device [16 P] complex
+ *   side           1 or -1, as for the solve (validated only)
+ *   grad_nodes     device [P][16][2], out
+ * Stream-ordered, no allocation; the workspace is
+ * qbx_solve_node_gradient_workspace_bytes(). */
+int qbx_solve_dirichlet_node_gradient(const qbx_geometry* g, const double* sigma,
+                                      const double* lambda, double k, int p, double r,
+                                      int oversample, int side, double alpha_re, double alpha_im,
+                                      double gamma, double* grad_nodes, void* ws,
+                                      size_t ws_bytes, hipStream_t stream);
+
 /* ---- adjoint ----------------------------------------------------------- */
 
 /* Vector-Jacobian product of qbx_layer_potential for the real scalar
@@ -314,7 +344,9 @@ typedef struct {
   double r;
 } qbx_batch_item;
 
-/* Workspace / tape bytes for a batch (items in HOST memory; 0 if invalid). */
+/* Workspace / tape bytes for a batch (items in HOST memory; 0 if invalid).
+ * As for qbx_workspace_bytes, the workspace size depends on the tuning
+ * (batch_adjoint_tasks, batch_fused_chunks): query again after a change. */
 size_t qbx_batched_workspace_bytes(const qbx_batch_item* items, int n_items, int oversample);
 size_t qbx_batched_tape_bytes(const qbx_batch_item* items, int n_items);
 
@@ -577,31 +609,54 @@ int qbx_get_tuning(qbx_tuning* t);
 #define QBX_TUNE_FUSED 8     /* fused_tiles; batched: batch_fused_chunks */
 #define QBX_TUNE_ALL 15
 
+/* Workspace bytes of qbx_autotune (0 for invalid arguments): a workspace for
+ * every candidate launch shape plus the output, tape and gradients it times. */
+size_t qbx_autotune_workspace_bytes(int n_panels, int q, int p, int oversample, int side,
+                                    int kind);
+
 /* Autotuner for one contour problem (the arguments of qbx_layer_potential).
- * SYNCHRONOUS, and unlike every other entry point it ALLOCATES (and frees)
- * device memory of its own: workspace, output, tape and gradients.  For each
- * field selected in `fields` -- forward_waves, tape_waves and adjoint_waves
- * over 2048 .. 131072, fused_tiles over 2048 .. 32768 (doubling; candidates
- * that give the same launch shape are timed once) -- it times its pass with
- * hipEvents on `stream`, the minimum over `passes` runs (1..20) after one
- * warm-up, keeps the fastest, installs the result with qbx_set_tuning and
- * writes it to *best (nullable).  Other fields are left as they were.  On
- * error the previous tuning is restored. */
+ * SYNCHRONOUS.  For each field selected in `fields` -- forward_waves,
+ * tape_waves and adjoint_waves over 2048 .. 131072, fused_tiles over
+ * 2048 .. 32768 (doubling; candidates that give the same launch shape are
+ * timed once) -- it times its pass with hipEvents on `stream`, the minimum
+ * over `passes` runs (1..20) after one warm-up, keeps the fastest, installs
+ * the result with qbx_set_tuning and writes it to *best (nullable).  Other
+ * fields are left as they were.  On error the previous tuning is restored.
+ *   ws, ws_bytes  device workspace of qbx_autotune_workspace_bytes() bytes: all
+ *                 device memory the timing uses (nothing is allocated)
+ *   cache_path    host path of a text cache file, or NULL.  A line
+ *                 "<key> => <value>" per result, the key naming the device
+ *                 (architecture, compute units) and the problem (P, p,
+ *                 oversample, side, kind, fields).  On a hit the stored fields
+ *                 are installed untimed (ws may then be NULL); on a miss the
+ *                 result is timed and written back (the file is rewritten
+ *                 through a temporary file and a rename).  QBX_EIO for an
+ *                 unreadable or unwritable file or a malformed entry; calls that
+ *                 share a file from several processes at once may lose a line.
+ */
 int qbx_autotune(const qbx_geometry* g, const double* density, double k, int p, double r,
-                 int oversample, int side, int kind, int passes, int fields, qbx_tuning* best,
+                 int oversample, int side, int kind, int passes, int fields,
+                 const char* cache_path, qbx_tuning* best, void* ws, size_t ws_bytes,
                  hipStream_t stream);
 
+/* Workspace bytes of qbx_autotune_batched (0 for an invalid batch). */
+size_t qbx_autotune_batched_workspace_bytes(const qbx_batch_item* items, int n_items,
+                                            int oversample);
+
 /* Autotuner for a batch (the arguments of qbx_layer_potential_batched; items
- * in host memory, arrays on the device).  SYNCHRONOUS and ALLOCATING like
- * qbx_autotune.  Times, as selected in `fields`, batch_grid_scale in
- * {0.5, 1, 2, 4} on the batched forward, batch_adjoint_tasks in
- * 2048 .. 262144 (doubling) on the batched adjoint with the tape and
- * batch_fused_chunks in {4, 8, 16, 32} on the batched adjoint without it
- * (QBX_TUNE_TAPE selects nothing here), keeps the fastest of each and
- * installs them. */
+ * in host memory, arrays on the device).  SYNCHRONOUS.  Times, as selected in
+ * `fields`, batch_grid_scale in {0.5, 1, 2, 4} on the batched forward,
+ * batch_adjoint_tasks in 2048 .. 262144 (doubling) on the batched adjoint
+ * with the tape and batch_fused_chunks in {4, 8, 16, 32} on the batched
+ * adjoint without it (QBX_TUNE_TAPE selects nothing here), keeps the fastest
+ * of each and installs them.  ws, cache_path: as qbx_autotune, with
+ * qbx_autotune_batched_workspace_bytes() and a key naming the device, the
+ * item count, oversample, fields and a 64-bit signature of the items'
+ * (n_panels, p, kind, side). */
 int qbx_autotune_batched(const qbx_batch_item* items, int n_items, const double* nodes,
                          const double* density, int oversample, int passes, int fields,
-                         qbx_tuning* best, hipStream_t stream);
+                         const char* cache_path, qbx_tuning* best, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
 
 /* ---- kernel timing (profiling hook) ----------------------------------- */
 

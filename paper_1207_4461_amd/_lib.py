@@ -1,7 +1,8 @@
 """ctypes binding of libqbx.so (include/qbx.h): argument marshalling only.
 
-The library is the in-tree ``libqbx.so`` built by ``paper_1207_4461_amd.build``;
-loading fails loudly when it is missing (there is no fallback path).
+The library is the in-tree ``libqbx.so`` built by ``paper_1207_4461_amd.build``
+(or the file QBX_LIB names, such as the sanitizer build); loading fails loudly
+when it is missing (there is no fallback path).
 """
 from __future__ import annotations
 
@@ -9,7 +10,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqbx.so")
+LIB_PATH = os.environ.get("QBX_LIB") or os.path.join(HERE, "libqbx.so")
 
 QBX_TUNE_FORWARD, QBX_TUNE_TAPE, QBX_TUNE_ADJOINT, QBX_TUNE_FUSED, QBX_TUNE_ALL = 1, 2, 4, 8, 15
 QBX_TIMER_CLASSES = 9   # entries qbx_kernel_timer_read writes
@@ -19,6 +20,7 @@ QBX_EWORKSPACE = -2
 QBX_EORIENT = -3
 QBX_EGRAF = -4
 QBX_EDEVICE = -5
+QBX_EIO = -6
 
 QBX_S = 1
 QBX_D = 2
@@ -128,10 +130,15 @@ def load() -> C.CDLL:
                                              vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "qbx_set_tuning": (i32, [C.POINTER(Tuning)]),
         "qbx_get_tuning": (i32, [C.POINTER(Tuning)]),
-        "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, i32, C.POINTER(Tuning),
-                               vp]),
+        "qbx_solve_node_gradient_workspace_bytes": (sz, [i32, i32, i32, i32]),
+        "qbx_solve_dirichlet_node_gradient": (i32, [gp, vp, vp, dbl, i32, dbl, i32, i32, dbl, dbl,
+                                                    dbl, vp, vp, sz, vp]),
+        "qbx_autotune_workspace_bytes": (sz, [i32, i32, i32, i32, i32, i32]),
+        "qbx_autotune": (i32, [gp, vp, dbl, i32, dbl, i32, i32, i32, i32, i32, C.c_char_p,
+                               C.POINTER(Tuning), vp, sz, vp]),
+        "qbx_autotune_batched_workspace_bytes": (sz, [C.POINTER(BatchItem), i32, i32]),
         "qbx_autotune_batched": (i32, [C.POINTER(BatchItem), i32, vp, vp, i32, i32, i32,
-                                       C.POINTER(Tuning), vp]),
+                                       C.c_char_p, C.POINTER(Tuning), vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

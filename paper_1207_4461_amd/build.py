@@ -2,6 +2,7 @@
 
 Every source under csrc/ is compiled as HIP for gfx950, one object per
 source (in parallel), then linked into paper_1207_4461_amd/libqbx.so.
+(build_sanitized.py builds a host-sanitizer copy for CPU runs of the host checks.)
 """
 from __future__ import annotations
 
@@ -15,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqbx.so")
+
 # (source, object name, extra flags), slowest first; the batched forward source is
 # compiled once per mode
 SOURCES = [("qbx_batched_fwd.hip", "qbx_batched_fwd1", ["-DQBX_FWD_MODE=1"]),
@@ -58,9 +60,11 @@ def _entry(e):
     return e
 
 
-def _compile(entry, verbose: bool, force: bool = True) -> str:
+def _compile(entry, verbose: bool, force: bool = True, outdir: str = BUILD,
+             extra=()) -> str:
     src, name, flags = _entry(entry)
-    obj = os.path.join(BUILD, name + ".o")
+    flags = [*flags, *extra]
+    obj = os.path.join(outdir, name + ".o")
     if not force and _up_to_date(src, obj):
         return obj
     cmd = [_hipcc(), "-x", "hip", *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj]

@@ -749,6 +749,7 @@ const char* qbx_strerror(int code) {
     case QBX_EORIENT: return "contour is clockwise";
     case QBX_EGRAF: return "Graf condition violated (source inside an expansion disk)";
     case QBX_EDEVICE: return "HIP device error";
+    case QBX_EIO: return "autotuner cache file error";
     default: return "unknown error";
   }
 }

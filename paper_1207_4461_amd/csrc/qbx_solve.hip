@@ -189,6 +189,27 @@ __global__ __launch_bounds__(256) void k_adj_combine(int T, const double2* __res
   y[t] = make_double2(fma(half, v[t].x, inv * (a.x - d.x)), fma(half, v[t].y, inv * (a.y - d.y)));
 }
 
+// node gradient of the solve: dens = [sigma; sigma] and, on both sides,
+// cot[si][0] = -conj(alpha) lambda / 2 (S) and cot[si][1] = lambda / 2 (D), the
+// cotangents whose layer-potential node adjoint is -grad_x Re <lambda, A(x) sigma>
+__global__ __launch_bounds__(256) void k_node_cot(int T, const double2* __restrict__ sigma,
+                                                  const double2* __restrict__ lambda,
+                                                  double2 alpha, double2* __restrict__ dens,
+                                                  double2* __restrict__ cot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double2 sg = sigma[t], lm = lambda[t];
+  dens[t] = sg;
+  dens[T + t] = sg;
+  const double2 ca = cmul(make_double2(alpha.x, -alpha.y), lm);
+  const double2 cs = make_double2(-0.5 * ca.x, -0.5 * ca.y);
+  const double2 cd = make_double2(0.5 * lm.x, 0.5 * lm.y);
+  cot[t] = cs;
+  cot[T + t] = cd;
+  cot[2 * T + t] = cs;
+  cot[3 * T + t] = cd;
+}
+
 __global__ __launch_bounds__(256) void k_zero(int n, double2* __restrict__ y) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) y[t] = make_double2(0.0, 0.0);
@@ -485,6 +506,51 @@ int qbx_solve_dirichlet(const qbx_geometry* g, const double* f, double k, int p,
                         double* residual, void* ws, size_t ws_bytes, hipStream_t stream) {
   return solve(g, f, k, p, r, oversample, side, alpha_re, alpha_im, gamma, tol, restart, max_iter,
                false, sigma, iterations, residual, ws, ws_bytes, stream);
+}
+
+size_t qbx_solve_node_gradient_workspace_bytes(int n_panels, int q, int p, int oversample) {
+  Dims d;
+  if (!make_dims(n_panels, q, p, oversample, QBX_BOTH, 3, 1.0, 0.5, &d)) return 0;
+  return align256(make_layout(d).total) + align256(sizeof(double2) * 2 * (size_t)d.T) +
+         align256(sizeof(double2) * 4 * (size_t)d.T);
+}
+
+int qbx_solve_dirichlet_node_gradient(const qbx_geometry* g, const double* sigma,
+                                      const double* lambda, double k, int p, double r,
+                                      int oversample, int side, double alpha_re, double alpha_im,
+                                      double gamma, double* grad_nodes, void* ws,
+                                      size_t ws_bytes, hipStream_t stream) {
+  if (side != QBX_EXTERIOR && side != QBX_INTERIOR)
+    return fail(QBX_EINVAL, "side = %d: the Dirichlet problem takes 1 or -1", side);
+  Dims d;
+  int rc = validate(g, p, k, r, oversample, QBX_BOTH, 3, &d);
+  if (rc) return rc;
+  if (!sigma || !lambda || !grad_nodes) return fail(QBX_EINVAL, "NULL array argument");
+  if (!std::isfinite(alpha_re) || !std::isfinite(alpha_im))
+    return fail(QBX_EINVAL, "alpha is not finite");
+  if (!(gamma >= 0.0)) return fail(QBX_EINVAL, "near-panel factor gamma = %g must be >= 0", gamma);
+  if (!ws) return fail(QBX_EINVAL, "workspace is NULL");
+  const size_t fws = make_layout(d).total;
+  const size_t o_dens = align256(fws), o_cot = o_dens + align256(sizeof(double2) * 2 * (size_t)d.T);
+  const size_t need = o_cot + align256(sizeof(double2) * 4 * (size_t)d.T);
+  if (ws_bytes < need)
+    return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  char* w = static_cast<char*>(ws);
+  double2* dens = reinterpret_cast<double2*>(w + o_dens);
+  double2* cot = reinterpret_cast<double2*>(w + o_cot);
+  hipLaunchKernelGGL(k_node_cot, dim3((d.T + 255) / 256), dim3(256), 0, stream, d.T,
+                     reinterpret_cast<const double2*>(sigma),
+                     reinterpret_cast<const double2*>(lambda), make_double2(alpha_re, alpha_im),
+                     dens, cot);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return device_fail(e, "node-gradient cotangent kernel");
+  const double* dp = reinterpret_cast<const double*>(dens);
+  const double* cp = reinterpret_cast<const double*>(cot);
+  if (gamma > 0.0)
+    return qbx_layer_potential_split_adjoint(g, dp, k, p, r, oversample, QBX_BOTH, 3, gamma, cp,
+                                             nullptr, grad_nodes, ws, fws, stream);
+  return qbx_layer_potential_adjoint(g, dp, k, p, r, oversample, QBX_BOTH, 3, cp, nullptr, nullptr,
+                                     grad_nodes, ws, fws, stream);
 }
 
 int qbx_solve_dirichlet_adjoint(const qbx_geometry* g, const double* rhs, double k, int p,

@@ -350,6 +350,33 @@ def solve_dirichlet_adjoint(nodes: torch.Tensor, g: torch.Tensor, k: float, p: i
                   gamma, tol, restart, max_iter, workspace)
 
 
+def solve_dirichlet_node_gradient(nodes: torch.Tensor, sigma: torch.Tensor, lam: torch.Tensor,
+                                  k: float, p: int, r: float = 0.5, oversample: int = 4,
+                                  side: int = EXTERIOR, alpha: complex = 1j, gamma: float = 0.0,
+                                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """-grad_nodes Re <lam, A(nodes) sigma> with sigma held fixed
+    (qbx_solve_dirichlet_node_gradient): the node part of the gradient through the
+    solve, with lam from solve_dirichlet_adjoint.  Returns [P, 16, 2]."""
+    lib = _lib.load()
+    P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
+    _need(nodes, "nodes", torch.float64, (P, Q, 2))
+    _need(sigma, "sigma", torch.complex128, (P * Q,))
+    _need(lam, "lam", torch.complex128, (P * Q,))
+    dev = nodes.device
+    nbytes = lib.qbx_solve_node_gradient_workspace_bytes(P, Q, int(p), int(oversample))
+    if nbytes == 0:
+        raise ValueError("invalid node-gradient arguments")
+    ws = _workspace(nbytes, dev, workspace)
+    gn = torch.empty((P, Q, 2), dtype=torch.float64, device=dev)
+    a = complex(alpha)
+    geo = _lib.Geometry(P, Q, nodes.data_ptr())
+    _lib.check(lib.qbx_solve_dirichlet_node_gradient(
+        C.byref(geo), sigma.data_ptr(), lam.data_ptr(), float(k), int(p), float(r),
+        int(oversample), int(side), a.real, a.imag, float(gamma), gn.data_ptr(), ws.data_ptr(),
+        ws.numel(), _stream(dev)))
+    return gn
+
+
 def _require_converged(what: str, iterations: int, residual: float, tol: float) -> None:
     """Raise when a solve inside the differentiable wrapper stopped (max_iter) with a true
     relative residual above 100 tol: its value and gradients would not be those of A^-1."""
@@ -384,19 +411,8 @@ class _DirichletSolve(torch.autograd.Function):
         _require_converged("dirichlet_solve_apply backward", it, res, tol)
         gn = None
         if ctx.needs_input_grad[0]:
-            cs = (0.5 * complex(alpha).conjugate()) * lam
-            cd = -0.5 * lam
-            cot = torch.stack([torch.stack([cs, cd]), torch.stack([cs, cd])])
-            if gamma > 0.0:
-                _, gnodes = layer_potential_split_vjp(nodes.detach(), torch.stack([sigma, sigma]),
-                                                      cot, k, p, r, oversample, BOTH, S | D,
-                                                      gamma=gamma, want_nodes=True,
-                                                      want_density=False)
-            else:
-                _, gnodes = layer_potential_vjp(nodes.detach(), torch.stack([sigma, sigma]), cot,
-                                                k, p, r, oversample, BOTH, S | D,
-                                                want_density=False)
-            gn = -gnodes
+            gn = solve_dirichlet_node_gradient(nodes.detach(), sigma, lam, k, p, r, oversample,
+                                               side, alpha, gamma)
         gf = lam if ctx.needs_input_grad[1] else None
         return gn, gf, None, None, None, None, None, None, None, None, None, None
 
@@ -737,19 +753,25 @@ TUNE_FORWARD, TUNE_TAPE, TUNE_ADJOINT, TUNE_FUSED, TUNE_ALL = (
 
 def autotune(nodes: torch.Tensor, density: torch.Tensor, k: float, p: int, r: float = 0.5,
              oversample: int = 4, side: int = EXTERIOR, kind: int = S, passes: int = 2,
-             fields: int = TUNE_ALL) -> dict:
+             fields: int = TUNE_ALL, cache_path: Optional[str] = None) -> dict:
     """Time the per-contour launch shapes of the passes in ``fields`` (TUNE_* bits)
-    on this problem and install the fastest (qbx_autotune); returns the tuning."""
+    on this problem and install the fastest (qbx_autotune); returns the tuning.
+    ``cache_path``: a text file of earlier results per device and problem; a hit is
+    installed untimed, a miss is timed and written back."""
     lib = _lib.load()
     P = int(nodes.shape[0]) if nodes.dim() == 3 else -1
     _need(nodes, "nodes", torch.float64, (P, Q, 2))
     _need(density, "density", torch.complex128, (n_kinds(kind), P * Q))
+    nbytes = lib.qbx_autotune_workspace_bytes(P, Q, int(p), int(oversample), int(side), int(kind))
+    if nbytes == 0:
+        raise ValueError("invalid autotune arguments")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=nodes.device)
     geo = _lib.Geometry(P, Q, nodes.data_ptr())
     t = _lib.Tuning()
     _lib.check(lib.qbx_autotune(C.byref(geo), density.data_ptr(), float(k), int(p), float(r),
                                 int(oversample), int(side), int(kind), int(passes), int(fields),
-                                C.byref(t),
-                                _stream(nodes.device)))
+                                cache_path.encode() if cache_path else None, C.byref(t),
+                                ws.data_ptr(), ws.numel(), _stream(nodes.device)))
     return _tuning_dict(t)
 
 
@@ -803,16 +825,21 @@ class Batch:
         if self.ws.numel() < nb:
             self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
 
-    def autotune(self, passes: int = 2, fields: int = TUNE_ALL) -> dict:
+    def autotune(self, passes: int = 2, fields: int = TUNE_ALL,
+                 cache_path: Optional[str] = None) -> dict:
         """Time the batched launch shapes of the passes in ``fields`` (TUNE_* bits)
         on this batch and install the fastest (qbx_autotune_batched); returns the
-        resulting tuning."""
+        resulting tuning.  ``cache_path`` as for ``autotune``."""
+        nbytes = self._lib.qbx_autotune_batched_workspace_bytes(self.items, len(self.problems),
+                                                                self.oversample)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         t = _lib.Tuning()
         _lib.check(self._lib.qbx_autotune_batched(
             self.items, len(self.problems), C.c_void_p(self.nodes.data_ptr()),
             C.c_void_p(self.density.data_ptr()), self.oversample, int(passes), int(fields),
-            C.byref(t),
-            C.c_void_p(_stream(self.device))))
+            cache_path.encode() if cache_path else None, C.byref(t),
+            C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()), C.c_void_p(_stream(self.device))))
+        del ws
         self._ensure_workspace()
         return _tuning_dict(t)
 

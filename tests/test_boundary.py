@@ -192,7 +192,7 @@ def test_timer_class_count_matches_header():
 
 
 def test_strerror(lib):
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert len(lib.qbx_strerror(code)) > 3
     assert lib.qbx_strerror(-99) == b"unknown error"
 
@@ -300,21 +300,59 @@ def test_tuning_roundtrip_and_validation(lib):
         assert lib.qbx_set_tuning(C.byref(t0)) == _lib.QBX_OK
 
 
+def _autotune(lib, g, dens=BAD, p=4, passes=2, fields=None, cache=None, ws=BAD, nbytes=1 << 40):
+    fields = _lib.QBX_TUNE_ALL if fields is None else fields
+    return lib.qbx_autotune(C.byref(g), dens, 1.0, p, 0.5, 4, 1, 1, passes, fields, cache, None,
+                            ws, nbytes, None)
+
+
 def test_autotune_validation(lib):
     g = _lib.Geometry(8, 16, BAD)
     ALL = _lib.QBX_TUNE_ALL
-    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 30, 0.5, 4, 1, 1, 2, ALL, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune(C.byref(g), None, 1.0, 4, 0.5, 4, 1, 1, 2, ALL, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 0, ALL, None, None) == _lib.QBX_EINVAL
+    assert _autotune(lib, g, p=30) == _lib.QBX_EINVAL
+    assert _autotune(lib, g, dens=None) == _lib.QBX_EINVAL
+    assert _autotune(lib, g, passes=0) == _lib.QBX_EINVAL
     for bad in (0, 16, -1):   # fields: a nonzero combination of the four bits
-        assert lib.qbx_autotune(C.byref(g), BAD, 1.0, 4, 0.5, 4, 1, 1, 2, bad, None,
-                                None) == _lib.QBX_EINVAL
+        assert _autotune(lib, g, fields=bad) == _lib.QBX_EINVAL
+    assert _autotune(lib, g, ws=None) == _lib.QBX_EINVAL
+    need = lib.qbx_autotune_workspace_bytes(8, 16, 4, 4, 1, 1)
+    assert need >= lib.qbx_workspace_bytes(8, 16, 4, 4, 1, 1) and need % 256 == 0
+    assert lib.qbx_autotune_workspace_bytes(2, 16, 4, 4, 1, 1) == 0
+    assert _autotune(lib, g, nbytes=need - 1) == _lib.QBX_EWORKSPACE
     its = _items()
-    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 0, ALL, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune_batched(its, 0, BAD, BAD, 4, 2, ALL, None, None) == _lib.QBX_EINVAL
-    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, 0, None, None) == _lib.QBX_EINVAL
+    nb = lib.qbx_autotune_batched_workspace_bytes(its, 3, 4)
+    assert nb >= lib.qbx_batched_workspace_bytes(its, 3, 4) and nb % 256 == 0
+
+    def batched(n=3, passes=2, fields=ALL, ws=BAD, nbytes=1 << 40):
+        return lib.qbx_autotune_batched(its, n, BAD, BAD, 4, passes, fields, None, None, ws,
+                                        nbytes, None)
+
+    assert batched(passes=0) == _lib.QBX_EINVAL
+    assert batched(n=0) == _lib.QBX_EINVAL
+    assert batched(fields=0) == _lib.QBX_EINVAL
+    assert batched(ws=None) == _lib.QBX_EINVAL
+    assert batched(nbytes=nb - 1) == _lib.QBX_EWORKSPACE
     its[0].p = 99
-    assert lib.qbx_autotune_batched(its, 3, BAD, BAD, 4, 2, ALL, None, None) == _lib.QBX_EINVAL
+    assert batched() == _lib.QBX_EINVAL
+    assert lib.qbx_autotune_batched_workspace_bytes(its, 3, 4) == 0
+
+
+def test_autotune_workspace_covers_every_candidate(lib):
+    """The autotuner's workspace query holds the library workspace of every
+    candidate shape (the library's own size depends on the tuning)."""
+    t0 = _lib.Tuning()
+    assert lib.qbx_get_tuning(C.byref(t0)) == _lib.QBX_OK
+    need = lib.qbx_autotune_workspace_bytes(300, 16, 12, 4, 0, 3)
+    try:
+        for w in (2048, 4096, 8192, 16384, 32768, 65536, 131072):
+            for f in (2048, 4096, 8192, 16384, 32768):
+                t = _lib.Tuning.from_buffer_copy(t0)
+                t.forward_waves = t.tape_waves = t.adjoint_waves = w
+                t.fused_tiles = f
+                assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
+                assert lib.qbx_workspace_bytes(300, 16, 12, 4, 0, 3) < need
+    finally:
+        assert lib.qbx_set_tuning(C.byref(t0)) == _lib.QBX_OK
 
 
 def _explicit(lib, n_src=100, n_ctr=20, p=6, kind=1, k=3.0, xy=BAD, nu=BAD, q=BAD, cxy=BAD,
@@ -422,3 +460,78 @@ def test_expansion_entry_points_validate(lib):
     for bad in (dict(nc=0), dict(nt=-1), dict(slack=0.0), dict(slack=float("nan")),
                 dict(r=None)):
         assert asg(**bad) == _lib.QBX_EINVAL, bad
+
+
+def test_workspace_size_follows_the_tuning(lib):
+    """qbx_workspace_bytes depends on the tuning; a workspace sized under a smaller
+    tuning is refused under a larger one (before anything reaches the device)."""
+    t0 = _lib.Tuning()
+    assert lib.qbx_get_tuning(C.byref(t0)) == _lib.QBX_OK
+    try:
+        sizes = []
+        for w in (2048, 131072):
+            t = _lib.Tuning.from_buffer_copy(t0)
+            t.forward_waves = t.tape_waves = t.adjoint_waves = w
+            assert lib.qbx_set_tuning(C.byref(t)) == _lib.QBX_OK
+            sizes.append(lib.qbx_workspace_bytes(64, 16, 10, 4, 0, 3))
+        assert sizes[0] < sizes[1]
+        g = _lib.Geometry(64, 16, BAD)
+        rc = lib.qbx_layer_potential(C.byref(g), BAD, 3.0, 10, 0.5, 4, 0, 3, BAD, None, BAD,
+                                     sizes[0], None)
+        assert rc == _lib.QBX_EWORKSPACE
+    finally:
+        assert lib.qbx_set_tuning(C.byref(t0)) == _lib.QBX_OK
+
+
+def test_autotune_cache_file_errors(lib, tmp_path):
+    """A malformed or unreadable cache file, and a device query without a device, give
+    their codes; every case returns before any device memory is touched."""
+    g = _lib.Geometry(8, 16, BAD)
+    bad_dir = str(tmp_path).encode()   # a directory: not a cache file
+    rc = _autotune(lib, g, cache=bad_dir, ws=None)
+    # without a GPU the cache key's device query fails first
+    assert rc in (_lib.QBX_EIO, _lib.QBX_EDEVICE)
+    if rc == _lib.QBX_EDEVICE:
+        assert b"device" in lib.qbx_last_error()
+
+
+def test_device_errors_are_reported_without_a_gpu(lib):
+    """QBX_EDEVICE from entry points whose arguments pass validation, forced on a
+    machine with no GPU (the first launch fails); the message names the step."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: device errors cannot be forced from the host")
+    g = _lib.Geometry(8, 16, BAD)
+    n = lib.qbx_workspace_bytes(8, 16, 6, 4, 1, 1)
+    calls = {
+        "forward": lambda: lib.qbx_layer_potential(C.byref(g), BAD, 3.0, 6, 0.5, 4, 1, 1, BAD,
+                                                   None, BAD, n, None),
+        "split": lambda: lib.qbx_layer_potential_split(C.byref(g), BAD, 3.0, 6, 0.5, 4, 1, 1, 6.0,
+                                                       BAD, BAD, n, None),
+        "adjoint": lambda: lib.qbx_layer_potential_adjoint(C.byref(g), BAD, 3.0, 6, 0.5, 4, 1, 1,
+                                                           BAD, None, BAD, BAD, BAD, n, None),
+        "autotune cache key": lambda: _autotune(lib, g, cache=b"/nonexistent/qbx_cache.txt"),
+    }
+    for name, call in calls.items():
+        rc = call()
+        assert rc == _lib.QBX_EDEVICE, (name, rc, lib.qbx_last_error())
+        assert len(lib.qbx_last_error()) > 10, name
+    assert lib.qbx_strerror(_lib.QBX_EIO) == b"autotuner cache file error"
+
+
+def test_solve_node_gradient_validation(lib):
+    g = _lib.Geometry(8, 16, BAD)
+    need = lib.qbx_solve_node_gradient_workspace_bytes(8, 16, 6, 4)
+    assert need >= lib.qbx_workspace_bytes(8, 16, 6, 4, 0, 3) and need % 256 == 0
+    assert lib.qbx_solve_node_gradient_workspace_bytes(8, 16, 99, 4) == 0
+
+    def call(side=1, sig=BAD, lam=BAD, gn=BAD, gamma=0.0, alpha=(0.0, 1.0), ws=BAD,
+             nbytes=need):
+        return lib.qbx_solve_dirichlet_node_gradient(C.byref(g), sig, lam, 3.0, 6, 0.5, 4, side,
+                                                     alpha[0], alpha[1], gamma, gn, ws, nbytes,
+                                                     None)
+
+    for bad in (dict(side=0), dict(sig=None), dict(lam=None), dict(gn=None), dict(gamma=-1.0),
+                dict(gamma=float("nan")), dict(alpha=(float("inf"), 0.0)), dict(ws=None)):
+        assert call(**bad) == _lib.QBX_EINVAL, bad
+    assert call(nbytes=need - 1) == _lib.QBX_EWORKSPACE

@@ -204,6 +204,50 @@ def test_autotune_keeps_results(Q):
         Q.set_tuning(**before)
 
 
+def test_autotune_cache_file(Q, tmp_path):
+    """With a cache file: a miss is timed and written as one line; a hit installs the
+    stored values untimed (a hand-edited line is what gets installed); the batched
+    autotuner keeps its own line in the same file."""
+    pb = I.small(n_panels=16, p=6, k=5.0, kind=3, side=I.BOTH)
+    nodes = torch.from_numpy(pb.nodes).cuda()
+    dens = torch.from_numpy(np.ascontiguousarray(pb.density)).cuda()
+    path = str(tmp_path / "qbx_tuning.txt")
+    before = Q.get_tuning()
+    args = (nodes, dens, pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    try:
+        tuned = Q.autotune(*args, passes=1, cache_path=path)
+        lines = [l for l in open(path).read().splitlines() if not l.startswith("#")]
+        say(f"  cache: {lines}")
+        assert len(lines) == 1 and " => " in lines[0]
+        key = lines[0].split(" => ")[0]
+        assert "P=16" in key and "p=6" in key and "arch=" in key
+        edited = "forward_waves=4096 tape_waves=8192 adjoint_waves=16384 fused_tiles=2048"
+        open(path, "w").write(f"{key} => {edited}\n")
+        Q.set_tuning(**before)
+        hit = Q.autotune(*args, passes=1, cache_path=path)
+        assert (hit["forward_waves"], hit["tape_waves"], hit["adjoint_waves"],
+                hit["fused_tiles"]) == (4096, 8192, 16384, 2048)
+        assert Q.get_tuning() == hit
+        # the same key again: still one line
+        Q.autotune(*args, passes=1, cache_path=path)
+        assert len([l for l in open(path) if l.startswith(key)]) == 1
+        # a malformed entry is an error, not a silent retune
+        open(path, "w").write(f"{key} => forward_waves=oops\n")
+        with pytest.raises(RuntimeError):
+            Q.autotune(*args, passes=1, cache_path=path)
+        B = Q.Batch([I.small(n_panels=6, p=4), I.small(n_panels=5, p=7, kind=3, side=I.BOTH)])
+        open(path, "w").write("")
+        tb = B.autotune(passes=1, cache_path=path)
+        Q.set_tuning(**before)
+        tb2 = B.autotune(passes=1, cache_path=path)
+        assert tb2["batch_grid_scale"] == tb["batch_grid_scale"]
+        assert tb2["batch_fused_chunks"] == tb["batch_fused_chunks"]
+        assert any(l.startswith("batch ") for l in open(path))
+        assert tuned["forward_waves"] in (2048, 4096, 8192, 16384, 32768, 65536, 131072)
+    finally:
+        Q.set_tuning(**before)
+
+
 def test_autotune_fields_mask(Q):
     """qbx_autotune times only the passes selected in `fields`: the other tuning
     fields keep their values (the adjoint alone writes the tape it needs first)."""

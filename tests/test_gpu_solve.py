@@ -165,6 +165,33 @@ def test_differentiable_solve_gradients(Q):
     assert abs(fd - an) <= 1e-6 * abs(an)
 
 
+def test_solve_node_gradient_entry_matches_its_definition(Q):
+    """qbx_solve_dirichlet_node_gradient against -grad_x Re <lam, A(x) sigma> formed
+    from the layer potentials' node adjoint with the cotangents written out here."""
+    curve, P, k, p = I.star((5, 0.25, 0.0)), 12, 4.0, 8
+    nodes = dev(I.panel_nodes(curve, P))
+    rng = np.random.default_rng(8)
+    T = P * 16
+    sig = dev(rng.standard_normal(T) + 1j * rng.standard_normal(T))
+    lam = dev(rng.standard_normal(T) + 1j * rng.standard_normal(T))
+    alpha = 0.3 + 1.1j
+    for gamma in (0.0, 4.0):
+        gn = Q.solve_dirichlet_node_gradient(nodes, sig, lam, k, p, oversample=2, side=I.INTERIOR,
+                                             alpha=alpha, gamma=gamma).cpu().numpy()
+        cs, cd = (0.5 * np.conj(alpha)) * lam, -0.5 * lam
+        cot = torch.stack([torch.stack([cs, cd]), torch.stack([cs, cd])]).contiguous()
+        dens = torch.stack([sig, sig]).contiguous()
+        if gamma > 0:
+            _, ref = Q.layer_potential_split_vjp(nodes, dens, cot, k, p, 0.5, 2, I.BOTH, 3,
+                                                 gamma=gamma, want_nodes=True, want_density=False)
+        else:
+            _, ref = Q.layer_potential_vjp(nodes, dens, cot, k, p, 0.5, 2, I.BOTH, 3,
+                                           want_density=False)
+        e = rel(gn, -ref.cpu().numpy())
+        say(f"  gamma {gamma}: entry vs written-out cotangents {e:.2e}")
+        assert e < 1e-13
+
+
 def test_differentiable_solve_with_split_products(Q):
     curve, P, k, p = I.star((5, 0.25, 0.0)), 64, 5.0, 20
     nodes = dev(I.panel_nodes(curve, P))
