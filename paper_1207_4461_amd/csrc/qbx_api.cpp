@@ -171,6 +171,8 @@ Layout make_layout(const Dims& d) {
   L.sg = take(sizeof(double) * (size_t)d.N * 8);
   L.scratch = take(sizeof(double) * (16 + (size_t)d.Mc));
   L.bnd = take(sizeof(double4) * (size_t)d.P);
+  L.ncount = take(sizeof(int) * (size_t)d.P);
+  L.nlist = take(sizeof(int) * (size_t)d.P * kNearCap);
   L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T * 2);
   L.gfar = take(sizeof(double2) * (size_t)d.nk * d.T);
   L.aacc = take(sizeof(double2) * (size_t)d.nk * d.N);
@@ -414,6 +416,24 @@ int qbx_layer_potential_ext(const qbx_geometry* g, const double* density, double
   return QBX_OK;
 }
 
+}  // extern "C"
+
+// the split's panel records and near lists (every split entry point, after prepare)
+static int split_geometry(const Dims& d, const Layout& L, const qbx_geometry* g, double g2,
+                          void* ws, hipStream_t stream, NearLists* nl) {
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd),
+                                     stream);
+  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  e = launch_near_lists(d, at<double4>(ws, L.bnd), g2, at<int>(ws, L.ncount), at<int>(ws, L.nlist),
+                        stream);
+  if (e != hipSuccess) return device_fail(e, "near list kernel");
+  nl->count = at<int>(ws, L.ncount);
+  nl->list = at<int>(ws, L.nlist);
+  return QBX_OK;
+}
+
+extern "C" {
+
 int qbx_layer_potential_split(const qbx_geometry* g, const double* density, double k, int p,
                               double r, int oversample, int side, int kind, double gamma,
                               double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
@@ -430,12 +450,13 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
   const double g2 = gamma * gamma;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
-  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  NearLists nl;
+  if ((rc = split_geometry(d, L, g, g2, ws, stream, &nl))) return rc;
   timer_begin(6, stream);
-  e = launch_split_near(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
-                        at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab), at<double4>(ws, L.bnd),
-                        g2, at<double2>(ws, L.partial), stream);
+  hipError_t e = launch_split_near(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                   at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
+                                   at<double4>(ws, L.bnd), g2, nl, at<double2>(ws, L.partial),
+                                   stream);
   timer_end(6, stream);
   if (e != hipSuccess) return device_fail(e, "split near kernel");
   timer_begin(7, stream);
@@ -464,14 +485,15 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
-  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
-  e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
+  NearLists nl;
+  if ((rc = split_geometry(d, L, g, gamma * gamma, ws, stream, &nl))) return rc;
+  hipError_t e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
   if (e != hipSuccess) return device_fail(e, "order-weighted table kernel");
   e = launch_split_gradient(d, g->nodes, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
-                            at<double4>(ws, L.bnd), gamma * gamma, at<double2>(ws, L.partial),
-                            at<double2>(ws, L.fpart), grad, dn, stream);
+                            at<double4>(ws, L.bnd), gamma * gamma, nl,
+                            at<double2>(ws, L.partial), at<double2>(ws, L.fpart), grad, dn,
+                            stream);
   if (e != hipSuccess) return device_fail(e, "split gradient kernels");
   return QBX_OK;
 }
@@ -495,16 +517,17 @@ int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* densi
     return fail(QBX_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd), stream);
-  if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
-  e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
+  NearLists nl;
+  if ((rc = split_geometry(d, L, g, gamma * gamma, ws, stream, &nl))) return rc;
+  hipError_t e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
   if (e != hipSuccess) return device_fail(e, "cotangent kernel");
   if (grad_nodes)
     e = launch_split_adjoint_nodes(d, g->nodes, density, at<double>(ws, L.tables),
                                    at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                                    at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
-                                   at<double4>(ws, L.bnd), gamma * gamma, at<double2>(ws, L.G),
-                                   at<double2>(ws, L.gfar), at<double>(ws, L.cg),
+                                   at<double4>(ws, L.bnd), gamma * gamma, nl,
+                                   at<double2>(ws, L.G), at<double2>(ws, L.gfar),
+                                   at<double>(ws, L.cg),
                                    at<double2>(ws, L.spart), at<double2>(ws, L.fpart),
                                    at<double2>(ws, L.apart), at<double>(ws, L.sg), grad_density,
                                    grad_nodes, stream);
@@ -512,7 +535,7 @@ int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* densi
     e = launch_split_adjoint_density(d, g->nodes, at<double>(ws, L.tables), at<double4>(ws, L.geo),
                                      at<double>(ws, L.wgt), at<CenterRec>(ws, L.ctr),
                                      at<double>(ws, L.jtab), at<double4>(ws, L.bnd), gamma * gamma,
-                                     at<double2>(ws, L.G), at<double2>(ws, L.gfar),
+                                     nl, at<double2>(ws, L.G), at<double2>(ws, L.gfar),
                                      at<double2>(ws, L.aacc), at<double2>(ws, L.apart),
                                      grad_density, stream);
   if (e != hipSuccess) return device_fail(e, "split adjoint kernels");

@@ -12,6 +12,16 @@ namespace qbx {
 
 constexpr int kQ = 16;      // nodes per panel
 constexpr int kWave = 64;   // CDNA wavefront
+// near/far split: capacity of a panel's near list; a panel with more near panels
+// is served by the scan of all panels instead
+constexpr int kNearCap = 64;
+
+// per-panel near lists of the split: count[m] and, when count[m] <= kNearCap,
+// list[m * kNearCap + i], i < count[m], the panels near m in ascending order
+struct NearLists {
+  const int* count;
+  const int* list;
+};
 constexpr int kPMax = 24;
 
 // One expansion center: position, radius and the direction of its target,
@@ -77,6 +87,8 @@ struct Layout {
   size_t sg;       // double[N][8] per-source gradients
   size_t scratch;  // double[16 + Mc] small reductions
   size_t bnd;      // double4[P] split forward: panel mean and squared radius
+  size_t ncount;   // int[P] split: near-panel counts
+  size_t nlist;    // int[P][kNearCap] split: near-panel lists
   size_t fpart;    // double2[n_fsplit][nk][T][2] split: far sums (forward: first half)
   size_t gfar;     // double2[nk][T] split adjoint: cotangent weights of both sides
   size_t aacc;     // double2[nk][N] split adjoint: near sums per source
@@ -157,7 +169,10 @@ hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4
 // partial [nk][Mc]: QBX sums over the sources of near panels
 hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
                              const CenterRec* ctr, const double* jtab, const double4* bnd,
-                             double g2, double2* partial, hipStream_t s);
+                             double g2, NearLists nl, double2* partial, hipStream_t s);
+// the near lists of every panel (count, list: NearLists' arrays)
+hipError_t launch_near_lists(const Dims& d, const double4* bnd, double g2, int* count, int* list,
+                             hipStream_t s);
 // partial [n_fsplit][nk][T]: direct sums over the sources of far panels
 hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
                             const double* nodes, const double4* bnd, double g2, double2* partial,
@@ -168,15 +183,15 @@ hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const doub
 // [n_fsplit][nk][T][2], then grad and n . grad (either may be NULL)
 hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
                                  const double2* dens, const CenterRec* ctr, const double* jtab,
-                                 const double4* bnd, double g2, double2* nearp, double2* farp,
-                                 double* grad, double* dn, hipStream_t s);
+                                 const double4* bnd, double g2, NearLists nl, double2* nearp,
+                                 double2* farp, double* grad, double* dn, hipStream_t s);
 // the split's adjoint with respect to the density (G from launch_make_G)
 hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
                                         const double4* geo, const double* wgt,
                                         const CenterRec* ctr, const double* jtab,
-                                        const double4* bnd, double g2, const double2* G,
-                                        double2* Gf, double2* acc, double2* partial,
-                                        double* grad_density, hipStream_t s);
+                                        const double4* bnd, double g2, NearLists nl,
+                                        const double2* G, double2* Gf, double2* acc,
+                                        double2* partial, double* grad_density, hipStream_t s);
 // the split's adjoint with respect to the nodes (and the density, through the
 // chain rule; either output may be NULL): cg [Mc][8], spart [src_slots][N], fpart
 // [n_fsplit][nk][T][2], apart [n_asplit][nk + 2][N], sg [N][8]
@@ -184,8 +199,8 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
                                       const double* tables, const double4* geo,
                                       const double2* dens, const CenterRec* ctr,
                                       const double* jtab, const double4* bnd, double g2,
-                                      const double2* G, double2* Gf, double* cg, double2* spart,
-                                      double2* fpart, double2* apart, double* sg,
+                                      NearLists nl, const double2* G, double2* Gf, double* cg,
+                                      double2* spart, double2* fpart, double2* apart, double* sg,
                                       double* grad_density, double* grad_nodes, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
 // the chain rule to the nodes and node densities from the per-source (sg) and

@@ -33,6 +33,89 @@ __device__ __forceinline__ bool panels_near(double4 a, double4 b, double g2) {
   return d2 < g2 * fmax(a.z, b.z);
 }
 
+// Near lists: one wave per panel m scans all panels (64 per ballot) and writes
+// the near ones in ascending order, at most kNearCap of them, and their count.
+__global__ __launch_bounds__(256) void k_near_lists(int NP, const double4* __restrict__ bnd,
+                                                    double g2, int* __restrict__ count,
+                                                    int* __restrict__ list) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + wave;
+  if (m >= NP) return;
+  const double4 bm = bnd[m];
+  int n = 0;
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mp = w0 + lane;
+    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
+    const unsigned long long mask = __ballot(nr);
+    const int pos = n + __popcll(mask & ((1ULL << lane) - 1ULL));
+    if (nr && pos < kNearCap) list[(size_t)m * kNearCap + pos] = mp;
+    n += __popcll(mask);
+  }
+  if (lane == 0) count[m] = n;
+}
+
+// f(pan) for every panel near panel m (wave-uniform), in ascending order: from
+// m's list when it fits, else by the wave's scan of all NP panels
+template <typename F>
+__device__ __forceinline__ void for_near_panels(int m, const double4* __restrict__ bnd, int NP,
+                                                double g2, NearLists nl, int lane, F&& f) {
+  const int cnt = nl.count[m];
+  if (cnt <= kNearCap) {
+    const int* __restrict__ L = nl.list + (size_t)m * kNearCap;
+    for (int i = 0; i < cnt; ++i) f(L[i]);
+    return;
+  }
+  const double4 bm = bnd[m];
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mp = w0 + lane;
+    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
+    unsigned long long mask = __ballot(nr);
+    while (mask) {
+      const int pan = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      f(pan);
+    }
+  }
+}
+
+// f(m) once for every panel m near any of the panels pa..pb (a 64-source chunk's
+// panels; the relation is symmetric): from their lists, each m at the first list
+// that holds it, when every list fits; else by the wave's scan (ascending)
+template <typename F>
+__device__ __forceinline__ void for_near_any(int pa, int pb, const double4* __restrict__ bnd,
+                                             int NP, double g2, NearLists nl, int lane, F&& f) {
+  bool fits = true;
+  for (int ps = pa; ps <= pb; ++ps) fits = fits && nl.count[ps] <= kNearCap;
+  if (fits) {
+    for (int ps = pa; ps <= pb; ++ps) {
+      const int* __restrict__ L = nl.list + (size_t)ps * kNearCap;
+      const int cnt = nl.count[ps];
+      for (int i = 0; i < cnt; ++i) {
+        const int m = L[i];
+        bool seen = false;
+        for (int pq = pa; pq < ps; ++pq) seen = seen || panels_near(bnd[m], bnd[pq], g2);
+        if (!seen) f(m);
+      }
+    }
+    return;
+  }
+  for (int w0 = 0; w0 < NP; w0 += kWave) {
+    const int mt = w0 + lane;
+    bool any = false;
+    if (mt < NP) {
+      const double4 bt = bnd[mt];
+      for (int ps = pa; ps <= pb; ++ps) any = any || panels_near(bt, bnd[ps], g2);
+    }
+    unsigned long long mask = __ballot(any);
+    while (mask) {
+      const int m = w0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      f(m);
+    }
+  }
+}
+
 // bnd[m] = {b_x, b_y, rad2, 0}
 __global__ __launch_bounds__(256) void k_panel_bounds(int NP, const double* __restrict__ nodes,
                                                       double4* __restrict__ bnd) {
@@ -79,7 +162,7 @@ __global__ __launch_bounds__(256) void k_split_near(const double4* __restrict__ 
                                                     int qs, const CenterRec* __restrict__ ctr,
                                                     const double* __restrict__ jtab, int NJ,
                                                     int Mc, int T, const double4* __restrict__ bnd,
-                                                    int NP, double g2, double k,
+                                                    int NP, double g2, NearLists nl, double k,
                                                     double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -88,26 +171,18 @@ __global__ __launch_bounds__(256) void k_split_near(const double4* __restrict__ 
   const int ci = blockIdx.x * 4 + wave;
   if (ci >= Mc) return;
   const int m = (ci % T) / kQ;                 // the target's panel
-  const double4 bm = bnd[m];
   const CenterRec* C = ctr + ci;
   const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
   const double inv_k = 1.0 / k;
   const double* Jtab = jtab + (size_t)ci * NJ;
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
-  for (int w0 = 0; w0 < NP; w0 += kWave) {
-    const int mp = w0 + lane;
-    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
-    unsigned long long mask = __ballot(nr);
-    while (mask) {
-      const int pan = w0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      for (int s0 = 0; s0 < qs; s0 += kWave) {
-        if (s0 + lane < qs)
-          forward_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k,
-                                  Jtab, sr, si, dr, di);
-      }
+  for_near_panels(m, bnd, NP, g2, nl, lane, [&](int pan) {
+    for (int s0 = 0; s0 < qs; s0 += kWave) {
+      if (s0 + lane < qs)
+        forward_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k,
+                                Jtab, sr, si, dr, di);
     }
-  }
+  });
   Cplx S = {sr, si}, Dd = {dr, di};
   if (kS) wave_sum(S);
   if (kD) wave_sum(Dd);
@@ -257,7 +332,7 @@ template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_split_near_adj(
     const double4* __restrict__ geo, int N, int qs, const CenterRec* __restrict__ ctr,
     const double* __restrict__ jtab, int NJ, int Mc, int T, int n_sides,
-    const double4* __restrict__ bnd, int NP, double g2, double k,
+    const double4* __restrict__ bnd, int NP, double g2, NearLists nl, double k,
     const double2* __restrict__ G, double2* __restrict__ acc) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -274,55 +349,44 @@ __global__ __launch_bounds__(256) void k_split_near_adj(
   const double4 g = geo[jj];
   const double inv_k = 1.0 / k;
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
-  for (int w0 = 0; w0 < NP; w0 += kWave) {
-    const int mt = w0 + lane;
-    bool any = false;
-    if (mt < NP) {
-      const double4 bt = bnd[mt];
-      for (int ps = pa; ps <= pb; ++ps) any = any || panels_near(bt, bnd[ps], g2);
-    }
-    unsigned long long mask = __ballot(any);
-    while (mask) {
-      const int m = w0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      if (valid && panels_near(bnd[m], bj, g2)) {
-        for (int si_ = 0; si_ < n_sides; ++si_) {
-          for (int a = 0; a < kQ; ++a) {
-            const int ci = si_ * T + m * kQ + a;
-            const int z0 = opaque_zero();
-            const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
-            const double* __restrict__ cf = g_seed_table + z0;
-            const CenterRec* C = ctr + ci;
-            const double vx = g.x - C->cx, vy = g.y - C->cy;
-            const double rho2 = fma(vx, vx, vy * vy);
-            const double ir = rsqrt_refined(rho2);
-            const double rho = rho2 * ir;
-            const double cd = (C->ct * vx + C->st * vy) * ir;
-            const double sd = (C->st * vx - C->ct * vy) * ir;
-            double cps = 0.0, sps = 0.0;
-            if (kD) {
-              cps = C->ct * g.z + C->st * g.w;
-              sps = C->st * g.z - C->ct * g.w;
-            }
-            double ks_r, ks_i, kd_r, kd_i;
-            pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, ks_r, ks_i, kd_r,
-                                 kd_i);
-            int kk = 0;
-            if (kS) {
-              const double2 Gi = G[(size_t)(kk++) * Mc + ci];
-              sr = fma(Gi.x, ks_r, fma(-Gi.y, ks_i, sr));
-              si = fma(Gi.x, ks_i, fma(Gi.y, ks_r, si));
-            }
-            if (kD) {
-              const double2 Gi = G[(size_t)kk * Mc + ci];
-              dr = fma(Gi.x, kd_r, fma(-Gi.y, kd_i, dr));
-              di = fma(Gi.x, kd_i, fma(Gi.y, kd_r, di));
-            }
+  for_near_any(pa, pb, bnd, NP, g2, nl, lane, [&](int m) {
+    if (valid && panels_near(bnd[m], bj, g2)) {
+      for (int si_ = 0; si_ < n_sides; ++si_) {
+        for (int a = 0; a < kQ; ++a) {
+          const int ci = si_ * T + m * kQ + a;
+          const int z0 = opaque_zero();
+          const double* __restrict__ J = jtab + (size_t)ci * NJ + z0;
+          const double* __restrict__ cf = g_seed_table + z0;
+          const CenterRec* C = ctr + ci;
+          const double vx = g.x - C->cx, vy = g.y - C->cy;
+          const double rho2 = fma(vx, vx, vy * vy);
+          const double ir = rsqrt_refined(rho2);
+          const double rho = rho2 * ir;
+          const double cd = (C->ct * vx + C->st * vy) * ir;
+          const double sd = (C->st * vx - C->ct * vy) * ir;
+          double cps = 0.0, sps = 0.0;
+          if (kD) {
+            cps = C->ct * g.z + C->st * g.w;
+            sps = C->st * g.z - C->ct * g.w;
+          }
+          double ks_r, ks_i, kd_r, kd_i;
+          pair_kernel<P, KIND>(k * rho, ir * inv_k, cd, sd, cps, sps, J, cf, ks_r, ks_i, kd_r,
+                               kd_i);
+          int kk = 0;
+          if (kS) {
+            const double2 Gi = G[(size_t)(kk++) * Mc + ci];
+            sr = fma(Gi.x, ks_r, fma(-Gi.y, ks_i, sr));
+            si = fma(Gi.x, ks_i, fma(Gi.y, ks_r, si));
+          }
+          if (kD) {
+            const double2 Gi = G[(size_t)kk * Mc + ci];
+            dr = fma(Gi.x, kd_r, fma(-Gi.y, kd_i, dr));
+            di = fma(Gi.x, kd_i, fma(Gi.y, kd_r, di));
           }
         }
       }
     }
-  }
+  });
   if (valid) {
     int kk = 0;
     if (kS) acc[(size_t)(kk++) * N + j] = make_double2(sr, si);
@@ -502,10 +566,12 @@ __global__ __launch_bounds__(256) void k_split_density_grad(
 template <int P>
 static hipError_t launch_split_near_adj_p(const Dims& d, const double4* geo, const CenterRec* ctr,
                                           const double* jtab, const double4* bnd, double g2,
-                                          const double2* G, double2* acc, hipStream_t s) {
+                                          NearLists nl, const double2* G, double2* acc,
+                                          hipStream_t s) {
   const int chunks = (d.N + kWave - 1) / kWave;
   const dim3 grid((unsigned)((chunks + 3) / 4)), block(256);
-#define QBX_NADJ_ARGS geo, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, d.k, G, acc
+#define QBX_NADJ_ARGS \
+  geo, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, nl, d.k, G, acc
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_near_adj<P, 1>), grid, block, 0, s, QBX_NADJ_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_near_adj<P, 2>), grid, block, 0, s, QBX_NADJ_ARGS); break;
@@ -518,13 +584,13 @@ static hipError_t launch_split_near_adj_p(const Dims& d, const double4* geo, con
 hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
                                         const double4* geo, const double* wgt,
                                         const CenterRec* ctr, const double* jtab,
-                                        const double4* bnd, double g2, const double2* G,
-                                        double2* Gf, double2* acc, double2* partial,
-                                        double* grad_density, hipStream_t s) {
+                                        const double4* bnd, double g2, NearLists nl,
+                                        const double2* G, double2* Gf, double2* acc,
+                                        double2* partial, double* grad_density, hipStream_t s) {
   hipError_t e;
   {
     auto launch = [&]() -> hipError_t {
-      QBX_P_SWITCH(d.p, launch_split_near_adj_p, d, geo, ctr, jtab, bnd, g2, G, acc, s)
+      QBX_P_SWITCH(d.p, launch_split_near_adj_p, d, geo, ctr, jtab, bnd, g2, nl, G, acc, s)
     };
     e = launch();
     if (e != hipSuccess) return e;
@@ -573,7 +639,7 @@ template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_split_near_cg(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
-    int side, const double4* __restrict__ bnd, int NP, double g2, double k,
+    int side, const double4* __restrict__ bnd, int NP, double g2, NearLists nl, double k,
     const double2* __restrict__ G, double* __restrict__ cg) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -583,7 +649,6 @@ __global__ __launch_bounds__(256) void k_split_near_cg(
   const int ci = blockIdx.x * 4 + wave;
   if (ci >= Mc) return;
   const int m = (ci % T) / kQ;
-  const double4 bm = bnd[m];
   const CenterRec* C = ctr + ci;
   const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
   const double inv_k = 1.0 / k;
@@ -593,20 +658,13 @@ __global__ __launch_bounds__(256) void k_split_near_cg(
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 5; ++b) A[a][b] = {0.0, 0.0};
-  for (int w0 = 0; w0 < NP; w0 += kWave) {
-    const int mp = w0 + lane;
-    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
-    unsigned long long mask = __ballot(nr);
-    while (mask) {
-      const int pan = w0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      for (int s0 = 0; s0 < qs; s0 += kWave) {
-        if (s0 + lane < qs)
-          tape_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
-                               NJ / 2, A);
-      }
+  for_near_panels(m, bnd, NP, g2, nl, lane, [&](int pan) {
+    for (int s0 = 0; s0 < qs; s0 += kWave) {
+      if (s0 + lane < qs)
+        tape_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
+                             NJ / 2, A);
     }
-  }
+  });
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk)
 #pragma unroll
@@ -657,7 +715,7 @@ template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_split_near_adj_nodes(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
-    int n_sides, const double4* __restrict__ bnd, int NP, double g2, double k,
+    int n_sides, const double4* __restrict__ bnd, int NP, double g2, NearLists nl, double k,
     const double2* __restrict__ G, double2* __restrict__ part) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -682,31 +740,20 @@ __global__ __launch_bounds__(256) void k_split_near_adj_nodes(
   Cplx A[NA];
 #pragma unroll
   for (int b = 0; b < NA; ++b) A[b] = {0.0, 0.0};
-  for (int w0 = 0; w0 < NP; w0 += kWave) {
-    const int mt = w0 + lane;
-    bool any = false;
-    if (mt < NP) {
-      const double4 bt = bnd[mt];
-      for (int ps = pa; ps <= pb; ++ps) any = any || panels_near(bt, bnd[ps], g2);
-    }
-    unsigned long long mask = __ballot(any);
-    while (mask) {
-      const int m = w0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      if (valid && panels_near(bnd[m], bj, g2)) {
-        for (int si_ = 0; si_ < n_sides; ++si_) {
-          for (int a = 0; a < kQ; ++a) {
-            const int ci = si_ * T + m * kQ + a;
-            const int z0 = opaque_zero();
-            const double2 GS = G[(size_t)ci + z0];
-            const double2 GD = NK == 2 ? G[(size_t)Mc + ci + z0] : GS;
-            adjoint_pair<P, KIND>(g, q, ctr + ci + z0, jtab + (size_t)ci * NJ + z0,
-                                  g_seed_table + z0, GS, GD, k, inv_k, nj, A);
-          }
+  for_near_any(pa, pb, bnd, NP, g2, nl, lane, [&](int m) {
+    if (valid && panels_near(bnd[m], bj, g2)) {
+      for (int si_ = 0; si_ < n_sides; ++si_) {
+        for (int a = 0; a < kQ; ++a) {
+          const int ci = si_ * T + m * kQ + a;
+          const int z0 = opaque_zero();
+          const double2 GS = G[(size_t)ci + z0];
+          const double2 GD = NK == 2 ? G[(size_t)Mc + ci + z0] : GS;
+          adjoint_pair<P, KIND>(g, q, ctr + ci + z0, jtab + (size_t)ci * NJ + z0,
+                                g_seed_table + z0, GS, GD, k, inv_k, nj, A);
         }
       }
     }
-  }
+  });
   if (valid) {
 #pragma unroll
     for (int b = 0; b < NA; ++b) part[(size_t)b * N + j] = make_double2(A[b].r, A[b].i);
@@ -781,7 +828,8 @@ template <int P, int KIND>
 __global__ __launch_bounds__(256) void k_split_near_grad(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
     const CenterRec* __restrict__ ctr, const double* __restrict__ jtab, int NJ, int Mc, int T,
-    const double4* __restrict__ bnd, int NP, double g2, double k, double2* __restrict__ partial) {
+    const double4* __restrict__ bnd, int NP, double g2, NearLists nl, double k,
+    double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
@@ -790,7 +838,6 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
   const int ci = blockIdx.x * 4 + wave;
   if (ci >= Mc) return;
   const int m = (ci % T) / kQ;
-  const double4 bm = bnd[m];
   const CenterRec* C = ctr + ci;
   const double cx = C->cx, cy = C->cy, ct = C->ct, st = C->st;
   const double inv_k = 1.0 / k;
@@ -799,20 +846,13 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
   Cplx A[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a) A[a][0] = A[a][1] = {0.0, 0.0};
-  for (int w0 = 0; w0 < NP; w0 += kWave) {
-    const int mp = w0 + lane;
-    const bool nr = mp < NP && panels_near(bm, bnd[mp], g2);
-    unsigned long long mask = __ballot(nr);
-    while (mask) {
-      const int pan = w0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      for (int s0 = 0; s0 < qs; s0 += kWave) {
-        if (s0 + lane < qs)
-          grad_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
-                               NJ / 2, Ltab, A);
-      }
+  for_near_panels(m, bnd, NP, g2, nl, lane, [&](int pan) {
+    for (int s0 = 0; s0 < qs; s0 += kWave) {
+      if (s0 + lane < qs)
+        grad_source<P, KIND>(geo, dens, N, pan * qs + s0 + lane, cx, cy, ct, st, k, inv_k, Jtab,
+                             NJ / 2, Ltab, A);
     }
-  }
+  });
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {
     wave_sum(A[kk][0]);
@@ -951,10 +991,11 @@ __global__ __launch_bounds__(256) void k_split_finalize_gradient(
 template <int P>
 static hipError_t launch_split_near_grad_p(const Dims& d, const double4* geo, const double2* dens,
                                            const CenterRec* ctr, const double* jtab,
-                                           const double4* bnd, double g2, double2* partial,
-                                           hipStream_t s) {
+                                           const double4* bnd, double g2, NearLists nl,
+                                           double2* partial, hipStream_t s) {
   const dim3 grid((unsigned)((d.Mc + 3) / 4)), block(256);
-#define QBX_NGRAD_ARGS geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, d.k, partial
+#define QBX_NGRAD_ARGS \
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, nl, d.k, partial
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_near_grad<P, 1>), grid, block, 0, s, QBX_NGRAD_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_near_grad<P, 2>), grid, block, 0, s, QBX_NGRAD_ARGS); break;
@@ -966,12 +1007,12 @@ static hipError_t launch_split_near_grad_p(const Dims& d, const double4* geo, co
 
 hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
                                  const double2* dens, const CenterRec* ctr, const double* jtab,
-                                 const double4* bnd, double g2, double2* nearp, double2* farp,
-                                 double* grad, double* dn, hipStream_t s) {
+                                 const double4* bnd, double g2, NearLists nl, double2* nearp,
+                                 double2* farp, double* grad, double* dn, hipStream_t s) {
   hipError_t e;
   {
     auto launch = [&]() -> hipError_t {
-      QBX_P_SWITCH(d.p, launch_split_near_grad_p, d, geo, dens, ctr, jtab, bnd, g2, nearp, s)
+      QBX_P_SWITCH(d.p, launch_split_near_grad_p, d, geo, dens, ctr, jtab, bnd, g2, nl, nearp, s)
     };
     e = launch();
     if (e != hipSuccess) return e;
@@ -1004,10 +1045,11 @@ hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4
 template <int P>
 static hipError_t launch_split_near_p(const Dims& d, const double4* geo, const double2* dens,
                                       const CenterRec* ctr, const double* jtab,
-                                      const double4* bnd, double g2, double2* partial,
-                                      hipStream_t s) {
+                                      const double4* bnd, double g2, NearLists nl,
+                                      double2* partial, hipStream_t s) {
   const dim3 grid((unsigned)((d.Mc + 3) / 4)), block(256);
-#define QBX_NEAR_ARGS geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, d.k, partial
+#define QBX_NEAR_ARGS \
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, bnd, d.P, g2, nl, d.k, partial
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_near<P, 1>), grid, block, 0, s, QBX_NEAR_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_near<P, 2>), grid, block, 0, s, QBX_NEAR_ARGS); break;
@@ -1019,8 +1061,15 @@ static hipError_t launch_split_near_p(const Dims& d, const double4* geo, const d
 
 hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
                              const CenterRec* ctr, const double* jtab, const double4* bnd,
-                             double g2, double2* partial, hipStream_t s) {
-  QBX_P_SWITCH(d.p, launch_split_near_p, d, geo, dens, ctr, jtab, bnd, g2, partial, s)
+                             double g2, NearLists nl, double2* partial, hipStream_t s) {
+  QBX_P_SWITCH(d.p, launch_split_near_p, d, geo, dens, ctr, jtab, bnd, g2, nl, partial, s)
+}
+
+hipError_t launch_near_lists(const Dims& d, const double4* bnd, double g2, int* count, int* list,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_near_lists, dim3((unsigned)((d.P + 3) / 4)), dim3(256), 0, s, d.P, bnd,
+                     g2, count, list);
+  return hipGetLastError();
 }
 
 hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
@@ -1052,15 +1101,15 @@ template <int P>
 static hipError_t launch_split_nodes_near_p(const Dims& d, const double4* geo,
                                             const double2* dens, const CenterRec* ctr,
                                             const double* jtab, const double4* bnd, double g2,
-                                            const double2* G, double* cg, double2* spart,
-                                            hipStream_t s) {
+                                            NearLists nl, const double2* G, double* cg,
+                                            double2* spart, hipStream_t s) {
   const dim3 gc((unsigned)((d.Mc + 3) / 4)), block(256);
   const int chunks = (d.N + kWave - 1) / kWave;
   const dim3 gs((unsigned)((chunks + 3) / 4));
 #define QBX_NCG_ARGS \
-  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.side, bnd, d.P, g2, d.k, G, cg
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.side, bnd, d.P, g2, nl, d.k, G, cg
 #define QBX_NSRC_ARGS \
-  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, d.k, G, spart
+  geo, dens, d.N, d.qs, ctr, jtab, d.NJ, d.Mc, d.T, d.n_sides, bnd, d.P, g2, nl, d.k, G, spart
   switch (d.kind) {
     case 1:
       hipLaunchKernelGGL((k_split_near_cg<P, 1>), gc, block, 0, s, QBX_NCG_ARGS);
@@ -1084,14 +1133,14 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
                                       const double* tables, const double4* geo,
                                       const double2* dens, const CenterRec* ctr,
                                       const double* jtab, const double4* bnd, double g2,
-                                      const double2* G, double2* Gf, double* cg, double2* spart,
-                                      double2* fpart, double2* apart, double* sg,
+                                      NearLists nl, const double2* G, double2* Gf, double* cg,
+                                      double2* spart, double2* fpart, double2* apart, double* sg,
                                       double* grad_density, double* grad_nodes, hipStream_t s) {
   hipError_t e;
   {
     auto launch = [&]() -> hipError_t {
-      QBX_P_SWITCH(d.p, launch_split_nodes_near_p, d, geo, dens, ctr, jtab, bnd, g2, G, cg, spart,
-                   s)
+      QBX_P_SWITCH(d.p, launch_split_nodes_near_p, d, geo, dens, ctr, jtab, bnd, g2, nl, G, cg,
+                   spart, s)
     };
     e = launch();
     if (e != hipSuccess) return e;

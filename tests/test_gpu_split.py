@@ -88,6 +88,29 @@ def test_split_all_near_is_the_plain_forward(Q):
     assert e < 1e-13
 
 
+def test_split_scan_path_when_lists_overflow(Q):
+    """72 panels, every one near every other: the near lists (64 entries) overflow and
+    the near passes scan all panels instead.  Forward, derivatives and both adjoints
+    then equal the plain (unsplit) results."""
+    pb = I.small(n_panels=72, p=6, k=5.0, kind=3, side=I.BOTH)
+    nodes, dens, cot = dev(pb.nodes), dev(pb.density), dev(pb.cotangent)
+    args = (pb.k, pb.p, pb.r, pb.oversample, pb.side, pb.kind)
+    g = 1e150
+    e_f = rel(Q.layer_potential_split(nodes, dens, *args, gamma=g).cpu().numpy(),
+              Q.layer_potential(nodes, dens, *args).cpu().numpy())
+    a_g, a_n = Q.layer_potential_split_gradient(nodes, dens, *args, gamma=g)
+    b_g, b_n = Q.layer_potential_gradient(nodes, dens, *args)
+    e_g = max(rel(a_g.cpu().numpy(), b_g.cpu().numpy()), rel(a_n.cpu().numpy(), b_n.cpu().numpy()))
+    sd = Q.layer_potential_split_vjp(nodes, dens, cot, *args, gamma=g)
+    sd2, sn = Q.layer_potential_split_vjp(nodes, dens, cot, *args, gamma=g, want_nodes=True)
+    pd, pn = Q.layer_potential_vjp(nodes, dens, cot, *args)
+    e_d = max(rel(sd.cpu().numpy(), pd.cpu().numpy()), rel(sd2.cpu().numpy(), pd.cpu().numpy()))
+    e_n = rel(sn.cpu().numpy(), pn.cpu().numpy())
+    say(f"  overflowing lists: forward {e_f:.1e} derivatives {e_g:.1e} density adjoint {e_d:.1e}"
+        f" node adjoint {e_n:.1e}")
+    assert e_f < 1e-13 and e_g < 1e-13 and e_d < 1e-13 and e_n < 1e-12
+
+
 @pytest.mark.parametrize("cfg,n", [("star256", 24), ("star1024", 16), ("star4096", 5)])
 def test_split_full_size_sampled(Q, cfg, n):
     """The workloads at full size (gamma = 6) on sampled targets against the oracle,
