@@ -8,9 +8,9 @@ Two regimes (z = k*rho > 0):
   at Chebyshev points in s = (Z0/z)^2 in (0, 1] from 40-digit mpmath values of
   J_nu + i Y_nu and stored as monomial coefficients in s:
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
-  A second, shorter fit of the same functions in s = (ZF/z)^2 serves z >= ZF
-  (used when every lane of a wavefront is that far), and a third, shorter still,
-  in s = (ZV/z)^2 serves z >= ZV (again when every lane of the wavefront is).
+  Shorter fits of the same functions serve the wavefronts whose every lane is
+  farther: in s = (ZM/z)^2 for z >= ZM, in s = (ZF/z)^2 for z >= ZF and, shortest,
+  in s = (ZV/z)^2 for z >= ZV.
 * the phase with the amplitude's constant, sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir}:
   n = rint(z N / 2 pi), r = z - 2 pi n / N by a three-part Cody-Waite reduction,
   T_n = sqrt(2/pi) e^{i(2 pi n/N - pi/4)} from a table of N entries (40-digit values
@@ -43,6 +43,8 @@ import numpy as np
 
 Z0 = 6.0
 DEG = 12          # degree in s of the P, Q fits
+ZM = 10.0
+DEG_MED = 9       # degree in s = (ZM/z)^2 of the fits for z >= ZM
 ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
 ZV = 60.0
@@ -146,6 +148,10 @@ def main():
                                             DEG_FAR)
         fits[f"FQ{nu}"] = cheb_fit_monomial(
             lambda s, nu=nu: pq(nu, ZF / mpmath.sqrt(s))[1] * (ZF / mpmath.sqrt(s)) / ZF, DEG_FAR)
+        fits[f"MP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZM / mpmath.sqrt(s))[0],
+                                            DEG_MED)
+        fits[f"MQ{nu}"] = cheb_fit_monomial(
+            lambda s, nu=nu: pq(nu, ZM / mpmath.sqrt(s))[1] * (ZM / mpmath.sqrt(s)) / ZM, DEG_MED)
         fits[f"VP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZV / mpmath.sqrt(s))[0],
                                             DEG_VFAR)
         fits[f"VQ{nu}"] = cheb_fit_monomial(
@@ -204,6 +210,14 @@ def main():
             Qv = (ZF / z) * horner(dbl[f"FQ{nu}"], s)
             pr, qr = pq(nu, z)
             worst_far = max(worst_far, abs(complex(P - float(pr), Qv - float(qr))))
+    worst_med = 0.0
+    for z in np.concatenate([np.geomspace(ZM, 2e4, 1500), rng.uniform(ZM, 30, 500)]):
+        s = (ZM / z) ** 2
+        for nu in (0, 1):
+            P = horner(dbl[f"MP{nu}"], s)
+            Qv = (ZM / z) * horner(dbl[f"MQ{nu}"], s)
+            pr, qr = pq(nu, z)
+            worst_med = max(worst_med, abs(complex(P - float(pr), Qv - float(qr))))
     worst_vfar = 0.0
     for z in np.concatenate([np.geomspace(ZV, 2e4, 1500), rng.uniform(ZV, 200, 500)]):
         s = (ZV / z) ** 2
@@ -233,6 +247,7 @@ def main():
             ref = complex(mpmath.besselj(nu, z) + 1j * mpmath.bessely(nu, z))
             worst_small = max(worst_small, abs(complex(Jv, Yv) - ref) / abs(ref))
     print(f"fit error of P,Q (absolute, |P+iQ| ~ 1) for z >= {Z0}: {worst_big:.3e}")
+    print(f"medium fit error of P,Q for z >= {ZM} (degree {DEG_MED}): {worst_med:.3e}")
     print(f"far fit error of P,Q for z >= {ZF} (degree {DEG_FAR}): {worst_far:.3e}")
     print(f"very-far fit error of P,Q for z >= {ZV} (degree {DEG_VFAR}): {worst_vfar:.3e}")
     print(f"mid-range relative error of H for {Z1} <= z < {Z0}: {worst_mid:.3e}")
@@ -301,6 +316,7 @@ def main():
     out.append("// Coefficients of the Hankel seeds H_0, H_1 (see qbx_special.h).\n#pragma once\n\n")
     out.append("namespace qbx {\nnamespace seed {\n\n")
     out.append(f"constexpr double kZ0 = {Z0:.17e};\nconstexpr double kZ1 = {Z1:.17e};\n")
+    out.append(f"constexpr double kZM = {ZM:.17e};\n")
     out.append(f"constexpr double kZF = {ZF:.17e};\n")
     out.append(f"constexpr double kZV = {ZV:.17e};\n")
     out.append(f"constexpr double kZC = {ZC:.17e};\nconstexpr double kInvZH = {1.0 / ZH:.17e};\n")
@@ -327,6 +343,7 @@ def main():
     block("TRIG", [sin_c + [0.0] * (len(cos_c) - len(sin_c)), cos_c])
     block("FAR", [dbl["FP0"], dbl["FQ0"], dbl["FP1"], dbl["FQ1"]])
     block("VFAR", [dbl["VP0"], dbl["VQ0"], dbl["VP1"], dbl["VQ1"]])
+    block("MED", [dbl["MP0"], dbl["MQ0"], dbl["MP1"], dbl["MQ1"]])
     for name, (o, n) in offs.items():
         out.append(f"constexpr int k{name}Off = {o};\nconstexpr int k{name}Len = {n};\n")
     out.append(f"constexpr int kTRIGLenA = {len(sin_c)};   // sin(r)/r coefficients in TRIG\n")

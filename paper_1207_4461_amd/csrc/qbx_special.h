@@ -19,9 +19,10 @@ namespace qbx {
 // gen_seed_coeffs.py from 40-digit reference values and exact rationals).
 //  * z >= Z0 = 6: H_nu = sqrt(2/(pi z)) e^{i(z - nu pi/2 - pi/4)} (P_nu + i Q_nu)
 //    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
-//    when every active lane of the wavefront has z >= ZF = 20 (a wave-uniform
-//    vote, so no lane diverges) the shorter fits in s = (ZF/z)^2 serve instead,
-//    and when every lane has z >= ZV = 60 the shortest, in s = (ZV/z)^2;
+//    when every active lane of the wavefront has z >= ZM = 10 (a wave-uniform
+//    vote, so no lane diverges) shorter fits in s = (ZM/z)^2 serve instead, past
+//    ZF = 20 shorter still in s = (ZF/z)^2, and when every lane has z >= ZV = 60
+//    the shortest, in s = (ZV/z)^2;
 //    sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta),
 //    delta = 2 pi / 256, r = z - n delta by a three-part Cody-Waite reduction
 //    (|r| <= delta / 2), T_n = sqrt(2/pi) e^{i(n delta - pi/4)} from a 256-entry
@@ -217,6 +218,13 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
     } else if (__all(z >= seed::kZF)) {
       const double t = seed::kZF * iz;
       const D4 pq = horner4<seed::kFARLen>(cf + seed::kFAROff, t * t);
+      P0 = pq.a;
+      Q0 = t * pq.b;
+      P1 = pq.c;
+      Q1 = t * pq.d;
+    } else if (__all(z >= seed::kZM)) {
+      const double t = seed::kZM * iz;
+      const D4 pq = horner4<seed::kMEDLen>(cf + seed::kMEDOff, t * t);
       P0 = pq.a;
       Q0 = t * pq.b;
       P1 = pq.c;

@@ -48,11 +48,13 @@ def assert_parity(u, ref, tol=TOL, what=""):
 
 
 def test_hankel_seeds_against_library(Q):
-    # whole wavefronts of 64 past z = 20 take the short far fits and past z = 60 the
-    # shortest; the waves of the ramps across 6, 20 and 60 mix the branches
+    # whole wavefronts of 64 past z = 10 take the medium fits, past z = 20 the short
+    # far fits and past z = 60 the shortest; the waves of the ramps across 6, 10, 20
+    # and 60 mix the branches
     z = np.concatenate([np.geomspace(1e-3, 400.0, 4000), np.linspace(0.5, 30.0, 3001),
                         np.geomspace(20.0, 1e5, 640), np.linspace(19.9, 20.1, 640),
-                        np.linspace(5.99, 6.01, 128), np.linspace(59.9, 60.1, 640)])
+                        np.linspace(5.99, 6.01, 128), np.linspace(59.9, 60.1, 640),
+                        np.linspace(10.0, 19.99, 640), np.linspace(9.99, 10.01, 640)])
     h0, h1 = Q.hankel01(torch.from_numpy(z).cuda())
     h0, h1 = h0.cpu().numpy(), h1.cpu().numpy()
     for n, h in ((0, h0), (1, h1)):
