@@ -9,14 +9,16 @@ Two regimes (z = k*rho > 0):
   J_nu + i Y_nu and stored as monomial coefficients in s:
       P_nu = sum_j p_j s^j,   Q_nu = (Z0/z) sum_j q_j s^j.
   Shorter fits of the same functions serve the wavefronts whose every lane is
-  farther: in s = (ZM/z)^2 for z >= ZM, in s = (ZF/z)^2 for z >= ZF and, shortest,
-  in s = (ZV/z)^2 for z >= ZV.
+  farther: in s = (ZM/z)^2 for z >= ZM, in s = (ZF/z)^2 for z >= ZF, in
+  s = (ZV/z)^2 for z >= ZV and, shortest, in s = (ZU/z)^2 for z >= ZU.
 * the phase with the amplitude's constant, sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir}:
-  n = rint(z N / 2 pi), r = z - 2 pi n / N by a three-part Cody-Waite reduction,
-  T_n = sqrt(2/pi) e^{i(2 pi n/N - pi/4)} from a table of N entries (40-digit values
-  rounded once; the factor sqrt(2/pi) of the amplitude sqrt(2/(pi z)) rides in the
-  table, so the kernels multiply by 1/sqrt(z) only), and sin r, cos r as
-  polynomials in r^2 interpolated at Chebyshev points of [0, R_TRIG^2].
+  n = rint(z N / 2 pi), r = z - 2 pi n / N by a two-part Cody-Waite reduction (the
+  first part's 29 bits make n times it exact; the second enters through one fused
+  multiply-add), T_n = sqrt(2/pi) e^{i(2 pi n/N - pi/4)} from a table of N = 1024
+  entries (40-digit values rounded once; the factor sqrt(2/pi) of the amplitude
+  sqrt(2/(pi z)) rides in the table, so the kernels multiply by 1/sqrt(z) only), and
+  sin r / r, cos r by their Taylor polynomials of degree 2 in r^2 (|r| <= pi/N, so
+  the first dropped terms are below 2e-18).
 * Z1 <= z < Z0: the entire functions J_0, J_1, R_0 = Y_0 - (2/pi) L J_0 and
   R_1 = Y_1 + 2/(pi z) - (2/pi) L J_1, L = ln(z/2) + gamma (the log terms of
   DLMF 10.8.1/10.8.2 split off), each interpolated at Chebyshev points of [Z1, Z0]
@@ -49,10 +51,10 @@ ZF = 20.0
 DEG_FAR = 6       # degree in s = (ZF/z)^2 of the far fits
 ZV = 60.0
 DEG_VFAR = 4      # degree in s = (ZV/z)^2 of the fits for z >= ZV
-PHASE_N = 256     # phase table entries sqrt(2/pi) e^{i(2 pi n/N - pi/4)}
-R_TRIG = 0.01228  # reduced argument bound (pi/N plus the reduction's rounding)
-DEG_SIN = 3       # degree in r^2 of sin(r)/r
-DEG_COS = 3       # degree in r^2 of cos(r)
+ZU = 80.0
+DEG_UFAR = 3      # degree in s = (ZU/z)^2 of the fits for z >= ZU
+PHASE_N = 1024    # phase table entries sqrt(2/pi) e^{i(2 pi n/N - pi/4)}
+R_TRIG = 0.00307  # reduced argument bound (pi/N plus the reduction's rounding)
 Z1 = 4.0          # below: ascending series; [Z1, Z0): interpolated entire parts
 NSER = 17         # series terms for z < Z1
 DEG_MID = 15      # degree of the mid-range fits in x = (z - ZC)/ZH in [-1, 1]
@@ -152,6 +154,10 @@ def main():
                                             DEG_MED)
         fits[f"MQ{nu}"] = cheb_fit_monomial(
             lambda s, nu=nu: pq(nu, ZM / mpmath.sqrt(s))[1] * (ZM / mpmath.sqrt(s)) / ZM, DEG_MED)
+        fits[f"UP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZU / mpmath.sqrt(s))[0],
+                                            DEG_UFAR)
+        fits[f"UQ{nu}"] = cheb_fit_monomial(
+            lambda s, nu=nu: pq(nu, ZU / mpmath.sqrt(s))[1] * (ZU / mpmath.sqrt(s)) / ZU, DEG_UFAR)
         fits[f"VP{nu}"] = cheb_fit_monomial(lambda s, nu=nu: pq(nu, ZV / mpmath.sqrt(s))[0],
                                             DEG_VFAR)
         fits[f"VQ{nu}"] = cheb_fit_monomial(
@@ -218,6 +224,14 @@ def main():
             Qv = (ZM / z) * horner(dbl[f"MQ{nu}"], s)
             pr, qr = pq(nu, z)
             worst_med = max(worst_med, abs(complex(P - float(pr), Qv - float(qr))))
+    worst_ufar = 0.0
+    for z in np.concatenate([np.geomspace(ZU, 2e4, 1500), rng.uniform(ZU, 250, 500)]):
+        s = (ZU / z) ** 2
+        for nu in (0, 1):
+            P = horner(dbl[f"UP{nu}"], s)
+            Qv = (ZU / z) * horner(dbl[f"UQ{nu}"], s)
+            pr, qr = pq(nu, z)
+            worst_ufar = max(worst_ufar, abs(complex(P - float(pr), Qv - float(qr))))
     worst_vfar = 0.0
     for z in np.concatenate([np.geomspace(ZV, 2e4, 1500), rng.uniform(ZV, 200, 500)]):
         s = (ZV / z) ** 2
@@ -250,6 +264,7 @@ def main():
     print(f"medium fit error of P,Q for z >= {ZM} (degree {DEG_MED}): {worst_med:.3e}")
     print(f"far fit error of P,Q for z >= {ZF} (degree {DEG_FAR}): {worst_far:.3e}")
     print(f"very-far fit error of P,Q for z >= {ZV} (degree {DEG_VFAR}): {worst_vfar:.3e}")
+    print(f"ultra-far fit error of P,Q for z >= {ZU} (degree {DEG_UFAR}): {worst_ufar:.3e}")
     print(f"mid-range relative error of H for {Z1} <= z < {Z0}: {worst_mid:.3e}")
     print(f"series relative error of H for z < {Z1}: {worst_small:.3e}")
 
@@ -258,49 +273,36 @@ def main():
         body = ",\n    ".join(f"{v:.17e}" for v in vals)
         return f"constexpr double {name}[{len(vals)}] = {{\n    {body}}};\n"
 
-    # delta = 2 pi / N split for the Cody-Waite reduction z - n delta (n < 2^24):
-    # the first two parts carry 29 significant bits each, so n*part is exact
+    # delta = 2 pi / N split for the Cody-Waite reduction z - n delta (n < 2^26, so
+    # z < 4e5): the first part carries 27 significant bits, so n*part is exact and z
+    # minus it is exact (Sterbenz); the second is the rest, rounded to double, and
+    # enters through one fused multiply-add
     delta = 2 * mpmath.pi / PHASE_N
-    parts = []
-    rem = delta
-    for _ in range(2):
-        e = mpmath.floor(mpmath.log(abs(rem), 2))
-        scale = mpmath.mpf(2) ** (28 - e)
-        hi = mpmath.floor(rem * scale) / scale
-        parts.append(float(hi))
-        rem = rem - hi
-    parts.append(float(rem))
+    e = mpmath.floor(mpmath.log(abs(delta), 2))
+    scale = mpmath.mpf(2) ** (26 - e)
+    hi = mpmath.floor(delta * scale) / scale
+    parts = [float(hi), float(delta - hi)]
     phase = []
     amp = mpmath.sqrt(2 / mpmath.pi)
     for n in range(PHASE_N):
         a = n * delta - mpmath.pi / 4
         phase += [float(amp * mpmath.cos(a)), float(amp * mpmath.sin(a))]
-    # sin(r)/r and cos(r) as polynomials in u = r^2 for |r| <= R_TRIG (just past
-    # pi/N, the bound of the reduced argument): Chebyshev interpolation in u at
-    # 40 digits, degrees DEG_SIN and DEG_COS
-    umax = mpmath.mpf(R_TRIG) ** 2
-
-    def on_u(f):
-        return lambda s: f(s * umax)
-
-    sin_c = [float(a * umax ** -i) for i, a in enumerate(cheb_fit_monomial(
-        on_u(lambda u: mpmath.sin(mpmath.sqrt(u)) / mpmath.sqrt(u) if u > 0 else mpmath.mpf(1)),
-        DEG_SIN))]
-    cos_c = [float(a * umax ** -i) for i, a in enumerate(cheb_fit_monomial(
-        on_u(lambda u: mpmath.cos(mpmath.sqrt(u))), DEG_COS))]
+    # sin(r)/r and cos(r): Taylor polynomials of degree 2 in u = r^2 (constant terms
+    # exactly 1, which the kernels take as inline constants)
+    sin_c = [1.0, float(mpmath.mpf(-1) / 6), float(mpmath.mpf(1) / 120)]
+    cos_c = [1.0, -0.5, float(mpmath.mpf(1) / 24)]
     worst_trig = 0.0
     for r in np.linspace(-R_TRIG, R_TRIG, 4001):
         u = r * r
         sv, cv = r * horner(sin_c, u), horner(cos_c, u)
         worst_trig = max(worst_trig, abs(sv - float(mpmath.sin(r))), abs(cv - float(mpmath.cos(r))))
-    print(f"sin/cos error for |r| <= {R_TRIG} (degrees {DEG_SIN}, {DEG_COS} in r^2): {worst_trig:.3e}")
+    print(f"sin/cos error for |r| <= {R_TRIG} (degree 2 in r^2): {worst_trig:.3e}")
     # the whole phase in double against 40 digits, z up to 2^24 delta
     worst_phase = 0.0
     for z in np.concatenate([rng.uniform(6, 60, 3000), np.geomspace(6, 4e5, 3000)]):
         n = float(np.rint(z * float(PHASE_N / (2 * mpmath.pi))))
-        r = z - n * parts[0]        # n * parts[0] and n * parts[1] are exact
-        r = r - n * parts[1]
-        r = r - n * parts[2]
+        r = z - n * parts[0]        # n * parts[0] is exact, and so is the difference
+        r = float(mpmath.mpf(r) - mpmath.mpf(n) * mpmath.mpf(parts[1]))   # one fma
         i = int(n) & (PHASE_N - 1)
         u = r * r
         sv, cv = r * horner(sin_c, u), horner(cos_c, u)
@@ -319,12 +321,12 @@ def main():
     out.append(f"constexpr double kZM = {ZM:.17e};\n")
     out.append(f"constexpr double kZF = {ZF:.17e};\n")
     out.append(f"constexpr double kZV = {ZV:.17e};\n")
+    out.append(f"constexpr double kZU = {ZU:.17e};\n")
     out.append(f"constexpr double kZC = {ZC:.17e};\nconstexpr double kInvZH = {1.0 / ZH:.17e};\n")
     out.append(f"constexpr int kPhaseN = {PHASE_N};\n")
     out.append(f"constexpr double kInvDelta = {float(PHASE_N / (2 * mpmath.pi)):.17e};\n")
     out.append(f"constexpr double kDeltaHi = {parts[0]:.17e};\n")
-    out.append(f"constexpr double kDeltaMid = {parts[1]:.17e};\n")
-    out.append(f"constexpr double kDeltaLo = {parts[2]:.17e};\n")
+    out.append(f"constexpr double kDeltaLo = {parts[1]:.17e};\n")
     # one packed table; four polynomials of a regime interleaved so that a wave reads
     # the coefficients of one Horner step with a single scalar load
     table, offs = [], {}
@@ -340,13 +342,13 @@ def main():
     block("MID", [dbl["MJ0"], dbl["MY0"], dbl["MJ1"], dbl["MY1"]])
     block("SER", [[float(a) for a in aJ0], [float(a) for a in bJ1], [float(a) for a in cY0],
                   [float(a) for a in dY1]])
-    block("TRIG", [sin_c + [0.0] * (len(cos_c) - len(sin_c)), cos_c])
+    block("TRIG", [sin_c, cos_c])
     block("FAR", [dbl["FP0"], dbl["FQ0"], dbl["FP1"], dbl["FQ1"]])
     block("VFAR", [dbl["VP0"], dbl["VQ0"], dbl["VP1"], dbl["VQ1"]])
     block("MED", [dbl["MP0"], dbl["MQ0"], dbl["MP1"], dbl["MQ1"]])
+    block("UFAR", [dbl["UP0"], dbl["UQ0"], dbl["UP1"], dbl["UQ1"]])
     for name, (o, n) in offs.items():
         out.append(f"constexpr int k{name}Off = {o};\nconstexpr int k{name}Len = {n};\n")
-    out.append(f"constexpr int kTRIGLenA = {len(sin_c)};   // sin(r)/r coefficients in TRIG\n")
     out.append(f"constexpr int kTableLen = {len(table)};\n")
     body = ", \\\n    ".join(f"{v:.17e}" for v in table)
     out.append(f"#define QBX_SEED_TABLE_VALUES \\\n    {body}\n")

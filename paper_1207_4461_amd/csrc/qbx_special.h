@@ -21,19 +21,19 @@ namespace qbx {
 //    with P_nu, Q_nu polynomial in s = (Z0/z)^2 (Q_nu carrying a factor Z0/z);
 //    when every active lane of the wavefront has z >= ZM = 10 (a wave-uniform
 //    vote, so no lane diverges) shorter fits in s = (ZM/z)^2 serve instead, past
-//    ZF = 20 shorter still in s = (ZF/z)^2, and when every lane has z >= ZV = 60
-//    the shortest, in s = (ZV/z)^2;
+//    ZF = 20 shorter still in s = (ZF/z)^2, past ZV = 60 in s = (ZV/z)^2, and
+//    when every lane has z >= ZU = 80 the shortest, in s = (ZU/z)^2;
 //    sqrt(2/pi) e^{i(z - pi/4)} = T_n e^{ir} with n = rint(z / delta),
-//    delta = 2 pi / 256, r = z - n delta by a three-part Cody-Waite reduction
-//    (|r| <= delta / 2), T_n = sqrt(2/pi) e^{i(n delta - pi/4)} from a 256-entry
+//    delta = 2 pi / 1024, r = z - n delta by a two-part Cody-Waite reduction
+//    (|r| <= delta / 2), T_n = sqrt(2/pi) e^{i(n delta - pi/4)} from a 1024-entry
 //    table gathered per lane (the amplitude's constant rides in the table), and
-//    short polynomials for sin r / r and cos r; the phase of H_1 is that of H_0
-//    turned by -pi/2.
+//    the degree-2 Taylor polynomials in r^2 of sin r / r and cos r; the phase of
+//    H_1 is that of H_0 turned by -pi/2.
 //  * z < Z0: Y_nu = (2/pi)(ln(z/2) + gamma) J_nu - nu 2/(pi z) + R_nu with J_nu, R_nu
 //    entire (DLMF 10.8.1, 10.8.2): for z < Z1 = 4 their ascending series in
 //    w = z^2/4 (DLMF 10.2.2), for Z1 <= z < Z0 polynomial fits in (z - 5).
-// Error <~ 2e-15 |H| for every z in (0, 4e5) (the reduction is exact for
-// n < 2^24).
+// Error <~ 2e-15 |H| for every z in (0, 4e5) (the reduction's first part is
+// exact for n < 2^26).
 // ---------------------------------------------------------------------------
 struct H01 {
   double h0r, h0i, h1r, h1i;
@@ -124,22 +124,26 @@ static __constant__ __align__(16) double g_phase_table[2 * seed::kPhaseN] = {
 
 // H_0, H_1 from the amplitude functions P0, Q0, P1, Q1 of the asymptotic form:
 // with E = sqrt(2/(pi z)) e^{i(z - pi/4)}, H_0 = E (P0 + i Q0), H_1 = E (Q1 - i P1).
-// sn0, cn0: the constant terms of the sin r / r and cos r polynomials
-// (cf[kTRIGOff], cf[kTRIGOff + 1]), passed in so that loops can hold them in
-// vector registers.
+// n = rint(z / delta) by adding and subtracting 1.5 * 2^52 (the sum's low word is n,
+// the table index); r = z - n delta in two parts (the first exact); sin r / r and
+// cos r to degree 2 in r^2, their constant terms and cos's -1/2 inline constants.
 __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, double P1, double Q1,
-                                             const double* __restrict__ cf, double sn0,
-                                             double cn0) {
+                                             const double* __restrict__ cf) {
+  constexpr double kRound = 6755399441055744.0;   // 1.5 * 2^52
   H01 h;
   // e^{i(z - pi/4)} = T_n e^{ir}
-  const double n = rint(z * seed::kInvDelta);
+  const double tq = fma(z, seed::kInvDelta, kRound);
+  const double n = tq - kRound;
   double r = fma(-n, seed::kDeltaHi, z);
-  r = fma(-n, seed::kDeltaMid, r);
   r = fma(-n, seed::kDeltaLo, r);
-  const double* __restrict__ T = g_phase_table + 2 * ((int)n & (seed::kPhaseN - 1));
+  const double* __restrict__ T =
+      g_phase_table + 2 * (__double2loint(tq) & (seed::kPhaseN - 1));
   const double tc = T[0], ts = T[1];
-  double sn, cs;
-  horner2<seed::kTRIGLen, seed::kTRIGLenA>(cf + seed::kTRIGOff, r * r, sn0, cn0, sn, cs);
+  const double u = r * r, u2 = u * u;
+  double sn = fma(cf[seed::kTRIGOff + 2], u, 1.0);      // 1 - u/6 + u^2/120
+  double cs = fma(u, -0.5, 1.0);                        // 1 - u/2 + u^2/24
+  sn = fma(cf[seed::kTRIGOff + 4], u2, sn);
+  cs = fma(cf[seed::kTRIGOff + 5], u2, cs);
   sn *= r;
   double er = fma(tc, cs, -ts * sn);
   double ei = fma(tc, sn, ts * cs);
@@ -153,15 +157,14 @@ __device__ __forceinline__ H01 hankel01_asym(double z, double P0, double Q0, dou
   return h;
 }
 
-// H_0(z), H_1(z) for z >= seed::kZV with the shortest fits (degree 4 in
+// H_0(z), H_1(z) for z >= seed::kZV with the z >= kZV fits (degree 4 in
 // (kZV/z)^2), no branches: the same values as hankel01's own z >= kZV tier,
 // which the direct passes of the near/far split call straight when every lane
 // of the wave is that far, without hankel01's per-lane range branches
 __device__ __forceinline__ H01 hankel01_vfar(double z, double iz, const double* __restrict__ cf) {
   const double t = seed::kZV * iz;
   const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
-  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf, cf[seed::kTRIGOff],
-                       cf[seed::kTRIGOff + 1]);
+  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf);
 }
 
 // A copy of a wave-uniform double in a vector register that the compiler cannot
@@ -174,29 +177,19 @@ __device__ __forceinline__ double in_vgpr(double s) {
   return v;
 }
 
-// The constant terms of the z >= kZV fits and of the phase polynomials, held in
-// vector registers by loops over many pairs (12 VGPRs)
-struct VfarC0 {
-  D4 pq;
-  double sn, cn;
-};
-
-__device__ __forceinline__ VfarC0 vfar_c0(const double* __restrict__ cf) {
-  VfarC0 c;
-  c.pq.a = in_vgpr(cf[seed::kVFAROff]);
-  c.pq.b = in_vgpr(cf[seed::kVFAROff + 1]);
-  c.pq.c = in_vgpr(cf[seed::kVFAROff + 2]);
-  c.pq.d = in_vgpr(cf[seed::kVFAROff + 3]);
-  c.sn = in_vgpr(cf[seed::kTRIGOff]);
-  c.cn = in_vgpr(cf[seed::kTRIGOff + 1]);
-  return c;
+// The constant terms of a fit block (its four interleaved polynomials), held in
+// vector registers by loops over many pairs (8 VGPRs)
+__device__ __forceinline__ D4 fit_c0(const double* __restrict__ fc) {
+  return D4{in_vgpr(fc[0]), in_vgpr(fc[1]), in_vgpr(fc[2]), in_vgpr(fc[3])};
 }
 
-// hankel01_vfar with t = kZV / z given and the constant terms from c0
-__device__ __forceinline__ H01 hankel01_vfar_c0(double z, double t, const double* __restrict__ cf,
-                                                const VfarC0& c0) {
-  const D4 pq = horner4_c0<seed::kVFARLen>(cf + seed::kVFAROff, t * t, c0.pq);
-  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf, c0.sn, c0.cn);
+// H_0, H_1 from one fit block of LEN terms at fc (a seed::k*Off block of the table
+// cf) with t = Zt / z for its threshold Zt, and its constant terms c0
+template <int LEN>
+__device__ __forceinline__ H01 hankel01_fit_c0(double z, double t, const double* __restrict__ fc,
+                                               const D4& c0, const double* __restrict__ cf) {
+  const D4 pq = horner4_c0<LEN>(fc, t * t, c0);
+  return hankel01_asym(z, pq.a, t * pq.b, pq.c, t * pq.d, cf);
 }
 
 // iz = 1/z (callers already hold it); cf = the coefficient table seed::kTable
@@ -208,7 +201,14 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
   H01 h;
   if (z >= seed::kZ0) {
     double P0, Q0, P1, Q1;
-    if (__all(z >= seed::kZV)) {
+    if (__all(z >= seed::kZU)) {
+      const double t = seed::kZU * iz;
+      const D4 pq = horner4<seed::kUFARLen>(cf + seed::kUFAROff, t * t);
+      P0 = pq.a;
+      Q0 = t * pq.b;
+      P1 = pq.c;
+      Q1 = t * pq.d;
+    } else if (__all(z >= seed::kZV)) {
       const double t = seed::kZV * iz;
       const D4 pq = horner4<seed::kVFARLen>(cf + seed::kVFAROff, t * t);
       P0 = pq.a;
@@ -237,7 +237,7 @@ __device__ __forceinline__ H01 hankel01(double z, double iz, const double* __res
       P1 = pq.c;
       Q1 = t * pq.d;
     }
-    h = hankel01_asym(z, P0, Q0, P1, Q1, cf, cf[seed::kTRIGOff], cf[seed::kTRIGOff + 1]);
+    h = hankel01_asym(z, P0, Q0, P1, Q1, cf);
   } else {
     const double L = log(0.5 * z) + kEuler;
     double J0, J1, R0, R1;   // Y0 = (2/pi) L J0 + R0,  Y1 = (2/pi)(L J1 - 1/z) + R1

@@ -20,6 +20,8 @@
 // sums do not depend on the side, so both sides share one far pass.  The
 // finalize adds, per center, the near sum and the far sums of its target in a
 // fixed order and applies i/4.
+#include <type_traits>
+
 #include "qbx_pair.h"
 #include "qbx_panel.h"
 
@@ -214,15 +216,17 @@ __device__ __forceinline__ void far_accumulate_q(const double2& wS, const double
 
 // partial[sp][kk][t]: direct sums of target t over the far sources of panels
 // [sp * ppw, (sp + 1) * ppw); wave gw = sp * n_tb + tb covers targets tb*64 ..
-// Per (wave, far panel) a vote: is every active lane at least kZV / k from every
+// Per (wave, far panel) a vote: is every active lane at least zt / k from every
 // source of the panel (the distance to the panel's mean less its source radius
-// bnd.w, with a relative margin for rounding)?  If so (about 84% of the pairs at
-// 4096 panels) the panel's pairs take the shortest seed fits with no per-pair
-// vote: the coefficient table is addressed once per panel, so its loads stay in
-// scalar registers through the panel's loop, and the fits' constant terms are
-// copied into vector registers once per panel.  Otherwise each pair votes as in
-// hankel01.  (Staging the source panels in LDS instead of reading them by scalar
-// loads was measured 4% slower: it costs vector registers the loop needs.)
+// bnd.w, with a relative margin for rounding), for the seed fits' thresholds
+// zt = 80, 60, 20 in turn?  The first that holds (75%, 9% and 11% of the pairs at
+// 4096 panels) gives the panel's pairs that fit with no per-pair vote: the
+// coefficient block is addressed once per panel, so its loads stay in scalar
+// registers through the panel's loop, and its constant terms are copied into
+// vector registers once per panel.  Otherwise (5%) each pair votes as in
+// hankel01.  (Panel votes for the z >= 10 and z >= 6 fits as well cost 20 more
+// vector registers, one wave a SIMD fewer and 3% of the time; staging the source
+// panels in LDS instead of reading them by scalar loads was measured 4% slower.)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ geo,
                                                    const double2* __restrict__ dens, int N, int qs,
@@ -247,10 +251,29 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
   const int p0 = sp * ppw;
   const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
-  const double kt = seed::kZV * inv_k;          // kZV / z = kt / rho
-  const double zv = seed::kZV * (1.0 + 1e-12);
+  const double zv = seed::kZV * (1.0 + 1e-12), zu = seed::kZU * (1.0 + 1e-12);
+  const double zf = seed::kZF * (1.0 + 1e-12);
   const double2* __restrict__ densD = dens + (kS ? (size_t)N : 0);
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+  // the pairs of one far panel with one fit block: LEN terms at offset OFF, for z
+  // past zt (t = zt / z = (zt / k) / rho)
+  auto panel_fit = [&](auto len, auto off, double zt, int j0) {
+    constexpr int LEN = decltype(len)::value;
+    const double* __restrict__ cf = g_seed_table + opaque_zero();
+    const double* __restrict__ fc = cf + decltype(off)::value;
+    const D4 c0 = fit_c0(fc);
+    const double kt = zt * inv_k;
+    for (int b = 0; b < qs; ++b) {
+      const int j = j0 + b;
+      const double4 g = geo[j];
+      const double dx = tx - g.x, dy = ty - g.y;
+      const double rho2 = fma(dx, dx, dy * dy);
+      const double ir = rsqrt_refined(rho2);
+      const double z = k * (rho2 * ir);
+      const H01 h = hankel01_fit_c0<LEN>(z, kt * ir, fc, c0, cf);
+      far_accumulate_q<kS, kD>(dens[j], densD[j], g, dx, dy, ir, h, sr, si, dr, di);
+    }
+  };
   for (int pm = p0; pm < p1; ++pm) {
     const double4 bp = bnd[pm];
     const bool far = valid && !panels_near(bt, bp, g2);
@@ -259,19 +282,15 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
       const double ex = tx - bp.x, ey = ty - bp.y;
       const double e2 = fma(ex, ex, ey * ey);
       const double lo = e2 * rsqrt_refined(e2) - bp.w;
-      if (__all(k * lo >= zv)) {
-        const double* __restrict__ cf = g_seed_table + opaque_zero();
-        const VfarC0 c0 = vfar_c0(cf);
-        for (int b = 0; b < qs; ++b) {
-          const int j = j0 + b;
-          const double4 g = geo[j];
-          const double dx = tx - g.x, dy = ty - g.y;
-          const double rho2 = fma(dx, dx, dy * dy);
-          const double ir = rsqrt_refined(rho2);
-          const double z = k * (rho2 * ir);
-          const H01 h = hankel01_vfar_c0(z, kt * ir, cf, c0);
-          far_accumulate_q<kS, kD>(dens[j], densD[j], g, dx, dy, ir, h, sr, si, dr, di);
-        }
+      if (__all(k * lo >= zu)) {
+        panel_fit(std::integral_constant<int, seed::kUFARLen>{},
+                  std::integral_constant<int, seed::kUFAROff>{}, seed::kZU, j0);
+      } else if (__all(k * lo >= zv)) {
+        panel_fit(std::integral_constant<int, seed::kVFARLen>{},
+                  std::integral_constant<int, seed::kVFAROff>{}, seed::kZV, j0);
+      } else if (__all(k * lo >= zf)) {
+        panel_fit(std::integral_constant<int, seed::kFARLen>{},
+                  std::integral_constant<int, seed::kFAROff>{}, seed::kZF, j0);
       } else {
         for (int b = 0; b < qs; ++b) {
           const int z0 = opaque_zero();
@@ -445,8 +464,8 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   const int p0 = sp * ppw;
   const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
-  const double kt = seed::kZV * inv_k;          // kZV / z = kt / rho
-  const double zv = seed::kZV * (1.0 + 1e-12);
+  const double zv = seed::kZV * (1.0 + 1e-12), zu = seed::kZU * (1.0 + 1e-12);
+  const double zf = seed::kZF * (1.0 + 1e-12);
   double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
   double2 qS = make_double2(0.0, 0.0), qD = qS;
   if (GEO) {
@@ -498,17 +517,31 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
       const double ex = g.x - bt.x, ey = g.y - bt.y;
       const double e2 = fma(ex, ex, ey * ey);
       const double lo = e2 * rsqrt_refined(e2) - bt.z * rsqrt_refined(bt.z);
-      if (__all(k * lo >= zv)) {
+      // the pairs of this target panel with one fit block (as in k_split_far)
+      auto panel_fit = [&](auto len, auto off, double zt) {
+        constexpr int LEN = decltype(len)::value;
         const double* __restrict__ cf = g_seed_table + opaque_zero();
-        const VfarC0 c0 = vfar_c0(cf);
+        const double* __restrict__ fc = cf + decltype(off)::value;
+        const D4 c0 = fit_c0(fc);
+        const double kt = zt * inv_k;
         for (int a = 0; a < kQ; ++a) {
           const int t = mt * kQ + a;
           const double dx = nodes[2 * (size_t)t] - g.x, dy = nodes[2 * (size_t)t + 1] - g.y;
           const double rho2 = fma(dx, dx, dy * dy);
           const double ir = rsqrt_refined(rho2);
           const double z = k * (rho2 * ir);
-          add(t, dx, dy, ir, hankel01_vfar_c0(z, kt * ir, cf, c0));
+          add(t, dx, dy, ir, hankel01_fit_c0<LEN>(z, kt * ir, fc, c0, cf));
         }
+      };
+      if (__all(k * lo >= zu)) {
+        panel_fit(std::integral_constant<int, seed::kUFARLen>{},
+                  std::integral_constant<int, seed::kUFAROff>{}, seed::kZU);
+      } else if (__all(k * lo >= zv)) {
+        panel_fit(std::integral_constant<int, seed::kVFARLen>{},
+                  std::integral_constant<int, seed::kVFAROff>{}, seed::kZV);
+      } else if (__all(k * lo >= zf)) {
+        panel_fit(std::integral_constant<int, seed::kFARLen>{},
+                  std::integral_constant<int, seed::kFAROff>{}, seed::kZF);
       } else {
         for (int a = 0; a < kQ; ++a) {
           const int t = mt * kQ + a;

@@ -4,20 +4,21 @@ Counting rule: add, sub, mul = 1; fused multiply-add = 2; sqrt, reciprocal squar
 root, divide and rint = 1 each, however the kernel computes them (the kernels refine
 a hardware reciprocal square root by a third-order step; that step is not counted).
 The counts follow the kernels' formulas for the common branch (every lane of the
-wavefront at z = k*rho >= 60: the asymptotic seed with the shortest fits), line by
+wavefront at z = k*rho >= 80: the asymptotic seed with the shortest fits), line by
 line:
 
 forward pair (one center, one source, order p):
   geometry      v = x'-c (2), rho = sqrt(vx^2+vy^2) (4), 1/rho (1), cos/sin of
                 theta_i - theta' (8), z and 1/z (2)                        = 17
   D geometry    cos/sin(theta_i - arg nu) (6)
-  seed H0, H1   60/z and (60/z)^2 (2), 4 interleaved degree-4 polynomials (35),
-                Q scaling (2), phase: reduction by 2 pi/256 (8), degree-3 sin/cos
-                polynomials in r^2 (16), times the table entry (6), 1/sqrt(z) and
-                the amplitude (3: the table holds sqrt(2/pi)), rotation by
-                P + iQ (12)                                                  =  84
-                (waves with a lane at 20 <= z < 60 run degree-6 fits, 103; the long
-                fits of 6 <= z < 20 cost 157: so the counts are lower bounds)
+  seed H0, H1   80/z and (80/z)^2 (2), 4 interleaved degree-3 polynomials (26),
+                Q scaling (2), phase: rounding by 1.5*2^52 and a two-part reduction
+                by 2 pi/1024 (7), degree-2 sin/cos polynomials in r^2 (11), times
+                the table entry (6), 1/sqrt(z) and the amplitude (3: the table holds
+                sqrt(2/pi)), rotation by P + iQ (12)                         =  69
+                (waves with a lane at 60 <= z < 80 run degree-4 fits, 78; at
+                20 <= z < 60 degree 6, 96; at 10 <= z < 20 degree 9, 123; the long
+                fits of 6 <= z < 10 cost 150: so the counts are lower bounds)
   recurrence    per order: H_{l+1} (4) + 2l/z (1)                            =  5
   S per order   J_l cos(l D) (1) + accumulate (4) + Chebyshev cos (2)        =  7
   D per order   J_{l+1} cos(lD+psi) - J_{l-1} cos(lD-psi) (3) + accumulate (4)
@@ -25,11 +26,11 @@ forward pair (one center, one source, order p):
   accumulation  w sigma K (8 per kind)
 
 Totals (derived in flops_forward_pair below):
-  S:   110 + 12 p        D:   129 + 16 p        S+D: 143 + 23 p
+  S:   95 + 12 p         D:   114 + 16 p        S+D: 128 + 23 p
 """
 from __future__ import annotations
 
-SEED = 84   # H_0, H_1 on the common branch (see above)
+SEED = 69   # H_0, H_1 on the common branch (see above)
 
 
 def flops_forward_pair(p: int, kind: int) -> int:
@@ -182,12 +183,11 @@ def flops_grad_pair(p: int, kind: int) -> int:
 def flops_far_pair(kind: int) -> int:
     """Far pass of the split forward, per (target, source) pair on a far panel (its
     density adjoint has the same count, with the cotangent weight in place of q):
-    x - x' (2), rho (4), 1/rho (1), z (1; 60/z is the seed's first multiply, of 1/rho),
-    seed H0, H1 on the branch a wave takes when all its lanes have k rho >= 60 (84:
-    the 53 flops of the degree-6 fits become 35 with degree 4); S: w sigma H_0 (8);
-    D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).  S: 100, D: 106,
-    S+D: 114.  Waves with a lane nearer run the z >= 20 fits, 18 flops more, so the
-    count is a lower bound."""
+    x - x' (2), rho (4), 1/rho (1), z (1; 80/z is the seed's first multiply, of 1/rho),
+    seed H0, H1 on the branch a panel takes when every lane is past k rho >= 80 (69);
+    S: w sigma H_0 (8); D: (x - x').n'/rho (4), w mu times it (2), times H_1 (8).
+    S: 85, D: 91, S+D: 99.  Panels with a lane nearer run longer fits (9 flops more
+    at z >= 60, 27 at z >= 20), so the count is a lower bound."""
     f = 2 + 4 + 1 + 1 + SEED
     if kind & 1:
         f += 8

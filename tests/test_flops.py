@@ -9,9 +9,9 @@ from paper_1207_4461_amd import inputs as I
 
 def test_forward_counts_follow_the_closed_forms():
     for p in range(1, 40):
-        assert F.flops_forward_pair(p, 1) == 110 + 12 * p
-        assert F.flops_forward_pair(p, 2) == 129 + 16 * p
-        assert F.flops_forward_pair(p, 3) == 143 + 23 * p
+        assert F.flops_forward_pair(p, 1) == 95 + 12 * p
+        assert F.flops_forward_pair(p, 2) == 114 + 16 * p
+        assert F.flops_forward_pair(p, 3) == 128 + 23 * p
 
 
 def test_counts_grow_with_the_order_and_fuse_below_the_sum():
@@ -27,7 +27,7 @@ def test_counts_grow_with_the_order_and_fuse_below_the_sum():
 
 
 def test_direct_pass_counts():
-    assert (F.flops_far_pair(1), F.flops_far_pair(2), F.flops_far_pair(3)) == (100, 106, 114)
+    assert (F.flops_far_pair(1), F.flops_far_pair(2), F.flops_far_pair(3)) == (85, 91, 99)
     assert F.interactions(10, 7, 3) == 140 and F.interactions(10, 7, 1) == 70
 
 
