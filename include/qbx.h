@@ -172,14 +172,16 @@ int qbx_layer_potential_gradient(const qbx_geometry* g, const double* density, d
                                  double* dn, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Near/far split of the forward (Section 5: QBX is needed only where a panel
- * is close to the target; distant panels are summed directly by the smooth
- * source rule).  Source panel m' is near target panel m when
+ * is close to the target; distant panels are summed directly by a smooth
+ * rule).  Source panel m' is near target panel m when
  *   |b_m - b_m'|^2 < gamma^2 max(rad2_m, rad2_m'),
  * b_m the mean of the panel's 16 nodes (added in node order, times 1/16) and
  * rad2_m = max_a |X_{m,a} - b_m|^2, every operation rounded on its own (no
  * fused multiply-add), so the decision is reproducible bit for bit.  Near
  * sources enter through the QBX expansion exactly as in qbx_layer_potential;
- * every other source x' adds (i/4) w sigma H_0(k|x - x'|) (S) or
+ * every other panel enters through its own 16-point Gauss-Legendre rule at its
+ * nodes (weight w = omega |X'(tau)|, the node's normal, the node density, no
+ * oversampling): each node x' adds (i/4) w sigma H_0(k|x - x'|) (S) or
  * (i/4) w mu dH_0(k|x - x'|)/dn' (D) at the target x itself.
  *   gamma > 0 (QBX_EINVAL otherwise); gamma^2 above the largest double makes
  *   every panel near, which is qbx_layer_potential.  Accuracy: the near

@@ -522,6 +522,26 @@ def near_panels(nodes, gamma: float) -> np.ndarray:
     return (dx * dx + dy * dy) < g2 * np.maximum(rad2[:, None], rad2[None, :])
 
 
+def nystrom_grid(nodes: torch.Tensor, density: torch.Tensor, kinds) -> Tuple[dict, dict]:
+    """The Nystrom (target) grid as a source grid: the 16 nodes of each panel with
+    their own 16-point Gauss-Legendre rule, w = omega |X'(tau)|, the outward normals
+    n = (y', -x')/|X'| at the nodes (the derivative of the 16-node interpolant), and
+    the node densities weighted, w sigma (no interpolation).  The far sums of the
+    near/far split take this grid: away from a panel its 16-point rule is as
+    accurate as the oversampled one (Section 3.4.2 oversamples only for the
+    expansion coefficients)."""
+    _, om = gauss_legendre(Q)
+    Dn = interpolation_matrices(1)["Dn"]
+    dX = torch.einsum("aq,pqd->pad", Dn, nodes)
+    speed = torch.sqrt(dX[..., 0] ** 2 + dX[..., 1] ** 2)
+    w = torch.from_numpy(om)[None, :] * speed
+    src = {"x": nodes[..., 0].reshape(-1), "y": nodes[..., 1].reshape(-1),
+           "w": w.reshape(-1),
+           "nx": (dX[..., 1] / speed).reshape(-1), "ny": (-dX[..., 0] / speed).reshape(-1)}
+    dens = {kk: src["w"].to(_C128) * density[i] for i, kk in enumerate(kinds)}
+    return src, dens
+
+
 def direct_sum(src, dens, tx, ty, k: float, kind: int, sel) -> Dict[str, torch.Tensor]:
     """Smooth-rule sums over the sources ``sel`` at the targets (tx, ty) [C], without
     the i/4: S: sum_j w_j sigma_j H_0(k rho_j); D: sum_j w_j mu_j dH_0(k|x - x'_j|)/dn'_j
@@ -588,6 +608,8 @@ def layer_potential_split_gradient(nodes, density, k: float, p: int, r: float = 
     tidx = np.arange(P * Q) if targets is None else np.asarray(targets, dtype=np.int64)
     xy = nodes.reshape(-1, 2)
     src_panel = np.arange(P * qs) // qs
+    nsrc, ndens = nystrom_grid(nodes, density, kinds)
+    node_panel = np.arange(P * Q) // Q
     sides = sides_of(side)
     ctrs = [expansion_centers(nodes, src["h"], src["n_tgt"], r, s) for s in sides]
     g = torch.zeros(len(sides), len(kinds), len(tidx), 2, dtype=_C128)
@@ -598,8 +620,9 @@ def layer_potential_split_gradient(nodes, density, k: float, p: int, r: float = 
         ni = torch.as_tensor(np.nonzero(near_src)[0], dtype=torch.long)
         sub = {key: src[key][ni] for key in ("x", "y", "nx", "ny")}
         dsub = {kk: dens[kk][ni] for kk in kinds}
-        far = torch.as_tensor(np.broadcast_to(~near_src, (len(rows), near_src.size)).copy())
-        dg = direct_gradient(src, dens, xy[ti, 0], xy[ti, 1], k, kind, far)
+        far = torch.as_tensor(np.broadcast_to(~near[m][node_panel],
+                                              (len(rows), node_panel.size)).copy())
+        dg = direct_gradient(nsrc, ndens, xy[ti, 0], xy[ti, 1], k, kind, far)
         for si in range(len(sides)):
             ctr = {key: val[ti] for key, val in ctrs[si].items()}
             a = coefficients(sub, dsub, ctr, k, p, kind, mode)
@@ -617,9 +640,10 @@ def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, over
     """One-sided limits with the near/far split of Section 5: for the targets of
     panel m, the sources of panels near m (``near_panels``) enter through the QBX
     expansion about each target's center (coefficients summed over those sources
-    only, evaluated as in ``layer_potential``), and all other sources through the
-    smooth rule applied directly at the target, (i/4) ``direct_sum``.  Same
-    arguments and layout as ``layer_potential``.
+    only, evaluated as in ``layer_potential``), and every other panel through its
+    own 16-point rule on the Nystrom grid (``nystrom_grid``) applied directly at
+    the target, (i/4) ``direct_sum``.  Same arguments and layout as
+    ``layer_potential``.
 
     The near sources alone form an open patch whose ends lie about gamma*rad from
     the target; their local expansion converges like (R/d_end)^(p+1), so the split
@@ -637,6 +661,8 @@ def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, over
     tidx = np.arange(P * Q) if targets is None else np.asarray(targets, dtype=np.int64)
     xy = nodes.reshape(-1, 2)
     src_panel = np.arange(P * qs) // qs
+    nsrc, ndens = nystrom_grid(nodes, density, kinds)
+    node_panel = np.arange(P * Q) // Q
     sides = sides_of(side)
     ctrs = [expansion_centers(nodes, src["h"], src["n_tgt"], r, s) for s in sides]
     u = torch.zeros(len(sides), len(kinds), len(tidx), dtype=_C128)
@@ -647,8 +673,9 @@ def layer_potential_split(nodes, density, k: float, p: int, r: float = 0.5, over
         ni = torch.as_tensor(np.nonzero(near_src)[0], dtype=torch.long)
         sub = {key: src[key][ni] for key in ("x", "y", "nx", "ny")}
         dsub = {kk: dens[kk][ni] for kk in kinds}
-        far = torch.as_tensor(np.broadcast_to(~near_src, (len(rows), near_src.size)).copy())
-        dsum = direct_sum(src, dens, xy[ti, 0], xy[ti, 1], k, kind, far)   # same for both sides
+        far = torch.as_tensor(np.broadcast_to(~near[m][node_panel],
+                                              (len(rows), node_panel.size)).copy())
+        dsum = direct_sum(nsrc, ndens, xy[ti, 0], xy[ti, 1], k, kind, far)   # both sides
         for si in range(len(sides)):
             ctr = {key: val[ti] for key, val in ctrs[si].items()}
             a = coefficients(sub, dsub, ctr, k, p, kind, mode)

@@ -262,9 +262,11 @@ __global__ __launch_bounds__(128) void k_chain(Dims d, const double* __restrict_
                                                const double* __restrict__ tab,
                                                const double* __restrict__ sg,
                                                const double* __restrict__ cg,
+                                               const double* __restrict__ gtw,
+                                               const double* __restrict__ gde,
                                                double* __restrict__ grad_density,
                                                double* __restrict__ grad_nodes) {
-  chain_panel(d, blockIdx.x, nodes, density, tab, sg, cg, grad_density, grad_nodes);
+  chain_panel(d, blockIdx.x, nodes, density, tab, sg, cg, gtw, gde, grad_density, grad_nodes);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,15 +413,16 @@ hipError_t launch_adjoint_fused(const Dims& d, const double* nodes, const double
   hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.kind,
                      d.n_cb, geo, spartial, sg);
   hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
-                     grad_density, grad_nodes);
+                     nullptr, nullptr, grad_density, grad_nodes);
   return hipGetLastError();
 }
 
 hipError_t launch_chain(const Dims& d, const double* nodes, const double* density,
                         const double* tables, const double* sg, const double* cg,
-                        double* grad_density, double* grad_nodes, hipStream_t s) {
+                        const double* gtw, const double* gde, double* grad_density,
+                        double* grad_nodes, hipStream_t s) {
   hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
-                     grad_density, grad_nodes);
+                     gtw, gde, grad_density, grad_nodes);
   return hipGetLastError();
 }
 
@@ -449,7 +452,7 @@ hipError_t launch_adjoint_rest(const Dims& d, const double* nodes, const double*
   hipLaunchKernelGGL(k_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N, d.kind,
                      d.n_csplit, geo, spartial, sg);
   hipLaunchKernelGGL(k_chain, dim3(d.P), dim3(128), 0, s, d, nodes, density, tables, sg, cg,
-                     grad_density, grad_nodes);
+                     nullptr, nullptr, grad_density, grad_nodes);
   return hipGetLastError();
 }
 

@@ -107,8 +107,8 @@ void set_launch_shape(Dims* d) {
   if (fs < 1) fs = 1;
   d->panels_per_fsplit = (int)((d->P + fs - 1) / fs);
   d->n_fsplit = (d->P + d->panels_per_fsplit - 1) / d->panels_per_fsplit;
-  // its density adjoint, far part: 64 sources a wave, target splits alike
-  long as = (kSplitFarWaves + d->chunks - 1) / d->chunks;
+  // its adjoint, far part: 64 far sources a wave, target splits alike
+  long as = (kSplitFarWaves + n_tb - 1) / n_tb;
   if (as > d->P) as = d->P;
   if (as < 1) as = 1;
   d->panels_per_asplit = (int)((d->P + as - 1) / as);
@@ -176,7 +176,12 @@ Layout make_layout(const Dims& d) {
   L.fpart = take(sizeof(double2) * (size_t)d.n_fsplit * d.nk * d.T * 2);
   L.gfar = take(sizeof(double2) * (size_t)d.nk * d.T);
   L.aacc = take(sizeof(double2) * (size_t)d.nk * d.N);
-  L.apart = take(sizeof(double2) * (size_t)d.n_asplit * (d.nk + 2) * d.N);
+  L.ngeo = take(sizeof(double4) * (size_t)d.T);
+  L.ndens = take(sizeof(double2) * (size_t)d.nk * d.T);
+  L.nw = take(sizeof(double) * (size_t)d.T);
+  L.apart = take(sizeof(double2) * (size_t)d.n_asplit * (d.nk + 2) * d.T);
+  L.gtw = take(sizeof(double) * (size_t)d.T * 2);
+  L.gde = take(sizeof(double2) * (size_t)d.nk * d.T);
   L.total = o;
   return L;
 }
@@ -418,12 +423,18 @@ int qbx_layer_potential_ext(const qbx_geometry* g, const double* density, double
 
 }  // extern "C"
 
-// the split's panel records and near lists (every split entry point, after prepare)
-static int split_geometry(const Dims& d, const Layout& L, const qbx_geometry* g, double g2,
-                          void* ws, hipStream_t stream, NearLists* nl) {
-  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.geo), at<double4>(ws, L.bnd),
-                                     stream);
+// the split's panel records, near lists and far sources (every split entry
+// point, after prepare)
+static int split_geometry(const Dims& d, const Layout& L, const qbx_geometry* g,
+                          const double* density, double g2, void* ws, hipStream_t stream,
+                          NearLists* nl, NystromSources* ns) {
+  hipError_t e = launch_panel_bounds(d, g->nodes, at<double4>(ws, L.bnd), stream);
   if (e != hipSuccess) return device_fail(e, "panel bounds kernel");
+  ns->geo = at<double4>(ws, L.ngeo);
+  ns->dens = at<double2>(ws, L.ndens);
+  ns->w = at<double>(ws, L.nw);
+  e = launch_nystrom_sources(d, g->nodes, density, at<double>(ws, L.tables), *ns, stream);
+  if (e != hipSuccess) return device_fail(e, "far source kernel");
   e = launch_near_lists(d, at<double4>(ws, L.bnd), g2, at<int>(ws, L.ncount), at<int>(ws, L.nlist),
                         stream);
   if (e != hipSuccess) return device_fail(e, "near list kernel");
@@ -451,7 +462,8 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   if (rc) return rc;
   const double g2 = gamma * gamma;
   NearLists nl;
-  if ((rc = split_geometry(d, L, g, g2, ws, stream, &nl))) return rc;
+  NystromSources ns;
+  if ((rc = split_geometry(d, L, g, density, g2, ws, stream, &nl, &ns))) return rc;
   timer_begin(6, stream);
   hipError_t e = launch_split_near(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
                                    at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
@@ -460,8 +472,8 @@ int qbx_layer_potential_split(const qbx_geometry* g, const double* density, doub
   timer_end(6, stream);
   if (e != hipSuccess) return device_fail(e, "split near kernel");
   timer_begin(7, stream);
-  e = launch_split_far(d, at<double4>(ws, L.geo), at<double2>(ws, L.dens), g->nodes,
-                       at<double4>(ws, L.bnd), g2, at<double2>(ws, L.fpart), stream);
+  e = launch_split_far(d, ns, g->nodes, at<double4>(ws, L.bnd), g2, at<double2>(ws, L.fpart),
+                       stream);
   timer_end(7, stream);
   if (e != hipSuccess) return device_fail(e, "split far kernel");
   e = launch_split_finalize(d, at<double2>(ws, L.partial), at<double2>(ws, L.fpart), out, stream);
@@ -486,10 +498,11 @@ int qbx_layer_potential_split_gradient(const qbx_geometry* g, const double* dens
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
   NearLists nl;
-  if ((rc = split_geometry(d, L, g, gamma * gamma, ws, stream, &nl))) return rc;
+  NystromSources ns;
+  if ((rc = split_geometry(d, L, g, density, gamma * gamma, ws, stream, &nl, &ns))) return rc;
   hipError_t e = launch_order_weighted(d, at<double>(ws, L.jtab), stream);
   if (e != hipSuccess) return device_fail(e, "order-weighted table kernel");
-  e = launch_split_gradient(d, g->nodes, at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+  e = launch_split_gradient(d, g->nodes, at<double4>(ws, L.geo), at<double2>(ws, L.dens), ns,
                             at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                             at<double4>(ws, L.bnd), gamma * gamma, nl,
                             at<double2>(ws, L.partial), at<double2>(ws, L.fpart), grad, dn,
@@ -518,26 +531,33 @@ int qbx_layer_potential_split_adjoint(const qbx_geometry* g, const double* densi
   rc = prepare(d, L, g->nodes, density, ws, stream);
   if (rc) return rc;
   NearLists nl;
-  if ((rc = split_geometry(d, L, g, gamma * gamma, ws, stream, &nl))) return rc;
+  NystromSources ns;
+  if ((rc = split_geometry(d, L, g, density, gamma * gamma, ws, stream, &nl, &ns))) return rc;
   hipError_t e = launch_make_G(d, cotangent, at<double2>(ws, L.G), stream);
   if (e != hipSuccess) return device_fail(e, "cotangent kernel");
-  if (grad_nodes)
+  if (grad_nodes) {
+    SplitNodeScratch w;
+    w.Gf = at<double2>(ws, L.gfar);
+    w.cg = at<double>(ws, L.cg);
+    w.spart = at<double2>(ws, L.spart);
+    w.fpart = at<double2>(ws, L.fpart);
+    w.apart = at<double2>(ws, L.apart);
+    w.sg = at<double>(ws, L.sg);
+    w.gtw = at<double>(ws, L.gtw);
+    w.gde = at<double2>(ws, L.gde);
     e = launch_split_adjoint_nodes(d, g->nodes, density, at<double>(ws, L.tables),
-                                   at<double4>(ws, L.geo), at<double2>(ws, L.dens),
+                                   at<double4>(ws, L.geo), at<double2>(ws, L.dens), ns,
                                    at<CenterRec>(ws, L.ctr), at<double>(ws, L.jtab),
                                    at<double4>(ws, L.bnd), gamma * gamma, nl,
-                                   at<double2>(ws, L.G), at<double2>(ws, L.gfar),
-                                   at<double>(ws, L.cg),
-                                   at<double2>(ws, L.spart), at<double2>(ws, L.fpart),
-                                   at<double2>(ws, L.apart), at<double>(ws, L.sg), grad_density,
-                                   grad_nodes, stream);
-  else
+                                   at<double2>(ws, L.G), w, grad_density, grad_nodes, stream);
+  } else {
     e = launch_split_adjoint_density(d, g->nodes, at<double>(ws, L.tables), at<double4>(ws, L.geo),
-                                     at<double>(ws, L.wgt), at<CenterRec>(ws, L.ctr),
+                                     at<double>(ws, L.wgt), ns, at<CenterRec>(ws, L.ctr),
                                      at<double>(ws, L.jtab), at<double4>(ws, L.bnd), gamma * gamma,
                                      nl, at<double2>(ws, L.G), at<double2>(ws, L.gfar),
                                      at<double2>(ws, L.aacc), at<double2>(ws, L.apart),
                                      grad_density, stream);
+  }
   if (e != hipSuccess) return device_fail(e, "split adjoint kernels");
   return QBX_OK;
 }

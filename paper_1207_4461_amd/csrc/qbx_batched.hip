@@ -328,7 +328,8 @@ __global__ __launch_bounds__(128) void k_chain_batched(
   const Dims d = B.d;
   const int m = (int)(blockIdx.x - pre_panel[it]);
   chain_panel(d, m, nodes + B.node_off, density + B.din_off, tab, sg + B.src_off * 8,
-              cg + B.ctr_off * 8, grad_density ? grad_density + B.din_off : nullptr,
+              cg + B.ctr_off * 8, nullptr, nullptr,
+              grad_density ? grad_density + B.din_off : nullptr,
               grad_nodes ? grad_nodes + B.node_off : nullptr);
 }
 

@@ -22,6 +22,14 @@ struct NearLists {
   const int* count;
   const int* list;
 };
+
+// the split's far sources, the Nystrom grid: per node {x, y, n_x, n_y}, the weighted
+// densities [nk][T] and the 16-point weights w = omega |X'|
+struct NystromSources {
+  double4* geo;
+  double2* dens;
+  double* w;
+};
 constexpr int kPMax = 24;
 
 // One expansion center: position, radius and the direction of its target,
@@ -62,10 +70,10 @@ struct Dims {
   // chunks_per_sb 64-source chunks, n_cb x n_sb tiles
   int fused_cblock, n_cb, n_sb, chunks_per_sb;
   // split forward, far pass: waves of 64 targets x panels_per_fsplit source
-  // panels, n_fsplit source splits
+  // panels (16 far sources each: the Nystrom grid), n_fsplit source splits
   int n_fsplit, panels_per_fsplit;
-  // its density adjoint, far part: waves of 64 sources x panels_per_asplit
-  // target panels, n_asplit target splits
+  // its adjoint, far part: waves of 64 far sources x panels_per_asplit target
+  // panels, n_asplit target splits
   int n_asplit, panels_per_asplit;
 };
 
@@ -92,8 +100,13 @@ struct Layout {
   size_t fpart;    // double2[n_fsplit][nk][T][2] split: far sums (forward: first half)
   size_t gfar;     // double2[nk][T] split adjoint: cotangent weights of both sides
   size_t aacc;     // double2[nk][N] split adjoint: near sums per source
-  size_t apart;    // double2[n_asplit][nk + 2][N] split adjoint: far sums per source
+  size_t ngeo;     // double4[T] split: the far sources (Nystrom grid) {x, y, nx, ny}
+  size_t ndens;    // double2[nk][T] split: their weighted densities
+  size_t nw;       // double[T] split: their 16-point weights
+  size_t apart;    // double2[n_asplit][nk + 2][T] split adjoint: far sums per far source
                    // (density; with the node gradient also position and normal)
+  size_t gtw;      // double[T][2] split node adjoint: far weights' tangent gradients
+  size_t gde;      // double2[nk][T] split node adjoint: far node density gradients
   size_t total;
 };
 
@@ -162,10 +175,12 @@ hipError_t launch_gradient_principal_value(int T, int nk, int side, int kind, co
                                            const double* grad, const double* dn,
                                            double* grad_pv, double* dn_pv, hipStream_t s);
 // ---- split forward (qbx_split.hip) ----
-// per panel {b_x, b_y, rad2, source radius}: the near relation's mean and squared
-// node radius, and max over the panel's sources of |x' - b|
-hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4* geo,
-                               double4* bnd, hipStream_t s);
+// per panel {b_x, b_y, rad2, sqrt(rad2)}: the near relation's mean and squared
+// node radius, and the node radius
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s);
+// the Nystrom grid's far sources from the nodes, node densities and tables
+hipError_t launch_nystrom_sources(const Dims& d, const double* nodes, const double* density,
+                                  const double* tables, NystromSources ns, hipStream_t s);
 // partial [nk][Mc]: QBX sums over the sources of near panels
 hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* dens,
                              const CenterRec* ctr, const double* jtab, const double4* bnd,
@@ -173,41 +188,54 @@ hipError_t launch_split_near(const Dims& d, const double4* geo, const double2* d
 // the near lists of every panel (count, list: NearLists' arrays)
 hipError_t launch_near_lists(const Dims& d, const double4* bnd, double g2, int* count, int* list,
                              hipStream_t s);
-// partial [n_fsplit][nk][T]: direct sums over the sources of far panels
-hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
-                            const double* nodes, const double4* bnd, double g2, double2* partial,
-                            hipStream_t s);
+// partial [n_fsplit][nk][T]: direct sums over the far sources (ns) of far panels
+hipError_t launch_split_far(const Dims& d, NystromSources ns, const double* nodes,
+                            const double4* bnd, double g2, double2* partial, hipStream_t s);
 hipError_t launch_split_finalize(const Dims& d, const double2* nearp, const double2* farp,
                                  double* out, hipStream_t s);
 // the split's target derivatives: near sums [nk][Mc][2], far sums
 // [n_fsplit][nk][T][2], then grad and n . grad (either may be NULL)
 hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
-                                 const double2* dens, const CenterRec* ctr, const double* jtab,
-                                 const double4* bnd, double g2, NearLists nl, double2* nearp,
-                                 double2* farp, double* grad, double* dn, hipStream_t s);
+                                 const double2* dens, NystromSources ns, const CenterRec* ctr,
+                                 const double* jtab, const double4* bnd, double g2, NearLists nl,
+                                 double2* nearp, double2* farp, double* grad, double* dn,
+                                 hipStream_t s);
 // the split's adjoint with respect to the density (G from launch_make_G)
 hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
-                                        const double4* geo, const double* wgt,
+                                        const double4* geo, const double* wgt, NystromSources ns,
                                         const CenterRec* ctr, const double* jtab,
                                         const double4* bnd, double g2, NearLists nl,
                                         const double2* G, double2* Gf, double2* acc,
                                         double2* partial, double* grad_density, hipStream_t s);
 // the split's adjoint with respect to the nodes (and the density, through the
 // chain rule; either output may be NULL): cg [Mc][8], spart [src_slots][N], fpart
-// [n_fsplit][nk][T][2], apart [n_asplit][nk + 2][N], sg [N][8]
+// [n_fsplit][nk][T][2], apart [n_asplit][nk + 2][T], sg [N][8], gtw [T][2],
+// gde [nk][T]
+struct SplitNodeScratch {
+  double2* Gf;
+  double* cg;
+  double2* spart;
+  double2* fpart;
+  double2* apart;
+  double* sg;
+  double* gtw;
+  double2* gde;
+};
 hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const double* density,
                                       const double* tables, const double4* geo,
-                                      const double2* dens, const CenterRec* ctr,
-                                      const double* jtab, const double4* bnd, double g2,
-                                      NearLists nl, const double2* G, double2* Gf, double* cg,
-                                      double2* spart, double2* fpart, double2* apart, double* sg,
+                                      const double2* dens, NystromSources ns,
+                                      const CenterRec* ctr, const double* jtab,
+                                      const double4* bnd, double g2, NearLists nl,
+                                      const double2* G, SplitNodeScratch w,
                                       double* grad_density, double* grad_nodes, hipStream_t s);
 // ---- adjoint (qbx_adjoint.hip) ----
 // the chain rule to the nodes and node densities from the per-source (sg) and
 // per-center (cg) gradients; one block per panel
+// (gtw, gde: the optional node terms of chain_panel, or NULL)
 hipError_t launch_chain(const Dims& d, const double* nodes, const double* density,
                         const double* tables, const double* sg, const double* cg,
-                        double* grad_density, double* grad_nodes, hipStream_t s);
+                        const double* gtw, const double* gde, double* grad_density,
+                        double* grad_nodes, hipStream_t s);
 hipError_t launch_forward_tape(const Dims& d, const double4* geo, const double2* dens,
                                const CenterRec* ctr, const double* jtab, double2* partial,
                                hipStream_t s);

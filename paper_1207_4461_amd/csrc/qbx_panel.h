@@ -121,13 +121,18 @@ __device__ __forceinline__ void upsample_panel(const Dims& d, int m, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// chain rule to the panel nodes and the node densities: one block per panel
+// chain rule to the panel nodes and the node densities: one block per panel.
+// Optional node terms (null when absent): gtw[t][2], a gradient with respect to
+// the node tangent X'(tau_a) itself, and gde[kk][t] (complex), one added to the
+// node density gradients (the split's far sources sit at the nodes).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chain_panel(const Dims& d, int m, const double* __restrict__ nodes,
                                                const double* __restrict__ density,
                                                const double* __restrict__ tab,
                                                const double* __restrict__ sg,
                                                const double* __restrict__ cg,
+                                               const double* __restrict__ gtw,
+                                               const double* __restrict__ gde,
                                                double* __restrict__ grad_density,
                                                double* __restrict__ grad_nodes) {
   const TableLayout L = table_layout(d.qs);
@@ -172,6 +177,11 @@ __device__ __forceinline__ void chain_panel(const Dims& d, int m, const double* 
     const double gn_n = gnx * nx + gny * ny;
     gtau[a][0] = (-gny - gn_n * tx * inv) * inv;
     gtau[a][1] = (gnx - gn_n * ty * inv) * inv;
+    if (gtw) {
+      const size_t o = (size_t)m * kQ + a;
+      gtau[a][0] += gtw[2 * o];
+      gtau[a][1] += gtw[2 * o + 1];
+    }
     gxt[a][0] = gx;
     gxt[a][1] = gy;
   }
@@ -244,6 +254,10 @@ __device__ __forceinline__ void chain_panel(const Dims& d, int m, const double* 
       ai = fma(v, gsf[kk][b].y, ai);
     }
     const size_t o = (size_t)kk * d.T + (size_t)m * kQ + c;
+    if (gde) {
+      ar += gde[2 * o];
+      ai += gde[2 * o + 1];
+    }
     grad_density[2 * o] = ar;
     grad_density[2 * o + 1] = ai;
   }

@@ -137,24 +137,42 @@ __global__ __launch_bounds__(256) void k_panel_bounds(int NP, const double* __re
     const double dy = X[2 * a + 1] - by;
     r2 = fmax(r2, dx * dx + dy * dy);
   }
-  bnd[m] = make_double4(bx, by, r2, 0.0);
+  // .w: the node radius, which bounds |x - x'| from below for a whole panel of
+  // the far sources (the panel's nodes) at once
+  bnd[m] = make_double4(bx, by, r2, sqrt(r2));
 }
 
-// bnd[m].w = max over the panel's sources of |x' - b_m|: with it the far pass
-// bounds |x - x'| from below for a whole panel at once
-__global__ __launch_bounds__(256) void k_panel_source_radius(int NP, int qs,
-                                                             const double4* __restrict__ geo,
-                                                             double4* __restrict__ bnd) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= NP) return;
-  const double4 b = bnd[m];
-  double r2 = 0.0;
-  for (int j = 0; j < qs; ++j) {
-    const double4 g = geo[(size_t)m * qs + j];
-    const double dx = g.x - b.x, dy = g.y - b.y;
-    r2 = fmax(r2, fma(dx, dx, dy * dy));
+// The Nystrom grid as the far sources (one thread per node t = 16 m + a): the node
+// itself, the outward normal n = (y', -x')/|X'| from the 16-node derivative (the
+// table's Dn rows, as for the centers), the 16-point Gauss-Legendre weight
+// w = omega_a |X'(tau_a)| (the table's w16) and the weighted node densities w sigma.
+__global__ __launch_bounds__(256) void k_nystrom_sources(int T, int nk,
+                                                         const double* __restrict__ nodes,
+                                                         const double* __restrict__ density,
+                                                         const double* __restrict__ Dn,
+                                                         const double* __restrict__ w16,
+                                                         double4* __restrict__ ngeo,
+                                                         double2* __restrict__ ndens,
+                                                         double* __restrict__ nw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const int m = t / kQ, a = t - m * kQ;
+  const double* X = nodes + (size_t)m * 2 * kQ;
+  const double* Dr = Dn + a * kQ;
+  double tx = 0.0, ty = 0.0;
+  for (int c = 0; c < kQ; ++c) {
+    tx = fma(Dr[c], X[2 * c], tx);
+    ty = fma(Dr[c], X[2 * c + 1], ty);
   }
-  bnd[m].w = sqrt(r2);
+  const double sp = sqrt(tx * tx + ty * ty);
+  const double inv = 1.0 / sp;
+  const double w = w16[a] * sp;
+  ngeo[t] = make_double4(X[2 * a], X[2 * a + 1], ty * inv, -tx * inv);
+  nw[t] = w;
+  for (int kk = 0; kk < nk; ++kk) {
+    const double* sg = density + 2 * ((size_t)kk * T + t);
+    ndens[(size_t)kk * T + t] = make_double2(w * sg[0], w * sg[1]);
+  }
 }
 
 // partial[kk][ci]: QBX sums of center ci over the sources of near panels
@@ -217,8 +235,8 @@ __device__ __forceinline__ void far_accumulate_q(const double2& wS, const double
 // partial[sp][kk][t]: direct sums of target t over the far sources of panels
 // [sp * ppw, (sp + 1) * ppw); wave gw = sp * n_tb + tb covers targets tb*64 ..
 // Per (wave, far panel) a vote: is every active lane at least zt / k from every
-// source of the panel (the distance to the panel's mean less its source radius
-// bnd.w, with a relative margin for rounding), for the seed fits' thresholds
+// far source of the panel, its nodes (the distance to the panel's mean less its
+// node radius bnd.w, with a relative margin for rounding), for the seed fits' thresholds
 // zt = 80, 60, 20 in turn?  The first that holds (75%, 9% and 11% of the pairs at
 // 4096 panels) gives the panel's pairs that fit with no per-pair vote: the
 // coefficient block is addressed once per panel, so its loads stay in scalar
@@ -516,7 +534,7 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
       // nodes) bounds |x - x'| from below
       const double ex = g.x - bt.x, ey = g.y - bt.y;
       const double e2 = fma(ex, ex, ey * ey);
-      const double lo = e2 * rsqrt_refined(e2) - bt.z * rsqrt_refined(bt.z);
+      const double lo = e2 * rsqrt_refined(e2) - bt.w;
       // the pairs of this target panel with one fit block (as in k_split_far)
       auto panel_fit = [&](auto len, auto off, double zt) {
         constexpr int LEN = decltype(len)::value;
@@ -568,12 +586,14 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   }
 }
 
-// grad_density[kk][16 m + a] = sum_b V[b][a] w_j conj(acc[kk][j] + sum_sp partial[sp][kk][j]),
-// j = m qs + b: one thread per node and kind
+// grad_density[kk][t] = sum_b V[b][a] w_j conj(acc[kk][j]) (j = m qs + b, the
+// near sources of panel m) + w_t conj(sum_sp partial[sp][kk][t]) (the far source
+// at node t = 16 m + a, weight w_t): one thread per node and kind
 __global__ __launch_bounds__(256) void k_split_density_grad(
     int T, int N, int qs, int nk, int n_asplit, const double* __restrict__ tab,
-    const double* __restrict__ wgt, const double2* __restrict__ acc,
-    const double2* __restrict__ partial, double* __restrict__ grad_density) {
+    const double* __restrict__ wgt, const double* __restrict__ nw,
+    const double2* __restrict__ acc, const double2* __restrict__ partial,
+    double* __restrict__ grad_density) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T * nk) return;
   const TableLayout L = table_layout(qs);
@@ -582,18 +602,20 @@ __global__ __launch_bounds__(256) void k_split_density_grad(
   double gr = 0.0, gi = 0.0;
   for (int b = 0; b < qs; ++b) {
     const size_t j = (size_t)m * qs + b;
-    double2 v = acc[(size_t)kk * N + j];
-    for (int sp = 0; sp < n_asplit; ++sp) {
-      const double2 q = partial[((size_t)sp * nk + kk) * N + j];
-      v.x += q.x;
-      v.y += q.y;
-    }
+    const double2 v = acc[(size_t)kk * N + j];
     const double c = tab[L.V + b * kQ + a] * wgt[j];
     gr = fma(c, v.x, gr);
     gi = fma(-c, v.y, gi);      // conj
   }
-  grad_density[2 * (size_t)e] = gr;
-  grad_density[2 * (size_t)e + 1] = gi;
+  double fr = 0.0, fi = 0.0;
+  for (int sp = 0; sp < n_asplit; ++sp) {
+    const double2 q = partial[((size_t)sp * nk + kk) * T + t];
+    fr += q.x;
+    fi += q.y;
+  }
+  const double w = nw[t];
+  grad_density[2 * (size_t)e] = fma(w, fr, gr);
+  grad_density[2 * (size_t)e + 1] = fma(-w, fi, gi);
 }
 
 template <int P>
@@ -615,7 +637,7 @@ static hipError_t launch_split_near_adj_p(const Dims& d, const double4* geo, con
 }
 
 hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, const double* tables,
-                                        const double4* geo, const double* wgt,
+                                        const double4* geo, const double* wgt, NystromSources ns,
                                         const CenterRec* ctr, const double* jtab,
                                         const double4* bnd, double g2, NearLists nl,
                                         const double2* G, double2* Gf, double2* acc,
@@ -631,11 +653,11 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   const int nt = d.T * d.nk;
   hipLaunchKernelGGL(k_split_gfar, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.nk, d.n_sides,
                      G, Gf);
-  const int n_sb = (d.N + kWave - 1) / kWave;
+  const int n_sb = (d.T + kWave - 1) / kWave;
   const long waves = (long)n_sb * d.n_asplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
-  geo, nullptr, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
+  ns.geo, nullptr, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
       d.panels_per_asplit, partial
   timer_begin(8, s);
   switch (d.kind) {
@@ -646,7 +668,7 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   timer_end(8, s);
 #undef QBX_FADJ_ARGS
   hipLaunchKernelGGL(k_split_density_grad, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.N, d.qs,
-                     d.nk, d.n_asplit, tables, wgt, acc, partial, grad_density);
+                     d.nk, d.n_asplit, tables, wgt, ns.w, acc, partial, grad_density);
   return hipGetLastError();
 }
 
@@ -659,10 +681,11 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
 //    gradients of center_grad_from_sums (target, radius, normal);
 //  * source side, near pairs (k_split_near_adj_nodes): the plain adjoint's pair
 //    body (adjoint_pair) over the centers of near target panels;
-//  * far pairs, source side: k_split_far_adj<KIND, true>; target side: the far
-//    target gradients of the split's derivative pass (k_split_far_grad),
-//    contracted with both sides' G (k_split_far_tgrad);
-//  * k_split_source_finalize adds both sides' source terms into the per-source
+//  * far pairs, source side: k_split_far_adj<KIND, true> over the far sources
+//    (the nodes); target side: the far target gradients of the split's
+//    derivative pass (k_split_far_grad); k_split_nystrom_grad puts both on the
+//    nodes (position, normal, the weight's tangent term, the density);
+//  * k_split_source_finalize puts the near source terms into the per-source
 //    layout of the plain adjoint, and the plain chain rule (chain_panel) maps
 //    everything to the nodes and node densities.
 // ---------------------------------------------------------------------------
@@ -716,19 +739,31 @@ __global__ __launch_bounds__(256) void k_split_near_cg(
   }
 }
 
-// cg[t][0..1] += Re(Gf_t . far target gradient) summed over kinds and far splits
-// (the first side's center of target t carries the target's own gradient)
-__global__ __launch_bounds__(256) void k_split_far_tgrad(int T, int nk, int n_fsplit,
-                                                         const double2* __restrict__ Gf,
-                                                         const double2* __restrict__ farp,
-                                                         double* __restrict__ cg) {
+// The far pairs' terms of the node gradient, per node t = 16 m + a (added to
+// the first side's center slot t, which the chain rule sums with the other's):
+//  * target side: Re(Gf_t . far target gradient) over kinds and far splits, into
+//    cg[t][0..1];
+//  * source side (the far source at node t), from the far splits' sums of
+//    k_split_far_adj<KIND, true>: F_kk (density), the position gradient into
+//    cg[t][0..1] and the normal gradient into cg[t][3..4] (the far source's normal
+//    is the node's own, as the center's); its weight w = omega_a |X'| enters through
+//    g_w = sum_kk Re(F_kk sigma_kk), gtw[t] = g_w omega_a X'/|X'| with X'/|X'| =
+//    (-n_y, n_x); gde[kk][t] = w conj(F_kk) joins the node density gradient.
+__global__ __launch_bounds__(256) void k_split_nystrom_grad(
+    int T, int nk, int n_fsplit, int n_asplit, const double* __restrict__ density,
+    const double4* __restrict__ ngeo, const double* __restrict__ nw,
+    const double* __restrict__ w16, const double2* __restrict__ Gf,
+    const double2* __restrict__ fpart, const double2* __restrict__ apart,
+    double* __restrict__ cg, double* __restrict__ gtw, double2* __restrict__ gde) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  double gx = 0.0, gy = 0.0;
+  const int ns = nk + 2;
+  const double w = nw[t];
+  double gx = 0.0, gy = 0.0, gnx = 0.0, gny = 0.0, gw = 0.0;
   for (int kk = 0; kk < nk; ++kk) {
     double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
     for (int sp = 0; sp < n_fsplit; ++sp) {
-      const double2* q = farp + (((size_t)sp * nk + kk) * T + t) * 2;
+      const double2* q = fpart + (((size_t)sp * nk + kk) * T + t) * 2;
       xr += q[0].x;
       xi += q[0].y;
       yr += q[1].x;
@@ -737,9 +772,33 @@ __global__ __launch_bounds__(256) void k_split_far_tgrad(int T, int nk, int n_fs
     const double2 g = Gf[(size_t)kk * T + t];
     gx += g.x * xr - g.y * xi;
     gy += g.x * yr - g.y * yi;
+    double fr = 0.0, fi = 0.0;
+    for (int sp = 0; sp < n_asplit; ++sp) {
+      const double2 v = apart[((size_t)sp * ns + kk) * T + t];
+      fr += v.x;
+      fi += v.y;
+    }
+    const double* sg = density + 2 * ((size_t)kk * T + t);
+    gw += fr * sg[0] - fi * sg[1];   // Re(F sigma)
+    gde[(size_t)kk * T + t] = make_double2(w * fr, -w * fi);
   }
-  cg[(size_t)t * 8] += gx;
-  cg[(size_t)t * 8 + 1] += gy;
+  for (int sp = 0; sp < n_asplit; ++sp) {
+    const double2 x = apart[((size_t)sp * ns + nk) * T + t];
+    const double2 n = apart[((size_t)sp * ns + nk + 1) * T + t];
+    gx += x.x;
+    gy += x.y;
+    gnx += n.x;
+    gny += n.y;
+  }
+  double* c = cg + (size_t)t * 8;
+  c[0] += gx;
+  c[1] += gy;
+  c[3] += gnx;
+  c[4] += gny;
+  const double4 g = ngeo[t];
+  const double om = w16[t % kQ];
+  gtw[2 * (size_t)t] = -gw * om * g.w;
+  gtw[2 * (size_t)t + 1] = gw * om * g.z;
 }
 
 // part[b][j], b < src_slots(KIND): the plain adjoint's source-side sums over the
@@ -793,53 +852,36 @@ __global__ __launch_bounds__(256) void k_split_near_adj_nodes(
   }
 }
 
-// sg[j] (the per-source layout of source_finalize_elem) from the near slots and
-// the far splits' sums: density gradients conj(near) + conj(far), source position
-// near + far, normal psi-projection (near) + far normal gradient
-__global__ __launch_bounds__(256) void k_split_source_finalize(
-    int N, int kind, int n_asplit, const double4* __restrict__ geo,
-    const double2* __restrict__ nearp, const double2* __restrict__ farp,
-    double* __restrict__ sg) {
+// sg[j] (the per-source layout of source_finalize_elem) from the near slots:
+// density gradients conj(near), source position, normal psi-projection (the far
+// pairs' source terms sit on the far sources, the nodes: k_split_nystrom_grad)
+__global__ __launch_bounds__(256) void k_split_source_finalize(int N, int kind,
+                                                               const double4* __restrict__ geo,
+                                                               const double2* __restrict__ nearp,
+                                                               double* __restrict__ sg) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
   const bool hasS = kind & 1, hasD = kind & 2;
   const int nk = hasS && hasD ? 2 : 1;
-  const int ns = nk + 2;
-  double fd[2][2] = {{0, 0}, {0, 0}}, fx = 0.0, fy = 0.0, fnx = 0.0, fny = 0.0;
-  for (int sp = 0; sp < n_asplit; ++sp) {
-    for (int kk = 0; kk < nk; ++kk) {
-      const double2 v = farp[((size_t)sp * ns + kk) * N + j];
-      fd[kk][0] += v.x;
-      fd[kk][1] += v.y;
-    }
-    const double2 x = farp[((size_t)sp * ns + nk) * N + j];
-    const double2 n = farp[((size_t)sp * ns + nk + 1) * N + j];
-    fx += x.x;
-    fy += x.y;
-    fnx += n.x;
-    fny += n.y;
-  }
   double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (hasS) {
     const double2 a = nearp[j];
-    o[0] = a.x + fd[0][0];
-    o[1] = a.y - fd[0][1];
+    o[0] = a.x;
+    o[1] = a.y;
   }
   if (hasD) {
     const double2 a = nearp[(size_t)(nk - 1) * N + j];
-    o[2] = a.x + fd[nk - 1][0];
-    o[3] = a.y - fd[nk - 1][1];
+    o[2] = a.x;
+    o[3] = a.y;
   }
   const double2 x = nearp[(size_t)nk * N + j];
-  o[4] = x.x + fx;
-  o[5] = x.y + fy;
-  o[6] = fnx;
-  o[7] = fny;
+  o[4] = x.x;
+  o[5] = x.y;
   if (hasD) {
     const double rp = nearp[(size_t)(nk + 1) * N + j].x;
     const double4 g = geo[j];
-    o[6] += rp * g.w;   // Re(w mu Psi) (n_y, -n_x)
-    o[7] -= rp * g.z;
+    o[6] = rp * g.w;   // Re(w mu Psi) (n_y, -n_x)
+    o[7] = -rp * g.z;
   }
   double* q = sg + (size_t)j * 8;
 #pragma unroll
@@ -1039,9 +1081,10 @@ static hipError_t launch_split_near_grad_p(const Dims& d, const double4* geo, co
 }
 
 hipError_t launch_split_gradient(const Dims& d, const double* nodes, const double4* geo,
-                                 const double2* dens, const CenterRec* ctr, const double* jtab,
-                                 const double4* bnd, double g2, NearLists nl, double2* nearp,
-                                 double2* farp, double* grad, double* dn, hipStream_t s) {
+                                 const double2* dens, NystromSources ns, const CenterRec* ctr,
+                                 const double* jtab, const double4* bnd, double g2, NearLists nl,
+                                 double2* nearp, double2* farp, double* grad, double* dn,
+                                 hipStream_t s) {
   hipError_t e;
   {
     auto launch = [&]() -> hipError_t {
@@ -1054,7 +1097,8 @@ hipError_t launch_split_gradient(const Dims& d, const double* nodes, const doubl
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FGRAD_ARGS \
-  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, farp
+  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+      farp
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_far_grad<2>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
@@ -1067,11 +1111,16 @@ hipError_t launch_split_gradient(const Dims& d, const double* nodes, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_panel_bounds(const Dims& d, const double* nodes, const double4* geo,
-                               double4* bnd, hipStream_t s) {
+hipError_t launch_panel_bounds(const Dims& d, const double* nodes, double4* bnd, hipStream_t s) {
   hipLaunchKernelGGL(k_panel_bounds, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, nodes, bnd);
-  hipLaunchKernelGGL(k_panel_source_radius, dim3((d.P + 255) / 256), dim3(256), 0, s, d.P, d.qs,
-                     geo, bnd);
+  return hipGetLastError();
+}
+
+hipError_t launch_nystrom_sources(const Dims& d, const double* nodes, const double* density,
+                                  const double* tables, NystromSources ns, hipStream_t s) {
+  const TableLayout L = table_layout(d.qs);
+  hipLaunchKernelGGL(k_nystrom_sources, dim3((d.T + 255) / 256), dim3(256), 0, s, d.T, d.nk,
+                     nodes, density, tables + L.Dn, tables + L.w16, ns.geo, ns.dens, ns.w);
   return hipGetLastError();
 }
 
@@ -1105,14 +1154,14 @@ hipError_t launch_near_lists(const Dims& d, const double4* bnd, double g2, int* 
   return hipGetLastError();
 }
 
-hipError_t launch_split_far(const Dims& d, const double4* geo, const double2* dens,
-                            const double* nodes, const double4* bnd, double g2, double2* partial,
-                            hipStream_t s) {
+hipError_t launch_split_far(const Dims& d, NystromSources ns, const double* nodes,
+                            const double4* bnd, double g2, double2* partial, hipStream_t s) {
   const int n_tb = (d.T + kWave - 1) / kWave;
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FAR_ARGS \
-  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, partial
+  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+      partial
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far<1>), grid, block, 0, s, QBX_FAR_ARGS); break;
     case 2: hipLaunchKernelGGL((k_split_far<2>), grid, block, 0, s, QBX_FAR_ARGS); break;
@@ -1164,47 +1213,46 @@ static hipError_t launch_split_nodes_near_p(const Dims& d, const double4* geo,
 
 hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const double* density,
                                       const double* tables, const double4* geo,
-                                      const double2* dens, const CenterRec* ctr,
-                                      const double* jtab, const double4* bnd, double g2,
-                                      NearLists nl, const double2* G, double2* Gf, double* cg,
-                                      double2* spart, double2* fpart, double2* apart, double* sg,
+                                      const double2* dens, NystromSources ns,
+                                      const CenterRec* ctr, const double* jtab,
+                                      const double4* bnd, double g2, NearLists nl,
+                                      const double2* G, SplitNodeScratch w,
                                       double* grad_density, double* grad_nodes, hipStream_t s) {
   hipError_t e;
   {
     auto launch = [&]() -> hipError_t {
-      QBX_P_SWITCH(d.p, launch_split_nodes_near_p, d, geo, dens, ctr, jtab, bnd, g2, nl, G, cg,
-                   spart, s)
+      QBX_P_SWITCH(d.p, launch_split_nodes_near_p, d, geo, dens, ctr, jtab, bnd, g2, nl, G, w.cg,
+                   w.spart, s)
     };
     e = launch();
     if (e != hipSuccess) return e;
   }
   const int nt = d.T * d.nk;
   hipLaunchKernelGGL(k_split_gfar, dim3((nt + 255) / 256), dim3(256), 0, s, d.T, d.nk, d.n_sides,
-                     G, Gf);
-  // far, target side: the split's far target gradients, contracted with Gf
+                     G, w.Gf);
+  // far, target side: the split's far target gradients
   {
     const int n_tb = (d.T + kWave - 1) / kWave;
     const long waves = (long)n_tb * d.n_fsplit;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-#define QBX_FGRAD_ARGS \
-  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, fpart
+#define QBX_FGRAD_ARGS                                                                          \
+  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+      w.fpart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
       case 2: hipLaunchKernelGGL((k_split_far_grad<2>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
       default: hipLaunchKernelGGL((k_split_far_grad<3>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
     }
 #undef QBX_FGRAD_ARGS
-    hipLaunchKernelGGL(k_split_far_tgrad, dim3((d.T + 255) / 256), dim3(256), 0, s, d.T, d.nk,
-                       d.n_fsplit, Gf, fpart, cg);
   }
-  // far, source side
+  // far, source side (the far sources at the nodes)
   {
-    const int n_sb = (d.N + kWave - 1) / kWave;
+    const int n_sb = (d.T + kWave - 1) / kWave;
     const long waves = (long)n_sb * d.n_asplit;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
-  geo, dens, d.N, d.qs, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,                \
-      d.panels_per_asplit, apart
+  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, w.Gf, n_sb, d.n_asplit,          \
+      d.panels_per_asplit, w.apart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_adj<1, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
       case 2: hipLaunchKernelGGL((k_split_far_adj<2, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
@@ -1212,11 +1260,16 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
     }
 #undef QBX_FADJ_ARGS
   }
+  const TableLayout L = table_layout(d.qs);
+  hipLaunchKernelGGL(k_split_nystrom_grad, dim3((d.T + 255) / 256), dim3(256), 0, s, d.T, d.nk,
+                     d.n_fsplit, d.n_asplit, density, ns.geo, ns.w, tables + L.w16, w.Gf, w.fpart,
+                     w.apart, w.cg, w.gtw, w.gde);
   hipLaunchKernelGGL(k_split_source_finalize, dim3((d.N + 255) / 256), dim3(256), 0, s, d.N,
-                     d.kind, d.n_asplit, geo, spart, apart, sg);
+                     d.kind, geo, w.spart, w.sg);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_chain(d, nodes, density, tables, sg, cg, grad_density, grad_nodes, s);
+  return launch_chain(d, nodes, density, tables, w.sg, w.cg, w.gtw,
+                      reinterpret_cast<const double*>(w.gde), grad_density, grad_nodes, s);
 }
 
 }  // namespace qbx

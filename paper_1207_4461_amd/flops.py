@@ -217,9 +217,14 @@ def near_panel_counts(nodes, gamma: float):
 
 
 def split_pairs(nodes, oversample: int, n_sides: int, gamma: float):
-    """(center-source pairs of the near pass, target-source pairs of the far pass)."""
+    """(center-source pairs of the near pass, target-source pairs of the far pass).
+
+    Near panels lend their q_s = 16 * oversample upsampled sources to each center;
+    far panels their 16 nodes (the far rule is the panel's own 16-point rule), the
+    pair taken once for both sides.
+    """
     cnt = near_panel_counts(nodes, gamma)
     P, qs = len(cnt), 16 * oversample
     near = int(cnt.sum()) * 16 * n_sides * qs
-    far = int((P - cnt).sum()) * 16 * qs
+    far = int((P - cnt).sum()) * 16 * 16
     return near, far

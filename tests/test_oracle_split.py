@@ -157,7 +157,9 @@ def test_planted_split_mistakes_are_caught(monkeypatch):
                             ("no_k", "direct_sum", no_k), ("h1_for_h0", "direct_sum", h1_for_h0)):
         monkeypatch.setattr(O, attr, bad)
         try:
-            assert rel(split(pb, 6.0), ref) > 1e-4, name
+            # a swapped relation puts each target's own node among the direct sources:
+            # the sum is not finite, which is caught as well
+            assert not rel(split(pb, 6.0), ref) <= 1e-4, name
         finally:
             monkeypatch.setattr(O, attr, orig_near if attr == "near_panels" else orig_direct)
 
@@ -280,3 +282,28 @@ def test_planted_split_gradient_mistake_is_caught(split_tiny, monkeypatch):
     _, bad = O.split_vjp(pb.nodes, pb.density, pb.k, pb.p, pb.r, pb.oversample, pb.side,
                          pb.kind, pb.cotangent, gamma)
     assert rel(bad, gn) > 1e-3
+
+
+def test_nystrom_grid_closed_forms():
+    """The far sources (``nystrom_grid``): the nodes' own 16-point rule gives the
+    ellipse's area by the divergence theorem (oint x n_x ds = oint y n_y ds = area
+    pi a b), the closed curve's oint n ds = 0, and the perimeter 4 a E(1 - b^2/a^2);
+    its weighted densities are w sigma at the nodes."""
+    a, b, P = 2.0, 1.0, 24
+    curve = I.ellipse(a, b)
+    nodes = torch.from_numpy(I.panel_nodes(curve, P))
+    sig = torch.arange(P * 16, dtype=torch.float64).to(torch.complex128) * (1 + 2j)
+    src, dens = O.nystrom_grid(nodes, sig[None, :], ("S",))
+    w = src["w"].numpy()
+    area = math.pi * a * b
+    assert abs((w * src["x"].numpy() * src["nx"].numpy()).sum() - area) < 1e-13 * area
+    assert abs((w * src["y"].numpy() * src["ny"].numpy()).sum() - area) < 1e-13 * area
+    assert abs((w * src["nx"].numpy()).sum()) < 1e-13 and abs((w * src["ny"].numpy()).sum()) < 1e-13
+    per = 4 * a * sps.ellipe(1 - (b / a) ** 2)   # the complete elliptic integral E(m)
+    assert abs(w.sum() - per) < 1e-12 * per
+    assert np.allclose(src["x"].numpy(), nodes[..., 0].reshape(-1).numpy(), rtol=0, atol=0)
+    assert torch.equal(dens["S"], src["w"].to(torch.complex128) * sig)
+    # unit normals, outward on a counter-clockwise curve: n . x > 0 on the ellipse
+    n2 = src["nx"] ** 2 + src["ny"] ** 2
+    assert float((n2 - 1).abs().max()) < 1e-15
+    assert bool(((src["nx"] * src["x"] + src["ny"] * src["y"]) > 0).all())
