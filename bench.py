@@ -210,7 +210,8 @@ def parse():
                     choices=["fwd", "fwdbwd", "grad", "split", "splitbwd", "solve"],
                     help="grad: the target derivatives (grad S, grad D, S', D') instead; "
                          "split: the forward with the near/far split (QBX for near panels "
-                         "only, the smooth rule applied directly for the rest); splitbwd: "
+                         "only, each other panel's own 16-point rule applied directly); "
+                         "splitbwd: "
                          "that forward and its density adjoint; solve: the "
                          "exterior Dirichlet problem with point-charge data, GMRES to 1e-14 "
                          "(products by the split when --gamma > 0)")

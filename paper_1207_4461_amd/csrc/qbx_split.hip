@@ -247,7 +247,7 @@ __device__ __forceinline__ void far_accumulate_q(const double2& wS, const double
 // panels in LDS instead of reading them by scalar loads was measured 4% slower.)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ geo,
-                                                   const double2* __restrict__ dens, int N, int qs,
+                                                   const double2* __restrict__ dens, int N,
                                                    const double* __restrict__ nodes, int T,
                                                    const double4* __restrict__ bnd, int NP,
                                                    double g2, double k, int n_tb, int n_fsplit,
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
     const double* __restrict__ fc = cf + decltype(off)::value;
     const D4 c0 = fit_c0(fc);
     const double kt = zt * inv_k;
-    for (int b = 0; b < qs; ++b) {
+    for (int b = 0; b < kQ; ++b) {
       const int j = j0 + b;
       const double4 g = geo[j];
       const double dx = tx - g.x, dy = ty - g.y;
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
     const double4 bp = bnd[pm];
     const bool far = valid && !panels_near(bt, bp, g2);
     if (far) {
-      const int j0 = pm * qs;
+      const int j0 = pm * kQ;
       const double ex = tx - bp.x, ey = ty - bp.y;
       const double e2 = fma(ex, ex, ey * ey);
       const double lo = e2 * rsqrt_refined(e2) - bp.w;
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
         panel_fit(std::integral_constant<int, seed::kFARLen>{},
                   std::integral_constant<int, seed::kFAROff>{}, seed::kZF, j0);
       } else {
-        for (int b = 0; b < qs; ++b) {
+        for (int b = 0; b < kQ; ++b) {
           const int z0 = opaque_zero();
           const double* __restrict__ cf = g_seed_table + z0;
           const int j = j0 + b;
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void k_split_gfar(int T, int nk, int n_sides,
 // each summed as Re(q G_t .) over the split's targets.
 template <int KIND, bool GEO>
 __global__ __launch_bounds__(256) void k_split_far_adj(
-    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
     const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
     double k, const double2* __restrict__ Gf, int n_sb, int n_asplit, int ppw,
     double2* __restrict__ partial) {
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   const bool valid = j < N;
   const int jj = valid ? j : N - 1;
   const double4 g = geo[jj];
-  const double4 bj = bnd[jj / qs];
+  const double4 bj = bnd[jj / kQ];
   const int p0 = sp * ppw;
   const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
@@ -657,7 +657,7 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   const long waves = (long)n_sb * d.n_asplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
-  ns.geo, nullptr, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
+  ns.geo, nullptr, d.T, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
       d.panels_per_asplit, partial
   timer_begin(8, s);
   switch (d.kind) {
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
 // sources of panels [sp * ppw, (sp + 1) * ppw), without the factors -k (S), k (D)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far_grad(
-    const double4* __restrict__ geo, const double2* __restrict__ dens, int N, int qs,
+    const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
     const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
     double k, int n_tb, int n_fsplit, int ppw, double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
@@ -972,8 +972,8 @@ __global__ __launch_bounds__(256) void k_split_far_grad(
   for (int pm = p0; pm < p1; ++pm) {
     const bool far = valid && !panels_near(bt, bnd[pm], g2);
     if (far) {
-      const int j0 = pm * qs;
-      for (int b = 0; b < qs; ++b) {
+      const int j0 = pm * kQ;
+      for (int b = 0; b < kQ; ++b) {
         const int z0 = opaque_zero();
         const double* __restrict__ cf = g_seed_table + z0;
         const int j = j0 + b;
@@ -1097,7 +1097,7 @@ hipError_t launch_split_gradient(const Dims& d, const double* nodes, const doubl
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FGRAD_ARGS \
-  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
       farp
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
@@ -1160,7 +1160,7 @@ hipError_t launch_split_far(const Dims& d, NystromSources ns, const double* node
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FAR_ARGS \
-  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
       partial
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far<1>), grid, block, 0, s, QBX_FAR_ARGS); break;
@@ -1236,7 +1236,7 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
     const long waves = (long)n_tb * d.n_fsplit;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FGRAD_ARGS                                                                          \
-  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
       w.fpart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
@@ -1251,7 +1251,7 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
     const long waves = (long)n_sb * d.n_asplit;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
-  ns.geo, ns.dens, d.T, kQ, nodes, d.T, bnd, d.P, g2, d.k, w.Gf, n_sb, d.n_asplit,          \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, w.Gf, n_sb, d.n_asplit,          \
       d.panels_per_asplit, w.apart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_adj<1, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
