@@ -412,6 +412,48 @@ def test_explicit_oracle_single_pair_is_graf():
     assert abs(out2[1] - 2.5 * out[1]) < 1e-13 * abs(out[1])
 
 
+def test_explicit_vjp_single_pair_closed_forms():
+    """apply_explicit_vjp on one source and one center at p = 40, where the truncated
+    Graf sums are H0 and nu . grad_x' H0 to rounding: every gradient against the
+    derivatives of (i/4) q H0(k r) and (i/4) q k H1(k r) nu . (x - x') / r, r = |x - x'|,
+    x = c + R (cos theta, sin theta), with H0' = -H1 and H1'(z) = H0(z) - H1(z)/z
+    (DLMF 10.6.2).  Complex inputs follow PyTorch: grad q = g conj(d out / d q)."""
+    k, p = 4.0, 40
+    xs = np.array([[0.9, -0.35]])
+    nu = np.array([[0.6, 0.8]])
+    q = np.array([[0.7 - 0.2j], [0.3 + 0.5j]])
+    c = np.array([[0.1, 0.2]])
+    R, th = np.array([0.3]), np.array([0.7])
+    g = np.array([[0.4 + 0.9j], [-1.1 + 0.25j]])
+    e = np.array([math.cos(th[0]), math.sin(th[0])])
+    x = c[0] + R[0] * e
+    d = x - xs[0]
+    r = float(np.hypot(*d))
+    u = d / r
+    z = k * r
+    h0, h1 = sps.hankel1(0, z), sps.hankel1(1, z)
+    dh1 = h0 - h1 / z
+    f = float(nu[0] @ u)
+    # d out / d x (the target), per kind
+    dS = 0.25j * q[0, 0] * (-k * h1) * u
+    dD = 0.25j * q[1, 0] * k * (k * dh1 * f * u + h1 * (nu[0] - f * u) / r)
+    dx = dS * np.conj(g[0, 0]) + dD * np.conj(g[1, 0])
+    dx = dx.real            # dL/dx = Re(conj(g) d out/dx), summed over kinds
+    ref = {
+        "src_xy": -dx,
+        "ctr_xy": dx,
+        "ctr_r": float(dx @ e),
+        "ctr_theta": float(dx @ (R[0] * np.array([-e[1], e[0]]))),
+        "src_nu": (np.conj(g[1, 0]) * 0.25j * q[1, 0] * k * h1 * u).real,
+        "q": np.array([g[0, 0] * np.conj(0.25j * h0), g[1, 0] * np.conj(0.25j * k * h1 * f)]),
+    }
+    got = O.apply_explicit_vjp(xs, nu, q, c, R, th, k, p, 3, g)
+    for key, val in ref.items():
+        val = np.asarray(val).reshape(-1)
+        out = np.asarray(got[key]).reshape(-1)
+        assert np.abs(out - val).max() < 1e-13 * np.abs(val).max(), key
+
+
 def test_explicit_oracle_matches_layer_potential():
     """The contour path is the explicit sums on the contour's own sources and centers."""
     pb = I.small(n_panels=6, p=7, k=3.0, kind=3, side=I.EXTERIOR)
