@@ -41,7 +41,7 @@ static int g_forward_waves = 16384;
 static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
 static int g_fused_tiles = 16384;  // fused adjoint workgroups aimed for
-static const int kSplitFarWaves = 16384;  // far-pass wavefronts aimed for
+static const int kSplitFarWaves = 65536;  // far-pass wavefronts aimed for
 static double g_fused_part_bytes = 2147483648.0;  // fused adjoint partial-sum bound
 
 double fused_part_budget() { return g_fused_part_bytes; }
@@ -99,8 +99,8 @@ void set_launch_shape(Dims* d) {
   if (sbs < 1) sbs = 1;
   d->chunks_per_sb = (int)((d->chunks + sbs - 1) / sbs);
   d->n_sb = (d->chunks + d->chunks_per_sb - 1) / d->chunks_per_sb;
-  // split forward, far pass: 64 targets a wave; enough source splits (runs of
-  // whole panels) for about kSplitFarWaves waves
+  // split forward, far pass: 64 targets a wave; enough source splits (split sp
+  // takes panels sp, sp + n_fsplit, ...) for about kSplitFarWaves waves
   const long n_tb = ((long)d->T + kWave - 1) / kWave;
   long fs = (kSplitFarWaves + n_tb - 1) / n_tb;
   if (fs > d->P) fs = d->P;

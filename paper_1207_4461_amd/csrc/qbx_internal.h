@@ -69,11 +69,12 @@ struct Dims {
   // fused adjoint launch shape: workgroup tiles of fused_cblock centers x
   // chunks_per_sb 64-source chunks, n_cb x n_sb tiles
   int fused_cblock, n_cb, n_sb, chunks_per_sb;
-  // split forward, far pass: waves of 64 targets x panels_per_fsplit source
-  // panels (16 far sources each: the Nystrom grid), n_fsplit source splits
+  // split forward, far pass: waves of 64 targets x about panels_per_fsplit
+  // source panels (16 far sources each: the Nystrom grid), n_fsplit source
+  // splits, split sp taking panels sp, sp + n_fsplit, ...
   int n_fsplit, panels_per_fsplit;
-  // its adjoint, far part: waves of 64 far sources x panels_per_asplit target
-  // panels, n_asplit target splits
+  // its adjoint, far part: waves of 64 far sources x about panels_per_asplit
+  // target panels, n_asplit target splits taken alike
   int n_asplit, panels_per_asplit;
 };
 

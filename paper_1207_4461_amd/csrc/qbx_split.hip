@@ -233,7 +233,9 @@ __device__ __forceinline__ void far_accumulate_q(const double2& wS, const double
 }
 
 // partial[sp][kk][t]: direct sums of target t over the far sources of panels
-// [sp * ppw, (sp + 1) * ppw); wave gw = sp * n_tb + tb covers targets tb*64 ..
+// sp, sp + n_fsplit, sp + 2 n_fsplit, ... (interleaved, so that the costly
+// panels next to each target's near zone spread over all splits); wave
+// gw = sp * n_tb + tb covers targets tb*64 ..
 // Per (wave, far panel) a vote: is every active lane at least zt / k from every
 // far source of the panel, its nodes (the distance to the panel's mean less its
 // node radius bnd.w, with a relative margin for rounding), for the seed fits' thresholds
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
                                                    const double* __restrict__ nodes, int T,
                                                    const double4* __restrict__ bnd, int NP,
                                                    double g2, double k, int n_tb, int n_fsplit,
-                                                   int ppw, double2* __restrict__ partial) {
+                                                   double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
@@ -266,8 +268,6 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
   const int tt = valid ? t : T - 1;
   const double tx = nodes[2 * (size_t)tt], ty = nodes[2 * (size_t)tt + 1];
   const double4 bt = bnd[tt / kQ];
-  const int p0 = sp * ppw;
-  const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
   const double zv = seed::kZV * (1.0 + 1e-12), zu = seed::kZU * (1.0 + 1e-12);
   const double zf = seed::kZF * (1.0 + 1e-12);
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_split_far(const double4* __restrict__ g
       far_accumulate_q<kS, kD>(dens[j], densD[j], g, dx, dy, ir, h, sr, si, dr, di);
     }
   };
-  for (int pm = p0; pm < p1; ++pm) {
+  for (int pm = sp; pm < NP; pm += n_fsplit) {
     const double4 bp = bnd[pm];
     const bool far = valid && !panels_near(bt, bp, g2);
     if (far) {
@@ -448,8 +448,9 @@ __global__ __launch_bounds__(256) void k_split_gfar(int T, int nk, int n_sides,
   Gf[e] = v;
 }
 
-// partial[sp][kk][j]: sum over the targets t of far panels in split sp of
-// Gf_t K_far(t, j); lanes are 64 consecutive sources, targets wave-uniform
+// partial[sp][kk][j]: sum over the targets t of far panels in split sp (panels
+// sp, sp + n_asplit, ...) of Gf_t K_far(t, j); lanes are 64 consecutive sources,
+// targets wave-uniform
 // The vote of k_split_far per (wave, target panel); here the targets are the
 // panel's nodes, so its node radius bounds them.
 // GEO adds the far pairs' gradients for the source's position and normal,
@@ -462,7 +463,7 @@ template <int KIND, bool GEO>
 __global__ __launch_bounds__(256) void k_split_far_adj(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
     const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
-    double k, const double2* __restrict__ Gf, int n_sb, int n_asplit, int ppw,
+    double k, const double2* __restrict__ Gf, int n_sb, int n_asplit,
     double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
@@ -479,8 +480,6 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
   const int jj = valid ? j : N - 1;
   const double4 g = geo[jj];
   const double4 bj = bnd[jj / kQ];
-  const int p0 = sp * ppw;
-  const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
   const double zv = seed::kZV * (1.0 + 1e-12), zu = seed::kZU * (1.0 + 1e-12);
   const double zf = seed::kZF * (1.0 + 1e-12);
@@ -525,7 +524,7 @@ __global__ __launch_bounds__(256) void k_split_far_adj(
       }
     }
   };
-  for (int mt = p0; mt < p1; ++mt) {
+  for (int mt = sp; mt < NP; mt += n_asplit) {
     const double4 bt = bnd[mt];
     const bool far = valid && !panels_near(bt, bj, g2);
     if (far) {
@@ -658,7 +657,7 @@ hipError_t launch_split_adjoint_density(const Dims& d, const double* nodes, cons
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
   ns.geo, nullptr, d.T, nodes, d.T, bnd, d.P, g2, d.k, Gf, n_sb, d.n_asplit,             \
-      d.panels_per_asplit, partial
+      partial
   timer_begin(8, s);
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far_adj<1, false>), grid, block, 0, s, QBX_FADJ_ARGS); break;
@@ -944,12 +943,12 @@ __global__ __launch_bounds__(256) void k_split_near_grad(
 }
 
 // partial[sp][kk][t][0..1]: the direct gradient (x, y) of target t over the far
-// sources of panels [sp * ppw, (sp + 1) * ppw), without the factors -k (S), k (D)
+// sources of panels sp, sp + n_fsplit, ..., without the factors -k (S), k (D)
 template <int KIND>
 __global__ __launch_bounds__(256) void k_split_far_grad(
     const double4* __restrict__ geo, const double2* __restrict__ dens, int N,
     const double* __restrict__ nodes, int T, const double4* __restrict__ bnd, int NP, double g2,
-    double k, int n_tb, int n_fsplit, int ppw, double2* __restrict__ partial) {
+    double k, int n_tb, int n_fsplit, double2* __restrict__ partial) {
   constexpr bool kS = (KIND & 1) != 0;
   constexpr bool kD = (KIND & 2) != 0;
   constexpr int NK = (kS ? 1 : 0) + (kD ? 1 : 0);
@@ -964,12 +963,10 @@ __global__ __launch_bounds__(256) void k_split_far_grad(
   const int tt = valid ? t : T - 1;
   const double tx = nodes[2 * (size_t)tt], ty = nodes[2 * (size_t)tt + 1];
   const double4 bt = bnd[tt / kQ];
-  const int p0 = sp * ppw;
-  const int p1 = min(NP, p0 + ppw);
   const double inv_k = 1.0 / k;
   double sxr = 0.0, sxi = 0.0, syr = 0.0, syi = 0.0;
   double dxr = 0.0, dxi = 0.0, dyr = 0.0, dyi = 0.0;
-  for (int pm = p0; pm < p1; ++pm) {
+  for (int pm = sp; pm < NP; pm += n_fsplit) {
     const bool far = valid && !panels_near(bt, bnd[pm], g2);
     if (far) {
       const int j0 = pm * kQ;
@@ -1097,7 +1094,7 @@ hipError_t launch_split_gradient(const Dims& d, const double* nodes, const doubl
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FGRAD_ARGS \
-  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, \
       farp
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
@@ -1160,7 +1157,7 @@ hipError_t launch_split_far(const Dims& d, NystromSources ns, const double* node
   const long waves = (long)n_tb * d.n_fsplit;
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FAR_ARGS \
-  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, \
       partial
   switch (d.kind) {
     case 1: hipLaunchKernelGGL((k_split_far<1>), grid, block, 0, s, QBX_FAR_ARGS); break;
@@ -1236,7 +1233,7 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
     const long waves = (long)n_tb * d.n_fsplit;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FGRAD_ARGS                                                                          \
-  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, d.panels_per_fsplit, \
+  ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, n_tb, d.n_fsplit, \
       w.fpart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_grad<1>), grid, block, 0, s, QBX_FGRAD_ARGS); break;
@@ -1252,7 +1249,7 @@ hipError_t launch_split_adjoint_nodes(const Dims& d, const double* nodes, const 
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
 #define QBX_FADJ_ARGS                                                                       \
   ns.geo, ns.dens, d.T, nodes, d.T, bnd, d.P, g2, d.k, w.Gf, n_sb, d.n_asplit,          \
-      d.panels_per_asplit, w.apart
+      w.apart
     switch (d.kind) {
       case 1: hipLaunchKernelGGL((k_split_far_adj<1, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
       case 2: hipLaunchKernelGGL((k_split_far_adj<2, true>), grid, block, 0, s, QBX_FADJ_ARGS); break;
