@@ -115,7 +115,8 @@ def test_split_scan_path_when_lists_overflow(Q):
 def test_split_full_size_sampled(Q, cfg, n):
     """The workloads at full size (gamma = 6) on sampled targets against the oracle,
     and the whole output against the plain QBX forward on the GPU (they differ by the
-    far sources' QBX truncation and the near patch's end effect only)."""
+    far panels' rule, 16 nodes against the oversampled grid, the far sources' QBX
+    truncation and the near patch's end effect only)."""
     pb = getattr(I, cfg)()
     idx = np.unique(np.concatenate([[0, pb.n_targets - 1],
                                     np.random.default_rng(9).choice(pb.n_targets, n, replace=False)]))
