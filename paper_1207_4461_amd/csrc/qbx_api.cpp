@@ -42,6 +42,7 @@ static int g_tape_waves = 16384;
 static int g_adjoint_waves = 16384;
 static int g_fused_tiles = 16384;  // fused adjoint workgroups aimed for
 static const int kSplitFarWaves = 65536;  // far-pass wavefronts aimed for
+static const int kFusedMinTile = 32;      // fewest centers a fused adjoint tile takes
 static double g_fused_part_bytes = 2147483648.0;  // fused adjoint partial-sum bound
 
 double fused_part_budget() { return g_fused_part_bytes; }
@@ -93,8 +94,21 @@ void set_launch_shape(Dims* d) {
   // about g_fused_tiles tiles, each of at least four chunks (one per wave)
   d->fused_cblock = fused_tile_height(d->Mc, d->N, d->kind);
   d->n_cb = (d->Mc + d->fused_cblock - 1) / d->fused_cblock;
-  long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
   long max_sb = (d->chunks + 3) / 4;
+  // small contours: when even the finest source blocks leave fewer tiles than
+  // aimed for, shorter tiles (down to kFusedMinTile centers) make up the rest,
+  // within the partial-sum bound
+  if ((long)d->n_cb * max_sb < g_fused_tiles && d->fused_cblock > kFusedMinTile) {
+    const long want_cb = ((long)g_fused_tiles + max_sb - 1) / max_sb;
+    const long h = std::max((long)kFusedMinTile, ((long)d->Mc + want_cb - 1) / want_cb);
+    const long n_cb = ((long)d->Mc + h - 1) / h;
+    if (h < d->fused_cblock &&
+        (double)n_cb * src_slots(d->kind) * (double)d->N * 16.0 <= fused_part_budget()) {
+      d->fused_cblock = (int)h;
+      d->n_cb = (int)n_cb;
+    }
+  }
+  long sbs = ((long)g_fused_tiles + d->n_cb - 1) / d->n_cb;
   if (sbs > max_sb) sbs = max_sb;
   if (sbs < 1) sbs = 1;
   d->chunks_per_sb = (int)((d->chunks + sbs - 1) / sbs);
